@@ -1,0 +1,424 @@
+/*
+ * cd_oracle.c -- CPU oracle for the 4D-AABB broad phase (test infrastructure).
+ *
+ * THIS IS TEST INFRASTRUCTURE.  Only tests, the smoke check and the benchmark's
+ * CPU-baseline leg may call it.  It is deliberately plain: no blocking, no
+ * fusion, no reordering beyond what each definition states, so that it can be
+ * read against the paper line by line.  OpenMP only splits the outermost loop
+ * of the literal pair test; the result is sorted afterwards, so it does not
+ * depend on the thread count.
+ *
+ * Readings of the paper this file takes (each one is listed in the design
+ * notes as well):
+ *   - The single-variable ODE of Eq. (nu-dot) is solved exactly through
+ *     Kepler's equation instead of by Runge-Kutta; its solution nu(t) is the
+ *     function g of Sec. 4.5.  The element set carries the mean anomaly at
+ *     t = 0 (m0), from which nu follows.
+ *   - The "three rotations involving i, Omega and omega" of Sec. 7.1 are
+ *     R_z(Omega) R_x(i) R_z(omega) applied to the perifocal position.
+ *   - occ-int over [t_a, t_b] is the axis-aligned hull of the two endpoint
+ *     positions grown by vmax*(t_b - t_a)/2 plus the radius r = thr/2, with
+ *     vmax the perigee speed.  It contains every position in the interval
+ *     (the speed bound) and equals occ at a single instant (Property 1).
+ *   - Time tags are half-open on the integer tick grid, [t_k, t_{k+1}); the
+ *     last interval is clamped at T as advanceTime does and its tag is closed
+ *     at T, stored as [t_{K-1}, T + 1).
+ *   - Box comparisons are closed (<=), as the occupancy cube is closed.
+ *   - A record never pairs an object with itself (queryObject excludes the
+ *     queried object; the brute-force inner loop is read as j > i).
+ */
+#include "cd_oracle.h"
+
+#include <float.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+static const double OR_TWO_PI = 6.283185307179586476925286766559;
+
+/* ------------------------------------------------------------------------ */
+/* Dynamics                                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* Kepler's equation E - e sin E = M by Newton's method.  For e < 1 the
+ * function is monotone; starting from M + e sin M it converges in a handful of
+ * steps for the eccentricities used here. */
+double or_eccentric_anomaly(double M, double e)
+{
+    double E = M + e * sin(M);
+    for (int it = 0; it < 60; ++it) {
+        double f = E - e * sin(E) - M;
+        double fp = 1.0 - e * cos(E);
+        double d = f / fp;
+        E -= d;
+        if (fabs(d) <= 1e-15 * (1.0 + fabs(E)))
+            break;
+    }
+    return E;
+}
+
+/* nu(t): the solution g of the single-variable ODE nu' = f(nu) of Eq.
+ * (nu-dot).  Mean anomaly grows linearly at n = sqrt(mu / a^3); the eccentric
+ * anomaly follows from Kepler's equation and the true anomaly from the
+ * half-angle relation. */
+double or_true_anomaly(const double el[6], double t_s, double mu)
+{
+    double a = el[0], e = el[1], m0 = el[5];
+    double n_mean = sqrt(mu / (a * a * a));
+    double M = fmod(m0 + n_mean * t_s, OR_TWO_PI);
+    if (M < 0.0)
+        M += OR_TWO_PI;
+    double E = or_eccentric_anomaly(M, e);
+    return 2.0 * atan2(sqrt(1.0 + e) * sin(0.5 * E), sqrt(1.0 - e) * cos(0.5 * E));
+}
+
+/* h(nu): the orbit equation gives the radius, the perifocal position is
+ * (r cos nu, r sin nu, 0), and three rotations (by omega about z, by i about
+ * x, by Omega about z) take it to the ECI frame (Sec. 7.1). */
+void or_position_from_nu(const double el[6], double nu, double pos[3])
+{
+    double a = el[0], e = el[1], inc = el[2], raan = el[3], argp = el[4];
+    double r = a * (1.0 - e * e) / (1.0 + e * cos(nu));
+    double v[3] = { r * cos(nu), r * sin(nu), 0.0 };
+    double w[3];
+    /* R_z(omega) */
+    w[0] = cos(argp) * v[0] - sin(argp) * v[1];
+    w[1] = sin(argp) * v[0] + cos(argp) * v[1];
+    w[2] = v[2];
+    /* R_x(i) */
+    v[0] = w[0];
+    v[1] = cos(inc) * w[1] - sin(inc) * w[2];
+    v[2] = sin(inc) * w[1] + cos(inc) * w[2];
+    /* R_z(Omega) */
+    pos[0] = cos(raan) * v[0] - sin(raan) * v[1];
+    pos[1] = sin(raan) * v[0] + cos(raan) * v[1];
+    pos[2] = v[2];
+}
+
+void or_position(const double el[6], double t_s, double mu, double pos[3])
+{
+    or_position_from_nu(el, or_true_anomaly(el, t_s, mu), pos);
+}
+
+/* Largest speed on a Kepler ellipse, reached at perigee (vis-viva at
+ * r = a(1 - e)). */
+double or_vmax(double a, double e, double mu)
+{
+    return sqrt(mu * (1.0 + e) / (a * (1.0 - e)));
+}
+
+/* ------------------------------------------------------------------------ */
+/* 4D boxes                                                                  */
+/* ------------------------------------------------------------------------ */
+
+uint64_t or_intervals(uint32_t dt, uint32_t T)
+{
+    if (T == 0)
+        return 1;
+    return ((uint64_t)T + dt - 1) / dt;
+}
+
+int64_t or_box_count(int64_t n, const uint32_t *dt, uint32_t T)
+{
+    int64_t N = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (dt[i] == 0)
+            return -1;
+        N += (int64_t)or_intervals(dt[i], T);
+    }
+    return N;
+}
+
+/* Each object's horizon [0, T] is cut into intervals of dt ticks, the last
+ * one clamped at T (advanceTime's clamp).  Interval k spans the continuous
+ * times [t_k, t_{k+1}] with t_k = min(k dt, T).  Its box is occ-int over that
+ * interval (the reading in the file header) and its tag is [t_k, t_{k+1}),
+ * with the last tag closed at T.  That gives the 4D occupancy region
+ * occ-int x interval of Def. 4D Occupancy Region. */
+int or_boxes(int64_t n, const double *el, const uint32_t *dt, uint32_t T,
+             double tick_s, double mu, double thr_km,
+             double *lo, double *hi, uint32_t *t0, uint32_t *t1, uint32_t *obj)
+{
+    if (T == UINT32_MAX)
+        return -1;
+    int64_t b = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        if (dt[i] == 0)
+            return -1;
+        const double *e6 = el + 6 * i;
+        double vmax = or_vmax(e6[0], e6[1], mu);
+        uint64_t K = or_intervals(dt[i], T);
+        for (uint64_t k = 0; k < K; ++k, ++b) {
+            uint64_t ta = k * dt[i] < T ? k * dt[i] : T;
+            uint64_t tb = (k + 1) * dt[i] < T ? (k + 1) * dt[i] : T;
+            double pa[3], pb[3];
+            or_position(e6, (double)ta * tick_s, mu, pa);
+            or_position(e6, (double)tb * tick_s, mu, pb);
+            double g = vmax * ((double)(tb - ta) * tick_s) / 2.0 + thr_km / 2.0;
+            for (int d = 0; d < 3; ++d) {
+                lo[3 * b + d] = fmin(pa[d], pb[d]) - g;
+                hi[3 * b + d] = fmax(pa[d], pb[d]) + g;
+            }
+            t0[b] = (uint32_t)ta;
+            t1[b] = (k + 1 == K) ? T + 1 : (uint32_t)tb;
+            obj[b] = (uint32_t)i;
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pair sets                                                                 */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    uint32_t *v;
+    int64_t n, cap;
+} or_vec;
+
+static void vec_push(or_vec *s, uint32_t i, uint32_t j, uint32_t a, uint32_t b)
+{
+    if (s->n == s->cap) {
+        s->cap = s->cap ? 2 * s->cap : 1024;
+        s->v = (uint32_t *)realloc(s->v, (size_t)s->cap * 4 * sizeof(uint32_t));
+    }
+    uint32_t *r = s->v + 4 * s->n++;
+    r[0] = i;
+    r[1] = j;
+    r[2] = a;
+    r[3] = b;
+}
+
+static int rec_cmp(const void *pa, const void *pb)
+{
+    const uint32_t *a = (const uint32_t *)pa, *b = (const uint32_t *)pb;
+    for (int k = 0; k < 4; ++k) {
+        if (a[k] < b[k])
+            return -1;
+        if (a[k] > b[k])
+            return 1;
+    }
+    return 0;
+}
+
+/* Concatenate per-thread record lists, sort lexicographically and drop
+ * repeated records: the canonical form of a pair set. */
+static int64_t canonical(or_vec *parts, int nparts, uint32_t **out)
+{
+    int64_t total = 0;
+    for (int t = 0; t < nparts; ++t)
+        total += parts[t].n;
+    uint32_t *all = (uint32_t *)malloc((size_t)(total > 0 ? total : 1) * 4 * sizeof(uint32_t));
+    int64_t at = 0;
+    for (int t = 0; t < nparts; ++t) {
+        if (parts[t].n)
+            memcpy(all + 4 * at, parts[t].v, (size_t)parts[t].n * 4 * sizeof(uint32_t));
+        at += parts[t].n;
+        free(parts[t].v);
+    }
+    qsort(all, (size_t)total, 4 * sizeof(uint32_t), rec_cmp);
+    int64_t m = 0;
+    for (int64_t r = 0; r < total; ++r)
+        if (m == 0 || rec_cmp(all + 4 * (m - 1), all + 4 * r) != 0) {
+            if (m != r)
+                memcpy(all + 4 * m, all + 4 * r, 4 * sizeof(uint32_t));
+            ++m;
+        }
+    *out = all;
+    return m;
+}
+
+/* Two 4D boxes intersect when their time tags overlap and, on every spatial
+ * axis, their closed extents overlap (Def. Collision applied to occ-4d). */
+static int boxes_overlap(const double *lo, const double *hi, const uint32_t *t0,
+                         const uint32_t *t1, int64_t a, int64_t b)
+{
+    if (!(t0[a] < t1[b] && t0[b] < t1[a]))
+        return 0;
+    for (int d = 0; d < 3; ++d)
+        if (!(lo[3 * a + d] <= hi[3 * b + d] && lo[3 * b + d] <= hi[3 * a + d]))
+            return 0;
+    return 1;
+}
+
+static void emit(or_vec *s, const uint32_t *t0, const uint32_t *t1,
+                 const uint32_t *obj, int64_t a, int64_t b)
+{
+    uint32_t i = obj[a] < obj[b] ? obj[a] : obj[b];
+    uint32_t j = obj[a] < obj[b] ? obj[b] : obj[a];
+    uint32_t tl = t0[a] > t0[b] ? t0[a] : t0[b];
+    uint32_t th = t1[a] < t1[b] ? t1[a] : t1[b];
+    vec_push(s, i, j, tl, th);
+}
+
+int or_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+int64_t or_pairs(int64_t N, const double *lo, const double *hi,
+                 const uint32_t *t0, const uint32_t *t1, const uint32_t *obj,
+                 uint32_t **out)
+{
+    int nt = or_num_threads();
+    or_vec *parts = (or_vec *)calloc((size_t)nt, sizeof(or_vec));
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t a = 0; a < N; ++a) {
+#ifdef _OPENMP
+        or_vec *mine = &parts[omp_get_thread_num()];
+#else
+        or_vec *mine = &parts[0];
+#endif
+        for (int64_t b = a + 1; b < N; ++b)
+            if (obj[a] != obj[b] && boxes_overlap(lo, hi, t0, t1, a, b))
+                emit(mine, t0, t1, obj, a, b);
+    }
+    int64_t m = canonical(parts, nt, out);
+    free(parts);
+    return m;
+}
+
+int64_t or_pairs_of(int64_t N, const double *lo, const double *hi,
+                    const uint32_t *t0, const uint32_t *t1, const uint32_t *obj,
+                    int64_t ns, const int64_t *sample, uint32_t **out)
+{
+    int nt = or_num_threads();
+    or_vec *parts = (or_vec *)calloc((size_t)nt, sizeof(or_vec));
+#pragma omp parallel for schedule(static)
+    for (int64_t b = 0; b < N; ++b) {
+#ifdef _OPENMP
+        or_vec *mine = &parts[omp_get_thread_num()];
+#else
+        or_vec *mine = &parts[0];
+#endif
+        for (int64_t s = 0; s < ns; ++s) {
+            int64_t a = sample[s];
+            if (a != b && obj[a] != obj[b] && boxes_overlap(lo, hi, t0, t1, a, b))
+                emit(mine, t0, t1, obj, a, b);
+        }
+    }
+    int64_t m = canonical(parts, nt, out);
+    free(parts);
+    return m;
+}
+
+int64_t or_time_overlapping_pairs(int64_t N, const uint32_t *t0,
+                                  const uint32_t *t1, const uint32_t *obj)
+{
+    int64_t c = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : c)
+    for (int64_t a = 0; a < N; ++a)
+        for (int64_t b = a + 1; b < N; ++b)
+            if (obj[a] != obj[b] && t0[a] < t1[b] && t0[b] < t1[a])
+                ++c;
+    return c;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Alg. Brute Force                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* For every multiple t of delta in [0, T], every pair i < j is tested for
+ * intersecting occupancy cubes: the closed cubes of radii r_i and r_j about
+ * the two positions meet exactly when the inf-norm distance of the centres is
+ * at most r_i + r_j.  The algorithm as printed stops at the first witness; it
+ * is run to the end here so that recall can be checked, and the first row of
+ * the output is its answer. */
+int64_t or_brute_force(int64_t n, const double *el, const double *r,
+                       uint32_t T, uint32_t delta, double tick_s, double mu,
+                       uint32_t **out)
+{
+    or_vec acc = { 0, 0, 0 };
+    double *p = (double *)malloc((size_t)(n > 0 ? n : 1) * 3 * sizeof(double));
+    if (delta == 0)
+        delta = 1;
+    for (uint64_t t = 0; t <= T; t += delta) {
+        for (int64_t i = 0; i < n; ++i)
+            or_position(el + 6 * i, (double)t * tick_s, mu, p + 3 * i);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = i + 1; j < n; ++j) {
+                double dmax = 0.0;
+                for (int d = 0; d < 3; ++d) {
+                    double dd = fabs(p[3 * i + d] - p[3 * j + d]);
+                    if (dd > dmax)
+                        dmax = dd;
+                }
+                if (dmax <= r[i] + r[j])
+                    vec_push(&acc, (uint32_t)t, (uint32_t)i, (uint32_t)j, 0);
+            }
+    }
+    free(p);
+    /* repack the 4-wide rows as 3-wide (t, i, j) */
+    uint32_t *res = (uint32_t *)malloc((size_t)(acc.n > 0 ? acc.n : 1) * 3 * sizeof(uint32_t));
+    for (int64_t k = 0; k < acc.n; ++k) {
+        res[3 * k + 0] = acc.v[4 * k + 0];
+        res[3 * k + 1] = acc.v[4 * k + 1];
+        res[3 * k + 2] = acc.v[4 * k + 2];
+    }
+    free(acc.v);
+    *out = res;
+    return acc.n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Growth pieces                                                             */
+/* ------------------------------------------------------------------------ */
+
+/* Largest float not above x: round to nearest, then step down once if that
+ * landed above. */
+float or_round_down_f32(double x)
+{
+    float f = (float)x;
+    if ((double)f > x)
+        f = nextafterf(f, -INFINITY);
+    return f;
+}
+
+/* Smallest float not below x. */
+float or_round_up_f32(double x)
+{
+    float f = (float)x;
+    if ((double)f < x)
+        f = nextafterf(f, INFINITY);
+    return f;
+}
+
+/* Per-object step: the largest whole number of ticks over which the object
+ * cannot move more than max_disp (speed bound vmax).  Any step gives
+ * conservative boxes; this one keeps every box's motion term near a fixed
+ * length. */
+void or_dt_heuristic(int64_t n, const double *el, double mu, double tick_s,
+                     double max_disp_km, uint32_t T, uint32_t *dt_out)
+{
+    double cap = T > 0 ? (double)T : 1.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double v = or_vmax(el[6 * i], el[6 * i + 1], mu);
+        double d = floor(max_disp_km / (v * tick_s));
+        if (!(d >= 1.0))
+            d = 1.0;
+        if (d > cap)
+            d = cap;
+        dt_out[i] = (uint32_t)d;
+    }
+}
+
+void or_outward_f32(int64_t m, const double *lo, const double *hi, float *lo32,
+                    float *hi32)
+{
+    for (int64_t k = 0; k < m; ++k) {
+        lo32[k] = or_round_down_f32(lo[k]);
+        hi32[k] = or_round_up_f32(hi[k]);
+    }
+}
+
+void or_free(void *p)
+{
+    free(p);
+}
