@@ -1,0 +1,214 @@
+/*
+ * cd4d.h -- C ABI of the MI355X (gfx950) 4D-AABB broad phase.
+ *
+ * Bak & Hobbs, "Efficient n-to-n Collision Detection for Space Debris using 4D
+ * AABB Trees".  The library answers the broad-phase half of the paper's
+ * problem (Def. Continuous / Discrete-Time n-to-n Collision Detection
+ * Problem, Sec. 2): given n world objects (Def. World Object) moving on Kepler
+ * orbits (Sec. 7.1) and a horizon T, it returns every candidate
+ *     (i, j, [t_lo, t_hi))   i < j
+ * whose 4D occupancy regions (Def. 4D Occupancy Region, Sec. 4) intersect.
+ * The paper's sequential tree (Alg. 4D AABB Tree Collision Detection) tests
+ * these box intersections one query at a time; here all of them are found in
+ * one bulk pass: boxes -> sorted Morton keys -> LBVH -> self-traversal ->
+ * canonical list.
+ *
+ * Conventions shared by every entry point:
+ *   - Units: km, s, rad.  Time is counted in integer ticks of tick_s seconds.
+ *   - Every pointer is a DEVICE pointer unless its name ends in _host.
+ *   - The caller allocates and owns all memory: elements, boxes, tree,
+ *     workspace and output.  The library allocates nothing and keeps no state
+ *     beyond a thread-local error string.
+ *   - Streams are hipStream_t values passed as void* (NULL = default stream).
+ *     Work is enqueued on that stream; functions marked "syncs" wait for it.
+ *   - Every function returns a status code; no exception crosses the ABI.
+ *     cd_last_error() gives a thread-local message for the last failure.
+ *   - Workspace sizes come from the matching *_ws query; passing less returns
+ *     CD_E_WORKSPACE before anything is enqueued.
+ */
+#ifndef CD4D_H
+#define CD4D_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define CD_OK 0
+#define CD_E_INVALID 1   /* bad argument: null pointer, n < 0, dt = 0, e outside [0,1), ... */
+#define CD_E_WORKSPACE 2 /* workspace (or tree buffer) smaller than required */
+#define CD_E_CAPACITY 3  /* more records than `capacity`; *count_host holds the need */
+#define CD_E_OVERFLOW 4  /* n, box count or T + 1 does not fit 32 bits */
+#define CD_E_DEVICE 5    /* HIP runtime error; see cd_last_error() */
+
+/* ---- precisions of boxes and trees ------------------------------------- */
+#define CD_FP64 0
+#define CD_FP32 1 /* outward-rounded: lo rounded down, hi rounded up */
+
+typedef void *cd_stream_t; /* a hipStream_t */
+
+/* Orbital elements of n objects, structure of arrays, FP64, device memory.
+ * a: semi-major axis (km, > 0); e: eccentricity in [0, 1); inc, raan, argp:
+ * inclination, right ascension of the ascending node, argument of perigee
+ * (rad); m0: mean anomaly at t = 0 (rad).  (Sec. 7.1 lists the true anomaly;
+ * the mean anomaly at epoch fixes it.) */
+typedef struct {
+    const double *a, *e, *inc, *raan, *argp, *m0;
+    int64_t n;
+} cd_elements;
+
+/* Run parameters.  threshold_km is the collision distance thr = 2r: every
+ * object is a world object with inf-norm radius r = thr / 2 (Def. World
+ * Object, Def. Occupancy Region).  horizon_ticks is T; its last tick is
+ * included, so T + 1 must fit 32 bits.  dt_ticks is the uniform time step,
+ * used when no per-object step array is given. */
+typedef struct {
+    double tick_s;          /* seconds per tick, e.g. 1e-3 */
+    double mu;              /* gravitational parameter, km^3/s^2 (398600.4418) */
+    double threshold_km;    /* thr >= 0 */
+    uint32_t horizon_ticks; /* T */
+    uint32_t dt_ticks;      /* uniform step (>= 1) when no dt array is given */
+} cd_params;
+
+/* A set of 4D boxes, structure of arrays, caller-owned device memory.
+ * Box b covers lo[d][b] <= x_d <= hi[d][b] (closed) during ticks
+ * t0[b] <= t < t1[b] and belongs to object obj[b].  lo/hi point to double
+ * (CD_FP64) or float (CD_FP32) arrays.
+ *
+ * Layout hints, written by cd_build_boxes and optional for caller-built boxes:
+ *   slab_ticks, slab_size: if slab_size > 0, boxes [s*slab_size,
+ *     (s+1)*slab_size) all have t0 / slab_ticks == s (time-major slabs);
+ *     the tree builder then sorts each slab inside one workgroup.
+ *   horizon_ticks: an upper bound on every t0 (used to size sort keys).
+ *   obj_count: an upper bound on obj + 1 (used to size sort keys); 0 means
+ *     "up to 2^32". */
+typedef struct {
+    int64_t count;
+    int precision;
+    void *lo[3], *hi[3];
+    uint32_t *t0, *t1, *obj;
+    uint32_t slab_ticks;
+    int64_t slab_size;
+    uint32_t horizon_ticks;
+    uint32_t obj_count;
+} cd_boxes;
+
+/* A linear BVH over a box set.  mem is a caller-owned device buffer of
+ * cd_tree_bytes(count, precision) bytes; cd_build_tree fills it and the
+ * remaining descriptor fields. */
+typedef struct {
+    void *mem;
+    size_t bytes;
+    int64_t count;      /* leaves */
+    int precision;
+    uint32_t slab_ticks;
+    uint32_t horizon_ticks;
+    uint32_t obj_count;
+} cd_tree;
+
+/* One candidate: objects i < j, whose boxes overlap during ticks
+ * [t_lo, t_hi) (t_hi = T + 1 marks an interval that ends at T inclusive). */
+typedef struct {
+    uint32_t i, j, t_lo, t_hi;
+} cd_pair;
+
+/* ---- diagnostics -------------------------------------------------------- */
+const char *cd_status_string(int status);
+const char *cd_last_error(void);
+int cd_version(void);
+
+/* Per-stage device time.  While enabled, every call records a hipEvent pair
+ * on its stream around each kernel stage ("boxes", "keys", "sort", "karras",
+ * "refit", "traverse", "canon").  cd_profile_read waits for the recorded
+ * events, accumulates elapsed milliseconds and launch counts per stage name,
+ * copies up to `max` entries (names are static strings) and returns how many
+ * stages exist; reset != 0 clears the totals.  Process-wide, guarded by a
+ * mutex; the events are created lazily and reused. */
+int cd_profile_enable(int on);
+int cd_profile_read(const char **names, double *ms_total, int64_t *launches, int max,
+                    int reset);
+
+/* ---- step 1: per-object time steps and box counts ----------------------- */
+
+/* Number of boxes the given steps produce: sum over objects of
+ * K_i = max(1, ceil(T / dt_i)).  Each object's interval sequence follows
+ * procedure advanceTime (Sec. 4.3): consecutive intervals on the tick grid,
+ * the last one clamped at T.  dt_ticks may be NULL (uniform params->dt_ticks;
+ * no device work) or a device array of n steps (syncs; CD_E_INVALID if any
+ * step is 0).  ws must hold cd_box_count_ws(n) bytes. */
+size_t cd_box_count_ws(int64_t n);
+int cd_box_count(const uint32_t *dt_ticks, int64_t n, const cd_params *p,
+                 int64_t *count_host, void *ws, size_t ws_bytes, cd_stream_t stream);
+
+/* Checks every element (finite; a > 0; 0 <= e < 1).  Syncs.  On failure
+ * returns CD_E_INVALID and *bad_index_host = first offending object. */
+size_t cd_validate_ws(int64_t n);
+int cd_validate_elements(const cd_elements *el, int64_t *bad_index_host, void *ws,
+                         size_t ws_bytes, cd_stream_t stream);
+
+/* Per-object step from the speed bound (config "interval displacement <=
+ * max_disp_km"): dt_i = clamp(floor(max_disp_km / (vmax_i * tick_s)), 1,
+ * max(T, 1)) ticks, vmax_i the perigee speed.  Any step keeps the boxes
+ * conservative; this one bounds each box's motion term.  Async. */
+int cd_dt_heuristic(const cd_elements *el, const cd_params *p, double max_disp_km,
+                    uint32_t *dt_out, cd_stream_t stream);
+
+/* ---- step 2: 4D boxes (Def. Interval Occupancy Region, 4D Occupancy) ----- */
+
+/* Builds every box.  For object i and interval k, with t_k = min(k dt_i, T):
+ *   positions p_a = pos(t_k), p_b = pos(t_{k+1}) by Kepler propagation (the
+ *   exact solution of Eq. nu-dot, mapped to ECI by the three rotations of
+ *   Sec. 7.1), in FP64;
+ *   g = vmax_i (t_{k+1} - t_k) tick_s / 2 + thr / 2;
+ *   lo = min(p_a, p_b) - g, hi = max(p_a, p_b) + g per axis;
+ *   tag [t_k, t_{k+1}), the last one [t_{K-1}, T + 1).
+ * The box holds every position in the interval (speed bound) and equals the
+ * occupancy cube at a single instant (Property 1).  With a CD_FP32 output the
+ * FP64 bounds are rounded outward.
+ * Order: uniform step (dt_ticks NULL) -> time-major, box (i,k) at k*n + i, and
+ * out->slab_size = n, out->slab_ticks = dt.  Per-object steps -> object-major,
+ * box (i,k) at off_i + k.  out->count must equal cd_box_count's result and
+ * out's arrays must hold that many entries.  Async; element validity is not
+ * rechecked here (see cd_validate_elements). */
+size_t cd_build_boxes_ws(int64_t n);
+int cd_build_boxes(const cd_elements *el, const uint32_t *dt_ticks, const cd_params *p,
+                   cd_boxes *out, void *ws, size_t ws_bytes, cd_stream_t stream);
+
+/* ---- step 3: the tree (Morton keys, LDS radix sort, Karras LBVH, refit) -- */
+
+/* Builds an LBVH over the boxes (the AABB tree of Sec. 3.2, built in bulk):
+ * each box gets a time-major key [t0 / slab_ticks | 30-bit Morton code of its
+ * centre]; keys are radix-sorted (inside one workgroup's LDS per slab when
+ * the slab hint is set, device-wide otherwise); a Karras hierarchy is built
+ * over the sorted keys and every inner box is set to the exact union of its
+ * children by an atomic bottom-up pass, so an inner node overlaps whatever
+ * its leaves overlap.  precision CD_FP32 is allowed for FP64 boxes (outward
+ * rounding at the leaves).  slab_ticks = 0 takes boxes->slab_ticks, else 1.
+ * Async. */
+size_t cd_tree_bytes(int64_t count, int precision);
+size_t cd_build_tree_ws(int64_t count);
+int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_tree *tree,
+                  void *ws, size_t ws_bytes, cd_stream_t stream);
+
+/* ---- step 4: the n-to-n query ------------------------------------------- */
+
+/* Self-traversal of the tree: every pair of boxes of different objects whose
+ * time tags overlap (t0_a < t1_b and t0_b < t1_a) and whose closed 3D
+ * extents overlap on every axis gives one record
+ *   (min(obj), max(obj), max(t0_a, t0_b), min(t1_a, t1_b)).
+ * The list written to out is sorted by (i, j, t_lo, t_hi) and free of
+ * repeats.  Syncs (it reads the record count).  If more than `capacity`
+ * records exist, returns CD_E_CAPACITY with *count_host = the number needed;
+ * out is then unspecified, the tree is untouched and the call can be repeated
+ * with a larger buffer and workspace. */
+size_t cd_query_pairs_ws(int64_t count, int64_t capacity);
+int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t *count_host,
+                   void *ws, size_t ws_bytes, cd_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

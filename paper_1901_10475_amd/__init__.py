@@ -1,0 +1,342 @@
+"""MI355X (gfx950) 4D-AABB broad phase for n-to-n orbital collision detection.
+
+Python binding of the C ABI in ``include/cd4d.h`` (library ``libcd4d.so``,
+hand-written HIP kernels).  This module only marshals arguments: PyTorch
+supplies device memory and the current HIP stream, every step of the path runs
+in the library's kernels, and there is no CPU fallback -- importing the module
+without the built library raises.
+
+The functions below keep the C names (``cd_build_boxes``, ``cd_build_tree``,
+``cd_query_pairs``, ...).  ``BroadPhase`` holds one set of buffers and runs the
+three steps in order for repeated queries.
+"""
+import ctypes
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libcd4d.so")
+
+CD_OK, CD_E_INVALID, CD_E_WORKSPACE, CD_E_CAPACITY, CD_E_OVERFLOW, CD_E_DEVICE = range(6)
+CD_FP64, CD_FP32 = 0, 1
+
+_vp = ctypes.c_void_p
+
+
+class cd_elements(ctypes.Structure):
+    _fields_ = [("a", _vp), ("e", _vp), ("inc", _vp), ("raan", _vp), ("argp", _vp),
+                ("m0", _vp), ("n", ctypes.c_int64)]
+
+
+class cd_params(ctypes.Structure):
+    _fields_ = [("tick_s", ctypes.c_double), ("mu", ctypes.c_double),
+                ("threshold_km", ctypes.c_double), ("horizon_ticks", ctypes.c_uint32),
+                ("dt_ticks", ctypes.c_uint32)]
+
+
+class cd_boxes(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int64), ("precision", ctypes.c_int), ("lo", _vp * 3),
+                ("hi", _vp * 3), ("t0", _vp), ("t1", _vp), ("obj", _vp),
+                ("slab_ticks", ctypes.c_uint32), ("slab_size", ctypes.c_int64),
+                ("horizon_ticks", ctypes.c_uint32), ("obj_count", ctypes.c_uint32)]
+
+
+class cd_tree(ctypes.Structure):
+    _fields_ = [("mem", _vp), ("bytes", ctypes.c_size_t), ("count", ctypes.c_int64),
+                ("precision", ctypes.c_int), ("slab_ticks", ctypes.c_uint32),
+                ("horizon_ticks", ctypes.c_uint32), ("obj_count", ctypes.c_uint32)]
+
+
+class CDError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{_status_name(status)} ({status}): {message}")
+        self.status = status
+
+
+def _status_name(s):
+    return {0: "CD_OK", 1: "CD_E_INVALID", 2: "CD_E_WORKSPACE", 3: "CD_E_CAPACITY",
+            4: "CD_E_OVERFLOW", 5: "CD_E_DEVICE"}.get(s, "CD_E_?")
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libcd4d.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            raise ImportError(f"{_LIB_PATH} is missing: build it with "
+                              "`python -m paper_1901_10475_amd.build`")
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.POINTER
+        i64, u32, sz, dbl = ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t, ctypes.c_double
+        sig = {
+            "cd_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+            "cd_last_error": (ctypes.c_char_p, []),
+            "cd_version": (ctypes.c_int, []),
+            "cd_profile_enable": (ctypes.c_int, [ctypes.c_int]),
+            "cd_profile_read": (ctypes.c_int, [P(ctypes.c_char_p), P(dbl), P(i64), ctypes.c_int,
+                                               ctypes.c_int]),
+            "cd_box_count_ws": (sz, [i64]),
+            "cd_box_count": (ctypes.c_int, [_vp, i64, P(cd_params), P(i64), _vp, sz, _vp]),
+            "cd_validate_ws": (sz, [i64]),
+            "cd_validate_elements": (ctypes.c_int, [P(cd_elements), P(i64), _vp, sz, _vp]),
+            "cd_dt_heuristic": (ctypes.c_int, [P(cd_elements), P(cd_params), dbl, _vp, _vp]),
+            "cd_build_boxes_ws": (sz, [i64]),
+            "cd_build_boxes": (ctypes.c_int, [P(cd_elements), _vp, P(cd_params), P(cd_boxes),
+                                              _vp, sz, _vp]),
+            "cd_tree_bytes": (sz, [i64, ctypes.c_int]),
+            "cd_build_tree_ws": (sz, [i64]),
+            "cd_build_tree": (ctypes.c_int, [P(cd_boxes), ctypes.c_int, u32, P(cd_tree), _vp,
+                                             sz, _vp]),
+            "cd_query_pairs_ws": (sz, [i64, i64]),
+            "cd_query_pairs": (ctypes.c_int, [P(cd_tree), _vp, i64, P(i64), _vp, sz, _vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("cd_status_string", "cd_last_error", "cd_version", "cd_profile_enable",
+            "cd_profile_read", "cd_box_count_ws",
+            "cd_box_count", "cd_validate_ws", "cd_validate_elements", "cd_dt_heuristic",
+            "cd_build_boxes_ws", "cd_build_boxes", "cd_tree_bytes", "cd_build_tree_ws",
+            "cd_build_tree", "cd_query_pairs_ws", "cd_query_pairs")
+
+
+def cd_profile_enable(on=True):
+    lib().cd_profile_enable(1 if on else 0)
+
+
+def cd_profile_read(reset=True):
+    """{stage: (total_ms, launches)} accumulated since the last reset (syncs)."""
+    m = 32
+    names = (ctypes.c_char_p * m)()
+    ms = (ctypes.c_double * m)()
+    ln = (ctypes.c_int64 * m)()
+    k = lib().cd_profile_read(names, ms, ln, m, 1 if reset else 0)
+    if k < 0:
+        _check(k)
+    return {names[i].decode(): (ms[i], ln[i]) for i in range(min(k, m))}
+
+
+def _check(rc):
+    if rc != CD_OK:
+        raise CDError(rc, lib().cd_last_error().decode())
+    return rc
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _bytes(nbytes, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+# ---- argument marshalling -----------------------------------------------------
+
+def elements_struct(el_soa):
+    """el_soa: float64 CUDA tensor [6, n] (rows a, e, inc, raan, argp, m0)."""
+    assert el_soa.dtype == torch.float64 and el_soa.is_cuda and el_soa.dim() == 2
+    assert el_soa.shape[0] == 6 and el_soa.is_contiguous()
+    n = el_soa.shape[1]
+    rows = [ctypes.c_void_p(el_soa[k].data_ptr() if n else 0) for k in range(6)]
+    return cd_elements(*rows, n)
+
+
+def params_struct(tick_s, mu, threshold_km, horizon_ticks, dt_ticks=0):
+    return cd_params(float(tick_s), float(mu), float(threshold_km), int(horizon_ticks),
+                     int(dt_ticks))
+
+
+class Boxes:
+    """Device box arrays (SoA) plus the cd_boxes descriptor."""
+
+    def __init__(self, count, precision, device="cuda"):
+        ft = torch.float64 if precision == CD_FP64 else torch.float32
+        self.count, self.precision = int(count), precision
+        self.lo = torch.empty((3, max(count, 1)), dtype=ft, device=device)
+        self.hi = torch.empty((3, max(count, 1)), dtype=ft, device=device)
+        self.t0 = torch.empty(max(count, 1), dtype=torch.int32, device=device)
+        self.t1 = torch.empty(max(count, 1), dtype=torch.int32, device=device)
+        self.obj = torch.empty(max(count, 1), dtype=torch.int32, device=device)
+        self.desc = cd_boxes()
+        self.desc.count = self.count
+        self.desc.precision = precision
+        for d in range(3):
+            self.desc.lo[d] = self.lo[d].data_ptr()
+            self.desc.hi[d] = self.hi[d].data_ptr()
+        self.desc.t0 = self.t0.data_ptr()
+        self.desc.t1 = self.t1.data_ptr()
+        self.desc.obj = self.obj.data_ptr()
+
+    @classmethod
+    def from_arrays(cls, lo, hi, t0, t1, obj, precision=CD_FP64, horizon_ticks=0,
+                    obj_count=0, slab_ticks=0, slab_size=0, device="cuda"):
+        """Caller-built boxes from host arrays lo/hi [N,3], t0/t1/obj [N]."""
+        import numpy as np
+        N = len(t0)
+        b = cls(N, precision, device)
+        npf = np.float64 if precision == CD_FP64 else np.float32
+        if N:
+            b.lo[:, :N].copy_(torch.from_numpy(np.ascontiguousarray(np.asarray(lo, npf).T)))
+            b.hi[:, :N].copy_(torch.from_numpy(np.ascontiguousarray(np.asarray(hi, npf).T)))
+            b.t0[:N].copy_(torch.from_numpy(np.asarray(t0, np.uint32).view(np.int32)))
+            b.t1[:N].copy_(torch.from_numpy(np.asarray(t1, np.uint32).view(np.int32)))
+            b.obj[:N].copy_(torch.from_numpy(np.asarray(obj, np.uint32).view(np.int32)))
+        b.desc.horizon_ticks = int(horizon_ticks) if horizon_ticks else int(
+            np.max(np.asarray(t0, np.uint64)) if N else 0)
+        b.desc.obj_count = int(obj_count) if obj_count else int(
+            np.max(np.asarray(obj, np.uint64)) + 1 if N else 0)
+        b.desc.slab_ticks = int(slab_ticks)
+        b.desc.slab_size = int(slab_size)
+        return b
+
+    def to_host(self):
+        """(lo [N,3] f64, hi [N,3] f64, t0, t1, obj uint32) as numpy arrays."""
+        import numpy as np
+        N = self.count
+        lo = self.lo[:, :N].T.double().cpu().numpy()
+        hi = self.hi[:, :N].T.double().cpu().numpy()
+        u = lambda t: t[:N].cpu().numpy().view(np.uint32)
+        return lo, hi, u(self.t0), u(self.t1), u(self.obj)
+
+
+class Tree:
+    def __init__(self, count, precision, device="cuda"):
+        nbytes = lib().cd_tree_bytes(int(count), precision)
+        self.mem = _bytes(nbytes, device)
+        self.desc = cd_tree()
+        self.desc.mem = self.mem.data_ptr()
+        self.desc.bytes = nbytes
+
+
+# ---- the C functions, marshalled ----------------------------------------------------
+
+def cd_box_count(dt_ticks, n, params, device="cuda"):
+    """Box count for per-object steps (int32/uint32 CUDA tensor) or, with
+    dt_ticks None, for the uniform params.dt_ticks."""
+    out = ctypes.c_int64(0)
+    if dt_ticks is None:
+        _check(lib().cd_box_count(None, int(n), ctypes.byref(params), ctypes.byref(out), None, 0,
+                                  _stream()))
+    else:
+        ws = _bytes(lib().cd_box_count_ws(int(n)), device)
+        _check(lib().cd_box_count(_ptr(dt_ticks), int(n), ctypes.byref(params),
+                                  ctypes.byref(out), _ptr(ws), ws.numel(), _stream()))
+    return out.value
+
+
+def cd_validate_elements(el_soa, device="cuda"):
+    el = elements_struct(el_soa)
+    ws = _bytes(lib().cd_validate_ws(el.n), device)
+    bad = ctypes.c_int64(-1)
+    rc = lib().cd_validate_elements(ctypes.byref(el), ctypes.byref(bad), _ptr(ws), ws.numel(),
+                                    _stream())
+    if rc == CD_E_INVALID and bad.value >= 0:
+        raise CDError(rc, lib().cd_last_error().decode())
+    _check(rc)
+
+
+def cd_dt_heuristic(el_soa, params, max_disp_km, dt_out):
+    el = elements_struct(el_soa)
+    _check(lib().cd_dt_heuristic(ctypes.byref(el), ctypes.byref(params), float(max_disp_km),
+                                 _ptr(dt_out), _stream()))
+
+
+def cd_build_boxes(el_soa, dt_ticks, params, boxes, ws):
+    el = elements_struct(el_soa)
+    _check(lib().cd_build_boxes(ctypes.byref(el), _ptr(dt_ticks) if dt_ticks is not None else None,
+                                ctypes.byref(params), ctypes.byref(boxes.desc), _ptr(ws),
+                                ws.numel(), _stream()))
+
+
+def cd_build_tree(boxes, precision, tree, ws, slab_ticks=0):
+    _check(lib().cd_build_tree(ctypes.byref(boxes.desc), precision, int(slab_ticks),
+                               ctypes.byref(tree.desc), _ptr(ws), ws.numel(), _stream()))
+
+
+def cd_query_pairs(tree, out, capacity, ws):
+    """Returns (status, count).  CD_E_CAPACITY is returned, not raised, with the
+    number of records needed."""
+    cnt = ctypes.c_int64(0)
+    rc = lib().cd_query_pairs(ctypes.byref(tree.desc), _ptr(out), int(capacity),
+                              ctypes.byref(cnt), _ptr(ws), ws.numel(), _stream())
+    if rc not in (CD_OK, CD_E_CAPACITY):
+        _check(rc)
+    return rc, cnt.value
+
+
+class BroadPhase:
+    """Buffers for repeated queries over one catalog shape.
+
+    ``run(el_soa)`` builds the boxes, the tree and the canonical pair list;
+    returns an int32 CUDA tensor [P, 4] (i, j, t_lo, t_hi; read as uint32).
+    Buffers are allocated here and grown only when the pair count exceeds the
+    current capacity (then the query alone is repeated).
+    """
+
+    def __init__(self, n, params, dt_ticks=None, box_precision=CD_FP64,
+                 tree_precision=CD_FP64, capacity=None, slab_ticks=0, device="cuda"):
+        self.n, self.params, self.dt = int(n), params, dt_ticks
+        self.device = device
+        self.count = cd_box_count(dt_ticks, n, params, device)
+        self.boxes = Boxes(self.count, box_precision, device)
+        self.tree_precision = tree_precision
+        self.tree = Tree(self.count, tree_precision, device)
+        self.ws_boxes = _bytes(lib().cd_build_boxes_ws(self.n), device)
+        self.ws_tree = _bytes(lib().cd_build_tree_ws(self.count), device)
+        self.slab_ticks = slab_ticks
+        self._alloc_query(capacity if capacity is not None else max(1 << 16, self.count // 64))
+
+    def _alloc_query(self, cap):
+        self.capacity = int(cap)
+        self.out = torch.empty((max(self.capacity, 1), 4), dtype=torch.int32, device=self.device)
+        self.ws_query = _bytes(lib().cd_query_pairs_ws(self.count, self.capacity), self.device)
+
+    def build(self, el_soa):
+        cd_build_boxes(el_soa, self.dt, self.params, self.boxes, self.ws_boxes)
+        cd_build_tree(self.boxes, self.tree_precision, self.tree, self.ws_tree, self.slab_ticks)
+
+    def query(self):
+        rc, cnt = cd_query_pairs(self.tree, self.out, self.capacity, self.ws_query)
+        if rc == CD_E_CAPACITY:
+            self._alloc_query(int(cnt * 1.25) + 1024)
+            rc, cnt = cd_query_pairs(self.tree, self.out, self.capacity, self.ws_query)
+            _check(rc)
+        return self.out[:cnt]
+
+    def run(self, el_soa):
+        self.build(el_soa)
+        return self.query()
+
+
+def query_boxes(boxes, tree_precision=CD_FP64, slab_ticks=0, capacity=1 << 16):
+    """Tree + canonical pairs over caller-built ``Boxes``."""
+    tree = Tree(boxes.count, tree_precision, boxes.lo.device)
+    ws = _bytes(lib().cd_build_tree_ws(boxes.count), boxes.lo.device)
+    cd_build_tree(boxes, tree_precision, tree, ws, slab_ticks)
+    while True:
+        out = torch.empty((max(capacity, 1), 4), dtype=torch.int32, device=boxes.lo.device)
+        wsq = _bytes(lib().cd_query_pairs_ws(boxes.count, capacity), boxes.lo.device)
+        rc, cnt = cd_query_pairs(tree, out, capacity, wsq)
+        if rc == CD_OK:
+            return out[:cnt]
+        capacity = int(cnt * 1.25) + 1024
+
+
+def soa(elements_np, device="cuda"):
+    """Host [n, 6] element rows -> device [6, n] float64 (the library's layout)."""
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(elements_np, np.float64).reshape(-1, 6).T)
+    return torch.from_numpy(a).to(device)

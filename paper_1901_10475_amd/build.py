@@ -1,0 +1,62 @@
+"""Build the HIP library (gfx950) and the host-side tree checker.
+
+    python -m paper_1901_10475_amd.build
+
+Sources are compiled in parallel with hipcc into objects under _build/ and
+linked in-tree as paper_1901_10475_amd/libcd4d.so (and libcd4d_hostcheck.so,
+which runs the LBVH index arithmetic on the CPU for the pre-flight tests).
+"""
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+BUILD = os.path.join(ROOT, "_build")
+ARCH = os.environ.get("CD4D_ARCH", "gfx950")
+
+LIB_SOURCES = ["k_boxes.hip", "k_sort.hip", "k_tree.hip", "k_query.hip", "cd_api.cpp"]
+HOSTCHECK_SOURCES = ["cd_hostcheck.cpp"]
+
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+          "-Wall", "-Wno-unused-function"]
+# packed FP32 instructions are left out of every code object
+DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def _compile(src, verbose):
+    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    lang = ["-x", "hip"] if src.endswith(".hip") else []
+    cmd = ["hipcc"] + lang + COMMON + DEVICE + ["-c", os.path.join(CSRC, src), "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+    if verbose and r.stderr.strip():
+        print(r.stderr, file=sys.stderr)
+    return obj
+
+
+def _link(objs, out, verbose):
+    cmd = ["hipcc", "-shared", "-fPIC", "--offload-arch=" + ARCH] + objs + ["-o", out + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(out + ".tmp", out)
+
+
+def build(verbose=False):
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = LIB_SOURCES + HOSTCHECK_SOURCES
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        objs = dict(zip(srcs, ex.map(lambda s: _compile(s, verbose), srcs)))
+    _link([objs[s] for s in LIB_SOURCES], os.path.join(PKG, "libcd4d.so"), verbose)
+    _link([objs[s] for s in HOSTCHECK_SOURCES], os.path.join(PKG, "libcd4d_hostcheck.so"),
+          verbose)
+
+
+if __name__ == "__main__":
+    build(verbose=True)

@@ -1,0 +1,658 @@
+// cd_api.cpp -- the C ABI of include/cd4d.h: argument checks, workspace
+// layout and the order of launches.  All arithmetic runs in the kernels.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "cd_internal.h"
+
+using namespace cd;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define CD_HIP(x)                                                                          \
+    do {                                                                                   \
+        hipError_t e_ = (x);                                                               \
+        if (e_ != hipSuccess)                                                              \
+            return fail(CD_E_DEVICE, "%s failed: %s", #x, hipGetErrorString(e_));           \
+    } while (0)
+
+// ---- stage timing (cd_profile_*) ----
+struct ProfPending {
+    const char *name;
+    hipEvent_t a, b;
+};
+struct ProfTotal {
+    const char *name;
+    double ms;
+    int64_t launches;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfPending> g_prof_pending;
+std::vector<hipEvent_t> g_prof_pool;
+std::vector<ProfTotal> g_prof_totals;
+
+hipEvent_t prof_event()
+{
+    if (!g_prof_pool.empty()) {
+        hipEvent_t e = g_prof_pool.back();
+        g_prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess)
+        return nullptr;
+    return e;
+}
+
+// Records an event pair around a stage when profiling is on.
+struct Stage {
+    const char *name;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    Stage(const char *n, hipStream_t st) : name(n), s(st)
+    {
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        if (!g_prof_on)
+            return;
+        a = prof_event();
+        if (a && hipEventRecord(a, s) != hipSuccess) {
+            g_prof_pool.push_back(a);
+            a = nullptr;
+        }
+    }
+    ~Stage()
+    {
+        if (!a)
+            return;
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        hipEvent_t b = prof_event();
+        if (b && hipEventRecord(b, s) == hipSuccess)
+            g_prof_pending.push_back({name, a, b});
+        else {
+            g_prof_pool.push_back(a);
+            if (b)
+                g_prof_pool.push_back(b);
+        }
+    }
+};
+
+constexpr int64_t kMaxBoxes = (1ll << 31) - 1;  // node ids of 2N - 1 nodes fit 32 bits
+constexpr size_t kTreeHeader = 256;             // uint32 error word + padding
+constexpr uint32_t kChunk = 16;                 // intervals per thread, per-object steps
+
+int check_params(const cd_params *p)
+{
+    if (!p)
+        return fail(CD_E_INVALID, "params is NULL");
+    if (!(p->tick_s > 0.0) || !isfinite(p->tick_s))
+        return fail(CD_E_INVALID, "tick_s must be finite and > 0");
+    if (!(p->mu > 0.0) || !isfinite(p->mu))
+        return fail(CD_E_INVALID, "mu must be finite and > 0");
+    if (!(p->threshold_km >= 0.0) || !isfinite(p->threshold_km))
+        return fail(CD_E_INVALID, "threshold_km must be finite and >= 0");
+    if (p->horizon_ticks == 0xFFFFFFFFu)
+        return fail(CD_E_OVERFLOW, "horizon_ticks + 1 must fit 32 bits");
+    return CD_OK;
+}
+
+int check_elements(const cd_elements *el)
+{
+    if (!el)
+        return fail(CD_E_INVALID, "elements is NULL");
+    if (el->n < 0)
+        return fail(CD_E_INVALID, "n < 0");
+    if (el->n >= (1ll << 31))
+        return fail(CD_E_OVERFLOW, "n must be < 2^31");
+    if (el->n > 0 && (!el->a || !el->e || !el->inc || !el->raan || !el->argp || !el->m0))
+        return fail(CD_E_INVALID, "element array is NULL");
+    return CD_OK;
+}
+
+uint64_t intervals(uint32_t dt, uint32_t T) { return T == 0 ? 1 : ((uint64_t)T + dt - 1) / dt; }
+
+int bits_for(uint64_t v)  // bits needed to hold values 0..v
+{
+    int b = 0;
+    while (b < 64 && (v >> b) != 0)
+        ++b;
+    return b;
+}
+
+BoxView view_of(const cd_boxes *b)
+{
+    BoxView v;
+    for (int d = 0; d < 3; ++d) {
+        v.lo[d] = b->lo[d];
+        v.hi[d] = b->hi[d];
+    }
+    v.t0 = b->t0;
+    v.t1 = b->t1;
+    v.obj = b->obj;
+    return v;
+}
+
+uint32_t default_slab(uint32_t horizon) { return horizon / 4096u > 0 ? horizon / 4096u : 1u; }
+
+// ---- workspace layouts (shared by the *_ws queries and the calls) ----
+
+struct CountWS {
+    ObjSteps *st;
+    uint32_t *Kc, *Cc;
+    unsigned long long *totals;
+    unsigned int *bad;
+};
+size_t layout_count(void *base, size_t bytes, int64_t n, CountWS *w)
+{
+    Carve c(base, bytes);
+    w->st = c.take<ObjSteps>(n);
+    w->Kc = c.take<uint32_t>(n);
+    w->Cc = c.take<uint32_t>(n);
+    w->totals = c.take<unsigned long long>(2);
+    w->bad = c.take<unsigned int>(1);
+    return c.off;
+}
+
+struct BoxWS {
+    CountWS cnt;
+    ObjConst *oc;
+    uint32_t *box_off, *chunk_off;
+    void *scan;
+};
+size_t layout_boxes(void *base, size_t bytes, int64_t n, BoxWS *w)
+{
+    size_t off = layout_count(base, bytes, n, &w->cnt);
+    Carve c(base, bytes);
+    c.off = off;
+    w->oc = c.take<ObjConst>(n);
+    w->box_off = c.take<uint32_t>(n);
+    w->chunk_off = c.take<uint32_t>(n);
+    w->scan = c.take_bytes(scan_ws_bytes((size_t)n));
+    return c.off;
+}
+
+struct TreeWS {
+    uint32_t *morton;
+    KV *kva, *kvb;
+    uint64_t *keys;
+    uint32_t *idx, *parent, *arrive;
+    unsigned long long *bounds;
+    void *radix;
+};
+size_t layout_tree(void *base, size_t bytes, int64_t N, TreeWS *w)
+{
+    Carve c(base, bytes);
+    size_t n = (size_t)(N > 0 ? N : 1);
+    w->morton = c.take<uint32_t>(n);
+    w->kva = c.take<KV>(n);
+    w->kvb = c.take<KV>(n);
+    w->keys = c.take<uint64_t>(n);
+    w->idx = c.take<uint32_t>(n);
+    w->parent = c.take<uint32_t>(2 * n);
+    w->arrive = c.take<uint32_t>(n);
+    w->bounds = c.take<unsigned long long>(6);
+    w->radix = c.take_bytes(radix_ws_bytes(n));
+    return c.off;
+}
+
+struct QueryWS {
+    Rec *raw, *alt;
+    unsigned long long *counter;
+    uint32_t *flags, *pos;
+    void *scan, *radix;
+};
+size_t layout_query(void *base, size_t bytes, int64_t cap, QueryWS *w)
+{
+    Carve c(base, bytes);
+    size_t m = (size_t)(cap > 0 ? cap : 1);
+    w->raw = c.take<Rec>(m);
+    w->alt = c.take<Rec>(m);
+    w->counter = c.take<unsigned long long>(1);
+    w->flags = c.take<uint32_t>(m);
+    w->pos = c.take<uint32_t>(m + 1);
+    w->scan = c.take_bytes(scan_ws_bytes(m));
+    w->radix = c.take_bytes(radix_ws_bytes(m));
+    return c.off;
+}
+
+} // namespace
+
+extern "C" {
+
+const char *cd_status_string(int status)
+{
+    switch (status) {
+    case CD_OK: return "ok";
+    case CD_E_INVALID: return "invalid argument";
+    case CD_E_WORKSPACE: return "workspace too small";
+    case CD_E_CAPACITY: return "output capacity too small";
+    case CD_E_OVERFLOW: return "size does not fit 32 bits";
+    case CD_E_DEVICE: return "HIP runtime error";
+    default: return "unknown status";
+    }
+}
+
+const char *cd_last_error(void) { return g_err; }
+
+int cd_version(void) { return 1; }
+
+int cd_profile_enable(int on)
+{
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof_on = on != 0;
+    return CD_OK;
+}
+
+int cd_profile_read(const char **names, double *ms_total, int64_t *launches, int max, int reset)
+{
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    for (auto &p : g_prof_pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(p.b) != hipSuccess || hipEventElapsedTime(&ms, p.a, p.b) !=
+                                                          hipSuccess)
+            return fail(CD_E_DEVICE, "reading stage events failed");
+        bool found = false;
+        for (auto &t : g_prof_totals)
+            if (strcmp(t.name, p.name) == 0) {
+                t.ms += ms;
+                t.launches += 1;
+                found = true;
+            }
+        if (!found)
+            g_prof_totals.push_back({p.name, (double)ms, 1});
+        g_prof_pool.push_back(p.a);
+        g_prof_pool.push_back(p.b);
+    }
+    g_prof_pending.clear();
+    int n = (int)g_prof_totals.size();
+    for (int k = 0; k < n && k < max; ++k) {
+        if (names)
+            names[k] = g_prof_totals[k].name;
+        if (ms_total)
+            ms_total[k] = g_prof_totals[k].ms;
+        if (launches)
+            launches[k] = g_prof_totals[k].launches;
+    }
+    if (reset)
+        g_prof_totals.clear();
+    return n;
+}
+
+// ---- step 1 -----------------------------------------------------------------------------
+
+size_t cd_box_count_ws(int64_t n)
+{
+    CountWS w;
+    return layout_count(nullptr, 0, n > 0 ? n : 0, &w);
+}
+
+int cd_box_count(const uint32_t *dt_ticks, int64_t n, const cd_params *p, int64_t *count_host,
+                 void *ws, size_t ws_bytes, cd_stream_t stream)
+{
+    int rc = check_params(p);
+    if (rc)
+        return rc;
+    if (!count_host)
+        return fail(CD_E_INVALID, "count_host is NULL");
+    if (n < 0)
+        return fail(CD_E_INVALID, "n < 0");
+    if (n >= (1ll << 31))
+        return fail(CD_E_OVERFLOW, "n must be < 2^31");
+    *count_host = 0;
+    if (n == 0)
+        return CD_OK;
+    uint64_t total;
+    if (!dt_ticks) {
+        if (p->dt_ticks == 0)
+            return fail(CD_E_INVALID, "dt_ticks must be >= 1");
+        total = (uint64_t)n * intervals(p->dt_ticks, p->horizon_ticks);
+    } else {
+        if (ws_bytes < cd_box_count_ws(n) || !ws)
+            return fail(CD_E_WORKSPACE, "box-count workspace too small");
+        hipStream_t s = (hipStream_t)stream;
+        CountWS w;
+        layout_count(ws, ws_bytes, n, &w);
+        CD_HIP(launch_steps(dt_ticks, (uint32_t)n, p->horizon_ticks, kChunk, w.st, w.Kc, w.Cc,
+                            w.totals, w.bad, s));
+        unsigned long long h[2];
+        unsigned int bad = 0;
+        CD_HIP(hipMemcpyAsync(h, w.totals, sizeof h, hipMemcpyDeviceToHost, s));
+        CD_HIP(hipMemcpyAsync(&bad, w.bad, sizeof bad, hipMemcpyDeviceToHost, s));
+        CD_HIP(hipStreamSynchronize(s));
+        if (bad)
+            return fail(CD_E_INVALID, "a per-object dt_ticks is 0");
+        total = h[0];
+    }
+    if (total > (uint64_t)kMaxBoxes)
+        return fail(CD_E_OVERFLOW, "box count %llu exceeds 2^31 - 1",
+                    (unsigned long long)total);
+    *count_host = (int64_t)total;
+    return CD_OK;
+}
+
+size_t cd_validate_ws(int64_t n) { return 256; }
+
+int cd_validate_elements(const cd_elements *el, int64_t *bad_index_host, void *ws,
+                         size_t ws_bytes, cd_stream_t stream)
+{
+    int rc = check_elements(el);
+    if (rc)
+        return rc;
+    if (!bad_index_host)
+        return fail(CD_E_INVALID, "bad_index_host is NULL");
+    *bad_index_host = -1;
+    if (el->n == 0)
+        return CD_OK;
+    if (!ws || ws_bytes < cd_validate_ws(el->n))
+        return fail(CD_E_WORKSPACE, "validate workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long *first = (unsigned long long *)ws;
+    CD_HIP(launch_validate(*el, first, s));
+    unsigned long long h = 0;
+    CD_HIP(hipMemcpyAsync(&h, first, sizeof h, hipMemcpyDeviceToHost, s));
+    CD_HIP(hipStreamSynchronize(s));
+    if (h != ~0ull) {
+        *bad_index_host = (int64_t)h;
+        return fail(CD_E_INVALID, "object %llu has invalid elements (need finite, a > 0, "
+                                  "0 <= e < 1)", h);
+    }
+    return CD_OK;
+}
+
+int cd_dt_heuristic(const cd_elements *el, const cd_params *p, double max_disp_km,
+                    uint32_t *dt_out, cd_stream_t stream)
+{
+    int rc = check_elements(el);
+    if (!rc)
+        rc = check_params(p);
+    if (rc)
+        return rc;
+    if (!(max_disp_km > 0.0) || !isfinite(max_disp_km))
+        return fail(CD_E_INVALID, "max_disp_km must be finite and > 0");
+    if (el->n > 0 && !dt_out)
+        return fail(CD_E_INVALID, "dt_out is NULL");
+    CD_HIP(launch_dt_heuristic(*el, p->mu, p->tick_s, max_disp_km, p->horizon_ticks, dt_out,
+                               (hipStream_t)stream));
+    return CD_OK;
+}
+
+// ---- step 2 -----------------------------------------------------------------------------
+
+size_t cd_build_boxes_ws(int64_t n)
+{
+    BoxWS w;
+    return layout_boxes(nullptr, 0, n > 0 ? n : 0, &w);
+}
+
+int cd_build_boxes(const cd_elements *el, const uint32_t *dt_ticks, const cd_params *p,
+                   cd_boxes *out, void *ws, size_t ws_bytes, cd_stream_t stream)
+{
+    int rc = check_elements(el);
+    if (!rc)
+        rc = check_params(p);
+    if (rc)
+        return rc;
+    if (!out)
+        return fail(CD_E_INVALID, "out is NULL");
+    if (out->precision != CD_FP64 && out->precision != CD_FP32)
+        return fail(CD_E_INVALID, "unknown box precision %d", out->precision);
+    if (out->count < 0 || out->count > kMaxBoxes)
+        return fail(CD_E_OVERFLOW, "box count out of range");
+    int64_t n = el->n;
+    uint32_t T = p->horizon_ticks;
+    out->horizon_ticks = T;
+    out->obj_count = (uint32_t)n;
+    out->slab_size = 0;
+    out->slab_ticks = 0;
+    if (n == 0) {
+        if (out->count != 0)
+            return fail(CD_E_INVALID, "out->count must be 0 for n = 0");
+        return CD_OK;
+    }
+    if (out->count > 0) {
+        for (int d = 0; d < 3; ++d)
+            if (!out->lo[d] || !out->hi[d])
+                return fail(CD_E_INVALID, "box array is NULL");
+        if (!out->t0 || !out->t1 || !out->obj)
+            return fail(CD_E_INVALID, "box tag array is NULL");
+    }
+    if (!ws || ws_bytes < cd_build_boxes_ws(n))
+        return fail(CD_E_WORKSPACE, "build-boxes workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    BoxWS w;
+    layout_boxes(ws, ws_bytes, n, &w);
+    BoxOut bo;
+    for (int d = 0; d < 3; ++d) {
+        bo.lo[d] = out->lo[d];
+        bo.hi[d] = out->hi[d];
+    }
+    bo.t0 = out->t0;
+    bo.t1 = out->t1;
+    bo.obj = out->obj;
+    bo.cap = (uint64_t)out->count;
+    Stage st_boxes("boxes", s);
+    CD_HIP(launch_object_setup(*el, p->mu, w.oc, s));
+    double half_thr = 0.5 * p->threshold_km;
+    if (!dt_ticks) {
+        if (p->dt_ticks == 0)
+            return fail(CD_E_INVALID, "dt_ticks must be >= 1");
+        uint64_t K = intervals(p->dt_ticks, T);
+        if ((uint64_t)n * K != (uint64_t)out->count)
+            return fail(CD_E_INVALID, "out->count %lld != n * K = %llu", (long long)out->count,
+                        (unsigned long long)((uint64_t)n * K));
+        CD_HIP(launch_boxes_uniform(w.oc, (uint32_t)n, (uint32_t)K, p->dt_ticks, T, p->tick_s,
+                                    half_thr, out->precision, bo, s));
+        out->slab_ticks = p->dt_ticks;
+        out->slab_size = n;
+    } else {
+        CD_HIP(launch_steps(dt_ticks, (uint32_t)n, T, kChunk, w.cnt.st, w.cnt.Kc, w.cnt.Cc,
+                            w.cnt.totals, w.cnt.bad, s));
+        CD_HIP(scan_exclusive_u32(w.cnt.Kc, w.box_off, (size_t)n, w.scan, s));
+        CD_HIP(scan_exclusive_u32(w.cnt.Cc, w.chunk_off, (size_t)n, w.scan, s));
+        CD_HIP(launch_steps_apply_offsets(w.cnt.st, w.box_off, w.chunk_off, (uint32_t)n, s));
+        // chunks <= boxes / chunk + objects; threads past the real total return
+        uint64_t upper = (uint64_t)out->count / kChunk + (uint64_t)n;
+        CD_HIP(launch_boxes_variable(w.oc, w.cnt.st, (uint32_t)n, (uint32_t)upper, kChunk, T,
+                                     p->tick_s, half_thr, out->precision, bo, s));
+    }
+    return CD_OK;
+}
+
+// ---- step 3 -----------------------------------------------------------------------------
+
+size_t cd_tree_bytes(int64_t count, int precision)
+{
+    if (count <= 0)
+        return kTreeHeader;
+    return kTreeHeader + (size_t)(2 * count - 1) * tree_node_bytes(precision);
+}
+
+size_t cd_build_tree_ws(int64_t count)
+{
+    TreeWS w;
+    return layout_tree(nullptr, 0, count > 0 ? count : 0, &w);
+}
+
+int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_tree *tree,
+                  void *ws, size_t ws_bytes, cd_stream_t stream)
+{
+    if (!boxes || !tree)
+        return fail(CD_E_INVALID, "boxes or tree is NULL");
+    if (precision != CD_FP64 && precision != CD_FP32)
+        return fail(CD_E_INVALID, "unknown tree precision %d", precision);
+    if (boxes->precision != CD_FP64 && boxes->precision != CD_FP32)
+        return fail(CD_E_INVALID, "unknown box precision %d", boxes->precision);
+    if (boxes->precision == CD_FP32 && precision == CD_FP64)
+        return fail(CD_E_INVALID, "an FP64 tree needs FP64 boxes");
+    int64_t N = boxes->count;
+    if (N < 0)
+        return fail(CD_E_INVALID, "box count < 0");
+    if (N > kMaxBoxes)
+        return fail(CD_E_OVERFLOW, "box count exceeds 2^31 - 1");
+    if (N > 0) {
+        for (int d = 0; d < 3; ++d)
+            if (!boxes->lo[d] || !boxes->hi[d])
+                return fail(CD_E_INVALID, "box array is NULL");
+        if (!boxes->t0 || !boxes->t1 || !boxes->obj)
+            return fail(CD_E_INVALID, "box tag array is NULL");
+    }
+    if (!tree->mem || tree->bytes < cd_tree_bytes(N, precision))
+        return fail(CD_E_WORKSPACE, "tree buffer too small (%zu < %zu)", tree->bytes,
+                    cd_tree_bytes(N, precision));
+    if (N > 0 && (!ws || ws_bytes < cd_build_tree_ws(N)))
+        return fail(CD_E_WORKSPACE, "build-tree workspace too small");
+    uint32_t horizon = boxes->horizon_ticks ? boxes->horizon_ticks : 0xFFFFFFFEu;
+    uint32_t w = slab_ticks ? slab_ticks
+                            : (boxes->slab_ticks ? boxes->slab_ticks : default_slab(horizon));
+    hipStream_t s = (hipStream_t)stream;
+    unsigned int *err = (unsigned int *)tree->mem;
+    void *nodes = (char *)tree->mem + kTreeHeader;
+    CD_HIP(launch_fill_u32(err, 0u, kTreeHeader / 4, s));
+    tree->count = N;
+    tree->precision = precision;
+    tree->slab_ticks = w;
+    tree->horizon_ticks = horizon;
+    tree->obj_count = boxes->obj_count;
+    if (N == 0)
+        return CD_OK;
+    TreeWS tw;
+    layout_tree(ws, ws_bytes, N, &tw);
+    BoxView bv = view_of(boxes);
+    uint32_t max_slab = horizon / w;
+    bool seg = boxes->slab_size > 0 && boxes->slab_size <= kSegCap && boxes->slab_ticks == w &&
+               N % boxes->slab_size == 0;
+    if (seg) {
+        uint32_t m = (uint32_t)boxes->slab_size;
+        {
+            Stage st("keys", s);
+            CD_HIP(launch_bounds(bv, boxes->precision, (uint32_t)N, tw.bounds, s));
+            CD_HIP(launch_keys(bv, boxes->precision, (uint32_t)N, w, max_slab, m, tw.bounds,
+                               tw.morton, nullptr, err, s));
+        }
+        Stage st("sort", s);
+        CD_HIP(launch_segment_sort(tw.morton, (uint32_t)(N / m), m, (uint32_t)N, tw.keys, tw.idx,
+                                   s));
+    } else {
+        {
+            Stage st("keys", s);
+            CD_HIP(launch_bounds(bv, boxes->precision, (uint32_t)N, tw.bounds, s));
+            CD_HIP(launch_keys(bv, boxes->precision, (uint32_t)N, w, max_slab, 0, tw.bounds,
+                               nullptr, tw.kva, err, s));
+        }
+        Stage st("sort", s);
+        DigitPlan plan;
+        memset(&plan, 0, sizeof plan);
+        for (int sh = 0; sh < 32; sh += 8)
+            plan.shift[plan.npass++] = (uint8_t)sh;
+        int sb = bits_for(max_slab);
+        for (int sh = 0; sh < sb; sh += 8)
+            plan.shift[plan.npass++] = (uint8_t)(32 + sh);
+        void *res = nullptr;
+        CD_HIP(radix_sort16(SORT_KV, tw.kva, tw.kvb, (size_t)N, plan, tw.radix, &res, s));
+        CD_HIP(launch_unpack_kv((const KV *)res, (uint32_t)N, tw.keys, tw.idx, s));
+    }
+    {
+        Stage st("karras", s);
+        CD_HIP(launch_karras(tw.keys, (uint32_t)N, precision, nodes, tw.parent, s));
+    }
+    {
+        Stage st("refit", s);
+        CD_HIP(launch_refit(bv, boxes->precision, precision, (uint32_t)N, tw.idx, tw.parent,
+                            tw.arrive, nodes, err, s));
+    }
+    return CD_OK;
+}
+
+// ---- step 4 -----------------------------------------------------------------------------
+
+size_t cd_query_pairs_ws(int64_t count, int64_t capacity)
+{
+    QueryWS w;
+    return layout_query(nullptr, 0, capacity > 0 ? capacity : 0, &w);
+}
+
+int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t *count_host,
+                   void *ws, size_t ws_bytes, cd_stream_t stream)
+{
+    if (!tree || !count_host)
+        return fail(CD_E_INVALID, "tree or count_host is NULL");
+    if (!tree->mem || tree->count < 0)
+        return fail(CD_E_INVALID, "tree is not built");
+    if (tree->bytes < cd_tree_bytes(tree->count, tree->precision))
+        return fail(CD_E_INVALID, "tree buffer smaller than its node count needs");
+    if (capacity < 0 || capacity > 0xFFFFFFFEll)
+        return fail(CD_E_INVALID, "capacity out of range");
+    if (capacity > 0 && !out)
+        return fail(CD_E_INVALID, "out is NULL");
+    if (!ws || ws_bytes < cd_query_pairs_ws(tree->count, capacity))
+        return fail(CD_E_WORKSPACE, "query workspace too small");
+    *count_host = 0;
+    hipStream_t s = (hipStream_t)stream;
+    int64_t N = tree->count;
+    unsigned int *err = (unsigned int *)tree->mem;
+    const void *nodes = (const char *)tree->mem + kTreeHeader;
+    QueryWS w;
+    layout_query(ws, ws_bytes, capacity, &w);
+    CD_HIP(launch_fill_u64(w.counter, 0ull, 1, s));
+    {
+        Stage st("traverse", s);
+        CD_HIP(launch_traverse(nodes, tree->precision, (uint32_t)N, tree->slab_ticks, w.raw,
+                               (unsigned long long)capacity, w.counter, err, s));
+    }
+    unsigned long long cnt = 0;
+    unsigned int e = 0;
+    CD_HIP(hipMemcpyAsync(&cnt, w.counter, sizeof cnt, hipMemcpyDeviceToHost, s));
+    CD_HIP(hipMemcpyAsync(&e, err, sizeof e, hipMemcpyDeviceToHost, s));
+    CD_HIP(hipStreamSynchronize(s));
+    if (e)
+        return fail(CD_E_INVALID, "tree inconsistent (error bits 0x%x): boxes disagree with "
+                                  "their slab hint or horizon, or the build failed", e);
+    *count_host = (int64_t)cnt;
+    if (cnt > (unsigned long long)capacity)
+        return fail(CD_E_CAPACITY, "%llu records exceed capacity %lld", cnt,
+                    (long long)capacity);
+    if (cnt == 0)
+        return CD_OK;
+    uint32_t count = (uint32_t)cnt;
+    int tb = bits_for((uint64_t)tree->horizon_ticks + 1);
+    int ob = tree->obj_count ? bits_for((uint64_t)tree->obj_count - 1) : 32;
+    DigitPlan plan;
+    memset(&plan, 0, sizeof plan);
+    const int fields[4] = {3, 2, 1, 0};  // least significant first: t_hi, t_lo, j, i
+    const int widths[4] = {tb, tb, ob, ob};
+    for (int f = 0; f < 4; ++f)
+        for (int sh = 0; sh < widths[f]; sh += 8) {
+            plan.field[plan.npass] = (uint8_t)fields[f];
+            plan.shift[plan.npass] = (uint8_t)sh;
+            ++plan.npass;
+        }
+    void *res = nullptr;
+    {
+        Stage st("canon", s);
+        CD_HIP(radix_sort16(SORT_REC, w.raw, w.alt, count, plan, w.radix, &res, s));
+        CD_HIP(launch_unique((const Rec *)res, count, w.flags, w.pos, w.scan, (Rec *)out, s));
+    }
+    uint32_t uniq = 0;
+    CD_HIP(hipMemcpyAsync(&uniq, w.pos + count, sizeof uniq, hipMemcpyDeviceToHost, s));
+    CD_HIP(hipStreamSynchronize(s));
+    *count_host = uniq;
+    return CD_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,178 @@
+// cd_internal.h -- types and launchers shared by the library's translation
+// units.  Not installed; the public surface is include/cd4d.h.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "cd4d.h"
+#include "cd_logic.h"
+
+namespace cd {
+
+// Per-object constants of the Kepler ellipse (row of object setup).
+struct ObjConst {
+    double a, e, b, n, m0, vmax;  // b = a sqrt(1 - e^2); n = mean motion (rad/s)
+    double P[3], Q[3];            // perifocal unit vectors in ECI
+};
+
+// Per-object interval bookkeeping for per-object steps (object-major boxes).
+struct ObjSteps {
+    uint32_t dt, K;      // step and interval count
+    uint32_t box_off;    // first box of the object
+    uint32_t chunk_off;  // first work chunk of the object
+};
+
+// Tree node layouts.  FP64: one 64-byte record per node.  FP32: a 32-byte box
+// record plus an 8-byte link record in a separate array.  link is the left
+// child of an inner node and the object id of a leaf; esc is the next node in
+// pre-order once the node's subtree is skipped.
+struct alignas(16) Node64 {
+    double lo[3];
+    double hi[3];
+    uint32_t t0, t1, link, esc;
+};
+struct alignas(16) Box32 {
+    float lo[3];
+    float hi[3];
+    uint32_t t0, t1;
+};
+struct Link {
+    uint32_t link, esc;
+};
+static_assert(sizeof(Node64) == 64, "Node64 layout");
+static_assert(sizeof(Box32) == 32, "Box32 layout");
+
+// Radix-sort items: 16 bytes each.
+struct KV {
+    uint64_t key;
+    uint32_t val, pad;
+};
+struct Rec {
+    uint32_t i, j, tlo, thi;
+};
+
+// Raw device view of a box set (pointers typed by precision at the use site).
+struct BoxView {
+    const void *lo[3], *hi[3];
+    const uint32_t *t0, *t1, *obj;
+};
+struct BoxOut {
+    void *lo[3], *hi[3];
+    uint32_t *t0, *t1, *obj;
+    uint64_t cap;  // entries the arrays hold; stores beyond are dropped
+};
+
+// Order-preserving map from double to uint64 (for atomic min/max).
+__host__ __device__ inline uint64_t ordered_bits(double x)
+{
+    uint64_t u = __builtin_bit_cast(uint64_t, x);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__host__ __device__ inline double from_ordered_bits(uint64_t u)
+{
+    u = (u >> 63) ? (u & 0x7FFFFFFFFFFFFFFFull) : ~u;
+    return __builtin_bit_cast(double, u);
+}
+
+// ---- launchers (each returns the launch status) -----------------------------
+
+// boxes
+hipError_t launch_object_setup(const cd_elements &el, double mu, ObjConst *oc, hipStream_t s);
+hipError_t launch_validate(const cd_elements &el, unsigned long long *first_bad, hipStream_t s);
+hipError_t launch_steps(const uint32_t *dt, uint32_t n, uint32_t T, uint32_t chunk,
+                        ObjSteps *st, uint32_t *Kc, uint32_t *Cc,
+                        unsigned long long *totals /*[2]: boxes, chunks*/,
+                        unsigned int *bad_dt, hipStream_t s);
+hipError_t launch_steps_apply_offsets(ObjSteps *st, const uint32_t *box_off,
+                                      const uint32_t *chunk_off, uint32_t n, hipStream_t s);
+hipError_t launch_dt_heuristic(const cd_elements &el, double mu, double tick_s,
+                               double max_disp, uint32_t T, uint32_t *dt_out, hipStream_t s);
+hipError_t launch_boxes_uniform(const ObjConst *oc, uint32_t n, uint32_t K, uint32_t dt,
+                                uint32_t T, double tick_s, double half_thr, int precision,
+                                const BoxOut &out, hipStream_t s);
+hipError_t launch_boxes_variable(const ObjConst *oc, const ObjSteps *st, uint32_t n,
+                                 uint32_t total_chunks, uint32_t chunk, uint32_t T, double tick_s,
+                                 double half_thr, int precision, const BoxOut &out,
+                                 hipStream_t s);
+
+// scans / sorts / fills
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t count, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, size_t count,
+                           hipStream_t s);
+size_t scan_ws_bytes(size_t count);
+hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, size_t count, void *ws,
+                              hipStream_t s);
+size_t radix_ws_bytes(size_t count);
+// Stable LSD sort of 16-byte items by the digits given by `fields`; the result
+// ends in *result (one of a, b).
+enum SortKind { SORT_KV = 0, SORT_REC = 1 };
+struct DigitPlan {
+    int npass;
+    uint8_t field[16];  // KV: ignored; Rec: 0..3 = i, j, tlo, thi
+    uint8_t shift[16];
+};
+hipError_t radix_sort16(SortKind kind, void *a, void *b, size_t count, const DigitPlan &plan,
+                        void *ws, void **result, hipStream_t s);
+// One workgroup per slab: sort (morton32, box index) pairs inside LDS and write
+// 64-bit keys (slab << 32 | morton) and box indices in sorted order.
+constexpr int kSegThreads = 1024;
+constexpr int kSegItems = 17;
+constexpr int64_t kSegCap = (int64_t)kSegThreads * kSegItems;
+hipError_t launch_segment_sort(const uint32_t *morton, uint32_t nslabs, uint32_t slab_size,
+                               uint32_t N, uint64_t *keys_out, uint32_t *idx_out,
+                               hipStream_t s);
+
+// tree
+hipError_t launch_bounds(const BoxView &b, int precision, uint32_t N,
+                         unsigned long long *bounds /*[6]: min xyz, max xyz*/, hipStream_t s);
+hipError_t launch_keys(const BoxView &b, int precision, uint32_t N, uint32_t slab_ticks,
+                       uint32_t max_slab, uint32_t slab_size,
+                       const unsigned long long *bounds, uint32_t *morton, KV *kv,
+                       unsigned int *err, hipStream_t s);
+hipError_t launch_unpack_kv(const KV *kv, uint32_t N, uint64_t *keys, uint32_t *idx,
+                            hipStream_t s);
+hipError_t launch_karras(const uint64_t *keys, uint32_t N, int precision, void *tree,
+                         uint32_t *parent, hipStream_t s);
+hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision, uint32_t N,
+                        const uint32_t *idx, const uint32_t *parent, unsigned int *arrive,
+                        void *tree, unsigned int *err, hipStream_t s);
+
+// query
+hipError_t launch_traverse(const void *tree, int precision, uint32_t N, uint32_t slab_ticks,
+                           Rec *out, unsigned long long capacity, unsigned long long *counter,
+                           unsigned int *err, hipStream_t s);
+hipError_t launch_unique(const Rec *in, uint32_t count, uint32_t *flags, uint32_t *pos,
+                         void *scan_ws, Rec *out, hipStream_t s);
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Bump allocator over a caller workspace.
+struct Carve {
+    char *base;
+    size_t size, off;
+    explicit Carve(void *p, size_t n) : base((char *)p), size(n), off(0) {}
+    template <typename T>
+    T *take(size_t count)
+    {
+        off = align_up(off, 256);
+        T *p = (T *)(base ? base + off : nullptr);
+        off += count * sizeof(T);
+        return p;
+    }
+    void *take_bytes(size_t bytes)
+    {
+        off = align_up(off, 256);
+        void *p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    }
+    bool fits() const { return off <= size; }
+};
+
+inline size_t tree_node_bytes(int precision)
+{
+    return precision == CD_FP64 ? sizeof(Node64) : sizeof(Box32) + sizeof(Link);
+}
+
+} // namespace cd

@@ -1,0 +1,138 @@
+// cd_logic.h -- index arithmetic of the LBVH, usable on the device and on the
+// host.  The kernels call these functions; a host build of the same header
+// (cd_hostcheck.hip) runs them on the CPU so that termination and tree
+// invariants can be checked before any GPU run.
+//
+// Node numbering: internal nodes 0 .. N-2, leaves N-1 .. 2N-2 (leaf i is the
+// i-th box in sorted key order).  The root is internal node 0 (leaf 0 when
+// N == 1).  kEnd marks "no node".
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cd {
+
+constexpr uint32_t kEnd = 0xFFFFFFFFu;
+
+// ---- Morton codes -----------------------------------------------------------
+
+// Spread the low 10 bits of v so that bit k moves to bit 3k.
+__host__ __device__ inline uint32_t spread3_10(uint32_t v)
+{
+    v &= 0x3FFu;
+    v = (v | (v << 16)) & 0x030000FFu;
+    v = (v | (v << 8)) & 0x0300F00Fu;
+    v = (v | (v << 4)) & 0x030C30C3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+// 30-bit Morton code of a point quantised to a 1024^3 grid over [mn, mx].
+__host__ __device__ inline uint32_t morton30(double x, double y, double z, const double mn[3],
+                                             const double inv_ext[3])
+{
+    double c[3] = {x, y, z};
+    uint32_t q[3];
+    for (int d = 0; d < 3; ++d) {
+        double u = (c[d] - mn[d]) * inv_ext[d];
+        u = u < 0.0 ? 0.0 : (u > 1.0 ? 1.0 : u);
+        uint32_t v = (uint32_t)(u * 1023.0 + 0.5);
+        q[d] = v > 1023u ? 1023u : v;
+    }
+    return (spread3_10(q[0]) << 2) | (spread3_10(q[1]) << 1) | spread3_10(q[2]);
+}
+
+// ---- Karras hierarchy over sorted keys ----------------------------------------
+//
+// delta(i, j): length of the common prefix of keys i and j, with the index
+// appended as a tie-break so that equal keys still give a strict order;
+// -1 outside [0, N).
+
+__host__ __device__ inline int karras_delta(const uint64_t *keys, int64_t N, int64_t i,
+                                            int64_t j)
+{
+    if (j < 0 || j >= N)
+        return -1;
+    uint64_t a = keys[i], b = keys[j];
+    if (a != b)
+        return __builtin_clzll(a ^ b);
+    uint64_t x = (uint64_t)i ^ (uint64_t)j;
+    return 64 + __builtin_clzll(x);
+}
+
+// Direction of internal node i: +1 if its leaf range extends right of i.
+__host__ __device__ inline int karras_dir(const uint64_t *keys, int64_t N, int64_t i)
+{
+    return karras_delta(keys, N, i, i + 1) >= karras_delta(keys, N, i, i - 1) ? 1 : -1;
+}
+
+// Node id of the right sibling of the lowest left-child ancestor of a node
+// whose leaf range ends at r: the next node in depth-first pre-order once that
+// node's subtree is skipped.  It starts at leaf r + 1 and is a right child, so
+// it is internal node r + 1 when that node's range starts at r + 1, and leaf
+// r + 1 otherwise.
+__host__ __device__ inline uint32_t karras_escape(const uint64_t *keys, int64_t N, int64_t r)
+{
+    if (r >= N - 1)
+        return kEnd;
+    int64_t s = r + 1;
+    if (s <= N - 2 && karras_dir(keys, N, s) > 0)
+        return (uint32_t)s;
+    return (uint32_t)(N - 1 + s);
+}
+
+struct KarrasNode {
+    uint32_t left, right;   // node ids
+    int64_t first, last;    // leaf range
+};
+
+// Internal node i of the Karras (2012) radix tree: find the range by an
+// exponential then a binary search on delta, then the split by a binary
+// search.  Requires N >= 2 and 0 <= i <= N - 2.
+__host__ __device__ inline KarrasNode karras_node(const uint64_t *keys, int64_t N, int64_t i)
+{
+    int d = karras_dir(keys, N, i);
+    int dmin = karras_delta(keys, N, i, i - d);
+    int64_t lmax = 2;
+    while (karras_delta(keys, N, i, i + lmax * d) > dmin)
+        lmax *= 2;
+    int64_t l = 0;
+    for (int64_t t = lmax / 2; t >= 1; t /= 2)
+        if (karras_delta(keys, N, i, i + (l + t) * d) > dmin)
+            l += t;
+    int64_t j = i + l * d;
+    int dnode = karras_delta(keys, N, i, j);
+    int64_t s = 0;
+    int64_t t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (karras_delta(keys, N, i, i + (s + t) * d) > dnode)
+            s += t;
+    } while (t > 1);
+    int64_t gamma = i + s * d + (d < 0 ? -1 : 0);
+    KarrasNode nd;
+    nd.first = i < j ? i : j;
+    nd.last = i < j ? j : i;
+    nd.left = (nd.first == gamma) ? (uint32_t)(N - 1 + gamma) : (uint32_t)gamma;
+    nd.right = (nd.last == gamma + 1) ? (uint32_t)(N - 1 + gamma + 1) : (uint32_t)(gamma + 1);
+    return nd;
+}
+
+// ---- 4D box overlap ------------------------------------------------------------
+
+// Time tags [t0, t1) overlap (integer ticks, half-open).
+__host__ __device__ inline bool time_overlap(uint32_t a0, uint32_t a1, uint32_t b0, uint32_t b1)
+{
+    return a0 < b1 && b0 < a1;
+}
+
+// Closed extents overlap on all three axes.
+template <typename F>
+__host__ __device__ inline bool space_overlap(const F *alo, const F *ahi, const F *blo,
+                                              const F *bhi)
+{
+    return alo[0] <= bhi[0] && blo[0] <= ahi[0] && alo[1] <= bhi[1] && blo[1] <= ahi[1] &&
+           alo[2] <= bhi[2] && blo[2] <= ahi[2];
+}
+
+} // namespace cd

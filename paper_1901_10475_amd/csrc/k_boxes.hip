@@ -1,0 +1,322 @@
+// k_boxes.hip -- object setup, per-object steps and 4D box construction.
+//
+// Box (i, k) is the 4D occupancy region of object i over interval k
+// (Def. Interval Occupancy Region, Def. 4D Occupancy Region): the hull of the
+// two endpoint positions, grown by vmax * dt / 2 (no point of a path whose
+// speed is at most vmax can stray further from both endpoints) and by the
+// radius thr / 2; the tag is the half-open tick interval, the last one closed
+// at T (advanceTime's clamp).  Positions come from Kepler's equation, the exact
+// solution of Eq. (nu-dot), mapped to ECI by three rotations (Sec. 7.1).
+//
+// One thread owns one object and a run of consecutive intervals, so each new
+// endpoint's Newton solve starts from the previous one (1-3 iterations) and
+// each endpoint is solved once.  With a uniform step the boxes are written
+// time-major (box k * n + i), so the lanes of a wave store consecutive boxes.
+#include "cd_internal.h"
+
+namespace cd {
+
+__global__ void k_object_setup(cd_elements el, double mu, ObjConst *oc)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= el.n)
+        return;
+    double a = el.a[i], e = el.e[i];
+    double ci, si, cO, sO, cw, sw;
+    sincos(el.inc[i], &si, &ci);
+    sincos(el.raan[i], &sO, &cO);
+    sincos(el.argp[i], &sw, &cw);
+    ObjConst c;
+    c.a = a;
+    c.e = e;
+    c.b = a * sqrt(1.0 - e * e);
+    c.n = sqrt(mu / (a * a * a));
+    c.m0 = el.m0[i];
+    c.vmax = sqrt(mu * (1.0 + e) / (a * (1.0 - e)));
+    // R_z(raan) R_x(inc) R_z(argp) applied to the perifocal x and y axes
+    c.P[0] = cO * cw - sO * sw * ci;
+    c.P[1] = sO * cw + cO * sw * ci;
+    c.P[2] = sw * si;
+    c.Q[0] = -cO * sw - sO * cw * ci;
+    c.Q[1] = -sO * sw + cO * cw * ci;
+    c.Q[2] = cw * si;
+    oc[i] = c;
+}
+
+__global__ void k_validate(cd_elements el, unsigned long long *first_bad)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= el.n)
+        return;
+    double v[6] = {el.a[i], el.e[i], el.inc[i], el.raan[i], el.argp[i], el.m0[i]};
+    bool ok = true;
+    for (int k = 0; k < 6; ++k)
+        ok = ok && isfinite(v[k]);
+    ok = ok && v[0] > 0.0 && v[1] >= 0.0 && v[1] < 1.0;
+    if (!ok)
+        atomicMin(first_bad, (unsigned long long)i);
+}
+
+// K_i = max(1, ceil(T / dt_i)) and the number of work chunks of each object.
+__global__ void k_steps(const uint32_t *dt, uint32_t n, uint32_t T, uint32_t chunk,
+                        ObjSteps *st, uint32_t *Kc, uint32_t *Cc, unsigned long long *totals,
+                        unsigned int *bad_dt)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    uint32_t d = dt[i];
+    if (d == 0) {
+        atomicOr(bad_dt, 1u);
+        d = 1;
+    }
+    uint64_t K = T == 0 ? 1 : ((uint64_t)T + d - 1) / d;
+    ObjSteps s;
+    s.dt = d;
+    s.K = (uint32_t)(K > 0xFFFFFFFFull ? 0xFFFFFFFFull : K);
+    s.box_off = 0;
+    s.chunk_off = (uint32_t)((K + chunk - 1) / chunk);  // chunk count, scanned later
+    st[i] = s;
+    Kc[i] = s.K;
+    Cc[i] = s.chunk_off;
+    atomicAdd(&totals[0], (unsigned long long)K);
+    atomicAdd(&totals[1], (unsigned long long)s.chunk_off);
+}
+
+__global__ void k_dt_heuristic(cd_elements el, double mu, double tick_s, double max_disp,
+                               uint32_t T, uint32_t *dt_out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= el.n)
+        return;
+    double a = el.a[i], e = el.e[i];
+    double vmax = sqrt(mu * (1.0 + e) / (a * (1.0 - e)));
+    double d = floor(max_disp / (vmax * tick_s));
+    double cap = T > 0 ? (double)T : 1.0;
+    if (!(d >= 1.0))
+        d = 1.0;
+    if (d > cap)
+        d = cap;
+    dt_out[i] = (uint32_t)d;
+}
+
+// Newton on Kepler's equation E - e sin E = M from the guess in E.  Returns
+// sin E and cos E at the converged E (first-order corrected for the last step).
+__device__ inline void kepler(double M, double e, double &E, double &sE, double &cE)
+{
+    for (int it = 0; it < 40; ++it) {
+        sincos(E, &sE, &cE);
+        double d = (E - e * sE - M) / (1.0 - e * cE);
+        E -= d;
+        if (fabs(d) <= 1e-15 * (1.0 + fabs(E))) {
+            double s0 = sE;
+            sE = sE - cE * d;
+            cE = cE + s0 * d;
+            return;
+        }
+    }
+    sincos(E, &sE, &cE);
+}
+
+__device__ inline void position(const ObjConst &c, double sE, double cE, double p[3])
+{
+    double u = c.a * (cE - c.e);
+    double v = c.b * sE;
+    p[0] = u * c.P[0] + v * c.Q[0];
+    p[1] = u * c.P[1] + v * c.Q[1];
+    p[2] = u * c.P[2] + v * c.Q[2];
+}
+
+template <int PREC>
+__device__ inline void store_box(const BoxOut &o, uint64_t b, const double pa[3],
+                                 const double pb[3], double g, uint32_t t0, uint32_t t1,
+                                 uint32_t obj)
+{
+    if (b >= o.cap)
+        return;
+    for (int d = 0; d < 3; ++d) {
+        double lo = fmin(pa[d], pb[d]) - g;
+        double hi = fmax(pa[d], pb[d]) + g;
+        if (PREC == CD_FP64) {
+            ((double *)o.lo[d])[b] = lo;
+            ((double *)o.hi[d])[b] = hi;
+        } else {
+            ((float *)o.lo[d])[b] = __double2float_rd(lo);
+            ((float *)o.hi[d])[b] = __double2float_ru(hi);
+        }
+    }
+    o.t0[b] = t0;
+    o.t1[b] = t1;
+    o.obj[b] = obj;
+}
+
+// Intervals [k0, k1) of object i; box of interval k at index base + k * stride.
+template <int PREC>
+__device__ inline void object_run(const ObjConst &c, uint32_t i, uint64_t k0, uint64_t k1,
+                                  uint64_t K, uint64_t dt, uint64_t T, double tick_s,
+                                  double half_thr, const BoxOut &out, uint64_t base,
+                                  uint64_t stride)
+{
+    uint64_t ta = k0 * dt < T ? k0 * dt : T;
+    double M = c.m0 + c.n * ((double)ta * tick_s);
+    double E = M + c.e * sin(M), sE, cE;
+    kepler(M, c.e, E, sE, cE);
+    double pa[3];
+    position(c, sE, cE, pa);
+    for (uint64_t k = k0; k < k1; ++k) {
+        uint64_t tb = (k + 1) * dt < T ? (k + 1) * dt : T;
+        double Mb = c.m0 + c.n * ((double)tb * tick_s);
+        E += (Mb - M) / (1.0 - c.e * cE);
+        kepler(Mb, c.e, E, sE, cE);
+        double pb[3];
+        position(c, sE, cE, pb);
+        double g = c.vmax * ((double)(tb - ta) * tick_s) * 0.5 + half_thr;
+        uint32_t t1 = (k + 1 == K) ? (uint32_t)(T + 1) : (uint32_t)tb;
+        store_box<PREC>(out, base + k * stride, pa, pb, g, (uint32_t)ta, t1, i);
+        pa[0] = pb[0];
+        pa[1] = pb[1];
+        pa[2] = pb[2];
+        ta = tb;
+        M = Mb;
+    }
+}
+
+template <int PREC>
+__global__ void k_boxes_uniform(const ObjConst *__restrict__ oc, uint32_t n, uint32_t K,
+                                uint32_t dt, uint32_t T, double tick_s, double half_thr,
+                                uint32_t chunk, BoxOut out)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    uint64_t k0 = (uint64_t)blockIdx.y * chunk;
+    if (k0 >= K)
+        return;
+    uint64_t k1 = k0 + chunk < K ? k0 + chunk : K;
+    object_run<PREC>(oc[i], i, k0, k1, K, dt, T, tick_s, half_thr, out, i, n);
+}
+
+template <int PREC>
+__global__ void k_boxes_variable(const ObjConst *__restrict__ oc,
+                                 const ObjSteps *__restrict__ st, uint32_t n,
+                                 uint32_t total_chunks, uint32_t chunk, uint32_t T,
+                                 double tick_s, double half_thr, BoxOut out)
+{
+    uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total_chunks)
+        return;
+    // object owning chunk g: last i with chunk_off[i] <= g
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (st[mid].chunk_off <= g)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    uint32_t i = lo;
+    ObjSteps s = st[i];
+    uint64_t k0 = (uint64_t)(g - s.chunk_off) * chunk;
+    if (k0 >= s.K)
+        return;
+    uint64_t k1 = k0 + chunk < s.K ? k0 + chunk : s.K;
+    object_run<PREC>(oc[i], i, k0, k1, s.K, s.dt, T, tick_s, half_thr, out, s.box_off, 1);
+}
+
+// After the chunk counts and K have been scanned into ObjSteps.
+__global__ void k_steps_apply_offsets(ObjSteps *st, const uint32_t *box_off,
+                                      const uint32_t *chunk_off, uint32_t n)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    st[i].box_off = box_off[i];
+    st[i].chunk_off = chunk_off[i];
+}
+
+static inline unsigned blocks_for(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t launch_object_setup(const cd_elements &el, double mu, ObjConst *oc, hipStream_t s)
+{
+    if (el.n == 0)
+        return hipSuccess;
+    k_object_setup<<<blocks_for(el.n, 256), 256, 0, s>>>(el, mu, oc);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate(const cd_elements &el, unsigned long long *first_bad, hipStream_t s)
+{
+    hipError_t e = launch_fill_u64(first_bad, ~0ull, 1, s);
+    if (e != hipSuccess || el.n == 0)
+        return e;
+    k_validate<<<blocks_for(el.n, 256), 256, 0, s>>>(el, first_bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_steps(const uint32_t *dt, uint32_t n, uint32_t T, uint32_t chunk,
+                        ObjSteps *st, uint32_t *Kc, uint32_t *Cc, unsigned long long *totals,
+                        unsigned int *bad_dt, hipStream_t s)
+{
+    hipError_t e = launch_fill_u64(totals, 0ull, 2, s);
+    if (e == hipSuccess)
+        e = launch_fill_u32(bad_dt, 0u, 1, s);
+    if (e != hipSuccess || n == 0)
+        return e;
+    k_steps<<<blocks_for(n, 256), 256, 0, s>>>(dt, n, T, chunk, st, Kc, Cc, totals, bad_dt);
+    return hipGetLastError();
+}
+
+hipError_t launch_dt_heuristic(const cd_elements &el, double mu, double tick_s,
+                               double max_disp, uint32_t T, uint32_t *dt_out, hipStream_t s)
+{
+    if (el.n == 0)
+        return hipSuccess;
+    k_dt_heuristic<<<blocks_for(el.n, 256), 256, 0, s>>>(el, mu, tick_s, max_disp, T, dt_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_boxes_uniform(const ObjConst *oc, uint32_t n, uint32_t K, uint32_t dt,
+                                uint32_t T, double tick_s, double half_thr, int precision,
+                                const BoxOut &out, hipStream_t s)
+{
+    if (n == 0 || K == 0)
+        return hipSuccess;
+    uint32_t chunk = 16;
+    while ((K + chunk - 1) / chunk > 65535u)
+        chunk *= 2;
+    dim3 grid(blocks_for(n, 128), (K + chunk - 1) / chunk);
+    if (precision == CD_FP64)
+        k_boxes_uniform<CD_FP64><<<grid, 128, 0, s>>>(oc, n, K, dt, T, tick_s, half_thr, chunk,
+                                                       out);
+    else
+        k_boxes_uniform<CD_FP32><<<grid, 128, 0, s>>>(oc, n, K, dt, T, tick_s, half_thr, chunk,
+                                                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_boxes_variable(const ObjConst *oc, const ObjSteps *st, uint32_t n,
+                                 uint32_t total_chunks, uint32_t chunk, uint32_t T, double tick_s,
+                                 double half_thr, int precision, const BoxOut &out,
+                                 hipStream_t s)
+{
+    if (n == 0 || total_chunks == 0)
+        return hipSuccess;
+    if (precision == CD_FP64)
+        k_boxes_variable<CD_FP64><<<blocks_for(total_chunks, 128), 128, 0, s>>>(
+            oc, st, n, total_chunks, chunk, T, tick_s, half_thr, out);
+    else
+        k_boxes_variable<CD_FP32><<<blocks_for(total_chunks, 128), 128, 0, s>>>(
+            oc, st, n, total_chunks, chunk, T, tick_s, half_thr, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_steps_apply_offsets(ObjSteps *st, const uint32_t *box_off,
+                                      const uint32_t *chunk_off, uint32_t n, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    k_steps_apply_offsets<<<blocks_for(n, 256), 256, 0, s>>>(st, box_off, chunk_off, n);
+    return hipGetLastError();
+}
+
+} // namespace cd

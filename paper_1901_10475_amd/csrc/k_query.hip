@@ -1,0 +1,196 @@
+// k_query.hip -- the n-to-n self-traversal and the canonical pair list.
+//
+// One lane per leaf (query box), leaves taken in sorted key order so that the
+// lanes of a wave hold neighbouring boxes and walk nearly the same nodes.  A
+// query visits only the part of the tree to the right of its own leaf: it
+// starts at its leaf's skip link (the next node in pre-order after the leaf)
+// and follows, without a stack, the left-child link into overlapping inner
+// nodes and the skip link past everything else.  Every unordered pair of
+// leaves is therefore tested once, from the left one.  The node test is the
+// 4D overlap of Def. 4D Occupancy Region: half-open integer time tags and
+// closed spatial extents; leaves of the same object are skipped, as queryObject
+// excludes the queried object (Sec. 4.4).
+//
+// Because keys are time-major, everything right of a node whose earliest tag
+// starts at t0 begins no earlier than slab(t0) * slab_ticks, so a query stops as
+// soon as t0_min(node) >= t1(query) + slab_ticks - 1.
+//
+// Records are appended through one atomic per wave per step: the lanes with a
+// hit are counted with a ballot, the lowest one reserves the range, and each
+// lane writes at its prefix position.
+#include "cd_internal.h"
+
+namespace cd {
+
+static inline unsigned nblk(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
+
+template <int TP>
+struct Q;
+
+template <>
+struct Q<CD_FP64> {
+    using F = double;
+    __device__ static void load(const void *tree, uint32_t N, uint32_t id, F lo[3], F hi[3],
+                                uint32_t &t0, uint32_t &t1, uint32_t &link, uint32_t &esc)
+    {
+        const Node64 *n = (const Node64 *)tree + id;
+        double4 a = *(const double4 *)&n->lo[0];   // lo0 lo1 lo2 hi0
+        double2 c = *(const double2 *)&n->hi[1];   // hi1 hi2
+        uint4 u = *(const uint4 *)&n->t0;          // t0 t1 link esc
+        lo[0] = a.x;
+        lo[1] = a.y;
+        lo[2] = a.z;
+        hi[0] = a.w;
+        hi[1] = c.x;
+        hi[2] = c.y;
+        t0 = u.x;
+        t1 = u.y;
+        link = u.z;
+        esc = u.w;
+    }
+};
+
+template <>
+struct Q<CD_FP32> {
+    using F = float;
+    __device__ static void load(const void *tree, uint32_t N, uint32_t id, F lo[3], F hi[3],
+                                uint32_t &t0, uint32_t &t1, uint32_t &link, uint32_t &esc)
+    {
+        const Box32 *b = (const Box32 *)tree + id;
+        float4 a = *(const float4 *)&b->lo[0];     // lo0 lo1 lo2 hi0
+        uint4 c = *(const uint4 *)&b->hi[1];       // hi1 hi2 t0 t1
+        uint2 l = *((const uint2 *)((const Box32 *)tree + (2 * (size_t)N - 1)) + id);
+        lo[0] = a.x;
+        lo[1] = a.y;
+        lo[2] = a.z;
+        hi[0] = a.w;
+        hi[1] = __uint_as_float(c.x);
+        hi[2] = __uint_as_float(c.y);
+        t0 = c.z;
+        t1 = c.w;
+        link = l.x;
+        esc = l.y;
+    }
+};
+
+// Physical block b runs on XCD b % 8.  Give each XCD one contiguous range of
+// leaf blocks, so the nodes its queries share stay in that XCD's L2.
+__device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb)
+{
+    uint32_t x = b & 7u, q = nb >> 3, r = nb & 7u;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+template <int TP>
+__global__ __launch_bounds__(256) void k_traverse(const void *__restrict__ tree, uint32_t N,
+                                                  uint32_t slab_ticks, Rec *__restrict__ out,
+                                                  unsigned long long capacity,
+                                                  unsigned long long *counter,
+                                                  unsigned int *err)
+{
+    using F = typename Q<TP>::F;
+    uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
+    uint32_t i = blk * blockDim.x + threadIdx.x;
+    if (i >= N)
+        return;
+    F qlo[3], qhi[3];
+    uint32_t qt0, qt1, qobj, node;
+    Q<TP>::load(tree, N, N - 1 + i, qlo, qhi, qt0, qt1, qobj, node);
+    const uint64_t stop = (uint64_t)qt1 + slab_ticks - 1;
+    const uint32_t limit = 2 * N + 2;
+    const uint64_t lt = (threadIdx.x & 63) ? (~0ull >> (64 - (threadIdx.x & 63))) : 0ull;
+    uint32_t steps = 0;
+    while (node != kEnd) {
+        if (++steps > limit || node >= 2 * N - 1) {
+            atomicOr(err, 4u);
+            break;
+        }
+        F lo[3], hi[3];
+        uint32_t t0, t1, link, esc;
+        Q<TP>::load(tree, N, node, lo, hi, t0, t1, link, esc);
+        if ((uint64_t)t0 >= stop)
+            break;
+        bool ov = time_overlap(qt0, qt1, t0, t1) && space_overlap(qlo, qhi, lo, hi);
+        bool leaf = node >= N - 1;
+        bool hit = ov && leaf && link != qobj;
+        uint64_t m = __ballot(hit);
+        if (m) {
+            int leader = __ffsll((unsigned long long)m) - 1;
+            unsigned long long base = 0;
+            if ((int)(threadIdx.x & 63) == leader)
+                base = atomicAdd(counter, (unsigned long long)__popcll(m));
+            base = __shfl(base, leader, 64);
+            if (hit) {
+                unsigned long long pos = base + (unsigned long long)__popcll(m & lt);
+                if (pos < capacity) {
+                    Rec r;
+                    r.i = qobj < link ? qobj : link;
+                    r.j = qobj < link ? link : qobj;
+                    r.tlo = qt0 > t0 ? qt0 : t0;
+                    r.thi = qt1 < t1 ? qt1 : t1;
+                    out[pos] = r;
+                }
+            }
+        }
+        node = (ov && !leaf) ? link : esc;
+    }
+}
+
+hipError_t launch_traverse(const void *tree, int precision, uint32_t N, uint32_t slab_ticks,
+                           Rec *out, unsigned long long capacity, unsigned long long *counter,
+                           unsigned int *err, hipStream_t s)
+{
+    if (N <= 1)
+        return hipSuccess;
+    unsigned g = nblk(N, 256);
+    if (precision == CD_FP64)
+        k_traverse<CD_FP64><<<g, 256, 0, s>>>(tree, N, slab_ticks, out, capacity, counter, err);
+    else
+        k_traverse<CD_FP32><<<g, 256, 0, s>>>(tree, N, slab_ticks, out, capacity, counter, err);
+    return hipGetLastError();
+}
+
+// ---- canonical list: sorted records, repeats dropped -----------------------------------------
+
+__global__ void k_unique_flags(const Rec *in, uint32_t count, uint32_t *flags)
+{
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= count)
+        return;
+    bool f = true;
+    if (r > 0) {
+        Rec a = in[r - 1], b = in[r];
+        f = a.i != b.i || a.j != b.j || a.tlo != b.tlo || a.thi != b.thi;
+    }
+    flags[r] = f ? 1u : 0u;
+}
+
+__global__ void k_unique_scatter(const Rec *in, uint32_t count, const uint32_t *flags,
+                                 const uint32_t *pos, Rec *out, uint32_t *total)
+{
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= count)
+        return;
+    if (flags[r])
+        out[pos[r]] = in[r];
+    if (r == count - 1)
+        *total = pos[r] + flags[r];
+}
+
+hipError_t launch_unique(const Rec *in, uint32_t count, uint32_t *flags, uint32_t *pos,
+                         void *scan_ws, Rec *out, hipStream_t s)
+{
+    // total is written to pos[count] (pos holds count + 1 entries)
+    if (count == 0)
+        return launch_fill_u32(pos, 0u, 1, s);
+    k_unique_flags<<<nblk(count, 256), 256, 0, s>>>(in, count, flags);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = scan_exclusive_u32(flags, pos, count, scan_ws, s);
+    if (e != hipSuccess)
+        return e;
+    k_unique_scatter<<<nblk(count, 256), 256, 0, s>>>(in, count, flags, pos, out, pos + count);
+    return hipGetLastError();
+}
+
+} // namespace cd

@@ -1,0 +1,443 @@
+// k_sort.hip -- fills, device-wide exclusive scan, stable LSD radix sorts.
+//
+// Two radix sorts live here:
+//   * radix_sort16: device-wide, stable, over 16-byte items (key/value pairs or
+//     pair records), 8-bit digits, one histogram + scan + scatter per digit.
+//     It sorts tree keys when boxes are not grouped in slabs and it puts pair
+//     records in canonical order.
+//   * k_segment_sort: one 1024-thread workgroup per time slab; keys stay in
+//     registers and move through LDS between digit passes, so a slab of up to
+//     kSegCap boxes is sorted with one read and one write of global memory.
+// Both rank digits stably with the same wave-level scheme: the lanes holding
+// equal digits are found with eight ballots, the lowest of them bumps a
+// per-(digit, wave) counter in LDS, and a digit-major scan of those counters
+// turns per-wave ranks into positions.
+#include "cd_internal.h"
+
+namespace cd {
+
+static inline unsigned nblk(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
+
+// ---- fills ---------------------------------------------------------------------
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, size_t count)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < count; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_u64(unsigned long long *p, unsigned long long v, size_t count)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < count; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t count, hipStream_t s)
+{
+    if (count == 0)
+        return hipSuccess;
+    unsigned g = nblk(count, 256);
+    k_fill_u32<<<g > 4096 ? 4096 : g, 256, 0, s>>>(p, v, count);
+    return hipGetLastError();
+}
+hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, size_t count,
+                           hipStream_t s)
+{
+    if (count == 0)
+        return hipSuccess;
+    unsigned g = nblk(count, 256);
+    k_fill_u64<<<g > 4096 ? 4096 : g, 256, 0, s>>>(p, v, count);
+    return hipGetLastError();
+}
+
+// ---- wave helpers -----------------------------------------------------------------
+
+__device__ inline uint32_t wave_inclusive_scan(uint32_t v)
+{
+    int lane = threadIdx.x & 63;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t u = __shfl_up(v, o, 64);
+        if (lane >= o)
+            v += u;
+    }
+    return v;
+}
+
+// Lanes (among `active`) whose 8-bit digit equals this lane's digit.
+__device__ inline uint64_t match_digit(uint32_t d, uint64_t active)
+{
+    uint64_t peers = active;
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+        uint64_t b = __ballot((d >> bit) & 1u);
+        peers &= ((d >> bit) & 1u) ? b : ~b;
+    }
+    return peers;
+}
+
+__device__ inline uint64_t lanemask_lt()
+{
+    int lane = threadIdx.x & 63;
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Exclusive scan over all threads of a block (blockDim multiple of 64, <= 1024).
+// `wsum` is LDS scratch of blockDim/64 entries.  Returns the exclusive prefix;
+// *total gets the block sum.
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *wsum, uint32_t *total)
+{
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    uint32_t inc = wave_inclusive_scan(v);
+    if (lane == 63)
+        wsum[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+        uint32_t x = lane < nw ? wsum[lane] : 0u;
+        uint32_t xi = wave_inclusive_scan(x);
+        if (lane < nw)
+            wsum[lane] = xi - x;
+        if (lane == nw - 1)
+            wsum[32] = xi;
+    }
+    __syncthreads();
+    uint32_t r = wsum[w] + inc - v;
+    *total = wsum[32];
+    __syncthreads();
+    return r;
+}
+
+// ---- device-wide exclusive scan of uint32 ---------------------------------------
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_tiles(const uint32_t *in, uint32_t *out,
+                                                             size_t count, uint32_t *tile_sums)
+{
+    __shared__ uint32_t tile[kScanTile];
+    __shared__ uint32_t wsum[64];
+    size_t base = (size_t)blockIdx.x * kScanTile;
+    for (int k = 0; k < kScanItems; ++k) {
+        size_t g = base + (size_t)k * kScanThreads + threadIdx.x;
+        tile[k * kScanThreads + threadIdx.x] = g < count ? in[g] : 0u;
+    }
+    __syncthreads();
+    uint32_t v[kScanItems];
+    uint32_t sum = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        v[k] = tile[threadIdx.x * kScanItems + k];
+        sum += v[k];
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(sum, wsum, &total);
+    for (int k = 0; k < kScanItems; ++k) {
+        uint32_t x = v[k];
+        tile[threadIdx.x * kScanItems + k] = run;
+        run += x;
+    }
+    __syncthreads();
+    for (int k = 0; k < kScanItems; ++k) {
+        size_t g = base + (size_t)k * kScanThreads + threadIdx.x;
+        if (g < count)
+            out[g] = tile[k * kScanThreads + threadIdx.x];
+    }
+    if (threadIdx.x == 0 && tile_sums)
+        tile_sums[blockIdx.x] = total;
+}
+
+__global__ void k_scan_add(uint32_t *out, size_t count, const uint32_t *tile_off)
+{
+    size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < count)
+        out[g] += tile_off[g / kScanTile];
+}
+
+size_t scan_ws_bytes(size_t count)
+{
+    size_t bytes = 0;
+    while (count > (size_t)kScanTile) {
+        count = (count + kScanTile - 1) / kScanTile;
+        bytes += align_up(count * sizeof(uint32_t), 256);
+    }
+    return bytes + 256;
+}
+
+hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, size_t count, void *ws,
+                              hipStream_t s)
+{
+    if (count == 0)
+        return hipSuccess;
+    size_t tiles = (count + kScanTile - 1) / kScanTile;
+    uint32_t *sums = tiles > 1 ? (uint32_t *)ws : nullptr;
+    k_scan_tiles<<<(unsigned)tiles, kScanThreads, 0, s>>>(in, out, count, sums);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || tiles == 1)
+        return e;
+    void *rest = (char *)ws + align_up(tiles * sizeof(uint32_t), 256);
+    e = scan_exclusive_u32(sums, sums, tiles, rest, s);
+    if (e != hipSuccess)
+        return e;
+    k_scan_add<<<nblk(count, 256), 256, 0, s>>>(out, count, sums);
+    return hipGetLastError();
+}
+
+// ---- device-wide LSD radix sort of 16-byte items -------------------------------------
+
+constexpr int kRadThreads = 256;
+constexpr int kRadItems = 16;
+constexpr int kRadTile = kRadThreads * kRadItems;  // 4096
+constexpr int kRadWaves = kRadThreads / 64;
+
+struct DigitKV {
+    uint32_t shift;
+    __device__ uint32_t operator()(const uint4 &it) const
+    {
+        uint64_t key = ((uint64_t)it.y << 32) | it.x;
+        return (uint32_t)(key >> shift) & 0xFFu;
+    }
+};
+struct DigitRec {
+    uint32_t field, shift;
+    __device__ uint32_t operator()(const uint4 &it) const
+    {
+        uint32_t v = field == 0 ? it.x : field == 1 ? it.y : field == 2 ? it.z : it.w;
+        return (v >> shift) & 0xFFu;
+    }
+};
+
+template <typename Digit>
+__global__ __launch_bounds__(kRadThreads) void k_radix_upsweep(const uint4 *in, size_t count,
+                                                               Digit dig, uint32_t *hist,
+                                                               uint32_t nblocks)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    size_t base = (size_t)blockIdx.x * kRadTile;
+    for (int k = 0; k < kRadItems; ++k) {
+        size_t g = base + (size_t)k * kRadThreads + threadIdx.x;
+        if (g < count)
+            atomicAdd(&h[dig(in[g])], 1u);
+    }
+    __syncthreads();
+    hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+template <typename Digit>
+__global__ __launch_bounds__(kRadThreads) void k_radix_downsweep(const uint4 *in, uint4 *out,
+                                                                 size_t count, Digit dig,
+                                                                 const uint32_t *hist_scan,
+                                                                 uint32_t nblocks)
+{
+    __shared__ uint32_t cnt[256 * kRadWaves];
+    __shared__ uint32_t dbase[256];
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int k = threadIdx.x; k < 256 * kRadWaves; k += kRadThreads)
+        cnt[k] = 0;
+    dbase[threadIdx.x] = hist_scan[(size_t)threadIdx.x * nblocks + blockIdx.x];
+    __syncthreads();
+    size_t wbase = (size_t)blockIdx.x * kRadTile + (size_t)w * (64 * kRadItems);
+    uint4 item[kRadItems];
+    uint32_t dg[kRadItems], rk[kRadItems];
+    uint64_t lt = lanemask_lt();
+    for (int j = 0; j < kRadItems; ++j) {
+        size_t g = wbase + (size_t)j * 64 + lane;
+        bool valid = g < count;
+        item[j] = valid ? in[g] : make_uint4(0, 0, 0, 0);
+        uint32_t d = valid ? dig(item[j]) : 0u;
+        uint64_t act = __ballot(valid);
+        uint64_t peers = match_digit(d, act);
+        uint32_t c = valid ? cnt[d * kRadWaves + w] : 0u;
+        uint32_t mine = (uint32_t)__popcll(peers & lt);
+        if (valid && mine == 0)
+            cnt[d * kRadWaves + w] = c + (uint32_t)__popcll(peers);
+        dg[j] = d;
+        rk[j] = c + mine;
+    }
+    __syncthreads();
+    {   // per digit: exclusive prefix over waves
+        uint32_t d = threadIdx.x, run = 0;
+        for (int ww = 0; ww < kRadWaves; ++ww) {
+            uint32_t t = cnt[d * kRadWaves + ww];
+            cnt[d * kRadWaves + ww] = run;
+            run += t;
+        }
+    }
+    __syncthreads();
+    for (int j = 0; j < kRadItems; ++j) {
+        size_t g = wbase + (size_t)j * 64 + lane;
+        if (g < count) {
+            size_t pos = (size_t)dbase[dg[j]] + cnt[dg[j] * kRadWaves + w] + rk[j];
+            if (pos < count)
+                out[pos] = item[j];
+        }
+    }
+}
+
+size_t radix_ws_bytes(size_t count)
+{
+    size_t nb = (count + kRadTile - 1) / kRadTile;
+    size_t h = nb * 256;
+    return align_up(h * sizeof(uint32_t), 256) + scan_ws_bytes(h);
+}
+
+hipError_t radix_sort16(SortKind kind, void *a, void *b, size_t count, const DigitPlan &plan,
+                        void *ws, void **result, hipStream_t s)
+{
+    *result = a;
+    if (count <= 1 || plan.npass == 0)
+        return hipSuccess;
+    uint32_t nb = (uint32_t)((count + kRadTile - 1) / kRadTile);
+    size_t h = (size_t)nb * 256;
+    uint32_t *hist = (uint32_t *)ws;
+    void *sws = (char *)ws + align_up(h * sizeof(uint32_t), 256);
+    uint4 *src = (uint4 *)a, *dst = (uint4 *)b;
+    for (int p = 0; p < plan.npass; ++p) {
+        if (kind == SORT_KV) {
+            DigitKV dg{plan.shift[p]};
+            k_radix_upsweep<<<nb, kRadThreads, 0, s>>>(src, count, dg, hist, nb);
+        } else {
+            DigitRec dg{plan.field[p], plan.shift[p]};
+            k_radix_upsweep<<<nb, kRadThreads, 0, s>>>(src, count, dg, hist, nb);
+        }
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess)
+            e = scan_exclusive_u32(hist, hist, h, sws, s);
+        if (e != hipSuccess)
+            return e;
+        if (kind == SORT_KV) {
+            DigitKV dg{plan.shift[p]};
+            k_radix_downsweep<<<nb, kRadThreads, 0, s>>>(src, dst, count, dg, hist, nb);
+        } else {
+            DigitRec dg{plan.field[p], plan.shift[p]};
+            k_radix_downsweep<<<nb, kRadThreads, 0, s>>>(src, dst, count, dg, hist, nb);
+        }
+        e = hipGetLastError();
+        if (e != hipSuccess)
+            return e;
+        uint4 *t = src;
+        src = dst;
+        dst = t;
+    }
+    *result = src;
+    return hipSuccess;
+}
+
+// ---- per-slab LDS radix sort ---------------------------------------------------------
+//
+// Block = kSegThreads (16 waves).  Wave w holds the keys with local index
+// w * 64 * kSegItems + j * 64 + lane (item j) in registers.  Per 8-bit digit:
+// rank inside the wave per item, scan the (digit, wave) counters, scatter the
+// keys and then the values through one LDS exchange buffer, read back.
+
+constexpr int kSegWaves = kSegThreads / 64;
+
+__global__ __launch_bounds__(kSegThreads) void k_segment_sort(const uint32_t *__restrict__ morton,
+                                                             uint32_t slab_size, uint32_t N,
+                                                             uint64_t *__restrict__ keys_out,
+                                                             uint32_t *__restrict__ idx_out)
+{
+    __shared__ uint32_t xch[kSegCap];
+    __shared__ uint32_t cnt[256 * kSegWaves];
+    __shared__ uint32_t wsum[64];
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint64_t slab = blockIdx.x;
+    uint64_t base = slab * slab_size;
+    uint32_t m = slab_size;
+    if (base + m > N)
+        m = base < N ? (uint32_t)(N - base) : 0u;
+    uint32_t key[kSegItems], val[kSegItems];
+    uint32_t li0 = (uint32_t)w * 64 * kSegItems + lane;
+#pragma unroll
+    for (int j = 0; j < kSegItems; ++j) {
+        uint32_t li = li0 + j * 64;
+        key[j] = li < m ? morton[base + li] : 0xFFFFFFFFu;
+        val[j] = li;
+    }
+    uint64_t lt = lanemask_lt();
+    for (int shift = 0; shift < 32; shift += 8) {
+        for (int k = threadIdx.x; k < 256 * kSegWaves; k += kSegThreads)
+            cnt[k] = 0;
+        __syncthreads();
+        uint32_t rk[kSegItems];  // rank inside (digit, wave), then final position
+#pragma unroll
+        for (int j = 0; j < kSegItems; ++j) {
+            uint32_t li = li0 + j * 64;
+            bool valid = li < m;
+            uint32_t d = (key[j] >> shift) & 0xFFu;
+            uint64_t peers = match_digit(d, __ballot(valid));
+            uint32_t c = valid ? cnt[d * kSegWaves + w] : 0u;
+            uint32_t mine = (uint32_t)__popcll(peers & lt);
+            if (valid && mine == 0)
+                cnt[d * kSegWaves + w] = c + (uint32_t)__popcll(peers);
+            rk[j] = c + mine;
+        }
+        __syncthreads();
+        {   // exclusive scan of the 4096 counters in (digit, wave) order
+            uint32_t v[4], sum = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                v[q] = cnt[threadIdx.x * 4 + q];
+                sum += v[q];
+            }
+            uint32_t total;
+            uint32_t run = block_exclusive_scan(sum, wsum, &total);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                cnt[threadIdx.x * 4 + q] = run;
+                run += v[q];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kSegItems; ++j) {
+            uint32_t d = (key[j] >> shift) & 0xFFu;
+            rk[j] += cnt[d * kSegWaves + w];
+        }
+        // keys, then values, through the exchange buffer
+#pragma unroll
+        for (int j = 0; j < kSegItems; ++j)
+            if (li0 + j * 64 < m && rk[j] < (uint32_t)kSegCap)
+                xch[rk[j]] = key[j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kSegItems; ++j)
+            if (li0 + j * 64 < m)
+                key[j] = xch[li0 + j * 64];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kSegItems; ++j)
+            if (li0 + j * 64 < m && rk[j] < (uint32_t)kSegCap)
+                xch[rk[j]] = val[j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kSegItems; ++j)
+            if (li0 + j * 64 < m)
+                val[j] = xch[li0 + j * 64];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < kSegItems; ++j) {
+        uint32_t li = li0 + j * 64;
+        if (li < m) {
+            keys_out[base + li] = (slab << 32) | key[j];
+            idx_out[base + li] = (uint32_t)base + val[j];
+        }
+    }
+}
+
+hipError_t launch_segment_sort(const uint32_t *morton, uint32_t nslabs, uint32_t slab_size,
+                               uint32_t N, uint64_t *keys_out, uint32_t *idx_out,
+                               hipStream_t s)
+{
+    if (nslabs == 0 || N == 0)
+        return hipSuccess;
+    if ((int64_t)slab_size > kSegCap)
+        return hipErrorInvalidValue;
+    k_segment_sort<<<nslabs, kSegThreads, 0, s>>>(morton, slab_size, N, keys_out, idx_out);
+    return hipGetLastError();
+}
+
+} // namespace cd

@@ -1,0 +1,57 @@
+"""Helpers shared by the GPU parity tests (not collected by pytest)."""
+import sys
+
+import numpy as np
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def need_gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU test run without a HIP device"
+
+
+def run_catalog(sc, box_precision=0, tree_precision=0, dt_array=None, capacity=None):
+    """Boxes, tree and canonical pairs for a scenario on the GPU."""
+    import torch
+    import paper_1901_10475_amd as cd
+    el = cd.soa(sc.elements)
+    p = cd.params_struct(sc.tick_s, sc.mu, sc.threshold_km, sc.horizon_ticks,
+                         sc.dt_ticks if np.ndim(sc.dt_ticks) == 0 else 0)
+    dt = None
+    if dt_array is not None:
+        dt = torch.from_numpy(np.asarray(dt_array, np.uint32).view(np.int32)).cuda()
+    bp = cd.BroadPhase(sc.n, p, dt, box_precision, tree_precision, capacity=capacity)
+    pairs = bp.run(el)
+    torch.cuda.synchronize()
+    return bp, pairs.cpu().numpy().view(np.uint32).copy()
+
+
+def gpu_to_object_major(n, K):
+    """Index map: oracle box (i, k) at i*K + k  ->  time-major GPU machine k*n + i."""
+    i = np.repeat(np.arange(n), K)
+    k = np.tile(np.arange(K), n)
+    return k * n + i
+
+
+def assert_boxes_close(g_lo, g_hi, o_lo, o_hi, a_obj):
+    """|gpu - cpu| <= 1e-9 * max(|cpu|, a) per coordinate (a = semi-major axis)."""
+    scale = np.maximum(np.maximum(np.abs(o_lo), np.abs(o_hi)), a_obj[:, None])
+    dlo = np.abs(g_lo - o_lo) / scale
+    dhi = np.abs(g_hi - o_hi) / scale
+    worst = max(dlo.max(initial=0.0), dhi.max(initial=0.0))
+    assert worst <= 1e-9, f"box bounds differ by {worst:.3e} (relative)"
+    return worst
+
+
+def records_of_boxes(recs, obj, t0, t1, sample):
+    """GPU records that involve sampled box s: object obj[s] on either side and
+    t_lo inside the box's tag (an object's tags partition time)."""
+    keep = np.zeros(len(recs), bool)
+    for s in sample:
+        o, a, b = obj[s], t0[s], t1[s]
+        keep |= ((recs[:, 0] == o) | (recs[:, 1] == o)) & (recs[:, 2] >= a) & (recs[:, 2] < b)
+    return recs[keep]

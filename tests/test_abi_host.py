@@ -1,0 +1,97 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/cd4d.h declares, and rejects bad arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "cd4d.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cd_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1901_10475_amd as cd
+    L = cd.lib()
+    decl = _declared()
+    assert len(decl) >= 15
+    for name in decl:
+        assert hasattr(L, name), name
+    assert set(decl) == set(cd.EXPORTED)
+
+
+def test_status_strings_and_version():
+    import paper_1901_10475_amd as cd
+    L = cd.lib()
+    assert L.cd_version() >= 1
+    for s in range(6):
+        assert L.cd_status_string(s).decode()
+    assert L.cd_status_string(99).decode() == "unknown status"
+
+
+def test_sizes_are_host_only_and_monotone():
+    import paper_1901_10475_amd as cd
+    L = cd.lib()
+    assert L.cd_tree_bytes(0, cd.CD_FP64) == 256
+    assert L.cd_tree_bytes(10, cd.CD_FP64) == 256 + 19 * 64
+    assert L.cd_tree_bytes(10, cd.CD_FP32) == 256 + 19 * 40
+    assert L.cd_build_tree_ws(1000) < L.cd_build_tree_ws(100000)
+    assert L.cd_query_pairs_ws(10, 1000) < L.cd_query_pairs_ws(10, 100000)
+
+
+def test_uniform_box_count_and_argument_errors():
+    import paper_1901_10475_amd as cd
+    L = cd.lib()
+    out = ctypes.c_int64(-1)
+    p = cd.params_struct(1e-3, 398600.4418, 1.0, 600_000, 10_000)
+    assert L.cd_box_count(None, 1000, ctypes.byref(p), ctypes.byref(out), None, 0, None) == 0
+    assert out.value == 60_000
+    p = cd.params_struct(1e-3, 398600.4418, 1.0, 25, 10)
+    assert L.cd_box_count(None, 3, ctypes.byref(p), ctypes.byref(out), None, 0, None) == 0
+    assert out.value == 9
+    p = cd.params_struct(1e-3, 398600.4418, 1.0, 0, 10)          # T = 0: one instant
+    assert L.cd_box_count(None, 4, ctypes.byref(p), ctypes.byref(out), None, 0, None) == 0
+    assert out.value == 4
+    bad = [cd.params_struct(1e-3, 398600.4418, 1.0, 600, 0),        # dt = 0
+           cd.params_struct(0.0, 398600.4418, 1.0, 600, 1),         # tick 0
+           cd.params_struct(1e-3, 398600.4418, -1.0, 600, 1),       # thr < 0
+           cd.params_struct(1e-3, float("nan"), 1.0, 600, 1)]
+    for q in bad:
+        assert L.cd_box_count(None, 5, ctypes.byref(q), ctypes.byref(out), None, 0,
+                              None) == cd.CD_E_INVALID
+        assert L.cd_last_error().decode()
+    q = cd.params_struct(1e-3, 398600.4418, 1.0, 2 ** 32 - 1, 1)
+    assert L.cd_box_count(None, 5, ctypes.byref(q), ctypes.byref(out), None, 0,
+                          None) == cd.CD_E_OVERFLOW
+    q = cd.params_struct(1e-3, 398600.4418, 1.0, 2 ** 31, 1)     # 2^31 boxes per object
+    assert L.cd_box_count(None, 5, ctypes.byref(q), ctypes.byref(out), None, 0,
+                          None) == cd.CD_E_OVERFLOW
+    assert L.cd_box_count(None, -1, ctypes.byref(p), ctypes.byref(out), None, 0,
+                          None) == cd.CD_E_INVALID
+    assert L.cd_box_count(None, 5, None, ctypes.byref(out), None, 0, None) == cd.CD_E_INVALID
+
+
+def test_null_and_workspace_errors_before_any_launch():
+    import paper_1901_10475_amd as cd
+    L = cd.lib()
+    p = cd.params_struct(1e-3, 398600.4418, 1.0, 600, 10)
+    el = cd.cd_elements(None, None, None, None, None, None, 5)     # n > 0, NULL arrays
+    b = cd.cd_boxes()
+    b.count = 300
+    assert L.cd_build_boxes(ctypes.byref(el), None, ctypes.byref(p), ctypes.byref(b), None, 0,
+                            None) == cd.CD_E_INVALID
+    tree = cd.cd_tree()
+    b.precision = 7
+    assert L.cd_build_tree(ctypes.byref(b), cd.CD_FP64, 0, ctypes.byref(tree), None, 0,
+                           None) == cd.CD_E_INVALID
+    b.precision = cd.CD_FP32
+    assert L.cd_build_tree(ctypes.byref(b), cd.CD_FP64, 0, ctypes.byref(tree), None, 0,
+                           None) == cd.CD_E_INVALID                  # FP64 tree of FP32 boxes
+    cnt = ctypes.c_int64(0)
+    assert L.cd_query_pairs(ctypes.byref(tree), None, 0, ctypes.byref(cnt), None, 0,
+                            None) == cd.CD_E_INVALID                 # tree not built

@@ -1,0 +1,169 @@
+"""Pre-flight of the LBVH index arithmetic (cd_logic.h, run on the CPU through
+libcd4d_hostcheck.so): the Karras topology is a binary tree over the sorted
+leaves, skip links follow pre-order, and the stackless walk that the traversal
+kernel performs terminates and finds exactly the oracle's pair set."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1901_10475_amd import catalog
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(os.path.dirname(HERE), "paper_1901_10475_amd", "libcd4d_hostcheck.so")
+END = 0xFFFFFFFF
+
+
+def _lib():
+    L = ctypes.CDLL(LIB)
+    vp = ctypes.c_void_p
+    L.hc_karras.argtypes = [vp, ctypes.c_int64, vp, vp, vp, vp, vp, vp]
+    L.hc_morton30.restype = ctypes.c_uint32
+    L.hc_morton30.argtypes = [ctypes.c_double] * 3 + [vp, vp]
+    L.hc_traverse.restype = ctypes.c_int64
+    L.hc_traverse.argtypes = [ctypes.c_int64, vp, vp, vp, vp, vp, vp, ctypes.c_uint32, vp,
+                              ctypes.c_int64]
+    return L
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def sorted_keys(lo, hi, t0, slab_ticks):
+    L = _lib()
+    c = 0.5 * (lo + hi)
+    mn = c.min(0) if len(c) else np.zeros(3)
+    ext = (c.max(0) - mn) if len(c) else np.zeros(3)
+    inv = np.where(ext > 0, 1.0 / np.where(ext > 0, ext, 1.0), 0.0)
+    mn, inv = np.ascontiguousarray(mn), np.ascontiguousarray(inv)
+    m = np.array([L.hc_morton30(x, y, z, _p(mn), _p(inv)) for x, y, z in c], np.uint64)
+    key = ((t0.astype(np.uint64) // np.uint64(slab_ticks)) << np.uint64(32)) | m
+    order = np.argsort(key, kind="stable")
+    return np.ascontiguousarray(key[order]), order
+
+
+def build_host_tree(lo, hi, t0, t1, obj, slab_ticks):
+    L = _lib()
+    N = len(t0)
+    keys, order = sorted_keys(lo, hi, t0, slab_ticks)
+    left = np.zeros(max(N - 1, 1), np.uint32)
+    right = np.zeros_like(left)
+    first = np.zeros(max(N - 1, 1), np.int64)
+    last = np.zeros_like(first)
+    esc_in = np.zeros(max(N - 1, 1), np.uint32)
+    esc_leaf = np.zeros(N, np.uint32)
+    L.hc_karras(_p(keys), N, _p(left), _p(right), _p(first), _p(last), _p(esc_in), _p(esc_leaf))
+    M = 2 * N - 1
+    nlo = np.zeros((M, 3))
+    nhi = np.zeros((M, 3))
+    nt0 = np.zeros(M, np.uint32)
+    nt1 = np.zeros(M, np.uint32)
+    link = np.zeros(M, np.uint32)
+    esc = np.zeros(M, np.uint32)
+    nlo[N - 1:] = lo[order]
+    nhi[N - 1:] = hi[order]
+    nt0[N - 1:] = t0[order]
+    nt1[N - 1:] = t1[order]
+    link[N - 1:] = obj[order]
+    esc[N - 1:] = esc_leaf
+    if N > 1:
+        link[:N - 1] = left[:N - 1]
+        esc[:N - 1] = esc_in[:N - 1]
+        # unions, children before parents (post-order)
+        def post(u):
+            stack, out = [(u, False)], []
+            while stack:
+                x, done = stack.pop()
+                if x >= N - 1:
+                    continue
+                if done:
+                    out.append(x)
+                else:
+                    stack += [(x, True), (int(right[x]), False), (int(left[x]), False)]
+            return out
+        for x in post(0):
+            l, r = int(left[x]), int(right[x])
+            nlo[x] = np.minimum(nlo[l], nlo[r])
+            nhi[x] = np.maximum(nhi[l], nhi[r])
+            nt0[x] = min(nt0[l], nt0[r])
+            nt1[x] = max(nt1[l], nt1[r])
+    topo = dict(left=left, right=right, first=first, last=last, esc=esc, N=N)
+    return (nlo, nhi, nt0, nt1, link, esc), topo
+
+
+def check_topology(topo):
+    N = topo["N"]
+    if N == 1:
+        assert topo["esc"][0] == END
+        return
+    left, right, first, last, esc = (topo[k] for k in ("left", "right", "first", "last", "esc"))
+    parent = {}
+    for i in range(N - 1):
+        for c in (int(left[i]), int(right[i])):
+            assert c not in parent, "node has two parents"
+            parent[c] = i
+    assert len(parent) == 2 * N - 2 and 0 not in parent          # all but the root
+    rng = lambda x: (x - (N - 1), x - (N - 1)) if x >= N - 1 else (first[x], last[x])
+    assert rng(0) == (0, N - 1)
+    for i in range(N - 1):
+        a, b = rng(int(left[i])), rng(int(right[i]))
+        assert a[0] == first[i] and b[1] == last[i] and a[1] + 1 == b[0]
+    # skip links: next node in pre-order after the node's subtree
+    pre, stack = [], [0]
+    while stack:
+        x = stack.pop()
+        pre.append(x)
+        if x < N - 1:
+            stack += [int(right[x]), int(left[x])]
+    size = {}
+    for x in reversed(pre):
+        size[x] = 1 if x >= N - 1 else 1 + size[int(left[x])] + size[int(right[x])]
+    where = {x: k for k, x in enumerate(pre)}
+    for x in pre:
+        k = where[x] + size[x]
+        want = pre[k] if k < len(pre) else END
+        assert int(esc[x]) == want
+
+
+CASES = [(kind, N, w) for kind in ("uniform", "identical", "disjoint", "line", "huge")
+         for N in (1, 2, 3, 5, 17, 64, 65, 300) for w in (1, 7)] + \
+        [("uniform", 1000, 3), ("uniform", 4097, 5), ("identical", 700, 1)]
+
+
+@pytest.mark.parametrize("kind,N,w", CASES)
+def test_host_walk_matches_oracle(kind, N, w):
+    lo, hi, t0, t1, obj = catalog.random_boxes(N * 7 + len(kind), N, max(2, N // 3),
+                                               extent=40, size=6, T=30, max_len=8, kind=kind)
+    nodes, topo = build_host_tree(lo, hi, t0, t1, obj, w)
+    check_topology(topo)
+    L = _lib()
+    nlo, nhi, nt0, nt1, link, esc = (np.ascontiguousarray(a) for a in nodes)
+    cap = N * N + 16
+    out = np.zeros((cap, 4), np.uint32)
+    cnt = L.hc_traverse(N, _p(nlo), _p(nhi), _p(nt0), _p(nt1), _p(link), _p(esc), w, _p(out), cap)
+    assert cnt >= 0, "walk did not terminate"
+    got = np.unique(out[:cnt], axis=0) if cnt else np.zeros((0, 4), np.uint32)
+    ref = oracle.pairs(oracle.Boxes(lo, hi, t0, t1, obj))
+    assert np.array_equal(got, ref)
+
+
+def test_host_walk_on_orbital_boxes():
+    sc = catalog.scaled(catalog.small_leo(seed=5, n=200, planted=8), horizon_ticks=60_000)
+    b = oracle.boxes(sc.elements, sc.dt_ticks, sc.horizon_ticks, sc.tick_s, sc.threshold_km)
+    nodes, topo = build_host_tree(b.lo, b.hi, b.t0, b.t1, b.obj, sc.dt_ticks)
+    check_topology(topo)
+    L = _lib()
+    nlo, nhi, nt0, nt1, link, esc = (np.ascontiguousarray(a) for a in nodes)
+    N = len(b)
+    out = np.zeros((100000, 4), np.uint32)
+    cnt = L.hc_traverse(N, _p(nlo), _p(nhi), _p(nt0), _p(nt1), _p(link), _p(esc),
+                        sc.dt_ticks, _p(out), 100000)
+    ref = oracle.pairs(b)
+    assert len(ref) > 0
+    # an object's tags partition time, so every record comes from one box pair:
+    # the walk reports each unordered pair exactly once
+    assert cnt == len(ref)
+    assert np.array_equal(np.unique(out[:cnt], axis=0), ref)
