@@ -191,7 +191,9 @@ struct TreeWS {
     uint32_t *morton;
     KV *kva, *kvb;
     uint64_t *keys;
-    uint32_t *idx, *parent, *arrive;
+    uint32_t *idx, *parent, *arrive, *starts;
+    unsigned int *nstarts;
+    Link *links;
     unsigned long long *bounds;
     void *radix;
 };
@@ -206,6 +208,9 @@ size_t layout_tree(void *base, size_t bytes, int64_t N, TreeWS *w)
     w->idx = c.take<uint32_t>(n);
     w->parent = c.take<uint32_t>(2 * n);
     w->arrive = c.take<uint32_t>(n);
+    w->starts = c.take<uint32_t>(refit_starts_cap((uint32_t)n));
+    w->nstarts = c.take<unsigned int>(1);
+    w->links = c.take<Link>(2 * n);
     w->bounds = c.take<unsigned long long>(6);
     w->radix = c.take_bytes(radix_ws_bytes(n));
     return c.off;
@@ -542,12 +547,10 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
         {
             Stage st("keys", s);
             CD_HIP(launch_bounds(bv, boxes->precision, (uint32_t)N, tw.bounds, s));
-            CD_HIP(launch_keys(bv, boxes->precision, (uint32_t)N, w, max_slab, m, tw.bounds,
-                               tw.morton, nullptr, err, s));
         }
         Stage st("sort", s);
-        CD_HIP(launch_segment_sort(tw.morton, (uint32_t)(N / m), m, (uint32_t)N, tw.keys, tw.idx,
-                                   s));
+        CD_HIP(launch_segment_sort(bv, boxes->precision, (uint32_t)(N / m), m, (uint32_t)N, w,
+                                   tw.bounds, tw.keys, tw.idx, err, s));
     } else {
         {
             Stage st("keys", s);
@@ -567,14 +570,19 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
         CD_HIP(radix_sort16(SORT_KV, tw.kva, tw.kvb, (size_t)N, plan, tw.radix, &res, s));
         CD_HIP(launch_unpack_kv((const KV *)res, (uint32_t)N, tw.keys, tw.idx, s));
     }
+    // FP32 trees keep their link records in the tree itself; FP64 records
+    // carry them inline and take them from the workspace during the refit
+    Link *links = precision == CD_FP32
+                      ? (Link *)((Box32 *)nodes + (2 * (size_t)N - 1))
+                      : tw.links;
     {
         Stage st("karras", s);
-        CD_HIP(launch_karras(tw.keys, (uint32_t)N, precision, nodes, tw.parent, s));
+        CD_HIP(launch_karras(tw.keys, (uint32_t)N, links, tw.parent, s));
     }
     {
         Stage st("refit", s);
         CD_HIP(launch_refit(bv, boxes->precision, precision, (uint32_t)N, tw.idx, tw.parent,
-                            tw.arrive, nodes, err, s));
+                            links, tw.arrive, tw.starts, tw.nstarts, nodes, err, s));
     }
     return CD_OK;
 }

@@ -63,6 +63,20 @@ struct BoxOut {
     uint64_t cap;  // entries the arrays hold; stores beyond are dropped
 };
 
+template <int PREC>
+__device__ inline void load_box(const BoxView &b, uint64_t k, double lo[3], double hi[3])
+{
+    for (int d = 0; d < 3; ++d) {
+        if (PREC == CD_FP64) {
+            lo[d] = ((const double *)b.lo[d])[k];
+            hi[d] = ((const double *)b.hi[d])[k];
+        } else {
+            lo[d] = ((const float *)b.lo[d])[k];
+            hi[d] = ((const float *)b.hi[d])[k];
+        }
+    }
+}
+
 // Order-preserving map from double to uint64 (for atomic min/max).
 __host__ __device__ inline uint64_t ordered_bits(double x)
 {
@@ -114,14 +128,16 @@ struct DigitPlan {
 };
 hipError_t radix_sort16(SortKind kind, void *a, void *b, size_t count, const DigitPlan &plan,
                         void *ws, void **result, hipStream_t s);
-// One workgroup per slab: sort (morton32, box index) pairs inside LDS and write
-// 64-bit keys (slab << 32 | morton) and box indices in sorted order.
+// One workgroup per slab: compute the Morton codes of the slab's boxes, sort
+// (code, box index) inside LDS and write 64-bit keys (slab << 32 | code) and
+// box indices in sorted order.  err bit 1: a box's t0 is outside its slab.
 constexpr int kSegThreads = 1024;
 constexpr int kSegItems = 17;
 constexpr int64_t kSegCap = (int64_t)kSegThreads * kSegItems;
-hipError_t launch_segment_sort(const uint32_t *morton, uint32_t nslabs, uint32_t slab_size,
-                               uint32_t N, uint64_t *keys_out, uint32_t *idx_out,
-                               hipStream_t s);
+hipError_t launch_segment_sort(const BoxView &b, int precision, uint32_t nslabs,
+                               uint32_t slab_size, uint32_t N, uint32_t slab_ticks,
+                               const unsigned long long *bounds, uint64_t *keys_out,
+                               uint32_t *idx_out, unsigned int *err, hipStream_t s);
 
 // tree
 hipError_t launch_bounds(const BoxView &b, int precision, uint32_t N,
@@ -132,10 +148,15 @@ hipError_t launch_keys(const BoxView &b, int precision, uint32_t N, uint32_t sla
                        unsigned int *err, hipStream_t s);
 hipError_t launch_unpack_kv(const KV *kv, uint32_t N, uint64_t *keys, uint32_t *idx,
                             hipStream_t s);
-hipError_t launch_karras(const uint64_t *keys, uint32_t N, int precision, void *tree,
-                         uint32_t *parent, hipStream_t s);
+// Refit chunking: one workgroup of kRefitThreads per kRefitLeaves leaves.
+constexpr int kRefitThreads = 1024;
+constexpr int kRefitLeaves = 16384;
+size_t refit_starts_cap(uint32_t N);
+hipError_t launch_karras(const uint64_t *keys, uint32_t N, Link *links, uint32_t *parent,
+                         hipStream_t s);
 hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision, uint32_t N,
-                        const uint32_t *idx, const uint32_t *parent, unsigned int *arrive,
+                        const uint32_t *idx, const uint32_t *parent, const Link *links,
+                        unsigned int *arrive, uint32_t *starts, unsigned int *nstarts,
                         void *tree, unsigned int *err, hipStream_t s);
 
 // query

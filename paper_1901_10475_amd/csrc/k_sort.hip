@@ -334,10 +334,13 @@ hipError_t radix_sort16(SortKind kind, void *a, void *b, size_t count, const Dig
 
 constexpr int kSegWaves = kSegThreads / 64;
 
-__global__ __launch_bounds__(kSegThreads) void k_segment_sort(const uint32_t *__restrict__ morton,
-                                                             uint32_t slab_size, uint32_t N,
+template <int PREC>
+__global__ __launch_bounds__(kSegThreads) void k_segment_sort(BoxView b, uint32_t slab_size,
+                                                             uint32_t N, uint32_t slab_ticks,
+                                                             const unsigned long long *bounds,
                                                              uint64_t *__restrict__ keys_out,
-                                                             uint32_t *__restrict__ idx_out)
+                                                             uint32_t *__restrict__ idx_out,
+                                                             unsigned int *err)
 {
     __shared__ uint32_t xch[kSegCap];
     __shared__ uint32_t cnt[256 * kSegWaves];
@@ -348,14 +351,30 @@ __global__ __launch_bounds__(kSegThreads) void k_segment_sort(const uint32_t *__
     uint32_t m = slab_size;
     if (base + m > N)
         m = base < N ? (uint32_t)(N - base) : 0u;
+    double mn[3], inv[3];
+    for (int d = 0; d < 3; ++d) {
+        mn[d] = from_ordered_bits(bounds[d]);
+        double ext = from_ordered_bits(bounds[3 + d]) - mn[d];
+        inv[d] = ext > 0.0 ? 1.0 / ext : 0.0;
+    }
     uint32_t key[kSegItems], val[kSegItems];
     uint32_t li0 = (uint32_t)w * 64 * kSegItems + lane;
+    bool bad = false;
 #pragma unroll
     for (int j = 0; j < kSegItems; ++j) {
         uint32_t li = li0 + j * 64;
-        key[j] = li < m ? morton[base + li] : 0xFFFFFFFFu;
+        key[j] = 0xFFFFFFFFu;
+        if (li < m) {
+            double lo[3], hi[3];
+            load_box<PREC>(b, base + li, lo, hi);
+            key[j] = morton30(0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]),
+                              0.5 * (lo[2] + hi[2]), mn, inv);
+            bad |= (b.t0[base + li] / slab_ticks) != slab;
+        }
         val[j] = li;
     }
+    if (bad)
+        atomicOr(err, 1u);
     uint64_t lt = lanemask_lt();
     for (int shift = 0; shift < 32; shift += 8) {
         for (int k = threadIdx.x; k < 256 * kSegWaves; k += kSegThreads)
@@ -428,15 +447,21 @@ __global__ __launch_bounds__(kSegThreads) void k_segment_sort(const uint32_t *__
     }
 }
 
-hipError_t launch_segment_sort(const uint32_t *morton, uint32_t nslabs, uint32_t slab_size,
-                               uint32_t N, uint64_t *keys_out, uint32_t *idx_out,
-                               hipStream_t s)
+hipError_t launch_segment_sort(const BoxView &b, int precision, uint32_t nslabs,
+                               uint32_t slab_size, uint32_t N, uint32_t slab_ticks,
+                               const unsigned long long *bounds, uint64_t *keys_out,
+                               uint32_t *idx_out, unsigned int *err, hipStream_t s)
 {
     if (nslabs == 0 || N == 0)
         return hipSuccess;
     if ((int64_t)slab_size > kSegCap)
         return hipErrorInvalidValue;
-    k_segment_sort<<<nslabs, kSegThreads, 0, s>>>(morton, slab_size, N, keys_out, idx_out);
+    if (precision == CD_FP64)
+        k_segment_sort<CD_FP64><<<nslabs, kSegThreads, 0, s>>>(b, slab_size, N, slab_ticks,
+                                                               bounds, keys_out, idx_out, err);
+    else
+        k_segment_sort<CD_FP32><<<nslabs, kSegThreads, 0, s>>>(b, slab_size, N, slab_ticks,
+                                                               bounds, keys_out, idx_out, err);
     return hipGetLastError();
 }
 
