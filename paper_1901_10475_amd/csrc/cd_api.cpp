@@ -93,7 +93,7 @@ struct Stage {
     }
 };
 
-constexpr int64_t kMaxBoxes = (1ll << 31) - 1;  // node ids of 2N - 1 nodes fit 32 bits
+constexpr int64_t kMaxBoxes = (1ll << 30) - 1;  // node ids of 2N - 1 nodes below 2^31
 constexpr size_t kTreeHeader = 256;             // uint32 error word + padding
 constexpr uint32_t kChunk = 16;                 // intervals per thread, per-object steps
 
@@ -191,8 +191,9 @@ struct TreeWS {
     uint32_t *morton;
     KV *kva, *kvb;
     uint64_t *keys;
-    uint32_t *idx, *parent, *arrive, *starts;
-    unsigned int *nstarts;
+    uint32_t *idx, *parent, *arrive, *list_items, *list_count;
+    uint8_t *clev;
+    uint2 *kids;
     Link *links;
     unsigned long long *bounds;
     void *radix;
@@ -208,8 +209,11 @@ size_t layout_tree(void *base, size_t bytes, int64_t N, TreeWS *w)
     w->idx = c.take<uint32_t>(n);
     w->parent = c.take<uint32_t>(2 * n);
     w->arrive = c.take<uint32_t>(n);
-    w->starts = c.take<uint32_t>(refit_starts_cap((uint32_t)n));
-    w->nstarts = c.take<unsigned int>(1);
+    size_t slots = refit_list_slots((uint32_t)n, nullptr) + 1;
+    w->list_items = c.take<uint32_t>(slots * kRefitListCap);
+    w->list_count = c.take<uint32_t>(slots);
+    w->clev = c.take<uint8_t>(n);
+    w->kids = c.take<uint2>(n);
     w->links = c.take<Link>(2 * n);
     w->bounds = c.take<unsigned long long>(6);
     w->radix = c.take_bytes(radix_ws_bytes(n));
@@ -577,12 +581,13 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
                       : tw.links;
     {
         Stage st("karras", s);
-        CD_HIP(launch_karras(tw.keys, (uint32_t)N, links, tw.parent, s));
+        CD_HIP(launch_karras(tw.keys, (uint32_t)N, tw.kids, links, tw.parent, tw.clev, s));
     }
     {
         Stage st("refit", s);
         CD_HIP(launch_refit(bv, boxes->precision, precision, (uint32_t)N, tw.idx, tw.parent,
-                            links, tw.arrive, tw.starts, tw.nstarts, nodes, err, s));
+                            tw.kids, links, tw.clev, tw.arrive, tw.list_items, tw.list_count,
+                            nodes, err, s));
     }
     return CD_OK;
 }

@@ -148,16 +148,51 @@ hipError_t launch_keys(const BoxView &b, int precision, uint32_t N, uint32_t sla
                        unsigned int *err, hipStream_t s);
 hipError_t launch_unpack_kv(const KV *kv, uint32_t N, uint64_t *keys, uint32_t *idx,
                             hipStream_t s);
-// Refit chunking: one workgroup of kRefitThreads per kRefitLeaves leaves.
-constexpr int kRefitThreads = 1024;
-constexpr int kRefitLeaves = 16384;
-size_t refit_starts_cap(uint32_t N);
-hipError_t launch_karras(const uint64_t *keys, uint32_t N, Link *links, uint32_t *parent,
-                         hipStream_t s);
+// Refit levels: level-k blocks hold refit_block(k) = 1024 * 16^k leaves.
+// Level 0 runs one workgroup per block with LDS-resident climbing; higher
+// levels climb in global memory from per-block queues.
+constexpr int kRefitChunk = 1024;
+constexpr int kRefitListCap = 4096;   // queued nodes per block
+constexpr int kRefitMaxLevels = 8;
+constexpr uint32_t kCross = 0x80000000u;   // parent pointer flag: parent level > 0
+constexpr uint32_t kNodeMask = 0x7FFFFFFFu;
+__host__ __device__ inline uint32_t refit_shift(uint32_t lev) { return 10u + 4u * lev; }
+
+struct RefitLists {
+    uint32_t *items;            // [slots][kRefitListCap]
+    uint32_t *count;            // [slots]
+    uint32_t base[kRefitMaxLevels];  // first slot of each level (levels >= 1)
+    // queue `node` for the level-`lev` block that holds leaf `leaf`
+    __device__ bool push(uint32_t lev, uint64_t leaf, uint32_t node) const
+    {
+        if (lev == 0 || lev >= (uint32_t)kRefitMaxLevels)
+            return false;
+        uint32_t slot = base[lev] + (uint32_t)(leaf >> refit_shift(lev));
+        unsigned int k = atomicAdd(&count[slot], 1u);
+        if (k >= (unsigned)kRefitListCap)
+            return false;
+        items[(size_t)slot * kRefitListCap + k] = node;
+        return true;
+    }
+};
+uint32_t refit_levels(uint32_t N);
+size_t refit_list_slots(uint32_t N, uint32_t *base);
+hipError_t launch_karras(const uint64_t *keys, uint32_t N, uint2 *kids, Link *links,
+                         uint32_t *parent, uint8_t *clev, hipStream_t s);
 hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision, uint32_t N,
-                        const uint32_t *idx, const uint32_t *parent, const Link *links,
-                        unsigned int *arrive, uint32_t *starts, unsigned int *nstarts,
-                        void *tree, unsigned int *err, hipStream_t s);
+                        const uint32_t *idx, const uint32_t *parent, const uint2 *kids,
+                        const Link *links, const uint8_t *clev, unsigned int *arrive,
+                        uint32_t *list_items, uint32_t *list_count, void *tree,
+                        unsigned int *err, hipStream_t s);
+
+// Physical block b runs on XCD b % 8.  Maps it to a logical block so that each
+// XCD gets one contiguous range of logical blocks (their data then shares that
+// XCD's L2).  A bijection on [0, nb).
+__device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb)
+{
+    uint32_t x = b & 7u, q = nb >> 3, r = nb & 7u;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
 
 // query
 hipError_t launch_traverse(const void *tree, int precision, uint32_t N, uint32_t slab_ticks,

@@ -73,14 +73,6 @@ struct Q<CD_FP32> {
     }
 };
 
-// Physical block b runs on XCD b % 8.  Give each XCD one contiguous range of
-// leaf blocks, so the nodes its queries share stay in that XCD's L2.
-__device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb)
-{
-    uint32_t x = b & 7u, q = nb >> 3, r = nb & 7u;
-    return x * q + (x < r ? x : r) + (b >> 3);
-}
-
 template <int TP>
 __global__ __launch_bounds__(256) void k_traverse(const void *__restrict__ tree, uint32_t N,
                                                   uint32_t slab_ticks, Rec *__restrict__ out,

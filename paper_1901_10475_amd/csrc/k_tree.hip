@@ -18,7 +18,7 @@ static inline unsigned nblk(uint64_t n, unsigned t) { return (unsigned)((n + t -
 // ---- scene bounds of the box centres -------------------------------------------------
 
 // The frame only shapes the tree (codes outside it are clamped), so a strided
-// sample of about 2^20 boxes is enough.
+// sample of about 2^18 boxes is enough.
 template <int PREC>
 __global__ __launch_bounds__(256) void k_bounds(BoxView b, uint32_t N, uint32_t stride,
                                                 unsigned long long *bounds)
@@ -69,7 +69,7 @@ hipError_t launch_bounds(const BoxView &b, int precision, uint32_t N, unsigned l
         e = launch_fill_u64(bounds + 3, 0ull, 3, s);
     if (e != hipSuccess || N == 0)
         return e;
-    uint32_t stride = N > (1u << 20) ? N >> 20 : 1u;
+    uint32_t stride = N > (1u << 18) ? N >> 18 : 1u;
     unsigned g = nblk((N + stride - 1) / stride, 256);
     g = g > 1024 ? 1024 : g;
     if (precision == CD_FP64)
@@ -156,26 +156,29 @@ hipError_t launch_unpack_kv(const KV *kv, uint32_t N, uint64_t *keys, uint32_t *
 
 // ---- Karras hierarchy + skip links ------------------------------------------------------
 //
-// Thread i builds inner node i.  Outputs, all compact: links[id] = {left child
-// (inner) or 0 (leaf), skip link} for every node id, and parent[child] = i with
-// bit 31 set when node i's leaf range crosses a refit chunk boundary (the
-// first refit phase stops below such nodes).
+// Thread i builds inner node i.  Outputs: kids[i] = {left, right};
+// links[id] = {left child (inner) or 0 (leaf), skip link} for every node id;
+// clev[i] = refit level of node i (the smallest k whose level-k blocks of
+// refit_block(k) leaves contain its whole leaf range); parent[child] = i, with
+// kCross set when clev[i] > 0.
 
-constexpr uint32_t kCrossBit = 0x80000000u;
-
-__global__ void k_karras(const uint64_t *__restrict__ keys, uint32_t N, Link *links,
-                         uint32_t *parent)
+__global__ void k_karras(const uint64_t *__restrict__ keys, uint32_t N, uint2 *kids, Link *links,
+                         uint32_t *parent, uint8_t *clev)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i + 1 >= N)
         return;
     KarrasNode nd = karras_node(keys, N, i);
-    bool cross = (nd.first / kRefitLeaves) != (nd.last / kRefitLeaves);
-    uint32_t pv = i | (cross ? kCrossBit : 0u);
+    uint32_t lev = 0;
+    while ((uint64_t)(nd.first >> refit_shift(lev)) != (uint64_t)(nd.last >> refit_shift(lev)))
+        ++lev;
+    clev[i] = (uint8_t)lev;
+    uint32_t pv = i | (lev > 0 ? kCross : 0u);
     parent[nd.left] = pv;
     parent[nd.right] = pv;
     if (i == 0)
         parent[0] = kEnd;
+    kids[i] = make_uint2(nd.left, nd.right);
     Link li;
     li.link = nd.left;
     li.esc = karras_escape(keys, N, nd.last);
@@ -201,8 +204,8 @@ __global__ void k_single_leaf(Link *links, uint32_t *parent)
     parent[0] = kEnd;
 }
 
-hipError_t launch_karras(const uint64_t *keys, uint32_t N, Link *links, uint32_t *parent,
-                         hipStream_t s)
+hipError_t launch_karras(const uint64_t *keys, uint32_t N, uint2 *kids, Link *links,
+                         uint32_t *parent, uint8_t *clev, hipStream_t s)
 {
     if (N == 0)
         return hipSuccess;
@@ -210,25 +213,27 @@ hipError_t launch_karras(const uint64_t *keys, uint32_t N, Link *links, uint32_t
         k_single_leaf<<<1, 1, 0, s>>>(links, parent);
         return hipGetLastError();
     }
-    k_karras<<<nblk(N - 1, 256), 256, 0, s>>>(keys, N, links, parent);
+    k_karras<<<nblk(N - 1, 256), 256, 0, s>>>(keys, N, kids, links, parent, clev);
     return hipGetLastError();
 }
 
 // ---- bottom-up refit ---------------------------------------------------------------------
 //
-// Every inner box is the exact union of its children.  MI355X's eight XCDs keep
-// separate L2 caches, and agent-scope release/acquire (needed when two threads
-// of different workgroups meet at a node) writes back and invalidates L2; done
-// at every node it costs two orders of magnitude.  The refit therefore runs in
-// two phases:
-//   1. one workgroup per chunk of kRefitLeaves consecutive leaves writes the
-//      leaf records and climbs; arrival counters live in LDS and ordering is
-//      workgroup-scope.  The first thread to reach a node stops, the second
-//      writes the union.  A climb also stops below a node whose leaf range
-//      crosses a chunk boundary and records where it stopped.
-//   2. one workgroup climbs from those stopping points through the remaining
-//      top of the tree (at most depth x chunks nodes), again workgroup-scope.
-// Kernel boundaries order phase 1's writes before phase 2's reads.
+// Every inner box is the exact union of its children.  The classic scheme (one
+// thread per leaf climbs; at each node the first arrival stops and the second
+// writes the union) needs, on MI355X, agent-scope release/acquire whenever the
+// two threads sit in different workgroups: the eight XCDs have separate L2
+// caches, so each such atomic writes back and invalidates L2.  Here every
+// meeting happens inside one workgroup instead.  Leaves are cut into blocks of
+// refit_block(k) = 1024 * 16^k consecutive leaves, level by level; a node
+// belongs to the lowest level whose blocks hold its whole range.
+//   level 0: one workgroup per 1024-leaf chunk, one leaf per thread.  Leaf
+//      boxes, parents, children and arrival counters are staged in LDS, so the
+//      climb touches LDS only; computed node records are written out after.
+//   level k >= 1: one workgroup per level-k block climbs, in global memory with
+//      workgroup-scope counters, from the nodes queued for it by lower levels.
+// A climb that meets a parent of a higher level queues the node for that level
+// and block.  Kernel boundaries order each level's writes before the next.
 
 template <int TP>
 struct NodeIO;
@@ -296,179 +301,250 @@ struct NodeIO<CD_FP32> {
     }
 };
 
-// Union of the box in (lo, hi, t0, t1) with the box of node `other`; writes
-// node p.  Returns false on an inconsistent link.
-template <int TP>
-__device__ inline bool unite_into(void *tree, const Link *links, uint32_t N, uint32_t node,
-                                  uint32_t p, double lo[3], double hi[3], uint32_t &t0,
-                                  uint32_t &t1)
+struct LBox {
+    double lo[3], hi[3];
+    uint32_t t0, t1;
+};
+
+__device__ inline void unite(double lo[3], double hi[3], uint32_t &t0, uint32_t &t1,
+                             const double olo[3], const double ohi[3], uint32_t ot0, uint32_t ot1)
 {
-    Link lp = links[p];
-    uint32_t l = lp.link;
-    if (l >= 2 * N - 1)
-        return false;
-    uint32_t r = links[l].esc;
-    uint32_t other = (l == node) ? r : l;
-    if (other >= 2 * N - 1 || (l != node && r != node))
-        return false;
-    double olo[3], ohi[3];
-    uint32_t ot0, ot1;
-    NodeIO<TP>::get_box(tree, N, other, olo, ohi, ot0, ot1);
     for (int d = 0; d < 3; ++d) {
         lo[d] = fmin(lo[d], olo[d]);
         hi[d] = fmax(hi[d], ohi[d]);
     }
     t0 = t0 < ot0 ? t0 : ot0;
     t1 = t1 > ot1 ? t1 : ot1;
-    NodeIO<TP>::put(tree, N, p, lo, hi, t0, t1, l, lp.esc);
-    return true;
 }
 
 template <int BP, int TP>
-__global__ __launch_bounds__(kRefitThreads) void k_refit_chunks(
+__global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
     BoxView b, uint32_t N, const uint32_t *__restrict__ idx, const uint32_t *__restrict__ parent,
-    const Link *__restrict__ links, void *tree, uint32_t *starts, uint32_t starts_cap,
-    unsigned int *nstarts, unsigned int *err)
+    const uint2 *__restrict__ kids, const Link *__restrict__ links, const uint8_t *clev,
+    void *tree, RefitLists L, unsigned int *err)
 {
-    __shared__ unsigned int cnt[kRefitLeaves];
-    uint32_t c0 = blockIdx.x * (uint32_t)kRefitLeaves;
-    uint32_t c1 = c0 + kRefitLeaves < N ? c0 + kRefitLeaves : N;
-    for (uint32_t k = threadIdx.x; k < (uint32_t)kRefitLeaves; k += kRefitThreads)
-        cnt[k] = 0;
-    __syncthreads();
-    for (uint32_t i = c0 + threadIdx.x; i < c1; i += kRefitThreads) {
+    __shared__ LBox leafb[kRefitChunk];
+    __shared__ LBox innb[kRefitChunk];
+    __shared__ uint2 kid[kRefitChunk];
+    __shared__ uint32_t par_leaf[kRefitChunk], par_in[kRefitChunk];
+    __shared__ unsigned int cnt[kRefitChunk];
+    const uint32_t t = threadIdx.x;
+    const uint32_t c = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t c0 = c * (uint32_t)kRefitChunk;
+    const uint32_t m = N - c0 < (uint32_t)kRefitChunk ? N - c0 : (uint32_t)kRefitChunk;
+    double lo[3], hi[3];
+    uint32_t t0 = 0, t1 = 0;
+    bool bad = false;
+    if (t < m) {
+        uint32_t i = c0 + t;
         uint32_t src = idx[i];
         if (src >= N) {
-            atomicOr(err, 2u);
-            continue;
+            bad = true;
+            src = 0;
         }
-        double lo[3], hi[3];
         load_box<BP>(b, src, lo, hi);
         if (TP == CD_FP32 && BP == CD_FP64) {
-            // the union below must see the rounded leaf, as the traversal does
+            // the unions must see the rounded leaves, as the traversal does
             for (int d = 0; d < 3; ++d) {
                 lo[d] = __double2float_rd(lo[d]);
                 hi[d] = __double2float_ru(hi[d]);
             }
         }
-        uint32_t t0 = b.t0[src], t1 = b.t1[src];
-        uint32_t node = N - 1 + i;
-        NodeIO<TP>::put(tree, N, node, lo, hi, t0, t1, b.obj[src], links[node].esc);
+        t0 = b.t0[src];
+        t1 = b.t1[src];
+        uint32_t leaf = N - 1 + i;
+        NodeIO<TP>::put(tree, N, leaf, lo, hi, t0, t1, b.obj[src], links[leaf].esc);
+        for (int d = 0; d < 3; ++d) {
+            leafb[t].lo[d] = lo[d];
+            leafb[t].hi[d] = hi[d];
+        }
+        leafb[t].t0 = t0;
+        leafb[t].t1 = t1;
+        par_leaf[t] = parent[leaf];
+    }
+    if (c0 + t + 1 < N) {  // inner node c0 + t exists
+        kid[t] = kids[c0 + t];
+        par_in[t] = parent[c0 + t];
+    }
+    cnt[t] = 0;
+    __syncthreads();
+    if (t < m) {
+        uint32_t node = N - 1 + c0 + t;
+        uint32_t pv = par_leaf[t];
         for (int guard = 0; guard < 160; ++guard) {
-            uint32_t pv = parent[node];
             if (pv == kEnd)
                 break;
-            uint32_t p = pv & ~kCrossBit;
-            if (p >= N - 1) {
-                atomicOr(err, 2u);
+            uint32_t p = pv & kNodeMask;
+            if (pv & kCross) {
+                bad |= !L.push(clev[p], c0, node);
                 break;
             }
-            if (pv & kCrossBit) {
-                unsigned int at = atomicAdd(nstarts, 1u);
-                if (at < starts_cap)
-                    starts[at] = node;
-                else
-                    atomicOr(err, 8u);
+            uint32_t slot = p - c0;
+            if (p < c0 || slot >= m) {
+                bad = true;
                 break;
             }
-            if (p < c0 || p >= c1) {
-                atomicOr(err, 2u);
-                break;
-            }
-            unsigned int old = __hip_atomic_fetch_add(&cnt[p - c0], 1u, __ATOMIC_ACQ_REL,
+            unsigned int old = __hip_atomic_fetch_add(&cnt[slot], 1u, __ATOMIC_ACQ_REL,
                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
             if (old == 0)
                 break;
-            if (!unite_into<TP>(tree, links, N, node, p, lo, hi, t0, t1)) {
-                atomicOr(err, 2u);
+            uint2 lr = kid[slot];
+            uint32_t sib = lr.x == node ? lr.y : lr.x;
+            const LBox *o = nullptr;
+            if (sib >= N - 1 && sib - (N - 1) - c0 < m)
+                o = &leafb[sib - (N - 1) - c0];
+            else if (sib < N - 1 && sib - c0 < m)
+                o = &innb[sib - c0];
+            if (!o || (lr.x != node && lr.y != node)) {
+                bad = true;
                 break;
             }
+            unite(lo, hi, t0, t1, o->lo, o->hi, o->t0, o->t1);
+            for (int d = 0; d < 3; ++d) {
+                innb[slot].lo[d] = lo[d];
+                innb[slot].hi[d] = hi[d];
+            }
+            innb[slot].t0 = t0;
+            innb[slot].t1 = t1;
             node = p;
+            pv = par_in[slot];
         }
     }
+    __syncthreads();
+    // inner nodes completed here (both children arrived) go out in one pass
+    if (c0 + t + 1 < N && cnt[t] == 2) {
+        uint32_t p = c0 + t;
+        NodeIO<TP>::put(tree, N, p, innb[t].lo, innb[t].hi, innb[t].t0, innb[t].t1, kid[t].x,
+                        links[p].esc);
+    }
+    if (bad)
+        atomicOr(err, 2u);
 }
 
+// Phase k >= 1: one workgroup per level-k block climbs from the nodes queued
+// for it, in global memory with workgroup-scope arrival counters, through the
+// nodes of level k; a parent of a higher level gets the node queued instead.
 template <int TP>
-__global__ __launch_bounds__(kRefitThreads) void k_refit_top(
-    uint32_t N, const uint32_t *__restrict__ parent, const Link *__restrict__ links, void *tree,
-    unsigned int *arrive, const uint32_t *starts, const unsigned int *nstarts, uint32_t starts_cap,
-    unsigned int *err)
+__global__ __launch_bounds__(kRefitChunk) void k_refit_level(
+    uint32_t N, uint32_t lev, const uint32_t *__restrict__ parent, const uint2 *__restrict__ kids,
+    const Link *__restrict__ links, const uint8_t *clev, void *tree, unsigned int *arrive,
+    RefitLists L, unsigned int *err)
 {
-    uint32_t ns = *nstarts;
-    ns = ns < starts_cap ? ns : starts_cap;
-    for (uint32_t s = threadIdx.x; s < ns; s += kRefitThreads) {
-        uint32_t node = starts[s];
+    uint32_t blk = blockIdx.x;
+    uint32_t n = L.count[L.base[lev] + blk];
+    n = n < (uint32_t)kRefitListCap ? n : (uint32_t)kRefitListCap;
+    const uint32_t *list = L.items + (size_t)(L.base[lev] + blk) * kRefitListCap;
+    uint64_t first_leaf = (uint64_t)blk << refit_shift(lev);
+    bool ok = true;
+    for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) {
+        uint32_t node = list[j];
         if (node >= 2 * N - 1) {
-            atomicOr(err, 2u);
+            ok = false;
             continue;
         }
         double lo[3], hi[3];
         uint32_t t0, t1;
         NodeIO<TP>::get_box(tree, N, node, lo, hi, t0, t1);
-        for (int guard = 0; guard < 160; ++guard) {
+        for (int guard = 0;; ++guard) {
             uint32_t pv = parent[node];
             if (pv == kEnd)
                 break;
-            uint32_t p = pv & ~kCrossBit;
-            if (p >= N - 1) {
-                atomicOr(err, 2u);
+            uint32_t p = pv & kNodeMask;
+            if (p >= N - 1 || guard > 160) {
+                ok = false;
+                break;
+            }
+            uint32_t pl = clev[p];
+            if (pl > lev) {
+                ok &= L.push(pl, first_leaf, node);
                 break;
             }
             unsigned int old = __hip_atomic_fetch_add(&arrive[p], 1u, __ATOMIC_ACQ_REL,
                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
             if (old == 0)
                 break;
-            if (!unite_into<TP>(tree, links, N, node, p, lo, hi, t0, t1)) {
-                atomicOr(err, 2u);
+            uint2 lr = kids[p];
+            if (lr.x != node && lr.y != node) {
+                ok = false;
                 break;
             }
+            uint32_t sib = lr.x == node ? lr.y : lr.x;
+            double olo[3], ohi[3];
+            uint32_t ot0, ot1;
+            NodeIO<TP>::get_box(tree, N, sib, olo, ohi, ot0, ot1);
+            unite(lo, hi, t0, t1, olo, ohi, ot0, ot1);
+            NodeIO<TP>::put(tree, N, p, lo, hi, t0, t1, lr.x, links[p].esc);
             node = p;
         }
     }
+    if (!ok)
+        atomicOr(err, 2u);
 }
 
-size_t refit_starts_cap(uint32_t N)
+uint32_t refit_levels(uint32_t N)
 {
-    size_t chunks = ((size_t)N + kRefitLeaves - 1) / kRefitLeaves;
-    return 2 * 160 * chunks + 64;
+    uint32_t lev = 0;
+    while (N > 1 && ((uint64_t)(N - 1) >> refit_shift(lev)) != 0)
+        ++lev;
+    return lev;
+}
+
+size_t refit_list_slots(uint32_t N, uint32_t *base)
+{
+    uint32_t L = refit_levels(N);
+    size_t slots = 0;
+    for (uint32_t k = 0; k <= L + 1 && k < kRefitMaxLevels; ++k) {
+        if (base)
+            base[k] = (uint32_t)slots;
+        if (k >= 1)
+            slots += ((uint64_t)N + (1ull << refit_shift(k)) - 1) >> refit_shift(k);
+    }
+    return slots;
 }
 
 hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision, uint32_t N,
-                        const uint32_t *idx, const uint32_t *parent, const Link *links,
-                        unsigned int *arrive, uint32_t *starts, unsigned int *nstarts,
-                        void *tree, unsigned int *err, hipStream_t s)
+                        const uint32_t *idx, const uint32_t *parent, const uint2 *kids,
+                        const Link *links, const uint8_t *clev, unsigned int *arrive,
+                        uint32_t *list_items, uint32_t *list_count, void *tree,
+                        unsigned int *err, hipStream_t s)
 {
     if (N == 0)
         return hipSuccess;
-    hipError_t e = launch_fill_u32(arrive, 0u, N > 1 ? N - 1 : 1, s);
-    if (e == hipSuccess)
-        e = launch_fill_u32(nstarts, 0u, 1, s);
-    if (e != hipSuccess)
-        return e;
-    uint32_t cap = (uint32_t)refit_starts_cap(N);
-    unsigned g = nblk(N, kRefitLeaves);
+    RefitLists L;
+    size_t slots = refit_list_slots(N, L.base);
+    L.items = list_items;
+    L.count = list_count;
+    uint32_t levels = refit_levels(N);
+    hipError_t e = hipSuccess;
+    if (levels > 0) {
+        e = launch_fill_u32(list_count, 0u, slots, s);
+        if (e == hipSuccess)
+            e = launch_fill_u32(arrive, 0u, N - 1, s);
+        if (e != hipSuccess)
+            return e;
+    }
+    uint32_t nchunks = nblk(N, kRefitChunk);
     if (box_precision == CD_FP64 && tree_precision == CD_FP64)
-        k_refit_chunks<CD_FP64, CD_FP64><<<g, kRefitThreads, 0, s>>>(b, N, idx, parent, links,
-                                                                      tree, starts, cap, nstarts,
-                                                                      err);
+        k_refit_chunks<CD_FP64, CD_FP64><<<nchunks, kRefitChunk, 0, s>>>(
+            b, N, idx, parent, kids, links, clev, tree, L, err);
     else if (box_precision == CD_FP64)
-        k_refit_chunks<CD_FP64, CD_FP32><<<g, kRefitThreads, 0, s>>>(b, N, idx, parent, links,
-                                                                      tree, starts, cap, nstarts,
-                                                                      err);
+        k_refit_chunks<CD_FP64, CD_FP32><<<nchunks, kRefitChunk, 0, s>>>(
+            b, N, idx, parent, kids, links, clev, tree, L, err);
     else
-        k_refit_chunks<CD_FP32, CD_FP32><<<g, kRefitThreads, 0, s>>>(b, N, idx, parent, links,
-                                                                      tree, starts, cap, nstarts,
-                                                                      err);
+        k_refit_chunks<CD_FP32, CD_FP32><<<nchunks, kRefitChunk, 0, s>>>(
+            b, N, idx, parent, kids, links, clev, tree, L, err);
     e = hipGetLastError();
-    if (e != hipSuccess || N <= (uint32_t)kRefitLeaves)
-        return e;
-    if (tree_precision == CD_FP64)
-        k_refit_top<CD_FP64><<<1, kRefitThreads, 0, s>>>(N, parent, links, tree, arrive, starts,
-                                                         nstarts, cap, err);
-    else
-        k_refit_top<CD_FP32><<<1, kRefitThreads, 0, s>>>(N, parent, links, tree, arrive, starts,
-                                                         nstarts, cap, err);
-    return hipGetLastError();
+    for (uint32_t k = 1; k <= levels && e == hipSuccess; ++k) {
+        uint32_t nb = (uint32_t)(((uint64_t)N + (1ull << refit_shift(k)) - 1) >> refit_shift(k));
+        if (tree_precision == CD_FP64)
+            k_refit_level<CD_FP64><<<nb, kRefitChunk, 0, s>>>(N, k, parent, kids, links, clev,
+                                                              tree, arrive, L, err);
+        else
+            k_refit_level<CD_FP32><<<nb, kRefitChunk, 0, s>>>(N, k, parent, kids, links, clev,
+                                                              tree, arrive, L, err);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 } // namespace cd
