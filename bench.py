@@ -28,20 +28,24 @@ METRIC = "ms per n-to-n query and box-pair tests/s at n=16848, 1h horizon; HBM G
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(stage, N, n, P, tree_prec, box_prec):
-    """Compulsory HBM bytes of one launch of a stage (see the design notes)."""
+def algorithmic_bytes(stage, N, n, P, tree_prec, box_prec, seeds=0):
+    """Compulsory HBM bytes of one launch of a stage: every input read once,
+    every output written once (intermediate LDS traffic excluded)."""
     fb = 8 if box_prec == 0 else 4          # box float bytes
     box = 6 * fb + 12                         # lo/hi + t0, t1, obj
     node = 64 if tree_prec == 0 else 40       # tree record (box + links)
     nodes = 2 * N - 1
     table = {
-        "boxes": N * box,                                 # written once
-        "keys": N * (6 * fb + 4) + N * 4,                 # read bounds/centres, write codes
-        "sort": N * 4 + N * 12,                           # read codes, write keys + index
-        "karras": N * 8 + nodes * 4 + nodes * 4 + N * 4,  # keys, parents, links, skips
-        "refit": N * (box + 4) + nodes * node + (N - 1) * 2 * node,  # boxes in, nodes out,
-                                                          # children read at each union
-        "traverse": nodes * node + P * 16,                # every node once, records out
+        "boxes": N * box,                                    # boxes written
+        "keys": 0,                                           # sampled frame only
+        "sort": N * (6 * fb + 4) + N * 12,                   # boxes + t0 in, keys + index out
+        "karras": N * 8 + (N - 1) * (8 + 1) + nodes * (8 + 4),  # keys in; kids, level,
+                                                             # links, parents out
+        "refit": N * (box + 4) + nodes * (4 + 8) + (N - 1) * 8 + nodes * node,
+                                                             # boxes, index, parents, links,
+                                                             # kids in; node records out
+        "traverse": seeds * (8 + 2 * node) + P * 16,         # seed pairs and their nodes,
+                                                             # records out
         "canon": P * 16 * 3,
     }
     return table.get(stage)
@@ -78,6 +82,9 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (a known-size "
+                         "kernel for calibrating HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1 "
@@ -90,6 +97,12 @@ def main():
     from paper_1901_10475_amd import catalog
 
     torch.cuda.set_device(0)
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     sc = catalog.tracked_hour()
     prec = cd.CD_FP64 if args.precision == "fp64" else cd.CD_FP32
     box_prec = cd.CD_FP64

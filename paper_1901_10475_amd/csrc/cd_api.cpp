@@ -94,7 +94,9 @@ struct Stage {
 };
 
 constexpr int64_t kMaxBoxes = (1ll << 30) - 1;  // node ids of 2N - 1 nodes below 2^31
-constexpr size_t kTreeHeader = 256;             // uint32 error word + padding
+constexpr size_t kTreeHeader = sizeof(TreeHeader);
+constexpr int kExpandBatch = 12;                 // levels launched between count checks
+constexpr int kExpandMaxLevels = 400;            // > 2 x the deepest possible tree
 constexpr uint32_t kChunk = 16;                 // intervals per thread, per-object steps
 
 int check_params(const cd_params *p)
@@ -193,7 +195,6 @@ struct TreeWS {
     uint64_t *keys;
     uint32_t *idx, *parent, *arrive, *list_items, *list_count;
     uint8_t *clev;
-    uint2 *kids;
     Link *links;
     unsigned long long *bounds;
     void *radix;
@@ -213,7 +214,6 @@ size_t layout_tree(void *base, size_t bytes, int64_t N, TreeWS *w)
     w->list_items = c.take<uint32_t>(slots * kRefitListCap);
     w->list_count = c.take<uint32_t>(slots);
     w->clev = c.take<uint8_t>(n);
-    w->kids = c.take<uint2>(n);
     w->links = c.take<Link>(2 * n);
     w->bounds = c.take<unsigned long long>(6);
     w->radix = c.take_bytes(radix_ws_bytes(n));
@@ -225,11 +225,20 @@ struct QueryWS {
     unsigned long long *counter;
     uint32_t *flags, *pos;
     void *scan, *radix;
+    uint2 *qa, *qb;
+    unsigned int *qcount, *qflags;
+    uint32_t qcap;
 };
-size_t layout_query(void *base, size_t bytes, int64_t cap, QueryWS *w)
+uint32_t queue_cap(int64_t N) { return (uint32_t)(N / 4 > 65536 ? N / 4 : 65536); }
+size_t layout_query(void *base, size_t bytes, int64_t N, int64_t cap, QueryWS *w)
 {
     Carve c(base, bytes);
     size_t m = (size_t)(cap > 0 ? cap : 1);
+    w->qcap = queue_cap(N);
+    w->qa = c.take<uint2>(w->qcap);
+    w->qb = c.take<uint2>(w->qcap);
+    w->qcount = c.take<unsigned int>(kExpandMaxLevels + 2);
+    w->qflags = c.take<unsigned int>(1);
     w->raw = c.take<Rec>(m);
     w->alt = c.take<Rec>(m);
     w->counter = c.take<unsigned long long>(1);
@@ -489,7 +498,8 @@ size_t cd_tree_bytes(int64_t count, int precision)
 {
     if (count <= 0)
         return kTreeHeader;
-    return kTreeHeader + (size_t)(2 * count - 1) * tree_node_bytes(precision);
+    return tree_seeds_offset((uint64_t)count, precision) +
+           seed_cap((uint64_t)count) * sizeof(uint2);
 }
 
 size_t cd_build_tree_ws(int64_t count)
@@ -579,15 +589,20 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
     Link *links = precision == CD_FP32
                       ? (Link *)((Box32 *)nodes + (2 * (size_t)N - 1))
                       : tw.links;
+    uint2 *kids = (uint2 *)((char *)tree->mem + tree_kids_offset((uint64_t)N, precision));
     {
         Stage st("karras", s);
-        CD_HIP(launch_karras(tw.keys, (uint32_t)N, tw.kids, links, tw.parent, tw.clev, s));
+        CD_HIP(launch_karras(tw.keys, (uint32_t)N, kids, links, tw.parent, tw.clev, s));
     }
     {
         Stage st("refit", s);
+        SeedSink sink;
+        sink.items = (uint2 *)((char *)tree->mem + tree_seeds_offset((uint64_t)N, precision));
+        sink.cap = (uint32_t)seed_cap((uint64_t)N);
+        sink.hdr = (TreeHeader *)tree->mem;
         CD_HIP(launch_refit(bv, boxes->precision, precision, (uint32_t)N, tw.idx, tw.parent,
-                            tw.kids, links, tw.clev, tw.arrive, tw.list_items, tw.list_count,
-                            nodes, err, s));
+                            kids, links, tw.clev, tw.arrive, tw.list_items, tw.list_count,
+                            nodes, sink, err, s));
     }
     return CD_OK;
 }
@@ -597,7 +612,7 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
 size_t cd_query_pairs_ws(int64_t count, int64_t capacity)
 {
     QueryWS w;
-    return layout_query(nullptr, 0, capacity > 0 ? capacity : 0, &w);
+    return layout_query(nullptr, 0, count, capacity > 0 ? capacity : 0, &w);
 }
 
 int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t *count_host,
@@ -621,15 +636,56 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
     unsigned int *err = (unsigned int *)tree->mem;
     const void *nodes = (const char *)tree->mem + kTreeHeader;
     QueryWS w;
-    layout_query(ws, ws_bytes, capacity, &w);
-    CD_HIP(launch_fill_u64(w.counter, 0ull, 1, s));
-    {
-        Stage st("traverse", s);
-        CD_HIP(launch_traverse(nodes, tree->precision, (uint32_t)N, tree->slab_ticks, w.raw,
-                               (unsigned long long)capacity, w.counter, err, s));
-    }
+    layout_query(ws, ws_bytes, N, capacity, &w);
+    TreeHeader *hdr = (TreeHeader *)tree->mem;
+    const uint2 *seeds =
+        (const uint2 *)((const char *)tree->mem + tree_seeds_offset((uint64_t)N, tree->precision));
+    const uint2 *kids =
+        (const uint2 *)((const char *)tree->mem + tree_kids_offset((uint64_t)N, tree->precision));
     unsigned long long cnt = 0;
     unsigned int e = 0;
+    bool done = false;
+    {
+        Stage st("traverse", s);
+        // node-pair traversal from the refit's overlapping sibling pairs
+        unsigned int h[3] = {0, 0, 0};
+        CD_HIP(hipMemcpyAsync(h, hdr, sizeof h, hipMemcpyDeviceToHost, s));
+        CD_HIP(hipStreamSynchronize(s));
+        if (h[0] == 0 && h[2] == 0 && N > 1) {
+            CD_HIP(launch_fill_u64(w.counter, 0ull, 1, s));
+            CD_HIP(launch_fill_u32(w.qcount, 0u, kExpandMaxLevels + 2, s));
+            CD_HIP(launch_fill_u32(w.qflags, 0u, 1, s));
+            const uint2 *in = seeds;
+            const unsigned int *n_in = &hdr->nseeds;
+            uint32_t in_cap = (uint32_t)seed_cap((uint64_t)N);
+            unsigned int qf = 0, left = 1;
+            for (int lev = 0; lev < kExpandMaxLevels; ++lev) {
+                uint2 *outq = (lev & 1) ? w.qb : w.qa;
+                CD_HIP(launch_expand(nodes, kids, tree->precision, (uint32_t)N, in, n_in, in_cap,
+                                     outq,
+                                     w.qcount + lev + 1, w.qcap, w.raw,
+                                     (unsigned long long)capacity, w.counter, w.qflags, s));
+                in = outq;
+                n_in = w.qcount + lev + 1;
+                in_cap = w.qcap;
+                if ((lev + 1) % kExpandBatch == 0 || lev + 1 == kExpandMaxLevels) {
+                    CD_HIP(hipMemcpyAsync(&left, n_in, sizeof left, hipMemcpyDeviceToHost, s));
+                    CD_HIP(hipMemcpyAsync(&qf, w.qflags, sizeof qf, hipMemcpyDeviceToHost, s));
+                    CD_HIP(hipStreamSynchronize(s));
+                    if (left == 0 || qf)
+                        break;
+                }
+            }
+            // done only if every queue drained without overflow
+            done = (qf == 0 && left == 0);
+        }
+        if (!done) {
+            // bounded fallback: one stackless walk per leaf
+            CD_HIP(launch_fill_u64(w.counter, 0ull, 1, s));
+            CD_HIP(launch_traverse(nodes, tree->precision, (uint32_t)N, tree->slab_ticks, w.raw,
+                                   (unsigned long long)capacity, w.counter, err, s));
+        }
+    }
     CD_HIP(hipMemcpyAsync(&cnt, w.counter, sizeof cnt, hipMemcpyDeviceToHost, s));
     CD_HIP(hipMemcpyAsync(&e, err, sizeof e, hipMemcpyDeviceToHost, s));
     CD_HIP(hipStreamSynchronize(s));

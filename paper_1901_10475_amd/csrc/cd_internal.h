@@ -77,6 +77,62 @@ __device__ inline void load_box(const BoxView &b, uint64_t k, double lo[3], doub
     }
 }
 
+// ---- wave helpers -----------------------------------------------------------------
+
+__device__ inline uint32_t wave_inclusive_scan(uint32_t v)
+{
+    int lane = threadIdx.x & 63;
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t u = __shfl_up(v, o, 64);
+        if (lane >= o)
+            v += u;
+    }
+    return v;
+}
+
+// Lanes (among `active`) whose 8-bit digit equals this lane's digit.
+__device__ inline uint64_t match_digit(uint32_t d, uint64_t active)
+{
+    uint64_t peers = active;
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+        uint64_t b = __ballot((d >> bit) & 1u);
+        peers &= ((d >> bit) & 1u) ? b : ~b;
+    }
+    return peers;
+}
+
+__device__ inline uint64_t lanemask_lt()
+{
+    int lane = threadIdx.x & 63;
+    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// Exclusive scan over all threads of a block (blockDim multiple of 64, <= 1024).
+// `wsum` is LDS scratch of blockDim/64 entries.  Returns the exclusive prefix;
+// *total gets the block sum.
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *wsum, uint32_t *total)
+{
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    uint32_t inc = wave_inclusive_scan(v);
+    if (lane == 63)
+        wsum[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+        uint32_t x = lane < nw ? wsum[lane] : 0u;
+        uint32_t xi = wave_inclusive_scan(x);
+        if (lane < nw)
+            wsum[lane] = xi - x;
+        if (lane == nw - 1)
+            wsum[32] = xi;
+    }
+    __syncthreads();
+    uint32_t r = wsum[w] + inc - v;
+    *total = wsum[32];
+    __syncthreads();
+    return r;
+}
+
 // Order-preserving map from double to uint64 (for atomic min/max).
 __host__ __device__ inline uint64_t ordered_bits(double x)
 {
@@ -158,6 +214,52 @@ constexpr uint32_t kCross = 0x80000000u;   // parent pointer flag: parent level 
 constexpr uint32_t kNodeMask = 0x7FFFFFFFu;
 __host__ __device__ inline uint32_t refit_shift(uint32_t lev) { return 10u + 4u * lev; }
 
+// Tree buffer header (the first 256 bytes of cd_tree.mem).
+struct TreeHeader {
+    uint32_t err;            // bit 0: slab hint / horizon violated, 1: refit, 2: traversal
+    uint32_t nseeds;         // overlapping sibling pairs found by the refit
+    uint32_t seed_overflow;  // set when more than seed_cap(N) pairs were found
+    uint32_t pad[61];
+};
+static_assert(sizeof(TreeHeader) == 256, "TreeHeader layout");
+inline size_t seed_cap(uint64_t N) { return (size_t)(N / 4 + 4096); }
+// Tree buffer layout: header | nodes (FP64: 64-byte records; FP32: 32-byte
+// boxes, then 8-byte links) | kids[N - 1] (both children of each inner node)
+// | seeds[seed_cap(N)].
+inline size_t tree_kids_offset(uint64_t N, int precision)
+{
+    return sizeof(TreeHeader) + (size_t)(2 * N - 1) *
+                                    (precision == CD_FP64 ? 64u : 40u);
+}
+inline size_t tree_seeds_offset(uint64_t N, int precision)
+{
+    return tree_kids_offset(N, precision) + (size_t)(N > 1 ? N - 1 : 1) * 8u;
+}
+
+// Overlapping sibling pairs recorded while the refit forms each union: the
+// seeds of the node-pair self-traversal.  Workgroups stage them in LDS and
+// reserve space with one atomic per flush.
+struct SeedSink {
+    uint2 *items;
+    uint32_t cap;
+    TreeHeader *hdr;
+    __device__ void put_many(const uint2 *src, uint32_t n, uint32_t base) const
+    {
+        for (uint32_t k = 0; k < n; ++k)
+            if (base + k < cap)
+                items[base + k] = src[k];
+    }
+    __device__ uint32_t reserve(uint32_t n) const
+    {
+        uint32_t base = atomicAdd(&hdr->nseeds, n);
+        if (base + n > cap)
+            atomicOr(&hdr->seed_overflow, 1u);
+        return base;
+    }
+};
+constexpr int kSeedStage = 256;  // LDS-staged seeds per workgroup before a flush
+constexpr int kRefitLevelThreads = 128;  // queue levels: few climbs per block
+
 struct RefitLists {
     uint32_t *items;            // [slots][kRefitListCap]
     uint32_t *count;            // [slots]
@@ -183,7 +285,7 @@ hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision,
                         const uint32_t *idx, const uint32_t *parent, const uint2 *kids,
                         const Link *links, const uint8_t *clev, unsigned int *arrive,
                         uint32_t *list_items, uint32_t *list_count, void *tree,
-                        unsigned int *err, hipStream_t s);
+                        const SeedSink &seeds, unsigned int *err, hipStream_t s);
 
 // Physical block b runs on XCD b % 8.  Maps it to a logical block so that each
 // XCD gets one contiguous range of logical blocks (their data then shares that
@@ -198,6 +300,16 @@ __device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb)
 hipError_t launch_traverse(const void *tree, int precision, uint32_t N, uint32_t slab_ticks,
                            Rec *out, unsigned long long capacity, unsigned long long *counter,
                            unsigned int *err, hipStream_t s);
+// One breadth-first level of the node-pair self-traversal: every pair in
+// `in` (count *n_in, at most in_cap) is expanded into the overlapping pairs of
+// its children; pairs of two leaves are emitted as records, the others queued
+// in `outq` (count *n_out, capacity out_cap; bit 0 of *flags on overflow).
+hipError_t launch_expand(const void *tree, const uint2 *kids, int precision, uint32_t N,
+                         const uint2 *in,
+                         const unsigned int *n_in, uint32_t in_cap, uint2 *outq,
+                         unsigned int *n_out, uint32_t out_cap, Rec *out,
+                         unsigned long long capacity, unsigned long long *counter,
+                         unsigned int *flags, hipStream_t s);
 hipError_t launch_unique(const Rec *in, uint32_t count, uint32_t *flags, uint32_t *pos,
                          void *scan_ws, Rec *out, hipStream_t s);
 

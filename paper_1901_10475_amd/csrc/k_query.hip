@@ -142,6 +142,148 @@ hipError_t launch_traverse(const void *tree, int precision, uint32_t N, uint32_t
     return hipGetLastError();
 }
 
+// ---- node-pair self-traversal ------------------------------------------------------------------
+//
+// The refit records every pair of sibling nodes whose 4D boxes overlap.  Every
+// overlapping pair of leaves lies under exactly one such pair (the children of
+// its lowest common ancestor), and expanding an overlapping node pair into the
+// overlapping pairs of their children reaches each of those leaf pairs exactly
+// once.  One launch per level: a lane takes one queued pair, loads the
+// children's boxes, tests the (up to) four child pairs, emits leaf pairs as
+// records and queues the rest; both appends are aggregated per wave with a
+// ballot and one atomic.
+
+// Side s of a pair: a leaf stays itself, an inner node is replaced by its two
+// children (kids of the tree).  Loads the boxes of the resulting nodes.
+template <int TP>
+__device__ inline bool load_side(const void *tree, const uint2 *kids, uint32_t N, uint32_t x,
+                                 uint32_t ids[2], typename Q<TP>::F lo[2][3],
+                                 typename Q<TP>::F hi[2][3], uint32_t t0[2], uint32_t t1[2],
+                                 uint32_t lk[2], uint32_t &cnt)
+{
+    const uint32_t nodes = 2 * N - 1;
+    uint32_t e;
+    if (x >= nodes)
+        return false;
+    if (x >= N - 1) {
+        ids[0] = x;
+        Q<TP>::load(tree, N, x, lo[0], hi[0], t0[0], t1[0], lk[0], e);
+        cnt = 1;
+        return true;
+    }
+    uint2 kk = kids[x];
+    if (kk.x >= nodes || kk.y >= nodes)
+        return false;
+    ids[0] = kk.x;
+    ids[1] = kk.y;
+    Q<TP>::load(tree, N, kk.x, lo[0], hi[0], t0[0], t1[0], lk[0], e);
+    Q<TP>::load(tree, N, kk.y, lo[1], hi[1], t0[1], t1[1], lk[1], e);
+    cnt = 2;
+    return true;
+}
+
+template <int TP>
+__global__ __launch_bounds__(256) void k_expand(const void *__restrict__ tree,
+                                                const uint2 *__restrict__ kids, uint32_t N,
+                                                const uint2 *__restrict__ in,
+                                                const unsigned int *n_in, uint32_t in_cap,
+                                                uint2 *__restrict__ outq, unsigned int *n_out,
+                                                uint32_t out_cap, Rec *__restrict__ out,
+                                                unsigned long long capacity,
+                                                unsigned long long *counter, unsigned int *flags)
+{
+    using F = typename Q<TP>::F;
+    __shared__ uint32_t wsum[64];
+    __shared__ unsigned int qbase;
+    __shared__ unsigned long long rbase;
+    uint32_t n = *n_in;
+    n = n < in_cap ? n : in_cap;
+    // block-uniform loop: the block scan below needs every thread
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
+        uint32_t k = base + threadIdx.x;
+        bool active = k < n;
+        uint32_t ids[2][2], cnt[2] = {0, 0};
+        F lo[2][2][3], hi[2][2][3];
+        uint32_t t0[2][2], t1[2][2], lk[2][2];
+        if (active) {
+            uint2 pr = in[k];
+            bool ok = load_side<TP>(tree, kids, N, pr.x, ids[0], lo[0], hi[0], t0[0], t1[0],
+                                    lk[0], cnt[0]) &&
+                      load_side<TP>(tree, kids, N, pr.y, ids[1], lo[1], hi[1], t0[1], t1[1],
+                                    lk[1], cnt[1]);
+            if (!ok) {
+                atomicOr(flags, 2u);
+                active = false;
+            }
+        }
+        uint32_t push_mask = 0, hit_mask = 0;
+        for (int ia = 0; ia < 2; ++ia)
+            for (int ic = 0; ic < 2; ++ic) {
+                bool ov = active && ia < (int)cnt[0] && ic < (int)cnt[1] &&
+                          time_overlap(t0[0][ia], t1[0][ia], t0[1][ic], t1[1][ic]) &&
+                          space_overlap(lo[0][ia], hi[0][ia], lo[1][ic], hi[1][ic]);
+                bool leaves = ov && ids[0][ia] >= N - 1 && ids[1][ic] >= N - 1;
+                int bit = ia * 2 + ic;
+                if (leaves && lk[0][ia] != lk[1][ic])
+                    hit_mask |= 1u << bit;
+                if (ov && !leaves)
+                    push_mask |= 1u << bit;
+            }
+        // one scan packs both counts: pushes in the low 16 bits, hits above
+        uint32_t mine = (uint32_t)__popc(push_mask) | ((uint32_t)__popc(hit_mask) << 16);
+        uint32_t total;
+        uint32_t pre = block_exclusive_scan(mine, wsum, &total);
+        if (threadIdx.x == 0) {
+            qbase = (total & 0xFFFFu) ? atomicAdd(n_out, total & 0xFFFFu) : 0u;
+            rbase = (total >> 16) ? atomicAdd(counter, (unsigned long long)(total >> 16)) : 0ull;
+        }
+        __syncthreads();
+        uint32_t q = qbase + (pre & 0xFFFFu);
+        unsigned long long r = rbase + (pre >> 16);
+        for (int bit = 0; bit < 4; ++bit) {
+            int ia = bit >> 1, ic = bit & 1;
+            if (push_mask & (1u << bit)) {
+                if (q < out_cap)
+                    outq[q] = make_uint2(ids[0][ia], ids[1][ic]);
+                else
+                    atomicOr(flags, 1u);
+                ++q;
+            }
+            if (hit_mask & (1u << bit)) {
+                if (r < capacity) {
+                    uint32_t oa = lk[0][ia], oc = lk[1][ic];
+                    Rec rec;
+                    rec.i = oa < oc ? oa : oc;
+                    rec.j = oa < oc ? oc : oa;
+                    rec.tlo = t0[0][ia] > t0[1][ic] ? t0[0][ia] : t0[1][ic];
+                    rec.thi = t1[0][ia] < t1[1][ic] ? t1[0][ia] : t1[1][ic];
+                    out[r] = rec;
+                }
+                ++r;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_expand(const void *tree, const uint2 *kids, int precision, uint32_t N,
+                         const uint2 *in, const unsigned int *n_in, uint32_t in_cap, uint2 *outq,
+                         unsigned int *n_out, uint32_t out_cap, Rec *out,
+                         unsigned long long capacity, unsigned long long *counter,
+                         unsigned int *flags, hipStream_t s)
+{
+    if (N <= 1)
+        return hipSuccess;
+    unsigned g = 2048;
+    if (precision == CD_FP64)
+        k_expand<CD_FP64><<<g, 256, 0, s>>>(tree, kids, N, in, n_in, in_cap, outq, n_out, out_cap,
+                                            out, capacity, counter, flags);
+    else
+        k_expand<CD_FP32><<<g, 256, 0, s>>>(tree, kids, N, in, n_in, in_cap, outq, n_out, out_cap,
+                                            out, capacity, counter, flags);
+    return hipGetLastError();
+}
+
 // ---- canonical list: sorted records, repeats dropped -----------------------------------------
 
 __global__ void k_unique_flags(const Rec *in, uint32_t count, uint32_t *flags)

@@ -51,62 +51,6 @@ hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, size_t c
     return hipGetLastError();
 }
 
-// ---- wave helpers -----------------------------------------------------------------
-
-__device__ inline uint32_t wave_inclusive_scan(uint32_t v)
-{
-    int lane = threadIdx.x & 63;
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t u = __shfl_up(v, o, 64);
-        if (lane >= o)
-            v += u;
-    }
-    return v;
-}
-
-// Lanes (among `active`) whose 8-bit digit equals this lane's digit.
-__device__ inline uint64_t match_digit(uint32_t d, uint64_t active)
-{
-    uint64_t peers = active;
-#pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
-        uint64_t b = __ballot((d >> bit) & 1u);
-        peers &= ((d >> bit) & 1u) ? b : ~b;
-    }
-    return peers;
-}
-
-__device__ inline uint64_t lanemask_lt()
-{
-    int lane = threadIdx.x & 63;
-    return lane == 0 ? 0ull : (~0ull >> (64 - lane));
-}
-
-// Exclusive scan over all threads of a block (blockDim multiple of 64, <= 1024).
-// `wsum` is LDS scratch of blockDim/64 entries.  Returns the exclusive prefix;
-// *total gets the block sum.
-__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *wsum, uint32_t *total)
-{
-    int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    uint32_t inc = wave_inclusive_scan(v);
-    if (lane == 63)
-        wsum[w] = inc;
-    __syncthreads();
-    if (w == 0) {
-        uint32_t x = lane < nw ? wsum[lane] : 0u;
-        uint32_t xi = wave_inclusive_scan(x);
-        if (lane < nw)
-            wsum[lane] = xi - x;
-        if (lane == nw - 1)
-            wsum[32] = xi;
-    }
-    __syncthreads();
-    uint32_t r = wsum[w] + inc - v;
-    *total = wsum[32];
-    __syncthreads();
-    return r;
-}
-
 // ---- device-wide exclusive scan of uint32 ---------------------------------------
 
 constexpr int kScanThreads = 256;

@@ -227,9 +227,11 @@ hipError_t launch_karras(const uint64_t *keys, uint32_t N, uint2 *kids, Link *li
 // meeting happens inside one workgroup instead.  Leaves are cut into blocks of
 // refit_block(k) = 1024 * 16^k consecutive leaves, level by level; a node
 // belongs to the lowest level whose blocks hold its whole range.
-//   level 0: one workgroup per 1024-leaf chunk, one leaf per thread.  Leaf
-//      boxes, parents, children and arrival counters are staged in LDS, so the
-//      climb touches LDS only; computed node records are written out after.
+//   level 0: one workgroup per 1024-leaf chunk, one leaf per thread.  Parents,
+//      children, arrival counters and computed inner boxes are staged in LDS
+//      (77 KB, two workgroups per CU); a sibling leaf is read back from its
+//      record, written before the barrier and still in L2.  Computed inner
+//      records are written out in one coalesced pass at the end.
 //   level k >= 1: one workgroup per level-k block climbs, in global memory with
 //      workgroup-scope counters, from the nodes queued for it by lower levels.
 // A climb that meets a parent of a higher level queues the node for that level
@@ -317,18 +319,51 @@ __device__ inline void unite(double lo[3], double hi[3], uint32_t &t0, uint32_t 
     t1 = t1 > ot1 ? t1 : ot1;
 }
 
+// Per-workgroup seed staging: lanes append to LDS; a full stage or the end of
+// the kernel flushes it with one global atomic.
+struct SeedStage {
+    uint2 *buf;            // LDS, kSeedStage entries
+    unsigned int *n;       // LDS counter
+    __device__ void push(const SeedSink &sink, uint32_t a, uint32_t b) const
+    {
+        unsigned int k = atomicAdd(n, 1u);
+        if (k < (unsigned)kSeedStage) {
+            buf[k] = make_uint2(a, b);
+        } else {  // stage full: this one goes straight out
+            uint2 one = make_uint2(a, b);
+            sink.put_many(&one, 1, sink.reserve(1));
+        }
+    }
+    // all threads of the block call this after the last push
+    __device__ void flush(const SeedSink &sink, unsigned int *base_lds) const
+    {
+        __syncthreads();
+        uint32_t m = *n < (unsigned)kSeedStage ? *n : (unsigned)kSeedStage;
+        if (threadIdx.x == 0)
+            *base_lds = m ? sink.reserve(m) : 0u;
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < m; k += blockDim.x)
+            if (*base_lds + k < sink.cap)
+                sink.items[*base_lds + k] = buf[k];
+    }
+};
+
 template <int BP, int TP>
 __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
     BoxView b, uint32_t N, const uint32_t *__restrict__ idx, const uint32_t *__restrict__ parent,
     const uint2 *__restrict__ kids, const Link *__restrict__ links, const uint8_t *clev,
-    void *tree, RefitLists L, unsigned int *err)
+    void *tree, RefitLists L, SeedSink seeds, unsigned int *err)
 {
-    __shared__ LBox leafb[kRefitChunk];
     __shared__ LBox innb[kRefitChunk];
     __shared__ uint2 kid[kRefitChunk];
     __shared__ uint32_t par_leaf[kRefitChunk], par_in[kRefitChunk];
     __shared__ unsigned int cnt[kRefitChunk];
+    __shared__ uint2 sbuf[kSeedStage];
+    __shared__ unsigned int sn, sbase;
+    const SeedStage stage{sbuf, &sn};
     const uint32_t t = threadIdx.x;
+    if (t == 0)
+        sn = 0;
     const uint32_t c = xcd_block(blockIdx.x, gridDim.x);
     const uint32_t c0 = c * (uint32_t)kRefitChunk;
     const uint32_t m = N - c0 < (uint32_t)kRefitChunk ? N - c0 : (uint32_t)kRefitChunk;
@@ -354,12 +389,6 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
         t1 = b.t1[src];
         uint32_t leaf = N - 1 + i;
         NodeIO<TP>::put(tree, N, leaf, lo, hi, t0, t1, b.obj[src], links[leaf].esc);
-        for (int d = 0; d < 3; ++d) {
-            leafb[t].lo[d] = lo[d];
-            leafb[t].hi[d] = hi[d];
-        }
-        leafb[t].t0 = t0;
-        leafb[t].t1 = t1;
         par_leaf[t] = parent[leaf];
     }
     if (c0 + t + 1 < N) {  // inner node c0 + t exists
@@ -390,16 +419,30 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
                 break;
             uint2 lr = kid[slot];
             uint32_t sib = lr.x == node ? lr.y : lr.x;
-            const LBox *o = nullptr;
-            if (sib >= N - 1 && sib - (N - 1) - c0 < m)
-                o = &leafb[sib - (N - 1) - c0];
-            else if (sib < N - 1 && sib - c0 < m)
-                o = &innb[sib - c0];
-            if (!o || (lr.x != node && lr.y != node)) {
+            if (lr.x != node && lr.y != node) {
                 bad = true;
                 break;
             }
-            unite(lo, hi, t0, t1, o->lo, o->hi, o->t0, o->t1);
+            double olo[3], ohi[3];
+            uint32_t ot0, ot1;
+            if (sib >= N - 1 && sib - (N - 1) - c0 < m) {
+                // a leaf of this chunk: its record was written before the barrier
+                NodeIO<TP>::get_box(tree, N, sib, olo, ohi, ot0, ot1);
+            } else if (sib < N - 1 && sib - c0 < m) {
+                const LBox &o = innb[sib - c0];
+                for (int d = 0; d < 3; ++d) {
+                    olo[d] = o.lo[d];
+                    ohi[d] = o.hi[d];
+                }
+                ot0 = o.t0;
+                ot1 = o.t1;
+            } else {
+                bad = true;
+                break;
+            }
+            if (time_overlap(t0, t1, ot0, ot1) && space_overlap(lo, hi, olo, ohi))
+                stage.push(seeds, lr.x, lr.y);
+            unite(lo, hi, t0, t1, olo, ohi, ot0, ot1);
             for (int d = 0; d < 3; ++d) {
                 innb[slot].lo[d] = lo[d];
                 innb[slot].hi[d] = hi[d];
@@ -417,6 +460,7 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
         NodeIO<TP>::put(tree, N, p, innb[t].lo, innb[t].hi, innb[t].t0, innb[t].t1, kid[t].x,
                         links[p].esc);
     }
+    stage.flush(seeds, &sbase);
     if (bad)
         atomicOr(err, 2u);
 }
@@ -425,11 +469,17 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
 // for it, in global memory with workgroup-scope arrival counters, through the
 // nodes of level k; a parent of a higher level gets the node queued instead.
 template <int TP>
-__global__ __launch_bounds__(kRefitChunk) void k_refit_level(
+__global__ __launch_bounds__(kRefitLevelThreads) void k_refit_level(
     uint32_t N, uint32_t lev, const uint32_t *__restrict__ parent, const uint2 *__restrict__ kids,
     const Link *__restrict__ links, const uint8_t *clev, void *tree, unsigned int *arrive,
-    RefitLists L, unsigned int *err)
+    RefitLists L, SeedSink seeds, unsigned int *err)
 {
+    __shared__ uint2 sbuf[kSeedStage];
+    __shared__ unsigned int sn, sbase;
+    const SeedStage stage{sbuf, &sn};
+    if (threadIdx.x == 0)
+        sn = 0;
+    __syncthreads();
     uint32_t blk = blockIdx.x;
     uint32_t n = L.count[L.base[lev] + blk];
     n = n < (uint32_t)kRefitListCap ? n : (uint32_t)kRefitListCap;
@@ -472,11 +522,14 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_level(
             double olo[3], ohi[3];
             uint32_t ot0, ot1;
             NodeIO<TP>::get_box(tree, N, sib, olo, ohi, ot0, ot1);
+            if (time_overlap(t0, t1, ot0, ot1) && space_overlap(lo, hi, olo, ohi))
+                stage.push(seeds, lr.x, lr.y);
             unite(lo, hi, t0, t1, olo, ohi, ot0, ot1);
             NodeIO<TP>::put(tree, N, p, lo, hi, t0, t1, lr.x, links[p].esc);
             node = p;
         }
     }
+    stage.flush(seeds, &sbase);
     if (!ok)
         atomicOr(err, 2u);
 }
@@ -506,7 +559,7 @@ hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision,
                         const uint32_t *idx, const uint32_t *parent, const uint2 *kids,
                         const Link *links, const uint8_t *clev, unsigned int *arrive,
                         uint32_t *list_items, uint32_t *list_count, void *tree,
-                        unsigned int *err, hipStream_t s)
+                        const SeedSink &seeds, unsigned int *err, hipStream_t s)
 {
     if (N == 0)
         return hipSuccess;
@@ -526,22 +579,22 @@ hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision,
     uint32_t nchunks = nblk(N, kRefitChunk);
     if (box_precision == CD_FP64 && tree_precision == CD_FP64)
         k_refit_chunks<CD_FP64, CD_FP64><<<nchunks, kRefitChunk, 0, s>>>(
-            b, N, idx, parent, kids, links, clev, tree, L, err);
+            b, N, idx, parent, kids, links, clev, tree, L, seeds, err);
     else if (box_precision == CD_FP64)
         k_refit_chunks<CD_FP64, CD_FP32><<<nchunks, kRefitChunk, 0, s>>>(
-            b, N, idx, parent, kids, links, clev, tree, L, err);
+            b, N, idx, parent, kids, links, clev, tree, L, seeds, err);
     else
         k_refit_chunks<CD_FP32, CD_FP32><<<nchunks, kRefitChunk, 0, s>>>(
-            b, N, idx, parent, kids, links, clev, tree, L, err);
+            b, N, idx, parent, kids, links, clev, tree, L, seeds, err);
     e = hipGetLastError();
     for (uint32_t k = 1; k <= levels && e == hipSuccess; ++k) {
         uint32_t nb = (uint32_t)(((uint64_t)N + (1ull << refit_shift(k)) - 1) >> refit_shift(k));
         if (tree_precision == CD_FP64)
-            k_refit_level<CD_FP64><<<nb, kRefitChunk, 0, s>>>(N, k, parent, kids, links, clev,
-                                                              tree, arrive, L, err);
+            k_refit_level<CD_FP64><<<nb, kRefitLevelThreads, 0, s>>>(N, k, parent, kids, links, clev,
+                                                              tree, arrive, L, seeds, err);
         else
-            k_refit_level<CD_FP32><<<nb, kRefitChunk, 0, s>>>(N, k, parent, kids, links, clev,
-                                                              tree, arrive, L, err);
+            k_refit_level<CD_FP32><<<nb, kRefitLevelThreads, 0, s>>>(N, k, parent, kids, links, clev,
+                                                              tree, arrive, L, seeds, err);
         e = hipGetLastError();
     }
     return e;

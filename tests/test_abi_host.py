@@ -38,8 +38,11 @@ def test_sizes_are_host_only_and_monotone():
     import paper_1901_10475_amd as cd
     L = cd.lib()
     assert L.cd_tree_bytes(0, cd.CD_FP64) == 256
-    assert L.cd_tree_bytes(10, cd.CD_FP64) == 256 + 19 * 64
-    assert L.cd_tree_bytes(10, cd.CD_FP32) == 256 + 19 * 40
+    # header, 2N-1 node records, children of the N-1 inner nodes, and room for
+    # the overlapping sibling pairs the refit records
+    seeds = (10 // 4 + 4096) * 8
+    assert L.cd_tree_bytes(10, cd.CD_FP64) == 256 + 19 * 64 + 9 * 8 + seeds
+    assert L.cd_tree_bytes(10, cd.CD_FP32) == 256 + 19 * 40 + 9 * 8 + seeds
     assert L.cd_build_tree_ws(1000) < L.cd_build_tree_ws(100000)
     assert L.cd_query_pairs_ws(10, 1000) < L.cd_query_pairs_ws(10, 100000)
 

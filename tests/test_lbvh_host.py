@@ -167,3 +167,57 @@ def test_host_walk_on_orbital_boxes():
     # the walk reports each unordered pair exactly once
     assert cnt == len(ref)
     assert np.array_equal(np.unique(out[:cnt], axis=0), ref)
+
+
+def node_pair_pairs(nodes, topo):
+    """The node-pair self-traversal in plain Python over a host-built tree:
+    seeds = overlapping sibling pairs, expanded level by level."""
+    nlo, nhi, nt0, nt1, link, esc = nodes
+    N = topo["N"]
+    left, right = topo["left"], topo["right"]
+
+    def ov(a, c):
+        return (nt0[a] < nt1[c] and nt0[c] < nt1[a] and np.all(nlo[a] <= nhi[c])
+                and np.all(nlo[c] <= nhi[a]))
+    level = [(int(left[p]), int(right[p])) for p in range(N - 1)
+             if ov(int(left[p]), int(right[p]))]
+    recs, levels = [], 0
+    while level:
+        nxt = []
+        for a, c in level:
+            A = [a] if a >= N - 1 else [int(left[a]), int(right[a])]
+            C = [c] if c >= N - 1 else [int(left[c]), int(right[c])]
+            for x in A:
+                for y in C:
+                    if not ov(x, y):
+                        continue
+                    if x >= N - 1 and y >= N - 1:
+                        if link[x] != link[y]:
+                            o1, o2 = sorted((int(link[x]), int(link[y])))
+                            recs.append((o1, o2, max(nt0[x], nt0[y]), min(nt1[x], nt1[y])))
+                    else:
+                        nxt.append((x, y))
+        level, levels = nxt, levels + 1
+    return recs, levels
+
+
+@pytest.mark.parametrize("kind,N,w", [("uniform", 300, 7), ("identical", 65, 1), ("huge", 500, 3),
+                                      ("line", 257, 1), ("uniform", 2, 1), ("uniform", 1, 1)])
+def test_node_pair_traversal_matches_oracle(kind, N, w):
+    lo, hi, t0, t1, obj = catalog.random_boxes(N + 3, N, max(2, N // 3), extent=40, size=6,
+                                               T=30, max_len=8, kind=kind)
+    nodes, topo = build_host_tree(lo, hi, t0, t1, obj, w)
+    recs, _ = node_pair_pairs(nodes, topo) if N > 1 else ([], 0)
+    got = np.unique(np.array(recs, np.uint32).reshape(-1, 4), axis=0)
+    ref = oracle.pairs(oracle.Boxes(lo, hi, t0, t1, obj))
+    assert np.array_equal(got, ref)
+
+
+def test_node_pair_traversal_reports_each_box_pair_once():
+    sc = catalog.scaled(catalog.small_leo(seed=5, n=200, planted=8), horizon_ticks=60_000)
+    b = oracle.boxes(sc.elements, sc.dt_ticks, sc.horizon_ticks, sc.tick_s, sc.threshold_km)
+    nodes, topo = build_host_tree(b.lo, b.hi, b.t0, b.t1, b.obj, sc.dt_ticks)
+    recs, levels = node_pair_pairs(nodes, topo)
+    ref = oracle.pairs(b)
+    assert len(recs) == len(ref) > 0
+    assert np.array_equal(np.unique(np.array(recs, np.uint32), axis=0), ref)
