@@ -38,12 +38,13 @@ def algorithmic_bytes(stage, N, n, P, tree_prec, box_prec, seeds=0):
     table = {
         "boxes": N * box,                                    # boxes written
         "keys": 0,                                           # sampled frame only
-        "sort": N * (6 * fb + 4) + N * 12,                   # boxes + t0 in, keys + index out
+        "sort": N * box + N * 8 + N * node,                  # slab build: boxes in; sorted
+                                                             # keys and leaf records out
         "karras": N * 8 + (N - 1) * (8 + 1) + nodes * (8 + 4),  # keys in; kids, level,
                                                              # links, parents out
-        "refit": N * (box + 4) + nodes * (4 + 8) + (N - 1) * 8 + nodes * node,
-                                                             # boxes, index, parents, links,
-                                                             # kids in; node records out
+        "refit": N * node + nodes * 4 + (N - 1) * (8 + 8) + (N - 1) * node,
+                                                             # leaf records, parents, kids
+                                                             # and links in; inner records out
         "traverse": seeds * (8 + 2 * node) + P * 16,         # seed pairs and their nodes,
                                                              # records out
         "canon": P * 16 * 3,

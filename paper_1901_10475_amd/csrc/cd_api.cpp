@@ -556,15 +556,27 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
     uint32_t max_slab = horizon / w;
     bool seg = boxes->slab_size > 0 && boxes->slab_size <= kSegCap && boxes->slab_ticks == w &&
                N % boxes->slab_size == 0;
+    // FP32 trees keep their link records in the tree itself; FP64 records
+    // carry them inline and take them from the workspace during the refit
+    Link *links = precision == CD_FP32
+                      ? (Link *)((Box32 *)nodes + (2 * (size_t)N - 1))
+                      : tw.links;
+    uint2 *kids = (uint2 *)((char *)tree->mem + tree_kids_offset((uint64_t)N, precision));
+    const uint32_t *leaf_src = tw.idx;  // nullptr once the leaf records exist
     if (seg) {
         uint32_t m = (uint32_t)boxes->slab_size;
         {
             Stage st("keys", s);
             CD_HIP(launch_bounds(bv, boxes->precision, (uint32_t)N, tw.bounds, s));
         }
-        Stage st("sort", s);
-        CD_HIP(launch_segment_sort(bv, boxes->precision, (uint32_t)(N / m), m, (uint32_t)N, w,
-                                   tw.bounds, tw.keys, tw.idx, err, s));
+        {
+            Stage st("sort", s);
+            CD_HIP(launch_slab_build(bv, boxes->precision, precision, (uint32_t)(N / m), m,
+                                     (uint32_t)N, w, tw.bounds, tw.keys, links, nodes, err, s));
+        }
+        leaf_src = nullptr;
+        Stage st("karras", s);
+        CD_HIP(launch_karras(tw.keys, (uint32_t)N, kids, links, tw.parent, tw.clev, false, s));
     } else {
         {
             Stage st("keys", s);
@@ -572,27 +584,21 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
             CD_HIP(launch_keys(bv, boxes->precision, (uint32_t)N, w, max_slab, 0, tw.bounds,
                                nullptr, tw.kva, err, s));
         }
-        Stage st("sort", s);
-        DigitPlan plan;
-        memset(&plan, 0, sizeof plan);
-        for (int sh = 0; sh < 32; sh += 8)
-            plan.shift[plan.npass++] = (uint8_t)sh;
-        int sb = bits_for(max_slab);
-        for (int sh = 0; sh < sb; sh += 8)
-            plan.shift[plan.npass++] = (uint8_t)(32 + sh);
-        void *res = nullptr;
-        CD_HIP(radix_sort16(SORT_KV, tw.kva, tw.kvb, (size_t)N, plan, tw.radix, &res, s));
-        CD_HIP(launch_unpack_kv((const KV *)res, (uint32_t)N, tw.keys, tw.idx, s));
-    }
-    // FP32 trees keep their link records in the tree itself; FP64 records
-    // carry them inline and take them from the workspace during the refit
-    Link *links = precision == CD_FP32
-                      ? (Link *)((Box32 *)nodes + (2 * (size_t)N - 1))
-                      : tw.links;
-    uint2 *kids = (uint2 *)((char *)tree->mem + tree_kids_offset((uint64_t)N, precision));
-    {
+        {
+            Stage st("sort", s);
+            DigitPlan plan;
+            memset(&plan, 0, sizeof plan);
+            for (int sh = 0; sh < 32; sh += 8)
+                plan.shift[plan.npass++] = (uint8_t)sh;
+            int sb = bits_for(max_slab);
+            for (int sh = 0; sh < sb; sh += 8)
+                plan.shift[plan.npass++] = (uint8_t)(32 + sh);
+            void *res = nullptr;
+            CD_HIP(radix_sort16(SORT_KV, tw.kva, tw.kvb, (size_t)N, plan, tw.radix, &res, s));
+            CD_HIP(launch_unpack_kv((const KV *)res, (uint32_t)N, tw.keys, tw.idx, s));
+        }
         Stage st("karras", s);
-        CD_HIP(launch_karras(tw.keys, (uint32_t)N, kids, links, tw.parent, tw.clev, s));
+        CD_HIP(launch_karras(tw.keys, (uint32_t)N, kids, links, tw.parent, tw.clev, true, s));
     }
     {
         Stage st("refit", s);
@@ -600,7 +606,7 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
         sink.items = (uint2 *)((char *)tree->mem + tree_seeds_offset((uint64_t)N, precision));
         sink.cap = (uint32_t)seed_cap((uint64_t)N);
         sink.hdr = (TreeHeader *)tree->mem;
-        CD_HIP(launch_refit(bv, boxes->precision, precision, (uint32_t)N, tw.idx, tw.parent,
+        CD_HIP(launch_refit(bv, boxes->precision, precision, (uint32_t)N, leaf_src, tw.parent,
                             kids, links, tw.clev, tw.arrive, tw.list_items, tw.list_count,
                             nodes, sink, err, s));
     }

@@ -19,16 +19,17 @@ int hc_karras(const uint64_t *keys, int64_t N, uint32_t *left, uint32_t *right, 
 {
     if (N < 1)
         return 0;
+    KeyArray K{keys};
     for (int64_t i = 0; i + 1 < N; ++i) {
-        KarrasNode nd = karras_node(keys, N, i);
+        KarrasNode nd = karras_node(K, N, i);
         left[i] = nd.left;
         right[i] = nd.right;
         first[i] = nd.first;
         last[i] = nd.last;
-        esc_inner[i] = karras_escape(keys, N, nd.last);
+        esc_inner[i] = karras_escape(K, N, nd.last);
     }
     for (int64_t i = 0; i < N; ++i)
-        esc_leaf[i] = karras_escape(keys, N, i);
+        esc_leaf[i] = karras_escape(K, N, i);
     return 0;
 }
 

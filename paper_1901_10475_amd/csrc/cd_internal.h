@@ -133,6 +133,90 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *wsum, uint
     return r;
 }
 
+// ---- node records ----------------------------------------------------------------
+
+template <int TP>
+struct NodeIO;
+
+template <>
+struct NodeIO<CD_FP64> {
+    __device__ static void put(void *tree, uint32_t N, uint32_t id, const double lo[3],
+                               const double hi[3], uint32_t t0, uint32_t t1, uint32_t link,
+                               uint32_t esc)
+    {
+        Node64 n;
+        for (int d = 0; d < 3; ++d) {
+            n.lo[d] = lo[d];
+            n.hi[d] = hi[d];
+        }
+        n.t0 = t0;
+        n.t1 = t1;
+        n.link = link;
+        n.esc = esc;
+        ((Node64 *)tree)[id] = n;
+    }
+    __device__ static void get_box(const void *tree, uint32_t N, uint32_t id, double lo[3],
+                                   double hi[3], uint32_t &t0, uint32_t &t1)
+    {
+        const Node64 *n = (const Node64 *)tree + id;
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = n->lo[d];
+            hi[d] = n->hi[d];
+        }
+        t0 = n->t0;
+        t1 = n->t1;
+    }
+};
+
+template <>
+struct NodeIO<CD_FP32> {
+    // outward rounding; inner unions of floats are exact in float
+    __device__ static void put(void *tree, uint32_t N, uint32_t id, const double lo[3],
+                               const double hi[3], uint32_t t0, uint32_t t1, uint32_t link,
+                               uint32_t esc)
+    {
+        Box32 b;
+        for (int d = 0; d < 3; ++d) {
+            b.lo[d] = __double2float_rd(lo[d]);
+            b.hi[d] = __double2float_ru(hi[d]);
+        }
+        b.t0 = t0;
+        b.t1 = t1;
+        ((Box32 *)tree)[id] = b;
+        Link l;
+        l.link = link;
+        l.esc = esc;
+        ((Link *)((Box32 *)tree + (2 * (size_t)N - 1)))[id] = l;
+    }
+    __device__ static void get_box(const void *tree, uint32_t N, uint32_t id, double lo[3],
+                                   double hi[3], uint32_t &t0, uint32_t &t1)
+    {
+        const Box32 *n = (const Box32 *)tree + id;
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = n->lo[d];
+            hi[d] = n->hi[d];
+        }
+        t0 = n->t0;
+        t1 = n->t1;
+    }
+};
+
+struct LBox {
+    double lo[3], hi[3];
+    uint32_t t0, t1;
+};
+
+__device__ inline void unite(double lo[3], double hi[3], uint32_t &t0, uint32_t &t1,
+                             const double olo[3], const double ohi[3], uint32_t ot0, uint32_t ot1)
+{
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = fmin(lo[d], olo[d]);
+        hi[d] = fmax(hi[d], ohi[d]);
+    }
+    t0 = t0 < ot0 ? t0 : ot0;
+    t1 = t1 > ot1 ? t1 : ot1;
+}
+
 // Order-preserving map from double to uint64 (for atomic min/max).
 __host__ __device__ inline uint64_t ordered_bits(double x)
 {
@@ -190,10 +274,16 @@ hipError_t radix_sort16(SortKind kind, void *a, void *b, size_t count, const Dig
 constexpr int kSegThreads = 1024;
 constexpr int kSegItems = 17;
 constexpr int64_t kSegCap = (int64_t)kSegThreads * kSegItems;
-hipError_t launch_segment_sort(const BoxView &b, int precision, uint32_t nslabs,
-                               uint32_t slab_size, uint32_t N, uint32_t slab_ticks,
-                               const unsigned long long *bounds, uint64_t *keys_out,
-                               uint32_t *idx_out, unsigned int *err, hipStream_t s);
+// Fixed-step slabs: one workgroup per slab sorts the slab's Morton codes in
+// LDS, writes the sorted 64-bit keys, and writes the slab's leaf records in
+// sorted order while the slab's boxes are still cached.  A leaf's skip link
+// needs only the keys next to it: those of this slab come from LDS, those of
+// other slabs differ in their slab bits, which alone decide the comparison.
+hipError_t launch_slab_build(const BoxView &b, int box_precision, int tree_precision,
+                             uint32_t nslabs, uint32_t slab_size, uint32_t N,
+                             uint32_t slab_ticks, const unsigned long long *bounds,
+                             uint64_t *keys_out, Link *links, void *tree, unsigned int *err,
+                             hipStream_t s);
 
 // tree
 hipError_t launch_bounds(const BoxView &b, int precision, uint32_t N,
@@ -279,8 +369,11 @@ struct RefitLists {
 };
 uint32_t refit_levels(uint32_t N);
 size_t refit_list_slots(uint32_t N, uint32_t *base);
+// leaf_links: also write the leaves' link records (skipped when the slab
+// build wrote them).
 hipError_t launch_karras(const uint64_t *keys, uint32_t N, uint2 *kids, Link *links,
-                         uint32_t *parent, uint8_t *clev, hipStream_t s);
+                         uint32_t *parent, uint8_t *clev, bool leaf_links, hipStream_t s);
+// idx == nullptr: the leaf records are already written (slab build).
 hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision, uint32_t N,
                         const uint32_t *idx, const uint32_t *parent, const uint2 *kids,
                         const Link *links, const uint8_t *clev, unsigned int *arrive,

@@ -42,18 +42,25 @@ __host__ __device__ inline uint32_t morton30(double x, double y, double z, const
     return (spread3_10(q[0]) << 2) | (spread3_10(q[1]) << 1) | spread3_10(q[2]);
 }
 
-// ---- Karras hierarchy over sorted keys ----------------------------------------
+// ---- Karras hierarchy over sorted keys ----------------------------------------------
 //
+// Keys are read through an accessor K (K(i) = key of sorted leaf i), so the
+// same code runs over a key array in memory or over keys held in LDS.
 // delta(i, j): length of the common prefix of keys i and j, with the index
 // appended as a tie-break so that equal keys still give a strict order;
 // -1 outside [0, N).
 
-__host__ __device__ inline int karras_delta(const uint64_t *keys, int64_t N, int64_t i,
-                                            int64_t j)
+struct KeyArray {
+    const uint64_t *keys;
+    __host__ __device__ uint64_t operator()(int64_t i) const { return keys[i]; }
+};
+
+template <class K>
+__host__ __device__ inline int karras_delta(const K &key, int64_t N, int64_t i, int64_t j)
 {
     if (j < 0 || j >= N)
         return -1;
-    uint64_t a = keys[i], b = keys[j];
+    uint64_t a = key(i), b = key(j);
     if (a != b)
         return __builtin_clzll(a ^ b);
     uint64_t x = (uint64_t)i ^ (uint64_t)j;
@@ -61,9 +68,10 @@ __host__ __device__ inline int karras_delta(const uint64_t *keys, int64_t N, int
 }
 
 // Direction of internal node i: +1 if its leaf range extends right of i.
-__host__ __device__ inline int karras_dir(const uint64_t *keys, int64_t N, int64_t i)
+template <class K>
+__host__ __device__ inline int karras_dir(const K &key, int64_t N, int64_t i)
 {
-    return karras_delta(keys, N, i, i + 1) >= karras_delta(keys, N, i, i - 1) ? 1 : -1;
+    return karras_delta(key, N, i, i + 1) >= karras_delta(key, N, i, i - 1) ? 1 : -1;
 }
 
 // Node id of the right sibling of the lowest left-child ancestor of a node
@@ -71,12 +79,13 @@ __host__ __device__ inline int karras_dir(const uint64_t *keys, int64_t N, int64
 // node's subtree is skipped.  It starts at leaf r + 1 and is a right child, so
 // it is internal node r + 1 when that node's range starts at r + 1, and leaf
 // r + 1 otherwise.
-__host__ __device__ inline uint32_t karras_escape(const uint64_t *keys, int64_t N, int64_t r)
+template <class K>
+__host__ __device__ inline uint32_t karras_escape(const K &key, int64_t N, int64_t r)
 {
     if (r >= N - 1)
         return kEnd;
     int64_t s = r + 1;
-    if (s <= N - 2 && karras_dir(keys, N, s) > 0)
+    if (s <= N - 2 && karras_dir(key, N, s) > 0)
         return (uint32_t)s;
     return (uint32_t)(N - 1 + s);
 }
@@ -89,24 +98,25 @@ struct KarrasNode {
 // Internal node i of the Karras (2012) radix tree: find the range by an
 // exponential then a binary search on delta, then the split by a binary
 // search.  Requires N >= 2 and 0 <= i <= N - 2.
-__host__ __device__ inline KarrasNode karras_node(const uint64_t *keys, int64_t N, int64_t i)
+template <class K>
+__host__ __device__ inline KarrasNode karras_node(const K &key, int64_t N, int64_t i)
 {
-    int d = karras_dir(keys, N, i);
-    int dmin = karras_delta(keys, N, i, i - d);
+    int d = karras_dir(key, N, i);
+    int dmin = karras_delta(key, N, i, i - d);
     int64_t lmax = 2;
-    while (karras_delta(keys, N, i, i + lmax * d) > dmin)
+    while (karras_delta(key, N, i, i + lmax * d) > dmin)
         lmax *= 2;
     int64_t l = 0;
     for (int64_t t = lmax / 2; t >= 1; t /= 2)
-        if (karras_delta(keys, N, i, i + (l + t) * d) > dmin)
+        if (karras_delta(key, N, i, i + (l + t) * d) > dmin)
             l += t;
     int64_t j = i + l * d;
-    int dnode = karras_delta(keys, N, i, j);
+    int dnode = karras_delta(key, N, i, j);
     int64_t s = 0;
     int64_t t = l;
     do {
         t = (t + 1) >> 1;
-        if (karras_delta(keys, N, i, i + (s + t) * d) > dnode)
+        if (karras_delta(key, N, i, i + (s + t) * d) > dnode)
             s += t;
     } while (t > 1);
     int64_t gamma = i + s * d + (d < 0 ? -1 : 0);

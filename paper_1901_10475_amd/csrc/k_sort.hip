@@ -278,13 +278,25 @@ hipError_t radix_sort16(SortKind kind, void *a, void *b, size_t count, const Dig
 
 constexpr int kSegWaves = kSegThreads / 64;
 
-template <int PREC>
-__global__ __launch_bounds__(kSegThreads) void k_segment_sort(BoxView b, uint32_t slab_size,
-                                                             uint32_t N, uint32_t slab_ticks,
-                                                             const unsigned long long *bounds,
-                                                             uint64_t *__restrict__ keys_out,
-                                                             uint32_t *__restrict__ idx_out,
-                                                             unsigned int *err)
+// Keys of the global sorted order seen from one slab's workgroup: leaves of
+// this slab from LDS, leaves of other slabs by their slab bits only.
+struct SlabKeys {
+    const uint32_t *lds;
+    uint64_t base, m, hi;  // hi = this slab's index << 32
+    __device__ uint64_t operator()(int64_t gi) const
+    {
+        uint64_t g = (uint64_t)gi;
+        if (g - base < m)
+            return hi | lds[g - base];
+        return (g / m) << 32;  // other slabs: only their slab bits matter
+    }
+};
+
+template <int PREC, int TP>
+__global__ __launch_bounds__(kSegThreads) void k_slab_build(
+    BoxView b, uint32_t slab_size, uint32_t N, uint32_t slab_ticks,
+    const unsigned long long *bounds, uint64_t *__restrict__ keys_out, Link *__restrict__ links,
+    void *tree, unsigned int *err)
 {
     __shared__ uint32_t xch[kSegCap];
     __shared__ uint32_t cnt[256 * kSegWaves];
@@ -381,31 +393,53 @@ __global__ __launch_bounds__(kSegThreads) void k_segment_sort(BoxView b, uint32_
                 val[j] = xch[li0 + j * 64];
         __syncthreads();
     }
+    // Leaf records.  Reading boxes by sorted position would gather 4-8 byte
+    // words from all over the slab; instead each box is read in source order
+    // (coalesced) and its whole record is written to its sorted slot.  LDS
+    // holds the sorted codes (for the skip links) and the inverse permutation.
+    __shared__ uint32_t vsrc[kSegCap];  // source box -> sorted position
 #pragma unroll
     for (int j = 0; j < kSegItems; ++j) {
-        uint32_t li = li0 + j * 64;
-        if (li < m) {
-            keys_out[base + li] = (slab << 32) | key[j];
-            idx_out[base + li] = (uint32_t)base + val[j];
+        uint32_t p = li0 + j * 64;
+        if (p < m) {
+            xch[p] = key[j];
+            vsrc[val[j]] = p;
+            keys_out[base + p] = (slab << 32) | key[j];
         }
+    }
+    __syncthreads();
+    const SlabKeys K{xch, base, slab_size, slab << 32};
+#pragma unroll 1
+    for (uint32_t li = threadIdx.x; li < m; li += kSegThreads) {
+        uint32_t p = vsrc[li];
+        uint32_t esc = karras_escape(K, N, (int64_t)(base + p));
+        uint64_t src = base + li;
+        double lo[3], hi[3];
+        load_box<PREC>(b, src, lo, hi);
+        NodeIO<TP>::put(tree, N, (uint32_t)(N - 1 + base + p), lo, hi, b.t0[src], b.t1[src],
+                        b.obj[src], esc);
     }
 }
 
-hipError_t launch_segment_sort(const BoxView &b, int precision, uint32_t nslabs,
-                               uint32_t slab_size, uint32_t N, uint32_t slab_ticks,
-                               const unsigned long long *bounds, uint64_t *keys_out,
-                               uint32_t *idx_out, unsigned int *err, hipStream_t s)
+hipError_t launch_slab_build(const BoxView &b, int box_precision, int tree_precision,
+                             uint32_t nslabs, uint32_t slab_size, uint32_t N,
+                             uint32_t slab_ticks, const unsigned long long *bounds,
+                             uint64_t *keys_out, Link *links, void *tree, unsigned int *err,
+                             hipStream_t s)
 {
     if (nslabs == 0 || N == 0)
         return hipSuccess;
     if ((int64_t)slab_size > kSegCap)
         return hipErrorInvalidValue;
-    if (precision == CD_FP64)
-        k_segment_sort<CD_FP64><<<nslabs, kSegThreads, 0, s>>>(b, slab_size, N, slab_ticks,
-                                                               bounds, keys_out, idx_out, err);
+    if (box_precision == CD_FP64 && tree_precision == CD_FP64)
+        k_slab_build<CD_FP64, CD_FP64><<<nslabs, kSegThreads, 0, s>>>(
+            b, slab_size, N, slab_ticks, bounds, keys_out, links, tree, err);
+    else if (box_precision == CD_FP64)
+        k_slab_build<CD_FP64, CD_FP32><<<nslabs, kSegThreads, 0, s>>>(
+            b, slab_size, N, slab_ticks, bounds, keys_out, links, tree, err);
     else
-        k_segment_sort<CD_FP32><<<nslabs, kSegThreads, 0, s>>>(b, slab_size, N, slab_ticks,
-                                                               bounds, keys_out, idx_out, err);
+        k_slab_build<CD_FP32, CD_FP32><<<nslabs, kSegThreads, 0, s>>>(
+            b, slab_size, N, slab_ticks, bounds, keys_out, links, tree, err);
     return hipGetLastError();
 }
 

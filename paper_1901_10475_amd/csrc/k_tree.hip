@@ -163,12 +163,13 @@ hipError_t launch_unpack_kv(const KV *kv, uint32_t N, uint64_t *keys, uint32_t *
 // kCross set when clev[i] > 0.
 
 __global__ void k_karras(const uint64_t *__restrict__ keys, uint32_t N, uint2 *kids, Link *links,
-                         uint32_t *parent, uint8_t *clev)
+                         uint32_t *parent, uint8_t *clev, bool leaf_links)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i + 1 >= N)
         return;
-    KarrasNode nd = karras_node(keys, N, i);
+    KeyArray K{keys};
+    KarrasNode nd = karras_node(K, N, i);
     uint32_t lev = 0;
     while ((uint64_t)(nd.first >> refit_shift(lev)) != (uint64_t)(nd.last >> refit_shift(lev)))
         ++lev;
@@ -181,11 +182,13 @@ __global__ void k_karras(const uint64_t *__restrict__ keys, uint32_t N, uint2 *k
     kids[i] = make_uint2(nd.left, nd.right);
     Link li;
     li.link = nd.left;
-    li.esc = karras_escape(keys, N, nd.last);
+    li.esc = karras_escape(K, N, nd.last);
     links[i] = li;
+    if (!leaf_links)
+        return;
     Link lf;
     lf.link = 0;
-    lf.esc = karras_escape(keys, N, i);
+    lf.esc = karras_escape(K, N, i);
     links[N - 1 + i] = lf;
     if (i == N - 2) {
         Link ll;
@@ -205,7 +208,7 @@ __global__ void k_single_leaf(Link *links, uint32_t *parent)
 }
 
 hipError_t launch_karras(const uint64_t *keys, uint32_t N, uint2 *kids, Link *links,
-                         uint32_t *parent, uint8_t *clev, hipStream_t s)
+                         uint32_t *parent, uint8_t *clev, bool leaf_links, hipStream_t s)
 {
     if (N == 0)
         return hipSuccess;
@@ -213,7 +216,7 @@ hipError_t launch_karras(const uint64_t *keys, uint32_t N, uint2 *kids, Link *li
         k_single_leaf<<<1, 1, 0, s>>>(links, parent);
         return hipGetLastError();
     }
-    k_karras<<<nblk(N - 1, 256), 256, 0, s>>>(keys, N, kids, links, parent, clev);
+    k_karras<<<nblk(N - 1, 256), 256, 0, s>>>(keys, N, kids, links, parent, clev, leaf_links);
     return hipGetLastError();
 }
 
@@ -236,88 +239,6 @@ hipError_t launch_karras(const uint64_t *keys, uint32_t N, uint2 *kids, Link *li
 //      workgroup-scope counters, from the nodes queued for it by lower levels.
 // A climb that meets a parent of a higher level queues the node for that level
 // and block.  Kernel boundaries order each level's writes before the next.
-
-template <int TP>
-struct NodeIO;
-
-template <>
-struct NodeIO<CD_FP64> {
-    __device__ static void put(void *tree, uint32_t N, uint32_t id, const double lo[3],
-                               const double hi[3], uint32_t t0, uint32_t t1, uint32_t link,
-                               uint32_t esc)
-    {
-        Node64 n;
-        for (int d = 0; d < 3; ++d) {
-            n.lo[d] = lo[d];
-            n.hi[d] = hi[d];
-        }
-        n.t0 = t0;
-        n.t1 = t1;
-        n.link = link;
-        n.esc = esc;
-        ((Node64 *)tree)[id] = n;
-    }
-    __device__ static void get_box(const void *tree, uint32_t N, uint32_t id, double lo[3],
-                                   double hi[3], uint32_t &t0, uint32_t &t1)
-    {
-        const Node64 *n = (const Node64 *)tree + id;
-        for (int d = 0; d < 3; ++d) {
-            lo[d] = n->lo[d];
-            hi[d] = n->hi[d];
-        }
-        t0 = n->t0;
-        t1 = n->t1;
-    }
-};
-
-template <>
-struct NodeIO<CD_FP32> {
-    // outward rounding; inner unions of floats are exact in float
-    __device__ static void put(void *tree, uint32_t N, uint32_t id, const double lo[3],
-                               const double hi[3], uint32_t t0, uint32_t t1, uint32_t link,
-                               uint32_t esc)
-    {
-        Box32 b;
-        for (int d = 0; d < 3; ++d) {
-            b.lo[d] = __double2float_rd(lo[d]);
-            b.hi[d] = __double2float_ru(hi[d]);
-        }
-        b.t0 = t0;
-        b.t1 = t1;
-        ((Box32 *)tree)[id] = b;
-        Link l;
-        l.link = link;
-        l.esc = esc;
-        ((Link *)((Box32 *)tree + (2 * (size_t)N - 1)))[id] = l;
-    }
-    __device__ static void get_box(const void *tree, uint32_t N, uint32_t id, double lo[3],
-                                   double hi[3], uint32_t &t0, uint32_t &t1)
-    {
-        const Box32 *n = (const Box32 *)tree + id;
-        for (int d = 0; d < 3; ++d) {
-            lo[d] = n->lo[d];
-            hi[d] = n->hi[d];
-        }
-        t0 = n->t0;
-        t1 = n->t1;
-    }
-};
-
-struct LBox {
-    double lo[3], hi[3];
-    uint32_t t0, t1;
-};
-
-__device__ inline void unite(double lo[3], double hi[3], uint32_t &t0, uint32_t &t1,
-                             const double olo[3], const double ohi[3], uint32_t ot0, uint32_t ot1)
-{
-    for (int d = 0; d < 3; ++d) {
-        lo[d] = fmin(lo[d], olo[d]);
-        hi[d] = fmax(hi[d], ohi[d]);
-    }
-    t0 = t0 < ot0 ? t0 : ot0;
-    t1 = t1 > ot1 ? t1 : ot1;
-}
 
 // Per-workgroup seed staging: lanes append to LDS; a full stage or the end of
 // the kernel flushes it with one global atomic.
@@ -370,7 +291,7 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
     double lo[3], hi[3];
     uint32_t t0 = 0, t1 = 0;
     bool bad = false;
-    if (t < m) {
+    if (t < m && idx) {
         uint32_t i = c0 + t;
         uint32_t src = idx[i];
         if (src >= N) {
@@ -389,6 +310,11 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
         t1 = b.t1[src];
         uint32_t leaf = N - 1 + i;
         NodeIO<TP>::put(tree, N, leaf, lo, hi, t0, t1, b.obj[src], links[leaf].esc);
+        par_leaf[t] = parent[leaf];
+    } else if (t < m) {
+        // leaf records already written in sorted order by the slab build
+        uint32_t leaf = N - 1 + c0 + t;
+        NodeIO<TP>::get_box(tree, N, leaf, lo, hi, t0, t1);
         par_leaf[t] = parent[leaf];
     }
     if (c0 + t + 1 < N) {  // inner node c0 + t exists
