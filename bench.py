@@ -27,6 +27,36 @@ sys.path.insert(0, ROOT)
 METRIC = "ms per n-to-n query and box-pair tests/s at n=16848, 1h horizon; HBM GB/s vs peak"
 HBM_PEAK_GBS = 8000.0
 
+# Measured HBM traffic per launch (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, KiB
+# per dispatch, one counter per pass), scaled by what the same counters read for
+# a 1 GiB device copy (FETCH 524308.56 KiB, WRITE 1048576 KiB).  Valid only for
+# the kernel source it was taken on: reported as null once that file changes.
+# Summary and commands: profiles/tracked16848_1h_fp64.md
+COPY_FETCH_KIB, COPY_WRITE_KIB = 524308.5625, 1048576.0
+TRAFFIC = {
+    ("sort", "fp64"): {"fetch_kib": 3621587.0, "write_kib": 5090350.0,
+                       "source": "paper_1901_10475_amd/csrc/k_sort.hip",
+                       "sha1": "6ca6284c7b18e59d6201e0b9a212d8c1bba54631"},
+    ("refit", "fp64"): {"fetch_kib": 2704670.0 + 300841.0 * 4, "write_kib": 3774597.0 + 93490 * 4,
+                        "source": "paper_1901_10475_amd/csrc/k_tree.hip",
+                        "sha1": "924db231a0b1ebdbfbb178721fe55c525f2abf65"},
+}
+
+
+def measured_traffic(stage, precision):
+    import hashlib
+    t = TRAFFIC.get((stage, precision))
+    if not t:
+        return None
+    try:
+        sha = hashlib.sha1(open(os.path.join(ROOT, t["source"]), "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if sha != t["sha1"]:
+        return None
+    return int(t["fetch_kib"] * 1024 * (1048576.0 / COPY_FETCH_KIB)
+               + t["write_kib"] * 1024 * (1048576.0 / COPY_WRITE_KIB))
+
 
 def algorithmic_bytes(stage, N, n, P, tree_prec, box_prec, seeds=0):
     """Compulsory HBM bytes of one launch of a stage: every input read once,
@@ -147,7 +177,7 @@ def main():
     achieved = nbytes / (mean_ms / 1000.0) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "bytes_per_launch": int(nbytes),
+                "traffic": measured_traffic(dom, args.precision), "bytes_per_launch": int(nbytes),
                 "mean_ms": round(mean_ms, 4)}
 
     out = {"metric": METRIC, "value": value, "unit": "box-pair tests/s", "n_gpus": 1,
