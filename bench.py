@@ -34,18 +34,18 @@ HBM_PEAK_GBS = 8000.0
 # Summary and commands: profiles/tracked16848_1h_fp64.md
 COPY_FETCH_KIB, COPY_WRITE_KIB = 524308.5625, 1048576.0
 TRAFFIC = {
-    ("sort", "fp64"): {"fetch_kib": 3621587.0, "write_kib": 5090350.0,
+    ("sort", "fp64", "fixed"): {"fetch_kib": 3621587.0, "write_kib": 5090350.0,
                        "source": "paper_1901_10475_amd/csrc/k_sort.hip",
                        "sha1": "6ca6284c7b18e59d6201e0b9a212d8c1bba54631"},
-    ("refit", "fp64"): {"fetch_kib": 2704670.0 + 300841.0 * 4, "write_kib": 3774597.0 + 93490 * 4,
+    ("refit", "fp64", "fixed"): {"fetch_kib": 2704670.0 + 300841.0 * 4, "write_kib": 3774597.0 + 93490 * 4,
                         "source": "paper_1901_10475_amd/csrc/k_tree.hip",
                         "sha1": "924db231a0b1ebdbfbb178721fe55c525f2abf65"},
 }
 
 
-def measured_traffic(stage, precision):
+def measured_traffic(stage, precision, dt_mode):
     import hashlib
-    t = TRAFFIC.get((stage, precision))
+    t = TRAFFIC.get((stage, precision, dt_mode))
     if not t:
         return None
     try:
@@ -82,6 +82,26 @@ def algorithmic_bytes(stage, N, n, P, tree_prec, box_prec, seeds=0):
     return table.get(stage)
 
 
+def time_overlap_pairs(dt, T):
+    """Brute-force-equivalent test count for per-object steps: pairs of boxes of
+    different objects whose half-open tags overlap.  Each object's tags tile
+    [0, T + 1), so for objects i, j the overlapping box pairs are the pieces of
+    the merged tiling: K_i + K_j - 1 - (interior boundaries they share), and
+    the shared boundaries are the multiples of lcm(dt_i, dt_j) in [1, T - 1]."""
+    import numpy as np
+    n = len(dt)
+    d = dt.astype(np.int64)
+    K = np.ones(n, np.int64) if T == 0 else -(-T // d)
+    total = (n - 1) * int(K.sum()) - n * (n - 1) // 2
+    vals, cnt = np.unique(d, return_counts=True)
+    for a in range(len(vals)):
+        for b in range(a, len(vals)):
+            m = (T - 1) // int(np.lcm(vals[a], vals[b])) if T > 0 else 0
+            pairs = cnt[a] * (cnt[a] - 1) // 2 if a == b else cnt[a] * cnt[b]
+            total -= int(pairs) * int(m)
+    return total
+
+
 def cpu_baseline(sc, seconds):
     """The CPU oracle on the first two steps of the hour (every object, t in
     [0, 2 s)): FP64 boxes, then literal all-pairs over those 2n boxes; repeated
@@ -110,7 +130,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+                    help="tree precision (boxes stay FP64 unless --boxes fp32)")
+    ap.add_argument("--boxes", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--dt", choices=["fixed", "heuristic"], default="fixed",
+                    help="fixed 1 s steps, or per-object steps bounding each box's motion "
+                         "to 5 km (computed inside the timed step)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -136,12 +161,14 @@ def main():
         del src, dst
     sc = catalog.tracked_hour()
     prec = cd.CD_FP64 if args.precision == "fp64" else cd.CD_FP32
-    box_prec = cd.CD_FP64
+    box_prec = cd.CD_FP64 if args.boxes == "fp64" else cd.CD_FP32
     el = cd.soa(sc.elements)
     p = cd.params_struct(sc.tick_s, sc.mu, sc.threshold_km, sc.horizon_ticks, sc.dt_ticks)
-    print(f"[bench] workload {sc.name}: n={sc.n} T={sc.horizon_ticks} ticks dt={sc.dt_ticks}",
+    heur = 5.0 if args.dt == "heuristic" else None
+    workload = sc.name if heur is None else sc.name.replace("dt1s", "dt_heuristic5km")
+    print(f"[bench] workload {workload}: n={sc.n} T={sc.horizon_ticks} ticks",
           file=sys.stderr, flush=True)
-    bp = cd.BroadPhase(sc.n, p, None, box_prec, prec)
+    bp = cd.BroadPhase(sc.n, p, None, box_prec, prec, dt_heuristic_km=heur, el_soa=el)
     N = bp.count
     for w in range(args.warmup):
         pairs = bp.run(el)
@@ -164,8 +191,11 @@ def main():
     stages = cd.cd_profile_read(reset=True)
     P = int(len(pairs))
     ms_step = wall * 1000.0 / args.steps
-    K = N // sc.n
-    tests = K * sc.n * (sc.n - 1) // 2
+    if args.dt == "fixed":
+        K = N // sc.n
+        tests = K * sc.n * (sc.n - 1) // 2
+    else:
+        tests = time_overlap_pairs(bp.dt.cpu().numpy().view(np.uint32), sc.horizon_ticks)
     value = tests / (ms_step / 1000.0)
     print(f"[bench] {args.steps} steps: {ms_step:.3f} ms/query, {P} pairs, stages "
           + ", ".join(f"{k}={v[0] / v[1]:.3f}ms" for k, v in stages.items()),
@@ -177,7 +207,7 @@ def main():
     achieved = nbytes / (mean_ms / 1000.0) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(dom, args.precision), "bytes_per_launch": int(nbytes),
+                "traffic": measured_traffic(dom, args.precision, args.dt), "bytes_per_launch": int(nbytes),
                 "mean_ms": round(mean_ms, 4)}
 
     out = {"metric": METRIC, "value": value, "unit": "box-pair tests/s", "n_gpus": 1,
@@ -186,13 +216,16 @@ def main():
            "dtype": "f64" if prec == cd.CD_FP64 else "f64 boxes, f32 tree",
            "data": "synthetic (seeded tracked-population catalog; the paper's TLE catalog is "
                    "not available)",
-           "config": {"workload": sc.name, "n": sc.n, "horizon_s": sc.horizon_ticks * sc.tick_s,
-                      "dt_s": sc.dt_ticks * sc.tick_s, "boxes": N, "threshold_km": sc.threshold_km,
-                      "tree_precision": args.precision, "brute_force_tests": tests},
+           "config": {"workload": workload,
+                      "n": sc.n, "horizon_s": sc.horizon_ticks * sc.tick_s,
+                      "dt_s": sc.dt_ticks * sc.tick_s if args.dt == "fixed" else "per-object",
+                      "boxes": N, "threshold_km": sc.threshold_km,
+                      "box_precision": args.boxes, "tree_precision": args.precision,
+                      "brute_force_tests": tests},
            "pairs": P,
            "stages_ms": {k: round(v[0] / v[1], 4) for k, v in stages.items()},
            "roofline": roofline}
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.dt == "fixed":
         print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -287,7 +287,14 @@ class BroadPhase:
     """
 
     def __init__(self, n, params, dt_ticks=None, box_precision=CD_FP64,
-                 tree_precision=CD_FP64, capacity=None, slab_ticks=0, device="cuda"):
+                 tree_precision=CD_FP64, capacity=None, slab_ticks=0, device="cuda",
+                 dt_heuristic_km=None, el_soa=None):
+        """dt_heuristic_km: per-object steps from cd_dt_heuristic (recomputed by
+        every build from the elements; el_soa is needed here to size buffers)."""
+        self.dt_heuristic_km = dt_heuristic_km
+        if dt_heuristic_km is not None:
+            dt_ticks = torch.empty(int(n), dtype=torch.int32, device=device)
+            cd_dt_heuristic(el_soa, params, dt_heuristic_km, dt_ticks)
         self.n, self.params, self.dt = int(n), params, dt_ticks
         self.device = device
         self.count = cd_box_count(dt_ticks, n, params, device)
@@ -305,6 +312,8 @@ class BroadPhase:
         self.ws_query = _bytes(lib().cd_query_pairs_ws(self.count, self.capacity), self.device)
 
     def build(self, el_soa):
+        if self.dt_heuristic_km is not None:
+            cd_dt_heuristic(el_soa, self.params, self.dt_heuristic_km, self.dt)
         cd_build_boxes(el_soa, self.dt, self.params, self.boxes, self.ws_boxes)
         cd_build_tree(self.boxes, self.tree_precision, self.tree, self.ws_tree, self.slab_ticks)
 

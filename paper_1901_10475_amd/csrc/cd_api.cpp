@@ -97,7 +97,6 @@ constexpr int64_t kMaxBoxes = (1ll << 30) - 1;  // node ids of 2N - 1 nodes belo
 constexpr size_t kTreeHeader = sizeof(TreeHeader);
 constexpr int kExpandBatch = 12;                 // levels launched between count checks
 constexpr int kExpandMaxLevels = 400;            // > 2 x the deepest possible tree
-constexpr uint32_t kChunk = 16;                 // intervals per thread, per-object steps
 
 int check_params(const cd_params *p)
 {
@@ -156,8 +155,8 @@ uint32_t default_slab(uint32_t horizon) { return horizon / 4096u > 0 ? horizon /
 
 struct CountWS {
     ObjSteps *st;
-    uint32_t *Kc, *Cc;
-    unsigned long long *totals;
+    uint32_t *Kc;
+    unsigned long long *total;
     unsigned int *bad;
 };
 size_t layout_count(void *base, size_t bytes, int64_t n, CountWS *w)
@@ -165,8 +164,7 @@ size_t layout_count(void *base, size_t bytes, int64_t n, CountWS *w)
     Carve c(base, bytes);
     w->st = c.take<ObjSteps>(n);
     w->Kc = c.take<uint32_t>(n);
-    w->Cc = c.take<uint32_t>(n);
-    w->totals = c.take<unsigned long long>(2);
+    w->total = c.take<unsigned long long>(1);
     w->bad = c.take<unsigned int>(1);
     return c.off;
 }
@@ -174,7 +172,7 @@ size_t layout_count(void *base, size_t bytes, int64_t n, CountWS *w)
 struct BoxWS {
     CountWS cnt;
     ObjConst *oc;
-    uint32_t *box_off, *chunk_off;
+    uint32_t *box_off;
     void *scan;
 };
 size_t layout_boxes(void *base, size_t bytes, int64_t n, BoxWS *w)
@@ -184,7 +182,6 @@ size_t layout_boxes(void *base, size_t bytes, int64_t n, BoxWS *w)
     c.off = off;
     w->oc = c.take<ObjConst>(n);
     w->box_off = c.take<uint32_t>(n);
-    w->chunk_off = c.take<uint32_t>(n);
     w->scan = c.take_bytes(scan_ws_bytes((size_t)n));
     return c.off;
 }
@@ -346,11 +343,11 @@ int cd_box_count(const uint32_t *dt_ticks, int64_t n, const cd_params *p, int64_
         hipStream_t s = (hipStream_t)stream;
         CountWS w;
         layout_count(ws, ws_bytes, n, &w);
-        CD_HIP(launch_steps(dt_ticks, (uint32_t)n, p->horizon_ticks, kChunk, w.st, w.Kc, w.Cc,
-                            w.totals, w.bad, s));
-        unsigned long long h[2];
+        CD_HIP(launch_steps(dt_ticks, (uint32_t)n, p->horizon_ticks, w.st, w.Kc, w.total, w.bad,
+                            s));
+        unsigned long long h[1];
         unsigned int bad = 0;
-        CD_HIP(hipMemcpyAsync(h, w.totals, sizeof h, hipMemcpyDeviceToHost, s));
+        CD_HIP(hipMemcpyAsync(h, w.total, sizeof h, hipMemcpyDeviceToHost, s));
         CD_HIP(hipMemcpyAsync(&bad, w.bad, sizeof bad, hipMemcpyDeviceToHost, s));
         CD_HIP(hipStreamSynchronize(s));
         if (bad)
@@ -479,15 +476,13 @@ int cd_build_boxes(const cd_elements *el, const uint32_t *dt_ticks, const cd_par
         out->slab_ticks = p->dt_ticks;
         out->slab_size = n;
     } else {
-        CD_HIP(launch_steps(dt_ticks, (uint32_t)n, T, kChunk, w.cnt.st, w.cnt.Kc, w.cnt.Cc,
-                            w.cnt.totals, w.cnt.bad, s));
+        CD_HIP(launch_steps(dt_ticks, (uint32_t)n, T, w.cnt.st, w.cnt.Kc, w.cnt.total, w.cnt.bad,
+                            s));
         CD_HIP(scan_exclusive_u32(w.cnt.Kc, w.box_off, (size_t)n, w.scan, s));
-        CD_HIP(scan_exclusive_u32(w.cnt.Cc, w.chunk_off, (size_t)n, w.scan, s));
-        CD_HIP(launch_steps_apply_offsets(w.cnt.st, w.box_off, w.chunk_off, (uint32_t)n, s));
-        // chunks <= boxes / chunk + objects; threads past the real total return
-        uint64_t upper = (uint64_t)out->count / kChunk + (uint64_t)n;
-        CD_HIP(launch_boxes_variable(w.oc, w.cnt.st, (uint32_t)n, (uint32_t)upper, kChunk, T,
-                                     p->tick_s, half_thr, out->precision, bo, s));
+        CD_HIP(launch_steps_apply_offsets(w.cnt.st, w.box_off, (uint32_t)n, s));
+        // out->count is the caller's box count; lanes past the real total return
+        CD_HIP(launch_boxes_variable(w.oc, w.cnt.st, (uint32_t)n, T, p->tick_s, half_thr,
+                                     out->precision, bo, s));
     }
     return CD_OK;
 }

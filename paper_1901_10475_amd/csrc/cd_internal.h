@@ -20,7 +20,7 @@ struct ObjConst {
 struct ObjSteps {
     uint32_t dt, K;      // step and interval count
     uint32_t box_off;    // first box of the object
-    uint32_t chunk_off;  // first work chunk of the object
+    uint32_t pad;
 };
 
 // Tree node layouts.  FP64: one 64-byte record per node.  FP32: a 32-byte box
@@ -234,20 +234,17 @@ __host__ __device__ inline double from_ordered_bits(uint64_t u)
 // boxes
 hipError_t launch_object_setup(const cd_elements &el, double mu, ObjConst *oc, hipStream_t s);
 hipError_t launch_validate(const cd_elements &el, unsigned long long *first_bad, hipStream_t s);
-hipError_t launch_steps(const uint32_t *dt, uint32_t n, uint32_t T, uint32_t chunk,
-                        ObjSteps *st, uint32_t *Kc, uint32_t *Cc,
-                        unsigned long long *totals /*[2]: boxes, chunks*/,
-                        unsigned int *bad_dt, hipStream_t s);
-hipError_t launch_steps_apply_offsets(ObjSteps *st, const uint32_t *box_off,
-                                      const uint32_t *chunk_off, uint32_t n, hipStream_t s);
+hipError_t launch_steps(const uint32_t *dt, uint32_t n, uint32_t T, ObjSteps *st, uint32_t *Kc,
+                        unsigned long long *total, unsigned int *bad_dt, hipStream_t s);
+hipError_t launch_steps_apply_offsets(ObjSteps *st, const uint32_t *box_off, uint32_t n,
+                                      hipStream_t s);
 hipError_t launch_dt_heuristic(const cd_elements &el, double mu, double tick_s,
                                double max_disp, uint32_t T, uint32_t *dt_out, hipStream_t s);
 hipError_t launch_boxes_uniform(const ObjConst *oc, uint32_t n, uint32_t K, uint32_t dt,
                                 uint32_t T, double tick_s, double half_thr, int precision,
                                 const BoxOut &out, hipStream_t s);
-hipError_t launch_boxes_variable(const ObjConst *oc, const ObjSteps *st, uint32_t n,
-                                 uint32_t total_chunks, uint32_t chunk, uint32_t T, double tick_s,
-                                 double half_thr, int precision, const BoxOut &out,
+hipError_t launch_boxes_variable(const ObjConst *oc, const ObjSteps *st, uint32_t n, uint32_t T,
+                                 double tick_s, double half_thr, int precision, const BoxOut &out,
                                  hipStream_t s);
 
 // scans / sorts / fills

@@ -57,10 +57,9 @@ __global__ void k_validate(cd_elements el, unsigned long long *first_bad)
         atomicMin(first_bad, (unsigned long long)i);
 }
 
-// K_i = max(1, ceil(T / dt_i)) and the number of work chunks of each object.
-__global__ void k_steps(const uint32_t *dt, uint32_t n, uint32_t T, uint32_t chunk,
-                        ObjSteps *st, uint32_t *Kc, uint32_t *Cc, unsigned long long *totals,
-                        unsigned int *bad_dt)
+// K_i = max(1, ceil(T / dt_i)) of each object and their total.
+__global__ void k_steps(const uint32_t *dt, uint32_t n, uint32_t T, ObjSteps *st, uint32_t *Kc,
+                        unsigned long long *total, unsigned int *bad_dt)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
@@ -75,12 +74,9 @@ __global__ void k_steps(const uint32_t *dt, uint32_t n, uint32_t T, uint32_t chu
     s.dt = d;
     s.K = (uint32_t)(K > 0xFFFFFFFFull ? 0xFFFFFFFFull : K);
     s.box_off = 0;
-    s.chunk_off = (uint32_t)((K + chunk - 1) / chunk);  // chunk count, scanned later
     st[i] = s;
     Kc[i] = s.K;
-    Cc[i] = s.chunk_off;
-    atomicAdd(&totals[0], (unsigned long long)K);
-    atomicAdd(&totals[1], (unsigned long long)s.chunk_off);
+    atomicAdd(total, (unsigned long long)K);
 }
 
 __global__ void k_dt_heuristic(cd_elements el, double mu, double tick_s, double max_disp,
@@ -196,42 +192,71 @@ __global__ void k_boxes_uniform(const ObjConst *__restrict__ oc, uint32_t n, uin
     object_run<PREC>(oc[i], i, k0, k1, K, dt, T, tick_s, half_thr, out, i, n);
 }
 
+// Per-object steps, object-major output (box off_i + k).  One lane per box, so
+// consecutive lanes store consecutive boxes.  Each lane solves Kepler's
+// equation for the start of its interval; the end of the interval is the next
+// box's start, taken from the next lane by a shuffle (a second solve only for
+// the last box of a wave or of an object).
 template <int PREC>
-__global__ void k_boxes_variable(const ObjConst *__restrict__ oc,
-                                 const ObjSteps *__restrict__ st, uint32_t n,
-                                 uint32_t total_chunks, uint32_t chunk, uint32_t T,
-                                 double tick_s, double half_thr, BoxOut out)
+__global__ __launch_bounds__(256) void k_boxes_variable(const ObjConst *__restrict__ oc,
+                                                        const ObjSteps *__restrict__ st,
+                                                        uint32_t n, uint32_t T, double tick_s,
+                                                        double half_thr, BoxOut out)
 {
-    uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= total_chunks)
-        return;
-    // object owning chunk g: last i with chunk_off[i] <= g
+    uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool active = b < out.cap;
+    // object owning box b: last i with box_off[i] <= b
     uint32_t lo = 0, hi = n;
     while (hi - lo > 1) {
         uint32_t mid = (lo + hi) >> 1;
-        if (st[mid].chunk_off <= g)
+        if (st[mid].box_off <= b)
             lo = mid;
         else
             hi = mid;
     }
     uint32_t i = lo;
     ObjSteps s = st[i];
-    uint64_t k0 = (uint64_t)(g - s.chunk_off) * chunk;
-    if (k0 >= s.K)
+    uint64_t k = active ? b - s.box_off : 0;
+    active = active && k < s.K;
+    ObjConst c = oc[i];
+    uint64_t ta = k * s.dt < T ? k * s.dt : T;
+    uint64_t tb = (k + 1) * s.dt < T ? (k + 1) * s.dt : T;
+    double Ma = c.m0 + c.n * ((double)ta * tick_s);
+    double E = Ma + c.e * sin(Ma), sE, cE;
+    kepler(Ma, c.e, E, sE, cE);
+    double pa[3];
+    position(c, sE, cE, pa);
+    // the next lane holds the start of this box's end, if it is the same object
+    int lane = threadIdx.x & 63;
+    double nx = __shfl_down(pa[0], 1, 64), ny = __shfl_down(pa[1], 1, 64),
+           nz = __shfl_down(pa[2], 1, 64);
+    uint32_t ni = __shfl_down(i, 1, 64);
+    uint64_t nk = __shfl_down(k, 1, 64);
+    double pb[3];
+    if (lane < 63 && ni == i && nk == k + 1 && k + 1 < s.K) {
+        pb[0] = nx;
+        pb[1] = ny;
+        pb[2] = nz;
+    } else {
+        double Mb = c.m0 + c.n * ((double)tb * tick_s);
+        E += (Mb - Ma) / (1.0 - c.e * cE);
+        kepler(Mb, c.e, E, sE, cE);
+        position(c, sE, cE, pb);
+    }
+    if (!active)
         return;
-    uint64_t k1 = k0 + chunk < s.K ? k0 + chunk : s.K;
-    object_run<PREC>(oc[i], i, k0, k1, s.K, s.dt, T, tick_s, half_thr, out, s.box_off, 1);
+    double g = c.vmax * ((double)(tb - ta) * tick_s) * 0.5 + half_thr;
+    uint32_t t1 = (k + 1 == s.K) ? (uint32_t)(T + 1) : (uint32_t)tb;
+    store_box<PREC>(out, b, pa, pb, g, (uint32_t)ta, t1, i);
 }
 
-// After the chunk counts and K have been scanned into ObjSteps.
-__global__ void k_steps_apply_offsets(ObjSteps *st, const uint32_t *box_off,
-                                      const uint32_t *chunk_off, uint32_t n)
+// After the interval counts have been scanned into first-box offsets.
+__global__ void k_steps_apply_offsets(ObjSteps *st, const uint32_t *box_off, uint32_t n)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
         return;
     st[i].box_off = box_off[i];
-    st[i].chunk_off = chunk_off[i];
 }
 
 static inline unsigned blocks_for(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
@@ -253,16 +278,15 @@ hipError_t launch_validate(const cd_elements &el, unsigned long long *first_bad,
     return hipGetLastError();
 }
 
-hipError_t launch_steps(const uint32_t *dt, uint32_t n, uint32_t T, uint32_t chunk,
-                        ObjSteps *st, uint32_t *Kc, uint32_t *Cc, unsigned long long *totals,
-                        unsigned int *bad_dt, hipStream_t s)
+hipError_t launch_steps(const uint32_t *dt, uint32_t n, uint32_t T, ObjSteps *st, uint32_t *Kc,
+                        unsigned long long *total, unsigned int *bad_dt, hipStream_t s)
 {
-    hipError_t e = launch_fill_u64(totals, 0ull, 2, s);
+    hipError_t e = launch_fill_u64(total, 0ull, 1, s);
     if (e == hipSuccess)
         e = launch_fill_u32(bad_dt, 0u, 1, s);
     if (e != hipSuccess || n == 0)
         return e;
-    k_steps<<<blocks_for(n, 256), 256, 0, s>>>(dt, n, T, chunk, st, Kc, Cc, totals, bad_dt);
+    k_steps<<<blocks_for(n, 256), 256, 0, s>>>(dt, n, T, st, Kc, total, bad_dt);
     return hipGetLastError();
 }
 
@@ -294,28 +318,27 @@ hipError_t launch_boxes_uniform(const ObjConst *oc, uint32_t n, uint32_t K, uint
     return hipGetLastError();
 }
 
-hipError_t launch_boxes_variable(const ObjConst *oc, const ObjSteps *st, uint32_t n,
-                                 uint32_t total_chunks, uint32_t chunk, uint32_t T, double tick_s,
-                                 double half_thr, int precision, const BoxOut &out,
+hipError_t launch_boxes_variable(const ObjConst *oc, const ObjSteps *st, uint32_t n, uint32_t T,
+                                 double tick_s, double half_thr, int precision, const BoxOut &out,
                                  hipStream_t s)
 {
-    if (n == 0 || total_chunks == 0)
+    if (n == 0 || out.cap == 0)
         return hipSuccess;
     if (precision == CD_FP64)
-        k_boxes_variable<CD_FP64><<<blocks_for(total_chunks, 128), 128, 0, s>>>(
-            oc, st, n, total_chunks, chunk, T, tick_s, half_thr, out);
+        k_boxes_variable<CD_FP64><<<blocks_for(out.cap, 256), 256, 0, s>>>(oc, st, n, T, tick_s,
+                                                                         half_thr, out);
     else
-        k_boxes_variable<CD_FP32><<<blocks_for(total_chunks, 128), 128, 0, s>>>(
-            oc, st, n, total_chunks, chunk, T, tick_s, half_thr, out);
+        k_boxes_variable<CD_FP32><<<blocks_for(out.cap, 256), 256, 0, s>>>(oc, st, n, T, tick_s,
+                                                                         half_thr, out);
     return hipGetLastError();
 }
 
-hipError_t launch_steps_apply_offsets(ObjSteps *st, const uint32_t *box_off,
-                                      const uint32_t *chunk_off, uint32_t n, hipStream_t s)
+hipError_t launch_steps_apply_offsets(ObjSteps *st, const uint32_t *box_off, uint32_t n,
+                                      hipStream_t s)
 {
     if (n == 0)
         return hipSuccess;
-    k_steps_apply_offsets<<<blocks_for(n, 256), 256, 0, s>>>(st, box_off, chunk_off, n);
+    k_steps_apply_offsets<<<blocks_for(n, 256), 256, 0, s>>>(st, box_off, n);
     return hipGetLastError();
 }
 

@@ -237,3 +237,46 @@ def test_tracked_hour_full_size_sampled():
     sub = oracle.boxes(sc.elements[ob_i], 1000, sc.horizon_ticks, sc.tick_s, 1.0)
     g = np.concatenate([np.arange(3600) * 16848 + i for i in ob_i])
     assert_boxes_close(lo[g], hi[g], sub.lo, sub.hi, sc.elements[obj[g], 0])
+
+
+def test_tracked_hour_heuristic_steps_full_size():
+    """Per-object steps (each box's motion bounded by 5 km; 79.7 M boxes,
+    object-major, device-wide sort path): sampled exact parity, planted
+    recall, and the FP32 tree's list contains the FP64 list (extras counted)."""
+    need_gpu()
+    say("tracked16848 1h heuristic dt full size")
+    import torch
+    import paper_1901_10475_amd as cd
+    sc = catalog.tracked_hour()
+    el = cd.soa(sc.elements)
+    p = cd.params_struct(sc.tick_s, sc.mu, sc.threshold_km, sc.horizon_ticks, 0)
+    bp = cd.BroadPhase(sc.n, p, None, cd.CD_FP64, cd.CD_FP64, dt_heuristic_km=5.0, el_soa=el)
+    pairs = bp.run(el).cpu().numpy().view(np.uint32).copy()
+    dt = bp.dt.cpu().numpy().view(np.uint32)
+    assert np.array_equal(dt, oracle.dt_heuristic(sc.elements, sc.tick_s, 5.0, sc.horizon_ticks))
+    lo, hi, t0, t1, obj = bp.boxes.to_host()
+    ob = oracle.Boxes(lo, hi, t0, t1, obj)
+    rng = np.random.default_rng(7)
+    sample = rng.choice(len(t0), 160, replace=False)
+    if len(pairs):
+        # boxes that have partners: object i's box containing t_lo
+        K = -(-sc.horizon_ticks // dt.astype(np.int64))
+        off = np.concatenate([[0], np.cumsum(K)[:-1]])
+        pick = pairs[rng.choice(len(pairs), min(48, len(pairs)), replace=False)]
+        extra = [off[i] + int(t) // int(dt[i]) for i, _, t, _ in pick]
+        sample = np.unique(np.concatenate([sample, extra]))
+    want = oracle.pairs_of(ob, sample)
+    got = records_of_boxes(pairs, obj, t0, t1, sample)
+    got = np.unique(got, axis=0) if len(got) else got.reshape(0, 4)
+    assert np.array_equal(got, want)
+    for i, j, tc in sc.planted:
+        hit = pairs[(pairs[:, 0] == i) & (pairs[:, 1] == j)]
+        assert np.any((hit[:, 2] <= tc) & (tc < hit[:, 3])), (i, j, tc)
+    del bp
+    torch.cuda.empty_cache()
+    bp32 = cd.BroadPhase(sc.n, p, None, cd.CD_FP64, cd.CD_FP32, dt_heuristic_km=5.0, el_soa=el)
+    p32 = bp32.run(el).cpu().numpy().view(np.uint32)
+    s64 = {tuple(x) for x in pairs.tolist()}
+    s32 = {tuple(x) for x in p32.tolist()}
+    assert s64 <= s32
+    say(f"heuristic dt: {len(s64)} FP64 records, {len(s32) - len(s64)} extra with an FP32 tree")
