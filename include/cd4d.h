@@ -149,8 +149,8 @@ size_t cd_validate_ws(int64_t n);
 int cd_validate_elements(const cd_elements *el, int64_t *bad_index_host, void *ws,
                          size_t ws_bytes, cd_stream_t stream);
 
-/* Per-object step from the speed bound (config "interval displacement <=
- * max_disp_km"): dt_i = clamp(floor(max_disp_km / (vmax_i * tick_s)), 1,
+/* Per-object step from the speed bound (each interval's displacement at most
+ * max_disp_km): dt_i = clamp(floor(max_disp_km / (vmax_i * tick_s)), 1,
  * max(T, 1)) ticks, vmax_i the perigee speed.  Any step keeps the boxes
  * conservative; this one bounds each box's motion term.  Async. */
 int cd_dt_heuristic(const cd_elements *el, const cd_params *p, double max_disp_km,
@@ -207,6 +207,59 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
 size_t cd_query_pairs_ws(int64_t count, int64_t capacity);
 int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t *count_host,
                    void *ws, size_t ws_bytes, cd_stream_t stream);
+
+/* ---- learned per-object step ------------------------------------------- */
+
+/* The paper keeps a time interval per object so that objects far from all
+ * others take long intervals (Sec. Collision Detection with 4D AABB Trees;
+ * Procedure advanceTime) and leaves the step rule open.  These calls run a
+ * 5 -> 64 -> 64 -> 1 ReLU network that predicts y = log2(step in seconds)
+ * from x = (a/42164, e, i/pi, r_p/42164, vmax/8), r_p = a(1 - e), vmax the
+ * perigee speed:
+ *   h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), y = w3 . h2 + b3,
+ *   dt = clamp(floor(2^y / tick_s), 1, max(T, 1)) ticks.
+ * Parameters: one flat vector of CD_MLP_PARAMS values in the order W1 (64x5,
+ * row-major), b1 (64), W2 (64x64, row-major), b2 (64), w3 (64), b3 (1).  Any
+ * step keeps the boxes conservative, so the network affects cost only.
+ * All pointers are device pointers unless named _host. */
+#define CD_MLP_PARAMS 4609
+
+/* x_out[i*5 + f] (FP32) = feature f of object i, computed in FP64.  Async. */
+int cd_mlp_features(const cd_elements *el, const cd_params *p, float *x_out,
+                    cd_stream_t stream);
+
+/* BF16 inference: w_bf16 holds the parameters as bfloat16 bit patterns;
+ * inputs and hidden activations are rounded to bfloat16, sums are FP32.
+ * dt_out[i] = the decoded step; where y is not finite, or w_bf16 is NULL, the
+ * cd_dt_heuristic step for fallback_disp_km is used.  y_out (nullable)
+ * receives y (NaN for every object when w_bf16 is NULL).  Async. */
+int cd_dt_mlp(const cd_elements *el, const uint16_t *w_bf16, double fallback_disp_km,
+              const cd_params *p, uint32_t *dt_out, float *y_out, cd_stream_t stream);
+
+/* FP32 forward pass: y_out[b] for x[b*5 .. b*5+4], w FP32 parameters.  Async. */
+int cd_mlp_forward(const float *w, const float *x, int64_t batch, float *y_out,
+                   cd_stream_t stream);
+
+/* FP32 loss L = mean_b (y_b - target_b)^2 and its gradient with respect to
+ * every parameter (grad_out[CD_MLP_PARAMS], same order as w); *loss_out is a
+ * device float (nullable).  The batch sum is taken per block of samples and
+ * the block partials are added in a fixed order: results are deterministic.
+ * 1 <= batch < 2^31.  Async. */
+size_t cd_mlp_grad_ws(int64_t batch);
+int cd_mlp_grad(const float *w, const float *x, const float *target, int64_t batch,
+                float *grad_out, float *loss_out, void *ws, size_t ws_bytes, cd_stream_t stream);
+
+/* One Adam step (Kingma & Ba, bias-corrected moments) in place on w, m, v
+ * (FP32, CD_MLP_PARAMS each) for gradient g; step >= 1 counts from 1.  If
+ * w_bf16_out is not NULL it receives the updated weights rounded to bfloat16
+ * (nearest, ties to even).  Async. */
+int cd_mlp_adam(float *w, float *m, float *v, const float *g, int64_t step, float lr,
+                float beta1, float beta2, float eps, uint16_t *w_bf16_out, cd_stream_t stream);
+
+/* counts_out[o] = number of records of pairs[0..count) naming object o (as i
+ * or j), o < n; names >= n are ignored.  Async. */
+int cd_pair_object_counts(const cd_pair *pairs, int64_t count, int64_t n, uint32_t *counts_out,
+                          cd_stream_t stream);
 
 #ifdef __cplusplus
 }

@@ -72,6 +72,7 @@ def lib():
         L = ctypes.CDLL(_LIB_PATH)
         P = ctypes.POINTER
         i64, u32, sz, dbl = ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t, ctypes.c_double
+        flt = ctypes.c_float
         sig = {
             "cd_status_string": (ctypes.c_char_p, [ctypes.c_int]),
             "cd_last_error": (ctypes.c_char_p, []),
@@ -93,6 +94,15 @@ def lib():
                                              sz, _vp]),
             "cd_query_pairs_ws": (sz, [i64, i64]),
             "cd_query_pairs": (ctypes.c_int, [P(cd_tree), _vp, i64, P(i64), _vp, sz, _vp]),
+            "cd_mlp_features": (ctypes.c_int, [P(cd_elements), P(cd_params), _vp, _vp]),
+            "cd_dt_mlp": (ctypes.c_int, [P(cd_elements), _vp, dbl, P(cd_params), _vp, _vp,
+                                         _vp]),
+            "cd_mlp_forward": (ctypes.c_int, [_vp, _vp, i64, _vp, _vp]),
+            "cd_mlp_grad_ws": (sz, [i64]),
+            "cd_mlp_grad": (ctypes.c_int, [_vp, _vp, _vp, i64, _vp, _vp, _vp, sz, _vp]),
+            "cd_mlp_adam": (ctypes.c_int, [_vp, _vp, _vp, _vp, i64, flt, flt, flt, flt, _vp,
+                                           _vp]),
+            "cd_pair_object_counts": (ctypes.c_int, [_vp, i64, i64, _vp, _vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -106,7 +116,9 @@ EXPORTED = ("cd_status_string", "cd_last_error", "cd_version", "cd_profile_enabl
             "cd_profile_read", "cd_box_count_ws",
             "cd_box_count", "cd_validate_ws", "cd_validate_elements", "cd_dt_heuristic",
             "cd_build_boxes_ws", "cd_build_boxes", "cd_tree_bytes", "cd_build_tree_ws",
-            "cd_build_tree", "cd_query_pairs_ws", "cd_query_pairs")
+            "cd_build_tree", "cd_query_pairs_ws", "cd_query_pairs", "cd_mlp_features",
+            "cd_dt_mlp", "cd_mlp_forward", "cd_mlp_grad_ws", "cd_mlp_grad", "cd_mlp_adam",
+            "cd_pair_object_counts")
 
 
 def cd_profile_enable(on=True):
@@ -288,13 +300,16 @@ class BroadPhase:
 
     def __init__(self, n, params, dt_ticks=None, box_precision=CD_FP64,
                  tree_precision=CD_FP64, capacity=None, slab_ticks=0, device="cuda",
-                 dt_heuristic_km=None, el_soa=None):
-        """dt_heuristic_km: per-object steps from cd_dt_heuristic (recomputed by
-        every build from the elements; el_soa is needed here to size buffers)."""
+                 dt_heuristic_km=None, el_soa=None, dt_mlp=None):
+        """dt_heuristic_km: per-object steps from cd_dt_heuristic; dt_mlp:
+        (bfloat16 weight tensor, fallback_disp_km) for steps from cd_dt_mlp.
+        Either is recomputed by every build from the elements (el_soa is
+        needed here to size the buffers)."""
         self.dt_heuristic_km = dt_heuristic_km
-        if dt_heuristic_km is not None:
+        self.dt_mlp = dt_mlp
+        if dt_heuristic_km is not None or dt_mlp is not None:
             dt_ticks = torch.empty(int(n), dtype=torch.int32, device=device)
-            cd_dt_heuristic(el_soa, params, dt_heuristic_km, dt_ticks)
+            self._steps(el_soa, params, dt_ticks)
         self.n, self.params, self.dt = int(n), params, dt_ticks
         self.device = device
         self.count = cd_box_count(dt_ticks, n, params, device)
@@ -311,9 +326,18 @@ class BroadPhase:
         self.out = torch.empty((max(self.capacity, 1), 4), dtype=torch.int32, device=self.device)
         self.ws_query = _bytes(lib().cd_query_pairs_ws(self.count, self.capacity), self.device)
 
+    def _steps(self, el_soa, params, dt):
+        if self.dt_mlp is not None:
+            el = elements_struct(el_soa)
+            w, fallback = self.dt_mlp
+            _check(lib().cd_dt_mlp(ctypes.byref(el), _ptr(w), float(fallback),
+                                   ctypes.byref(params), _ptr(dt), None, _stream()))
+        else:
+            cd_dt_heuristic(el_soa, params, self.dt_heuristic_km, dt)
+
     def build(self, el_soa):
-        if self.dt_heuristic_km is not None:
-            cd_dt_heuristic(el_soa, self.params, self.dt_heuristic_km, self.dt)
+        if self.dt_heuristic_km is not None or self.dt_mlp is not None:
+            self._steps(el_soa, self.params, self.dt)
         cd_build_boxes(el_soa, self.dt, self.params, self.boxes, self.ws_boxes)
         cd_build_tree(self.boxes, self.tree_precision, self.tree, self.ws_tree, self.slab_ticks)
 

@@ -12,6 +12,12 @@ the mean anomaly at t = 0.  Time is counted in integer ticks of ``tick_s``
 seconds (1 ms by default).  Random numbers come from numpy's PCG64
 (``default_rng(seed)``), drawn per class in the order a, e, i, raan, argp, m0.
 
+Fragment clouds (the projected-debris catalog) are also built in element
+space: each fragment takes its parent's elements changed by the first-order
+effect of a small impulse on a near-circular orbit (Gauss's variational
+equations), and its phase drifts at its own mean motion from the breakup
+epoch to t = 0.
+
 Planted conjunctions are built in element space only.  Two objects share a,
 e, raan and argp but sit in planes of different inclination, so both orbits
 pass through the same point on the common line of nodes.  Their mean anomaly
@@ -33,7 +39,8 @@ DEG = math.pi / 180.0
 class Scenario:
     name: str
     elements: np.ndarray          # [n, 6] float64
-    dt_ticks: object              # int (uniform step) or np.ndarray[n] uint32
+    dt_ticks: object              # int (uniform step), np.ndarray[n] uint32, or None
+                                  # (the step is chosen per object by a rule)
     horizon_ticks: int            # T
     threshold_km: float           # thr = 2 r
     tick_s: float = TICK_S
@@ -46,7 +53,8 @@ class Scenario:
 
     @property
     def uniform_dt(self):
-        return np.isscalar(self.dt_ticks) or np.ndim(self.dt_ticks) == 0
+        return self.dt_ticks is not None and (np.isscalar(self.dt_ticks)
+                                              or np.ndim(self.dt_ticks) == 0)
 
 
 def _draw(rng, n, a_lo, a_hi, e_lo, e_hi, i_lo, i_hi, a_normal=None):
@@ -171,6 +179,70 @@ def batch_member(s, n, seed_base=4001):
     """Scenario s of the uneven batch: n LEO objects, 30-minute horizon, dt = 1 s."""
     rng = np.random.default_rng(seed_base + s)
     return Scenario(f"batch{s}_n{n}", leo_mix(rng, n), 1_000, 1_800_000, 1.0)
+
+
+def fragment_clouds(rng, parents, per_parent, dv_sigma_kms, age_range_s, mu=MU_EARTH):
+    """Fragments of impulsive breakups of near-circular parents.
+
+    For each parent (a row of elements) and each fragment: an impulse with
+    radial, along-track and normal parts R, S, W ~ N(0, dv_sigma^2); the
+    breakup happened `age` seconds before t = 0, age ~ U[age_range], at the
+    parent's argument of latitude u_b at that epoch.  With v = sqrt(mu / a)
+    the first-order element changes of a circular orbit are
+        da = 2 a S / v,
+        d(e cos w) = (R sin u_b + 2 S cos u_b) / v,
+        d(e sin w) = (-R cos u_b + 2 S sin u_b) / v,
+        di = W cos u_b / v,   draan = W sin u_b / (v sin i),
+    and the fragment's mean argument of latitude at t = 0 is
+    u_b + n_frag * age.  Returns [len(parents) * per_parent, 6].
+    """
+    out = []
+    for par in parents:
+        a, e, inc, raan, argp, m0 = (float(v) for v in par)
+        n_par = math.sqrt(mu / a ** 3)
+        v = math.sqrt(mu / a)
+        age = rng.uniform(age_range_s[0], age_range_s[1])
+        u_b = (argp + m0 - n_par * age) % TWO_PI
+        R, S, W = (rng.normal(0.0, dv_sigma_kms, per_parent) for _ in range(3))
+        su, cu = math.sin(u_b), math.cos(u_b)
+        fa = a + 2.0 * a * S / v
+        ex = e * math.cos(argp) + (R * su + 2.0 * S * cu) / v
+        ey = e * math.sin(argp) + (-R * cu + 2.0 * S * su) / v
+        fe = np.minimum(np.hypot(ex, ey), 0.9)
+        fw = np.arctan2(ey, ex) % TWO_PI
+        fi = np.clip(inc + W * cu / v, 0.0, math.pi)
+        fO = (raan + W * su / (v * max(math.sin(inc), 1e-3))) % TWO_PI
+        n_frag = np.sqrt(mu / fa ** 3)
+        fm = (u_b + n_frag * age - fw) % TWO_PI
+        out.append(np.stack([fa, fe, fi, fO, fw, fm], axis=1))
+    return np.concatenate(out, axis=0) if out else np.zeros((0, 6))
+
+
+def projected_debris(seed=5001, n=100_000, fragment_share=0.2, parents=50,
+                     horizon_ticks=21_600_000, planted=16, dv_sigma_kms=0.05,
+                     age_days=(1.0, 30.0)):
+    """Projected-debris catalog: (1 - fragment_share) n objects of the
+    10-minute test population plus fragment clouds of `parents` breakups
+    (parents drawn among those objects, an equal share of fragments each,
+    impulses N(0, 50 m/s) per axis, breakups 1-30 days before t = 0).
+    Threshold 1 km; the step is chosen per object (dt_ticks None)."""
+    rng = np.random.default_rng(seed)
+    per = int(round(n * fragment_share / parents)) if parents else 0
+    n_base = n - per * parents
+    base = leo_mix(rng, n_base)
+    pidx = rng.choice(n_base, size=parents, replace=False) if parents else []
+    frag = fragment_clouds(rng, base[pidx], per, dv_sigma_kms,
+                           (age_days[0] * 86400.0, age_days[1] * 86400.0))
+    el = np.concatenate([base, frag], axis=0)
+    # planted pairs replace rows of the base population (fragments stay whole)
+    pl = []
+    if planted:
+        head = el[:n_base]
+        pl = plant_conjunctions(rng, head, planted, horizon_ticks, 1_000, 1.0)
+        el[:n_base] = head
+    hours = horizon_ticks / 3_600_000
+    name = f"debris{n}_{hours:g}h" if hours >= 1 else f"debris{n}_{horizon_ticks // 1000}s"
+    return Scenario(name, el, None, int(horizon_ticks), 1.0, planted=pl)
 
 
 def random_boxes(seed, N, n_obj, extent=100.0, size=5.0, T=100, max_len=10,

@@ -725,4 +725,118 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
     return CD_OK;
 }
 
+// ---- learned per-object step ---------------------------------------------------------
+
+struct MlpWS {
+    float *act, *part;
+};
+size_t layout_mlp(void *base, size_t bytes, int64_t B, MlpWS *w)
+{
+    Carve c(base, bytes);
+    uint64_t nblk = ((uint64_t)B + kMlpOuterSamples - 1) / kMlpOuterSamples;
+    w->act = c.take<float>((size_t)258 * (size_t)B);
+    w->part = c.take<float>((size_t)nblk * (kMlpParams + 1));
+    return c.off;
+}
+
+int cd_mlp_features(const cd_elements *el, const cd_params *p, float *x_out, cd_stream_t stream)
+{
+    int rc = check_elements(el);
+    if (!rc)
+        rc = check_params(p);
+    if (rc)
+        return rc;
+    if (el->n > 0 && !x_out)
+        return fail(CD_E_INVALID, "x_out is NULL");
+    CD_HIP(launch_mlp_features(*el, p->mu, x_out, (hipStream_t)stream));
+    return CD_OK;
+}
+
+int cd_dt_mlp(const cd_elements *el, const uint16_t *w_bf16, double fallback_disp_km,
+              const cd_params *p, uint32_t *dt_out, float *y_out, cd_stream_t stream)
+{
+    int rc = check_elements(el);
+    if (!rc)
+        rc = check_params(p);
+    if (rc)
+        return rc;
+    if (!(fallback_disp_km > 0.0) || !isfinite(fallback_disp_km))
+        return fail(CD_E_INVALID, "fallback_disp_km must be finite and > 0");
+    if (el->n > 0 && !dt_out)
+        return fail(CD_E_INVALID, "dt_out is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    if (!w_bf16) {
+        CD_HIP(launch_dt_heuristic(*el, p->mu, p->tick_s, fallback_disp_km, p->horizon_ticks,
+                                   dt_out, s));
+        if (y_out && el->n > 0)
+            CD_HIP(launch_fill_u32((uint32_t *)y_out, 0x7FC00000u, (size_t)el->n, s));
+        return CD_OK;
+    }
+    CD_HIP(launch_dt_mlp(*el, w_bf16, p->mu, p->tick_s, fallback_disp_km, p->horizon_ticks,
+                         dt_out, y_out, s));
+    return CD_OK;
+}
+
+int cd_mlp_forward(const float *w, const float *x, int64_t batch, float *y_out,
+                   cd_stream_t stream)
+{
+    if (batch < 0 || batch >= (1ll << 31))
+        return fail(CD_E_INVALID, "batch out of range");
+    if (batch > 0 && (!w || !x || !y_out))
+        return fail(CD_E_INVALID, "NULL pointer");
+    CD_HIP(launch_mlp_forward(w, x, (uint32_t)batch, y_out, (hipStream_t)stream));
+    return CD_OK;
+}
+
+size_t cd_mlp_grad_ws(int64_t batch)
+{
+    MlpWS w;
+    return layout_mlp(nullptr, 0, batch > 0 ? batch : 0, &w);
+}
+
+int cd_mlp_grad(const float *w, const float *x, const float *target, int64_t batch,
+                float *grad_out, float *loss_out, void *ws, size_t ws_bytes, cd_stream_t stream)
+{
+    if (batch < 1 || batch >= (1ll << 31))
+        return fail(CD_E_INVALID, "batch must be in [1, 2^31)");
+    if (!w || !x || !target || !grad_out)
+        return fail(CD_E_INVALID, "NULL pointer");
+    if (!ws || ws_bytes < cd_mlp_grad_ws(batch))
+        return fail(CD_E_WORKSPACE, "mlp workspace too small");
+    MlpWS m;
+    layout_mlp(ws, ws_bytes, batch, &m);
+    CD_HIP(launch_mlp_grad(w, x, target, (uint32_t)batch, m.act, m.part, grad_out, loss_out,
+                           (hipStream_t)stream));
+    return CD_OK;
+}
+
+int cd_mlp_adam(float *w, float *m, float *v, const float *g, int64_t step, float lr,
+                float beta1, float beta2, float eps, uint16_t *w_bf16_out, cd_stream_t stream)
+{
+    if (!w || !m || !v || !g)
+        return fail(CD_E_INVALID, "NULL pointer");
+    if (step < 1)
+        return fail(CD_E_INVALID, "step must be >= 1");
+    if (!(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+        !(eps >= 0.0f) || !isfinite(lr) || !isfinite(eps))
+        return fail(CD_E_INVALID, "Adam hyper-parameters out of range");
+    CD_HIP(launch_mlp_adam(w, m, v, g, step, lr, beta1, beta2, eps, w_bf16_out,
+                           (hipStream_t)stream));
+    return CD_OK;
+}
+
+int cd_pair_object_counts(const cd_pair *pairs, int64_t count, int64_t n, uint32_t *counts_out,
+                          cd_stream_t stream)
+{
+    if (count < 0 || n < 0 || n >= (1ll << 31))
+        return fail(CD_E_INVALID, "count or n out of range");
+    if ((count > 0 && !pairs) || (n > 0 && !counts_out))
+        return fail(CD_E_INVALID, "NULL pointer");
+    if (n == 0)
+        return CD_OK;
+    CD_HIP(launch_pair_object_counts(pairs, (uint64_t)count, (uint32_t)n, counts_out,
+                                     (hipStream_t)stream));
+    return CD_OK;
+}
+
 } // extern "C"

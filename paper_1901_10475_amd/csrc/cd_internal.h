@@ -229,6 +229,34 @@ __host__ __device__ inline double from_ordered_bits(uint64_t u)
     return __builtin_bit_cast(double, u);
 }
 
+// Step from the bound vmax * dt <= max_disp: floor(max_disp / (vmax * tick)),
+// clamped to [1, max(T, 1)] ticks.
+__device__ inline uint32_t heuristic_step(double vmax, double tick_s, double max_disp,
+                                          uint32_t T)
+{
+    double d = floor(max_disp / (vmax * tick_s));
+    double cap = T > 0 ? (double)T : 1.0;
+    if (!(d >= 1.0))
+        d = 1.0;
+    if (d > cap)
+        d = cap;
+    return (uint32_t)d;
+}
+
+// Step network: 5 -> 64 -> 64 -> 1, parameters W1 [64][5], b1, W2 [64][64],
+// b2, w3, b3 in one flat vector.
+constexpr int kMlpIn = 5;
+constexpr int kMlpHid = 64;
+constexpr int kMlpW1 = 0;
+constexpr int kMlpB1 = kMlpW1 + kMlpHid * kMlpIn;
+constexpr int kMlpW2 = kMlpB1 + kMlpHid;
+constexpr int kMlpB2 = kMlpW2 + kMlpHid * kMlpHid;
+constexpr int kMlpW3 = kMlpB2 + kMlpHid;
+constexpr int kMlpB3 = kMlpW3 + kMlpHid;
+constexpr int kMlpParams = kMlpB3 + 1;   // 4609
+constexpr int kMlpOuterThreads = 256;
+constexpr int kMlpOuterSamples = 1024;   // samples per outer-product block
+
 // ---- launchers (each returns the launch status) -----------------------------
 
 // boxes
@@ -248,6 +276,21 @@ hipError_t launch_boxes_variable(const ObjConst *oc, const ObjSteps *st, uint32_
                                  hipStream_t s);
 
 // scans / sorts / fills
+// step network
+hipError_t launch_mlp_features(const cd_elements &el, double mu, float *x, hipStream_t s);
+hipError_t launch_dt_mlp(const cd_elements &el, const uint16_t *w, double mu, double tick_s,
+                         double fallback_disp, uint32_t T, uint32_t *dt, float *y,
+                         hipStream_t s);
+hipError_t launch_mlp_forward(const float *w, const float *x, uint32_t B, float *y,
+                              hipStream_t s);
+// act: [4 * 64 + 1][B] (h1, dz1, h2, dz2, dy), part: [blocks][kMlpParams + 1]
+hipError_t launch_mlp_grad(const float *w, const float *x, const float *target, uint32_t B,
+                           float *act, float *part, float *grad, float *loss, hipStream_t s);
+hipError_t launch_mlp_adam(float *w, float *m, float *v, const float *g, int64_t step,
+                           float lr, float beta1, float beta2, float eps, uint16_t *w_bf16,
+                           hipStream_t s);
+hipError_t launch_pair_object_counts(const cd_pair *pairs, uint64_t count, uint32_t n,
+                                     uint32_t *counts, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t count, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, size_t count,
                            hipStream_t s);

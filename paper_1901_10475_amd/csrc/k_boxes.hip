@@ -87,13 +87,7 @@ __global__ void k_dt_heuristic(cd_elements el, double mu, double tick_s, double 
         return;
     double a = el.a[i], e = el.e[i];
     double vmax = sqrt(mu * (1.0 + e) / (a * (1.0 - e)));
-    double d = floor(max_disp / (vmax * tick_s));
-    double cap = T > 0 ? (double)T : 1.0;
-    if (!(d >= 1.0))
-        d = 1.0;
-    if (d > cap)
-        d = cap;
-    dt_out[i] = (uint32_t)d;
+    dt_out[i] = heuristic_step(vmax, tick_s, max_disp, T);
 }
 
 // Newton on Kepler's equation E - e sin E = M from the guess in E.  Returns

@@ -98,3 +98,33 @@ def test_null_and_workspace_errors_before_any_launch():
     cnt = ctypes.c_int64(0)
     assert L.cd_query_pairs(ctypes.byref(tree), None, 0, ctypes.byref(cnt), None, 0,
                             None) == cd.CD_E_INVALID                 # tree not built
+
+
+def test_step_network_argument_errors_before_any_launch():
+    import paper_1901_10475_amd as cd
+    L = cd.lib()
+    p = cd.params_struct(1e-3, 398600.4418, 1.0, 600, 10)
+    el = cd.cd_elements(None, None, None, None, None, None, 5)     # n > 0, NULL arrays
+    assert L.cd_mlp_features(ctypes.byref(el), ctypes.byref(p), None, None) == cd.CD_E_INVALID
+    el0 = cd.cd_elements(None, None, None, None, None, None, 0)
+    assert L.cd_mlp_features(ctypes.byref(el0), ctypes.byref(p), None, None) == cd.CD_OK
+    assert L.cd_dt_mlp(ctypes.byref(el0), None, 0.0, ctypes.byref(p), None, None,
+                       None) == cd.CD_E_INVALID                      # fallback <= 0
+    assert L.cd_dt_mlp(ctypes.byref(el0), None, 5.0, ctypes.byref(p), None, None,
+                       None) == cd.CD_OK                             # n = 0: nothing to do
+    fake = ctypes.c_void_p(16)                                       # never dereferenced
+    assert L.cd_mlp_forward(fake, fake, -1, fake, None) == cd.CD_E_INVALID
+    assert L.cd_mlp_forward(None, None, 0, None, None) == cd.CD_OK
+    assert L.cd_mlp_grad(fake, fake, fake, 0, fake, None, fake, 1 << 30,
+                         None) == cd.CD_E_INVALID                    # empty batch
+    assert L.cd_mlp_grad(fake, fake, fake, 10, fake, None, fake, 16,
+                         None) == cd.CD_E_WORKSPACE
+    assert L.cd_mlp_adam(fake, fake, fake, fake, 0, 1e-3, 0.9, 0.999, 1e-8, None,
+                         None) == cd.CD_E_INVALID                    # step counts from 1
+    assert L.cd_mlp_adam(fake, fake, fake, fake, 1, 1e-3, 1.0, 0.999, 1e-8, None,
+                         None) == cd.CD_E_INVALID                    # beta1 = 1
+    assert L.cd_pair_object_counts(None, 3, 5, fake, None) == cd.CD_E_INVALID
+    assert L.cd_pair_object_counts(None, 0, 0, None, None) == cd.CD_OK
+    # workspace grows with the batch: activations + one partial row per 1024 samples
+    w1, w2 = L.cd_mlp_grad_ws(1), L.cd_mlp_grad_ws(5000)
+    assert w2 >= 258 * 4 * 5000 + 5 * 4610 * 4 > w1 > 0
