@@ -208,6 +208,58 @@ size_t cd_query_pairs_ws(int64_t count, int64_t capacity);
 int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t *count_host,
                    void *ws, size_t ws_bytes, cd_stream_t stream);
 
+/* Graph-capturable form of cd_query_pairs: the same records in the same
+ * order, with no host synchronisation and no host reads, so the call can be
+ * recorded into a hipGraph (cd_graph_*) and replayed.  Results stay on the
+ * device:
+ *   *count_dev  (uint64): records written to out; when status bit 1 is set,
+ *                         the number of raw records found instead (an upper
+ *                         bound of what a repeat with more capacity needs);
+ *   *status_dev (uint32): 0, or bit 1 = capacity exceeded (out incomplete),
+ *                         bit 2 = tree inconsistent (as CD_E_INVALID above).
+ * The node-pair traversal runs for the tuning's max_levels levels, each
+ * level ending at once when the previous queue is empty; if its queue
+ * overflows or is not drained by then, the per-leaf walk redoes the
+ * traversal, decided on the device.  The canonical sort runs over all
+ * `capacity` slots (unused slots hold a filler record that sorts last), so
+ * its cost follows the capacity, not the count.  Workspace as for
+ * cd_query_pairs.  Returns CD_OK once everything is enqueued. */
+int cd_query_pairs_async(const cd_tree *tree, cd_pair *out, int64_t capacity,
+                         unsigned long long *count_dev, unsigned int *status_dev, void *ws,
+                         size_t ws_bytes, cd_stream_t stream);
+
+/* ---- launch shapes of the traversal -------------------------------------- */
+
+/* Process-wide launch shapes, read by every later query call (a captured
+ * graph keeps the shapes in force at capture time).  Zero fields take the
+ * defaults in brackets. */
+typedef struct {
+    uint32_t expand_blocks;   /* workgroups per node-pair level, 64..65536 [2048] */
+    uint32_t expand_threads;  /* lanes per node-pair workgroup: 64, 128 or 256 [256] */
+    uint32_t walk_threads;    /* lanes per per-leaf-walk workgroup: 64, 128 or 256 [256] */
+    uint32_t mode;            /* 0 = node pairs, per-leaf walk as fallback; 1 = per-leaf
+                                 walk only [0] */
+    uint32_t max_levels;      /* node-pair levels of cd_query_pairs_async, 1..400 [96] */
+} cd_tuning;
+
+/* NULL restores the defaults; out-of-range fields give CD_E_INVALID and
+ * change nothing. */
+int cd_set_tuning(const cd_tuning *t);
+int cd_get_tuning(cd_tuning *t);
+
+/* ---- graphs ------------------------------------------------------------- */
+
+/* Record the work the calling thread enqueues on `stream` (any of the calls
+ * above except those that synchronise: cd_box_count, cd_validate_elements,
+ * cd_query_pairs) and replay it with one launch.  The stream must not be the
+ * legacy default stream.  Buffers named by the recorded calls must stay
+ * allocated while the graph exists; a replay rereads their current contents. */
+typedef struct cd_graph_s *cd_graph;
+int cd_graph_begin(cd_stream_t stream);
+int cd_graph_end(cd_stream_t stream, cd_graph *graph_out);
+int cd_graph_launch(cd_graph graph, cd_stream_t stream);
+int cd_graph_destroy(cd_graph graph);
+
 /* ---- learned per-object step ------------------------------------------- */
 
 /* The paper keeps a time interval per object so that objects far from all

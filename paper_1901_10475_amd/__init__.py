@@ -48,6 +48,12 @@ class cd_tree(ctypes.Structure):
                 ("horizon_ticks", ctypes.c_uint32), ("obj_count", ctypes.c_uint32)]
 
 
+class cd_tuning(ctypes.Structure):
+    _fields_ = [("expand_blocks", ctypes.c_uint32), ("expand_threads", ctypes.c_uint32),
+                ("walk_threads", ctypes.c_uint32), ("mode", ctypes.c_uint32),
+                ("max_levels", ctypes.c_uint32)]
+
+
 class CDError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{_status_name(status)} ({status}): {message}")
@@ -94,6 +100,14 @@ def lib():
                                              sz, _vp]),
             "cd_query_pairs_ws": (sz, [i64, i64]),
             "cd_query_pairs": (ctypes.c_int, [P(cd_tree), _vp, i64, P(i64), _vp, sz, _vp]),
+            "cd_query_pairs_async": (ctypes.c_int, [P(cd_tree), _vp, i64, _vp, _vp, _vp, sz,
+                                                    _vp]),
+            "cd_set_tuning": (ctypes.c_int, [P(cd_tuning)]),
+            "cd_get_tuning": (ctypes.c_int, [P(cd_tuning)]),
+            "cd_graph_begin": (ctypes.c_int, [_vp]),
+            "cd_graph_end": (ctypes.c_int, [_vp, P(_vp)]),
+            "cd_graph_launch": (ctypes.c_int, [_vp, _vp]),
+            "cd_graph_destroy": (ctypes.c_int, [_vp]),
             "cd_mlp_features": (ctypes.c_int, [P(cd_elements), P(cd_params), _vp, _vp]),
             "cd_dt_mlp": (ctypes.c_int, [P(cd_elements), _vp, dbl, P(cd_params), _vp, _vp,
                                          _vp]),
@@ -116,7 +130,9 @@ EXPORTED = ("cd_status_string", "cd_last_error", "cd_version", "cd_profile_enabl
             "cd_profile_read", "cd_box_count_ws",
             "cd_box_count", "cd_validate_ws", "cd_validate_elements", "cd_dt_heuristic",
             "cd_build_boxes_ws", "cd_build_boxes", "cd_tree_bytes", "cd_build_tree_ws",
-            "cd_build_tree", "cd_query_pairs_ws", "cd_query_pairs", "cd_mlp_features",
+            "cd_build_tree", "cd_query_pairs_ws", "cd_query_pairs", "cd_query_pairs_async",
+            "cd_set_tuning", "cd_get_tuning", "cd_graph_begin", "cd_graph_end",
+            "cd_graph_launch", "cd_graph_destroy", "cd_mlp_features",
             "cd_dt_mlp", "cd_mlp_forward", "cd_mlp_grad_ws", "cd_mlp_grad", "cd_mlp_adam",
             "cd_pair_object_counts")
 
@@ -287,6 +303,63 @@ def cd_query_pairs(tree, out, capacity, ws):
     if rc not in (CD_OK, CD_E_CAPACITY):
         _check(rc)
     return rc, cnt.value
+
+
+def cd_query_pairs_async(tree, out, capacity, count_dev, status_dev, ws):
+    """Enqueue the graph-capturable query; count_dev (int64 [1]) and
+    status_dev (int32 [1]) are CUDA tensors written by the device."""
+    if capacity < 1 or out.shape[0] < capacity:
+        raise ValueError("out must hold `capacity` records")
+    _check(lib().cd_query_pairs_async(ctypes.byref(tree.desc), _ptr(out), int(capacity),
+                                      _ptr(count_dev), _ptr(status_dev), _ptr(ws), ws.numel(),
+                                      _stream()))
+
+
+TUNING_DEFAULTS = {"expand_blocks": 2048, "expand_threads": 256, "walk_threads": 256,
+                   "mode": 0, "max_levels": 96}
+
+
+def cd_set_tuning(t=None):
+    """t: dict of cd_tuning fields (missing or 0 -> default), or None for defaults."""
+    if t is None:
+        _check(lib().cd_set_tuning(None))
+        return
+    v = cd_tuning(*(int(t.get(k, 0)) for k, _ in cd_tuning._fields_))
+    _check(lib().cd_set_tuning(ctypes.byref(v)))
+
+
+def cd_get_tuning():
+    v = cd_tuning()
+    _check(lib().cd_get_tuning(ctypes.byref(v)))
+    return {k: int(getattr(v, k)) for k, _ in cd_tuning._fields_}
+
+
+class Graph:
+    """Work recorded from the current stream between begin() and end(),
+    replayed by launch() (cd_graph_*)."""
+
+    def __init__(self):
+        self.h = ctypes.c_void_p(0)
+
+    def begin(self):
+        _check(lib().cd_graph_begin(_stream()))
+
+    def end(self):
+        _check(lib().cd_graph_end(_stream(), ctypes.byref(self.h)))
+
+    def launch(self):
+        _check(lib().cd_graph_launch(self.h, _stream()))
+
+    def close(self):
+        if self.h:
+            lib().cd_graph_destroy(self.h)
+            self.h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class BroadPhase:

@@ -1,0 +1,198 @@
+"""Many independent scenarios in one graph launch.
+
+The paper notes that sub-problems of the collision search are independent
+(Sec. Decomposition of the AABB Tree State Space), which makes batching them
+natural.  ``BatchRunner`` runs the whole path (boxes, tree, canonical pairs)
+for every scenario of a batch, one after another on one stream, and records
+that sequence once into a hipGraph (``cd_graph_*``); a replay is one launch
+for the whole batch, with no host synchronisation inside it.
+
+The scenarios run in order and share one set of box, tree and workspace
+buffers sized for the largest; each keeps its own output list, record count
+and status word on the device.  Output capacities come from one eager pass
+(``calibrate``); a replay whose status reports exceeded capacity is repeated
+eagerly for that scenario by ``results``.  Launch shapes can differ per
+scenario (``tunings``): they are read while the graph is recorded.
+"""
+import ctypes
+import math
+
+import numpy as np
+import torch
+
+from . import (CD_E_CAPACITY, CD_FP64, CD_OK, Graph, _bytes, _check, _ptr, _stream,
+               cd_boxes, cd_build_boxes, cd_get_tuning, cd_query_pairs, cd_query_pairs_async,
+               cd_set_tuning, cd_tree, lib, params_struct, soa)
+
+
+class _Boxes:
+    """Descriptor over shared box arrays for one scenario's count."""
+
+    def __init__(self, arrays, count, precision):
+        self.desc = cd_boxes()
+        self.desc.count = int(count)
+        self.desc.precision = precision
+        lo, hi, t0, t1, obj = arrays
+        for d in range(3):
+            self.desc.lo[d] = lo[d].data_ptr()
+            self.desc.hi[d] = hi[d].data_ptr()
+        self.desc.t0 = t0.data_ptr()
+        self.desc.t1 = t1.data_ptr()
+        self.desc.obj = obj.data_ptr()
+
+
+class _Tree:
+    def __init__(self, mem, count, precision):
+        self.desc = cd_tree()
+        self.desc.mem = mem.data_ptr()
+        self.desc.bytes = lib().cd_tree_bytes(int(count), precision)
+
+
+class BatchRunner:
+    def __init__(self, scenarios, box_precision=CD_FP64, tree_precision=CD_FP64,
+                 margin=1.25, min_capacity=4096, device="cuda"):
+        self.sc = list(scenarios)
+        self.box_precision, self.tree_precision = box_precision, tree_precision
+        self.margin, self.min_capacity = margin, min_capacity
+        self.device = device
+        self.el = [soa(s.elements, device) for s in self.sc]
+        self.params = []
+        self.counts = []
+        for s in self.sc:
+            if not s.uniform_dt:
+                raise ValueError("batched scenarios take a uniform step")
+            p = params_struct(s.tick_s, s.mu, s.threshold_km, s.horizon_ticks, s.dt_ticks)
+            self.params.append(p)
+            K = 1 if s.horizon_ticks == 0 else -(-s.horizon_ticks // int(s.dt_ticks))
+            self.counts.append(s.n * K)
+        Nmax = max(self.counts)
+        ft = torch.float64 if box_precision == CD_FP64 else torch.float32
+        self.arrays = (torch.empty((3, Nmax), dtype=ft, device=device),
+                       torch.empty((3, Nmax), dtype=ft, device=device),
+                       torch.empty(Nmax, dtype=torch.int32, device=device),
+                       torch.empty(Nmax, dtype=torch.int32, device=device),
+                       torch.empty(Nmax, dtype=torch.int32, device=device))
+        self.tree_mem = _bytes(lib().cd_tree_bytes(Nmax, tree_precision), device)
+        self.ws_boxes = _bytes(max(lib().cd_build_boxes_ws(s.n) for s in self.sc), device)
+        self.ws_tree = _bytes(lib().cd_build_tree_ws(Nmax), device)
+        self.boxes = [_Boxes(self.arrays, N, box_precision) for N in self.counts]
+        self.trees = [_Tree(self.tree_mem, N, tree_precision) for N in self.counts]
+        S = len(self.sc)
+        self.count_dev = torch.zeros(S, dtype=torch.int64, device=device)
+        self.status_dev = torch.zeros(S, dtype=torch.int32, device=device)
+        self.capacity = [0] * S
+        self.out = [None] * S
+        self.ws_query = None
+        self.graph = None
+        self.stream = torch.cuda.Stream(device=device)
+        self.tunings = [None] * S
+
+    # -- one scenario, eager ------------------------------------------------------
+    def _build(self, k):
+        b = self.boxes[k]
+        cd_build_boxes(self.el[k], None, self.params[k], b, self.ws_boxes)
+        _check(lib().cd_build_tree(ctypes.byref(b.desc), self.tree_precision, 0,
+                                   ctypes.byref(self.trees[k].desc), _ptr(self.ws_tree),
+                                   self.ws_tree.numel(), _stream()))
+
+    def run_eager(self, k):
+        """Pairs of scenario k by the synchronising query (int32 [P, 4])."""
+        self._build(k)
+        cap = max(self.capacity[k], self.min_capacity)
+        while True:
+            out = torch.empty((cap, 4), dtype=torch.int32, device=self.device)
+            ws = _bytes(lib().cd_query_pairs_ws(self.counts[k], cap), self.device)
+            rc, cnt = cd_query_pairs(self.trees[k], out, cap, ws)
+            if rc == CD_OK:
+                return out[:cnt]
+            cap = int(cnt * self.margin) + 1024
+
+    def calibrate(self):
+        """One eager pass: sets every scenario's output capacity."""
+        with torch.cuda.stream(self.stream):
+            for k in range(len(self.sc)):
+                self._apply_tuning(k)
+                P = int(self.run_eager(k).shape[0])
+                self.capacity[k] = max(self.min_capacity, int(math.ceil(P * self.margin)))
+        self.stream.synchronize()
+        self._alloc_outputs()
+
+    def _alloc_outputs(self):
+        self.out = [torch.empty((c, 4), dtype=torch.int32, device=self.device)
+                    for c in self.capacity]
+        Nmax, cmax = max(self.counts), max(self.capacity)
+        self.ws_query = _bytes(lib().cd_query_pairs_ws(Nmax, cmax), self.device)
+
+    def _apply_tuning(self, k):
+        cd_set_tuning(self.tunings[k])
+
+    # -- the batch as one graph -------------------------------------------------------
+    def enqueue(self):
+        """Enqueue the whole batch (boxes, tree, device-count query per scenario)."""
+        saved = cd_get_tuning()
+        try:
+            for k in range(len(self.sc)):
+                self._apply_tuning(k)
+                self._build(k)
+                cd_query_pairs_async(self.trees[k], self.out[k], self.capacity[k],
+                                     self.count_dev[k:k + 1], self.status_dev[k:k + 1],
+                                     self.ws_query)
+        finally:
+            cd_set_tuning(saved)
+
+    def capture(self):
+        if self.ws_query is None:
+            self.calibrate()
+        elif any(o.shape[0] < c for o, c in zip(self.out, self.capacity)):
+            self._alloc_outputs()
+        self.close()
+        g = Graph()
+        self.stream.synchronize()
+        with torch.cuda.stream(self.stream):
+            g.begin()
+            try:
+                self.enqueue()
+            finally:
+                g.end()
+        self.graph = g
+
+    def replay(self):
+        with torch.cuda.stream(self.stream):
+            self.graph.launch()
+
+    def results(self):
+        """Wait for the last replay; per-scenario pair tensors (int32 [P, 4]).
+        A scenario whose capacity was exceeded is rerun eagerly (and its
+        capacity raised for the next capture)."""
+        self.stream.synchronize()
+        cnt = self.count_dev.cpu().numpy()
+        st = self.status_dev.cpu().numpy()
+        res = []
+        for k in range(len(self.sc)):
+            if st[k] & 2:
+                raise RuntimeError(f"scenario {k}: tree inconsistent (status {st[k]})")
+            if st[k] & 1:
+                self.capacity[k] = int(cnt[k] * self.margin) + 1024
+                with torch.cuda.stream(self.stream):
+                    res.append(self.run_eager(k))
+                self.stream.synchronize()
+            else:
+                res.append(self.out[k][:int(cnt[k])])
+        return res
+
+    def close(self):
+        if self.graph is not None:
+            self.graph.close()
+            self.graph = None
+
+    def boxes_total(self):
+        return int(sum(self.counts))
+
+    def brute_force_tests(self):
+        """Box pairs of different objects whose tags overlap (uniform step:
+        K * C(n, 2) per scenario)."""
+        tot = 0
+        for s, N in zip(self.sc, self.counts):
+            K = N // s.n
+            tot += K * s.n * (s.n - 1) // 2
+        return tot

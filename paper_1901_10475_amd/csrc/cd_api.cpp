@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "cd_internal.h"
@@ -71,6 +72,9 @@ struct Stage {
         std::lock_guard<std::mutex> g(g_prof_mu);
         if (!g_prof_on)
             return;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+            return;   // no timing inside a graph
         a = prof_event();
         if (a && hipEventRecord(a, s) != hipSuccess) {
             g_prof_pool.push_back(a);
@@ -92,6 +96,16 @@ struct Stage {
         }
     }
 };
+
+// ---- launch shapes (cd_set_tuning) ----
+std::mutex g_tune_mu;
+cd_tuning g_tune = {2048, 256, 256, 0, 96};
+
+cd_tuning tuning()
+{
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    return g_tune;
+}
 
 constexpr int64_t kMaxBoxes = (1ll << 30) - 1;  // node ids of 2N - 1 nodes below 2^31
 constexpr size_t kTreeHeader = sizeof(TreeHeader);
@@ -226,6 +240,25 @@ struct QueryWS {
     unsigned int *qcount, *qflags;
     uint32_t qcap;
 };
+// Radix passes of the canonical order (i, j, t_lo, t_hi), least significant
+// field first, over the bits each field can use.
+DigitPlan record_plan(const cd_tree *tree)
+{
+    int tb = bits_for((uint64_t)tree->horizon_ticks + 1);
+    int ob = tree->obj_count ? bits_for((uint64_t)tree->obj_count - 1) : 32;
+    DigitPlan plan;
+    memset(&plan, 0, sizeof plan);
+    const int fields[4] = {3, 2, 1, 0};  // t_hi, t_lo, j, i
+    const int widths[4] = {tb, tb, ob, ob};
+    for (int f = 0; f < 4; ++f)
+        for (int sh = 0; sh < widths[f]; sh += 8) {
+            plan.field[plan.npass] = (uint8_t)fields[f];
+            plan.shift[plan.npass] = (uint8_t)sh;
+            ++plan.npass;
+        }
+    return plan;
+}
+
 uint32_t queue_cap(int64_t N) { return (uint32_t)(N / 4 > 65536 ? N / 4 : 65536); }
 size_t layout_query(void *base, size_t bytes, int64_t N, int64_t cap, QueryWS *w)
 {
@@ -646,13 +679,14 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
     unsigned long long cnt = 0;
     unsigned int e = 0;
     bool done = false;
+    const cd_tuning tu = tuning();
     {
         Stage st("traverse", s);
         // node-pair traversal from the refit's overlapping sibling pairs
         unsigned int h[3] = {0, 0, 0};
         CD_HIP(hipMemcpyAsync(h, hdr, sizeof h, hipMemcpyDeviceToHost, s));
         CD_HIP(hipStreamSynchronize(s));
-        if (h[0] == 0 && h[2] == 0 && N > 1) {
+        if (h[0] == 0 && h[2] == 0 && N > 1 && tu.mode == 0) {
             CD_HIP(launch_fill_u64(w.counter, 0ull, 1, s));
             CD_HIP(launch_fill_u32(w.qcount, 0u, kExpandMaxLevels + 2, s));
             CD_HIP(launch_fill_u32(w.qflags, 0u, 1, s));
@@ -665,7 +699,8 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
                 CD_HIP(launch_expand(nodes, kids, tree->precision, (uint32_t)N, in, n_in, in_cap,
                                      outq,
                                      w.qcount + lev + 1, w.qcap, w.raw,
-                                     (unsigned long long)capacity, w.counter, w.qflags, s));
+                                     (unsigned long long)capacity, w.counter, w.qflags, 0,
+                                     tu.expand_blocks, tu.expand_threads, s));
                 in = outq;
                 n_in = w.qcount + lev + 1;
                 in_cap = w.qcap;
@@ -684,7 +719,8 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
             // bounded fallback: one stackless walk per leaf
             CD_HIP(launch_fill_u64(w.counter, 0ull, 1, s));
             CD_HIP(launch_traverse(nodes, tree->precision, (uint32_t)N, tree->slab_ticks, w.raw,
-                                   (unsigned long long)capacity, w.counter, err, s));
+                                   (unsigned long long)capacity, w.counter, err, nullptr,
+                                   tu.walk_threads, s));
         }
     }
     CD_HIP(hipMemcpyAsync(&cnt, w.counter, sizeof cnt, hipMemcpyDeviceToHost, s));
@@ -700,18 +736,7 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
     if (cnt == 0)
         return CD_OK;
     uint32_t count = (uint32_t)cnt;
-    int tb = bits_for((uint64_t)tree->horizon_ticks + 1);
-    int ob = tree->obj_count ? bits_for((uint64_t)tree->obj_count - 1) : 32;
-    DigitPlan plan;
-    memset(&plan, 0, sizeof plan);
-    const int fields[4] = {3, 2, 1, 0};  // least significant first: t_hi, t_lo, j, i
-    const int widths[4] = {tb, tb, ob, ob};
-    for (int f = 0; f < 4; ++f)
-        for (int sh = 0; sh < widths[f]; sh += 8) {
-            plan.field[plan.npass] = (uint8_t)fields[f];
-            plan.shift[plan.npass] = (uint8_t)sh;
-            ++plan.npass;
-        }
+    DigitPlan plan = record_plan(tree);
     void *res = nullptr;
     {
         Stage st("canon", s);
@@ -722,6 +747,164 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
     CD_HIP(hipMemcpyAsync(&uniq, w.pos + count, sizeof uniq, hipMemcpyDeviceToHost, s));
     CD_HIP(hipStreamSynchronize(s));
     *count_host = uniq;
+    return CD_OK;
+}
+
+int cd_query_pairs_async(const cd_tree *tree, cd_pair *out, int64_t capacity,
+                         unsigned long long *count_dev, unsigned int *status_dev, void *ws,
+                         size_t ws_bytes, cd_stream_t stream)
+{
+    if (!tree || !count_dev || !status_dev)
+        return fail(CD_E_INVALID, "tree, count_dev or status_dev is NULL");
+    if (!tree->mem || tree->count < 0)
+        return fail(CD_E_INVALID, "tree is not built");
+    if (tree->bytes < cd_tree_bytes(tree->count, tree->precision))
+        return fail(CD_E_INVALID, "tree buffer smaller than its node count needs");
+    if (capacity < 1 || capacity > 0xFFFFFFFEll)
+        return fail(CD_E_INVALID, "capacity must be in [1, 2^32 - 2]");
+    if (!out)
+        return fail(CD_E_INVALID, "out is NULL");
+    if (!ws || ws_bytes < cd_query_pairs_ws(tree->count, capacity))
+        return fail(CD_E_WORKSPACE, "query workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    int64_t N = tree->count;
+    unsigned int *err = (unsigned int *)tree->mem;
+    const void *nodes = (const char *)tree->mem + kTreeHeader;
+    QueryWS w;
+    layout_query(ws, ws_bytes, N, capacity, &w);
+    const TreeHeader *hdr = (const TreeHeader *)tree->mem;
+    const uint2 *seeds =
+        (const uint2 *)((const char *)tree->mem + tree_seeds_offset((uint64_t)N, tree->precision));
+    const uint2 *kids =
+        (const uint2 *)((const char *)tree->mem + tree_kids_offset((uint64_t)N, tree->precision));
+    const cd_tuning tu = tuning();
+    const uint32_t cap = (uint32_t)capacity;
+    // qcount[kExpandMaxLevels + 1] doubles as the per-leaf-walk flag
+    unsigned int *walk = w.qcount + kExpandMaxLevels + 1;
+    CD_HIP(launch_fill_u64(w.counter, 0ull, 1, s));
+    {
+        Stage st("traverse", s);
+        CD_HIP(launch_fill_u32(w.qcount, 0u, kExpandMaxLevels + 2, s));
+        CD_HIP(launch_fill_u32(w.qflags, tu.mode == 0 ? 0u : 4u, 1, s));
+        if (N > 1) {
+            CD_HIP(launch_query_begin(hdr, w.qflags, s));
+            const uint2 *in = seeds;
+            const unsigned int *n_in = &hdr->nseeds;
+            uint32_t in_cap = (uint32_t)seed_cap((uint64_t)N);
+            uint32_t levels = tu.mode == 0 ? tu.max_levels : 0;
+            for (uint32_t lev = 0; lev < levels; ++lev) {
+                uint2 *outq = (lev & 1) ? w.qb : w.qa;
+                CD_HIP(launch_expand(nodes, kids, tree->precision, (uint32_t)N, in, n_in, in_cap,
+                                     outq, w.qcount + lev + 1, w.qcap, w.raw, cap, w.counter,
+                                     w.qflags, 1, tu.expand_blocks, tu.expand_threads, s));
+                in = outq;
+                n_in = w.qcount + lev + 1;
+                in_cap = w.qcap;
+            }
+            CD_HIP(launch_query_decide(n_in, w.qflags, w.counter, walk, s));
+            CD_HIP(launch_traverse(nodes, tree->precision, (uint32_t)N, tree->slab_ticks, w.raw,
+                                   cap, w.counter, err, walk, tu.walk_threads, s));
+        }
+    }
+    {
+        Stage st("canon", s);
+        CD_HIP(launch_pad_records(w.raw, w.counter, cap, s));
+        DigitPlan plan = record_plan(tree);
+        void *res = nullptr;
+        CD_HIP(radix_sort16(SORT_REC, w.raw, w.alt, cap, plan, w.radix, &res, s));
+        CD_HIP(launch_unique((const Rec *)res, cap, w.flags, w.pos, w.scan, (Rec *)out, s));
+        CD_HIP(launch_query_finish(w.counter, err, w.pos + cap, cap, count_dev, status_dev, s));
+    }
+    return CD_OK;
+}
+
+int cd_set_tuning(const cd_tuning *t)
+{
+    cd_tuning v = {2048, 256, 256, 0, 96};
+    if (t) {
+        auto lanes_ok = [](uint32_t x) { return x == 0 || x == 64 || x == 128 || x == 256; };
+        if ((t->expand_blocks && (t->expand_blocks < 64 || t->expand_blocks > 65536)) ||
+            !lanes_ok(t->expand_threads) || !lanes_ok(t->walk_threads) || t->mode > 1 ||
+            t->max_levels > (uint32_t)kExpandMaxLevels)
+            return fail(CD_E_INVALID, "tuning field out of range");
+        if (t->expand_blocks)
+            v.expand_blocks = t->expand_blocks;
+        if (t->expand_threads)
+            v.expand_threads = t->expand_threads;
+        if (t->walk_threads)
+            v.walk_threads = t->walk_threads;
+        v.mode = t->mode;
+        if (t->max_levels)
+            v.max_levels = t->max_levels;
+    }
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune = v;
+    return CD_OK;
+}
+
+int cd_get_tuning(cd_tuning *t)
+{
+    if (!t)
+        return fail(CD_E_INVALID, "t is NULL");
+    *t = tuning();
+    return CD_OK;
+}
+
+struct cd_graph_s {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+int cd_graph_begin(cd_stream_t stream)
+{
+    if (!stream)
+        return fail(CD_E_INVALID, "the legacy default stream cannot be captured");
+    CD_HIP(hipStreamBeginCapture((hipStream_t)stream, hipStreamCaptureModeThreadLocal));
+    return CD_OK;
+}
+
+int cd_graph_end(cd_stream_t stream, cd_graph *graph_out)
+{
+    if (!stream || !graph_out)
+        return fail(CD_E_INVALID, "stream or graph_out is NULL");
+    *graph_out = nullptr;
+    hipGraph_t g = nullptr;
+    CD_HIP(hipStreamEndCapture((hipStream_t)stream, &g));
+    hipGraphExec_t x = nullptr;
+    hipError_t e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        hipGraphDestroy(g);
+        return fail(CD_E_DEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    }
+    cd_graph h = new (std::nothrow) cd_graph_s;
+    if (!h) {
+        hipGraphExecDestroy(x);
+        hipGraphDestroy(g);
+        return fail(CD_E_DEVICE, "out of host memory");
+    }
+    h->graph = g;
+    h->exec = x;
+    *graph_out = h;
+    return CD_OK;
+}
+
+int cd_graph_launch(cd_graph graph, cd_stream_t stream)
+{
+    if (!graph)
+        return fail(CD_E_INVALID, "graph is NULL");
+    CD_HIP(hipGraphLaunch(graph->exec, (hipStream_t)stream));
+    return CD_OK;
+}
+
+int cd_graph_destroy(cd_graph graph)
+{
+    if (!graph)
+        return CD_OK;
+    hipError_t a = hipGraphExecDestroy(graph->exec);
+    hipError_t b = hipGraphDestroy(graph->graph);
+    delete graph;
+    if (a != hipSuccess || b != hipSuccess)
+        return fail(CD_E_DEVICE, "graph destroy failed");
     return CD_OK;
 }
 

@@ -432,17 +432,26 @@ __device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb)
 // query
 hipError_t launch_traverse(const void *tree, int precision, uint32_t N, uint32_t slab_ticks,
                            Rec *out, unsigned long long capacity, unsigned long long *counter,
-                           unsigned int *err, hipStream_t s);
+                           unsigned int *err, const unsigned int *run_if, uint32_t threads,
+                           hipStream_t s);
 // One breadth-first level of the node-pair self-traversal: every pair in
 // `in` (count *n_in, at most in_cap) is expanded into the overlapping pairs of
 // its children; pairs of two leaves are emitted as records, the others queued
 // in `outq` (count *n_out, capacity out_cap; bit 0 of *flags on overflow).
 hipError_t launch_expand(const void *tree, const uint2 *kids, int precision, uint32_t N,
-                         const uint2 *in,
-                         const unsigned int *n_in, uint32_t in_cap, uint2 *outq,
+                         const uint2 *in, const unsigned int *n_in, uint32_t in_cap, uint2 *outq,
                          unsigned int *n_out, uint32_t out_cap, Rec *out,
                          unsigned long long capacity, unsigned long long *counter,
-                         unsigned int *flags, hipStream_t s);
+                         unsigned int *flags, int gated, uint32_t blocks, uint32_t threads,
+                         hipStream_t s);
+hipError_t launch_query_begin(const TreeHeader *hdr, unsigned int *qflags, hipStream_t s);
+hipError_t launch_query_decide(const unsigned int *last_count, const unsigned int *qflags,
+                               unsigned long long *counter, unsigned int *walk, hipStream_t s);
+hipError_t launch_pad_records(Rec *raw, const unsigned long long *counter, uint32_t cap,
+                              hipStream_t s);
+hipError_t launch_query_finish(const unsigned long long *counter, const unsigned int *tree_err,
+                               const uint32_t *uniq, uint32_t cap, unsigned long long *count_out,
+                               unsigned int *status_out, hipStream_t s);
 hipError_t launch_unique(const Rec *in, uint32_t count, uint32_t *flags, uint32_t *pos,
                          void *scan_ws, Rec *out, hipStream_t s);
 

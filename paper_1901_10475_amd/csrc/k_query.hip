@@ -78,9 +78,11 @@ __global__ __launch_bounds__(256) void k_traverse(const void *__restrict__ tree,
                                                   uint32_t slab_ticks, Rec *__restrict__ out,
                                                   unsigned long long capacity,
                                                   unsigned long long *counter,
-                                                  unsigned int *err)
+                                                  unsigned int *err, const unsigned int *run_if)
 {
     using F = typename Q<TP>::F;
+    if (run_if && *run_if == 0)
+        return;
     uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     uint32_t i = blk * blockDim.x + threadIdx.x;
     if (i >= N)
@@ -130,15 +132,18 @@ __global__ __launch_bounds__(256) void k_traverse(const void *__restrict__ tree,
 
 hipError_t launch_traverse(const void *tree, int precision, uint32_t N, uint32_t slab_ticks,
                            Rec *out, unsigned long long capacity, unsigned long long *counter,
-                           unsigned int *err, hipStream_t s)
+                           unsigned int *err, const unsigned int *run_if, uint32_t threads,
+                           hipStream_t s)
 {
     if (N <= 1)
         return hipSuccess;
-    unsigned g = nblk(N, 256);
+    unsigned g = nblk(N, threads);
     if (precision == CD_FP64)
-        k_traverse<CD_FP64><<<g, 256, 0, s>>>(tree, N, slab_ticks, out, capacity, counter, err);
+        k_traverse<CD_FP64><<<g, threads, 0, s>>>(tree, N, slab_ticks, out, capacity, counter,
+                                                  err, run_if);
     else
-        k_traverse<CD_FP32><<<g, 256, 0, s>>>(tree, N, slab_ticks, out, capacity, counter, err);
+        k_traverse<CD_FP32><<<g, threads, 0, s>>>(tree, N, slab_ticks, out, capacity, counter,
+                                                  err, run_if);
     return hipGetLastError();
 }
 
@@ -190,12 +195,17 @@ __global__ __launch_bounds__(256) void k_expand(const void *__restrict__ tree,
                                                 uint2 *__restrict__ outq, unsigned int *n_out,
                                                 uint32_t out_cap, Rec *__restrict__ out,
                                                 unsigned long long capacity,
-                                                unsigned long long *counter, unsigned int *flags)
+                                                unsigned long long *counter, unsigned int *flags,
+                                                int gated)
 {
     using F = typename Q<TP>::F;
     __shared__ uint32_t wsum[64];
     __shared__ unsigned int qbase;
     __shared__ unsigned long long rbase;
+    // gated: a set flag (queue overflow, bad node, or the traversal handed to
+    // the per-leaf walk) ends the node-pair levels
+    if (gated && *flags)
+        return;
     uint32_t n = *n_in;
     n = n < in_cap ? n : in_cap;
     // block-uniform loop: the block scan below needs every thread
@@ -270,17 +280,105 @@ hipError_t launch_expand(const void *tree, const uint2 *kids, int precision, uin
                          const uint2 *in, const unsigned int *n_in, uint32_t in_cap, uint2 *outq,
                          unsigned int *n_out, uint32_t out_cap, Rec *out,
                          unsigned long long capacity, unsigned long long *counter,
-                         unsigned int *flags, hipStream_t s)
+                         unsigned int *flags, int gated, uint32_t blocks, uint32_t threads,
+                         hipStream_t s)
 {
     if (N <= 1)
         return hipSuccess;
-    unsigned g = 2048;
     if (precision == CD_FP64)
-        k_expand<CD_FP64><<<g, 256, 0, s>>>(tree, kids, N, in, n_in, in_cap, outq, n_out, out_cap,
-                                            out, capacity, counter, flags);
+        k_expand<CD_FP64><<<blocks, threads, 0, s>>>(tree, kids, N, in, n_in, in_cap, outq, n_out,
+                                                     out_cap, out, capacity, counter, flags,
+                                                     gated);
     else
-        k_expand<CD_FP32><<<g, 256, 0, s>>>(tree, kids, N, in, n_in, in_cap, outq, n_out, out_cap,
-                                            out, capacity, counter, flags);
+        k_expand<CD_FP32><<<blocks, threads, 0, s>>>(tree, kids, N, in, n_in, in_cap, outq, n_out,
+                                                     out_cap, out, capacity, counter, flags,
+                                                     gated);
+    return hipGetLastError();
+}
+
+// ---- device-side control of the query (no host reads) -----------------------------------------
+
+// Before the node-pair levels: a build error or lost seeds hand the whole
+// traversal to the per-leaf walk.
+__global__ void k_query_begin(const TreeHeader *hdr, unsigned int *qflags)
+{
+    if (hdr->err || hdr->seed_overflow)
+        atomicOr(qflags, 4u);
+}
+
+// After the last level: the per-leaf walk runs (from a cleared counter) if
+// any flag is set or the last queue is not empty.
+__global__ void k_query_decide(const unsigned int *last_count, const unsigned int *qflags,
+                               unsigned long long *counter, unsigned int *walk)
+{
+    unsigned int w = (*qflags != 0 || *last_count != 0) ? 1u : 0u;
+    if (w)
+        *counter = 0ull;
+    *walk = w;
+}
+
+// Slots [min(count, cap), cap) get a record that sorts after every real one
+// and is the same in every slot, so the sort and the repeat removal can run
+// over a fixed number of slots.
+__global__ void k_pad_records(Rec *raw, const unsigned long long *counter, uint32_t cap)
+{
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long c = *counter;
+    if (r >= cap || (unsigned long long)r < c)
+        return;
+    Rec pad;
+    pad.i = pad.j = pad.tlo = pad.thi = 0xFFFFFFFFu;
+    raw[r] = pad;
+}
+
+// Result words: count (records written, or records found when they exceed the
+// capacity) and status bits (1 capacity exceeded, 2 tree inconsistent).
+__global__ void k_query_finish(const unsigned long long *counter, const unsigned int *tree_err,
+                               const uint32_t *uniq, uint32_t cap, unsigned long long *count_out,
+                               unsigned int *status_out)
+{
+    unsigned long long c = *counter;
+    unsigned int st = 0;
+    if (c > cap)
+        st |= 1u;
+    if (*tree_err)
+        st |= 2u;
+    unsigned long long n = 0;
+    if (c > cap)
+        n = c;
+    else if (c > 0)
+        n = (unsigned long long)*uniq - (c < cap ? 1ull : 0ull);
+    *count_out = n;
+    *status_out = st;
+}
+
+hipError_t launch_query_begin(const TreeHeader *hdr, unsigned int *qflags, hipStream_t s)
+{
+    k_query_begin<<<1, 1, 0, s>>>(hdr, qflags);
+    return hipGetLastError();
+}
+
+hipError_t launch_query_decide(const unsigned int *last_count, const unsigned int *qflags,
+                               unsigned long long *counter, unsigned int *walk, hipStream_t s)
+{
+    k_query_decide<<<1, 1, 0, s>>>(last_count, qflags, counter, walk);
+    return hipGetLastError();
+}
+
+hipError_t launch_pad_records(Rec *raw, const unsigned long long *counter, uint32_t cap,
+                              hipStream_t s)
+{
+    if (cap == 0)
+        return hipSuccess;
+    k_pad_records<<<nblk(cap, 256), 256, 0, s>>>(raw, counter, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_query_finish(const unsigned long long *counter, const unsigned int *tree_err,
+                               const uint32_t *uniq, uint32_t cap, unsigned long long *count_out,
+                               unsigned int *status_out, hipStream_t s)
+{
+    k_query_finish<<<1, 1, 0, s>>>(counter, tree_err, uniq, cap, count_out, status_out);
     return hipGetLastError();
 }
 
