@@ -14,6 +14,14 @@ recorded on the library's stream during the timed steps.  cpu_baseline: the
 CPU oracle (literal all-pairs) on a bounded sample of the same workload.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--precision fp64|fp32]
+                    [--boxes fp64|fp32] [--dt fixed|heuristic|mlp] [--workload tracked|batch]
+
+Other workloads (not the default line): --dt heuristic (per-object steps
+bounding each box's motion to 5 km), --dt mlp (per-object steps from the step
+network, trained beforehand on step sweeps of two other catalogs of the same
+recipe; the inference runs inside the timed step), --workload batch (64
+independent scenarios of 2 000-50 000 objects, 30-minute horizons, 1 s steps,
+replayed as one graph launch per step).
 """
 import argparse
 import json
@@ -58,7 +66,7 @@ def measured_traffic(stage, precision, dt_mode):
                + t["write_kib"] * 1024 * (1048576.0 / COPY_WRITE_KIB))
 
 
-def algorithmic_bytes(stage, N, n, P, tree_prec, box_prec, seeds=0):
+def algorithmic_bytes(stage, N, n, P, tree_prec, box_prec):
     """Compulsory HBM bytes of one launch of a stage: every input read once,
     every output written once (intermediate LDS traffic excluded)."""
     fb = 8 if box_prec == 0 else 4          # box float bytes
@@ -75,7 +83,7 @@ def algorithmic_bytes(stage, N, n, P, tree_prec, box_prec, seeds=0):
         "refit": N * node + nodes * 4 + (N - 1) * (8 + 8) + (N - 1) * node,
                                                              # leaf records, parents, kids
                                                              # and links in; inner records out
-        "traverse": seeds * (8 + 2 * node) + P * 16,         # seed pairs and their nodes,
+        "traverse": nodes * node + P * 16,                   # every node read once,
                                                              # records out
         "canon": P * 16 * 3,
     }
@@ -125,33 +133,8 @@ def cpu_baseline(sc, seconds):
                       f"counted as 2 * C(n, 2) brute-force-equivalent tests per repetition"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
-                    help="tree precision (boxes stay FP64 unless --boxes fp32)")
-    ap.add_argument("--boxes", choices=["fp64", "fp32"], default="fp64")
-    ap.add_argument("--dt", choices=["fixed", "heuristic"], default="fixed",
-                    help="fixed 1 s steps, or per-object steps bounding each box's motion "
-                         "to 5 km (computed inside the timed step)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-mib", type=int, default=0,
-                    help="first run one device-to-device copy of this many MiB (a known-size "
-                         "kernel for calibrating HBM byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; --gpus must be 1 "
-                                   "(multi-GPU sharding is a design note, not a run)"}))
-        sys.exit(2)
-
-    import numpy as np
+def _setup(args):
     import torch
-    import paper_1901_10475_amd as cd
-    from paper_1901_10475_amd import catalog
-
     torch.cuda.set_device(0)
     if args.copy_mib:
         src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
@@ -159,32 +142,77 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+
+def _roofline(stages, N, n, P, prec, box_prec, precision_name, dt_mode):
+    dom = max(stages, key=lambda k: stages[k][0])
+    mean_ms = stages[dom][0] / stages[dom][1]
+    nbytes = algorithmic_bytes(dom, N, n, P, prec, box_prec)
+    achieved = nbytes / (mean_ms / 1000.0) / 1e9
+    return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(dom, precision_name, dt_mode),
+            "bytes_per_launch": int(nbytes), "mean_ms": round(mean_ms, 4)}
+
+
+def _train_step_net(sc_recipe, seeds, cd, ld, catalog, log):
+    """Step network trained on step sweeps of catalogs drawn from the same
+    recipe with other seeds (outside the timed region)."""
+    import torch
+    xs, ts = [], []
+    for seed in seeds:
+        sc = sc_recipe(seed)
+        p = cd.params_struct(sc.tick_s, sc.mu, sc.threshold_km, sc.horizon_ticks, 0)
+        x, t, summary = ld.sweep_targets(cd.soa(sc.elements), p)
+        log(f"[bench] sweep seed {seed}: " + ", ".join(
+            f"x{r['scale']:g}: {r['boxes']} boxes {r['records']} rec" for r in summary))
+        xs.append(x)
+        ts.append(t)
+    X, Y = torch.cat(xs), torch.cat(ts)
+    net = ld.StepNet(seed=0)
+    net.set_output_bias(float(Y.mean().item()))
+    losses = net.train(X, Y, steps=1000, lr=3e-3, lr_end=1e-4)
+    log(f"[bench] step network: loss {losses[0]:.4f} -> {losses[-1]:.4f} "
+        f"(target variance {float(Y.var().item()):.4f})")
+    return net
+
+
+def run_tracked(args, log):
+    import numpy as np
+    import torch
+    import paper_1901_10475_amd as cd
+    from paper_1901_10475_amd import catalog
+    from paper_1901_10475_amd import learned_dt as ld
+
     sc = catalog.tracked_hour()
     prec = cd.CD_FP64 if args.precision == "fp64" else cd.CD_FP32
     box_prec = cd.CD_FP64 if args.boxes == "fp64" else cd.CD_FP32
     el = cd.soa(sc.elements)
-    p = cd.params_struct(sc.tick_s, sc.mu, sc.threshold_km, sc.horizon_ticks, sc.dt_ticks)
-    heur = 5.0 if args.dt == "heuristic" else None
-    workload = sc.name if heur is None else sc.name.replace("dt1s", "dt_heuristic5km")
-    print(f"[bench] workload {workload}: n={sc.n} T={sc.horizon_ticks} ticks",
-          file=sys.stderr, flush=True)
-    bp = cd.BroadPhase(sc.n, p, None, box_prec, prec, dt_heuristic_km=heur, el_soa=el)
+    p = cd.params_struct(sc.tick_s, sc.mu, sc.threshold_km, sc.horizon_ticks,
+                         sc.dt_ticks if args.dt == "fixed" else 0)
+    workload = {"fixed": sc.name, "heuristic": sc.name.replace("dt1s", "dt_heuristic5km"),
+                "mlp": sc.name.replace("dt1s", "dt_mlp")}[args.dt]
+    log(f"[bench] workload {workload}: n={sc.n} T={sc.horizon_ticks} ticks")
+    kw = {}
+    if args.dt == "heuristic":
+        kw = {"dt_heuristic_km": 5.0, "el_soa": el}
+    elif args.dt == "mlp":
+        net = _train_step_net(lambda seed: catalog.tracked_hour(seed=seed, planted=0),
+                              (2002, 2003), cd, ld, catalog, log)
+        kw = {"dt_mlp": (net.w_bf16, 5.0), "el_soa": el}
+    bp = cd.BroadPhase(sc.n, p, None, box_prec, prec, **kw)
     N = bp.count
     for w in range(args.warmup):
         pairs = bp.run(el)
-        print(f"[bench] warmup {w}: {len(pairs)} pairs", file=sys.stderr, flush=True)
+        log(f"[bench] warmup {w}: {len(pairs)} pairs")
     torch.cuda.synchronize()
 
     cd.cd_profile_read(reset=True)
     cd.cd_profile_enable(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ev0.record()
     for _ in range(args.steps):
         pairs = bp.run(el)
-    ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     cd.cd_profile_enable(False)
@@ -197,23 +225,19 @@ def main():
     else:
         tests = time_overlap_pairs(bp.dt.cpu().numpy().view(np.uint32), sc.horizon_ticks)
     value = tests / (ms_step / 1000.0)
-    print(f"[bench] {args.steps} steps: {ms_step:.3f} ms/query, {P} pairs, stages "
-          + ", ".join(f"{k}={v[0] / v[1]:.3f}ms" for k, v in stages.items()),
-          file=sys.stderr, flush=True)
-
-    dom = max(stages, key=lambda k: stages[k][0])
-    mean_ms = stages[dom][0] / stages[dom][1]
-    nbytes = algorithmic_bytes(dom, N, sc.n, P, prec, box_prec)
-    achieved = nbytes / (mean_ms / 1000.0) / 1e9
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(dom, args.precision, args.dt), "bytes_per_launch": int(nbytes),
-                "mean_ms": round(mean_ms, 4)}
-
+    log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/query, {P} pairs, stages "
+        + ", ".join(f"{k}={v[0] / v[1]:.3f}ms" for k, v in stages.items()))
+    recall = None
+    if sc.planted:
+        pr = pairs.cpu().numpy().view(np.uint32)
+        hit = sum(bool(((pr[:, 0] == i) & (pr[:, 1] == j) & (pr[:, 2] <= t)
+                        & (t < pr[:, 3])).any()) for i, j, t in sc.planted)
+        recall = hit / len(sc.planted)
     out = {"metric": METRIC, "value": value, "unit": "box-pair tests/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f64" if prec == cd.CD_FP64 else "f64 boxes, f32 tree",
+           "dtype": "f64" if prec == cd.CD_FP64 and box_prec == cd.CD_FP64 else
+                    ("f64 boxes, f32 tree" if box_prec == cd.CD_FP64 else "f32 boxes, f32 tree"),
            "data": "synthetic (seeded tracked-population catalog; the paper's TLE catalog is "
                    "not available)",
            "config": {"workload": workload,
@@ -222,12 +246,104 @@ def main():
                       "boxes": N, "threshold_km": sc.threshold_km,
                       "box_precision": args.boxes, "tree_precision": args.precision,
                       "brute_force_tests": tests},
-           "pairs": P,
+           "pairs": P, "planted_recall": recall,
            "stages_ms": {k: round(v[0] / v[1], 4) for k, v in stages.items()},
-           "roofline": roofline}
+           "roofline": _roofline(stages, N, sc.n, P, prec, box_prec, args.precision, args.dt)}
     if not args.no_cpu_baseline and args.dt == "fixed":
-        print("[bench] CPU oracle baseline ...", file=sys.stderr, flush=True)
+        log("[bench] CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
+    return out
+
+
+def run_batch(args, log):
+    """64 uneven scenarios, one graph launch per step."""
+    import torch
+    import paper_1901_10475_amd as cd
+    from paper_1901_10475_amd import catalog
+    from paper_1901_10475_amd.batch import BatchRunner
+
+    prec = cd.CD_FP64 if args.precision == "fp64" else cd.CD_FP32
+    box_prec = cd.CD_FP64 if args.boxes == "fp64" else cd.CD_FP32
+    sizes = catalog.batch_sizes()
+    scs = [catalog.batch_member(s, n) for s, n in enumerate(sizes)]
+    br = BatchRunner(scs, box_prec, prec)
+    log(f"[bench] batch: {len(scs)} scenarios, n {min(sizes)}..{max(sizes)}, "
+        f"{br.boxes_total()} boxes")
+    # eager pass with stage timing: capacities, and the per-kernel breakdown
+    cd.cd_profile_read(reset=True)
+    cd.cd_profile_enable(True)
+    br.calibrate()
+    cd.cd_profile_enable(False)
+    stages = cd.cd_profile_read(reset=True)
+    br.capture()
+    log("[bench] batch captured")
+    for w in range(args.warmup):
+        br.replay()
+        res = br.results()
+        log(f"[bench] warmup {w}: {sum(int(r.shape[0]) for r in res)} pairs")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        br.replay()
+    br.stream.synchronize()
+    wall = time.perf_counter() - t0
+    res = br.results()
+    P = sum(int(r.shape[0]) for r in res)
+    ms_step = wall * 1000.0 / args.steps
+    tests = br.brute_force_tests()
+    log(f"[bench] {args.steps} replays: {ms_step:.3f} ms/batch, {P} pairs; eager stages "
+        + ", ".join(f"{k}={v[0]:.1f}ms/{v[1]}" for k, v in stages.items()))
+    # roofline of the dominant stage over the eager pass (all scenarios)
+    dom = max(stages, key=lambda k: stages[k][0])
+    nbytes = sum(algorithmic_bytes(dom, N, s.n, 0, prec, box_prec)
+                 for s, N in zip(scs, br.counts))
+    achieved = nbytes / (stages[dom][0] / 1000.0) / 1e9
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None, "bytes_per_launch": int(nbytes / len(scs)),
+            "mean_ms": round(stages[dom][0] / stages[dom][1], 4),
+            "from": "eager pass over the batch (stage timing is off inside graphs)"}
+    return {"metric": METRIC, "value": tests / (ms_step / 1000.0), "unit": "box-pair tests/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "f64" if prec == cd.CD_FP64 and box_prec == cd.CD_FP64 else "f32 tree",
+            "data": "synthetic (seeded LEO scenarios)",
+            "config": {"workload": f"batch64_leo_30min_dt1s", "scenarios": len(scs),
+                       "n_min": min(sizes), "n_max": max(sizes), "boxes": br.boxes_total(),
+                       "brute_force_tests": tests, "graph": "one launch per step"},
+            "pairs": P, "stages_ms_eager_total": {k: round(v[0], 3) for k, v in stages.items()},
+            "roofline": roof}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
+                    help="tree precision (boxes stay FP64 unless --boxes fp32)")
+    ap.add_argument("--boxes", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--dt", choices=["fixed", "heuristic", "mlp"], default="fixed",
+                    help="fixed 1 s steps; per-object steps bounding each box's motion to "
+                         "5 km; or per-object steps from the trained step network")
+    ap.add_argument("--workload", choices=["tracked", "batch"], default="tracked")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB (a known-size "
+                         "kernel for calibrating HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "only one GPU is measured; --gpus must be 1 (how the path "
+                                   "would shard over several GPUs is described, not run)"}))
+        sys.exit(2)
+
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    _setup(args)
+    out = run_batch(args, log) if args.workload == "batch" else run_tracked(args, log)
     print(json.dumps(out), flush=True)
 
 

@@ -186,7 +186,8 @@ int cd_build_boxes(const cd_elements *el, const uint32_t *dt_ticks, const cd_par
  * over the sorted keys and every inner box is set to the exact union of its
  * children by an atomic bottom-up pass, so an inner node overlaps whatever
  * its leaves overlap.  precision CD_FP32 is allowed for FP64 boxes (outward
- * rounding at the leaves).  slab_ticks = 0 takes boxes->slab_ticks, else 1.
+ * rounding at the leaves).  slab_ticks = 0 takes boxes->slab_ticks if set,
+ * else horizon / 64 (at least 1).
  * Async. */
 size_t cd_tree_bytes(int64_t count, int precision);
 size_t cd_build_tree_ws(int64_t count);

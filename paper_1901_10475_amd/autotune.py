@@ -1,12 +1,15 @@
-"""Launch-shape autotuner for the traversal.
+"""Autotuner for the traversal's launch shapes and the tree's time slabs.
 
-Searches the fields of ``cd_tuning`` (node-pair workgroups per level and lanes
-per workgroup, per-leaf-walk lanes, traversal mode) on a built tree, timing
-the query alone (median of ``reps`` runs after one warm-up, device events on
-the query's stream), and caches the best shape in a JSON file keyed by
-(GPU architecture, tree precision, box-count bucket, step mode).  Every
-candidate yields the same record list -- only time differs -- and ``tune``
-checks that before it accepts a timing.
+``tune`` searches the fields of ``cd_tuning`` (node-pair workgroups per level
+and lanes per workgroup, per-leaf-walk lanes, traversal mode) on a built
+tree, timing the query alone; ``tune_slab`` searches the width of the time
+field of the tree key (``slab_ticks`` of cd_build_tree) for boxes without a
+slab structure (per-object steps), timing tree build and query together.
+Timings are medians of ``reps`` runs after one warm-up, from device events on
+the current stream.  The best choice is cached in a JSON file keyed by (GPU
+architecture, tree precision, box-count bucket, step mode, what was tuned).
+Every candidate yields the same record list -- only time differs -- and the
+tuner checks that before it accepts a timing.
 """
 import json
 import math
@@ -32,12 +35,13 @@ def candidates():
     return out
 
 
-def cache_key(precision, boxes, dt_mode, arch=None):
+def cache_key(precision, boxes, dt_mode, arch=None, what="launch"):
     if arch is None:
         arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     bucket = int(round(math.log2(max(int(boxes), 1))))
     prec = "fp64" if precision == 0 else "fp32"
-    return f"{arch}|{prec}|2^{bucket}|{dt_mode}"
+    key = f"{arch}|{prec}|2^{bucket}|{dt_mode}"
+    return key if what == "launch" else key + "|" + what
 
 
 def load_cache(path=None):
@@ -102,5 +106,39 @@ def tuned(query, precision, boxes, dt_mode, path=None, reps=3, log=None):
     best, results = tune(query, reps=reps, log=log)
     cache[key] = {"tuning": best,
                   "ms": {json.dumps(c, sort_keys=True): ms for c, ms in results}}
+    save_cache(cache, path)
+    return best, False
+
+
+def slab_candidates(horizon_ticks):
+    """Time-slab widths from 1/1024 of the horizon to a quarter of it."""
+    T = max(int(horizon_ticks), 1)
+    return sorted({max(1, T // d) for d in (1024, 256, 64, 16, 4)})
+
+
+def tune_slab(run, horizon_ticks, reps=3, log=None):
+    """run(slab_ticks): builds the tree with that slab width and queries it,
+    returning the record list.  Returns (best slab_ticks, [(slab, ms)])."""
+    results = []
+    ref = None
+    for w in slab_candidates(horizon_ticks):
+        ms, out = _time_query(lambda: run(w), reps)
+        if ref is None:
+            ref = out.cpu()
+        elif not torch.equal(out.cpu(), ref):
+            raise RuntimeError(f"slab width {w} changed the record list")
+        results.append((w, ms))
+        if log:
+            log(f"[tune] slab {w} ticks {ms:.3f} ms")
+    return min(results, key=lambda r: r[1])[0], results
+
+
+def tuned_slab(run, horizon_ticks, precision, boxes, dt_mode, path=None, reps=3, log=None):
+    key = cache_key(precision, boxes, dt_mode, what="slab")
+    cache = load_cache(path)
+    if key in cache:
+        return cache[key]["slab_ticks"], True
+    best, results = tune_slab(run, horizon_ticks, reps=reps, log=log)
+    cache[key] = {"slab_ticks": best, "ms": {str(w): ms for w, ms in results}}
     save_cache(cache, path)
     return best, False

@@ -163,7 +163,12 @@ BoxView view_of(const cd_boxes *b)
     return v;
 }
 
-uint32_t default_slab(uint32_t horizon) { return horizon / 4096u > 0 ? horizon / 4096u : 1u; }
+// Time field of the key when the boxes carry no slab hint (per-object steps,
+// caller-built boxes): 64 slabs over the horizon.  Narrow slabs leave nearly
+// every box straddling a slab edge, and the traversal then joins neighbouring
+// slabs through union boxes that span all of space; measured on the tracked
+// hour with 5 km steps, T/4096 -> T/64 cut the query from 34.6 to 20.1 ms.
+uint32_t default_slab(uint32_t horizon) { return horizon / 64u > 0 ? horizon / 64u : 1u; }
 
 // ---- workspace layouts (shared by the *_ws queries and the calls) ----
 
@@ -259,7 +264,9 @@ DigitPlan record_plan(const cd_tree *tree)
     return plan;
 }
 
-uint32_t queue_cap(int64_t N) { return (uint32_t)(N / 4 > 65536 ? N / 4 : 65536); }
+// node pairs per traversal level: N covers every case seen short of boxes that
+// overlap nearly everything (those overflow into the per-leaf walk)
+uint32_t queue_cap(int64_t N) { return (uint32_t)(N > 65536 ? N : 65536); }
 size_t layout_query(void *base, size_t bytes, int64_t N, int64_t cap, QueryWS *w)
 {
     Carve c(base, bytes);

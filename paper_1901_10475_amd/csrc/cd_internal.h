@@ -255,7 +255,7 @@ constexpr int kMlpW3 = kMlpB2 + kMlpHid;
 constexpr int kMlpB3 = kMlpW3 + kMlpHid;
 constexpr int kMlpParams = kMlpB3 + 1;   // 4609
 constexpr int kMlpOuterThreads = 256;
-constexpr int kMlpOuterSamples = 1024;   // samples per outer-product block
+constexpr int kMlpOuterSamples = 128;    // samples per outer-product block
 
 // ---- launchers (each returns the launch status) -----------------------------
 

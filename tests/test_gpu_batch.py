@@ -171,3 +171,24 @@ def test_autotuner_searches_checks_and_caches(tmp_path):
     again, hit = autotune.tuned(bp.query, cd.CD_FP64, bp.count, "fixed", path=path)
     assert hit and again == best
     say("autotuned", best)
+
+
+def test_slab_tuner_keeps_the_record_list(tmp_path):
+    need_gpu()
+    sc = catalog.projected_debris(seed=93, n=3000, parents=2, horizon_ticks=120_000, planted=4)
+    el = cd.soa(sc.elements)
+    p = cd.params_struct(sc.tick_s, sc.mu, sc.threshold_km, sc.horizon_ticks, 0)
+    bp = cd.BroadPhase(sc.n, p, dt_heuristic_km=5.0, el_soa=el)
+
+    def run(w):
+        bp.slab_ticks = w
+        return bp.run(el)
+
+    path = str(tmp_path / "tune.json")
+    best, hit = autotune.tuned_slab(run, sc.horizon_ticks, cd.CD_FP64, bp.count, "heuristic",
+                                    path=path, reps=2)
+    assert not hit and best in autotune.slab_candidates(sc.horizon_ticks)
+    again, hit = autotune.tuned_slab(run, sc.horizon_ticks, cd.CD_FP64, bp.count, "heuristic",
+                                     path=path)
+    assert hit and again == best
+    say("slab tuned", best)
