@@ -64,13 +64,17 @@ typedef struct {
  * object is a world object with inf-norm radius r = thr / 2 (Def. World
  * Object, Def. Occupancy Region).  horizon_ticks is T; its last tick is
  * included, so T + 1 must fit 32 bits.  dt_ticks is the uniform time step,
- * used when no per-object step array is given. */
+ * used when no per-object step array is given.  start_ticks places the
+ * horizon at absolute ticks [start, start + T] after the elements' epoch
+ * (positions are taken at start + t); tags and records stay relative to
+ * start, so a long horizon can be run as consecutive windows. */
 typedef struct {
     double tick_s;          /* seconds per tick, e.g. 1e-3 */
     double mu;              /* gravitational parameter, km^3/s^2 (398600.4418) */
     double threshold_km;    /* thr >= 0 */
     uint32_t horizon_ticks; /* T */
     uint32_t dt_ticks;      /* uniform step (>= 1) when no dt array is given */
+    uint32_t start_ticks;   /* absolute tick of the horizon's t = 0 (0: the epoch) */
 } cd_params;
 
 /* A set of 4D boxes, structure of arrays, caller-owned device memory.

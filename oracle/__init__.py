@@ -58,7 +58,7 @@ def lib():
         L.or_box_count.restype = ctypes.c_int64
         L.or_box_count.argtypes = [ctypes.c_int64, _dp, ctypes.c_uint32]
         L.or_boxes.restype = ctypes.c_int
-        L.or_boxes.argtypes = [ctypes.c_int64, _dp, _dp, ctypes.c_uint32,
+        L.or_boxes.argtypes = [ctypes.c_int64, _dp, _dp, ctypes.c_uint32, ctypes.c_uint32,
                                ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                _dp, _dp, _dp, _dp, _dp]
         L.or_pairs.restype = ctypes.c_int64
@@ -152,7 +152,8 @@ class Boxes:
         return Boxes(self.lo[idx], self.hi[idx], self.t0[idx], self.t1[idx], self.obj[idx])
 
 
-def boxes(elements, dt, T, tick_s, thr_km, mu=MU_EARTH):
+def boxes(elements, dt, T, tick_s, thr_km, mu=MU_EARTH, start=0):
+    """Boxes over absolute ticks [start, start + T], tags relative to start."""
     el = _c(elements, np.float64).reshape(-1, 6)
     n = len(el)
     dt = _c(np.broadcast_to(np.asarray(dt, dtype=np.uint32), (n,)), np.uint32)
@@ -164,7 +165,7 @@ def boxes(elements, dt, T, tick_s, thr_km, mu=MU_EARTH):
     t0 = np.zeros(N, np.uint32)
     t1 = np.zeros(N, np.uint32)
     obj = np.zeros(N, np.uint32)
-    rc = lib().or_boxes(n, _ptr(el), _ptr(dt), int(T), float(tick_s), float(mu),
+    rc = lib().or_boxes(n, _ptr(el), _ptr(dt), int(T), int(start), float(tick_s), float(mu),
                         float(thr_km), _ptr(lo), _ptr(hi), _ptr(t0), _ptr(t1), _ptr(obj))
     if rc != 0:
         raise ValueError("invalid box parameters")

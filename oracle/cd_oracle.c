@@ -138,7 +138,7 @@ int64_t or_box_count(int64_t n, const uint32_t *dt, uint32_t T)
  * interval (the reading in the file header) and its tag is [t_k, t_{k+1}),
  * with the last tag closed at T.  That gives the 4D occupancy region
  * occ-int x interval of Def. 4D Occupancy Region. */
-int or_boxes(int64_t n, const double *el, const uint32_t *dt, uint32_t T,
+int or_boxes(int64_t n, const double *el, const uint32_t *dt, uint32_t T, uint32_t start,
              double tick_s, double mu, double thr_km,
              double *lo, double *hi, uint32_t *t0, uint32_t *t1, uint32_t *obj)
 {
@@ -155,8 +155,8 @@ int or_boxes(int64_t n, const double *el, const uint32_t *dt, uint32_t T,
             uint64_t ta = k * dt[i] < T ? k * dt[i] : T;
             uint64_t tb = (k + 1) * dt[i] < T ? (k + 1) * dt[i] : T;
             double pa[3], pb[3];
-            or_position(e6, (double)ta * tick_s, mu, pa);
-            or_position(e6, (double)tb * tick_s, mu, pb);
+            or_position(e6, (double)(start + ta) * tick_s, mu, pa);
+            or_position(e6, (double)(start + tb) * tick_s, mu, pb);
             double g = vmax * ((double)(tb - ta) * tick_s) / 2.0 + thr_km / 2.0;
             for (int d = 0; d < 3; ++d) {
                 lo[3 * b + d] = fmin(pa[d], pb[d]) - g;

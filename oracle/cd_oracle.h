@@ -40,8 +40,11 @@ double or_vmax(double a, double e, double mu);
 uint64_t or_intervals(uint32_t dt, uint32_t T);
 int64_t or_box_count(int64_t n, const uint32_t *dt, uint32_t T);
 /* Object-major boxes: box (i, k) is at off_i + k, off_i = sum_{i'<i} K_i'.
+ * The horizon covers absolute ticks [start, start + T]: positions are taken
+ * at start + t_k, tags are relative to start (a window of a longer horizon
+ * is the same problem over a shifted time interval).
  * Returns 0, or -1 on invalid input (dt = 0, T + 1 overflow). */
-int or_boxes(int64_t n, const double *el, const uint32_t *dt, uint32_t T,
+int or_boxes(int64_t n, const double *el, const uint32_t *dt, uint32_t T, uint32_t start,
              double tick_s, double mu, double thr_km,
              double *lo, double *hi, uint32_t *t0, uint32_t *t1, uint32_t *obj);
 

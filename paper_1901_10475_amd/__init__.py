@@ -32,7 +32,7 @@ class cd_elements(ctypes.Structure):
 class cd_params(ctypes.Structure):
     _fields_ = [("tick_s", ctypes.c_double), ("mu", ctypes.c_double),
                 ("threshold_km", ctypes.c_double), ("horizon_ticks", ctypes.c_uint32),
-                ("dt_ticks", ctypes.c_uint32)]
+                ("dt_ticks", ctypes.c_uint32), ("start_ticks", ctypes.c_uint32)]
 
 
 class cd_boxes(ctypes.Structure):
@@ -182,9 +182,9 @@ def elements_struct(el_soa):
     return cd_elements(*rows, n)
 
 
-def params_struct(tick_s, mu, threshold_km, horizon_ticks, dt_ticks=0):
+def params_struct(tick_s, mu, threshold_km, horizon_ticks, dt_ticks=0, start_ticks=0):
     return cd_params(float(tick_s), float(mu), float(threshold_km), int(horizon_ticks),
-                     int(dt_ticks))
+                     int(dt_ticks), int(start_ticks))
 
 
 class Boxes:

@@ -502,7 +502,7 @@ int cd_build_boxes(const cd_elements *el, const uint32_t *dt_ticks, const cd_par
     bo.obj = out->obj;
     bo.cap = (uint64_t)out->count;
     Stage st_boxes("boxes", s);
-    CD_HIP(launch_object_setup(*el, p->mu, w.oc, s));
+    CD_HIP(launch_object_setup(*el, p->mu, (double)p->start_ticks * p->tick_s, w.oc, s));
     double half_thr = 0.5 * p->threshold_km;
     if (!dt_ticks) {
         if (p->dt_ticks == 0)

@@ -260,7 +260,8 @@ constexpr int kMlpOuterSamples = 128;    // samples per outer-product block
 // ---- launchers (each returns the launch status) -----------------------------
 
 // boxes
-hipError_t launch_object_setup(const cd_elements &el, double mu, ObjConst *oc, hipStream_t s);
+hipError_t launch_object_setup(const cd_elements &el, double mu, double start_s, ObjConst *oc,
+                               hipStream_t s);
 hipError_t launch_validate(const cd_elements &el, unsigned long long *first_bad, hipStream_t s);
 hipError_t launch_steps(const uint32_t *dt, uint32_t n, uint32_t T, ObjSteps *st, uint32_t *Kc,
                         unsigned long long *total, unsigned int *bad_dt, hipStream_t s);

@@ -16,7 +16,8 @@
 
 namespace cd {
 
-__global__ void k_object_setup(cd_elements el, double mu, ObjConst *oc)
+// m0 is advanced to the horizon's start: M(start + t) = m0 + n (start + t).
+__global__ void k_object_setup(cd_elements el, double mu, double start_s, ObjConst *oc)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= el.n)
@@ -31,7 +32,7 @@ __global__ void k_object_setup(cd_elements el, double mu, ObjConst *oc)
     c.e = e;
     c.b = a * sqrt(1.0 - e * e);
     c.n = sqrt(mu / (a * a * a));
-    c.m0 = el.m0[i];
+    c.m0 = el.m0[i] + c.n * start_s;
     c.vmax = sqrt(mu * (1.0 + e) / (a * (1.0 - e)));
     // R_z(raan) R_x(inc) R_z(argp) applied to the perifocal x and y axes
     c.P[0] = cO * cw - sO * sw * ci;
@@ -255,11 +256,12 @@ __global__ void k_steps_apply_offsets(ObjSteps *st, const uint32_t *box_off, uin
 
 static inline unsigned blocks_for(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
 
-hipError_t launch_object_setup(const cd_elements &el, double mu, ObjConst *oc, hipStream_t s)
+hipError_t launch_object_setup(const cd_elements &el, double mu, double start_s, ObjConst *oc,
+                               hipStream_t s)
 {
     if (el.n == 0)
         return hipSuccess;
-    k_object_setup<<<blocks_for(el.n, 256), 256, 0, s>>>(el, mu, oc);
+    k_object_setup<<<blocks_for(el.n, 256), 256, 0, s>>>(el, mu, start_s, oc);
     return hipGetLastError();
 }
 

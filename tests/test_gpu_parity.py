@@ -280,3 +280,32 @@ def test_tracked_hour_heuristic_steps_full_size():
     s32 = {tuple(x) for x in p32.tolist()}
     assert s64 <= s32
     say(f"heuristic dt: {len(s64)} FP64 records, {len(s32) - len(s64)} extra with an FP32 tree")
+
+
+@pytest.mark.parametrize("start", [10_000, 1_234_567])
+def test_window_boxes_and_pairs(start):
+    """A horizon placed at absolute ticks [start, start + T]: boxes match the
+    oracle's window boxes, records match the oracle on the same boxes."""
+    need_gpu()
+    say("window start", start)
+    import torch
+    import paper_1901_10475_amd as cd
+    sc = catalog.scaled(catalog.small_leo(), n=600, horizon_ticks=60_000)
+    el = cd.soa(sc.elements)
+    for dt in (None, oracle.dt_heuristic(sc.elements, sc.tick_s, 5.0, sc.horizon_ticks)):
+        p = cd.params_struct(sc.tick_s, sc.mu, sc.threshold_km, sc.horizon_ticks,
+                             sc.dt_ticks if dt is None else 0, start_ticks=start)
+        dtt = None if dt is None else torch.from_numpy(dt.view(np.int32)).cuda()
+        bp = cd.BroadPhase(sc.n, p, dtt)
+        pairs = bp.run(el).cpu().numpy().view(np.uint32)
+        lo, hi, t0, t1, obj = bp.boxes.to_host()
+        ob = oracle.boxes(sc.elements, sc.dt_ticks if dt is None else dt, sc.horizon_ticks,
+                          sc.tick_s, sc.threshold_km, start=start)
+        if dt is None:
+            g = gpu_to_object_major(sc.n, oracle.intervals(sc.dt_ticks, sc.horizon_ticks))
+            lo, hi, t0, t1, obj = lo[g], hi[g], t0[g], t1[g], obj[g]
+        assert np.array_equal(t0, ob.t0) and np.array_equal(t1, ob.t1)
+        assert np.array_equal(obj, ob.obj)
+        assert_boxes_close(lo, hi, ob.lo, ob.hi, sc.elements[ob.obj, 0])
+        ref = oracle.pairs(oracle.Boxes(*bp.boxes.to_host()))
+        assert np.array_equal(pairs, ref)

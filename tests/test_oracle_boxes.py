@@ -155,3 +155,23 @@ def test_dt_heuristic_bound():
         assert dt[i] >= 1
         assert v * dt[i] * TICK <= 5.0 + 1e-12          # displacement bound holds
         assert v * (dt[i] + 1) * TICK > 5.0             # and is the largest such step
+
+
+def test_window_boxes_are_the_shifted_tail_of_the_long_horizon():
+    """A horizon [S, S + T] with S a multiple of every step is the tail of the
+    horizon [0, S + T]: same positions (same absolute ticks), tags shifted by S."""
+    import numpy as np
+    import oracle
+    from paper_1901_10475_amd import catalog
+    sc = catalog.scaled(catalog.small_leo(), n=20)
+    dt = np.array([1000, 2000, 500, 4000] * 5, np.uint32)
+    S, T = 8000, 6000
+    long = oracle.boxes(sc.elements, dt, S + T, sc.tick_s, sc.threshold_km)
+    win = oracle.boxes(sc.elements, dt, T, sc.tick_s, sc.threshold_km, start=S)
+    keep = long.t0 >= S
+    assert keep.sum() == len(win.t0)
+    np.testing.assert_array_equal(long.lo[keep], win.lo)
+    np.testing.assert_array_equal(long.hi[keep], win.hi)
+    np.testing.assert_array_equal(long.t0[keep] - S, win.t0)
+    np.testing.assert_array_equal(long.t1[keep] - S, win.t1)
+    np.testing.assert_array_equal(long.obj[keep], win.obj)
