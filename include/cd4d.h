@@ -88,7 +88,14 @@ typedef struct {
  *     the tree builder then sorts each slab inside one workgroup.
  *   horizon_ticks: an upper bound on every t0 (used to size sort keys).
  *   obj_count: an upper bound on obj + 1 (used to size sort keys); 0 means
- *     "up to 2^32". */
+ *     "up to 2^32".
+ *   code, code_valid: optional per-box 30-bit Morton code of the box centre
+ *     (the tree's spatial sort key).  If code is not NULL, cd_build_boxes
+ *     writes it (in the frame of the orbits' bounding boxes, so no code is
+ *     clamped) and sets code_valid = 1; cd_build_tree then sorts by these
+ *     codes instead of re-reading every box to form them.  Codes only shape
+ *     the tree: any codes give the same records.  code_valid = 0 (or code
+ *     NULL) makes cd_build_tree compute codes from the boxes. */
 typedef struct {
     int64_t count;
     int precision;
@@ -98,6 +105,8 @@ typedef struct {
     int64_t slab_size;
     uint32_t horizon_ticks;
     uint32_t obj_count;
+    uint32_t *code;
+    int code_valid;
 } cd_boxes;
 
 /* A linear BVH over a box set.  mem is a caller-owned device buffer of

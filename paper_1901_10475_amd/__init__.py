@@ -39,7 +39,8 @@ class cd_boxes(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int64), ("precision", ctypes.c_int), ("lo", _vp * 3),
                 ("hi", _vp * 3), ("t0", _vp), ("t1", _vp), ("obj", _vp),
                 ("slab_ticks", ctypes.c_uint32), ("slab_size", ctypes.c_int64),
-                ("horizon_ticks", ctypes.c_uint32), ("obj_count", ctypes.c_uint32)]
+                ("horizon_ticks", ctypes.c_uint32), ("obj_count", ctypes.c_uint32),
+                ("code", _vp), ("code_valid", ctypes.c_int)]
 
 
 class cd_tree(ctypes.Structure):
@@ -188,9 +189,10 @@ def params_struct(tick_s, mu, threshold_km, horizon_ticks, dt_ticks=0, start_tic
 
 
 class Boxes:
-    """Device box arrays (SoA) plus the cd_boxes descriptor."""
+    """Device box arrays (SoA) plus the cd_boxes descriptor.  codes=True adds
+    the per-box Morton code array that cd_build_boxes fills for the tree."""
 
-    def __init__(self, count, precision, device="cuda"):
+    def __init__(self, count, precision, device="cuda", codes=False):
         ft = torch.float64 if precision == CD_FP64 else torch.float32
         self.count, self.precision = int(count), precision
         self.lo = torch.empty((3, max(count, 1)), dtype=ft, device=device)
@@ -198,6 +200,8 @@ class Boxes:
         self.t0 = torch.empty(max(count, 1), dtype=torch.int32, device=device)
         self.t1 = torch.empty(max(count, 1), dtype=torch.int32, device=device)
         self.obj = torch.empty(max(count, 1), dtype=torch.int32, device=device)
+        self.code = (torch.empty(max(count, 1), dtype=torch.int32, device=device)
+                     if codes else None)
         self.desc = cd_boxes()
         self.desc.count = self.count
         self.desc.precision = precision
@@ -207,6 +211,8 @@ class Boxes:
         self.desc.t0 = self.t0.data_ptr()
         self.desc.t1 = self.t1.data_ptr()
         self.desc.obj = self.obj.data_ptr()
+        self.desc.code = self.code.data_ptr() if codes else None
+        self.desc.code_valid = 0
 
     @classmethod
     def from_arrays(cls, lo, hi, t0, t1, obj, precision=CD_FP64, horizon_ticks=0,
@@ -373,7 +379,7 @@ class BroadPhase:
 
     def __init__(self, n, params, dt_ticks=None, box_precision=CD_FP64,
                  tree_precision=CD_FP64, capacity=None, slab_ticks=0, device="cuda",
-                 dt_heuristic_km=None, el_soa=None, dt_mlp=None):
+                 dt_heuristic_km=None, el_soa=None, dt_mlp=None, codes=True):
         """dt_heuristic_km: per-object steps from cd_dt_heuristic; dt_mlp:
         (bfloat16 weight tensor, fallback_disp_km) for steps from cd_dt_mlp.
         Either is recomputed by every build from the elements (el_soa is
@@ -386,7 +392,7 @@ class BroadPhase:
         self.n, self.params, self.dt = int(n), params, dt_ticks
         self.device = device
         self.count = cd_box_count(dt_ticks, n, params, device)
-        self.boxes = Boxes(self.count, box_precision, device)
+        self.boxes = Boxes(self.count, box_precision, device, codes=codes)
         self.tree_precision = tree_precision
         self.tree = Tree(self.count, tree_precision, device)
         self.ws_boxes = _bytes(lib().cd_build_boxes_ws(self.n), device)

@@ -32,13 +32,15 @@ class _Boxes:
         self.desc = cd_boxes()
         self.desc.count = int(count)
         self.desc.precision = precision
-        lo, hi, t0, t1, obj = arrays
+        lo, hi, t0, t1, obj, code = arrays
         for d in range(3):
             self.desc.lo[d] = lo[d].data_ptr()
             self.desc.hi[d] = hi[d].data_ptr()
         self.desc.t0 = t0.data_ptr()
         self.desc.t1 = t1.data_ptr()
         self.desc.obj = obj.data_ptr()
+        self.desc.code = code.data_ptr()
+        self.desc.code_valid = 0
 
 
 class _Tree:
@@ -69,6 +71,7 @@ class BatchRunner:
         ft = torch.float64 if box_precision == CD_FP64 else torch.float32
         self.arrays = (torch.empty((3, Nmax), dtype=ft, device=device),
                        torch.empty((3, Nmax), dtype=ft, device=device),
+                       torch.empty(Nmax, dtype=torch.int32, device=device),
                        torch.empty(Nmax, dtype=torch.int32, device=device),
                        torch.empty(Nmax, dtype=torch.int32, device=device),
                        torch.empty(Nmax, dtype=torch.int32, device=device))

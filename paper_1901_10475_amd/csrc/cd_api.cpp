@@ -160,6 +160,7 @@ BoxView view_of(const cd_boxes *b)
     v.t0 = b->t0;
     v.t1 = b->t1;
     v.obj = b->obj;
+    v.code = (b->code && b->code_valid) ? b->code : nullptr;
     return v;
 }
 
@@ -192,6 +193,7 @@ struct BoxWS {
     CountWS cnt;
     ObjConst *oc;
     uint32_t *box_off;
+    unsigned long long *frame;
     void *scan;
 };
 size_t layout_boxes(void *base, size_t bytes, int64_t n, BoxWS *w)
@@ -201,6 +203,7 @@ size_t layout_boxes(void *base, size_t bytes, int64_t n, BoxWS *w)
     c.off = off;
     w->oc = c.take<ObjConst>(n);
     w->box_off = c.take<uint32_t>(n);
+    w->frame = c.take<unsigned long long>(6);
     w->scan = c.take_bytes(scan_ws_bytes((size_t)n));
     return c.off;
 }
@@ -500,9 +503,14 @@ int cd_build_boxes(const cd_elements *el, const uint32_t *dt_ticks, const cd_par
     bo.t0 = out->t0;
     bo.t1 = out->t1;
     bo.obj = out->obj;
+    bo.code = out->code;
+    bo.frame = w.frame;
     bo.cap = (uint64_t)out->count;
+    out->code_valid = 0;
     Stage st_boxes("boxes", s);
     CD_HIP(launch_object_setup(*el, p->mu, (double)p->start_ticks * p->tick_s, w.oc, s));
+    if (out->code)
+        CD_HIP(launch_orbit_frame(w.oc, (uint32_t)n, w.frame, s));
     double half_thr = 0.5 * p->threshold_km;
     if (!dt_ticks) {
         if (p->dt_ticks == 0)
@@ -524,6 +532,7 @@ int cd_build_boxes(const cd_elements *el, const uint32_t *dt_ticks, const cd_par
         CD_HIP(launch_boxes_variable(w.oc, w.cnt.st, (uint32_t)n, T, p->tick_s, half_thr,
                                      out->precision, bo, s));
     }
+    out->code_valid = out->code ? 1 : 0;
     return CD_OK;
 }
 
@@ -600,7 +609,7 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
     const uint32_t *leaf_src = tw.idx;  // nullptr once the leaf records exist
     if (seg) {
         uint32_t m = (uint32_t)boxes->slab_size;
-        {
+        if (!bv.code) {
             Stage st("keys", s);
             CD_HIP(launch_bounds(bv, boxes->precision, (uint32_t)N, tw.bounds, s));
         }
@@ -611,11 +620,16 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
         }
         leaf_src = nullptr;
         Stage st("karras", s);
-        CD_HIP(launch_karras(tw.keys, (uint32_t)N, kids, links, tw.parent, tw.clev, false, s));
+        if (N > 1)
+            CD_HIP(launch_karras_slabs(tw.keys, (uint32_t)N, m, kids, links, tw.parent, tw.clev,
+                                       s));
+        else
+            CD_HIP(launch_karras(tw.keys, (uint32_t)N, kids, links, tw.parent, tw.clev, false, s));
     } else {
         {
             Stage st("keys", s);
-            CD_HIP(launch_bounds(bv, boxes->precision, (uint32_t)N, tw.bounds, s));
+            if (!bv.code)
+                CD_HIP(launch_bounds(bv, boxes->precision, (uint32_t)N, tw.bounds, s));
             CD_HIP(launch_keys(bv, boxes->precision, (uint32_t)N, w, max_slab, 0, tw.bounds,
                                nullptr, tw.kva, err, s));
         }

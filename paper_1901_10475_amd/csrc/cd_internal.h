@@ -56,10 +56,13 @@ struct Rec {
 struct BoxView {
     const void *lo[3], *hi[3];
     const uint32_t *t0, *t1, *obj;
+    const uint32_t *code;   // Morton codes written with the boxes, or nullptr
 };
 struct BoxOut {
     void *lo[3], *hi[3];
     uint32_t *t0, *t1, *obj;
+    uint32_t *code;                        // Morton code of each box centre, or nullptr
+    const unsigned long long *frame;       // code frame: ordered bits, min xyz, max xyz
     uint64_t cap;  // entries the arrays hold; stores beyond are dropped
 };
 
@@ -257,11 +260,31 @@ constexpr int kMlpParams = kMlpB3 + 1;   // 4609
 constexpr int kMlpOuterThreads = 256;
 constexpr int kMlpOuterSamples = 128;    // samples per outer-product block
 
+// Keys of a Karras hierarchy over time-major slabs, with one slab's 32-bit
+// codes in LDS: key(g) = slab(g) << 32 | code(g) inside the slab; outside it
+// only the slab bits are returned.  Exact for every comparison that involves a
+// key of the slab itself, since keys of different slabs differ in their slab
+// bits.
+struct SlabKeys {
+    const uint32_t *lds;
+    uint64_t base, m, hi;  // hi = this slab's index << 32
+    __device__ uint64_t operator()(int64_t gi) const
+    {
+        uint64_t g = (uint64_t)gi;
+        if (g - base < m)
+            return hi | lds[g - base];
+        return (g / m) << 32;  // other slabs: only their slab bits matter
+    }
+};
+
 // ---- launchers (each returns the launch status) -----------------------------
 
 // boxes
 hipError_t launch_object_setup(const cd_elements &el, double mu, double start_s, ObjConst *oc,
                                hipStream_t s);
+// union of the orbits' bounding boxes (ordered bits: min xyz, max xyz)
+hipError_t launch_orbit_frame(const ObjConst *oc, uint32_t n, unsigned long long *frame,
+                              hipStream_t s);
 hipError_t launch_validate(const cd_elements &el, unsigned long long *first_bad, hipStream_t s);
 hipError_t launch_steps(const uint32_t *dt, uint32_t n, uint32_t T, ObjSteps *st, uint32_t *Kc,
                         unsigned long long *total, unsigned int *bad_dt, hipStream_t s);
@@ -414,6 +437,10 @@ size_t refit_list_slots(uint32_t N, uint32_t *base);
 // build wrote them).
 hipError_t launch_karras(const uint64_t *keys, uint32_t N, uint2 *kids, Link *links,
                          uint32_t *parent, uint8_t *clev, bool leaf_links, hipStream_t s);
+// slab path (time-major slabs of slab_size leaves, slab_size <= kSegCap); the
+// leaf links are written by the slab build
+hipError_t launch_karras_slabs(const uint64_t *keys, uint32_t N, uint32_t slab_size, uint2 *kids,
+                               Link *links, uint32_t *parent, uint8_t *clev, hipStream_t s);
 // idx == nullptr: the leaf records are already written (slab build).
 hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision, uint32_t N,
                         const uint32_t *idx, const uint32_t *parent, const uint2 *kids,

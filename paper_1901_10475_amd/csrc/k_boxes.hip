@@ -44,6 +44,36 @@ __global__ void k_object_setup(cd_elements el, double mu, double start_s, ObjCon
     oc[i] = c;
 }
 
+// Union of the orbits' bounding boxes: on the ellipse,
+// x_d(E) = -a e P_d + a P_d cos E + b Q_d sin E, so x_d spans
+// -a e P_d +- sqrt((a P_d)^2 + (b Q_d)^2).  Every box centre (the midpoint of
+// two orbit points) lies inside it, so Morton codes in this frame never clamp.
+__global__ void k_orbit_frame(const ObjConst *oc, uint32_t n, unsigned long long *frame)
+{
+    uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long mn[3] = {~0ull, ~0ull, ~0ull}, mx[3] = {0ull, 0ull, 0ull};
+    if (i < n) {
+        ObjConst c = oc[i];
+        for (int d = 0; d < 3; ++d) {
+            double ctr = -c.a * c.e * c.P[d];
+            double w = sqrt(c.a * c.P[d] * c.a * c.P[d] + c.b * c.Q[d] * c.b * c.Q[d]);
+            mn[d] = ordered_bits(ctr - w);
+            mx[d] = ordered_bits(ctr + w);
+        }
+    }
+    for (int d = 0; d < 3; ++d)
+        for (int o = 32; o >= 1; o >>= 1) {
+            unsigned long long a = __shfl_xor(mn[d], o, 64), b = __shfl_xor(mx[d], o, 64);
+            mn[d] = a < mn[d] ? a : mn[d];
+            mx[d] = b > mx[d] ? b : mx[d];
+        }
+    if ((threadIdx.x & 63) == 0)
+        for (int d = 0; d < 3; ++d) {
+            atomicMin(&frame[d], mn[d]);
+            atomicMax(&frame[3 + d], mx[d]);
+        }
+}
+
 __global__ void k_validate(cd_elements el, unsigned long long *first_bad)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -118,13 +148,32 @@ __device__ inline void position(const ObjConst &c, double sE, double cE, double 
     p[2] = u * c.P[2] + v * c.Q[2];
 }
 
+// Morton frame of the box codes (decoded once per thread).
+struct CodeFrame {
+    double mn[3], inv[3];
+    __device__ explicit CodeFrame(const BoxOut &o)
+    {
+        for (int d = 0; d < 3; ++d) {
+            mn[d] = inv[d] = 0.0;
+            if (o.code) {
+                mn[d] = from_ordered_bits(o.frame[d]);
+                double ext = from_ordered_bits(o.frame[3 + d]) - mn[d];
+                inv[d] = ext > 0.0 ? 1.0 / ext : 0.0;
+            }
+        }
+    }
+};
+
 template <int PREC>
-__device__ inline void store_box(const BoxOut &o, uint64_t b, const double pa[3],
-                                 const double pb[3], double g, uint32_t t0, uint32_t t1,
-                                 uint32_t obj)
+__device__ inline void store_box(const BoxOut &o, const CodeFrame &f, uint64_t b,
+                                 const double pa[3], const double pb[3], double g, uint32_t t0,
+                                 uint32_t t1, uint32_t obj)
 {
     if (b >= o.cap)
         return;
+    if (o.code)
+        o.code[b] = morton30(0.5 * (pa[0] + pb[0]), 0.5 * (pa[1] + pb[1]),
+                             0.5 * (pa[2] + pb[2]), f.mn, f.inv);
     for (int d = 0; d < 3; ++d) {
         double lo = fmin(pa[d], pb[d]) - g;
         double hi = fmax(pa[d], pb[d]) + g;
@@ -148,6 +197,7 @@ __device__ inline void object_run(const ObjConst &c, uint32_t i, uint64_t k0, ui
                                   double half_thr, const BoxOut &out, uint64_t base,
                                   uint64_t stride)
 {
+    const CodeFrame f(out);
     uint64_t ta = k0 * dt < T ? k0 * dt : T;
     double M = c.m0 + c.n * ((double)ta * tick_s);
     double E = M + c.e * sin(M), sE, cE;
@@ -163,7 +213,7 @@ __device__ inline void object_run(const ObjConst &c, uint32_t i, uint64_t k0, ui
         position(c, sE, cE, pb);
         double g = c.vmax * ((double)(tb - ta) * tick_s) * 0.5 + half_thr;
         uint32_t t1 = (k + 1 == K) ? (uint32_t)(T + 1) : (uint32_t)tb;
-        store_box<PREC>(out, base + k * stride, pa, pb, g, (uint32_t)ta, t1, i);
+        store_box<PREC>(out, f, base + k * stride, pa, pb, g, (uint32_t)ta, t1, i);
         pa[0] = pb[0];
         pa[1] = pb[1];
         pa[2] = pb[2];
@@ -242,7 +292,8 @@ __global__ __launch_bounds__(256) void k_boxes_variable(const ObjConst *__restri
         return;
     double g = c.vmax * ((double)(tb - ta) * tick_s) * 0.5 + half_thr;
     uint32_t t1 = (k + 1 == s.K) ? (uint32_t)(T + 1) : (uint32_t)tb;
-    store_box<PREC>(out, b, pa, pb, g, (uint32_t)ta, t1, i);
+    const CodeFrame f(out);
+    store_box<PREC>(out, f, b, pa, pb, g, (uint32_t)ta, t1, i);
 }
 
 // After the interval counts have been scanned into first-box offsets.
@@ -262,6 +313,18 @@ hipError_t launch_object_setup(const cd_elements &el, double mu, double start_s,
     if (el.n == 0)
         return hipSuccess;
     k_object_setup<<<blocks_for(el.n, 256), 256, 0, s>>>(el, mu, start_s, oc);
+    return hipGetLastError();
+}
+
+hipError_t launch_orbit_frame(const ObjConst *oc, uint32_t n, unsigned long long *frame,
+                              hipStream_t s)
+{
+    hipError_t e = launch_fill_u64(frame, ~0ull, 3, s);
+    if (e == hipSuccess)
+        e = launch_fill_u64(frame + 3, 0ull, 3, s);
+    if (e != hipSuccess || n == 0)
+        return e;
+    k_orbit_frame<<<blocks_for(n, 256), 256, 0, s>>>(oc, n, frame);
     return hipGetLastError();
 }
 

@@ -5,7 +5,7 @@
 //     pair records), 8-bit digits, one histogram + scan + scatter per digit.
 //     It sorts tree keys when boxes are not grouped in slabs and it puts pair
 //     records in canonical order.
-//   * k_segment_sort: one 1024-thread workgroup per time slab; keys stay in
+//   * k_slab_build: one 1024-thread workgroup per time slab; keys stay in
 //     registers and move through LDS between digit passes, so a slab of up to
 //     kSegCap boxes is sorted with one read and one write of global memory.
 // Both rank digits stably with the same wave-level scheme: the lanes holding
@@ -175,10 +175,13 @@ __global__ __launch_bounds__(kRadThreads) void k_radix_downsweep(const uint4 *in
                                                                  const uint32_t *hist_scan,
                                                                  uint32_t nblocks)
 {
-    __shared__ uint32_t cnt[256 * kRadWaves];
+    // per-(wave, digit) counters, wave-major with a 257-word row: lanes of a
+    // wave (same w, random d) and the per-digit prefix (same d, all w) both
+    // spread over the banks
+    __shared__ uint32_t cnt[kRadWaves * 257];
     __shared__ uint32_t dbase[256];
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int k = threadIdx.x; k < 256 * kRadWaves; k += kRadThreads)
+    for (int k = threadIdx.x; k < kRadWaves * 257; k += kRadThreads)
         cnt[k] = 0;
     dbase[threadIdx.x] = hist_scan[(size_t)threadIdx.x * nblocks + blockIdx.x];
     __syncthreads();
@@ -193,10 +196,10 @@ __global__ __launch_bounds__(kRadThreads) void k_radix_downsweep(const uint4 *in
         uint32_t d = valid ? dig(item[j]) : 0u;
         uint64_t act = __ballot(valid);
         uint64_t peers = match_digit(d, act);
-        uint32_t c = valid ? cnt[d * kRadWaves + w] : 0u;
+        uint32_t c = valid ? cnt[w * 257 + d] : 0u;
         uint32_t mine = (uint32_t)__popcll(peers & lt);
         if (valid && mine == 0)
-            cnt[d * kRadWaves + w] = c + (uint32_t)__popcll(peers);
+            cnt[w * 257 + d] = c + (uint32_t)__popcll(peers);
         dg[j] = d;
         rk[j] = c + mine;
     }
@@ -204,8 +207,8 @@ __global__ __launch_bounds__(kRadThreads) void k_radix_downsweep(const uint4 *in
     {   // per digit: exclusive prefix over waves
         uint32_t d = threadIdx.x, run = 0;
         for (int ww = 0; ww < kRadWaves; ++ww) {
-            uint32_t t = cnt[d * kRadWaves + ww];
-            cnt[d * kRadWaves + ww] = run;
+            uint32_t t = cnt[ww * 257 + d];
+            cnt[ww * 257 + d] = run;
             run += t;
         }
     }
@@ -213,7 +216,7 @@ __global__ __launch_bounds__(kRadThreads) void k_radix_downsweep(const uint4 *in
     for (int j = 0; j < kRadItems; ++j) {
         size_t g = wbase + (size_t)j * 64 + lane;
         if (g < count) {
-            size_t pos = (size_t)dbase[dg[j]] + cnt[dg[j] * kRadWaves + w] + rk[j];
+            size_t pos = (size_t)dbase[dg[j]] + cnt[w * 257 + dg[j]] + rk[j];
             if (pos < count)
                 out[pos] = item[j];
         }
@@ -278,28 +281,16 @@ hipError_t radix_sort16(SortKind kind, void *a, void *b, size_t count, const Dig
 
 constexpr int kSegWaves = kSegThreads / 64;
 
-// Keys of the global sorted order seen from one slab's workgroup: leaves of
-// this slab from LDS, leaves of other slabs by their slab bits only.
-struct SlabKeys {
-    const uint32_t *lds;
-    uint64_t base, m, hi;  // hi = this slab's index << 32
-    __device__ uint64_t operator()(int64_t gi) const
-    {
-        uint64_t g = (uint64_t)gi;
-        if (g - base < m)
-            return hi | lds[g - base];
-        return (g / m) << 32;  // other slabs: only their slab bits matter
-    }
-};
-
-template <int PREC, int TP>
+template <int PREC, int TP, bool CODES>
 __global__ __launch_bounds__(kSegThreads) void k_slab_build(
     BoxView b, uint32_t slab_size, uint32_t N, uint32_t slab_ticks,
     const unsigned long long *bounds, uint64_t *__restrict__ keys_out, Link *__restrict__ links,
     void *tree, unsigned int *err)
 {
     __shared__ uint32_t xch[kSegCap];
-    __shared__ uint32_t cnt[256 * kSegWaves];
+    // counters of (digit, wave), stored wave-major with a 257-word row (see
+    // k_radix_downsweep): index w * 257 + d
+    __shared__ uint32_t cnt[kSegWaves * 257];
     __shared__ uint32_t wsum[64];
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     uint64_t slab = blockIdx.x;
@@ -308,10 +299,13 @@ __global__ __launch_bounds__(kSegThreads) void k_slab_build(
     if (base + m > N)
         m = base < N ? (uint32_t)(N - base) : 0u;
     double mn[3], inv[3];
-    for (int d = 0; d < 3; ++d) {
-        mn[d] = from_ordered_bits(bounds[d]);
-        double ext = from_ordered_bits(bounds[3 + d]) - mn[d];
-        inv[d] = ext > 0.0 ? 1.0 / ext : 0.0;
+    for (int d = 0; d < 3; ++d) {   // the frame is read only when codes are formed here
+        mn[d] = inv[d] = 0.0;
+        if (!CODES) {
+            mn[d] = from_ordered_bits(bounds[d]);
+            double ext = from_ordered_bits(bounds[3 + d]) - mn[d];
+            inv[d] = ext > 0.0 ? 1.0 / ext : 0.0;
+        }
     }
     uint32_t key[kSegItems], val[kSegItems];
     uint32_t li0 = (uint32_t)w * 64 * kSegItems + lane;
@@ -321,10 +315,14 @@ __global__ __launch_bounds__(kSegThreads) void k_slab_build(
         uint32_t li = li0 + j * 64;
         key[j] = 0xFFFFFFFFu;
         if (li < m) {
-            double lo[3], hi[3];
-            load_box<PREC>(b, base + li, lo, hi);
-            key[j] = morton30(0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]),
-                              0.5 * (lo[2] + hi[2]), mn, inv);
+            if (CODES) {   // codes written with the boxes: 4 bytes instead of 48
+                key[j] = b.code[base + li];
+            } else {
+                double lo[3], hi[3];
+                load_box<PREC>(b, base + li, lo, hi);
+                key[j] = morton30(0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]),
+                                  0.5 * (lo[2] + hi[2]), mn, inv);
+            }
             bad |= (b.t0[base + li] / slab_ticks) != slab;
         }
         val[j] = li;
@@ -333,7 +331,7 @@ __global__ __launch_bounds__(kSegThreads) void k_slab_build(
         atomicOr(err, 1u);
     uint64_t lt = lanemask_lt();
     for (int shift = 0; shift < 32; shift += 8) {
-        for (int k = threadIdx.x; k < 256 * kSegWaves; k += kSegThreads)
+        for (int k = threadIdx.x; k < kSegWaves * 257; k += kSegThreads)
             cnt[k] = 0;
         __syncthreads();
         uint32_t rk[kSegItems];  // rank inside (digit, wave), then final position
@@ -343,10 +341,10 @@ __global__ __launch_bounds__(kSegThreads) void k_slab_build(
             bool valid = li < m;
             uint32_t d = (key[j] >> shift) & 0xFFu;
             uint64_t peers = match_digit(d, __ballot(valid));
-            uint32_t c = valid ? cnt[d * kSegWaves + w] : 0u;
+            uint32_t c = valid ? cnt[w * 257 + d] : 0u;
             uint32_t mine = (uint32_t)__popcll(peers & lt);
             if (valid && mine == 0)
-                cnt[d * kSegWaves + w] = c + (uint32_t)__popcll(peers);
+                cnt[w * 257 + d] = c + (uint32_t)__popcll(peers);
             rk[j] = c + mine;
         }
         __syncthreads();
@@ -354,14 +352,16 @@ __global__ __launch_bounds__(kSegThreads) void k_slab_build(
             uint32_t v[4], sum = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                v[q] = cnt[threadIdx.x * 4 + q];
+                uint32_t o = threadIdx.x * 4 + q;   // (digit, wave) order
+                v[q] = cnt[(o % kSegWaves) * 257 + o / kSegWaves];
                 sum += v[q];
             }
             uint32_t total;
             uint32_t run = block_exclusive_scan(sum, wsum, &total);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                cnt[threadIdx.x * 4 + q] = run;
+                uint32_t o = threadIdx.x * 4 + q;
+                cnt[(o % kSegWaves) * 257 + o / kSegWaves] = run;
                 run += v[q];
             }
         }
@@ -369,7 +369,7 @@ __global__ __launch_bounds__(kSegThreads) void k_slab_build(
 #pragma unroll
         for (int j = 0; j < kSegItems; ++j) {
             uint32_t d = (key[j] >> shift) & 0xFFu;
-            rk[j] += cnt[d * kSegWaves + w];
+            rk[j] += cnt[w * 257 + d];
         }
         // keys, then values, through the exchange buffer
 #pragma unroll
@@ -421,6 +421,7 @@ __global__ __launch_bounds__(kSegThreads) void k_slab_build(
     }
 }
 
+
 hipError_t launch_slab_build(const BoxView &b, int box_precision, int tree_precision,
                              uint32_t nslabs, uint32_t slab_size, uint32_t N,
                              uint32_t slab_ticks, const unsigned long long *bounds,
@@ -431,15 +432,27 @@ hipError_t launch_slab_build(const BoxView &b, int box_precision, int tree_preci
         return hipSuccess;
     if ((int64_t)slab_size > kSegCap)
         return hipErrorInvalidValue;
-    if (box_precision == CD_FP64 && tree_precision == CD_FP64)
-        k_slab_build<CD_FP64, CD_FP64><<<nslabs, kSegThreads, 0, s>>>(
-            b, slab_size, N, slab_ticks, bounds, keys_out, links, tree, err);
-    else if (box_precision == CD_FP64)
-        k_slab_build<CD_FP64, CD_FP32><<<nslabs, kSegThreads, 0, s>>>(
-            b, slab_size, N, slab_ticks, bounds, keys_out, links, tree, err);
-    else
-        k_slab_build<CD_FP32, CD_FP32><<<nslabs, kSegThreads, 0, s>>>(
-            b, slab_size, N, slab_ticks, bounds, keys_out, links, tree, err);
+#define CD_SLAB_LAUNCH(P, T, C)                                                             \
+    k_slab_build<P, T, C><<<nslabs, kSegThreads, 0, s>>>(b, slab_size, N, slab_ticks, bounds,  \
+                                                         keys_out, links, tree, err)
+    const bool codes = b.code != nullptr;
+    if (box_precision == CD_FP64 && tree_precision == CD_FP64) {
+        if (codes)
+            CD_SLAB_LAUNCH(CD_FP64, CD_FP64, true);
+        else
+            CD_SLAB_LAUNCH(CD_FP64, CD_FP64, false);
+    } else if (box_precision == CD_FP64) {
+        if (codes)
+            CD_SLAB_LAUNCH(CD_FP64, CD_FP32, true);
+        else
+            CD_SLAB_LAUNCH(CD_FP64, CD_FP32, false);
+    } else {
+        if (codes)
+            CD_SLAB_LAUNCH(CD_FP32, CD_FP32, true);
+        else
+            CD_SLAB_LAUNCH(CD_FP32, CD_FP32, false);
+    }
+#undef CD_SLAB_LAUNCH
     return hipGetLastError();
 }
 

@@ -93,15 +93,23 @@ __global__ void k_keys(BoxView b, uint32_t N, uint32_t slab_ticks, uint32_t max_
     if (k >= N)
         return;
     double mn[3], inv[3];
-    for (int d = 0; d < 3; ++d) {
-        mn[d] = from_ordered_bits(bounds[d]);
-        double ext = from_ordered_bits(bounds[3 + d]) - mn[d];
-        inv[d] = ext > 0.0 ? 1.0 / ext : 0.0;
+    for (int d = 0; d < 3; ++d) {   // the frame is read only when codes are formed here
+        mn[d] = inv[d] = 0.0;
+        if (!b.code) {
+            mn[d] = from_ordered_bits(bounds[d]);
+            double ext = from_ordered_bits(bounds[3 + d]) - mn[d];
+            inv[d] = ext > 0.0 ? 1.0 / ext : 0.0;
+        }
     }
-    double lo[3], hi[3];
-    load_box<PREC>(b, k, lo, hi);
-    uint32_t m = morton30(0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2]),
-                          mn, inv);
+    uint32_t m;
+    if (b.code) {
+        m = b.code[k];
+    } else {
+        double lo[3], hi[3];
+        load_box<PREC>(b, k, lo, hi);
+        m = morton30(0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]), 0.5 * (lo[2] + hi[2]), mn,
+                     inv);
+    }
     uint32_t slab = b.t0[k] / slab_ticks;
     if (slab > max_slab) {
         atomicOr(err, 1u);
@@ -198,6 +206,47 @@ __global__ void k_karras(const uint64_t *__restrict__ keys, uint32_t N, uint2 *k
     }
 }
 
+// Same nodes as k_karras for time-major slabs: one workgroup per slab holds
+// the slab's sorted 32-bit codes in LDS and computes every inner node whose
+// index lies in the slab (node i's searches always compare key i, a key of the
+// slab, so the slab-bits-only view of other slabs is exact).  The binary
+// searches then wait on LDS instead of L2.  Leaf skip links come from the
+// slab build.
+__global__ __launch_bounds__(kSegThreads) void k_karras_slabs(const uint64_t *__restrict__ keys,
+                                                              uint32_t N, uint32_t slab_size,
+                                                              uint2 *kids, Link *links,
+                                                              uint32_t *parent, uint8_t *clev)
+{
+    __shared__ uint32_t sk[kSegCap];
+    uint64_t slab = blockIdx.x;
+    uint64_t base = slab * slab_size;
+    uint32_t m = (uint32_t)(base + slab_size <= N ? slab_size : N - base);
+    for (uint32_t k = threadIdx.x; k < m; k += blockDim.x)
+        sk[k] = (uint32_t)keys[base + k];
+    __syncthreads();
+    const SlabKeys K{sk, base, slab_size, slab << 32};
+    for (uint32_t k = threadIdx.x; k < m; k += blockDim.x) {
+        uint32_t i = (uint32_t)(base + k);
+        if (i + 1 >= N)
+            break;
+        KarrasNode nd = karras_node(K, N, i);
+        uint32_t lev = 0;
+        while ((uint64_t)(nd.first >> refit_shift(lev)) != (uint64_t)(nd.last >> refit_shift(lev)))
+            ++lev;
+        clev[i] = (uint8_t)lev;
+        uint32_t pv = i | (lev > 0 ? kCross : 0u);
+        parent[nd.left] = pv;
+        parent[nd.right] = pv;
+        if (i == 0)
+            parent[0] = kEnd;
+        kids[i] = make_uint2(nd.left, nd.right);
+        Link li;
+        li.link = nd.left;
+        li.esc = karras_escape(K, N, nd.last);
+        links[i] = li;
+    }
+}
+
 __global__ void k_single_leaf(Link *links, uint32_t *parent)
 {
     Link l;
@@ -217,6 +266,16 @@ hipError_t launch_karras(const uint64_t *keys, uint32_t N, uint2 *kids, Link *li
         return hipGetLastError();
     }
     k_karras<<<nblk(N - 1, 256), 256, 0, s>>>(keys, N, kids, links, parent, clev, leaf_links);
+    return hipGetLastError();
+}
+
+hipError_t launch_karras_slabs(const uint64_t *keys, uint32_t N, uint32_t slab_size, uint2 *kids,
+                               Link *links, uint32_t *parent, uint8_t *clev, hipStream_t s)
+{
+    if (N <= 1 || slab_size == 0 || (int64_t)slab_size > kSegCap)
+        return hipErrorInvalidValue;
+    uint32_t nslabs = (uint32_t)((N + slab_size - 1) / slab_size);
+    k_karras_slabs<<<nslabs, kSegThreads, 0, s>>>(keys, N, slab_size, kids, links, parent, clev);
     return hipGetLastError();
 }
 

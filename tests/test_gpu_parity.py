@@ -309,3 +309,31 @@ def test_window_boxes_and_pairs(start):
         assert_boxes_close(lo, hi, ob.lo, ob.hi, sc.elements[ob.obj, 0])
         ref = oracle.pairs(oracle.Boxes(*bp.boxes.to_host()))
         assert np.array_equal(pairs, ref)
+
+
+@pytest.mark.parametrize("heur", [None, 5.0])
+def test_box_codes_change_tree_shape_not_records(heur):
+    """Morton codes written with the boxes (orbit-frame) versus codes formed by
+    the tree builder from the boxes: the same record list."""
+    need_gpu()
+    say("codes", heur)
+    import torch
+    import paper_1901_10475_amd as cd
+    sc = catalog.scaled(catalog.tracked_hour(seed=14), n=4000, horizon_ticks=90_000)
+    el = cd.soa(sc.elements)
+    p = cd.params_struct(sc.tick_s, sc.mu, sc.threshold_km, sc.horizon_ticks,
+                         sc.dt_ticks if heur is None else 0)
+    out = []
+    for codes in (True, False):
+        for tp in (cd.CD_FP64, cd.CD_FP32):
+            bp = cd.BroadPhase(sc.n, p, None, cd.CD_FP64, tp, codes=codes,
+                               dt_heuristic_km=heur, el_soa=el)
+            out.append((codes, tp, bp.run(el).cpu().numpy().copy()))
+            if codes:
+                c = bp.boxes.code[:bp.count].cpu().numpy().view(np.uint32)
+                assert bp.boxes.desc.code_valid == 1
+                assert c.max() < (1 << 30) and len(np.unique(c)) > bp.count // 10
+    by = {(c, tp): r for c, tp, r in out}
+    assert np.array_equal(by[(True, cd.CD_FP64)], by[(False, cd.CD_FP64)])
+    assert np.array_equal(by[(True, cd.CD_FP32)], by[(False, cd.CD_FP32)])
+    assert len(by[(True, cd.CD_FP64)]) > 0
