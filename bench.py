@@ -42,12 +42,13 @@ HBM_PEAK_GBS = 8000.0
 # Summary and commands: profiles/tracked16848_1h_fp64.md
 COPY_FETCH_KIB, COPY_WRITE_KIB = 524308.5625, 1048576.0
 TRAFFIC = {
-    ("sort", "fp64", "fixed"): {"fetch_kib": 3621587.0, "write_kib": 5090350.0,
-                       "source": "paper_1901_10475_amd/csrc/k_sort.hip",
-                       "sha1": "6ca6284c7b18e59d6201e0b9a212d8c1bba54631"},
-    ("refit", "fp64", "fixed"): {"fetch_kib": 2704670.0 + 300841.0 * 4, "write_kib": 3774597.0 + 93490 * 4,
-                        "source": "paper_1901_10475_amd/csrc/k_tree.hip",
-                        "sha1": "924db231a0b1ebdbfbb178721fe55c525f2abf65"},
+    ("sort", "fp64", "fixed"): {"fetch_kib": 2143257.0, "write_kib": 4937829.0,
+                                "source": "paper_1901_10475_amd/csrc/k_sort.hip",
+                                "sha1": "c1f97b9d28e605f89b7d79554e6819be7f5d0cc6"},
+    ("refit", "fp64", "fixed"): {"fetch_kib": 2702337.0 + 323155.0,
+                                 "write_kib": 3774284.0 + 103963.0,
+                                 "source": "paper_1901_10475_amd/csrc/k_tree.hip",
+                                 "sha1": "46b8593eb1623a1e76c222e5c57f033106560748"},
 }
 
 
@@ -76,8 +77,9 @@ def algorithmic_bytes(stage, N, n, P, tree_prec, box_prec):
     table = {
         "boxes": N * box,                                    # boxes written
         "keys": 0,                                           # sampled frame only
-        "sort": N * box + N * 8 + N * node,                  # slab build: boxes in; sorted
-                                                             # keys and leaf records out
+        "sort": N * (4 + 4) + N * box + N * 8 + N * node,    # slab build: codes and tags,
+                                                             # then boxes in; sorted keys
+                                                             # and leaf records out
         "karras": N * 8 + (N - 1) * (8 + 1) + nodes * (8 + 4),  # keys in; kids, level,
                                                              # links, parents out
         "refit": N * node + nodes * 4 + (N - 1) * (8 + 8) + (N - 1) * node,
