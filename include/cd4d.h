@@ -274,6 +274,27 @@ int cd_graph_end(cd_stream_t stream, cd_graph *graph_out);
 int cd_graph_launch(cd_graph graph, cd_stream_t stream);
 int cd_graph_destroy(cd_graph graph);
 
+/* ---- narrow phase: the first collision (Alg. Brute Force over candidates) */
+
+/* For record r of pairs[0..count) (as returned by cd_query_pairs for the same
+ * elements and params): witness_out[r] = the first instant t, in ticks
+ * relative to the horizon's start like the records, with t_lo <= t < t_hi,
+ * t <= T and start_ticks + t a multiple of delta_ticks (the instants 0,
+ * delta, 2 delta, ... of Alg. Brute Force), at which
+ * ||p_i(t) - p_j(t)||_inf <= threshold_km (the occupancy cubes of radius
+ * thr / 2 touch or overlap, Def. Occupancy Region); CD_NO_WITNESS if none.
+ * first_out (device uint64, nullable) receives min over records of
+ * (t << 32 | r): the earliest collision and, among equal instants, the first
+ * record in canonical order, i.e. the smallest (i, j); ~0 if no record has
+ * one.  Positions are those of cd_build_boxes (FP64 Kepler propagation).
+ * Because every collision instant lies inside some record (the boxes are
+ * conservative), the result equals Alg. Brute Force's first collision.
+ * delta_ticks >= 1.  Async. */
+#define CD_NO_WITNESS 0xFFFFFFFFu
+int cd_first_witness(const cd_elements *el, const cd_params *p, uint32_t delta_ticks,
+                     const cd_pair *pairs, int64_t count, uint32_t *witness_out,
+                     unsigned long long *first_out, cd_stream_t stream);
+
 /* ---- learned per-object step ------------------------------------------- */
 
 /* The paper keeps a time interval per object so that objects far from all

@@ -109,6 +109,8 @@ def lib():
             "cd_graph_end": (ctypes.c_int, [_vp, P(_vp)]),
             "cd_graph_launch": (ctypes.c_int, [_vp, _vp]),
             "cd_graph_destroy": (ctypes.c_int, [_vp]),
+            "cd_first_witness": (ctypes.c_int, [P(cd_elements), P(cd_params), u32, _vp, i64, _vp,
+                                                _vp, _vp]),
             "cd_mlp_features": (ctypes.c_int, [P(cd_elements), P(cd_params), _vp, _vp]),
             "cd_dt_mlp": (ctypes.c_int, [P(cd_elements), _vp, dbl, P(cd_params), _vp, _vp,
                                          _vp]),
@@ -133,7 +135,7 @@ EXPORTED = ("cd_status_string", "cd_last_error", "cd_version", "cd_profile_enabl
             "cd_build_boxes_ws", "cd_build_boxes", "cd_tree_bytes", "cd_build_tree_ws",
             "cd_build_tree", "cd_query_pairs_ws", "cd_query_pairs", "cd_query_pairs_async",
             "cd_set_tuning", "cd_get_tuning", "cd_graph_begin", "cd_graph_end",
-            "cd_graph_launch", "cd_graph_destroy", "cd_mlp_features",
+            "cd_graph_launch", "cd_graph_destroy", "cd_first_witness", "cd_mlp_features",
             "cd_dt_mlp", "cd_mlp_forward", "cd_mlp_grad_ws", "cd_mlp_grad", "cd_mlp_adam",
             "cd_pair_object_counts")
 
@@ -366,6 +368,35 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+CD_NO_WITNESS = 0xFFFFFFFF
+
+
+def cd_first_witness(el_soa, params, delta_ticks, pairs):
+    """Narrow phase over records (int32 [P, 4] CUDA tensor): (witness int32 [P]
+    -- CD_NO_WITNESS read as uint32 where none --, first int64 [1] on the
+    device = min over records of (t << 32 | record))."""
+    if not (pairs.is_cuda and pairs.dtype == torch.int32 and pairs.dim() == 2
+            and pairs.shape[1] == 4 and pairs.is_contiguous()):
+        raise ValueError("pairs: need a contiguous int32 CUDA tensor [P, 4]")
+    el = elements_struct(el_soa)
+    P = int(pairs.shape[0])
+    wit = torch.empty(max(P, 1), dtype=torch.int32, device=pairs.device)
+    first = torch.empty(1, dtype=torch.int64, device=pairs.device)
+    _check(lib().cd_first_witness(ctypes.byref(el), ctypes.byref(params), int(delta_ticks),
+                                  _ptr(pairs), P, _ptr(wit), _ptr(first), _stream()))
+    return wit[:P], first
+
+
+def first_collision(pairs, first):
+    """(t, i, j) of the earliest collision from cd_first_witness's result, or None."""
+    v = int(first.item()) & 0xFFFFFFFFFFFFFFFF
+    if v == 0xFFFFFFFFFFFFFFFF:
+        return None
+    t, r = v >> 32, v & 0xFFFFFFFF
+    i, j = (int(x) & 0xFFFFFFFF for x in pairs[r, :2].tolist())
+    return t, i, j
 
 
 class BroadPhase:

@@ -929,6 +929,27 @@ int cd_graph_destroy(cd_graph graph)
     return CD_OK;
 }
 
+int cd_first_witness(const cd_elements *el, const cd_params *p, uint32_t delta_ticks,
+                     const cd_pair *pairs, int64_t count, uint32_t *witness_out,
+                     unsigned long long *first_out, cd_stream_t stream)
+{
+    int rc = check_elements(el);
+    if (!rc)
+        rc = check_params(p);
+    if (rc)
+        return rc;
+    if (delta_ticks == 0)
+        return fail(CD_E_INVALID, "delta_ticks must be >= 1");
+    if (count < 0)
+        return fail(CD_E_INVALID, "count < 0");
+    if (count > 0 && (!pairs || !witness_out))
+        return fail(CD_E_INVALID, "pairs or witness_out is NULL");
+    CD_HIP(launch_first_witness(*el, p->mu, p->tick_s, p->start_ticks, p->threshold_km,
+                                p->horizon_ticks, delta_ticks, pairs, (uint64_t)count,
+                                witness_out, first_out, (hipStream_t)stream));
+    return CD_OK;
+}
+
 // ---- learned per-object step ---------------------------------------------------------
 
 struct MlpWS {

@@ -315,6 +315,11 @@ hipError_t launch_mlp_adam(float *w, float *m, float *v, const float *g, int64_t
                            hipStream_t s);
 hipError_t launch_pair_object_counts(const cd_pair *pairs, uint64_t count, uint32_t n,
                                      uint32_t *counts, hipStream_t s);
+// narrow phase
+hipError_t launch_first_witness(const cd_elements &el, double mu, double tick_s, uint32_t start,
+                                double thr, uint32_t T, uint32_t delta, const cd_pair *pairs,
+                                uint64_t count, uint32_t *witness, unsigned long long *first,
+                                hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t count, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, size_t count,
                            hipStream_t s);

@@ -13,6 +13,7 @@
 // each endpoint is solved once.  With a uniform step the boxes are written
 // time-major (box k * n + i), so the lanes of a wave store consecutive boxes.
 #include "cd_internal.h"
+#include "orbit.h"
 
 namespace cd {
 
@@ -22,26 +23,8 @@ __global__ void k_object_setup(cd_elements el, double mu, double start_s, ObjCon
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= el.n)
         return;
-    double a = el.a[i], e = el.e[i];
-    double ci, si, cO, sO, cw, sw;
-    sincos(el.inc[i], &si, &ci);
-    sincos(el.raan[i], &sO, &cO);
-    sincos(el.argp[i], &sw, &cw);
-    ObjConst c;
-    c.a = a;
-    c.e = e;
-    c.b = a * sqrt(1.0 - e * e);
-    c.n = sqrt(mu / (a * a * a));
-    c.m0 = el.m0[i] + c.n * start_s;
-    c.vmax = sqrt(mu * (1.0 + e) / (a * (1.0 - e)));
-    // R_z(raan) R_x(inc) R_z(argp) applied to the perifocal x and y axes
-    c.P[0] = cO * cw - sO * sw * ci;
-    c.P[1] = sO * cw + cO * sw * ci;
-    c.P[2] = sw * si;
-    c.Q[0] = -cO * sw - sO * cw * ci;
-    c.Q[1] = -sO * sw + cO * cw * ci;
-    c.Q[2] = cw * si;
-    oc[i] = c;
+    oc[i] = object_const(el.a[i], el.e[i], el.inc[i], el.raan[i], el.argp[i], el.m0[i], mu,
+                         start_s);
 }
 
 // Union of the orbits' bounding boxes: on the ellipse,
@@ -119,33 +102,6 @@ __global__ void k_dt_heuristic(cd_elements el, double mu, double tick_s, double 
     double a = el.a[i], e = el.e[i];
     double vmax = sqrt(mu * (1.0 + e) / (a * (1.0 - e)));
     dt_out[i] = heuristic_step(vmax, tick_s, max_disp, T);
-}
-
-// Newton on Kepler's equation E - e sin E = M from the guess in E.  Returns
-// sin E and cos E at the converged E (first-order corrected for the last step).
-__device__ inline void kepler(double M, double e, double &E, double &sE, double &cE)
-{
-    for (int it = 0; it < 40; ++it) {
-        sincos(E, &sE, &cE);
-        double d = (E - e * sE - M) / (1.0 - e * cE);
-        E -= d;
-        if (fabs(d) <= 1e-15 * (1.0 + fabs(E))) {
-            double s0 = sE;
-            sE = sE - cE * d;
-            cE = cE + s0 * d;
-            return;
-        }
-    }
-    sincos(E, &sE, &cE);
-}
-
-__device__ inline void position(const ObjConst &c, double sE, double cE, double p[3])
-{
-    double u = c.a * (cE - c.e);
-    double v = c.b * sE;
-    p[0] = u * c.P[0] + v * c.Q[0];
-    p[1] = u * c.P[1] + v * c.Q[1];
-    p[2] = u * c.P[2] + v * c.Q[2];
 }
 
 // Morton frame of the box codes (decoded once per thread).
