@@ -251,10 +251,34 @@ def run_tracked(args, log):
            "pairs": P, "planted_recall": recall,
            "stages_ms": {k: round(v[0] / v[1], 4) for k, v in stages.items()},
            "roofline": _roofline(stages, N, sc.n, P, prec, box_prec, args.precision, args.dt)}
+    out["narrow_phase"] = narrow_phase(cd, el, p, pairs, log)
     if not args.no_cpu_baseline and args.dt == "fixed":
         log("[bench] CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
     return out
+
+
+def narrow_phase(cd, el, p, pairs, log, delta=1, reps=5):
+    """The first collision instant of every record at every tick (delta = 1),
+    timed after the broad-phase steps (it is not part of a step)."""
+    import torch
+    wit, first = cd.cd_first_witness(el, p, delta, pairs)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        wit, first = cd.cd_first_witness(el, p, delta, pairs)
+        b.record()
+    torch.cuda.synchronize()
+    ms = sorted(a.elapsed_time(b) for a, b in ev)[reps // 2]
+    fc = cd.first_collision(pairs, first)
+    hits = int((wit != -1).sum().item())
+    log(f"[bench] narrow phase (delta {delta} tick): {ms:.3f} ms, {hits} records with a "
+        f"collision, first {fc}")
+    return {"delta_ticks": delta, "ms": round(ms, 4), "records": int(pairs.shape[0]),
+            "records_with_collision": hits,
+            "first_collision": None if fc is None else {"t_ticks": fc[0], "i": fc[1],
+                                                        "j": fc[2]}}
 
 
 def run_batch(args, log):
