@@ -24,6 +24,10 @@ _u32pp = ctypes.POINTER(_u32p)
 _dp = ctypes.c_void_p
 
 
+class _Iv(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_double), ("hi", ctypes.c_double)]
+
+
 def build(verbose=False):
     """Compile the oracle (gcc, -O2, OpenMP; no fast-math, no FMA contraction)."""
     cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fPIC",
@@ -59,8 +63,19 @@ def lib():
         L.or_box_count.argtypes = [ctypes.c_int64, _dp, ctypes.c_uint32]
         L.or_boxes.restype = ctypes.c_int
         L.or_boxes.argtypes = [ctypes.c_int64, _dp, _dp, ctypes.c_uint32, ctypes.c_uint32,
-                               ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                _dp, _dp, _dp, _dp, _dp]
+        for nm in ("add", "sub", "mul", "div"):
+            f = getattr(L, "or_iv_" + nm)
+            f.restype = _Iv
+            f.argtypes = [_Iv, _Iv]
+        for nm in ("sqr", "cos", "sin"):
+            f = getattr(L, "or_iv_" + nm)
+            f.restype = _Iv
+            f.argtypes = [_Iv]
+        L.or_box_interval.restype = None
+        L.or_box_interval.argtypes = [_dp, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_int, _dp, _dp]
         L.or_pairs.restype = ctypes.c_int64
         L.or_pairs.argtypes = [ctypes.c_int64, _dp, _dp, _dp, _dp, _dp, _u32pp]
         L.or_pairs_of.restype = ctypes.c_int64
@@ -152,8 +167,13 @@ class Boxes:
         return Boxes(self.lo[idx], self.hi[idx], self.t0[idx], self.t1[idx], self.obj[idx])
 
 
-def boxes(elements, dt, T, tick_s, thr_km, mu=MU_EARTH, start=0):
-    """Boxes over absolute ticks [start, start + T], tags relative to start."""
+BOX_SPEED, BOX_INTERVAL_NU, BOX_INTERVAL_E = 0, 1, 2
+
+
+def boxes(elements, dt, T, tick_s, thr_km, mu=MU_EARTH, start=0, rule=BOX_SPEED):
+    """Boxes over absolute ticks [start, start + T], tags relative to start.
+    rule: BOX_SPEED (endpoint hull + vmax growth) or an interval evaluation
+    over the true (BOX_INTERVAL_NU) or eccentric (BOX_INTERVAL_E) anomaly."""
     el = _c(elements, np.float64).reshape(-1, 6)
     n = len(el)
     dt = _c(np.broadcast_to(np.asarray(dt, dtype=np.uint32), (n,)), np.uint32)
@@ -166,10 +186,32 @@ def boxes(elements, dt, T, tick_s, thr_km, mu=MU_EARTH, start=0):
     t1 = np.zeros(N, np.uint32)
     obj = np.zeros(N, np.uint32)
     rc = lib().or_boxes(n, _ptr(el), _ptr(dt), int(T), int(start), float(tick_s), float(mu),
-                        float(thr_km), _ptr(lo), _ptr(hi), _ptr(t0), _ptr(t1), _ptr(obj))
+                        float(thr_km), int(rule), _ptr(lo), _ptr(hi), _ptr(t0), _ptr(t1),
+                        _ptr(obj))
     if rc != 0:
         raise ValueError("invalid box parameters")
     return Boxes(lo, hi, t0, t1, obj)
+
+
+def iv(lo, hi=None):
+    return _Iv(float(lo), float(lo if hi is None else hi))
+
+
+def iv_op(name, *args):
+    """Interval operation or_iv_<name> on (lo, hi) pairs; returns (lo, hi)."""
+    r = getattr(lib(), "or_iv_" + name)(*[iv(*a) for a in args])
+    return (r.lo, r.hi)
+
+
+def box_interval(el, ta_s, tb_s, thr_km, var, mu=MU_EARTH):
+    """occ-int of one object over [ta_s, tb_s] by interval evaluation over the
+    true (var=1) or eccentric (var=2) anomaly: (lo[3], hi[3])."""
+    el = _c(el, np.float64)
+    lo = np.zeros(3)
+    hi = np.zeros(3)
+    lib().or_box_interval(_ptr(el), float(ta_s), float(tb_s), float(mu), float(thr_km),
+                          int(var), _ptr(lo), _ptr(hi))
+    return lo, hi
 
 
 def _take_records(n, ptr, width):

@@ -20,6 +20,9 @@
  *     positions grown by vmax*(t_b - t_a)/2 plus the radius r = thr/2, with
  *     vmax the perigee speed.  It contains every position in the interval
  *     (the speed bound) and equals occ at a single instant (Property 1).
+ *     The alternative occ-int of Sec. 4.5, an interval evaluation of h over
+ *     the range of the single variable (nu, or the eccentric anomaly), is
+ *     or_box_interval; or_boxes takes either by its rule argument.
  *   - Time tags are half-open on the integer tick grid, [t_k, t_{k+1}); the
  *     last interval is clamped at T as advanceTime does and its tag is closed
  *     at T, stored as [t_{K-1}, T + 1).
@@ -38,6 +41,7 @@
 #endif
 
 static const double OR_TWO_PI = 6.283185307179586476925286766559;
+static const double OR_PI = 3.1415926535897932384626433832795;
 
 /* ------------------------------------------------------------------------ */
 /* Dynamics                                                                  */
@@ -111,6 +115,199 @@ double or_vmax(double a, double e, double mu)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Interval arithmetic (Sec. 4.5)                                            */
+/* ------------------------------------------------------------------------ */
+
+/* Every operation rounds to nearest and then moves each bound one ulp
+ * outward, so the true result of the operation on any points of the operand
+ * intervals lies inside the returned interval. */
+static double iv_dn(double x) { return nextafter(x, -INFINITY); }
+static double iv_up(double x) { return nextafter(x, INFINITY); }
+
+or_iv or_iv_make(double lo, double hi)
+{
+    or_iv r = { lo, hi };
+    return r;
+}
+
+or_iv or_iv_add(or_iv a, or_iv b)
+{
+    return or_iv_make(iv_dn(a.lo + b.lo), iv_up(a.hi + b.hi));
+}
+
+or_iv or_iv_sub(or_iv a, or_iv b)
+{
+    return or_iv_make(iv_dn(a.lo - b.hi), iv_up(a.hi - b.lo));
+}
+
+or_iv or_iv_mul(or_iv a, or_iv b)
+{
+    double p[4] = { a.lo * b.lo, a.lo * b.hi, a.hi * b.lo, a.hi * b.hi };
+    double mn = p[0], mx = p[0];
+    for (int k = 1; k < 4; ++k) {
+        mn = fmin(mn, p[k]);
+        mx = fmax(mx, p[k]);
+    }
+    return or_iv_make(iv_dn(mn), iv_up(mx));
+}
+
+/* b must not contain 0 */
+or_iv or_iv_div(or_iv a, or_iv b)
+{
+    double p[4] = { a.lo / b.lo, a.lo / b.hi, a.hi / b.lo, a.hi / b.hi };
+    double mn = p[0], mx = p[0];
+    for (int k = 1; k < 4; ++k) {
+        mn = fmin(mn, p[k]);
+        mx = fmax(mx, p[k]);
+    }
+    return or_iv_make(iv_dn(mn), iv_up(mx));
+}
+
+/* x * x as one operation (the tight square, free of the dependency problem) */
+or_iv or_iv_sqr(or_iv a)
+{
+    double l2 = a.lo * a.lo, h2 = a.hi * a.hi;
+    if (a.lo >= 0.0)
+        return or_iv_make(iv_dn(l2), iv_up(h2));
+    if (a.hi <= 0.0)
+        return or_iv_make(iv_dn(h2), iv_up(l2));
+    return or_iv_make(0.0, iv_up(fmax(l2, h2)));
+}
+
+/* cos over [lo, hi]: the end values, widened by two ulps for the library's
+ * rounding, and 1 or -1 where an even or odd multiple of pi lies inside (with
+ * a relative slack of 1e-12, so an extremum at an end is never missed). */
+or_iv or_iv_cos(or_iv x)
+{
+    if (!(x.hi - x.lo < OR_TWO_PI))
+        return or_iv_make(-1.0, 1.0);
+    double ca = cos(x.lo), cb = cos(x.hi);
+    double mn = iv_dn(iv_dn(fmin(ca, cb))), mx = iv_up(iv_up(fmax(ca, cb)));
+    double k0 = ceil(x.lo / OR_PI - 1e-12), k1 = floor(x.hi / OR_PI + 1e-12);
+    for (double k = k0; k <= k1; k += 1.0) {
+        if (fmod(fabs(k), 2.0) == 0.0)
+            mx = 1.0;
+        else
+            mn = -1.0;
+    }
+    return or_iv_make(fmax(mn, -1.0), fmin(mx, 1.0));
+}
+
+/* sin over [lo, hi]: likewise, with the extrema at pi/2 + k pi (1 for even
+ * k, -1 for odd k). */
+or_iv or_iv_sin(or_iv x)
+{
+    if (!(x.hi - x.lo < OR_TWO_PI))
+        return or_iv_make(-1.0, 1.0);
+    double sa = sin(x.lo), sb = sin(x.hi);
+    double mn = iv_dn(iv_dn(fmin(sa, sb))), mx = iv_up(iv_up(fmax(sa, sb)));
+    double k0 = ceil(x.lo / OR_PI - 0.5 - 1e-12), k1 = floor(x.hi / OR_PI - 0.5 + 1e-12);
+    for (double k = k0; k <= k1; k += 1.0) {
+        if (fmod(fabs(k), 2.0) == 0.0)
+            mx = 1.0;
+        else
+            mn = -1.0;
+    }
+    return or_iv_make(fmax(mn, -1.0), fmin(mx, 1.0));
+}
+
+/* Eccentric anomaly of object el at time t_s, in [0, 2 pi). */
+static double or_ecc_at(const double el[6], double t_s, double mu)
+{
+    double a = el[0], e = el[1], m0 = el[5];
+    double M = fmod(m0 + sqrt(mu / (a * a * a)) * t_s, OR_TWO_PI);
+    if (M < 0.0)
+        M += OR_TWO_PI;
+    return or_eccentric_anomaly(M, e);
+}
+
+/* occ-int by interval evaluation (Sec. 4.5): simulate the single variable x
+ * at both ends of [t_a, t_b], then evaluate h over [x(t_a), x(t_b)] in
+ * interval arithmetic and add the radius thr / 2.  P and Q are the perifocal
+ * axes in ECI (the three rotations of Sec. 7.1 applied to the plane's x and y
+ * axes).
+ *
+ * var = 1: x is the true anomaly nu (the variable Sec. 7.1 names) and h is
+ *   the orbit equation r = p / (1 + e cos nu), p = a (1 - e^2), followed by
+ *   (r cos nu) P + (r sin nu) Q.
+ * var = 2: x is the eccentric anomaly E (it too solves a single-variable ODE,
+ *   E' = n / (1 - e cos E)); coordinate d of a (cos E - e) P + b sin E Q,
+ *   b = a sqrt(1 - e^2), is written as the one sinusoid
+ *   -a e P_d + R_d cos(E - phi_d), R_d = sqrt((a P_d)^2 + (b Q_d)^2),
+ *   phi_d = atan2(b Q_d, a P_d), in which E occurs once, so the interval
+ *   evaluation has no dependency overestimate.
+ * Both variables increase with t, so over [t_a, t_b] x stays between its end
+ * values, taken unwrapped (the forward difference mod 2 pi), and covers the
+ * whole turn when the mean anomaly advances 2 pi or more.  The range is
+ * widened by 1e-10 rad for the rounding of the two end solutions, each
+ * coefficient of P and Q by 4 DBL_EPSILON, and R_d, phi_d and the centre
+ * term by 4 ulps. */
+void or_box_interval(const double el[6], double ta_s, double tb_s, double mu, double thr_km,
+                     int var, double lo[3], double hi[3])
+{
+    double a = el[0], e = el[1], inc = el[2], raan = el[3], argp = el[4];
+    double n_mean = sqrt(mu / (a * a * a));
+    double dM = n_mean * (tb_s - ta_s);
+    const double w = 1e-10;
+    or_iv x;
+    if (dM >= OR_TWO_PI) {
+        x = or_iv_make(0.0, OR_TWO_PI);
+    } else {
+        double xa, xb, rate;
+        if (var == 1) {
+            xa = or_true_anomaly(el, ta_s, mu);
+            xb = or_true_anomaly(el, tb_s, mu);
+            rate = sqrt((1.0 + e) / ((1.0 - e) * (1.0 - e) * (1.0 - e)));   /* max dnu/dM */
+        } else {
+            xa = or_ecc_at(el, ta_s, mu);
+            xb = or_ecc_at(el, tb_s, mu);
+            rate = 1.0 / (1.0 - e);                                         /* max dE/dM */
+        }
+        double d = xb - xa;
+        while (d < 0.0)
+            d += OR_TWO_PI;
+        /* an advance beyond the largest possible one is a rounding wrap of a
+         * tiny step */
+        if (d > dM * rate * (1.0 + 1e-9) + 1e-9)
+            d = 0.0;
+        x = or_iv_make(xa - w, xa + d + w);
+    }
+    double ci = cos(inc), si = sin(inc), cO = cos(raan), sO = sin(raan), cw = cos(argp),
+           sw = sin(argp);
+    double P[3] = { cO * cw - sO * sw * ci, sO * cw + cO * sw * ci, sw * si };
+    double Q[3] = { -cO * sw - sO * cw * ci, -sO * sw + cO * cw * ci, cw * si };
+    or_iv pos[3];
+    if (var == 1) {
+        or_iv C = or_iv_cos(x), S = or_iv_sin(x);
+        or_iv one = or_iv_make(1.0, 1.0), ee = or_iv_make(e, e);
+        or_iv p = or_iv_mul(or_iv_make(a, a), or_iv_sub(one, or_iv_sqr(ee)));
+        or_iv r = or_iv_div(p, or_iv_add(one, or_iv_mul(ee, C)));
+        or_iv X = or_iv_mul(r, C), Y = or_iv_mul(r, S);
+        for (int d = 0; d < 3; ++d) {
+            or_iv Pd = or_iv_make(P[d] - 4.0 * DBL_EPSILON, P[d] + 4.0 * DBL_EPSILON);
+            or_iv Qd = or_iv_make(Q[d] - 4.0 * DBL_EPSILON, Q[d] + 4.0 * DBL_EPSILON);
+            pos[d] = or_iv_add(or_iv_mul(X, Pd), or_iv_mul(Y, Qd));
+        }
+    } else {
+        double b = a * sqrt(1.0 - e * e);
+        for (int d = 0; d < 3; ++d) {
+            double A = a * P[d], B = b * Q[d];
+            double R = sqrt(A * A + B * B), phi = atan2(B, A), c = -a * e * P[d];
+            double ur = 4.0 * DBL_EPSILON * R + 4.0 * DBL_EPSILON * a;
+            double uc = 4.0 * DBL_EPSILON * a;
+            or_iv arg = or_iv_sub(x, or_iv_make(phi - 4.0 * DBL_EPSILON * (1.0 + fabs(phi)),
+                                                phi + 4.0 * DBL_EPSILON * (1.0 + fabs(phi))));
+            pos[d] = or_iv_add(or_iv_make(c - uc, c + uc),
+                               or_iv_mul(or_iv_make(R - ur, R + ur), or_iv_cos(arg)));
+        }
+    }
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = iv_dn(pos[d].lo - 0.5 * thr_km);
+        hi[d] = iv_up(pos[d].hi + 0.5 * thr_km);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* 4D boxes                                                                  */
 /* ------------------------------------------------------------------------ */
 
@@ -139,10 +336,10 @@ int64_t or_box_count(int64_t n, const uint32_t *dt, uint32_t T)
  * with the last tag closed at T.  That gives the 4D occupancy region
  * occ-int x interval of Def. 4D Occupancy Region. */
 int or_boxes(int64_t n, const double *el, const uint32_t *dt, uint32_t T, uint32_t start,
-             double tick_s, double mu, double thr_km,
+             double tick_s, double mu, double thr_km, int rule,
              double *lo, double *hi, uint32_t *t0, uint32_t *t1, uint32_t *obj)
 {
-    if (T == UINT32_MAX)
+    if (T == UINT32_MAX || rule < 0 || rule > 2)
         return -1;
     int64_t b = 0;
     for (int64_t i = 0; i < n; ++i) {
@@ -154,13 +351,19 @@ int or_boxes(int64_t n, const double *el, const uint32_t *dt, uint32_t T, uint32
         for (uint64_t k = 0; k < K; ++k, ++b) {
             uint64_t ta = k * dt[i] < T ? k * dt[i] : T;
             uint64_t tb = (k + 1) * dt[i] < T ? (k + 1) * dt[i] : T;
-            double pa[3], pb[3];
-            or_position(e6, (double)(start + ta) * tick_s, mu, pa);
-            or_position(e6, (double)(start + tb) * tick_s, mu, pb);
-            double g = vmax * ((double)(tb - ta) * tick_s) / 2.0 + thr_km / 2.0;
-            for (int d = 0; d < 3; ++d) {
-                lo[3 * b + d] = fmin(pa[d], pb[d]) - g;
-                hi[3 * b + d] = fmax(pa[d], pb[d]) + g;
+            if (rule == 1 || rule == 2) {
+                or_box_interval(e6, (double)(start + ta) * tick_s,
+                                (double)(start + tb) * tick_s, mu, thr_km, rule, lo + 3 * b,
+                                hi + 3 * b);
+            } else {
+                double pa[3], pb[3];
+                or_position(e6, (double)(start + ta) * tick_s, mu, pa);
+                or_position(e6, (double)(start + tb) * tick_s, mu, pb);
+                double g = vmax * ((double)(tb - ta) * tick_s) / 2.0 + thr_km / 2.0;
+                for (int d = 0; d < 3; ++d) {
+                    lo[3 * b + d] = fmin(pa[d], pb[d]) - g;
+                    hi[3 * b + d] = fmax(pa[d], pb[d]) + g;
+                }
             }
             t0[b] = (uint32_t)ta;
             t1[b] = (k + 1 == K) ? T + 1 : (uint32_t)tb;

@@ -45,8 +45,25 @@ int64_t or_box_count(int64_t n, const uint32_t *dt, uint32_t T);
  * is the same problem over a shifted time interval).
  * Returns 0, or -1 on invalid input (dt = 0, T + 1 overflow). */
 int or_boxes(int64_t n, const double *el, const uint32_t *dt, uint32_t T, uint32_t start,
-             double tick_s, double mu, double thr_km,
+             double tick_s, double mu, double thr_km, int rule,
              double *lo, double *hi, uint32_t *t0, uint32_t *t1, uint32_t *obj);
+
+/* ---- interval arithmetic and the interval-evaluation box (Sec. 4.5) ---- */
+/* rule of or_boxes: 0 the speed-bound box; 1 or 2 or_box_interval over the
+ * true (1) or eccentric (2) anomaly */
+typedef struct {
+    double lo, hi;
+} or_iv;
+or_iv or_iv_make(double lo, double hi);
+or_iv or_iv_add(or_iv a, or_iv b);
+or_iv or_iv_sub(or_iv a, or_iv b);
+or_iv or_iv_mul(or_iv a, or_iv b);
+or_iv or_iv_div(or_iv a, or_iv b);
+or_iv or_iv_sqr(or_iv a);
+or_iv or_iv_cos(or_iv x);
+or_iv or_iv_sin(or_iv x);
+void or_box_interval(const double el[6], double ta_s, double tb_s, double mu, double thr_km,
+                     int var, double lo[3], double hi[3]);
 
 /* ---- pair sets: the plain definition, all box pairs tested -------------- */
 /* Literal all-pairs over N boxes.  *out receives a malloc'd, canonical
