@@ -41,6 +41,10 @@ HBM_PEAK_GBS = 8000.0
 # the kernel source it was taken on: reported as null once that file changes.
 # Summary and commands: profiles/tracked16848_1h_fp64.md
 COPY_FETCH_KIB, COPY_WRITE_KIB = 524308.5625, 1048576.0
+# box rule of cd_params (CD_BOX_SPEED, CD_BOX_INTERVAL_NU, CD_BOX_INTERVAL_E)
+BOX_RULES = {"speed": 0, "nu": 1, "ecc": 2}
+BOX_SUFFIX = {"speed": "", "nu": "_box_interval_nu", "ecc": "_box_interval_ecc"}
+
 TRAFFIC = {
     ("sort", "fp64", "fixed"): {"fetch_kib": 2143257.0, "write_kib": 4937829.0,
                                 "source": "paper_1901_10475_amd/csrc/k_sort.hip",
@@ -191,13 +195,14 @@ def run_tracked(args, log):
     box_prec = cd.CD_FP64 if args.boxes == "fp64" else cd.CD_FP32
     el = cd.soa(sc.elements)
     p = cd.params_struct(sc.tick_s, sc.mu, sc.threshold_km, sc.horizon_ticks,
-                         sc.dt_ticks if args.dt == "fixed" else 0)
-    workload = {"fixed": sc.name, "heuristic": sc.name.replace("dt1s", "dt_heuristic5km"),
-                "mlp": sc.name.replace("dt1s", "dt_mlp")}[args.dt]
+                         sc.dt_ticks if args.dt == "fixed" else 0, box_rule=BOX_RULES[args.box])
+    workload = {"fixed": sc.name,
+                "heuristic": sc.name.replace("dt1s", f"dt_heuristic{args.heur_km:g}km"),
+                "mlp": sc.name.replace("dt1s", "dt_mlp")}[args.dt] + BOX_SUFFIX[args.box]
     log(f"[bench] workload {workload}: n={sc.n} T={sc.horizon_ticks} ticks")
     kw = {}
     if args.dt == "heuristic":
-        kw = {"dt_heuristic_km": 5.0, "el_soa": el}
+        kw = {"dt_heuristic_km": args.heur_km, "el_soa": el}
     elif args.dt == "mlp":
         net = _train_step_net(lambda seed: catalog.tracked_hour(seed=seed, planted=0),
                               (2002, 2003), cd, ld, catalog, log)
@@ -247,7 +252,7 @@ def run_tracked(args, log):
                       "dt_s": sc.dt_ticks * sc.tick_s if args.dt == "fixed" else "per-object",
                       "boxes": N, "threshold_km": sc.threshold_km,
                       "box_precision": args.boxes, "tree_precision": args.precision,
-                      "brute_force_tests": tests},
+                      "box_rule": args.box, "brute_force_tests": tests},
            "pairs": P, "planted_recall": recall,
            "stages_ms": {k: round(v[0] / v[1], 4) for k, v in stages.items()},
            "roofline": _roofline(stages, N, sc.n, P, prec, box_prec, args.precision, args.dt)}
@@ -361,17 +366,18 @@ def run_debris(args, log):
     prec = cd.CD_FP64 if args.precision == "fp64" else cd.CD_FP32
     box_prec = cd.CD_FP64 if args.boxes == "fp64" else cd.CD_FP32
     el = cd.soa(sc.elements)
-    p = cd.params_struct(sc.tick_s, sc.mu, sc.threshold_km, W, 0)
+    p = cd.params_struct(sc.tick_s, sc.mu, sc.threshold_km, W, 0, box_rule=BOX_RULES[args.box])
     if args.dt == "mlp":
         net = _train_step_net(
             lambda seed: catalog.projected_debris(seed=seed, horizon_ticks=300_000, planted=0),
             (5002, 5003), cd, ld, catalog, log)
         kw = {"dt_mlp": (net.w_bf16, 5.0), "el_soa": el}
     elif args.dt == "heuristic":
-        kw = {"dt_heuristic_km": 5.0, "el_soa": el}
+        kw = {"dt_heuristic_km": args.heur_km, "el_soa": el}
     else:
         raise SystemExit("the debris catalog takes per-object steps (--dt heuristic|mlp)")
-    workload = f"{sc.name}_dt_{'mlp' if args.dt == 'mlp' else 'heuristic5km'}"
+    workload = (f"{sc.name}_dt_{'mlp' if args.dt == 'mlp' else f'heuristic{args.heur_km:g}km'}"
+                + BOX_SUFFIX[args.box])
     bp = cd.BroadPhase(sc.n, p, None, box_prec, prec, **kw)
     log(f"[bench] workload {workload}: n={sc.n}, {nwin} windows of {W} ticks, "
         f"{bp.count} boxes per window")
@@ -440,9 +446,14 @@ def main():
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
                     help="tree precision (boxes stay FP64 unless --boxes fp32)")
     ap.add_argument("--boxes", choices=["fp64", "fp32"], default="fp64")
+    ap.add_argument("--box", choices=list(BOX_RULES), default="speed",
+                    help="occ-int of a box: speed bound, or interval evaluation over the "
+                         "true (nu) or eccentric (ecc) anomaly")
     ap.add_argument("--dt", choices=["fixed", "heuristic", "mlp"], default="fixed",
                     help="fixed 1 s steps; per-object steps bounding each box's motion to "
                          "5 km; or per-object steps from the trained step network")
+    ap.add_argument("--heur-km", type=float, default=5.0,
+                    help="largest displacement per interval of the speed-bound step")
     ap.add_argument("--workload", choices=["tracked", "batch", "debris"], default="tracked")
     ap.add_argument("--window-s", type=float, default=1800.0,
                     help="debris workload: window length in seconds (divides 6 h)")

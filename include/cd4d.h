@@ -67,7 +67,15 @@ typedef struct {
  * used when no per-object step array is given.  start_ticks places the
  * horizon at absolute ticks [start, start + T] after the elements' epoch
  * (positions are taken at start + t); tags and records stay relative to
- * start, so a long horizon can be run as consecutive windows. */
+ * start, so a long horizon can be run as consecutive windows.  box_rule
+ * chooses how cd_build_boxes bounds an object over an interval (the occ-int
+ * of Def. Interval Occupancy Region): CD_BOX_SPEED (0) or one of the two
+ * interval evaluations of Sec. 4.5; other values are CD_E_INVALID. */
+enum {
+    CD_BOX_SPEED = 0,       /* endpoint hull grown by vmax * dt / 2 */
+    CD_BOX_INTERVAL_NU = 1, /* interval evaluation over the true anomaly */
+    CD_BOX_INTERVAL_E = 2   /* interval evaluation over the eccentric anomaly */
+};
 typedef struct {
     double tick_s;          /* seconds per tick, e.g. 1e-3 */
     double mu;              /* gravitational parameter, km^3/s^2 (398600.4418) */
@@ -75,6 +83,7 @@ typedef struct {
     uint32_t horizon_ticks; /* T */
     uint32_t dt_ticks;      /* uniform step (>= 1) when no dt array is given */
     uint32_t start_ticks;   /* absolute tick of the horizon's t = 0 (0: the epoch) */
+    uint32_t box_rule;      /* CD_BOX_* (0: the speed bound) */
 } cd_params;
 
 /* A set of 4D boxes, structure of arrays, caller-owned device memory.
@@ -171,16 +180,26 @@ int cd_dt_heuristic(const cd_elements *el, const cd_params *p, double max_disp_k
 
 /* ---- step 2: 4D boxes (Def. Interval Occupancy Region, 4D Occupancy) ----- */
 
-/* Builds every box.  For object i and interval k, with t_k = min(k dt_i, T):
- *   positions p_a = pos(t_k), p_b = pos(t_{k+1}) by Kepler propagation (the
- *   exact solution of Eq. nu-dot, mapped to ECI by the three rotations of
- *   Sec. 7.1), in FP64;
- *   g = vmax_i (t_{k+1} - t_k) tick_s / 2 + thr / 2;
- *   lo = min(p_a, p_b) - g, hi = max(p_a, p_b) + g per axis;
+/* Builds every box.  For object i and interval k, with t_k = min(k dt_i, T),
+ * Kepler propagation (the exact solution of Eq. nu-dot, mapped to ECI by the
+ * three rotations of Sec. 7.1) gives, in FP64, the positions p_a = pos(t_k),
+ * p_b = pos(t_{k+1}) and the eccentric anomalies E_a, E_b.  The box is
+ *   CD_BOX_SPEED: g = vmax_i (t_{k+1} - t_k) tick_s / 2 + thr / 2,
+ *     lo = min(p_a, p_b) - g, hi = max(p_a, p_b) + g per axis;
+ *   CD_BOX_INTERVAL_NU (Sec. 4.5 with the variable of Sec. 7.1): h evaluated
+ *     in outward-rounded interval arithmetic over [nu_a, nu_b] (the whole
+ *     turn when the mean anomaly advances 2 pi or more), h being
+ *     r = a (1 - e^2) / (1 + e cos nu), then (r cos nu) P + (r sin nu) Q;
+ *   CD_BOX_INTERVAL_E: the same over [E_a, E_b] with coordinate d written
+ *     as ctr_d + R_d cos(E - phi_d), in which E occurs once, so the box is
+ *     the hull of the path itself (the endpoint hull, extended to
+ *     ctr_d +- R_d where E - phi_d crosses a multiple of pi);
+ *   the interval rules widen the variable's range by 1e-10 rad and add
+ *   thr / 2;
  *   tag [t_k, t_{k+1}), the last one [t_{K-1}, T + 1).
- * The box holds every position in the interval (speed bound) and equals the
- * occupancy cube at a single instant (Property 1).  With a CD_FP32 output the
- * FP64 bounds are rounded outward.
+ * Every rule holds each position in the interval and equals the occupancy
+ * cube at a single instant (Property 1).  With a CD_FP32 output the FP64
+ * bounds are rounded outward.
  * Order: uniform step (dt_ticks NULL) -> time-major, box (i,k) at k*n + i, and
  * out->slab_size = n, out->slab_ticks = dt.  Per-object steps -> object-major,
  * box (i,k) at off_i + k.  out->count must equal cd_box_count's result and

@@ -20,6 +20,7 @@ _LIB_PATH = os.path.join(_HERE, "libcd4d.so")
 
 CD_OK, CD_E_INVALID, CD_E_WORKSPACE, CD_E_CAPACITY, CD_E_OVERFLOW, CD_E_DEVICE = range(6)
 CD_FP64, CD_FP32 = 0, 1
+CD_BOX_SPEED, CD_BOX_INTERVAL_NU, CD_BOX_INTERVAL_E = 0, 1, 2
 
 _vp = ctypes.c_void_p
 
@@ -32,7 +33,8 @@ class cd_elements(ctypes.Structure):
 class cd_params(ctypes.Structure):
     _fields_ = [("tick_s", ctypes.c_double), ("mu", ctypes.c_double),
                 ("threshold_km", ctypes.c_double), ("horizon_ticks", ctypes.c_uint32),
-                ("dt_ticks", ctypes.c_uint32), ("start_ticks", ctypes.c_uint32)]
+                ("dt_ticks", ctypes.c_uint32), ("start_ticks", ctypes.c_uint32),
+                ("box_rule", ctypes.c_uint32)]
 
 
 class cd_boxes(ctypes.Structure):
@@ -185,9 +187,11 @@ def elements_struct(el_soa):
     return cd_elements(*rows, n)
 
 
-def params_struct(tick_s, mu, threshold_km, horizon_ticks, dt_ticks=0, start_ticks=0):
+def params_struct(tick_s, mu, threshold_km, horizon_ticks, dt_ticks=0, start_ticks=0,
+                  box_rule=0):
+    """box_rule: CD_BOX_SPEED, CD_BOX_INTERVAL_NU or CD_BOX_INTERVAL_E."""
     return cd_params(float(tick_s), float(mu), float(threshold_km), int(horizon_ticks),
-                     int(dt_ticks), int(start_ticks))
+                     int(dt_ticks), int(start_ticks), int(box_rule))
 
 
 class Boxes:

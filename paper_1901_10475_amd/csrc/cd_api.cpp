@@ -124,6 +124,8 @@ int check_params(const cd_params *p)
         return fail(CD_E_INVALID, "threshold_km must be finite and >= 0");
     if (p->horizon_ticks == 0xFFFFFFFFu)
         return fail(CD_E_OVERFLOW, "horizon_ticks + 1 must fit 32 bits");
+    if (p->box_rule > CD_BOX_INTERVAL_E)
+        return fail(CD_E_INVALID, "unknown box_rule %u", p->box_rule);
     return CD_OK;
 }
 
@@ -192,6 +194,7 @@ size_t layout_count(void *base, size_t bytes, int64_t n, CountWS *w)
 struct BoxWS {
     CountWS cnt;
     ObjConst *oc;
+    ObjSinus *os;
     uint32_t *box_off;
     unsigned long long *frame;
     void *scan;
@@ -202,6 +205,7 @@ size_t layout_boxes(void *base, size_t bytes, int64_t n, BoxWS *w)
     Carve c(base, bytes);
     c.off = off;
     w->oc = c.take<ObjConst>(n);
+    w->os = c.take<ObjSinus>(n);
     w->box_off = c.take<uint32_t>(n);
     w->frame = c.take<unsigned long long>(6);
     w->scan = c.take_bytes(scan_ws_bytes((size_t)n));
@@ -508,7 +512,7 @@ int cd_build_boxes(const cd_elements *el, const uint32_t *dt_ticks, const cd_par
     bo.cap = (uint64_t)out->count;
     out->code_valid = 0;
     Stage st_boxes("boxes", s);
-    CD_HIP(launch_object_setup(*el, p->mu, (double)p->start_ticks * p->tick_s, w.oc, s));
+    CD_HIP(launch_object_setup(*el, p->mu, (double)p->start_ticks * p->tick_s, w.oc, w.os, s));
     if (out->code)
         CD_HIP(launch_orbit_frame(w.oc, (uint32_t)n, w.frame, s));
     double half_thr = 0.5 * p->threshold_km;
@@ -519,8 +523,9 @@ int cd_build_boxes(const cd_elements *el, const uint32_t *dt_ticks, const cd_par
         if ((uint64_t)n * K != (uint64_t)out->count)
             return fail(CD_E_INVALID, "out->count %lld != n * K = %llu", (long long)out->count,
                         (unsigned long long)((uint64_t)n * K));
-        CD_HIP(launch_boxes_uniform(w.oc, (uint32_t)n, (uint32_t)K, p->dt_ticks, T, p->tick_s,
-                                    half_thr, out->precision, bo, s));
+        CD_HIP(launch_boxes_uniform(w.oc, w.os, (uint32_t)n, (uint32_t)K, p->dt_ticks, T,
+                                    p->tick_s, half_thr, out->precision, (int)p->box_rule, bo,
+                                    s));
         out->slab_ticks = p->dt_ticks;
         out->slab_size = n;
     } else {
@@ -529,8 +534,8 @@ int cd_build_boxes(const cd_elements *el, const uint32_t *dt_ticks, const cd_par
         CD_HIP(scan_exclusive_u32(w.cnt.Kc, w.box_off, (size_t)n, w.scan, s));
         CD_HIP(launch_steps_apply_offsets(w.cnt.st, w.box_off, (uint32_t)n, s));
         // out->count is the caller's box count; lanes past the real total return
-        CD_HIP(launch_boxes_variable(w.oc, w.cnt.st, (uint32_t)n, T, p->tick_s, half_thr,
-                                     out->precision, bo, s));
+        CD_HIP(launch_boxes_variable(w.oc, w.os, w.cnt.st, (uint32_t)n, T, p->tick_s, half_thr,
+                                     out->precision, (int)p->box_rule, bo, s));
     }
     out->code_valid = out->code ? 1 : 0;
     return CD_OK;
@@ -894,13 +899,13 @@ int cd_graph_end(cd_stream_t stream, cd_graph *graph_out)
     hipGraphExec_t x = nullptr;
     hipError_t e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-        hipGraphDestroy(g);
+        (void)hipGraphDestroy(g);   // the instantiate error is the one reported
         return fail(CD_E_DEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
     }
     cd_graph h = new (std::nothrow) cd_graph_s;
     if (!h) {
-        hipGraphExecDestroy(x);
-        hipGraphDestroy(g);
+        (void)hipGraphExecDestroy(x);
+        (void)hipGraphDestroy(g);
         return fail(CD_E_DEVICE, "out of host memory");
     }
     h->graph = g;

@@ -16,6 +16,12 @@ struct ObjConst {
     double P[3], Q[3];            // perifocal unit vectors in ECI
 };
 
+// Coordinate d of the orbit as one sinusoid of the eccentric anomaly:
+// x_d(E) = ctr_d + R_d cos(E - phi_d) (for the eccentric-anomaly interval box).
+struct ObjSinus {
+    double R[3], phi[3], ctr[3];
+};
+
 // Per-object interval bookkeeping for per-object steps (object-major boxes).
 struct ObjSteps {
     uint32_t dt, K;      // step and interval count
@@ -281,7 +287,7 @@ struct SlabKeys {
 
 // boxes
 hipError_t launch_object_setup(const cd_elements &el, double mu, double start_s, ObjConst *oc,
-                               hipStream_t s);
+                               ObjSinus *os, hipStream_t s);
 // union of the orbits' bounding boxes (ordered bits: min xyz, max xyz)
 hipError_t launch_orbit_frame(const ObjConst *oc, uint32_t n, unsigned long long *frame,
                               hipStream_t s);
@@ -292,12 +298,13 @@ hipError_t launch_steps_apply_offsets(ObjSteps *st, const uint32_t *box_off, uin
                                       hipStream_t s);
 hipError_t launch_dt_heuristic(const cd_elements &el, double mu, double tick_s,
                                double max_disp, uint32_t T, uint32_t *dt_out, hipStream_t s);
-hipError_t launch_boxes_uniform(const ObjConst *oc, uint32_t n, uint32_t K, uint32_t dt,
-                                uint32_t T, double tick_s, double half_thr, int precision,
-                                const BoxOut &out, hipStream_t s);
-hipError_t launch_boxes_variable(const ObjConst *oc, const ObjSteps *st, uint32_t n, uint32_t T,
-                                 double tick_s, double half_thr, int precision, const BoxOut &out,
-                                 hipStream_t s);
+// rule: CD_BOX_SPEED, CD_BOX_INTERVAL_NU or CD_BOX_INTERVAL_E
+hipError_t launch_boxes_uniform(const ObjConst *oc, const ObjSinus *os, uint32_t n, uint32_t K,
+                                uint32_t dt, uint32_t T, double tick_s, double half_thr,
+                                int precision, int rule, const BoxOut &out, hipStream_t s);
+hipError_t launch_boxes_variable(const ObjConst *oc, const ObjSinus *os, const ObjSteps *st,
+                                 uint32_t n, uint32_t T, double tick_s, double half_thr,
+                                 int precision, int rule, const BoxOut &out, hipStream_t s);
 
 // scans / sorts / fills
 // step network

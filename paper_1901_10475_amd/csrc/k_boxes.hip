@@ -8,23 +8,49 @@
 // at T (advanceTime's clamp).  Positions come from Kepler's equation, the exact
 // solution of Eq. (nu-dot), mapped to ECI by three rotations (Sec. 7.1).
 //
+// The alternative boxes of Sec. 4.5 evaluate the map from one orbit variable
+// to ECI in interval arithmetic over the variable's range between the two
+// endpoints: the true anomaly (the variable Sec. 7.1 names), or the eccentric
+// anomaly with each coordinate written as one sinusoid (the variable occurs
+// once, so the box is the hull of the path).  Both variables grow with time,
+// so their range over an interval lies between the endpoint values, which the
+// Kepler solve already has.  The true-anomaly box runs the interval
+// operations; the eccentric-anomaly box is that exact range, which needs no
+// trigonometry beyond the solve: the endpoint positions, extended to a
+// sinusoid's extreme where the interval crosses it.
+//
 // One thread owns one object and a run of consecutive intervals, so each new
 // endpoint's Newton solve starts from the previous one (1-3 iterations) and
 // each endpoint is solved once.  With a uniform step the boxes are written
 // time-major (box k * n + i), so the lanes of a wave store consecutive boxes.
+#include <type_traits>
+
 #include "cd_internal.h"
+#include "interval.h"
 #include "orbit.h"
 
 namespace cd {
 
 // m0 is advanced to the horizon's start: M(start + t) = m0 + n (start + t).
-__global__ void k_object_setup(cd_elements el, double mu, double start_s, ObjConst *oc)
+// x_d(E) = a (cos E - e) P_d + b sin E Q_d = -a e P_d + R_d cos(E - phi_d) with
+// R_d cos phi_d = a P_d and R_d sin phi_d = b Q_d.
+__global__ void k_object_setup(cd_elements el, double mu, double start_s, ObjConst *oc,
+                               ObjSinus *os)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= el.n)
         return;
-    oc[i] = object_const(el.a[i], el.e[i], el.inc[i], el.raan[i], el.argp[i], el.m0[i], mu,
-                         start_s);
+    ObjConst c = object_const(el.a[i], el.e[i], el.inc[i], el.raan[i], el.argp[i], el.m0[i], mu,
+                              start_s);
+    oc[i] = c;
+    ObjSinus w;
+    for (int d = 0; d < 3; ++d) {
+        double A = c.a * c.P[d], B = c.b * c.Q[d];
+        w.R[d] = sqrt(A * A + B * B);
+        w.phi[d] = atan2(B, A);
+        w.ctr[d] = -c.a * c.e * c.P[d];
+    }
+    os[i] = w;
 }
 
 // Union of the orbits' bounding boxes: on the ellipse,
@@ -120,10 +146,89 @@ struct CodeFrame {
     }
 };
 
+// Kepler solution at an interval endpoint.
+struct EndPt {
+    double M, E, sE, cE;
+};
+
+// Bounds of object c over the interval between endpoints A and B (positions pa,
+// pb) under the box rule RULE, before the radius thr / 2 is added by the caller
+// (speed rule) or here (interval rules).
+template <int RULE>
+__device__ inline void box_bounds(const ObjConst &c, const ObjSinus *os, uint32_t i,
+                                  const EndPt &A, const EndPt &B, const double pa[3],
+                                  const double pb[3], double span_s, double half_thr,
+                                  double lo[3], double hi[3])
+{
+    if (RULE == CD_BOX_SPEED) {
+        double g = c.vmax * span_s * 0.5 + half_thr;
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = fmin(pa[d], pb[d]) - g;
+            hi[d] = fmax(pa[d], pb[d]) + g;
+        }
+        return;
+    }
+    const double w = 1e-10;                       // rad, for the endpoint solves' rounding
+    const double eps4 = 4.0 * 2.220446049250313e-16;
+    bool full = B.M - A.M >= kTwoPi;
+    Iv pos[3];
+    if (RULE == CD_BOX_INTERVAL_NU) {
+        // nu = E + 2 atan(beta sin E / (1 - beta cos E)), beta = e / (1 + sqrt(1 - e^2)):
+        // continuous in E, so unwrapped E gives unwrapped nu
+        double beta = c.e * c.a / (c.a + c.b);
+        double nua = A.E + 2.0 * atan(beta * A.sE / (1.0 - beta * A.cE));
+        double nub = B.E + 2.0 * atan(beta * B.sE / (1.0 - beta * B.cE));
+        Iv x = full ? iv(0.0, kTwoPi) : iv(nua - w, fmax(nua, nub) + w);
+        Iv C = iv_cos(x), S = iv_sin(x);
+        Iv one = iv(1.0, 1.0), ee = iv(c.e, c.e);
+        Iv r = (iv(c.a, c.a) * (one - ee * ee)) / (one + ee * C);
+        Iv X = r * C, Y = r * S;
+        for (int d = 0; d < 3; ++d)
+            pos[d] = X * iv_around(c.P[d], eps4) + Y * iv_around(c.Q[d], eps4);
+    } else {
+        // The exact range of ctr_d + R_d cos(E - phi_d) over [E_a - w, E_b + w]:
+        // between its critical points the function is monotone, so the range
+        // is the two end values -- the endpoint positions, already computed --
+        // extended to ctr_d + R_d (E - phi_d an even multiple of pi) or
+        // ctr_d - R_d (an odd one) when such a point lies inside; the
+        // widening w moves an end value by at most w R_d.
+        const ObjSinus &s = os[i];
+        double elo = A.E - w, ehi = fmax(A.E, B.E) + w;
+        for (int d = 0; d < 3; ++d) {
+            double vmin = fmin(pa[d], pb[d]), vmax = fmax(pa[d], pb[d]);
+            double top = s.ctr[d] + s.R[d], bot = s.ctr[d] - s.R[d];
+            if (full) {
+                vmin = bot;
+                vmax = top;
+            } else {
+                double k0 = ceil((elo - s.phi[d]) * kInvPi - 1e-12);
+                double k1 = floor((ehi - s.phi[d]) * kInvPi + 1e-12);
+                if (k0 <= k1) {
+                    if ((((long long)k0) & 1) == 0)
+                        vmax = top;
+                    else
+                        vmin = bot;
+                    if (k0 + 1.0 <= k1) {
+                        vmin = bot;
+                        vmax = top;
+                    }
+                }
+            }
+            // range widening plus the rounding of positions and constants
+            double pad = w * s.R[d] + 16.0 * 2.220446049250313e-16 * c.a;
+            pos[d] = Iv{vmin - pad, vmax + pad};
+        }
+    }
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = iv_dn(pos[d].lo - half_thr);
+        hi[d] = iv_up(pos[d].hi + half_thr);
+    }
+}
+
 template <int PREC>
 __device__ inline void store_box(const BoxOut &o, const CodeFrame &f, uint64_t b,
-                                 const double pa[3], const double pb[3], double g, uint32_t t0,
-                                 uint32_t t1, uint32_t obj)
+                                 const double pa[3], const double pb[3], const double blo[3],
+                                 const double bhi[3], uint32_t t0, uint32_t t1, uint32_t obj)
 {
     if (b >= o.cap)
         return;
@@ -131,8 +236,8 @@ __device__ inline void store_box(const BoxOut &o, const CodeFrame &f, uint64_t b
         o.code[b] = morton30(0.5 * (pa[0] + pb[0]), 0.5 * (pa[1] + pb[1]),
                              0.5 * (pa[2] + pb[2]), f.mn, f.inv);
     for (int d = 0; d < 3; ++d) {
-        double lo = fmin(pa[d], pb[d]) - g;
-        double hi = fmax(pa[d], pb[d]) + g;
+        double lo = blo[d];
+        double hi = bhi[d];
         if (PREC == CD_FP64) {
             ((double *)o.lo[d])[b] = lo;
             ((double *)o.hi[d])[b] = hi;
@@ -147,41 +252,44 @@ __device__ inline void store_box(const BoxOut &o, const CodeFrame &f, uint64_t b
 }
 
 // Intervals [k0, k1) of object i; box of interval k at index base + k * stride.
-template <int PREC>
-__device__ inline void object_run(const ObjConst &c, uint32_t i, uint64_t k0, uint64_t k1,
-                                  uint64_t K, uint64_t dt, uint64_t T, double tick_s,
-                                  double half_thr, const BoxOut &out, uint64_t base,
-                                  uint64_t stride)
+template <int PREC, int RULE>
+__device__ inline void object_run(const ObjConst &c, const ObjSinus *os, uint32_t i,
+                                  uint64_t k0, uint64_t k1, uint64_t K, uint64_t dt, uint64_t T,
+                                  double tick_s, double half_thr, const BoxOut &out,
+                                  uint64_t base, uint64_t stride)
 {
     const CodeFrame f(out);
     uint64_t ta = k0 * dt < T ? k0 * dt : T;
-    double M = c.m0 + c.n * ((double)ta * tick_s);
-    double E = M + c.e * sin(M), sE, cE;
-    kepler(M, c.e, E, sE, cE);
+    EndPt A;
+    A.M = c.m0 + c.n * ((double)ta * tick_s);
+    A.E = A.M + c.e * sin(A.M);
+    kepler(A.M, c.e, A.E, A.sE, A.cE);
     double pa[3];
-    position(c, sE, cE, pa);
+    position(c, A.sE, A.cE, pa);
     for (uint64_t k = k0; k < k1; ++k) {
         uint64_t tb = (k + 1) * dt < T ? (k + 1) * dt : T;
-        double Mb = c.m0 + c.n * ((double)tb * tick_s);
-        E += (Mb - M) / (1.0 - c.e * cE);
-        kepler(Mb, c.e, E, sE, cE);
+        EndPt B;
+        B.M = c.m0 + c.n * ((double)tb * tick_s);
+        B.E = A.E + (B.M - A.M) / (1.0 - c.e * A.cE);
+        kepler(B.M, c.e, B.E, B.sE, B.cE);
         double pb[3];
-        position(c, sE, cE, pb);
-        double g = c.vmax * ((double)(tb - ta) * tick_s) * 0.5 + half_thr;
+        position(c, B.sE, B.cE, pb);
+        double lo[3], hi[3];
+        box_bounds<RULE>(c, os, i, A, B, pa, pb, (double)(tb - ta) * tick_s, half_thr, lo, hi);
         uint32_t t1 = (k + 1 == K) ? (uint32_t)(T + 1) : (uint32_t)tb;
-        store_box<PREC>(out, f, base + k * stride, pa, pb, g, (uint32_t)ta, t1, i);
+        store_box<PREC>(out, f, base + k * stride, pa, pb, lo, hi, (uint32_t)ta, t1, i);
         pa[0] = pb[0];
         pa[1] = pb[1];
         pa[2] = pb[2];
         ta = tb;
-        M = Mb;
+        A = B;
     }
 }
 
-template <int PREC>
-__global__ void k_boxes_uniform(const ObjConst *__restrict__ oc, uint32_t n, uint32_t K,
-                                uint32_t dt, uint32_t T, double tick_s, double half_thr,
-                                uint32_t chunk, BoxOut out)
+template <int PREC, int RULE>
+__global__ __launch_bounds__(128) void k_boxes_uniform(const ObjConst *__restrict__ oc, const ObjSinus *__restrict__ os,
+                                uint32_t n, uint32_t K, uint32_t dt, uint32_t T, double tick_s,
+                                double half_thr, uint32_t chunk, BoxOut out)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
@@ -190,7 +298,7 @@ __global__ void k_boxes_uniform(const ObjConst *__restrict__ oc, uint32_t n, uin
     if (k0 >= K)
         return;
     uint64_t k1 = k0 + chunk < K ? k0 + chunk : K;
-    object_run<PREC>(oc[i], i, k0, k1, K, dt, T, tick_s, half_thr, out, i, n);
+    object_run<PREC, RULE>(oc[i], os, i, k0, k1, K, dt, T, tick_s, half_thr, out, i, n);
 }
 
 // Per-object steps, object-major output (box off_i + k).  One lane per box, so
@@ -198,8 +306,9 @@ __global__ void k_boxes_uniform(const ObjConst *__restrict__ oc, uint32_t n, uin
 // equation for the start of its interval; the end of the interval is the next
 // box's start, taken from the next lane by a shuffle (a second solve only for
 // the last box of a wave or of an object).
-template <int PREC>
+template <int PREC, int RULE>
 __global__ __launch_bounds__(256) void k_boxes_variable(const ObjConst *__restrict__ oc,
+                                                        const ObjSinus *__restrict__ os,
                                                         const ObjSteps *__restrict__ st,
                                                         uint32_t n, uint32_t T, double tick_s,
                                                         double half_thr, BoxOut out)
@@ -222,34 +331,42 @@ __global__ __launch_bounds__(256) void k_boxes_variable(const ObjConst *__restri
     ObjConst c = oc[i];
     uint64_t ta = k * s.dt < T ? k * s.dt : T;
     uint64_t tb = (k + 1) * s.dt < T ? (k + 1) * s.dt : T;
-    double Ma = c.m0 + c.n * ((double)ta * tick_s);
-    double E = Ma + c.e * sin(Ma), sE, cE;
-    kepler(Ma, c.e, E, sE, cE);
+    EndPt A;
+    A.M = c.m0 + c.n * ((double)ta * tick_s);
+    A.E = A.M + c.e * sin(A.M);
+    kepler(A.M, c.e, A.E, A.sE, A.cE);
     double pa[3];
-    position(c, sE, cE, pa);
+    position(c, A.sE, A.cE, pa);
     // the next lane holds the start of this box's end, if it is the same object
     int lane = threadIdx.x & 63;
     double nx = __shfl_down(pa[0], 1, 64), ny = __shfl_down(pa[1], 1, 64),
            nz = __shfl_down(pa[2], 1, 64);
     uint32_t ni = __shfl_down(i, 1, 64);
     uint64_t nk = __shfl_down(k, 1, 64);
+    EndPt B;
+    B.M = c.m0 + c.n * ((double)tb * tick_s);
+    if (RULE != CD_BOX_SPEED) {
+        B.E = __shfl_down(A.E, 1, 64);
+        B.sE = __shfl_down(A.sE, 1, 64);
+        B.cE = __shfl_down(A.cE, 1, 64);
+    }
     double pb[3];
     if (lane < 63 && ni == i && nk == k + 1 && k + 1 < s.K) {
         pb[0] = nx;
         pb[1] = ny;
         pb[2] = nz;
     } else {
-        double Mb = c.m0 + c.n * ((double)tb * tick_s);
-        E += (Mb - Ma) / (1.0 - c.e * cE);
-        kepler(Mb, c.e, E, sE, cE);
-        position(c, sE, cE, pb);
+        B.E = A.E + (B.M - A.M) / (1.0 - c.e * A.cE);
+        kepler(B.M, c.e, B.E, B.sE, B.cE);
+        position(c, B.sE, B.cE, pb);
     }
     if (!active)
         return;
-    double g = c.vmax * ((double)(tb - ta) * tick_s) * 0.5 + half_thr;
+    double blo[3], bhi[3];
+    box_bounds<RULE>(c, os, i, A, B, pa, pb, (double)(tb - ta) * tick_s, half_thr, blo, bhi);
     uint32_t t1 = (k + 1 == s.K) ? (uint32_t)(T + 1) : (uint32_t)tb;
     const CodeFrame f(out);
-    store_box<PREC>(out, f, b, pa, pb, g, (uint32_t)ta, t1, i);
+    store_box<PREC>(out, f, b, pa, pb, blo, bhi, (uint32_t)ta, t1, i);
 }
 
 // After the interval counts have been scanned into first-box offsets.
@@ -263,12 +380,39 @@ __global__ void k_steps_apply_offsets(ObjSteps *st, const uint32_t *box_off, uin
 
 static inline unsigned blocks_for(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
 
+// Calls go(precision tag, rule tag) with compile-time constants; the caller
+// has checked both values.
+template <class F>
+static void dispatch_rule(int precision, int rule, F &&go)
+{
+    using P64 = std::integral_constant<int, CD_FP64>;
+    using P32 = std::integral_constant<int, CD_FP32>;
+    using R0 = std::integral_constant<int, CD_BOX_SPEED>;
+    using R1 = std::integral_constant<int, CD_BOX_INTERVAL_NU>;
+    using R2 = std::integral_constant<int, CD_BOX_INTERVAL_E>;
+    if (precision == CD_FP64) {
+        if (rule == CD_BOX_INTERVAL_NU)
+            go(P64{}, R1{});
+        else if (rule == CD_BOX_INTERVAL_E)
+            go(P64{}, R2{});
+        else
+            go(P64{}, R0{});
+    } else {
+        if (rule == CD_BOX_INTERVAL_NU)
+            go(P32{}, R1{});
+        else if (rule == CD_BOX_INTERVAL_E)
+            go(P32{}, R2{});
+        else
+            go(P32{}, R0{});
+    }
+}
+
 hipError_t launch_object_setup(const cd_elements &el, double mu, double start_s, ObjConst *oc,
-                               hipStream_t s)
+                               ObjSinus *os, hipStream_t s)
 {
     if (el.n == 0)
         return hipSuccess;
-    k_object_setup<<<blocks_for(el.n, 256), 256, 0, s>>>(el, mu, start_s, oc);
+    k_object_setup<<<blocks_for(el.n, 256), 256, 0, s>>>(el, mu, start_s, oc, os);
     return hipGetLastError();
 }
 
@@ -314,9 +458,18 @@ hipError_t launch_dt_heuristic(const cd_elements &el, double mu, double tick_s,
     return hipGetLastError();
 }
 
-hipError_t launch_boxes_uniform(const ObjConst *oc, uint32_t n, uint32_t K, uint32_t dt,
-                                uint32_t T, double tick_s, double half_thr, int precision,
-                                const BoxOut &out, hipStream_t s)
+template <int PREC, int RULE>
+static void boxes_uniform(dim3 grid, hipStream_t s, const ObjConst *oc, const ObjSinus *os,
+                          uint32_t n, uint32_t K, uint32_t dt, uint32_t T, double tick_s,
+                          double half_thr, uint32_t chunk, const BoxOut &out)
+{
+    k_boxes_uniform<PREC, RULE><<<grid, 128, 0, s>>>(oc, os, n, K, dt, T, tick_s, half_thr,
+                                                     chunk, out);
+}
+
+hipError_t launch_boxes_uniform(const ObjConst *oc, const ObjSinus *os, uint32_t n, uint32_t K,
+                                uint32_t dt, uint32_t T, double tick_s, double half_thr,
+                                int precision, int rule, const BoxOut &out, hipStream_t s)
 {
     if (n == 0 || K == 0)
         return hipSuccess;
@@ -324,27 +477,34 @@ hipError_t launch_boxes_uniform(const ObjConst *oc, uint32_t n, uint32_t K, uint
     while ((K + chunk - 1) / chunk > 65535u)
         chunk *= 2;
     dim3 grid(blocks_for(n, 128), (K + chunk - 1) / chunk);
-    if (precision == CD_FP64)
-        k_boxes_uniform<CD_FP64><<<grid, 128, 0, s>>>(oc, n, K, dt, T, tick_s, half_thr, chunk,
-                                                       out);
-    else
-        k_boxes_uniform<CD_FP32><<<grid, 128, 0, s>>>(oc, n, K, dt, T, tick_s, half_thr, chunk,
-                                                       out);
+    auto go = [&](auto prec, auto rl) {
+        boxes_uniform<decltype(prec)::value, decltype(rl)::value>(grid, s, oc, os, n, K, dt, T,
+                                                                  tick_s, half_thr, chunk, out);
+    };
+    dispatch_rule(precision, rule, go);
     return hipGetLastError();
 }
 
-hipError_t launch_boxes_variable(const ObjConst *oc, const ObjSteps *st, uint32_t n, uint32_t T,
-                                 double tick_s, double half_thr, int precision, const BoxOut &out,
-                                 hipStream_t s)
+template <int PREC, int RULE>
+static void boxes_variable(hipStream_t s, const ObjConst *oc, const ObjSinus *os,
+                           const ObjSteps *st, uint32_t n, uint32_t T, double tick_s,
+                           double half_thr, const BoxOut &out)
+{
+    k_boxes_variable<PREC, RULE><<<blocks_for(out.cap, 256), 256, 0, s>>>(oc, os, st, n, T,
+                                                                         tick_s, half_thr, out);
+}
+
+hipError_t launch_boxes_variable(const ObjConst *oc, const ObjSinus *os, const ObjSteps *st,
+                                 uint32_t n, uint32_t T, double tick_s, double half_thr,
+                                 int precision, int rule, const BoxOut &out, hipStream_t s)
 {
     if (n == 0 || out.cap == 0)
         return hipSuccess;
-    if (precision == CD_FP64)
-        k_boxes_variable<CD_FP64><<<blocks_for(out.cap, 256), 256, 0, s>>>(oc, st, n, T, tick_s,
-                                                                         half_thr, out);
-    else
-        k_boxes_variable<CD_FP32><<<blocks_for(out.cap, 256), 256, 0, s>>>(oc, st, n, T, tick_s,
-                                                                         half_thr, out);
+    auto go = [&](auto prec, auto rl) {
+        boxes_variable<decltype(prec)::value, decltype(rl)::value>(s, oc, os, st, n, T, tick_s,
+                                                                   half_thr, out);
+    };
+    dispatch_rule(precision, rule, go);
     return hipGetLastError();
 }
 

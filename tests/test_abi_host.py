@@ -63,7 +63,8 @@ def test_uniform_box_count_and_argument_errors():
     bad = [cd.params_struct(1e-3, 398600.4418, 1.0, 600, 0),        # dt = 0
            cd.params_struct(0.0, 398600.4418, 1.0, 600, 1),         # tick 0
            cd.params_struct(1e-3, 398600.4418, -1.0, 600, 1),       # thr < 0
-           cd.params_struct(1e-3, float("nan"), 1.0, 600, 1)]
+           cd.params_struct(1e-3, float("nan"), 1.0, 600, 1),
+           cd.params_struct(1e-3, 398600.4418, 1.0, 600, 1, box_rule=3)]  # unknown rule
     for q in bad:
         assert L.cd_box_count(None, 5, ctypes.byref(q), ctypes.byref(out), None, 0,
                               None) == cd.CD_E_INVALID

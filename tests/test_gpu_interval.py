@@ -1,0 +1,155 @@
+"""Interval-evaluation boxes (Sec. 4.5) on the GPU against the oracle.
+
+Boxes of both interval rules (true anomaly, eccentric anomaly) within 1e-9
+relative of the oracle's interval boxes (the two sides differ by the rounding
+of the endpoint solves and of the library cos/sin only; both widen by the same
+stated amounts), tags exact; records equal the oracle's literal all-pairs
+result on the same boxes; every propagated position of a sampled box lies in
+it; the eccentric-anomaly box lies inside the speed-bound box, so its records
+are a subset of the speed-bound records.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_1901_10475_amd as cd
+from paper_1901_10475_amd import catalog
+from tests.gpu_util import assert_boxes_close, gpu_to_object_major, need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+RULES = [cd.CD_BOX_INTERVAL_NU, cd.CD_BOX_INTERVAL_E]
+
+
+def _scenario(seed, n, T, dt, start=0, planted=8):
+    """Tracked-population mix, a few highly eccentric orbits, and planted
+    conjunction pairs at absolute ticks start + t_c."""
+    rng = np.random.default_rng(seed)
+    el = catalog.tracked_population(rng, n)
+    k = max(n // 20, 2)
+    heo = np.stack([rng.uniform(20000.0, 30000.0, k), rng.uniform(0.5, 0.8, k),
+                    rng.uniform(0.0, np.pi, k), rng.uniform(0.0, 2 * np.pi, k),
+                    rng.uniform(0.0, 2 * np.pi, k), rng.uniform(0.0, 2 * np.pi, k)], axis=1)
+    el[:k] = heo
+    thr = 25.0
+    pl = catalog.plant_conjunctions(rng, el, planted, T, dt, thr) if planted else []
+    for i, j, _ in pl:
+        for o in (i, j):
+            n_mean = np.sqrt(catalog.MU_EARTH / el[o, 0] ** 3)
+            el[o, 5] = (el[o, 5] - n_mean * start * catalog.TICK_S) % (2 * np.pi)
+    return catalog.Scenario(f"mix{n}", el, dt, T, thr, planted=pl)
+
+
+def _recall(sc, pairs):
+    for i, j, tc in sc.planted:
+        hit = pairs[(pairs[:, 0] == i) & (pairs[:, 1] == j)]
+        assert np.any((hit[:, 2] <= tc) & (tc < hit[:, 3])), (i, j, tc)
+
+
+def _run(sc, rule, dt=None, start=0, box_precision=cd.CD_FP64, tree_precision=cd.CD_FP64):
+    el = cd.soa(sc.elements)
+    p = cd.params_struct(sc.tick_s, sc.mu, sc.threshold_km, sc.horizon_ticks,
+                         sc.dt_ticks if dt is None else 0, start_ticks=start, box_rule=rule)
+    dtt = None if dt is None else torch.from_numpy(np.asarray(dt, np.uint32).view(np.int32)).cuda()
+    bp = cd.BroadPhase(sc.n, p, dtt, box_precision, tree_precision)
+    pairs = bp.run(el).cpu().numpy().view(np.uint32).copy()
+    torch.cuda.synchronize()
+    return bp, pairs
+
+
+def _host_object_major(bp, sc, dt):
+    lo, hi, t0, t1, obj = bp.boxes.to_host()
+    if dt is None:
+        g = gpu_to_object_major(sc.n, oracle.intervals(sc.dt_ticks, sc.horizon_ticks))
+        lo, hi, t0, t1, obj = lo[g], hi[g], t0[g], t1[g], obj[g]
+    return lo, hi, t0, t1, obj
+
+
+@pytest.mark.parametrize("rule", RULES)
+@pytest.mark.parametrize("steps", ["uniform", "per_object"])
+@pytest.mark.parametrize("start", [0, 987_654])
+def test_interval_boxes_and_pairs(rule, steps, start):
+    need_gpu()
+    say("interval boxes rule", rule, steps, "start", start)
+    sc = _scenario(31 + rule, 400, 240_000, 20_000, start)
+    dt = None if steps == "uniform" else oracle.dt_heuristic(sc.elements, sc.tick_s, 40.0,
+                                                             sc.horizon_ticks)
+    bp, pairs = _run(sc, rule, dt, start)
+    lo, hi, t0, t1, obj = _host_object_major(bp, sc, dt)
+    ob = oracle.boxes(sc.elements, sc.dt_ticks if dt is None else dt, sc.horizon_ticks,
+                      sc.tick_s, sc.threshold_km, start=start, rule=rule)
+    assert bp.count == len(ob)
+    assert np.array_equal(t0, ob.t0) and np.array_equal(t1, ob.t1)
+    assert np.array_equal(obj, ob.obj)
+    worst = assert_boxes_close(lo, hi, ob.lo, ob.hi, sc.elements[ob.obj, 0])
+    say("worst relative box difference", worst)
+    ref = oracle.pairs(oracle.Boxes(*bp.boxes.to_host()))
+    assert len(ref) > 0
+    assert np.array_equal(pairs, ref)
+    _recall(sc, pairs)
+
+
+@pytest.mark.parametrize("rule", RULES)
+def test_interval_boxes_contain_the_path(rule):
+    need_gpu()
+    say("interval boxes contain path, rule", rule)
+    sc = _scenario(41, 120, 600_000, 150_000)
+    dt = oracle.dt_heuristic(sc.elements, sc.tick_s, 300.0, sc.horizon_ticks)
+    bp, _ = _run(sc, rule, dt, start=5_000)
+    lo, hi, t0, t1, obj = bp.boxes.to_host()
+    rng = np.random.default_rng(42)
+    r = sc.threshold_km / 2
+    for b in rng.choice(len(t0), 120, replace=False):
+        i = obj[b]
+        tb = min(int(t1[b]), sc.horizon_ticks)
+        for t in np.unique(np.linspace(int(t0[b]), tb, 25).astype(np.int64)):
+            p = oracle.position(sc.elements[i], (5_000 + int(t)) * sc.tick_s)
+            assert np.all(p - r >= lo[b] - 1e-9) and np.all(p + r <= hi[b] + 1e-9), (b, t)
+
+
+@pytest.mark.parametrize("precision", [cd.CD_FP32])
+def test_interval_boxes_fp32_outward(precision):
+    need_gpu()
+    say("interval boxes fp32")
+    sc = _scenario(51, 300, 120_000, 10_000)
+    for rule in RULES:
+        bp64, p64 = _run(sc, rule)
+        bp32, p32 = _run(sc, rule, box_precision=precision, tree_precision=precision)
+        lo, hi, t0, t1, obj = bp64.boxes.to_host()
+        l32, h32, u0, u1, uo = bp32.boxes.to_host()
+        r = oracle.outward_f32(oracle.Boxes(lo, hi, t0, t1, obj))
+        assert np.array_equal(l32, r.lo) and np.array_equal(h32, r.hi)
+        assert np.array_equal(p32, oracle.pairs(r))
+        assert {tuple(x) for x in p64.tolist()} <= {tuple(x) for x in p32.tolist()}
+
+
+def test_eccentric_rule_records_within_speed_rule():
+    need_gpu()
+    say("eccentric-anomaly records within speed-bound records")
+    sc = catalog.scaled(catalog.tracked_hour(seed=61), n=3000, horizon_ticks=300_000,
+                        dt_ticks=10_000)
+    counts = {}
+    sets = {}
+    for rule in (cd.CD_BOX_SPEED, cd.CD_BOX_INTERVAL_NU, cd.CD_BOX_INTERVAL_E):
+        bp, pairs = _run(sc, rule)
+        lo, hi, *_ = bp.boxes.to_host()
+        counts[rule] = (len(pairs), float(np.mean(np.prod(hi - lo, axis=1))))
+        sets[rule] = {tuple(x) for x in pairs.tolist()}
+    say("records / mean box volume per rule", counts)
+    assert sets[cd.CD_BOX_INTERVAL_E] <= sets[cd.CD_BOX_SPEED]
+    assert counts[cd.CD_BOX_INTERVAL_E][1] < counts[cd.CD_BOX_SPEED][1]
+    # planted conjunctions are found by every rule
+    for rule, s in sets.items():
+        for i, j, tc in sc.planted:
+            assert any(a == i and b == j and lo_ <= tc < hi_ for a, b, lo_, hi_ in s), (rule, i, j)
+
+
+def test_unknown_box_rule_rejected():
+    need_gpu()
+    sc = _scenario(71, 10, 1000, 1000, planted=0)
+    el = cd.soa(sc.elements)
+    p = cd.params_struct(sc.tick_s, sc.mu, sc.threshold_km, sc.horizon_ticks, sc.dt_ticks,
+                         box_rule=3)
+    with pytest.raises(cd.CDError):
+        cd.BroadPhase(sc.n, p).run(el)

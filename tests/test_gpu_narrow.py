@@ -35,10 +35,11 @@ def _dist(sc, i, j, t_abs):
     return float(np.max(np.abs(np.asarray(pi) - np.asarray(pj))))
 
 
-def _check(sc, start, delta, heur=None):
+def _check(sc, start, delta, heur=None, box_rule=0):
     el = cd.soa(sc.elements)
     p = cd.params_struct(sc.tick_s, sc.mu, sc.threshold_km, sc.horizon_ticks,
-                         sc.dt_ticks if heur is None else 0, start_ticks=start)
+                         sc.dt_ticks if heur is None else 0, start_ticks=start,
+                         box_rule=box_rule)
     bp = cd.BroadPhase(sc.n, p, dt_heuristic_km=heur, el_soa=el)
     pairs = bp.run(el)
     wit, first = cd.cd_first_witness(el, p, delta, pairs)
@@ -98,6 +99,17 @@ def test_first_witness_window_and_per_object_steps():
     sc = _planted_leo(72, 160, 6, 40_000, 1000)
     say("narrow window + heuristic steps")
     _check(sc, 12_345, 10, heur=5.0)
+
+
+@pytest.mark.parametrize("rule", [cd.CD_BOX_INTERVAL_NU, cd.CD_BOX_INTERVAL_E])
+def test_first_witness_interval_boxes(rule):
+    """Records from the interval-evaluation boxes still hold every brute-force
+    witness, and the first collision is the brute-force answer."""
+    need_gpu()
+    sc = _planted_leo(74, 160, 6, 40_000, 2000)
+    say("narrow interval boxes rule", rule)
+    got = _check(sc, 3_000, 5, box_rule=rule)
+    assert (got != NONE).sum() >= 1
 
 
 def test_first_witness_empty_and_argument_errors():
