@@ -161,14 +161,16 @@ def _roofline(stages, N, n, P, prec, box_prec, precision_name, dt_mode):
             "bytes_per_launch": int(nbytes), "mean_ms": round(mean_ms, 4)}
 
 
-def _train_step_net(sc_recipe, seeds, cd, ld, catalog, log):
+def _train_step_net(sc_recipe, seeds, cd, ld, catalog, log, box_rule=0):
     """Step network trained on step sweeps of catalogs drawn from the same
-    recipe with other seeds (outside the timed region)."""
+    recipe with other seeds (outside the timed region), with the box rule of
+    the query it will serve."""
     import torch
     xs, ts = [], []
     for seed in seeds:
         sc = sc_recipe(seed)
-        p = cd.params_struct(sc.tick_s, sc.mu, sc.threshold_km, sc.horizon_ticks, 0)
+        p = cd.params_struct(sc.tick_s, sc.mu, sc.threshold_km, sc.horizon_ticks, 0,
+                             box_rule=box_rule)
         x, t, summary = ld.sweep_targets(cd.soa(sc.elements), p)
         log(f"[bench] sweep seed {seed}: " + ", ".join(
             f"x{r['scale']:g}: {r['boxes']} boxes {r['records']} rec" for r in summary))
@@ -205,7 +207,7 @@ def run_tracked(args, log):
         kw = {"dt_heuristic_km": args.heur_km, "el_soa": el}
     elif args.dt == "mlp":
         net = _train_step_net(lambda seed: catalog.tracked_hour(seed=seed, planted=0),
-                              (2002, 2003), cd, ld, catalog, log)
+                              (2002, 2003), cd, ld, catalog, log, BOX_RULES[args.box])
         kw = {"dt_mlp": (net.w_bf16, 5.0), "el_soa": el}
     bp = cd.BroadPhase(sc.n, p, None, box_prec, prec, **kw)
     N = bp.count
@@ -277,11 +279,16 @@ def narrow_phase(cd, el, p, pairs, log, delta=1, reps=5):
     torch.cuda.synchronize()
     ms = sorted(a.elapsed_time(b) for a, b in ev)[reps // 2]
     fc = cd.first_collision(pairs, first)
-    hits = int((wit != -1).sum().item())
+    hit = wit != -1
+    hits = int(hit.sum().item())
+    # distinct object pairs with a collision in the horizon: the same set for
+    # every step and box rule, since every rule's boxes are conservative
+    hp = pairs[hit][:, :2].long()
+    colliding = int(torch.unique(hp[:, 0] * (1 << 32) + hp[:, 1]).numel()) if hits else 0
     log(f"[bench] narrow phase (delta {delta} tick): {ms:.3f} ms, {hits} records with a "
         f"collision, first {fc}")
     return {"delta_ticks": delta, "ms": round(ms, 4), "records": int(pairs.shape[0]),
-            "records_with_collision": hits,
+            "records_with_collision": hits, "colliding_object_pairs": colliding,
             "first_collision": None if fc is None else {"t_ticks": fc[0], "i": fc[1],
                                                         "j": fc[2]}}
 
@@ -370,7 +377,7 @@ def run_debris(args, log):
     if args.dt == "mlp":
         net = _train_step_net(
             lambda seed: catalog.projected_debris(seed=seed, horizon_ticks=300_000, planted=0),
-            (5002, 5003), cd, ld, catalog, log)
+            (5002, 5003), cd, ld, catalog, log, BOX_RULES[args.box])
         kw = {"dt_mlp": (net.w_bf16, 5.0), "el_soa": el}
     elif args.dt == "heuristic":
         kw = {"dt_heuristic_km": args.heur_km, "el_soa": el}

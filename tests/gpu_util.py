@@ -14,13 +14,14 @@ def need_gpu():
     assert torch.cuda.is_available(), "GPU test run without a HIP device"
 
 
-def run_catalog(sc, box_precision=0, tree_precision=0, dt_array=None, capacity=None):
+def run_catalog(sc, box_precision=0, tree_precision=0, dt_array=None, capacity=None,
+                box_rule=0):
     """Boxes, tree and canonical pairs for a scenario on the GPU."""
     import torch
     import paper_1901_10475_amd as cd
     el = cd.soa(sc.elements)
     p = cd.params_struct(sc.tick_s, sc.mu, sc.threshold_km, sc.horizon_ticks,
-                         sc.dt_ticks if np.ndim(sc.dt_ticks) == 0 else 0)
+                         sc.dt_ticks if np.ndim(sc.dt_ticks) == 0 else 0, box_rule=box_rule)
     dt = None
     if dt_array is not None:
         dt = torch.from_numpy(np.asarray(dt_array, np.uint32).view(np.int32)).cuda()

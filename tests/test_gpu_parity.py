@@ -201,13 +201,15 @@ def test_per_object_step_pairs_parity():
     assert np.array_equal(pairs, ref)
 
 
-def test_tracked_hour_full_size_sampled():
-    """The benchmark workload (16 848 objects, 1 h, dt = 1 s, 60.65 M boxes, FP64):
+@pytest.mark.parametrize("rule", [0, 2])
+def test_tracked_hour_full_size_sampled(rule):
+    """The benchmark workload (16 848 objects, 1 h, dt = 1 s, 60.65 M boxes, FP64),
+    with the speed-bound box (0) and the eccentric-anomaly interval box (2):
     sampled exact parity, exact parity on a time window, planted recall."""
     need_gpu()
-    say("tracked16848 1h full size")
+    say("tracked16848 1h full size, box rule", rule)
     sc = catalog.tracked_hour()
-    bp, pairs = run_catalog(sc)
+    bp, pairs = run_catalog(sc, box_rule=rule)
     N = bp.count
     assert N == 16848 * 3600
     lo, hi, t0, t1, obj = bp.boxes.to_host()
@@ -234,7 +236,7 @@ def test_tracked_hour_full_size_sampled():
         assert np.any((hit[:, 2] <= tc) & (tc < hit[:, 3])), (i, j, tc)
     # box bounds of sampled boxes against the oracle's own construction
     ob_i = np.unique(obj[sample])[:16]
-    sub = oracle.boxes(sc.elements[ob_i], 1000, sc.horizon_ticks, sc.tick_s, 1.0)
+    sub = oracle.boxes(sc.elements[ob_i], 1000, sc.horizon_ticks, sc.tick_s, 1.0, rule=rule)
     g = np.concatenate([np.arange(3600) * 16848 + i for i in ob_i])
     assert_boxes_close(lo[g], hi[g], sub.lo, sub.hi, sc.elements[obj[g], 0])
 
