@@ -5,6 +5,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <atomic>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -111,6 +112,16 @@ constexpr int64_t kMaxBoxes = (1ll << 30) - 1;  // node ids of 2N - 1 nodes belo
 constexpr size_t kTreeHeader = sizeof(TreeHeader);
 constexpr int kExpandBatch = 12;                 // levels launched between count checks
 constexpr int kExpandMaxLevels = 400;            // > 2 x the deepest possible tree
+// Query control block (32-bit words): [l] queue count after level l - 1,
+// then the per-leaf-walk flag, the level flags, and a status copy (record
+// count low/high, tree error) at an 8-byte-aligned word.
+constexpr int kCtlWalk = kExpandMaxLevels + 1;
+constexpr int kCtlFlags = kExpandMaxLevels + 2;
+constexpr int kCtlStatus = kExpandMaxLevels + 4;
+constexpr int kCtlWords = kCtlStatus + 4;
+// Node-pair levels the last drained traversal needed: the next synchronous
+// query launches that many before its first count check.
+std::atomic<int> g_expand_levels{kExpandBatch};
 
 int check_params(const cd_params *p)
 {
@@ -281,8 +292,8 @@ size_t layout_query(void *base, size_t bytes, int64_t N, int64_t cap, QueryWS *w
     w->qcap = queue_cap(N);
     w->qa = c.take<uint2>(w->qcap);
     w->qb = c.take<uint2>(w->qcap);
-    w->qcount = c.take<unsigned int>(kExpandMaxLevels + 2);
-    w->qflags = c.take<unsigned int>(1);
+    w->qcount = c.take<unsigned int>(kCtlWords);
+    w->qflags = w->qcount + kCtlFlags;
     w->raw = c.take<Rec>(m);
     w->alt = c.take<Rec>(m);
     w->counter = c.take<unsigned long long>(1);
@@ -702,46 +713,58 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
         (const uint2 *)((const char *)tree->mem + tree_seeds_offset((uint64_t)N, tree->precision));
     const uint2 *kids =
         (const uint2 *)((const char *)tree->mem + tree_kids_offset((uint64_t)N, tree->precision));
-    unsigned long long cnt = 0;
-    unsigned int e = 0;
-    bool done = false;
     const cd_tuning tu = tuning();
     {
         Stage st("traverse", s);
-        // node-pair traversal from the refit's overlapping sibling pairs
-        unsigned int h[3] = {0, 0, 0};
-        CD_HIP(hipMemcpyAsync(h, hdr, sizeof h, hipMemcpyDeviceToHost, s));
-        CD_HIP(hipStreamSynchronize(s));
-        if (h[0] == 0 && h[2] == 0 && N > 1 && tu.mode == 0) {
+        // node-pair traversal from the refit's overlapping sibling pairs; a
+        // build error or lost seeds (k_query_begin), a queue overflow or a bad
+        // node hand the query to the per-leaf walk, decided from one read of
+        // the control block per batch of levels
+        bool walk = true;
+        if (N > 1 && tu.mode == 0) {
+            CD_HIP(launch_fill_u32(w.qcount, 0u, kCtlWords, s));
             CD_HIP(launch_fill_u64(w.counter, 0ull, 1, s));
-            CD_HIP(launch_fill_u32(w.qcount, 0u, kExpandMaxLevels + 2, s));
-            CD_HIP(launch_fill_u32(w.qflags, 0u, 1, s));
+            CD_HIP(launch_query_begin(hdr, w.qflags, s));
             const uint2 *in = seeds;
             const unsigned int *n_in = &hdr->nseeds;
             uint32_t in_cap = (uint32_t)seed_cap((uint64_t)N);
-            unsigned int qf = 0, left = 1;
-            for (int lev = 0; lev < kExpandMaxLevels; ++lev) {
-                uint2 *outq = (lev & 1) ? w.qb : w.qa;
-                CD_HIP(launch_expand(nodes, kids, tree->precision, (uint32_t)N, in, n_in, in_cap,
-                                     outq,
-                                     w.qcount + lev + 1, w.qcap, w.raw,
-                                     (unsigned long long)capacity, w.counter, w.qflags, 0,
-                                     tu.expand_blocks, tu.expand_threads, s));
-                in = outq;
-                n_in = w.qcount + lev + 1;
-                in_cap = w.qcap;
-                if ((lev + 1) % kExpandBatch == 0 || lev + 1 == kExpandMaxLevels) {
-                    CD_HIP(hipMemcpyAsync(&left, n_in, sizeof left, hipMemcpyDeviceToHost, s));
-                    CD_HIP(hipMemcpyAsync(&qf, w.qflags, sizeof qf, hipMemcpyDeviceToHost, s));
-                    CD_HIP(hipStreamSynchronize(s));
-                    if (left == 0 || qf)
-                        break;
+            unsigned int ctl[kCtlFlags + 1];
+            int lev = 0;
+            int batch = g_expand_levels.load(std::memory_order_relaxed);
+            batch = batch < 1 ? 1 : (batch > kExpandMaxLevels ? kExpandMaxLevels : batch);
+            unsigned int qf = 0;
+            while (lev < kExpandMaxLevels) {
+                int end = lev + batch < kExpandMaxLevels ? lev + batch : kExpandMaxLevels;
+                for (; lev < end; ++lev) {
+                    uint2 *outq = (lev & 1) ? w.qb : w.qa;
+                    CD_HIP(launch_expand(nodes, kids, tree->precision, (uint32_t)N, in, n_in,
+                                         in_cap, outq, w.qcount + lev + 1, w.qcap, w.raw,
+                                         (unsigned long long)capacity, w.counter, w.qflags, 1,
+                                         tu.expand_blocks, tu.expand_threads, s));
+                    in = outq;
+                    n_in = w.qcount + lev + 1;
+                    in_cap = w.qcap;
                 }
+                CD_HIP(hipMemcpyAsync(ctl, w.qcount, sizeof ctl, hipMemcpyDeviceToHost, s));
+                CD_HIP(hipStreamSynchronize(s));
+                qf = ctl[kCtlFlags];
+                if (qf)
+                    break;
+                batch = kExpandBatch;
             }
-            // done only if every queue drained without overflow
-            done = (qf == 0 && left == 0);
+            // drained (flag 8) with no overflow, bad node or handover: done
+            walk = (qf & 7u) != 0 || (qf & 8u) == 0;
+            if (!walk) {
+                // levels needed: the last non-empty queue's reader and the one
+                // that found the queue empty
+                int last = 0;
+                for (int l = 1; l <= lev && l <= kExpandMaxLevels; ++l)
+                    if (ctl[l])
+                        last = l;
+                g_expand_levels.store(last + 2, std::memory_order_relaxed);
+            }
         }
-        if (!done) {
+        if (walk) {
             // bounded fallback: one stackless walk per leaf
             CD_HIP(launch_fill_u64(w.counter, 0ull, 1, s));
             CD_HIP(launch_traverse(nodes, tree->precision, (uint32_t)N, tree->slab_ticks, w.raw,
@@ -749,9 +772,12 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
                                    tu.walk_threads, s));
         }
     }
-    CD_HIP(hipMemcpyAsync(&cnt, w.counter, sizeof cnt, hipMemcpyDeviceToHost, s));
-    CD_HIP(hipMemcpyAsync(&e, err, sizeof e, hipMemcpyDeviceToHost, s));
+    unsigned int stw[3];
+    CD_HIP(launch_query_status(w.counter, err, w.qcount + kCtlStatus, s));
+    CD_HIP(hipMemcpyAsync(stw, w.qcount + kCtlStatus, sizeof stw, hipMemcpyDeviceToHost, s));
     CD_HIP(hipStreamSynchronize(s));
+    unsigned long long cnt = (unsigned long long)stw[0] | ((unsigned long long)stw[1] << 32);
+    unsigned int e = stw[2];
     if (e)
         return fail(CD_E_INVALID, "tree inconsistent (error bits 0x%x): boxes disagree with "
                                   "their slab hint or horizon, or the build failed", e);
@@ -805,8 +831,7 @@ int cd_query_pairs_async(const cd_tree *tree, cd_pair *out, int64_t capacity,
         (const uint2 *)((const char *)tree->mem + tree_kids_offset((uint64_t)N, tree->precision));
     const cd_tuning tu = tuning();
     const uint32_t cap = (uint32_t)capacity;
-    // qcount[kExpandMaxLevels + 1] doubles as the per-leaf-walk flag
-    unsigned int *walk = w.qcount + kExpandMaxLevels + 1;
+    unsigned int *walk = w.qcount + kCtlWalk;
     CD_HIP(launch_fill_u64(w.counter, 0ull, 1, s));
     {
         Stage st("traverse", s);

@@ -477,13 +477,18 @@ hipError_t launch_traverse(const void *tree, int precision, uint32_t N, uint32_t
 // One breadth-first level of the node-pair self-traversal: every pair in
 // `in` (count *n_in, at most in_cap) is expanded into the overlapping pairs of
 // its children; pairs of two leaves are emitted as records, the others queued
-// in `outq` (count *n_out, capacity out_cap; bit 0 of *flags on overflow).
+// in `outq` (count *n_out, capacity out_cap; bit 0 of *flags on overflow,
+// bit 1 on a bad node, bit 3 when *n_in is 0).  gated: return at once if any
+// flag is set.
 hipError_t launch_expand(const void *tree, const uint2 *kids, int precision, uint32_t N,
                          const uint2 *in, const unsigned int *n_in, uint32_t in_cap, uint2 *outq,
                          unsigned int *n_out, uint32_t out_cap, Rec *out,
                          unsigned long long capacity, unsigned long long *counter,
                          unsigned int *flags, int gated, uint32_t blocks, uint32_t threads,
                          hipStream_t s);
+// out[0..2] = low and high words of *counter, *tree_err
+hipError_t launch_query_status(const unsigned long long *counter, const unsigned int *tree_err,
+                               unsigned int *out, hipStream_t s);
 hipError_t launch_query_begin(const TreeHeader *hdr, unsigned int *qflags, hipStream_t s);
 hipError_t launch_query_decide(const unsigned int *last_count, const unsigned int *qflags,
                                unsigned long long *counter, unsigned int *walk, hipStream_t s);

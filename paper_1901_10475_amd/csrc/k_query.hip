@@ -202,12 +202,19 @@ __global__ __launch_bounds__(256) void k_expand(const void *__restrict__ tree,
     __shared__ uint32_t wsum[64];
     __shared__ unsigned int qbase;
     __shared__ unsigned long long rbase;
-    // gated: a set flag (queue overflow, bad node, or the traversal handed to
-    // the per-leaf walk) ends the node-pair levels
+    // gated: a set flag (queue overflow, bad node, the traversal handed to the
+    // per-leaf walk, or an earlier level found its queue empty) ends the
+    // node-pair levels
     if (gated && *flags)
         return;
     uint32_t n = *n_in;
     n = n < in_cap ? n : in_cap;
+    if (n == 0) {
+        // every pair has been expanded: flag 8 tells the host (and the gate)
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            atomicOr(flags, 8u);
+        return;
+    }
     // block-uniform loop: the block scan below needs every thread
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         uint32_t k = base + threadIdx.x;
@@ -307,11 +314,12 @@ __global__ void k_query_begin(const TreeHeader *hdr, unsigned int *qflags)
 }
 
 // After the last level: the per-leaf walk runs (from a cleared counter) if
-// any flag is set or the last queue is not empty.
+// an overflow, bad-node or handover flag is set (bits 1, 2, 4; bit 8 only
+// marks a drained queue) or the last queue is not empty.
 __global__ void k_query_decide(const unsigned int *last_count, const unsigned int *qflags,
                                unsigned long long *counter, unsigned int *walk)
 {
-    unsigned int w = (*qflags != 0 || *last_count != 0) ? 1u : 0u;
+    unsigned int w = ((*qflags & 7u) != 0 || *last_count != 0) ? 1u : 0u;
     if (w)
         *counter = 0ull;
     *walk = w;
@@ -350,6 +358,23 @@ __global__ void k_query_finish(const unsigned long long *counter, const unsigned
         n = (unsigned long long)*uniq - (c < cap ? 1ull : 0ull);
     *count_out = n;
     *status_out = st;
+}
+
+// The record count and the tree's error word side by side, for one read.
+__global__ void k_query_status(const unsigned long long *counter, const unsigned int *tree_err,
+                               unsigned int *out)
+{
+    unsigned long long c = *counter;
+    out[0] = (unsigned int)c;
+    out[1] = (unsigned int)(c >> 32);
+    out[2] = *tree_err;
+}
+
+hipError_t launch_query_status(const unsigned long long *counter, const unsigned int *tree_err,
+                               unsigned int *out, hipStream_t s)
+{
+    k_query_status<<<1, 1, 0, s>>>(counter, tree_err, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_query_begin(const TreeHeader *hdr, unsigned int *qflags, hipStream_t s)
