@@ -97,6 +97,10 @@ def lib():
         L.or_dt_heuristic.argtypes = [ctypes.c_int64, _dp, ctypes.c_double,
                                       ctypes.c_double, ctypes.c_double,
                                       ctypes.c_uint32, _dp]
+        L.or_refine.restype = ctypes.c_int64
+        L.or_refine.argtypes = [ctypes.c_int64, _dp, ctypes.c_uint32, ctypes.c_uint32,
+                                ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64, _dp, _u32pp]
         L.or_free.restype = None
         L.or_free.argtypes = [ctypes.c_void_p]
         L.or_num_threads.restype = ctypes.c_int
@@ -266,6 +270,21 @@ def brute_force(elements, r, T, delta, tick_s, mu=MU_EARTH):
     w = lib().or_brute_force(n, _ptr(el), _ptr(rr), int(T), int(delta), float(tick_s),
                              float(mu), ctypes.byref(out))
     return _take_records(w, out, 3)
+
+
+def refine(elements, records, T, tick_s, thr_km, delta, min_steps=1, rule=BOX_SPEED,
+           mu=MU_EARTH, start=0):
+    """Bulk interval refinement of candidate records [R,4] (i, j, t_lo, t_hi):
+    the canonical leaves [L,4] (i, j, first instant, last instant + 1)."""
+    el = _c(elements, np.float64).reshape(-1, 6)
+    rec = _c(np.asarray(records, dtype=np.uint32).reshape(-1, 4), np.uint32)
+    out = _u32p()
+    m = lib().or_refine(len(el), _ptr(el), int(T), int(start), float(tick_s), float(mu),
+                        float(thr_km), int(rule), int(delta), int(min_steps), len(rec),
+                        _ptr(rec), ctypes.byref(out))
+    if m < 0:
+        raise ValueError("invalid refinement arguments")
+    return _take_records(m, out, 4)
 
 
 def round_down_f32(x):

@@ -571,6 +571,94 @@ int64_t or_brute_force(int64_t n, const double *el, const double *r,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Bulk interval refinement                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* occ-int of one object over the continuous times [ta_s, tb_s] by the given
+ * rule: 0 the speed-bound box (endpoint hull grown by vmax * span / 2 and the
+ * radius), 1 or 2 the interval evaluation over the true or eccentric anomaly. */
+static void occ_int(const double e6[6], double ta_s, double tb_s, double mu, double thr_km,
+                    int rule, double lo[3], double hi[3])
+{
+    if (rule == 1 || rule == 2) {
+        or_box_interval(e6, ta_s, tb_s, mu, thr_km, rule, lo, hi);
+        return;
+    }
+    double pa[3], pb[3];
+    or_position(e6, ta_s, mu, pa);
+    or_position(e6, tb_s, mu, pb);
+    double g = or_vmax(e6[0], e6[1], mu) * (tb_s - ta_s) / 2.0 + thr_km / 2.0;
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = fmin(pa[d], pb[d]) - g;
+        hi[d] = fmax(pa[d], pb[d]) + g;
+    }
+}
+
+typedef struct {
+    const double *el;
+    double tick_s, mu, thr;
+    int rule;
+    uint64_t delta, start, min_steps;
+    or_vec *acc;
+} refine_ctx;
+
+/* Grid instants u..v (absolute tick u * delta .. v * delta) of objects i, j:
+ * dropped when their occ-int boxes over that span do not meet (no instant in
+ * it can collide); kept as one leaf once it holds at most min_steps instants;
+ * otherwise halved, the first half taking floor of half the steps as
+ * resolveCollisions does. */
+static void refine_span(const refine_ctx *c, uint32_t i, uint32_t j, uint64_t u, uint64_t v)
+{
+    double li[3], hi_[3], lj[3], hj[3];
+    double ta = (double)(u * c->delta) * c->tick_s, tb = (double)(v * c->delta) * c->tick_s;
+    occ_int(c->el + 6 * i, ta, tb, c->mu, c->thr, c->rule, li, hi_);
+    occ_int(c->el + 6 * j, ta, tb, c->mu, c->thr, c->rule, lj, hj);
+    for (int d = 0; d < 3; ++d)
+        if (li[d] > hj[d] || lj[d] > hi_[d])
+            return;
+    if (v - u + 1 <= c->min_steps) {
+        vec_push(c->acc, i, j, (uint32_t)(u * c->delta - c->start),
+                 (uint32_t)(v * c->delta - c->start + 1));
+        return;
+    }
+    uint64_t m = u + (v - u) / 2;
+    refine_span(c, i, j, u, m);
+    refine_span(c, i, j, m + 1, v);
+}
+
+/* The data-parallel form of the time halving of Procedure resolveCollisions:
+ * every candidate record (i, j, t_lo, t_hi) -- times relative to start, the
+ * last instant T -- covers the grid instants t with start + t a multiple of
+ * delta in [t_lo, min(t_hi - 1, T)]; their span is halved while the two
+ * objects' boxes over it meet.  Output: the canonical list of kept leaves
+ * (i, j, first instant, last instant + 1).  With min_steps = 1 and the speed
+ * box the leaves are exactly the instants at which the pair collides (a box
+ * over one instant is the occupancy cube, Property 1). */
+int64_t or_refine(int64_t n, const double *el, uint32_t T, uint32_t start, double tick_s,
+                  double mu, double thr_km, int rule, uint32_t delta, uint32_t min_steps,
+                  int64_t R, const uint32_t *rec, uint32_t **out)
+{
+    if (delta == 0 || min_steps == 0 || rule < 0 || rule > 2)
+        return -1;
+    or_vec acc = { 0, 0, 0 };
+    refine_ctx c = { el, tick_s, mu, thr_km, rule, delta, start, min_steps, &acc };
+    for (int64_t r = 0; r < R; ++r) {
+        uint32_t i = rec[4 * r], j = rec[4 * r + 1], tlo = rec[4 * r + 2], thi = rec[4 * r + 3];
+        if (i >= (uint64_t)n || j >= (uint64_t)n || thi <= tlo)
+            continue;
+        uint64_t last = (uint64_t)thi - 1 < (uint64_t)T ? (uint64_t)thi - 1 : (uint64_t)T;
+        if ((uint64_t)tlo > last)
+            continue;
+        uint64_t u = ((uint64_t)start + tlo + delta - 1) / delta;
+        uint64_t v = ((uint64_t)start + last) / delta;
+        if (u > v)
+            continue;
+        refine_span(&c, i, j, u, v);
+    }
+    return canonical(&acc, 1, out);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Growth pieces                                                             */
 /* ------------------------------------------------------------------------ */
 

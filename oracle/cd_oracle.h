@@ -103,6 +103,14 @@ void or_dt_heuristic(int64_t n, const double *el, double mu, double tick_s,
 void or_free(void *p);
 int or_num_threads(void);
 
+/* ---- bulk interval refinement (resolveCollisions' halving, in bulk) ---- */
+/* rec: R records (i, j, t_lo, t_hi) relative to start; rule as or_boxes;
+ * returns the canonical leaf count (rows of 4 in *out, free with or_free),
+ * -1 on bad arguments. */
+int64_t or_refine(int64_t n, const double *el, uint32_t T, uint32_t start, double tick_s,
+                  double mu, double thr_km, int rule, uint32_t delta, uint32_t min_steps,
+                  int64_t R, const uint32_t *rec, uint32_t **out);
+
 #ifdef __cplusplus
 }
 #endif
