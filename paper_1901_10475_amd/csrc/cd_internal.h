@@ -370,15 +370,19 @@ hipError_t launch_keys(const BoxView &b, int precision, uint32_t N, uint32_t sla
                        unsigned int *err, hipStream_t s);
 hipError_t launch_unpack_kv(const KV *kv, uint32_t N, uint64_t *keys, uint32_t *idx,
                             hipStream_t s);
-// Refit levels: level-k blocks hold refit_block(k) = 1024 * 16^k leaves.
-// Level 0 runs one workgroup per block with LDS-resident climbing; higher
-// levels climb in global memory from per-block queues.
-constexpr int kRefitChunk = 1024;
+// Refit levels: level-k blocks hold refit_block(k) = kRefitChunk * 16^k
+// leaves.  Level 0 runs one workgroup per block with LDS-resident climbing;
+// higher levels climb in global memory from per-block queues.
+constexpr int kRefitChunkLog = 10;
+constexpr int kRefitChunk = 1 << kRefitChunkLog;
 constexpr int kRefitListCap = 4096;   // queued nodes per block
 constexpr int kRefitMaxLevels = 8;
 constexpr uint32_t kCross = 0x80000000u;   // parent pointer flag: parent level > 0
 constexpr uint32_t kNodeMask = 0x7FFFFFFFu;
-__host__ __device__ inline uint32_t refit_shift(uint32_t lev) { return 10u + 4u * lev; }
+__host__ __device__ inline uint32_t refit_shift(uint32_t lev)
+{
+    return (uint32_t)kRefitChunkLog + 4u * lev;
+}
 
 // Tree buffer header (the first 256 bytes of cd_tree.mem).
 struct TreeHeader {
