@@ -314,6 +314,32 @@ int cd_first_witness(const cd_elements *el, const cd_params *p, uint32_t delta_t
                      const cd_pair *pairs, int64_t count, uint32_t *witness_out,
                      unsigned long long *first_out, cd_stream_t stream);
 
+/* ---- bulk interval refinement (Procedure resolveCollisions, in bulk) ----- */
+
+/* The time halving of Procedure resolveCollisions applied to every candidate
+ * record at once.  Record r = (i, j, t_lo, t_hi) of pairs[0..count) covers
+ * the grid instants t (relative ticks, start_ticks + t a multiple of
+ * delta_ticks) with t_lo <= t <= min(t_hi - 1, T).  Their span is dropped when
+ * the two objects' occ-int boxes over it (p->box_rule, as cd_build_boxes
+ * forms them, over the continuous time between its first and last instant)
+ * do not meet; kept as a leaf once it holds at most min_steps instants;
+ * otherwise halved, the first half taking half of the remaining steps rounded
+ * down, and each half tested again.  out receives the canonical list (sorted
+ * by i, j, t_lo, t_hi; repeats removed) of leaves (i, j, first instant, last
+ * instant + 1).  With min_steps = 1 and CD_BOX_SPEED the leaves are exactly
+ * the instants at which the pair collides (a box over one instant is the
+ * occupancy cube, Property 1); the interval rules add only instants within
+ * their 1e-10 rad widening of the threshold.
+ * *count_host = leaves written.  CD_E_CAPACITY: more leaves than capacity
+ * (*count_host = the leaf count), or a level's work queue, max(2 count,
+ * capacity, 65536) items, overflowed (*count_host = twice that); retry with
+ * capacity >= *count_host.  Synchronises. */
+size_t cd_refine_records_ws(int64_t n, int64_t count, int64_t capacity);
+int cd_refine_records(const cd_elements *el, const cd_params *p, uint32_t delta_ticks,
+                      uint32_t min_steps, const cd_pair *pairs, int64_t count, cd_pair *out,
+                      int64_t capacity, int64_t *count_host, void *ws, size_t ws_bytes,
+                      cd_stream_t stream);
+
 /* ---- learned per-object step ------------------------------------------- */
 
 /* The paper keeps a time interval per object so that objects far from all

@@ -113,6 +113,10 @@ def lib():
             "cd_graph_destroy": (ctypes.c_int, [_vp]),
             "cd_first_witness": (ctypes.c_int, [P(cd_elements), P(cd_params), u32, _vp, i64, _vp,
                                                 _vp, _vp]),
+            "cd_refine_records_ws": (sz, [i64, i64, i64]),
+            "cd_refine_records": (ctypes.c_int, [P(cd_elements), P(cd_params), u32, u32, _vp,
+                                                 i64, _vp, i64, P(ctypes.c_int64), _vp, sz,
+                                                 _vp]),
             "cd_mlp_features": (ctypes.c_int, [P(cd_elements), P(cd_params), _vp, _vp]),
             "cd_dt_mlp": (ctypes.c_int, [P(cd_elements), _vp, dbl, P(cd_params), _vp, _vp,
                                          _vp]),
@@ -137,7 +141,8 @@ EXPORTED = ("cd_status_string", "cd_last_error", "cd_version", "cd_profile_enabl
             "cd_build_boxes_ws", "cd_build_boxes", "cd_tree_bytes", "cd_build_tree_ws",
             "cd_build_tree", "cd_query_pairs_ws", "cd_query_pairs", "cd_query_pairs_async",
             "cd_set_tuning", "cd_get_tuning", "cd_graph_begin", "cd_graph_end",
-            "cd_graph_launch", "cd_graph_destroy", "cd_first_witness", "cd_mlp_features",
+            "cd_graph_launch", "cd_graph_destroy", "cd_first_witness", "cd_refine_records_ws",
+            "cd_refine_records", "cd_mlp_features",
             "cd_dt_mlp", "cd_mlp_forward", "cd_mlp_grad_ws", "cd_mlp_grad", "cd_mlp_adam",
             "cd_pair_object_counts")
 
@@ -391,6 +396,31 @@ def cd_first_witness(el_soa, params, delta_ticks, pairs):
     _check(lib().cd_first_witness(ctypes.byref(el), ctypes.byref(params), int(delta_ticks),
                                   _ptr(pairs), P, _ptr(wit), _ptr(first), _stream()))
     return wit[:P], first
+
+
+def cd_refine_records(el_soa, params, delta_ticks, pairs, min_steps=1, capacity=None):
+    """Bulk interval refinement of records (int32 [P, 4] CUDA tensor): the
+    canonical leaves, int32 [L, 4] (i, j, first instant, last instant + 1; read
+    as uint32).  Grows the output and work buffers and repeats when they are
+    too small."""
+    if not (pairs.is_cuda and pairs.dtype == torch.int32 and pairs.dim() == 2
+            and pairs.shape[1] == 4 and pairs.is_contiguous()):
+        raise ValueError("pairs: need a contiguous int32 CUDA tensor [P, 4]")
+    el = elements_struct(el_soa)
+    P = int(pairs.shape[0])
+    cap = int(capacity) if capacity is not None else max(4 * P, 1 << 16)
+    for _ in range(8):
+        out = torch.empty((max(cap, 1), 4), dtype=torch.int32, device=pairs.device)
+        ws = _bytes(lib().cd_refine_records_ws(el.n, P, cap), pairs.device)
+        cnt = ctypes.c_int64(0)
+        rc = lib().cd_refine_records(ctypes.byref(el), ctypes.byref(params), int(delta_ticks),
+                                     int(min_steps), _ptr(pairs), P, _ptr(out), cap,
+                                     ctypes.byref(cnt), _ptr(ws), ws.numel(), _stream())
+        if rc != CD_E_CAPACITY:
+            _check(rc)
+            return out[:cnt.value]
+        cap = max(int(cnt.value * 1.25) + 1024, 2 * cap)
+    _check(rc)
 
 
 def first_collision(pairs, first):

@@ -265,10 +265,10 @@ struct QueryWS {
 };
 // Radix passes of the canonical order (i, j, t_lo, t_hi), least significant
 // field first, over the bits each field can use.
-DigitPlan record_plan(const cd_tree *tree)
+DigitPlan record_plan_bits(uint32_t horizon_ticks, uint32_t obj_count)
 {
-    int tb = bits_for((uint64_t)tree->horizon_ticks + 1);
-    int ob = tree->obj_count ? bits_for((uint64_t)tree->obj_count - 1) : 32;
+    int tb = bits_for((uint64_t)horizon_ticks + 1);
+    int ob = obj_count ? bits_for((uint64_t)obj_count - 1) : 32;
     DigitPlan plan;
     memset(&plan, 0, sizeof plan);
     const int fields[4] = {3, 2, 1, 0};  // t_hi, t_lo, j, i
@@ -280,6 +280,11 @@ DigitPlan record_plan(const cd_tree *tree)
             ++plan.npass;
         }
     return plan;
+}
+
+DigitPlan record_plan(const cd_tree *tree)
+{
+    return record_plan_bits(tree->horizon_ticks, tree->obj_count);
 }
 
 // node pairs per traversal level: N covers every case seen short of boxes that
@@ -294,6 +299,57 @@ size_t layout_query(void *base, size_t bytes, int64_t N, int64_t cap, QueryWS *w
     w->qb = c.take<uint2>(w->qcap);
     w->qcount = c.take<unsigned int>(kCtlWords);
     w->qflags = w->qcount + kCtlFlags;
+    w->raw = c.take<Rec>(m);
+    w->alt = c.take<Rec>(m);
+    w->counter = c.take<unsigned long long>(1);
+    w->flags = c.take<uint32_t>(m);
+    w->pos = c.take<uint32_t>(m + 1);
+    w->scan = c.take_bytes(scan_ws_bytes(m));
+    w->radix = c.take_bytes(radix_ws_bytes(m));
+    return c.off;
+}
+
+// Bulk interval refinement: control words [l] = queue count before level l,
+// then the level flags and a status copy (leaf count low/high, flags, last
+// queue count).
+constexpr int kRefineMaxLevels = 40;      // > log2(2^32 instants) + 2
+constexpr int kRefCtlFlags = kRefineMaxLevels + 1;
+constexpr int kRefCtlStatus = kRefineMaxLevels + 4;
+constexpr int kRefCtlWords = kRefCtlStatus + 4;
+
+struct RefineWS {
+    ObjConst *oc;
+    ObjSinus *os;
+    uint4 *qa, *qb;
+    unsigned int *ctl;
+    Rec *raw, *alt;
+    unsigned long long *counter;
+    uint32_t *flags, *pos;
+    void *scan, *radix;
+    uint32_t qcap;
+};
+// work items per level: the records twice over, the output capacity, or 2^16
+uint32_t refine_queue_cap(int64_t count, int64_t capacity)
+{
+    uint64_t q = (uint64_t)(count > 0 ? count : 0) * 2;
+    if ((uint64_t)capacity > q)
+        q = (uint64_t)capacity;
+    if (q < 65536)
+        q = 65536;
+    return (uint32_t)(q < 0xFFFFFFF0ull ? q : 0xFFFFFFF0ull);
+}
+size_t layout_refine(void *base, size_t bytes, int64_t n, int64_t count, int64_t cap,
+                     RefineWS *w)
+{
+    Carve c(base, bytes);
+    size_t m = (size_t)(cap > 0 ? cap : 1);
+    size_t no = (size_t)(n > 0 ? n : 1);
+    w->qcap = refine_queue_cap(count, cap);
+    w->oc = c.take<ObjConst>(no);
+    w->os = c.take<ObjSinus>(no);
+    w->qa = c.take<uint4>(w->qcap);
+    w->qb = c.take<uint4>(w->qcap);
+    w->ctl = c.take<unsigned int>(kRefCtlWords);
     w->raw = c.take<Rec>(m);
     w->alt = c.take<Rec>(m);
     w->counter = c.take<unsigned long long>(1);
@@ -977,6 +1033,109 @@ int cd_first_witness(const cd_elements *el, const cd_params *p, uint32_t delta_t
     CD_HIP(launch_first_witness(*el, p->mu, p->tick_s, p->start_ticks, p->threshold_km,
                                 p->horizon_ticks, delta_ticks, pairs, (uint64_t)count,
                                 witness_out, first_out, (hipStream_t)stream));
+    return CD_OK;
+}
+
+// ---- bulk interval refinement -----------------------------------------------------------
+
+size_t cd_refine_records_ws(int64_t n, int64_t count, int64_t capacity)
+{
+    RefineWS w;
+    return layout_refine(nullptr, 0, n, count, capacity, &w);
+}
+
+int cd_refine_records(const cd_elements *el, const cd_params *p, uint32_t delta_ticks,
+                      uint32_t min_steps, const cd_pair *pairs, int64_t count, cd_pair *out,
+                      int64_t capacity, int64_t *count_host, void *ws, size_t ws_bytes,
+                      cd_stream_t stream)
+{
+    int rc = check_elements(el);
+    if (!rc)
+        rc = check_params(p);
+    if (rc)
+        return rc;
+    if (!count_host)
+        return fail(CD_E_INVALID, "count_host is NULL");
+    *count_host = 0;
+    if (delta_ticks == 0 || min_steps == 0)
+        return fail(CD_E_INVALID, "delta_ticks and min_steps must be >= 1");
+    if (count < 0 || count > 0x7FFFFFFFll)
+        return fail(CD_E_INVALID, "count out of range");
+    if (capacity < 0 || capacity > 0xFFFFFFFEll)
+        return fail(CD_E_INVALID, "capacity out of range");
+    if (count > 0 && !pairs)
+        return fail(CD_E_INVALID, "pairs is NULL");
+    if (capacity > 0 && !out)
+        return fail(CD_E_INVALID, "out is NULL");
+    if (!ws || ws_bytes < cd_refine_records_ws(el->n, count, capacity))
+        return fail(CD_E_WORKSPACE, "refine workspace too small");
+    if (count == 0 || el->n == 0)
+        return CD_OK;
+    hipStream_t s = (hipStream_t)stream;
+    RefineWS w;
+    layout_refine(ws, ws_bytes, el->n, count, capacity, &w);
+    const uint32_t T = p->horizon_ticks;
+    // levels: every split halves a span, and a record holds at most T / delta + 1
+    // instants, so after ceil(log2) + 2 levels every item is a leaf or dropped
+    uint64_t kmax = (uint64_t)T / delta_ticks + 1;
+    int levels = 2;
+    while ((1ull << (levels - 2)) < kmax)
+        ++levels;
+    unsigned int st4[4];
+    {
+        Stage st("refine", s);
+        CD_HIP(launch_object_setup(*el, p->mu, (double)p->start_ticks * p->tick_s, w.oc, w.os,
+                                   s));
+        CD_HIP(launch_fill_u32(w.ctl, 0u, kRefCtlWords, s));
+        CD_HIP(launch_fill_u32(w.ctl, (uint32_t)count, 1, s));
+        CD_HIP(launch_fill_u64(w.counter, 0ull, 1, s));
+        CD_HIP(launch_refine_seed(pairs, (uint32_t)count, p->start_ticks, T, delta_ticks, w.qa,
+                                  s));
+        for (int lev = 0; lev < levels; ++lev) {
+            const uint4 *in = (lev & 1) ? w.qb : w.qa;
+            uint4 *outq = (lev & 1) ? w.qa : w.qb;
+            // at most count * 2^lev items reach level lev
+            uint64_t most = (uint64_t)count << (lev < 32 ? lev : 32);
+            if (most > w.qcap)
+                most = w.qcap;
+            uint32_t blocks = (uint32_t)((most + 255) / 256);
+            blocks = blocks < 1 ? 1 : (blocks > 2048 ? 2048 : blocks);
+            CD_HIP(launch_refine_level((int)p->box_rule, w.oc, w.os, (uint32_t)el->n, pairs, in,
+                                       w.ctl + lev, w.qcap, outq, w.ctl + lev + 1, w.qcap,
+                                       w.raw, (unsigned long long)capacity, w.counter,
+                                       w.ctl + kRefCtlFlags, delta_ticks, min_steps, p->tick_s,
+                                       0.5 * p->threshold_km, blocks, s));
+        }
+        CD_HIP(launch_refine_status(w.counter, w.ctl + kRefCtlFlags, w.ctl + levels,
+                                    w.ctl + kRefCtlStatus, s));
+        CD_HIP(hipMemcpyAsync(st4, w.ctl + kRefCtlStatus, sizeof st4, hipMemcpyDeviceToHost, s));
+        CD_HIP(hipStreamSynchronize(s));
+    }
+    unsigned long long cnt = (unsigned long long)st4[0] | ((unsigned long long)st4[1] << 32);
+    if (st4[2] & 1u) {
+        // a level's work queue overflowed: ask for room for twice that many
+        *count_host = 2 * (int64_t)w.qcap;
+        return fail(CD_E_CAPACITY, "refinement work queue of %u items overflowed", w.qcap);
+    }
+    if (st4[3] != 0)
+        return fail(CD_E_DEVICE, "refinement did not finish in %d levels", levels);
+    *count_host = (int64_t)cnt;
+    if (cnt > (unsigned long long)capacity)
+        return fail(CD_E_CAPACITY, "%llu leaves exceed capacity %lld", cnt, (long long)capacity);
+    if (cnt == 0)
+        return CD_OK;
+    uint32_t nleaf = (uint32_t)cnt;
+    DigitPlan plan = record_plan_bits(T, (uint32_t)el->n);
+    void *res = nullptr;
+    {
+        Stage st("refine_canon", s);
+        CD_HIP(radix_sort16(SORT_REC, w.raw, w.alt, nleaf, plan, w.radix, &res, s));
+        CD_HIP(launch_unique((const Rec *)res, nleaf, w.flags, w.pos, w.scan, (Rec *)out, s));
+    }
+    uint32_t uniq = 0;
+    CD_HIP(hipMemcpyAsync(&uniq, w.pos + nleaf, sizeof uniq, hipMemcpyDeviceToHost, s));
+    CD_HIP(hipStreamSynchronize(s));
+    *count_host = uniq;
     return CD_OK;
 }
 

@@ -501,6 +501,18 @@ hipError_t launch_pad_records(Rec *raw, const unsigned long long *counter, uint3
 hipError_t launch_query_finish(const unsigned long long *counter, const unsigned int *tree_err,
                                const uint32_t *uniq, uint32_t cap, unsigned long long *count_out,
                                unsigned int *status_out, hipStream_t s);
+// bulk interval refinement (items {record, first instant, last instant, 0})
+hipError_t launch_refine_seed(const cd_pair *pairs, uint32_t count, uint32_t start, uint32_t T,
+                              uint32_t delta, uint4 *items, hipStream_t s);
+hipError_t launch_refine_level(int rule, const ObjConst *oc, const ObjSinus *os, uint32_t n,
+                               const cd_pair *pairs, const uint4 *in, const unsigned int *n_in,
+                               uint32_t in_cap, uint4 *outq, unsigned int *n_out,
+                               uint32_t out_cap, Rec *leaves, unsigned long long leaf_cap,
+                               unsigned long long *leaf_count, unsigned int *flags,
+                               uint32_t delta, uint32_t min_steps, double tick_s,
+                               double half_thr, uint32_t blocks, hipStream_t s);
+hipError_t launch_refine_status(const unsigned long long *leaf_count, const unsigned int *flags,
+                                const unsigned int *last_count, unsigned int *out, hipStream_t s);
 hipError_t launch_unique(const Rec *in, uint32_t count, uint32_t *flags, uint32_t *pos,
                          void *scan_ws, Rec *out, hipStream_t s);
 

@@ -129,3 +129,34 @@ def test_step_network_argument_errors_before_any_launch():
     # workspace grows with the batch: activations + one partial row per 128 samples
     w1, w2 = L.cd_mlp_grad_ws(1), L.cd_mlp_grad_ws(5000)
     assert w2 >= 258 * 4 * 5000 + 40 * 4610 * 4 > w1 > 0
+
+
+def test_refine_argument_errors_before_any_launch():
+    import paper_1901_10475_amd as cd
+    L = cd.lib()
+    p = cd.params_struct(1e-3, 398600.4418, 1.0, 600, 10)
+    el0 = cd.cd_elements(None, None, None, None, None, None, 0)
+    fake = ctypes.c_void_p(16)                                       # never dereferenced
+    cnt = ctypes.c_int64(7)
+    ws_bytes = L.cd_refine_records_ws(0, 0, 0)
+    assert ws_bytes > 0
+    # delta or min_steps 0, negative count, NULL pairs, missing workspace
+    assert L.cd_refine_records(ctypes.byref(el0), ctypes.byref(p), 0, 1, None, 0, None, 0,
+                               ctypes.byref(cnt), fake, ws_bytes, None) == cd.CD_E_INVALID
+    assert L.cd_refine_records(ctypes.byref(el0), ctypes.byref(p), 1, 0, None, 0, None, 0,
+                               ctypes.byref(cnt), fake, ws_bytes, None) == cd.CD_E_INVALID
+    assert L.cd_refine_records(ctypes.byref(el0), ctypes.byref(p), 1, 1, None, -1, None, 0,
+                               ctypes.byref(cnt), fake, ws_bytes, None) == cd.CD_E_INVALID
+    assert L.cd_refine_records(ctypes.byref(el0), ctypes.byref(p), 1, 1, None, 5, fake, 5,
+                               ctypes.byref(cnt), fake, 1 << 30, None) == cd.CD_E_INVALID
+    assert L.cd_refine_records(ctypes.byref(el0), ctypes.byref(p), 1, 1, fake, 5, fake, 5,
+                               ctypes.byref(cnt), fake, 16, None) == cd.CD_E_WORKSPACE
+    bad = cd.params_struct(1e-3, 398600.4418, 1.0, 600, 10, box_rule=9)
+    assert L.cd_refine_records(ctypes.byref(el0), ctypes.byref(bad), 1, 1, None, 0, None, 0,
+                               ctypes.byref(cnt), fake, ws_bytes, None) == cd.CD_E_INVALID
+    # nothing to refine: no launch, zero leaves
+    assert L.cd_refine_records(ctypes.byref(el0), ctypes.byref(p), 1, 1, None, 0, None, 0,
+                               ctypes.byref(cnt), fake, ws_bytes, None) == cd.CD_OK
+    assert cnt.value == 0
+    # the work queue is sized from the records and the capacity
+    assert L.cd_refine_records_ws(100, 10**6, 0) > L.cd_refine_records_ws(100, 10, 0)
