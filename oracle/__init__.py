@@ -101,6 +101,16 @@ def lib():
         L.or_refine.argtypes = [ctypes.c_int64, _dp, ctypes.c_uint32, ctypes.c_uint32,
                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                 ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int64, _dp, _u32pp]
+        L.or_band.restype = None
+        L.or_band.argtypes = [_dp, ctypes.c_double, _dp, _dp]
+        L.or_band_compatible.restype = ctypes.c_int
+        L.or_band_compatible.argtypes = [_dp, _dp, ctypes.c_double]
+        L.or_band_filter.restype = ctypes.c_int64
+        L.or_band_filter.argtypes = [ctypes.c_int64, _dp, ctypes.c_double, ctypes.c_int64, _dp,
+                                     _u32pp]
+        L.or_band_partition.restype = ctypes.c_int64
+        L.or_band_partition.argtypes = [ctypes.c_int64, _dp, ctypes.c_double, ctypes.c_int,
+                                        _dp, _dp, _dp]
         L.or_free.restype = None
         L.or_free.argtypes = [ctypes.c_void_p]
         L.or_num_threads.restype = ctypes.c_int
@@ -285,6 +295,45 @@ def refine(elements, records, T, tick_s, thr_km, delta, min_steps=1, rule=BOX_SP
     if m < 0:
         raise ValueError("invalid refinement arguments")
     return _take_records(m, out, 4)
+
+
+def band(el, thr_km):
+    """Radial band [lo, hi] of one object (perigee/apogee widened by sqrt(3) r)."""
+    el = _c(el, np.float64)
+    lo, hi = ctypes.c_double(0), ctypes.c_double(0)
+    lib().or_band(_ptr(el), float(thr_km), ctypes.byref(lo), ctypes.byref(hi))
+    return lo.value, hi.value
+
+
+def band_compatible(el_i, el_j, thr_km):
+    a = _c(el_i, np.float64)
+    b = _c(el_j, np.float64)
+    return bool(lib().or_band_compatible(_ptr(a), _ptr(b), float(thr_km)))
+
+
+def band_filter(elements, records, thr_km):
+    el = _c(elements, np.float64).reshape(-1, 6)
+    rec = _c(np.asarray(records, dtype=np.uint32).reshape(-1, 4), np.uint32)
+    out = _u32p()
+    m = lib().or_band_filter(len(el), _ptr(el), float(thr_km), len(rec), _ptr(rec),
+                             ctypes.byref(out))
+    return _take_records(m, out, 4)
+
+
+def band_partition(elements, thr_km, p):
+    """(edges [p+1], per-band object id arrays) of the altitude-band edge partition."""
+    el = _c(elements, np.float64).reshape(-1, 6)
+    edges = np.zeros(p + 1)
+    count = np.zeros(p, np.int64)
+    total = lib().or_band_partition(len(el), _ptr(el), float(thr_km), int(p), _ptr(edges),
+                                    _ptr(count), None)
+    if total < 0:
+        raise ValueError("p must be >= 1")
+    members = np.zeros(max(total, 1), np.uint32)
+    lib().or_band_partition(len(el), _ptr(el), float(thr_km), int(p), _ptr(edges),
+                            _ptr(count), _ptr(members))
+    off = np.concatenate([[0], np.cumsum(count)])
+    return edges, [members[off[k]:off[k + 1]] for k in range(p)]
 
 
 def round_down_f32(x):

@@ -659,6 +659,100 @@ int64_t or_refine(int64_t n, const double *el, uint32_t T, uint32_t start, doubl
 }
 
 /* ------------------------------------------------------------------------ */
+/* Potential-collision graph by altitude bands                               */
+/* ------------------------------------------------------------------------ */
+
+/* Radial band of an object (Def. Potential-Collision Graph with the perigee
+ * and apogee test of the orbit evaluation): every position lies between the
+ * perigee a(1 - e) and the apogee a(1 + e) from the Earth's centre, and every
+ * point of its occupancy cube within sqrt(3) r of the position (the cube's
+ * circumscribed sphere), r = thr / 2. */
+void or_band(const double el6[6], double thr_km, double *lo, double *hi)
+{
+    double a = el6[0], e = el6[1];
+    double pad = sqrt(3.0) * 0.5 * thr_km;
+    *lo = a * (1.0 - e) - pad;
+    *hi = a * (1.0 + e) + pad;
+}
+
+/* Two objects can collide only if their bands meet: a common point of the two
+ * cubes has one distance from the centre, inside both bands. */
+int or_band_compatible(const double el_i[6], const double el_j[6], double thr_km)
+{
+    double li, hi, lj, hj;
+    or_band(el_i, thr_km, &li, &hi);
+    or_band(el_j, thr_km, &lj, &hj);
+    return li <= hj && lj <= hi;
+}
+
+/* The records (i, j, t_lo, t_hi) whose objects are band-compatible, in input
+ * order; returns their count (rows of 4 in *out). */
+int64_t or_band_filter(int64_t n, const double *el, double thr_km, int64_t R,
+                       const uint32_t *rec, uint32_t **out)
+{
+    uint32_t *res = (uint32_t *)malloc((size_t)(R > 0 ? R : 1) * 4 * sizeof(uint32_t));
+    int64_t m = 0;
+    for (int64_t r = 0; r < R; ++r) {
+        uint32_t i = rec[4 * r], j = rec[4 * r + 1];
+        if (i >= (uint64_t)n || j >= (uint64_t)n)
+            continue;
+        if (or_band_compatible(el + 6 * i, el + 6 * j, thr_km)) {
+            memcpy(res + 4 * m, rec + 4 * r, 4 * sizeof(uint32_t));
+            ++m;
+        }
+    }
+    *out = res;
+    return m;
+}
+
+static int cmp_double(const void *pa, const void *pb)
+{
+    double a = *(const double *)pa, b = *(const double *)pb;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+/* Edge partitioning into p altitude bands (Sec. 7, orbital decomposition):
+ * the semi-major axes sorted, every d-th one (d = floor(n / p), at least 1)
+ * marks an edge, edges[0] = -inf and edges[p] = +inf; object i joins every
+ * band [edges[k], edges[k+1]) that its radial band [lo_i, hi_i] meets.
+ * Writes edges[p + 1] and count[p] (objects per band); if members is not NULL
+ * it receives the bands' object ids, band by band, ascending within a band
+ * (sum of count entries).  Returns that sum. */
+int64_t or_band_partition(int64_t n, const double *el, double thr_km, int p, double *edges,
+                          int64_t *count, uint32_t *members)
+{
+    if (p < 1)
+        return -1;
+    double *a = (double *)malloc((size_t)(n > 0 ? n : 1) * sizeof(double));
+    for (int64_t i = 0; i < n; ++i)
+        a[i] = el[6 * i];
+    qsort(a, (size_t)n, sizeof(double), cmp_double);
+    int64_t d = n / p > 0 ? n / p : 1;
+    edges[0] = -INFINITY;
+    edges[p] = INFINITY;
+    for (int k = 1; k < p; ++k) {
+        int64_t at = (int64_t)k * d;
+        edges[k] = n > 0 ? a[at < n ? at : n - 1] : 0.0;
+    }
+    free(a);
+    int64_t total = 0;
+    for (int k = 0; k < p; ++k) {
+        count[k] = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            double lo, hi;
+            or_band(el + 6 * i, thr_km, &lo, &hi);
+            if (lo < edges[k + 1] && hi >= edges[k]) {
+                if (members)
+                    members[total] = (uint32_t)i;
+                ++count[k];
+                ++total;
+            }
+        }
+    }
+    return total;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Growth pieces                                                             */
 /* ------------------------------------------------------------------------ */
 

@@ -111,6 +111,14 @@ int64_t or_refine(int64_t n, const double *el, uint32_t T, uint32_t start, doubl
                   double mu, double thr_km, int rule, uint32_t delta, uint32_t min_steps,
                   int64_t R, const uint32_t *rec, uint32_t **out);
 
+/* ---- potential-collision graph by altitude bands ---- */
+void or_band(const double el6[6], double thr_km, double *lo, double *hi);
+int or_band_compatible(const double el_i[6], const double el_j[6], double thr_km);
+int64_t or_band_filter(int64_t n, const double *el, double thr_km, int64_t R,
+                       const uint32_t *rec, uint32_t **out);
+int64_t or_band_partition(int64_t n, const double *el, double thr_km, int p, double *edges,
+                          int64_t *count, uint32_t *members);
+
 #ifdef __cplusplus
 }
 #endif
