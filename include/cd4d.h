@@ -340,6 +340,60 @@ int cd_refine_records(const cd_elements *el, const cd_params *p, uint32_t delta_
                       int64_t capacity, int64_t *count_host, void *ws, size_t ws_bytes,
                       cd_stream_t stream);
 
+/* ---- potential-collision graph by altitude bands ------------------------ */
+
+/* Def. Potential-Collision Graph, with the perigee/apogee test of the orbit
+ * evaluation: object i lies at distances from the Earth's centre in its radial
+ * band [a_i(1 - e_i) - sqrt(3) r, a_i(1 + e_i) + sqrt(3) r], r = thr / 2 (a
+ * point of its occupancy cube is within sqrt(3) r of the position, the cube's
+ * circumscribed sphere), so objects with disjoint bands never collide.
+ *
+ * cd_band_filter: out[0..*count_host) = the records of pairs[0..count) whose
+ * objects' bands meet, in input order (a canonical input stays canonical).
+ * out may not alias pairs.  Synchronises. */
+size_t cd_band_filter_ws(int64_t count);
+int cd_band_filter(const cd_elements *el, const cd_params *p, const cd_pair *pairs,
+                   int64_t count, cd_pair *out, int64_t *count_host, void *ws, size_t ws_bytes,
+                   cd_stream_t stream);
+
+/* Edge partitioning into nbands altitude bands (Sec. 6 and the orbit
+ * evaluation's decomposition): edges[0] = -inf, edges[nbands] = +inf and
+ * edges[k] = the (k * max(1, n / nbands))-th smallest semi-major axis; object
+ * i joins every band k with lo_i < edges[k + 1] and hi_i >= edges[k] (its
+ * radial band meets [edges[k], edges[k + 1])).  Every band-compatible pair
+ * shares a band, so the bands are independent problems whose records, mapped
+ * back (cd_remap_records) and filtered (cd_band_filter), make up the filtered
+ * records of the whole catalog.  Outputs (device): edges[nbands + 1] (double),
+ * offsets[nbands + 1] (uint32: band k's objects are members[offsets[k] ..
+ * offsets[k + 1]), ascending ids), members[capacity].  *count_host = the
+ * number of memberships; CD_E_CAPACITY if it exceeds capacity.
+ * 1 <= nbands <= 4096, n * nbands < 2^32.  Synchronises. */
+size_t cd_band_partition_ws(int64_t n, int32_t nbands);
+int cd_band_partition(const cd_elements *el, const cd_params *p, int32_t nbands, double *edges,
+                      uint32_t *offsets, uint32_t *members, int64_t capacity,
+                      int64_t *count_host, void *ws, size_t ws_bytes, cd_stream_t stream);
+
+/* out (device, 6 * count doubles): row d = element d (a, e, inc, raan, argp,
+ * m0) of objects ids[0..count), at out + d * count.  Ids >= el->n leave their
+ * column untouched.  Async. */
+int cd_gather_elements(const cd_elements *el, const uint32_t *ids, int64_t count, double *out,
+                       cd_stream_t stream);
+
+/* out[r] = (min(ids[i], ids[j]), max(ids[i], ids[j]), t_lo, t_hi) for record
+ * r = (i, j, t_lo, t_hi) of in (local ids < nids; others map to 0xFFFFFFFF).
+ * out may alias in.  Async. */
+int cd_remap_records(const cd_pair *in, int64_t count, const uint32_t *ids, int64_t nids,
+                     cd_pair *out, cd_stream_t stream);
+
+/* The canonical list of any records (sorted by i, j, t_lo, t_hi; repeats
+ * removed), e.g. the bands' records merged: out[0..*count_host).  Record
+ * fields must fit horizon_ticks + 1 (times) and obj_count (ids).
+ * Synchronises. */
+size_t cd_canonical_records_ws(int64_t count);
+int cd_canonical_records(const cd_pair *in, int64_t count, uint32_t horizon_ticks,
+                         uint32_t obj_count, cd_pair *out, int64_t *count_host, void *ws,
+                         size_t ws_bytes, cd_stream_t stream);
+
 /* ---- learned per-object step ------------------------------------------- */
 
 /* The paper keeps a time interval per object so that objects far from all

@@ -114,6 +114,18 @@ def lib():
             "cd_first_witness": (ctypes.c_int, [P(cd_elements), P(cd_params), u32, _vp, i64, _vp,
                                                 _vp, _vp]),
             "cd_refine_records_ws": (sz, [i64, i64, i64]),
+            "cd_band_filter_ws": (sz, [i64]),
+            "cd_band_filter": (ctypes.c_int, [P(cd_elements), P(cd_params), _vp, i64, _vp,
+                                              P(ctypes.c_int64), _vp, sz, _vp]),
+            "cd_band_partition_ws": (sz, [i64, ctypes.c_int32]),
+            "cd_band_partition": (ctypes.c_int, [P(cd_elements), P(cd_params), ctypes.c_int32,
+                                                 _vp, _vp, _vp, i64, P(ctypes.c_int64), _vp,
+                                                 sz, _vp]),
+            "cd_gather_elements": (ctypes.c_int, [P(cd_elements), _vp, i64, _vp, _vp]),
+            "cd_remap_records": (ctypes.c_int, [_vp, i64, _vp, i64, _vp, _vp]),
+            "cd_canonical_records_ws": (sz, [i64]),
+            "cd_canonical_records": (ctypes.c_int, [_vp, i64, u32, u32, _vp,
+                                                    P(ctypes.c_int64), _vp, sz, _vp]),
             "cd_refine_records": (ctypes.c_int, [P(cd_elements), P(cd_params), u32, u32, _vp,
                                                  i64, _vp, i64, P(ctypes.c_int64), _vp, sz,
                                                  _vp]),
@@ -142,7 +154,9 @@ EXPORTED = ("cd_status_string", "cd_last_error", "cd_version", "cd_profile_enabl
             "cd_build_tree", "cd_query_pairs_ws", "cd_query_pairs", "cd_query_pairs_async",
             "cd_set_tuning", "cd_get_tuning", "cd_graph_begin", "cd_graph_end",
             "cd_graph_launch", "cd_graph_destroy", "cd_first_witness", "cd_refine_records_ws",
-            "cd_refine_records", "cd_mlp_features",
+            "cd_refine_records", "cd_band_filter_ws", "cd_band_filter", "cd_band_partition_ws",
+            "cd_band_partition", "cd_gather_elements", "cd_remap_records",
+            "cd_canonical_records_ws", "cd_canonical_records", "cd_mlp_features",
             "cd_dt_mlp", "cd_mlp_forward", "cd_mlp_grad_ws", "cd_mlp_grad", "cd_mlp_adam",
             "cd_pair_object_counts")
 
@@ -421,6 +435,79 @@ def cd_refine_records(el_soa, params, delta_ticks, pairs, min_steps=1, capacity=
             return out[:cnt.value]
         cap = max(int(cnt.value * 1.25) + 1024, 2 * cap)
     _check(rc)
+
+
+def _need_pairs(pairs):
+    if not (pairs.is_cuda and pairs.dtype == torch.int32 and pairs.dim() == 2
+            and pairs.shape[1] == 4 and pairs.is_contiguous()):
+        raise ValueError("pairs: need a contiguous int32 CUDA tensor [P, 4]")
+
+
+def cd_band_filter(el_soa, params, pairs):
+    """The records whose objects' radial bands meet (int32 [K, 4], input order)."""
+    _need_pairs(pairs)
+    el = elements_struct(el_soa)
+    P = int(pairs.shape[0])
+    out = torch.empty((max(P, 1), 4), dtype=torch.int32, device=pairs.device)
+    ws = _bytes(lib().cd_band_filter_ws(P), pairs.device)
+    cnt = ctypes.c_int64(0)
+    _check(lib().cd_band_filter(ctypes.byref(el), ctypes.byref(params), _ptr(pairs), P,
+                                _ptr(out), ctypes.byref(cnt), _ptr(ws), ws.numel(), _stream()))
+    return out[:cnt.value]
+
+
+def cd_band_partition(el_soa, params, nbands):
+    """(edges float64 [p+1], offsets int32 [p+1], members int32 [M]) on the device:
+    band k's objects are members[offsets[k]:offsets[k+1]]."""
+    el = elements_struct(el_soa)
+    dev = el_soa.device
+    edges = torch.empty(int(nbands) + 1, dtype=torch.float64, device=dev)
+    offsets = torch.empty(int(nbands) + 1, dtype=torch.int32, device=dev)
+    cap = max(2 * el.n, 1)
+    ws = _bytes(lib().cd_band_partition_ws(el.n, int(nbands)), dev)
+    for _ in range(2):
+        members = torch.empty(cap, dtype=torch.int32, device=dev)
+        cnt = ctypes.c_int64(0)
+        rc = lib().cd_band_partition(ctypes.byref(el), ctypes.byref(params), int(nbands),
+                                     _ptr(edges), _ptr(offsets), _ptr(members), cap,
+                                     ctypes.byref(cnt), _ptr(ws), ws.numel(), _stream())
+        if rc != CD_E_CAPACITY:
+            _check(rc)
+            return edges, offsets, members[:cnt.value]
+        cap = int(cnt.value)
+    _check(rc)
+
+
+def cd_gather_elements(el_soa, ids):
+    """Elements [6, len(ids)] of objects ids (int32 CUDA tensor)."""
+    el = elements_struct(el_soa)
+    out = torch.empty((6, max(int(ids.numel()), 1)), dtype=torch.float64, device=el_soa.device)
+    _check(lib().cd_gather_elements(ctypes.byref(el), _ptr(ids), int(ids.numel()), _ptr(out),
+                                    _stream()))
+    return out[:, :int(ids.numel())]
+
+
+def cd_remap_records(pairs, ids, out=None):
+    """Local ids of records mapped through ids (int32 CUDA tensor) into out."""
+    _need_pairs(pairs)
+    if out is None:
+        out = torch.empty_like(pairs)
+    _check(lib().cd_remap_records(_ptr(pairs), int(pairs.shape[0]), _ptr(ids),
+                                  int(ids.numel()), _ptr(out), _stream()))
+    return out
+
+
+def cd_canonical_records(pairs, horizon_ticks, obj_count):
+    """The canonical list (sorted, repeats removed) of any records."""
+    _need_pairs(pairs)
+    P = int(pairs.shape[0])
+    out = torch.empty((max(P, 1), 4), dtype=torch.int32, device=pairs.device)
+    ws = _bytes(lib().cd_canonical_records_ws(P), pairs.device)
+    cnt = ctypes.c_int64(0)
+    _check(lib().cd_canonical_records(_ptr(pairs), P, int(horizon_ticks), int(obj_count),
+                                      _ptr(out), ctypes.byref(cnt), _ptr(ws), ws.numel(),
+                                      _stream()))
+    return out[:cnt.value]
 
 
 def first_collision(pairs, first):

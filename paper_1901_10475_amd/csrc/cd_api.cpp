@@ -360,6 +360,47 @@ size_t layout_refine(void *base, size_t bytes, int64_t n, int64_t count, int64_t
     return c.off;
 }
 
+// Potential-collision graph by altitude bands.
+constexpr int kMaxBands = 4096;
+double band_pad(const cd_params *p) { return sqrt(3.0) * 0.5 * p->threshold_km; }
+
+struct BandWS {
+    KV *ka, *kb;
+    uint32_t *cnt, *off;
+    void *scan, *radix;
+};
+size_t layout_bands(void *base, size_t bytes, int64_t n, int64_t nbands, BandWS *w)
+{
+    Carve c(base, bytes);
+    size_t no = (size_t)(n > 0 ? n : 1);
+    size_t m = no * (size_t)(nbands > 0 ? nbands : 1);   // memberships: at most n per band
+    w->ka = c.take<KV>(m);
+    w->kb = c.take<KV>(m);
+    w->cnt = c.take<uint32_t>(no + 1);
+    w->off = c.take<uint32_t>(no + 1);
+    w->scan = c.take_bytes(scan_ws_bytes(no + 1));
+    w->radix = c.take_bytes(radix_ws_bytes(m));
+    return c.off;
+}
+
+struct RecWS {
+    Rec *raw, *alt;
+    uint32_t *flags, *pos;
+    void *scan, *radix;
+};
+size_t layout_records(void *base, size_t bytes, int64_t count, RecWS *w)
+{
+    Carve c(base, bytes);
+    size_t m = (size_t)(count > 0 ? count : 1);
+    w->raw = c.take<Rec>(m);
+    w->alt = c.take<Rec>(m);
+    w->flags = c.take<uint32_t>(m + 1);
+    w->pos = c.take<uint32_t>(m + 1);
+    w->scan = c.take_bytes(scan_ws_bytes(m + 1));
+    w->radix = c.take_bytes(radix_ws_bytes(m));
+    return c.off;
+}
+
 } // namespace
 
 extern "C" {
@@ -1134,6 +1175,181 @@ int cd_refine_records(const cd_elements *el, const cd_params *p, uint32_t delta_
     }
     uint32_t uniq = 0;
     CD_HIP(hipMemcpyAsync(&uniq, w.pos + nleaf, sizeof uniq, hipMemcpyDeviceToHost, s));
+    CD_HIP(hipStreamSynchronize(s));
+    *count_host = uniq;
+    return CD_OK;
+}
+
+// ---- potential-collision graph by altitude bands ------------------------------------------
+
+size_t cd_band_filter_ws(int64_t count)
+{
+    RecWS w;
+    return layout_records(nullptr, 0, count, &w);
+}
+
+int cd_band_filter(const cd_elements *el, const cd_params *p, const cd_pair *pairs,
+                   int64_t count, cd_pair *out, int64_t *count_host, void *ws, size_t ws_bytes,
+                   cd_stream_t stream)
+{
+    int rc = check_elements(el);
+    if (!rc)
+        rc = check_params(p);
+    if (rc)
+        return rc;
+    if (!count_host)
+        return fail(CD_E_INVALID, "count_host is NULL");
+    *count_host = 0;
+    if (count < 0 || count > 0x7FFFFFFFll)
+        return fail(CD_E_INVALID, "count out of range");
+    if (count > 0 && (!pairs || !out))
+        return fail(CD_E_INVALID, "pairs or out is NULL");
+    if (!ws || ws_bytes < cd_band_filter_ws(count))
+        return fail(CD_E_WORKSPACE, "band-filter workspace too small");
+    if (count == 0)
+        return CD_OK;
+    hipStream_t s = (hipStream_t)stream;
+    RecWS w;
+    layout_records(ws, ws_bytes, count, &w);
+    uint32_t m = (uint32_t)count;
+    CD_HIP(launch_fill_u32(w.flags + m, 0u, 1, s));
+    CD_HIP(launch_band_flags(*el, band_pad(p), pairs, m, w.flags, s));
+    CD_HIP(scan_exclusive_u32(w.flags, w.pos, (size_t)m + 1, w.scan, s));
+    CD_HIP(launch_compact_pairs(pairs, w.flags, w.pos, m, out, s));
+    uint32_t kept = 0;
+    CD_HIP(hipMemcpyAsync(&kept, w.pos + m, sizeof kept, hipMemcpyDeviceToHost, s));
+    CD_HIP(hipStreamSynchronize(s));
+    *count_host = kept;
+    return CD_OK;
+}
+
+size_t cd_band_partition_ws(int64_t n, int32_t nbands)
+{
+    BandWS w;
+    return layout_bands(nullptr, 0, n, nbands, &w);
+}
+
+int cd_band_partition(const cd_elements *el, const cd_params *p, int32_t nbands, double *edges,
+                      uint32_t *offsets, uint32_t *members, int64_t capacity,
+                      int64_t *count_host, void *ws, size_t ws_bytes, cd_stream_t stream)
+{
+    int rc = check_elements(el);
+    if (!rc)
+        rc = check_params(p);
+    if (rc)
+        return rc;
+    if (!count_host)
+        return fail(CD_E_INVALID, "count_host is NULL");
+    *count_host = 0;
+    if (nbands < 1 || nbands > kMaxBands)
+        return fail(CD_E_INVALID, "nbands must be in [1, %d]", kMaxBands);
+    if ((uint64_t)el->n * (uint64_t)nbands > 0xFFFFFFFFull)
+        return fail(CD_E_OVERFLOW, "n * nbands must fit 32 bits");
+    if (!edges || !offsets || (capacity > 0 && !members) || capacity < 0)
+        return fail(CD_E_INVALID, "edges, offsets or members is NULL, or capacity < 0");
+    if (!ws || ws_bytes < cd_band_partition_ws(el->n, nbands))
+        return fail(CD_E_WORKSPACE, "band-partition workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t n = (uint32_t)el->n, P = (uint32_t)nbands;
+    double pad = band_pad(p);
+    if (n == 0) {
+        CD_HIP(launch_fill_u32(offsets, 0u, (size_t)P + 1, s));
+        CD_HIP(hipStreamSynchronize(s));
+        return CD_OK;
+    }
+    BandWS w;
+    layout_bands(ws, ws_bytes, el->n, nbands, &w);
+    Stage st("bands", s);
+    // edges: every (n / p)-th semi-major axis in sorted order
+    CD_HIP(launch_band_axis_keys(*el, w.ka, s));
+    DigitPlan plan;
+    memset(&plan, 0, sizeof plan);
+    for (int sh = 0; sh < 64; sh += 8)
+        plan.shift[plan.npass++] = (uint8_t)sh;
+    void *res = nullptr;
+    CD_HIP(radix_sort16(SORT_KV, w.ka, w.kb, n, plan, w.radix, &res, s));
+    CD_HIP(launch_band_edges((const KV *)res, n, P, edges, s));
+    // memberships: count, offsets, then the (band, object) keys sorted by band
+    CD_HIP(launch_fill_u32(w.cnt + n, 0u, 1, s));
+    CD_HIP(launch_band_members(*el, pad, edges, P, w.cnt, nullptr, nullptr, s));
+    CD_HIP(scan_exclusive_u32(w.cnt, w.off, (size_t)n + 1, w.scan, s));
+    uint32_t total = 0;
+    CD_HIP(hipMemcpyAsync(&total, w.off + n, sizeof total, hipMemcpyDeviceToHost, s));
+    CD_HIP(hipStreamSynchronize(s));
+    *count_host = total;
+    if ((int64_t)total > capacity)
+        return fail(CD_E_CAPACITY, "%u memberships exceed capacity %lld", total,
+                    (long long)capacity);
+    CD_HIP(launch_band_members(*el, pad, edges, P, w.cnt, w.off, w.ka, s));
+    memset(&plan, 0, sizeof plan);
+    for (int sh = 0; sh < bits_for(n - 1 > 0 ? n - 1 : 1); sh += 8)
+        plan.shift[plan.npass++] = (uint8_t)sh;
+    for (int sh = 0; sh < bits_for(P - 1 > 0 ? P - 1 : 1); sh += 8)
+        plan.shift[plan.npass++] = (uint8_t)(32 + sh);
+    CD_HIP(radix_sort16(SORT_KV, w.ka, w.kb, total, plan, w.radix, &res, s));
+    CD_HIP(launch_band_csr((const KV *)res, total, P, members, offsets, s));
+    CD_HIP(hipStreamSynchronize(s));
+    return CD_OK;
+}
+
+int cd_gather_elements(const cd_elements *el, const uint32_t *ids, int64_t count, double *out,
+                       cd_stream_t stream)
+{
+    int rc = check_elements(el);
+    if (rc)
+        return rc;
+    if (count < 0 || count > 0x7FFFFFFFll)
+        return fail(CD_E_INVALID, "count out of range");
+    if (count > 0 && (!ids || !out))
+        return fail(CD_E_INVALID, "ids or out is NULL");
+    CD_HIP(launch_gather_elements(*el, ids, (uint32_t)count, out, (hipStream_t)stream));
+    return CD_OK;
+}
+
+int cd_remap_records(const cd_pair *in, int64_t count, const uint32_t *ids, int64_t nids,
+                     cd_pair *out, cd_stream_t stream)
+{
+    if (count < 0 || count > 0x7FFFFFFFll || nids < 0 || nids > 0xFFFFFFFFll)
+        return fail(CD_E_INVALID, "count or nids out of range");
+    if (count > 0 && (!in || !ids || !out))
+        return fail(CD_E_INVALID, "in, ids or out is NULL");
+    CD_HIP(launch_remap_records(in, (uint32_t)count, ids, (uint32_t)nids, out,
+                                (hipStream_t)stream));
+    return CD_OK;
+}
+
+size_t cd_canonical_records_ws(int64_t count)
+{
+    RecWS w;
+    return layout_records(nullptr, 0, count, &w);
+}
+
+int cd_canonical_records(const cd_pair *in, int64_t count, uint32_t horizon_ticks,
+                         uint32_t obj_count, cd_pair *out, int64_t *count_host, void *ws,
+                         size_t ws_bytes, cd_stream_t stream)
+{
+    if (!count_host)
+        return fail(CD_E_INVALID, "count_host is NULL");
+    *count_host = 0;
+    if (count < 0 || count > 0x7FFFFFFFll)
+        return fail(CD_E_INVALID, "count out of range");
+    if (count > 0 && (!in || !out))
+        return fail(CD_E_INVALID, "in or out is NULL");
+    if (!ws || ws_bytes < cd_canonical_records_ws(count))
+        return fail(CD_E_WORKSPACE, "canonical-records workspace too small");
+    if (count == 0)
+        return CD_OK;
+    hipStream_t s = (hipStream_t)stream;
+    RecWS w;
+    layout_records(ws, ws_bytes, count, &w);
+    uint32_t m = (uint32_t)count;
+    CD_HIP(hipMemcpyAsync(w.raw, in, (size_t)m * sizeof(Rec), hipMemcpyDeviceToDevice, s));
+    DigitPlan plan = record_plan_bits(horizon_ticks, obj_count);
+    void *res = nullptr;
+    CD_HIP(radix_sort16(SORT_REC, w.raw, w.alt, m, plan, w.radix, &res, s));
+    CD_HIP(launch_unique((const Rec *)res, m, w.flags, w.pos, w.scan, (Rec *)out, s));
+    uint32_t uniq = 0;
+    CD_HIP(hipMemcpyAsync(&uniq, w.pos + m, sizeof uniq, hipMemcpyDeviceToHost, s));
     CD_HIP(hipStreamSynchronize(s));
     *count_host = uniq;
     return CD_OK;

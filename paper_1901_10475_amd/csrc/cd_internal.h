@@ -513,6 +513,23 @@ hipError_t launch_refine_level(int rule, const ObjConst *oc, const ObjSinus *os,
                                double half_thr, uint32_t blocks, hipStream_t s);
 hipError_t launch_refine_status(const unsigned long long *leaf_count, const unsigned int *flags,
                                 const unsigned int *last_count, unsigned int *out, hipStream_t s);
+// altitude bands (potential-collision graph); pad = sqrt(3) thr / 2
+hipError_t launch_band_flags(const cd_elements &el, double pad, const cd_pair *pairs,
+                             uint32_t count, uint32_t *flags, hipStream_t s);
+hipError_t launch_compact_pairs(const cd_pair *pairs, const uint32_t *flags, const uint32_t *pos,
+                                uint32_t count, cd_pair *out, hipStream_t s);
+hipError_t launch_band_axis_keys(const cd_elements &el, KV *kv, hipStream_t s);
+hipError_t launch_band_edges(const KV *sorted, uint32_t n, uint32_t p, double *edges,
+                             hipStream_t s);
+// out == nullptr: cnt[i] = bands met by object i; else keys (k << 32 | i) at out + off[i]
+hipError_t launch_band_members(const cd_elements &el, double pad, const double *edges, uint32_t p,
+                               uint32_t *cnt, const uint32_t *off, KV *out, hipStream_t s);
+hipError_t launch_band_csr(const KV *sorted, uint32_t total, uint32_t p, uint32_t *members,
+                           uint32_t *offsets, hipStream_t s);
+hipError_t launch_gather_elements(const cd_elements &el, const uint32_t *ids, uint32_t count,
+                                  double *out, hipStream_t s);
+hipError_t launch_remap_records(const cd_pair *in, uint32_t count, const uint32_t *ids,
+                                uint32_t nids, cd_pair *out, hipStream_t s);
 hipError_t launch_unique(const Rec *in, uint32_t count, uint32_t *flags, uint32_t *pos,
                          void *scan_ws, Rec *out, hipStream_t s);
 

@@ -160,3 +160,35 @@ def test_refine_argument_errors_before_any_launch():
     assert cnt.value == 0
     # the work queue is sized from the records and the capacity
     assert L.cd_refine_records_ws(100, 10**6, 0) > L.cd_refine_records_ws(100, 10, 0)
+
+
+def test_band_argument_errors_before_any_launch():
+    import paper_1901_10475_amd as cd
+    L = cd.lib()
+    p = cd.params_struct(1e-3, 398600.4418, 1.0, 600, 10)
+    el0 = cd.cd_elements(None, None, None, None, None, None, 0)
+    el5 = cd.cd_elements(None, None, None, None, None, None, 5)     # n > 0, NULL arrays
+    fake = ctypes.c_void_p(16)                                       # never dereferenced
+    cnt = ctypes.c_int64(7)
+    assert L.cd_band_filter(ctypes.byref(el5), ctypes.byref(p), fake, 1, fake,
+                            ctypes.byref(cnt), fake, 1 << 20, None) == cd.CD_E_INVALID
+    assert L.cd_band_filter(ctypes.byref(el0), ctypes.byref(p), fake, 10, fake,
+                            ctypes.byref(cnt), fake, 8, None) == cd.CD_E_WORKSPACE
+    assert L.cd_band_filter(ctypes.byref(el0), ctypes.byref(p), None, 0, None,
+                            ctypes.byref(cnt), fake, L.cd_band_filter_ws(0), None) == cd.CD_OK
+    assert cnt.value == 0
+    ws = L.cd_band_partition_ws(0, 4)
+    for bands in (0, 4097):
+        assert L.cd_band_partition(ctypes.byref(el0), ctypes.byref(p), bands, fake, fake, fake,
+                                   0, ctypes.byref(cnt), fake, 1 << 30, None) == cd.CD_E_INVALID
+    assert L.cd_band_partition(ctypes.byref(el0), ctypes.byref(p), 4, None, fake, fake, 0,
+                               ctypes.byref(cnt), fake, ws, None) == cd.CD_E_INVALID
+    assert L.cd_band_partition_ws(1000, 8) > L.cd_band_partition_ws(1000, 2)
+    assert L.cd_gather_elements(ctypes.byref(el0), None, -1, None, None) == cd.CD_E_INVALID
+    assert L.cd_gather_elements(ctypes.byref(el0), None, 3, None, None) == cd.CD_E_INVALID
+    assert L.cd_remap_records(None, 2, None, 5, None, None) == cd.CD_E_INVALID
+    assert L.cd_remap_records(None, 0, None, 0, None, None) == cd.CD_OK
+    assert L.cd_canonical_records(None, 3, 10, 10, None, ctypes.byref(cnt), fake, 1 << 20,
+                                  None) == cd.CD_E_INVALID
+    assert L.cd_canonical_records(fake, 3, 10, 10, fake, ctypes.byref(cnt), fake, 8,
+                                  None) == cd.CD_E_WORKSPACE
