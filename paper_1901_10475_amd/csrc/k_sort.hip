@@ -409,15 +409,34 @@ __global__ __launch_bounds__(kSegThreads) void k_slab_build(
     }
     __syncthreads();
     const SlabKeys K{xch, base, slab_size, slab << 32};
+    // kScatterBatch boxes per lane at a time: their loads are all in flight
+    // before the first record is written
+    constexpr int kScatterBatch = 4;
 #pragma unroll 1
-    for (uint32_t li = threadIdx.x; li < m; li += kSegThreads) {
-        uint32_t p = vsrc[li];
-        uint32_t esc = karras_escape(K, N, (int64_t)(base + p));
-        uint64_t src = base + li;
-        double lo[3], hi[3];
-        load_box<PREC>(b, src, lo, hi);
-        NodeIO<TP>::put(tree, N, (uint32_t)(N - 1 + base + p), lo, hi, b.t0[src], b.t1[src],
-                        b.obj[src], esc);
+    for (uint32_t l0 = threadIdx.x; l0 < m; l0 += kSegThreads * kScatterBatch) {
+        double lo[kScatterBatch][3], hi[kScatterBatch][3];
+        uint32_t t0[kScatterBatch], t1[kScatterBatch], ob[kScatterBatch];
+#pragma unroll
+        for (int q = 0; q < kScatterBatch; ++q) {
+            uint32_t li = l0 + q * kSegThreads;
+            if (li < m) {
+                uint64_t src = base + li;
+                load_box<PREC>(b, src, lo[q], hi[q]);
+                t0[q] = b.t0[src];
+                t1[q] = b.t1[src];
+                ob[q] = b.obj[src];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kScatterBatch; ++q) {
+            uint32_t li = l0 + q * kSegThreads;
+            if (li < m) {
+                uint32_t p = vsrc[li];
+                uint32_t esc = karras_escape(K, N, (int64_t)(base + p));
+                NodeIO<TP>::put(tree, N, (uint32_t)(N - 1 + base + p), lo[q], hi[q], t0[q],
+                                t1[q], ob[q], esc);
+            }
+        }
     }
 }
 
