@@ -46,9 +46,9 @@ BOX_RULES = {"speed": 0, "nu": 1, "ecc": 2}
 BOX_SUFFIX = {"speed": "", "nu": "_box_interval_nu", "ecc": "_box_interval_ecc"}
 
 TRAFFIC = {
-    ("sort", "fp64", "fixed"): {"fetch_kib": 2143257.0, "write_kib": 4937829.0,
+    ("sort", "fp64", "fixed"): {"fetch_kib": 2147086.0, "write_kib": 4676786.0,
                                 "source": "paper_1901_10475_amd/csrc/k_sort.hip",
-                                "sha1": "c1f97b9d28e605f89b7d79554e6819be7f5d0cc6"},
+                                "sha1": "87a1534549ce49271f4cc191810f2eab7e323d70"},
     ("refit", "fp64", "fixed"): {"fetch_kib": 2702337.0 + 323155.0,
                                  "write_kib": 3774284.0 + 103963.0,
                                  "source": "paper_1901_10475_amd/csrc/k_tree.hip",
