@@ -48,6 +48,13 @@ struct Q<CD_FP64> {
         link = u.z;
         esc = u.w;
     }
+    // the box and tags alone (the links share the record's last 16 bytes)
+    __device__ static void load_box(const void *tree, uint32_t N, uint32_t id, F lo[3],
+                                    F hi[3], uint32_t &t0, uint32_t &t1)
+    {
+        uint32_t link, esc;
+        load(tree, N, id, lo, hi, t0, t1, link, esc);
+    }
 };
 
 template <>
@@ -70,6 +77,22 @@ struct Q<CD_FP32> {
         t1 = c.w;
         link = l.x;
         esc = l.y;
+    }
+    // the box and tags alone: the link array is a second cache line
+    __device__ static void load_box(const void *tree, uint32_t N, uint32_t id, F lo[3],
+                                    F hi[3], uint32_t &t0, uint32_t &t1)
+    {
+        const Box32 *b = (const Box32 *)tree + id;
+        float4 a = *(const float4 *)&b->lo[0];
+        uint4 c = *(const uint4 *)&b->hi[1];
+        lo[0] = a.x;
+        lo[1] = a.y;
+        lo[2] = a.z;
+        hi[0] = a.w;
+        hi[1] = __uint_as_float(c.x);
+        hi[2] = __uint_as_float(c.y);
+        t0 = c.z;
+        t1 = c.w;
     }
 };
 
@@ -181,8 +204,23 @@ __device__ inline bool load_side(const void *tree, const uint2 *kids, uint32_t N
         return false;
     ids[0] = kk.x;
     ids[1] = kk.y;
-    Q<TP>::load(tree, N, kk.x, lo[0], hi[0], t0[0], t1[0], lk[0], e);
-    Q<TP>::load(tree, N, kk.y, lo[1], hi[1], t0[1], t1[1], lk[1], e);
+    if (TP == CD_FP64) {   // the links share the record's cache line
+        Q<TP>::load(tree, N, kk.x, lo[0], hi[0], t0[0], t1[0], lk[0], e);
+        Q<TP>::load(tree, N, kk.y, lo[1], hi[1], t0[1], t1[1], lk[1], e);
+        cnt = 2;
+        return true;
+    }
+    // FP32: an inner child's link (a second cache line) is never used, its
+    // children come from kids, so only a leaf child pays for the object id
+    lk[0] = lk[1] = 0;
+    if (kk.x >= N - 1)
+        Q<TP>::load(tree, N, kk.x, lo[0], hi[0], t0[0], t1[0], lk[0], e);
+    else
+        Q<TP>::load_box(tree, N, kk.x, lo[0], hi[0], t0[0], t1[0]);
+    if (kk.y >= N - 1)
+        Q<TP>::load(tree, N, kk.y, lo[1], hi[1], t0[1], t1[1], lk[1], e);
+    else
+        Q<TP>::load_box(tree, N, kk.y, lo[1], hi[1], t0[1], t1[1]);
     cnt = 2;
     return true;
 }

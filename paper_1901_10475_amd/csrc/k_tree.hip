@@ -398,21 +398,26 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
                 bad = true;
                 break;
             }
+            uint2 lr = kid[slot];
+            uint32_t sib = lr.x == node ? lr.y : lr.x;
+            // a leaf sibling of this chunk: its record was written before the
+            // barrier and never changes here, so its load need not wait for
+            // the arrival order and overlaps the atomic
+            bool sib_leaf = sib >= N - 1 && sib - (N - 1) - c0 < m;
+            double olo[3], ohi[3];
+            uint32_t ot0 = 0, ot1 = 0;
+            if (sib_leaf)
+                NodeIO<TP>::get_box(tree, N, sib, olo, ohi, ot0, ot1);
             unsigned int old = __hip_atomic_fetch_add(&cnt[slot], 1u, __ATOMIC_ACQ_REL,
                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
             if (old == 0)
                 break;
-            uint2 lr = kid[slot];
-            uint32_t sib = lr.x == node ? lr.y : lr.x;
             if (lr.x != node && lr.y != node) {
                 bad = true;
                 break;
             }
-            double olo[3], ohi[3];
-            uint32_t ot0, ot1;
-            if (sib >= N - 1 && sib - (N - 1) - c0 < m) {
-                // a leaf of this chunk: its record was written before the barrier
-                NodeIO<TP>::get_box(tree, N, sib, olo, ohi, ot0, ot1);
+            if (sib_leaf) {
+                // loaded above
             } else if (sib < N - 1 && sib - c0 < m) {
                 const LBox &o = innb[sib - c0];
                 for (int d = 0; d < 3; ++d) {
@@ -480,8 +485,8 @@ __global__ __launch_bounds__(kRefitLevelThreads) void k_refit_level(
         double lo[3], hi[3];
         uint32_t t0, t1;
         NodeIO<TP>::get_box(tree, N, node, lo, hi, t0, t1);
+        uint32_t pv = parent[node];
         for (int guard = 0;; ++guard) {
-            uint32_t pv = parent[node];
             if (pv == kEnd)
                 break;
             uint32_t p = pv & kNodeMask;
@@ -489,7 +494,12 @@ __global__ __launch_bounds__(kRefitLevelThreads) void k_refit_level(
                 ok = false;
                 break;
             }
+            // everything about p that does not depend on the arrival order is
+            // loaded at once; only the sibling's box waits for the acquire
             uint32_t pl = clev[p];
+            uint2 lr = kids[p];
+            uint32_t pesc = links[p].esc;
+            uint32_t ppv = parent[p];
             if (pl > lev) {
                 ok &= L.push(pl, first_leaf, node);
                 break;
@@ -498,7 +508,6 @@ __global__ __launch_bounds__(kRefitLevelThreads) void k_refit_level(
                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
             if (old == 0)
                 break;
-            uint2 lr = kids[p];
             if (lr.x != node && lr.y != node) {
                 ok = false;
                 break;
@@ -510,8 +519,9 @@ __global__ __launch_bounds__(kRefitLevelThreads) void k_refit_level(
             if (time_overlap(t0, t1, ot0, ot1) && space_overlap(lo, hi, olo, ohi))
                 stage.push(seeds, lr.x, lr.y);
             unite(lo, hi, t0, t1, olo, ohi, ot0, ot1);
-            NodeIO<TP>::put(tree, N, p, lo, hi, t0, t1, lr.x, links[p].esc);
+            NodeIO<TP>::put(tree, N, p, lo, hi, t0, t1, lr.x, pesc);
             node = p;
+            pv = ppv;
         }
     }
     stage.flush(seeds, &sbase);
