@@ -885,12 +885,17 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
     if (cnt == 0)
         return CD_OK;
     uint32_t count = (uint32_t)cnt;
-    DigitPlan plan = record_plan(tree);
-    void *res = nullptr;
     {
         Stage st("canon", s);
-        CD_HIP(radix_sort16(SORT_REC, w.raw, w.alt, count, plan, w.radix, &res, s));
-        CD_HIP(launch_unique((const Rec *)res, count, w.flags, w.pos, w.scan, (Rec *)out, s));
+        if (count <= (uint32_t)kSmallCanon) {
+            CD_HIP(launch_small_canon(w.raw, count, (Rec *)out, w.pos + count, s));
+        } else {
+            DigitPlan plan = record_plan(tree);
+            void *res = nullptr;
+            CD_HIP(radix_sort16(SORT_REC, w.raw, w.alt, count, plan, w.radix, &res, s));
+            CD_HIP(launch_unique((const Rec *)res, count, w.flags, w.pos, w.scan, (Rec *)out,
+                                 s));
+        }
     }
     uint32_t uniq = 0;
     CD_HIP(hipMemcpyAsync(&uniq, w.pos + count, sizeof uniq, hipMemcpyDeviceToHost, s));
@@ -1166,12 +1171,17 @@ int cd_refine_records(const cd_elements *el, const cd_params *p, uint32_t delta_
     if (cnt == 0)
         return CD_OK;
     uint32_t nleaf = (uint32_t)cnt;
-    DigitPlan plan = record_plan_bits(T, (uint32_t)el->n);
-    void *res = nullptr;
     {
         Stage st("refine_canon", s);
-        CD_HIP(radix_sort16(SORT_REC, w.raw, w.alt, nleaf, plan, w.radix, &res, s));
-        CD_HIP(launch_unique((const Rec *)res, nleaf, w.flags, w.pos, w.scan, (Rec *)out, s));
+        if (nleaf <= (uint32_t)kSmallCanon) {
+            CD_HIP(launch_small_canon(w.raw, nleaf, (Rec *)out, w.pos + nleaf, s));
+        } else {
+            DigitPlan plan = record_plan_bits(T, (uint32_t)el->n);
+            void *res = nullptr;
+            CD_HIP(radix_sort16(SORT_REC, w.raw, w.alt, nleaf, plan, w.radix, &res, s));
+            CD_HIP(launch_unique((const Rec *)res, nleaf, w.flags, w.pos, w.scan, (Rec *)out,
+                                 s));
+        }
     }
     uint32_t uniq = 0;
     CD_HIP(hipMemcpyAsync(&uniq, w.pos + nleaf, sizeof uniq, hipMemcpyDeviceToHost, s));
@@ -1343,11 +1353,15 @@ int cd_canonical_records(const cd_pair *in, int64_t count, uint32_t horizon_tick
     RecWS w;
     layout_records(ws, ws_bytes, count, &w);
     uint32_t m = (uint32_t)count;
-    CD_HIP(hipMemcpyAsync(w.raw, in, (size_t)m * sizeof(Rec), hipMemcpyDeviceToDevice, s));
-    DigitPlan plan = record_plan_bits(horizon_ticks, obj_count);
-    void *res = nullptr;
-    CD_HIP(radix_sort16(SORT_REC, w.raw, w.alt, m, plan, w.radix, &res, s));
-    CD_HIP(launch_unique((const Rec *)res, m, w.flags, w.pos, w.scan, (Rec *)out, s));
+    if (m <= (uint32_t)kSmallCanon) {
+        CD_HIP(launch_small_canon((const Rec *)in, m, (Rec *)out, w.pos + m, s));
+    } else {
+        CD_HIP(hipMemcpyAsync(w.raw, in, (size_t)m * sizeof(Rec), hipMemcpyDeviceToDevice, s));
+        DigitPlan plan = record_plan_bits(horizon_ticks, obj_count);
+        void *res = nullptr;
+        CD_HIP(radix_sort16(SORT_REC, w.raw, w.alt, m, plan, w.radix, &res, s));
+        CD_HIP(launch_unique((const Rec *)res, m, w.flags, w.pos, w.scan, (Rec *)out, s));
+    }
     uint32_t uniq = 0;
     CD_HIP(hipMemcpyAsync(&uniq, w.pos + m, sizeof uniq, hipMemcpyDeviceToHost, s));
     CD_HIP(hipStreamSynchronize(s));

@@ -445,6 +445,88 @@ hipError_t launch_query_finish(const unsigned long long *counter, const unsigned
     return hipGetLastError();
 }
 
+// Small lists (count <= kSmallCanon) in one workgroup: the records in LDS,
+// a bitonic sort on the full (i, j, t_lo, t_hi) order (padded with records
+// that sort last), then repeat flags, one block scan and the scatter.  The
+// order and the count equal the radix path's; one launch instead of a pass
+// triple per digit.
+__device__ inline bool rec_less(const Rec &a, const Rec &b)
+{
+    if (a.i != b.i)
+        return a.i < b.i;
+    if (a.j != b.j)
+        return a.j < b.j;
+    if (a.tlo != b.tlo)
+        return a.tlo < b.tlo;
+    return a.thi < b.thi;
+}
+
+__device__ inline bool rec_eq(const Rec &a, const Rec &b)
+{
+    return a.i == b.i && a.j == b.j && a.tlo == b.tlo && a.thi == b.thi;
+}
+
+__global__ __launch_bounds__(1024) void k_small_canon(const Rec *__restrict__ in,
+                                                      uint32_t count, Rec *__restrict__ out,
+                                                      uint32_t *total)
+{
+    __shared__ Rec r[kSmallCanon];
+    __shared__ uint32_t wsum[64];
+    uint32_t n2 = 2;
+    while (n2 < count)
+        n2 <<= 1;
+    for (uint32_t k = threadIdx.x; k < n2; k += blockDim.x) {
+        Rec x;
+        if (k < count) {
+            x = in[k];
+        } else {
+            x.i = x.j = x.tlo = x.thi = 0xFFFFFFFFu;
+        }
+        r[k] = x;
+    }
+    __syncthreads();
+    for (uint32_t size = 2; size <= n2; size <<= 1) {
+        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+            for (uint32_t t = threadIdx.x; t < n2 / 2; t += blockDim.x) {
+                uint32_t a = (t / stride) * stride * 2 + (t % stride);
+                uint32_t b = a + stride;
+                bool up = (a & size) == 0;
+                Rec x = r[a], y = r[b];
+                if (rec_less(y, x) == up && !rec_eq(x, y)) {
+                    r[a] = y;
+                    r[b] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // repeats dropped: each thread owns up to 4 consecutive records
+    constexpr int kPer = kSmallCanon / 1024;
+    uint32_t k0 = threadIdx.x * kPer;
+    uint32_t f[kPer], mine = 0;
+    for (int q = 0; q < kPer; ++q) {
+        uint32_t k = k0 + q;
+        f[q] = (k < count && (k == 0 || !rec_eq(r[k], r[k - 1]))) ? 1u : 0u;
+        mine += f[q];
+    }
+    uint32_t all;
+    uint32_t pos = block_exclusive_scan(mine, wsum, &all);
+    for (int q = 0; q < kPer; ++q)
+        if (f[q])
+            out[pos++] = r[k0 + q];
+    if (threadIdx.x == 0)
+        *total = all;
+}
+
+hipError_t launch_small_canon(const Rec *in, uint32_t count, Rec *out, uint32_t *total,
+                              hipStream_t s)
+{
+    if (count == 0 || count > (uint32_t)kSmallCanon)
+        return hipErrorInvalidValue;
+    k_small_canon<<<1, 1024, 0, s>>>(in, count, out, total);
+    return hipGetLastError();
+}
+
 // ---- canonical list: sorted records, repeats dropped -----------------------------------------
 
 __global__ void k_unique_flags(const Rec *in, uint32_t count, uint32_t *flags)

@@ -93,3 +93,21 @@ def test_gather_remap_canonical():
                        dtype=torch.int32, device="cuda")
     c = cd.cd_canonical_records(dup, 20, 10).cpu().numpy()
     assert c.tolist() == [[1, 2, 0, 4], [1, 2, 9, 10], [5, 6, 2, 3]]
+
+
+@pytest.mark.parametrize("count", [1, 2, 3, 1000, 4095, 4096, 4097, 20000])
+def test_canonical_records_small_and_radix_paths(count):
+    """Up to 4096 records take the one-workgroup LDS sort, more the radix
+    path: both give numpy's sorted unique rows."""
+    need_gpu()
+    rng = np.random.default_rng(45 + count)
+    rec = np.stack([rng.integers(0, 300, count), rng.integers(0, 300, count),
+                    rng.integers(0, 3000, count), rng.integers(0, 3001, count)],
+                   axis=1).astype(np.uint32)
+    if count > 10:
+        rec[count // 2:count // 2 + 7] = rec[:7]     # exact repeats
+        rec[-3:, :3] = rec[0, :3]                    # same (i, j, t_lo), other t_hi
+    t = torch.from_numpy(rec.view(np.int32)).cuda()
+    got = cd.cd_canonical_records(t, 3001, 300).cpu().numpy().view(np.uint32)
+    want = np.unique(rec, axis=0)
+    assert np.array_equal(got, want)
