@@ -889,6 +889,9 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
         Stage st("canon", s);
         if (count <= (uint32_t)kSmallCanon) {
             CD_HIP(launch_small_canon(w.raw, count, (Rec *)out, w.pos + count, s));
+        } else if (count <= (uint32_t)kMediumCanon) {
+            CD_HIP(launch_medium_canon(w.raw, w.alt, count, w.flags, w.pos, w.scan, (Rec *)out,
+                                       s));
         } else {
             DigitPlan plan = record_plan(tree);
             void *res = nullptr;
@@ -962,10 +965,17 @@ int cd_query_pairs_async(const cd_tree *tree, cd_pair *out, int64_t capacity,
     {
         Stage st("canon", s);
         CD_HIP(launch_pad_records(w.raw, w.counter, cap, s));
-        DigitPlan plan = record_plan(tree);
-        void *res = nullptr;
-        CD_HIP(radix_sort16(SORT_REC, w.raw, w.alt, cap, plan, w.radix, &res, s));
-        CD_HIP(launch_unique((const Rec *)res, cap, w.flags, w.pos, w.scan, (Rec *)out, s));
+        if (cap <= (uint32_t)kSmallCanon) {
+            CD_HIP(launch_small_canon(w.raw, cap, (Rec *)out, w.pos + cap, s));
+        } else if (cap <= (uint32_t)kMediumCanon) {
+            CD_HIP(launch_medium_canon(w.raw, w.alt, cap, w.flags, w.pos, w.scan, (Rec *)out,
+                                       s));
+        } else {
+            DigitPlan plan = record_plan(tree);
+            void *res = nullptr;
+            CD_HIP(radix_sort16(SORT_REC, w.raw, w.alt, cap, plan, w.radix, &res, s));
+            CD_HIP(launch_unique((const Rec *)res, cap, w.flags, w.pos, w.scan, (Rec *)out, s));
+        }
         CD_HIP(launch_query_finish(w.counter, err, w.pos + cap, cap, count_dev, status_dev, s));
     }
     return CD_OK;
@@ -1175,6 +1185,9 @@ int cd_refine_records(const cd_elements *el, const cd_params *p, uint32_t delta_
         Stage st("refine_canon", s);
         if (nleaf <= (uint32_t)kSmallCanon) {
             CD_HIP(launch_small_canon(w.raw, nleaf, (Rec *)out, w.pos + nleaf, s));
+        } else if (nleaf <= (uint32_t)kMediumCanon) {
+            CD_HIP(launch_medium_canon(w.raw, w.alt, nleaf, w.flags, w.pos, w.scan, (Rec *)out,
+                                       s));
         } else {
             DigitPlan plan = record_plan_bits(T, (uint32_t)el->n);
             void *res = nullptr;
@@ -1355,6 +1368,9 @@ int cd_canonical_records(const cd_pair *in, int64_t count, uint32_t horizon_tick
     uint32_t m = (uint32_t)count;
     if (m <= (uint32_t)kSmallCanon) {
         CD_HIP(launch_small_canon((const Rec *)in, m, (Rec *)out, w.pos + m, s));
+    } else if (m <= (uint32_t)kMediumCanon) {
+        CD_HIP(hipMemcpyAsync(w.raw, in, (size_t)m * sizeof(Rec), hipMemcpyDeviceToDevice, s));
+        CD_HIP(launch_medium_canon(w.raw, w.alt, m, w.flags, w.pos, w.scan, (Rec *)out, s));
     } else {
         CD_HIP(hipMemcpyAsync(w.raw, in, (size_t)m * sizeof(Rec), hipMemcpyDeviceToDevice, s));
         DigitPlan plan = record_plan_bits(horizon_ticks, obj_count);

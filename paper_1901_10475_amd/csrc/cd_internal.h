@@ -535,6 +535,12 @@ hipError_t launch_remap_records(const cd_pair *in, uint32_t count, const uint32_
 constexpr int kSmallCanon = 4096;
 hipError_t launch_small_canon(const Rec *in, uint32_t count, Rec *out, uint32_t *total,
                               hipStream_t s);
+// kSmallCanon < count <= kMediumCanon: tiles sorted in LDS, merged pairwise,
+// then repeats removed (launch_unique; total at pos[count]).  a holds the
+// records and is overwritten; b is scratch of count records.
+constexpr int kMediumCanon = 1 << 16;
+hipError_t launch_medium_canon(Rec *a, Rec *b, uint32_t count, uint32_t *flags, uint32_t *pos,
+                               void *scan_ws, Rec *out, hipStream_t s);
 hipError_t launch_unique(const Rec *in, uint32_t count, uint32_t *flags, uint32_t *pos,
                          void *scan_ws, Rec *out, hipStream_t s);
 

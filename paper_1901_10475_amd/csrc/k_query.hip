@@ -466,25 +466,9 @@ __device__ inline bool rec_eq(const Rec &a, const Rec &b)
     return a.i == b.i && a.j == b.j && a.tlo == b.tlo && a.thi == b.thi;
 }
 
-__global__ __launch_bounds__(1024) void k_small_canon(const Rec *__restrict__ in,
-                                                      uint32_t count, Rec *__restrict__ out,
-                                                      uint32_t *total)
+// Bitonic sort of r[0..n2) (n2 a power of two) by the whole workgroup.
+__device__ inline void lds_bitonic(Rec *r, uint32_t n2)
 {
-    __shared__ Rec r[kSmallCanon];
-    __shared__ uint32_t wsum[64];
-    uint32_t n2 = 2;
-    while (n2 < count)
-        n2 <<= 1;
-    for (uint32_t k = threadIdx.x; k < n2; k += blockDim.x) {
-        Rec x;
-        if (k < count) {
-            x = in[k];
-        } else {
-            x.i = x.j = x.tlo = x.thi = 0xFFFFFFFFu;
-        }
-        r[k] = x;
-    }
-    __syncthreads();
     for (uint32_t size = 2; size <= n2; size <<= 1) {
         for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
             for (uint32_t t = threadIdx.x; t < n2 / 2; t += blockDim.x) {
@@ -500,6 +484,36 @@ __global__ __launch_bounds__(1024) void k_small_canon(const Rec *__restrict__ in
             __syncthreads();
         }
     }
+}
+
+// Records [0, count) into LDS, padded to a power of two with records that
+// sort last; returns that power.
+__device__ inline uint32_t lds_load_padded(Rec *r, const Rec *__restrict__ in, uint32_t count)
+{
+    uint32_t n2 = 2;
+    while (n2 < count)
+        n2 <<= 1;
+    for (uint32_t k = threadIdx.x; k < n2; k += blockDim.x) {
+        Rec x;
+        if (k < count) {
+            x = in[k];
+        } else {
+            x.i = x.j = x.tlo = x.thi = 0xFFFFFFFFu;
+        }
+        r[k] = x;
+    }
+    __syncthreads();
+    return n2;
+}
+
+__global__ __launch_bounds__(1024) void k_small_canon(const Rec *__restrict__ in,
+                                                      uint32_t count, Rec *__restrict__ out,
+                                                      uint32_t *total)
+{
+    __shared__ Rec r[kSmallCanon];
+    __shared__ uint32_t wsum[64];
+    uint32_t n2 = lds_load_padded(r, in, count);
+    lds_bitonic(r, n2);
     // repeats dropped: each thread owns up to 4 consecutive records
     constexpr int kPer = kSmallCanon / 1024;
     uint32_t k0 = threadIdx.x * kPer;
@@ -518,6 +532,50 @@ __global__ __launch_bounds__(1024) void k_small_canon(const Rec *__restrict__ in
         *total = all;
 }
 
+// Medium lists: each workgroup sorts one kSmallCanon-record tile in LDS ...
+__global__ __launch_bounds__(1024) void k_tile_sort(const Rec *__restrict__ in, uint32_t count,
+                                                    Rec *__restrict__ out)
+{
+    __shared__ Rec r[kSmallCanon];
+    uint32_t base = blockIdx.x * (uint32_t)kSmallCanon;
+    uint32_t m = count - base < (uint32_t)kSmallCanon ? count - base : (uint32_t)kSmallCanon;
+    uint32_t n2 = lds_load_padded(r, in + base, m);
+    lds_bitonic(r, n2);
+    for (uint32_t k = threadIdx.x; k < m; k += blockDim.x)
+        out[base + k] = r[k];
+}
+
+// ... then sorted runs of `width` records are merged pairwise: output k finds
+// by binary search how many of its predecessors come from the left run (the
+// stable merge path: on equal records the left run goes first).
+__global__ __launch_bounds__(256) void k_merge_runs(const Rec *__restrict__ in, uint32_t count,
+                                                    uint32_t width, Rec *__restrict__ out)
+{
+    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= count)
+        return;
+    uint64_t q0 = (uint64_t)(k / (2ull * width)) * 2ull * width;
+    uint32_t la = (uint32_t)(count - q0 < width ? count - q0 : width);
+    uint64_t b0 = q0 + la;
+    uint32_t lb = (uint32_t)(count - b0 < width ? count - b0 : width);
+    if (b0 >= count)
+        lb = 0;
+    const Rec *A = in + q0, *B = in + b0;
+    uint32_t kk = (uint32_t)(k - q0);   // rank inside the merged pair
+    uint32_t lo = kk > lb ? kk - lb : 0u, hi = kk < la ? kk : la;
+    // smallest i in [lo, hi] with not (A[i] <= B[kk - i - 1])
+    while (lo < hi) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (!rec_less(B[kk - mid - 1], A[mid]))
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    uint32_t i = lo, j = kk - lo;
+    bool take_a = i < la && (j >= lb || !rec_less(B[j], A[i]));
+    out[k] = take_a ? A[i] : B[j];
+}
+
 hipError_t launch_small_canon(const Rec *in, uint32_t count, Rec *out, uint32_t *total,
                               hipStream_t s)
 {
@@ -525,6 +583,27 @@ hipError_t launch_small_canon(const Rec *in, uint32_t count, Rec *out, uint32_t 
         return hipErrorInvalidValue;
     k_small_canon<<<1, 1024, 0, s>>>(in, count, out, total);
     return hipGetLastError();
+}
+
+hipError_t launch_medium_canon(Rec *a, Rec *b, uint32_t count, uint32_t *flags, uint32_t *pos,
+                               void *scan_ws, Rec *out, hipStream_t s)
+{
+    if (count <= (uint32_t)kSmallCanon || count > (uint32_t)kMediumCanon)
+        return hipErrorInvalidValue;
+    uint32_t tiles = (count + kSmallCanon - 1) / kSmallCanon;
+    k_tile_sort<<<tiles, 1024, 0, s>>>(a, count, b);
+    hipError_t e = hipGetLastError();
+    Rec *src = b, *dst = a;
+    for (uint32_t w = kSmallCanon; e == hipSuccess && w < count; w *= 2) {
+        k_merge_runs<<<nblk(count, 256), 256, 0, s>>>(src, count, w, dst);
+        e = hipGetLastError();
+        Rec *t = src;
+        src = dst;
+        dst = t;
+    }
+    if (e != hipSuccess)
+        return e;
+    return launch_unique(src, count, flags, pos, scan_ws, out, s);
 }
 
 // ---- canonical list: sorted records, repeats dropped -----------------------------------------

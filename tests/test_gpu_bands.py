@@ -23,10 +23,10 @@ def _mixed(seed, n, T, dt, thr):
     return catalog.Scenario(f"mixed{n}", el, dt, T, thr, planted=pl)
 
 
-@pytest.mark.parametrize("p", [1, 3, 16, 100])
-def test_partition_matches_oracle(p):
+@pytest.mark.parametrize("p,n", [(1, 2000), (3, 2000), (16, 2000), (100, 2000), (64, 30)])
+def test_partition_matches_oracle(p, n):
     need_gpu()
-    sc = _mixed(41, 2000, 1000, 1000, 40.0)
+    sc = _mixed(41, n, 1000, 1000, 40.0)
     say("band partition p", p)
     el = cd.soa(sc.elements)
     params = cd.params_struct(sc.tick_s, sc.mu, sc.threshold_km, sc.horizon_ticks, sc.dt_ticks)
@@ -95,10 +95,12 @@ def test_gather_remap_canonical():
     assert c.tolist() == [[1, 2, 0, 4], [1, 2, 9, 10], [5, 6, 2, 3]]
 
 
-@pytest.mark.parametrize("count", [1, 2, 3, 1000, 4095, 4096, 4097, 20000])
-def test_canonical_records_small_and_radix_paths(count):
-    """Up to 4096 records take the one-workgroup LDS sort, more the radix
-    path: both give numpy's sorted unique rows."""
+@pytest.mark.parametrize("count", [1, 2, 3, 1000, 4095, 4096, 4097, 20000, 65536, 65537,
+                                   100000])
+def test_canonical_records_small_medium_and_radix_paths(count):
+    """Up to 4096 records take the one-workgroup LDS sort, up to 65536 the
+    LDS tiles merged pairwise, more the radix path: all give numpy's sorted
+    unique rows."""
     need_gpu()
     rng = np.random.default_rng(45 + count)
     rec = np.stack([rng.integers(0, 300, count), rng.integers(0, 300, count),

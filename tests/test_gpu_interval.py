@@ -153,3 +153,23 @@ def test_unknown_box_rule_rejected():
                          box_rule=3)
     with pytest.raises(cd.CDError):
         cd.BroadPhase(sc.n, p).run(el)
+
+
+@pytest.mark.parametrize("rule", RULES)
+@pytest.mark.parametrize("T,dt", [(0, 1000), (25_500, 10_000), (7_000, 9_000)])
+def test_interval_boxes_single_instant_and_ragged(rule, T, dt):
+    """T = 0 (one instant: Property 1, the box is the occupancy cube up to the
+    widening) and horizons that end inside a step (the last interval clamped)."""
+    need_gpu()
+    say("interval boxes edge", rule, T, dt)
+    sc = _scenario(81, 130, T, dt, planted=0)
+    bp, pairs = _run(sc, rule)
+    lo, hi, t0, t1, obj = _host_object_major(bp, sc, None)
+    ob = oracle.boxes(sc.elements, dt, T, sc.tick_s, sc.threshold_km, rule=rule)
+    assert np.array_equal(t0, ob.t0) and np.array_equal(t1, ob.t1) and np.array_equal(obj, ob.obj)
+    assert_boxes_close(lo, hi, ob.lo, ob.hi, sc.elements[ob.obj, 0])
+    if T == 0:
+        P = np.stack([oracle.position(e, 0.0) for e in sc.elements])
+        r = sc.threshold_km / 2
+        assert np.allclose(lo, P - r, atol=1e-5) and np.allclose(hi, P + r, atol=1e-5)
+    assert np.array_equal(pairs, oracle.pairs(oracle.Boxes(*bp.boxes.to_host())))
