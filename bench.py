@@ -46,13 +46,13 @@ BOX_RULES = {"speed": 0, "nu": 1, "ecc": 2}
 BOX_SUFFIX = {"speed": "", "nu": "_box_interval_nu", "ecc": "_box_interval_ecc"}
 
 TRAFFIC = {
-    ("sort", "fp64", "fixed"): {"fetch_kib": 2147086.0, "write_kib": 4676786.0,
+    ("sort", "fp64", "fixed"): {"fetch_kib": 2147404.0, "write_kib": 4708076.0,
                                 "source": "paper_1901_10475_amd/csrc/k_sort.hip",
                                 "sha1": "87a1534549ce49271f4cc191810f2eab7e323d70"},
-    ("refit", "fp64", "fixed"): {"fetch_kib": 2671446.0 + 423181.0,
-                                 "write_kib": 3774752.0 + 102317.0,
-                                 "source": "paper_1901_10475_amd/csrc/k_tree.hip",
-                                 "sha1": "a8f60631c9461644bbce02b742f16d142cfd0c65"},
+    ("refit", "fp64", "fixed"): {"fetch_kib": 2670106.0 + 423606.0,
+                                 "write_kib": 3774825.0 + 102323.0,
+                                 "source": "paper_1901_10475_amd/csrc/k_refit.hip",
+                                 "sha1": "33afe3055fa5f41281864162873fd35b09050fa5"},
 }
 
 

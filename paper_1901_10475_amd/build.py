@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 ARCH = os.environ.get("CD4D_ARCH", "gfx950")
 
-LIB_SOURCES = ["k_boxes.hip", "k_sort.hip", "k_tree.hip", "k_query.hip", "k_mlp.hip",
+LIB_SOURCES = ["k_boxes.hip", "k_sort.hip", "k_tree.hip", "k_refit.hip", "k_query.hip", "k_mlp.hip",
                "k_narrow.hip", "k_refine.hip", "k_bands.hip", "cd_api.cpp"]
 HOSTCHECK_SOURCES = ["cd_hostcheck.cpp"]
 

@@ -283,6 +283,61 @@ struct SlabKeys {
     }
 };
 
+// Two keys of the node's own slab share their slab bits, so their common
+// prefix is 32 plus that of their 32-bit codes: the comparison stays in 32
+// bits (same result as the 64-bit keys).
+template <>
+__host__ __device__ inline int karras_delta<SlabKeys>(const SlabKeys &key, int64_t N, int64_t i,
+                                                      int64_t j)
+{
+    if (j < 0 || j >= N)
+        return -1;
+    uint64_t ui = (uint64_t)i - key.base, uj = (uint64_t)j - key.base;
+    if (ui < key.m && uj < key.m) {
+        uint32_t a = key.lds[ui], b = key.lds[uj];
+        if (a != b)
+            return 32 + __builtin_clz(a ^ b);
+        return 64 + __builtin_clzll((uint64_t)i ^ (uint64_t)j);
+    }
+    uint64_t a = key(i), b = key(j);
+    if (a != b)
+        return __builtin_clzll(a ^ b);
+    return 64 + __builtin_clzll((uint64_t)i ^ (uint64_t)j);
+}
+
+// karras_node with 32-bit index arithmetic (N < 2^30, so lmax <= 2^30 and every
+// probe i + offset stays below 2^31; the exponential probe is formed in 64 bits).
+template <class K>
+__device__ inline KarrasNode karras_node32(const K &key, uint32_t N, uint32_t i)
+{
+    const int64_t n = N;
+    const int ii = (int)i;
+    int d = karras_delta(key, n, ii, ii + 1) >= karras_delta(key, n, ii, ii - 1) ? 1 : -1;
+    int dmin = karras_delta(key, n, ii, ii - d);
+    int lmax = 2;
+    while (karras_delta(key, n, ii, (int64_t)ii + (int64_t)lmax * d) > dmin)
+        lmax *= 2;
+    int l = 0;
+    for (int t = lmax / 2; t >= 1; t /= 2)
+        if (karras_delta(key, n, ii, ii + (l + t) * d) > dmin)
+            l += t;
+    int j = ii + l * d;
+    int dnode = karras_delta(key, n, ii, j);
+    int s = 0, t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (karras_delta(key, n, ii, ii + (s + t) * d) > dnode)
+            s += t;
+    } while (t > 1);
+    int gamma = ii + s * d + (d < 0 ? -1 : 0);
+    KarrasNode nd;
+    nd.first = ii < j ? ii : j;
+    nd.last = ii < j ? j : ii;
+    nd.left = (nd.first == gamma) ? (uint32_t)(N - 1 + gamma) : (uint32_t)gamma;
+    nd.right = (nd.last == gamma + 1) ? (uint32_t)(N - 1 + gamma + 1) : (uint32_t)(gamma + 1);
+    return nd;
+}
+
 // ---- launchers (each returns the launch status) -----------------------------
 
 // boxes

@@ -1,0 +1,329 @@
+// k_refit.hip -- the atomic bottom-up refit of the tree's inner boxes.
+//
+// Each inner box (space and time) is set to the exact union of its two
+// children by a bottom-up pass in which the second of the two threads reaching
+// a node computes it; the pass also records every pair of sibling nodes whose
+// boxes overlap, the seeds of the node-pair traversal.
+#include "cd_internal.h"
+
+namespace cd {
+
+static inline unsigned nblk(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
+
+// ---- bottom-up refit ---------------------------------------------------------------------
+//
+// Every inner box is the exact union of its children.  The classic scheme (one
+// thread per leaf climbs; at each node the first arrival stops and the second
+// writes the union) needs, on MI355X, agent-scope release/acquire whenever the
+// two threads sit in different workgroups: the eight XCDs have separate L2
+// caches, so each such atomic writes back and invalidates L2.  Here every
+// meeting happens inside one workgroup instead.  Leaves are cut into blocks of
+// refit_block(k) = 1024 * 16^k consecutive leaves, level by level; a node
+// belongs to the lowest level whose blocks hold its whole range.
+//   level 0: one workgroup per 1024-leaf chunk, one leaf per thread.  Parents,
+//      children, arrival counters and computed inner boxes are staged in LDS
+//      (77 KB, two workgroups per CU); a sibling leaf is read back from its
+//      record, written before the barrier and still in L2.  Computed inner
+//      records are written out in one coalesced pass at the end.
+//   level k >= 1: one workgroup per level-k block climbs, in global memory with
+//      workgroup-scope counters, from the nodes queued for it by lower levels.
+// A climb that meets a parent of a higher level queues the node for that level
+// and block.  Kernel boundaries order each level's writes before the next.
+
+// Per-workgroup seed staging: lanes append to LDS; a full stage or the end of
+// the kernel flushes it with one global atomic.
+struct SeedStage {
+    uint2 *buf;            // LDS, kSeedStage entries
+    unsigned int *n;       // LDS counter
+    __device__ void push(const SeedSink &sink, uint32_t a, uint32_t b) const
+    {
+        unsigned int k = atomicAdd(n, 1u);
+        if (k < (unsigned)kSeedStage) {
+            buf[k] = make_uint2(a, b);
+        } else {  // stage full: this one goes straight out
+            uint2 one = make_uint2(a, b);
+            sink.put_many(&one, 1, sink.reserve(1));
+        }
+    }
+    // all threads of the block call this after the last push
+    __device__ void flush(const SeedSink &sink, unsigned int *base_lds) const
+    {
+        __syncthreads();
+        uint32_t m = *n < (unsigned)kSeedStage ? *n : (unsigned)kSeedStage;
+        if (threadIdx.x == 0)
+            *base_lds = m ? sink.reserve(m) : 0u;
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < m; k += blockDim.x)
+            if (*base_lds + k < sink.cap)
+                sink.items[*base_lds + k] = buf[k];
+    }
+};
+
+template <int BP, int TP>
+__global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
+    BoxView b, uint32_t N, const uint32_t *__restrict__ idx, const uint32_t *__restrict__ parent,
+    const uint2 *__restrict__ kids, const Link *__restrict__ links, const uint8_t *clev,
+    void *tree, RefitLists L, SeedSink seeds, unsigned int *err)
+{
+    __shared__ LBox innb[kRefitChunk];
+    __shared__ uint2 kid[kRefitChunk];
+    __shared__ uint32_t par_leaf[kRefitChunk], par_in[kRefitChunk];
+    __shared__ unsigned int cnt[kRefitChunk];
+    __shared__ uint2 sbuf[kSeedStage];
+    __shared__ unsigned int sn, sbase;
+    const SeedStage stage{sbuf, &sn};
+    const uint32_t t = threadIdx.x;
+    if (t == 0)
+        sn = 0;
+    const uint32_t c = xcd_block(blockIdx.x, gridDim.x);
+    const uint32_t c0 = c * (uint32_t)kRefitChunk;
+    const uint32_t m = N - c0 < (uint32_t)kRefitChunk ? N - c0 : (uint32_t)kRefitChunk;
+    double lo[3], hi[3];
+    uint32_t t0 = 0, t1 = 0;
+    bool bad = false;
+    if (t < m && idx) {
+        uint32_t i = c0 + t;
+        uint32_t src = idx[i];
+        if (src >= N) {
+            bad = true;
+            src = 0;
+        }
+        load_box<BP>(b, src, lo, hi);
+        if (TP == CD_FP32 && BP == CD_FP64) {
+            // the unions must see the rounded leaves, as the traversal does
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = __double2float_rd(lo[d]);
+                hi[d] = __double2float_ru(hi[d]);
+            }
+        }
+        t0 = b.t0[src];
+        t1 = b.t1[src];
+        uint32_t leaf = N - 1 + i;
+        NodeIO<TP>::put(tree, N, leaf, lo, hi, t0, t1, b.obj[src], links[leaf].esc);
+        par_leaf[t] = parent[leaf];
+    } else if (t < m) {
+        // leaf records already written in sorted order by the slab build
+        uint32_t leaf = N - 1 + c0 + t;
+        NodeIO<TP>::get_box(tree, N, leaf, lo, hi, t0, t1);
+        par_leaf[t] = parent[leaf];
+    }
+    if (c0 + t + 1 < N) {  // inner node c0 + t exists
+        kid[t] = kids[c0 + t];
+        par_in[t] = parent[c0 + t];
+    }
+    cnt[t] = 0;
+    __syncthreads();
+    if (t < m) {
+        uint32_t node = N - 1 + c0 + t;
+        uint32_t pv = par_leaf[t];
+        for (int guard = 0; guard < 160; ++guard) {
+            if (pv == kEnd)
+                break;
+            uint32_t p = pv & kNodeMask;
+            if (pv & kCross) {
+                bad |= !L.push(clev[p], c0, node);
+                break;
+            }
+            uint32_t slot = p - c0;
+            if (p < c0 || slot >= m) {
+                bad = true;
+                break;
+            }
+            uint2 lr = kid[slot];
+            uint32_t sib = lr.x == node ? lr.y : lr.x;
+            // a leaf sibling of this chunk: its record was written before the
+            // barrier and never changes here, so its load need not wait for
+            // the arrival order and overlaps the atomic
+            bool sib_leaf = sib >= N - 1 && sib - (N - 1) - c0 < m;
+            double olo[3], ohi[3];
+            uint32_t ot0 = 0, ot1 = 0;
+            if (sib_leaf)
+                NodeIO<TP>::get_box(tree, N, sib, olo, ohi, ot0, ot1);
+            unsigned int old = __hip_atomic_fetch_add(&cnt[slot], 1u, __ATOMIC_ACQ_REL,
+                                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (old == 0)
+                break;
+            if (lr.x != node && lr.y != node) {
+                bad = true;
+                break;
+            }
+            if (sib_leaf) {
+                // loaded above
+            } else if (sib < N - 1 && sib - c0 < m) {
+                const LBox &o = innb[sib - c0];
+                for (int d = 0; d < 3; ++d) {
+                    olo[d] = o.lo[d];
+                    ohi[d] = o.hi[d];
+                }
+                ot0 = o.t0;
+                ot1 = o.t1;
+            } else {
+                bad = true;
+                break;
+            }
+            if (time_overlap(t0, t1, ot0, ot1) && space_overlap(lo, hi, olo, ohi))
+                stage.push(seeds, lr.x, lr.y);
+            unite(lo, hi, t0, t1, olo, ohi, ot0, ot1);
+            for (int d = 0; d < 3; ++d) {
+                innb[slot].lo[d] = lo[d];
+                innb[slot].hi[d] = hi[d];
+            }
+            innb[slot].t0 = t0;
+            innb[slot].t1 = t1;
+            node = p;
+            pv = par_in[slot];
+        }
+    }
+    __syncthreads();
+    // inner nodes completed here (both children arrived) go out in one pass
+    if (c0 + t + 1 < N && cnt[t] == 2) {
+        uint32_t p = c0 + t;
+        NodeIO<TP>::put(tree, N, p, innb[t].lo, innb[t].hi, innb[t].t0, innb[t].t1, kid[t].x,
+                        links[p].esc);
+    }
+    stage.flush(seeds, &sbase);
+    if (bad)
+        atomicOr(err, 2u);
+}
+
+// Phase k >= 1: one workgroup per level-k block climbs from the nodes queued
+// for it, in global memory with workgroup-scope arrival counters, through the
+// nodes of level k; a parent of a higher level gets the node queued instead.
+template <int TP>
+__global__ __launch_bounds__(kRefitLevelThreads) void k_refit_level(
+    uint32_t N, uint32_t lev, const uint32_t *__restrict__ parent, const uint2 *__restrict__ kids,
+    const Link *__restrict__ links, const uint8_t *clev, void *tree, unsigned int *arrive,
+    RefitLists L, SeedSink seeds, unsigned int *err)
+{
+    __shared__ uint2 sbuf[kSeedStage];
+    __shared__ unsigned int sn, sbase;
+    const SeedStage stage{sbuf, &sn};
+    if (threadIdx.x == 0)
+        sn = 0;
+    __syncthreads();
+    uint32_t blk = blockIdx.x;
+    uint32_t n = L.count[L.base[lev] + blk];
+    n = n < (uint32_t)kRefitListCap ? n : (uint32_t)kRefitListCap;
+    const uint32_t *list = L.items + (size_t)(L.base[lev] + blk) * kRefitListCap;
+    uint64_t first_leaf = (uint64_t)blk << refit_shift(lev);
+    bool ok = true;
+    for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) {
+        uint32_t node = list[j];
+        if (node >= 2 * N - 1) {
+            ok = false;
+            continue;
+        }
+        double lo[3], hi[3];
+        uint32_t t0, t1;
+        NodeIO<TP>::get_box(tree, N, node, lo, hi, t0, t1);
+        uint32_t pv = parent[node];
+        for (int guard = 0;; ++guard) {
+            if (pv == kEnd)
+                break;
+            uint32_t p = pv & kNodeMask;
+            if (p >= N - 1 || guard > 160) {
+                ok = false;
+                break;
+            }
+            // everything about p that does not depend on the arrival order is
+            // loaded at once; only the sibling's box waits for the acquire
+            uint32_t pl = clev[p];
+            uint2 lr = kids[p];
+            uint32_t pesc = links[p].esc;
+            uint32_t ppv = parent[p];
+            if (pl > lev) {
+                ok &= L.push(pl, first_leaf, node);
+                break;
+            }
+            unsigned int old = __hip_atomic_fetch_add(&arrive[p], 1u, __ATOMIC_ACQ_REL,
+                                                      __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (old == 0)
+                break;
+            if (lr.x != node && lr.y != node) {
+                ok = false;
+                break;
+            }
+            uint32_t sib = lr.x == node ? lr.y : lr.x;
+            double olo[3], ohi[3];
+            uint32_t ot0, ot1;
+            NodeIO<TP>::get_box(tree, N, sib, olo, ohi, ot0, ot1);
+            if (time_overlap(t0, t1, ot0, ot1) && space_overlap(lo, hi, olo, ohi))
+                stage.push(seeds, lr.x, lr.y);
+            unite(lo, hi, t0, t1, olo, ohi, ot0, ot1);
+            NodeIO<TP>::put(tree, N, p, lo, hi, t0, t1, lr.x, pesc);
+            node = p;
+            pv = ppv;
+        }
+    }
+    stage.flush(seeds, &sbase);
+    if (!ok)
+        atomicOr(err, 2u);
+}
+
+uint32_t refit_levels(uint32_t N)
+{
+    uint32_t lev = 0;
+    while (N > 1 && ((uint64_t)(N - 1) >> refit_shift(lev)) != 0)
+        ++lev;
+    return lev;
+}
+
+size_t refit_list_slots(uint32_t N, uint32_t *base)
+{
+    uint32_t L = refit_levels(N);
+    size_t slots = 0;
+    for (uint32_t k = 0; k <= L + 1 && k < kRefitMaxLevels; ++k) {
+        if (base)
+            base[k] = (uint32_t)slots;
+        if (k >= 1)
+            slots += ((uint64_t)N + (1ull << refit_shift(k)) - 1) >> refit_shift(k);
+    }
+    return slots;
+}
+
+hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision, uint32_t N,
+                        const uint32_t *idx, const uint32_t *parent, const uint2 *kids,
+                        const Link *links, const uint8_t *clev, unsigned int *arrive,
+                        uint32_t *list_items, uint32_t *list_count, void *tree,
+                        const SeedSink &seeds, unsigned int *err, hipStream_t s)
+{
+    if (N == 0)
+        return hipSuccess;
+    RefitLists L;
+    size_t slots = refit_list_slots(N, L.base);
+    L.items = list_items;
+    L.count = list_count;
+    uint32_t levels = refit_levels(N);
+    hipError_t e = hipSuccess;
+    if (levels > 0) {
+        e = launch_fill_u32(list_count, 0u, slots, s);
+        if (e == hipSuccess)
+            e = launch_fill_u32(arrive, 0u, N - 1, s);
+        if (e != hipSuccess)
+            return e;
+    }
+    uint32_t nchunks = nblk(N, kRefitChunk);
+    if (box_precision == CD_FP64 && tree_precision == CD_FP64)
+        k_refit_chunks<CD_FP64, CD_FP64><<<nchunks, kRefitChunk, 0, s>>>(
+            b, N, idx, parent, kids, links, clev, tree, L, seeds, err);
+    else if (box_precision == CD_FP64)
+        k_refit_chunks<CD_FP64, CD_FP32><<<nchunks, kRefitChunk, 0, s>>>(
+            b, N, idx, parent, kids, links, clev, tree, L, seeds, err);
+    else
+        k_refit_chunks<CD_FP32, CD_FP32><<<nchunks, kRefitChunk, 0, s>>>(
+            b, N, idx, parent, kids, links, clev, tree, L, seeds, err);
+    e = hipGetLastError();
+    for (uint32_t k = 1; k <= levels && e == hipSuccess; ++k) {
+        uint32_t nb = (uint32_t)(((uint64_t)N + (1ull << refit_shift(k)) - 1) >> refit_shift(k));
+        if (tree_precision == CD_FP64)
+            k_refit_level<CD_FP64><<<nb, kRefitLevelThreads, 0, s>>>(N, k, parent, kids, links, clev,
+                                                              tree, arrive, L, seeds, err);
+        else
+            k_refit_level<CD_FP32><<<nb, kRefitLevelThreads, 0, s>>>(N, k, parent, kids, links, clev,
+                                                              tree, arrive, L, seeds, err);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+} // namespace cd
