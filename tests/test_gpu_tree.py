@@ -1,0 +1,170 @@
+"""Tree invariants on the GPU, checked on the tree buffer itself, apart from
+any query: the leaves are the input boxes (outward-rounded for an FP32 tree),
+every inner box is the exact union of its children's boxes in space and time
+(the refit of the bottom-up pass), every node but the root is the child of
+exactly one inner node, the link and skip records walk every node once in
+depth-first pre-order, and the seed list holds exactly the sibling pairs whose
+boxes overlap (closed extents in space, half-open tags in time).
+
+Covered: uniform steps, where the boxes of each interval form one slab that
+one workgroup sorts in LDS before the Karras pass over the slab codes and the
+chunked refit (slabs of 1, 2, 300 and 17 408 boxes, the largest one workgroup
+sorts, and 70 000 slabs of 3); per-object steps (the general path: one radix
+sort of all keys); FP64 and FP32 trees; boxes with and without Morton codes.
+
+Tree buffer layout read here: a 256-byte header (error bits, seed count, seed
+overflow), the node records (FP64: 64 bytes each, lo[3], hi[3] as doubles, then
+t0, t1, link, esc as uint32; FP32: 32-byte boxes with float lo/hi and t0, t1,
+then 8-byte (link, esc) records), kids[N - 1] (left, right) and the seeds.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1901_10475_amd as cd
+from paper_1901_10475_amd import catalog
+from tests.gpu_util import need_gpu, say
+
+pytestmark = pytest.mark.gpu
+END = 0xFFFFFFFF
+
+
+def _decode(tree, N, prec):
+    raw = tree.mem.cpu().numpy().view(np.uint8)
+    hdr = raw[:256].view(np.uint32)
+    nn = 2 * N - 1
+    if prec == cd.CD_FP64:
+        rec = raw[256:256 + nn * 64].reshape(nn, 64)
+        lo = rec[:, 0:24].copy().view(np.float64)
+        hi = rec[:, 24:48].copy().view(np.float64)
+        tags = rec[:, 48:64].copy().view(np.uint32)
+        t0, t1, link, esc = tags[:, 0], tags[:, 1], tags[:, 2], tags[:, 3]
+        kids_off = 256 + nn * 64
+    else:
+        box = raw[256:256 + nn * 32].reshape(nn, 32)
+        lo = box[:, 0:12].copy().view(np.float32).astype(np.float64)
+        hi = box[:, 12:24].copy().view(np.float32).astype(np.float64)
+        tg = box[:, 24:32].copy().view(np.uint32)
+        t0, t1 = tg[:, 0], tg[:, 1]
+        lk = raw[256 + nn * 32:256 + nn * 40].copy().view(np.uint32).reshape(nn, 2)
+        link, esc = lk[:, 0], lk[:, 1]
+        kids_off = 256 + nn * 40
+    kids = raw[kids_off:kids_off + (N - 1) * 8].copy().view(np.uint32).reshape(N - 1, 2)
+    seeds_off = kids_off + max(N - 1, 1) * 8
+    ns = int(hdr[1])
+    ns = min(ns, N // 4 + 4096)
+    seeds = raw[seeds_off:seeds_off + ns * 8].copy().view(np.uint32).reshape(ns, 2)
+    return dict(err=int(hdr[0]), overflow=int(hdr[2]), lo=lo, hi=hi, t0=t0, t1=t1, link=link,
+                esc=esc, kids=kids.astype(np.int64), seeds=seeds)
+
+
+def _round_out(lo, hi):
+    f_lo, f_hi = lo.astype(np.float32), hi.astype(np.float32)
+    f_lo = np.where(f_lo.astype(np.float64) > lo, np.nextafter(f_lo, np.float32(-np.inf)), f_lo)
+    f_hi = np.where(f_hi.astype(np.float64) < hi, np.nextafter(f_hi, np.float32(np.inf)), f_hi)
+    return f_lo.astype(np.float64), f_hi.astype(np.float64)
+
+
+def check_tree(bp):
+    N, prec = bp.count, bp.tree_precision
+    torch.cuda.synchronize()
+    t = _decode(bp.tree, N, prec)
+    assert t["err"] == 0
+    lo, hi, t0, t1, kids = t["lo"], t["hi"], t["t0"], t["t1"], t["kids"]
+    # leaves: the input boxes, in some order
+    b = bp.boxes
+    blo = b.lo[:, :N].cpu().numpy().T.astype(np.float64)
+    bhi = b.hi[:, :N].cpu().numpy().T.astype(np.float64)
+    if prec == cd.CD_FP32 and b.precision == cd.CD_FP64:
+        blo, bhi = _round_out(blo, bhi)
+    bt0 = b.t0[:N].cpu().numpy().view(np.uint32)
+    bt1 = b.t1[:N].cpu().numpy().view(np.uint32)
+    bob = b.obj[:N].cpu().numpy().view(np.uint32)
+    want = np.column_stack([blo, bhi, bt0, bt1, bob])
+    L = slice(N - 1, 2 * N - 1)
+    got = np.column_stack([lo[L], hi[L], t0[L], t1[L], t["link"][L]])
+    assert np.array_equal(want[np.lexsort(want.T[::-1])], got[np.lexsort(got.T[::-1])])
+    if N == 1:
+        return
+    # every node but the root is a child exactly once
+    seen = np.bincount(kids.ravel(), minlength=2 * N - 1)
+    assert seen[0] == 0 and np.all(seen[1:] == 1)
+    # exact unions, bottom-up definition checked top-down on every inner node
+    l, r = kids[:, 0], kids[:, 1]
+    I = slice(0, N - 1)
+    assert np.array_equal(lo[I], np.minimum(lo[l], lo[r]))
+    assert np.array_equal(hi[I], np.maximum(hi[l], hi[r]))
+    assert np.array_equal(t0[I], np.minimum(t0[l], t0[r]))
+    assert np.array_equal(t1[I], np.maximum(t1[l], t1[r]))
+    assert np.array_equal(t["link"][I], l.astype(np.uint32))
+    # pre-order walk by link (inner) and esc (leaf), and esc skips the subtree
+    order, cur = [], 0
+    while cur != END and len(order) <= 2 * N:
+        order.append(cur)
+        cur = int(t["link"][cur]) if cur < N - 1 else int(t["esc"][cur])
+    assert len(order) == 2 * N - 1 and len(set(order)) == 2 * N - 1
+    pos = np.empty(2 * N - 1, np.int64)
+    pos[np.array(order)] = np.arange(2 * N - 1)
+    size = np.ones(2 * N - 1, np.int64)
+    for v in reversed(order):
+        if v < N - 1:
+            size[v] = 1 + size[kids[v, 0]] + size[kids[v, 1]]
+    nxt = pos + size
+    esc = t["esc"].astype(np.int64)
+    has = nxt < 2 * N - 1
+    assert np.all(esc[~has] == END)
+    assert np.array_equal(pos[esc[has]], nxt[has])
+    # seeds: exactly the overlapping sibling pairs
+    ov = ((t0[l] < t1[r]) & (t0[r] < t1[l])
+          & np.all(lo[l] <= hi[r], axis=1) & np.all(lo[r] <= hi[l], axis=1))
+    want_s = {(int(a), int(c)) for a, c in zip(l[ov], r[ov])}
+    got_s = {(int(a), int(c)) for a, c in t["seeds"]}
+    assert len(got_s) == len(t["seeds"])
+    if t["overflow"]:   # a full seed list holds some of them (the query then walks)
+        assert got_s <= want_s
+    else:
+        assert got_s == want_s
+    return len(want_s)
+
+
+def _uniform(n, K, dt, seed=0, box_precision=cd.CD_FP64, tree_precision=cd.CD_FP64,
+             codes=True):
+    """n LEO objects, K intervals of dt one-second ticks, threshold 1 km."""
+    rng = np.random.default_rng(seed)
+    el = catalog.leo_mix(rng, n)
+    p = cd.params_struct(1.0, catalog.MU_EARTH, 1.0, K * dt - 1, dt)
+    bp = cd.BroadPhase(n, p, box_precision=box_precision, tree_precision=tree_precision,
+                       codes=codes)
+    bp.build(cd.soa(el))
+    return bp
+
+
+@pytest.mark.parametrize("n,K", [(1, 50), (2, 40), (300, 60), (17408, 3), (3, 70000)])
+def test_uniform_step_trees(n, K):
+    need_gpu()
+    say("tree invariants, uniform steps, n", n, "K", K)
+    bp = _uniform(n, K, 2, seed=n)
+    assert bp.count == n * K
+    say("seeds", check_tree(bp))
+
+
+@pytest.mark.parametrize("box_prec,tree_prec,codes", [(cd.CD_FP64, cd.CD_FP32, True),
+                                                      (cd.CD_FP32, cd.CD_FP32, True),
+                                                      (cd.CD_FP64, cd.CD_FP64, False)])
+def test_uniform_step_tree_precisions(box_prec, tree_prec, codes):
+    need_gpu()
+    say("tree invariants, precisions", box_prec, tree_prec, "codes", codes)
+    bp = _uniform(500, 40, 30, seed=7, box_precision=box_prec, tree_precision=tree_prec,
+                  codes=codes)
+    check_tree(bp)
+
+
+def test_per_object_step_tree():
+    need_gpu()
+    say("tree invariants, per-object steps")
+    rng = np.random.default_rng(11)
+    el = catalog.leo_mix(rng, 400)
+    p = cd.params_struct(1.0, catalog.MU_EARTH, 1.0, 3000, 0)
+    bp = cd.BroadPhase(400, p, dt_heuristic_km=20.0, el_soa=cd.soa(el))
+    bp.build(cd.soa(el))
+    check_tree(bp)
