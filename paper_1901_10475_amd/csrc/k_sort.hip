@@ -404,7 +404,9 @@ __global__ __launch_bounds__(kSegThreads) void k_slab_build(
         if (p < m) {
             xch[p] = key[j];
             vsrc[val[j]] = p;
-            keys_out[base + p] = (slab << 32) | key[j];
+            // streaming store: lanes write consecutive keys (whole lines)
+            __builtin_nontemporal_store((unsigned long long)((slab << 32) | key[j]),
+                                        (unsigned long long *)&keys_out[base + p]);
         }
     }
     __syncthreads();
