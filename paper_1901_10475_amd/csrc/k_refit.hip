@@ -176,10 +176,65 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
     }
     __syncthreads();
     // inner nodes completed here (both children arrived) go out in one pass
-    if (c0 + t + 1 < N && cnt[t] == 2) {
+    if (TP == CD_FP64) {
+        // Four lanes per 64-byte record, 16 bytes each: every store
+        // instruction of a wave writes 16 consecutive records (1 KB of whole
+        // lines), so the stores can bypass the caches (non-temporal) without
+        // partial-line writes.
+        typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
+        for (uint32_t x = t; x < 4u * (uint32_t)kRefitChunk; x += (uint32_t)kRefitChunk) {
+            uint32_t r = x >> 2, q = x & 3u;
+            uint32_t p = c0 + r;
+            if (p + 1 < N && cnt[r] == 2) {
+                const LBox &o = innb[r];
+                u64x2 v;
+                if (q == 0) {
+                    v.x = __builtin_bit_cast(unsigned long long, o.lo[0]);
+                    v.y = __builtin_bit_cast(unsigned long long, o.lo[1]);
+                } else if (q == 1) {
+                    v.x = __builtin_bit_cast(unsigned long long, o.lo[2]);
+                    v.y = __builtin_bit_cast(unsigned long long, o.hi[0]);
+                } else if (q == 2) {
+                    v.x = __builtin_bit_cast(unsigned long long, o.hi[1]);
+                    v.y = __builtin_bit_cast(unsigned long long, o.hi[2]);
+                } else {
+                    v.x = (unsigned long long)o.t0 | ((unsigned long long)o.t1 << 32);
+                    v.y = (unsigned long long)kid[r].x |
+                          ((unsigned long long)links[p].esc << 32);
+                }
+                __builtin_nontemporal_store(v, (u64x2 *)((Node64 *)tree + p) + q);
+            }
+        }
+    } else {
+        // FP32: two lanes per 32-byte box record, then one lane per 8-byte
+        // link record; the unions of float-valued boxes are exact in float
+        typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+        typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+        for (uint32_t x = t; x < 2u * (uint32_t)kRefitChunk; x += (uint32_t)kRefitChunk) {
+            uint32_t r = x >> 1, q = x & 1u;
+            uint32_t p = c0 + r;
+            if (p + 1 < N && cnt[r] == 2) {
+                const LBox &o = innb[r];
+                u32x4 v;
+                if (q == 0) {
+                    v.x = __float_as_uint(__double2float_rd(o.lo[0]));
+                    v.y = __float_as_uint(__double2float_rd(o.lo[1]));
+                    v.z = __float_as_uint(__double2float_rd(o.lo[2]));
+                    v.w = __float_as_uint(__double2float_ru(o.hi[0]));
+                } else {
+                    v.x = __float_as_uint(__double2float_ru(o.hi[1]));
+                    v.y = __float_as_uint(__double2float_ru(o.hi[2]));
+                    v.z = o.t0;
+                    v.w = o.t1;
+                }
+                __builtin_nontemporal_store(v, (u32x4 *)((Box32 *)tree + p) + q);
+            }
+        }
         uint32_t p = c0 + t;
-        NodeIO<TP>::put(tree, N, p, innb[t].lo, innb[t].hi, innb[t].t0, innb[t].t1, kid[t].x,
-                        links[p].esc);
+        if (p + 1 < N && cnt[t] == 2) {
+            u32x2 l = {kid[t].x, links[p].esc};
+            __builtin_nontemporal_store(l, (u32x2 *)((Link *)((Box32 *)tree + (2 * (size_t)N - 1)) + p));
+        }
     }
     stage.flush(seeds, &sbase);
     if (bad)
