@@ -81,10 +81,10 @@ def algorithmic_bytes(stage, N, n, P, tree_prec, box_prec):
     table = {
         "boxes": N * box,                                    # boxes written
         "keys": 0,                                           # sampled frame only
-        "sort": N * (4 + 4) + N * box + N * 8 + N * node,    # slab build: codes and tags,
-                                                             # then boxes in; sorted keys
+        "sort": N * (4 + 4) + N * box + N * 4 + N * node,    # slab build: codes and tags,
+                                                             # then boxes in; sorted codes
                                                              # and leaf records out
-        "karras": N * 8 + (N - 1) * (8 + 1) + nodes * (8 + 4),  # keys in; kids, level,
+        "karras": N * 4 + (N - 1) * (8 + 1) + nodes * (8 + 4),  # codes in; kids, level,
                                                              # links, parents out
         "refit": N * node + nodes * 4 + (N - 1) * (8 + 8) + (N - 1) * node,
                                                              # leaf records, parents, kids

@@ -729,13 +729,14 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
         {
             Stage st("sort", s);
             CD_HIP(launch_slab_build(bv, boxes->precision, precision, (uint32_t)(N / m), m,
-                                     (uint32_t)N, w, tw.bounds, tw.keys, links, nodes, err, s));
+                                     (uint32_t)N, w, tw.bounds, (uint32_t *)tw.keys, links, nodes,
+                                     err, s));
         }
         leaf_src = nullptr;
         Stage st("karras", s);
         if (N > 1)
-            CD_HIP(launch_karras_slabs(tw.keys, (uint32_t)N, m, kids, links, tw.parent, tw.clev,
-                                       s));
+            CD_HIP(launch_karras_slabs((const uint32_t *)tw.keys, (uint32_t)N, m, kids, links,
+                                       tw.parent, tw.clev, s));
         else
             CD_HIP(launch_karras(tw.keys, (uint32_t)N, kids, links, tw.parent, tw.clev, false, s));
     } else {

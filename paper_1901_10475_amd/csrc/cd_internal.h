@@ -413,7 +413,7 @@ constexpr int64_t kSegCap = (int64_t)kSegThreads * kSegItems;
 hipError_t launch_slab_build(const BoxView &b, int box_precision, int tree_precision,
                              uint32_t nslabs, uint32_t slab_size, uint32_t N,
                              uint32_t slab_ticks, const unsigned long long *bounds,
-                             uint64_t *keys_out, Link *links, void *tree, unsigned int *err,
+                             uint32_t *codes_out, Link *links, void *tree, unsigned int *err,
                              hipStream_t s);
 
 // tree
@@ -510,7 +510,7 @@ hipError_t launch_karras(const uint64_t *keys, uint32_t N, uint2 *kids, Link *li
                          uint32_t *parent, uint8_t *clev, bool leaf_links, hipStream_t s);
 // slab path (time-major slabs of slab_size leaves, slab_size <= kSegCap); the
 // leaf links are written by the slab build
-hipError_t launch_karras_slabs(const uint64_t *keys, uint32_t N, uint32_t slab_size, uint2 *kids,
+hipError_t launch_karras_slabs(const uint32_t *codes, uint32_t N, uint32_t slab_size, uint2 *kids,
                                Link *links, uint32_t *parent, uint8_t *clev, hipStream_t s);
 // idx == nullptr: the leaf records are already written (slab build).
 hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision, uint32_t N,

@@ -284,7 +284,7 @@ constexpr int kSegWaves = kSegThreads / 64;
 template <int PREC, int TP, bool CODES>
 __global__ __launch_bounds__(kSegThreads) void k_slab_build(
     BoxView b, uint32_t slab_size, uint32_t N, uint32_t slab_ticks,
-    const unsigned long long *bounds, uint64_t *__restrict__ keys_out, Link *__restrict__ links,
+    const unsigned long long *bounds, uint32_t *__restrict__ codes_out, Link *__restrict__ links,
     void *tree, unsigned int *err)
 {
     __shared__ uint32_t xch[kSegCap];
@@ -404,9 +404,9 @@ __global__ __launch_bounds__(kSegThreads) void k_slab_build(
         if (p < m) {
             xch[p] = key[j];
             vsrc[val[j]] = p;
-            // streaming store: lanes write consecutive keys (whole lines)
-            __builtin_nontemporal_store((unsigned long long)((slab << 32) | key[j]),
-                                        (unsigned long long *)&keys_out[base + p]);
+            // the sorted 32-bit codes (a slab's key bits above them are its
+            // index); streaming stores: lanes write consecutive words
+            __builtin_nontemporal_store(key[j], &codes_out[base + p]);
         }
     }
     __syncthreads();
@@ -446,7 +446,7 @@ __global__ __launch_bounds__(kSegThreads) void k_slab_build(
 hipError_t launch_slab_build(const BoxView &b, int box_precision, int tree_precision,
                              uint32_t nslabs, uint32_t slab_size, uint32_t N,
                              uint32_t slab_ticks, const unsigned long long *bounds,
-                             uint64_t *keys_out, Link *links, void *tree, unsigned int *err,
+                             uint32_t *codes_out, Link *links, void *tree, unsigned int *err,
                              hipStream_t s)
 {
     if (nslabs == 0 || N == 0)
@@ -455,7 +455,7 @@ hipError_t launch_slab_build(const BoxView &b, int box_precision, int tree_preci
         return hipErrorInvalidValue;
 #define CD_SLAB_LAUNCH(P, T, C)                                                             \
     k_slab_build<P, T, C><<<nslabs, kSegThreads, 0, s>>>(b, slab_size, N, slab_ticks, bounds,  \
-                                                         keys_out, links, tree, err)
+                                                         codes_out, links, tree, err)
     const bool codes = b.code != nullptr;
     if (box_precision == CD_FP64 && tree_precision == CD_FP64) {
         if (codes)

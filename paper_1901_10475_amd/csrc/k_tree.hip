@@ -210,7 +210,7 @@ __global__ void k_karras(const uint64_t *__restrict__ keys, uint32_t N, uint2 *k
 // slab, so the slab-bits-only view of other slabs is exact).  The binary
 // searches then wait on LDS instead of L2.  Leaf skip links come from the
 // slab build.
-__global__ __launch_bounds__(kSegThreads) void k_karras_slabs(const uint64_t *__restrict__ keys,
+__global__ __launch_bounds__(kSegThreads) void k_karras_slabs(const uint32_t *__restrict__ codes,
                                                               uint32_t N, uint32_t slab_size,
                                                               uint2 *kids, Link *links,
                                                               uint32_t *parent, uint8_t *clev)
@@ -220,7 +220,7 @@ __global__ __launch_bounds__(kSegThreads) void k_karras_slabs(const uint64_t *__
     uint64_t base = slab * slab_size;
     uint32_t m = (uint32_t)(base + slab_size <= N ? slab_size : N - base);
     for (uint32_t k = threadIdx.x; k < m; k += blockDim.x)
-        sk[k] = (uint32_t)keys[base + k];
+        sk[k] = codes[base + k];
     __syncthreads();
     const SlabKeys K{sk, base, slab_size, slab << 32};
     for (uint32_t k = threadIdx.x; k < m; k += blockDim.x) {
@@ -267,13 +267,13 @@ hipError_t launch_karras(const uint64_t *keys, uint32_t N, uint2 *kids, Link *li
     return hipGetLastError();
 }
 
-hipError_t launch_karras_slabs(const uint64_t *keys, uint32_t N, uint32_t slab_size, uint2 *kids,
+hipError_t launch_karras_slabs(const uint32_t *codes, uint32_t N, uint32_t slab_size, uint2 *kids,
                                Link *links, uint32_t *parent, uint8_t *clev, hipStream_t s)
 {
     if (N <= 1 || slab_size == 0 || (int64_t)slab_size > kSegCap)
         return hipErrorInvalidValue;
     uint32_t nslabs = (uint32_t)((N + slab_size - 1) / slab_size);
-    k_karras_slabs<<<nslabs, kSegThreads, 0, s>>>(keys, N, slab_size, kids, links, parent, clev);
+    k_karras_slabs<<<nslabs, kSegThreads, 0, s>>>(codes, N, slab_size, kids, links, parent, clev);
     return hipGetLastError();
 }
 
