@@ -229,7 +229,7 @@ struct TreeWS {
     uint64_t *keys;
     uint32_t *idx, *parent, *arrive, *list_items, *list_count;
     uint8_t *clev;
-    Link *links;
+    uint32_t *esc;   // escapes of an FP64 tree's nodes, for the refit
     unsigned long long *bounds;
     void *radix;
 };
@@ -248,7 +248,7 @@ size_t layout_tree(void *base, size_t bytes, int64_t N, TreeWS *w)
     w->list_items = c.take<uint32_t>(slots * kRefitListCap);
     w->list_count = c.take<uint32_t>(slots);
     w->clev = c.take<uint8_t>(n);
-    w->links = c.take<Link>(2 * n);
+    w->esc = c.take<uint32_t>(2 * n);
     w->bounds = c.take<unsigned long long>(6);
     w->radix = c.take_bytes(radix_ws_bytes(n));
     return c.off;
@@ -714,10 +714,11 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
     bool seg = boxes->slab_size > 0 && boxes->slab_size <= kSegCap && boxes->slab_ticks == w &&
                N % boxes->slab_size == 0;
     // FP32 trees keep their link records in the tree itself; FP64 records
-    // carry them inline and take them from the workspace during the refit
-    Link *links = precision == CD_FP32
-                      ? (Link *)((Box32 *)nodes + (2 * (size_t)N - 1))
-                      : tw.links;
+    // carry them inline and take the escapes from the workspace during the
+    // refit (their link word is the left child, which the refit holds)
+    LinkSink links;
+    links.rec = precision == CD_FP32 ? (Link *)((Box32 *)nodes + (2 * (size_t)N - 1)) : nullptr;
+    links.esc = precision == CD_FP32 ? nullptr : tw.esc;
     uint2 *kids = (uint2 *)((char *)tree->mem + tree_kids_offset((uint64_t)N, precision));
     const uint32_t *leaf_src = tw.idx;  // nullptr once the leaf records exist
     if (seg) {
@@ -729,8 +730,8 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
         {
             Stage st("sort", s);
             CD_HIP(launch_slab_build(bv, boxes->precision, precision, (uint32_t)(N / m), m,
-                                     (uint32_t)N, w, tw.bounds, (uint32_t *)tw.keys, links, nodes,
-                                     err, s));
+                                     (uint32_t)N, w, tw.bounds, (uint32_t *)tw.keys, nodes, err,
+                                     s));
         }
         leaf_src = nullptr;
         Stage st("karras", s);

@@ -47,6 +47,26 @@ struct Link {
     uint32_t link, esc;
 };
 static_assert(sizeof(Node64) == 64, "Node64 layout");
+// Where the Karras pass leaves each node's (link, esc) for the refit: the
+// FP32 tree's own link records, or, for an FP64 tree (whose records get both
+// words from the refit, the link being the left child), the escapes alone.
+struct LinkSink {
+    Link *rec;       // FP32 tree link records, or nullptr
+    uint32_t *esc;   // escapes only, when rec == nullptr
+    __device__ void put(uint32_t id, uint32_t link, uint32_t e) const
+    {
+        if (rec) {
+            Link l;
+            l.link = link;
+            l.esc = e;
+            rec[id] = l;
+        } else {
+            esc[id] = e;
+        }
+    }
+    __device__ uint32_t esc_of(uint32_t id) const { return rec ? rec[id].esc : esc[id]; }
+};
+
 static_assert(sizeof(Box32) == 32, "Box32 layout");
 
 // Radix-sort items: 16 bytes each.
@@ -413,7 +433,7 @@ constexpr int64_t kSegCap = (int64_t)kSegThreads * kSegItems;
 hipError_t launch_slab_build(const BoxView &b, int box_precision, int tree_precision,
                              uint32_t nslabs, uint32_t slab_size, uint32_t N,
                              uint32_t slab_ticks, const unsigned long long *bounds,
-                             uint32_t *codes_out, Link *links, void *tree, unsigned int *err,
+                             uint32_t *codes_out, void *tree, unsigned int *err,
                              hipStream_t s);
 
 // tree
@@ -506,16 +526,16 @@ uint32_t refit_levels(uint32_t N);
 size_t refit_list_slots(uint32_t N, uint32_t *base);
 // leaf_links: also write the leaves' link records (skipped when the slab
 // build wrote them).
-hipError_t launch_karras(const uint64_t *keys, uint32_t N, uint2 *kids, Link *links,
+hipError_t launch_karras(const uint64_t *keys, uint32_t N, uint2 *kids, const LinkSink &links,
                          uint32_t *parent, uint8_t *clev, bool leaf_links, hipStream_t s);
 // slab path (time-major slabs of slab_size leaves, slab_size <= kSegCap); the
 // leaf links are written by the slab build
 hipError_t launch_karras_slabs(const uint32_t *codes, uint32_t N, uint32_t slab_size, uint2 *kids,
-                               Link *links, uint32_t *parent, uint8_t *clev, hipStream_t s);
+                               const LinkSink &links, uint32_t *parent, uint8_t *clev, hipStream_t s);
 // idx == nullptr: the leaf records are already written (slab build).
 hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision, uint32_t N,
                         const uint32_t *idx, const uint32_t *parent, const uint2 *kids,
-                        const Link *links, const uint8_t *clev, unsigned int *arrive,
+                        const LinkSink &links, const uint8_t *clev, unsigned int *arrive,
                         uint32_t *list_items, uint32_t *list_count, void *tree,
                         const SeedSink &seeds, unsigned int *err, hipStream_t s);
 

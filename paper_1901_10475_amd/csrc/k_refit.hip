@@ -62,7 +62,7 @@ struct SeedStage {
 template <int BP, int TP>
 __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
     BoxView b, uint32_t N, const uint32_t *__restrict__ idx, const uint32_t *__restrict__ parent,
-    const uint2 *__restrict__ kids, const Link *__restrict__ links, const uint8_t *clev,
+    const uint2 *__restrict__ kids, LinkSink links, const uint8_t *clev,
     void *tree, RefitLists L, SeedSink seeds, unsigned int *err)
 {
     __shared__ LBox innb[kRefitChunk];
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
         t0 = b.t0[src];
         t1 = b.t1[src];
         uint32_t leaf = N - 1 + i;
-        NodeIO<TP>::put(tree, N, leaf, lo, hi, t0, t1, b.obj[src], links[leaf].esc);
+        NodeIO<TP>::put(tree, N, leaf, lo, hi, t0, t1, b.obj[src], links.esc_of(leaf));
         par_leaf[t] = parent[leaf];
     } else if (t < m) {
         // leaf records already written in sorted order by the slab build
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
                 } else {
                     v.x = (unsigned long long)o.t0 | ((unsigned long long)o.t1 << 32);
                     v.y = (unsigned long long)kid[r].x |
-                          ((unsigned long long)links[p].esc << 32);
+                          ((unsigned long long)links.esc_of(p) << 32);
                 }
                 __builtin_nontemporal_store(v, (u64x2 *)((Node64 *)tree + p) + q);
             }
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
         }
         uint32_t p = c0 + t;
         if (p + 1 < N && cnt[t] == 2) {
-            u32x2 l = {kid[t].x, links[p].esc};
+            u32x2 l = {kid[t].x, links.esc_of(p)};
             __builtin_nontemporal_store(l, (u32x2 *)((Link *)((Box32 *)tree + (2 * (size_t)N - 1)) + p));
         }
     }
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
 template <int TP>
 __global__ __launch_bounds__(kRefitLevelThreads) void k_refit_level(
     uint32_t N, uint32_t lev, const uint32_t *__restrict__ parent, const uint2 *__restrict__ kids,
-    const Link *__restrict__ links, const uint8_t *clev, void *tree, unsigned int *arrive,
+    LinkSink links, const uint8_t *clev, void *tree, unsigned int *arrive,
     RefitLists L, SeedSink seeds, unsigned int *err)
 {
     __shared__ uint2 sbuf[kSeedStage];
@@ -284,7 +284,7 @@ __global__ __launch_bounds__(kRefitLevelThreads) void k_refit_level(
             // loaded at once; only the sibling's box waits for the acquire
             uint32_t pl = clev[p];
             uint2 lr = kids[p];
-            uint32_t pesc = links[p].esc;
+            uint32_t pesc = links.esc_of(p);
             uint32_t ppv = parent[p];
             if (pl > lev) {
                 ok &= L.push(pl, first_leaf, node);
@@ -338,7 +338,7 @@ size_t refit_list_slots(uint32_t N, uint32_t *base)
 
 hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision, uint32_t N,
                         const uint32_t *idx, const uint32_t *parent, const uint2 *kids,
-                        const Link *links, const uint8_t *clev, unsigned int *arrive,
+                        const LinkSink &links, const uint8_t *clev, unsigned int *arrive,
                         uint32_t *list_items, uint32_t *list_count, void *tree,
                         const SeedSink &seeds, unsigned int *err, hipStream_t s)
 {

@@ -284,8 +284,8 @@ constexpr int kSegWaves = kSegThreads / 64;
 template <int PREC, int TP, bool CODES>
 __global__ __launch_bounds__(kSegThreads) void k_slab_build(
     BoxView b, uint32_t slab_size, uint32_t N, uint32_t slab_ticks,
-    const unsigned long long *bounds, uint32_t *__restrict__ codes_out, Link *__restrict__ links,
-    void *tree, unsigned int *err)
+    const unsigned long long *bounds, uint32_t *__restrict__ codes_out, void *tree,
+    unsigned int *err)
 {
     __shared__ uint32_t xch[kSegCap];
     // counters of (digit, wave), stored wave-major with a 257-word row (see
@@ -446,7 +446,7 @@ __global__ __launch_bounds__(kSegThreads) void k_slab_build(
 hipError_t launch_slab_build(const BoxView &b, int box_precision, int tree_precision,
                              uint32_t nslabs, uint32_t slab_size, uint32_t N,
                              uint32_t slab_ticks, const unsigned long long *bounds,
-                             uint32_t *codes_out, Link *links, void *tree, unsigned int *err,
+                             uint32_t *codes_out, void *tree, unsigned int *err,
                              hipStream_t s)
 {
     if (nslabs == 0 || N == 0)
@@ -455,7 +455,7 @@ hipError_t launch_slab_build(const BoxView &b, int box_precision, int tree_preci
         return hipErrorInvalidValue;
 #define CD_SLAB_LAUNCH(P, T, C)                                                             \
     k_slab_build<P, T, C><<<nslabs, kSegThreads, 0, s>>>(b, slab_size, N, slab_ticks, bounds,  \
-                                                         codes_out, links, tree, err)
+                                                         codes_out, tree, err)
     const bool codes = b.code != nullptr;
     if (box_precision == CD_FP64 && tree_precision == CD_FP64) {
         if (codes)

@@ -168,7 +168,7 @@ hipError_t launch_unpack_kv(const KV *kv, uint32_t N, uint64_t *keys, uint32_t *
 // refit_block(k) leaves contain its whole leaf range); parent[child] = i, with
 // kCross set when clev[i] > 0.
 
-__global__ void k_karras(const uint64_t *__restrict__ keys, uint32_t N, uint2 *kids, Link *links,
+__global__ void k_karras(const uint64_t *__restrict__ keys, uint32_t N, uint2 *kids, LinkSink links,
                          uint32_t *parent, uint8_t *clev, bool leaf_links)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -186,22 +186,12 @@ __global__ void k_karras(const uint64_t *__restrict__ keys, uint32_t N, uint2 *k
     if (i == 0)
         parent[0] = kEnd;
     kids[i] = make_uint2(nd.left, nd.right);
-    Link li;
-    li.link = nd.left;
-    li.esc = karras_escape(K, N, nd.last);
-    links[i] = li;
+    links.put(i, nd.left, karras_escape(K, N, nd.last));
     if (!leaf_links)
         return;
-    Link lf;
-    lf.link = 0;
-    lf.esc = karras_escape(K, N, i);
-    links[N - 1 + i] = lf;
-    if (i == N - 2) {
-        Link ll;
-        ll.link = 0;
-        ll.esc = kEnd;
-        links[2 * N - 2] = ll;
-    }
+    links.put(N - 1 + i, 0, karras_escape(K, N, i));
+    if (i == N - 2)
+        links.put(2 * N - 2, 0, kEnd);
 }
 
 // Same nodes as k_karras for time-major slabs: one workgroup per slab holds
@@ -212,7 +202,7 @@ __global__ void k_karras(const uint64_t *__restrict__ keys, uint32_t N, uint2 *k
 // slab build.
 __global__ __launch_bounds__(kSegThreads) void k_karras_slabs(const uint32_t *__restrict__ codes,
                                                               uint32_t N, uint32_t slab_size,
-                                                              uint2 *kids, Link *links,
+                                                              uint2 *kids, LinkSink links,
                                                               uint32_t *parent, uint8_t *clev)
 {
     __shared__ uint32_t sk[kSegCap];
@@ -238,23 +228,17 @@ __global__ __launch_bounds__(kSegThreads) void k_karras_slabs(const uint32_t *__
         if (i == 0)
             parent[0] = kEnd;
         kids[i] = make_uint2(nd.left, nd.right);
-        Link li;
-        li.link = nd.left;
-        li.esc = karras_escape(K, N, nd.last);
-        links[i] = li;
+        links.put(i, nd.left, karras_escape(K, N, nd.last));
     }
 }
 
-__global__ void k_single_leaf(Link *links, uint32_t *parent)
+__global__ void k_single_leaf(LinkSink links, uint32_t *parent)
 {
-    Link l;
-    l.link = 0;
-    l.esc = kEnd;
-    links[0] = l;
+    links.put(0, 0, kEnd);
     parent[0] = kEnd;
 }
 
-hipError_t launch_karras(const uint64_t *keys, uint32_t N, uint2 *kids, Link *links,
+hipError_t launch_karras(const uint64_t *keys, uint32_t N, uint2 *kids, const LinkSink &links,
                          uint32_t *parent, uint8_t *clev, bool leaf_links, hipStream_t s)
 {
     if (N == 0)
@@ -268,7 +252,7 @@ hipError_t launch_karras(const uint64_t *keys, uint32_t N, uint2 *kids, Link *li
 }
 
 hipError_t launch_karras_slabs(const uint32_t *codes, uint32_t N, uint32_t slab_size, uint2 *kids,
-                               Link *links, uint32_t *parent, uint8_t *clev, hipStream_t s)
+                               const LinkSink &links, uint32_t *parent, uint8_t *clev, hipStream_t s)
 {
     if (N <= 1 || slab_size == 0 || (int64_t)slab_size > kSegCap)
         return hipErrorInvalidValue;
