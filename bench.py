@@ -46,13 +46,13 @@ BOX_RULES = {"speed": 0, "nu": 1, "ecc": 2}
 BOX_SUFFIX = {"speed": "", "nu": "_box_interval_nu", "ecc": "_box_interval_ecc"}
 
 TRAFFIC = {
-    ("sort", "fp64", "fixed"): {"fetch_kib": 2145742.0, "write_kib": 4709474.0,
+    ("sort", "fp64", "fixed"): {"fetch_kib": 2139990.0, "write_kib": 4482004.0,
                                 "source": "paper_1901_10475_amd/csrc/k_sort.hip",
-                                "sha1": "d6b8d6b366c6b3c12f57830617618e955b2d4ac0"},
-    ("refit", "fp64", "fixed"): {"fetch_kib": 2636763.0 + 423134.0,
-                                 "write_kib": 3772820.0 + 102294.0,
+                                "sha1": "08315350322cb1e7c7962b6875935713ffc67b92"},
+    ("refit", "fp64", "fixed"): {"fetch_kib": 2518332.0 + 417692.0,
+                                 "write_kib": 3772824.0 + 102267.0,
                                  "source": "paper_1901_10475_amd/csrc/k_refit.hip",
-                                 "sha1": "e9e9a4fb23d8492aefafe35661dbe29961ba96f2"},
+                                 "sha1": "770b9a83be466daa1f57842894d014328a13bef7"},
 }
 
 
@@ -86,9 +86,10 @@ def algorithmic_bytes(stage, N, n, P, tree_prec, box_prec):
                                                              # and leaf records out
         "karras": N * 4 + (N - 1) * (8 + 1) + nodes * (8 + 4),  # codes in; kids, level,
                                                              # links, parents out
-        "refit": N * node + nodes * 4 + (N - 1) * (8 + 8) + (N - 1) * node,
+        "refit": N * node + nodes * 4 + (N - 1) * (8 + 4) + (N - 1) * node,
                                                              # leaf records, parents, kids
-                                                             # and links in; inner records out
+                                                             # and escapes in; inner records
+                                                             # out
         "traverse": nodes * node + P * 16,                   # every node read once,
                                                              # records out
         "canon": P * 16 * 3,
