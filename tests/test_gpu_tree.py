@@ -9,7 +9,8 @@ boxes overlap (closed extents in space, half-open tags in time).
 Covered: uniform steps, where the boxes of each interval form one slab that
 one workgroup sorts in LDS before the Karras pass over the slab codes and the
 chunked refit (slabs of 1, 2, 300 and 17 408 boxes, the largest one workgroup
-sorts, and 70 000 slabs of 3); per-object steps (the general path: one radix
+sorts, and 70 000 slabs of 3; 17 409 objects per interval take the device-wide
+sort instead); per-object steps (the general path: one radix
 sort of all keys); FP64 and FP32 trees; boxes with and without Morton codes.
 
 Tree buffer layout read here: a 256-byte header (error bits, seed count, seed
@@ -139,7 +140,8 @@ def _uniform(n, K, dt, seed=0, box_precision=cd.CD_FP64, tree_precision=cd.CD_FP
     return bp
 
 
-@pytest.mark.parametrize("n,K", [(1, 50), (2, 40), (300, 60), (17408, 3), (3, 70000)])
+@pytest.mark.parametrize("n,K", [(1, 50), (2, 40), (300, 60), (17408, 3), (17409, 3),
+                                 (3, 70000)])
 def test_uniform_step_trees(n, K):
     need_gpu()
     say("tree invariants, uniform steps, n", n, "K", K)
