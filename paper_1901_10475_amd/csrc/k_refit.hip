@@ -111,6 +111,20 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
         kid[t] = kids[c0 + t];
         par_in[t] = parent[c0 + t];
     }
+    // The skip links of the records this lane writes at the end, loaded now
+    // so that the final pass waits on no global load: FP64, the last quarter
+    // of records (t / 4) + 256 j; FP32, the link record of node c0 + t.
+    uint32_t esc_w[4] = {0, 0, 0, 0};
+    if (TP == CD_FP64) {
+        if ((t & 3u) == 3u)
+            for (int j = 0; j < 4; ++j) {
+                uint32_t p = c0 + (t >> 2) + 256u * (uint32_t)j;
+                if (p + 1 < N)
+                    esc_w[j] = links.esc_of(p);
+            }
+    } else if (c0 + t + 1 < N) {
+        esc_w[0] = links.esc_of(c0 + t);
+    }
     cnt[t] = 0;
     __syncthreads();
     if (t < m) {
@@ -175,6 +189,13 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
         }
     }
     __syncthreads();
+    // the staged seeds' space is reserved now; the atomic's round trip
+    // overlaps the record pass below
+    uint32_t seed_res = 0;
+    if (t == 0) {
+        uint32_t ms = sn < (unsigned)kSeedStage ? sn : (unsigned)kSeedStage;
+        seed_res = ms ? seeds.reserve(ms) : 0u;
+    }
     // inner nodes completed here (both children arrived) go out in one pass
     if (TP == CD_FP64) {
         // Four lanes per 64-byte record, 16 bytes each: every store
@@ -182,7 +203,9 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
         // lines), so the stores can bypass the caches (non-temporal) without
         // partial-line writes.
         typedef unsigned long long u64x2 __attribute__((ext_vector_type(2)));
-        for (uint32_t x = t; x < 4u * (uint32_t)kRefitChunk; x += (uint32_t)kRefitChunk) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            uint32_t x = t + (uint32_t)kRefitChunk * (uint32_t)j;
             uint32_t r = x >> 2, q = x & 3u;
             uint32_t p = c0 + r;
             if (p + 1 < N && cnt[r] == 2) {
@@ -199,8 +222,7 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
                     v.y = __builtin_bit_cast(unsigned long long, o.hi[2]);
                 } else {
                     v.x = (unsigned long long)o.t0 | ((unsigned long long)o.t1 << 32);
-                    v.y = (unsigned long long)kid[r].x |
-                          ((unsigned long long)links.esc_of(p) << 32);
+                    v.y = (unsigned long long)kid[r].x | ((unsigned long long)esc_w[j] << 32);
                 }
                 __builtin_nontemporal_store(v, (u64x2 *)((Node64 *)tree + p) + q);
             }
@@ -232,11 +254,19 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
         }
         uint32_t p = c0 + t;
         if (p + 1 < N && cnt[t] == 2) {
-            u32x2 l = {kid[t].x, links.esc_of(p)};
+            u32x2 l = {kid[t].x, esc_w[0]};
             __builtin_nontemporal_store(l, (u32x2 *)((Link *)((Box32 *)tree + (2 * (size_t)N - 1)) + p));
         }
     }
-    stage.flush(seeds, &sbase);
+    if (t == 0)
+        sbase = seed_res;
+    __syncthreads();
+    {
+        uint32_t ms = sn < (unsigned)kSeedStage ? sn : (unsigned)kSeedStage;
+        for (uint32_t k = t; k < ms; k += blockDim.x)
+            if (sbase + k < seeds.cap)
+                seeds.items[sbase + k] = sbuf[k];
+    }
     if (bad)
         atomicOr(err, 2u);
 }
