@@ -452,6 +452,8 @@ constexpr int kRefitChunkLog = 10;
 constexpr int kRefitChunk = 1 << kRefitChunkLog;
 constexpr int kRefitListCap = 4096;   // queued nodes per block
 constexpr int kRefitMaxLevels = 8;
+constexpr int kPushLevels = 6;    // levels whose hand-offs the chunk refit stages in LDS
+constexpr int kPushStage = 64;    // staged hand-offs per level and chunk
 constexpr uint32_t kCross = 0x80000000u;   // parent pointer flag: parent level > 0
 constexpr uint32_t kNodeMask = 0x7FFFFFFFu;
 __host__ __device__ inline uint32_t refit_shift(uint32_t lev)

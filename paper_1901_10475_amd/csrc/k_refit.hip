@@ -71,10 +71,16 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
     __shared__ unsigned int cnt[kRefitChunk];
     __shared__ uint2 sbuf[kSeedStage];
     __shared__ unsigned int sn, sbase;
+    // nodes handed to levels 1..kPushLevels, staged per level: all of this
+    // chunk's go to one list per level, reserved with one atomic at the end
+    __shared__ uint32_t pstage[kPushLevels][kPushStage];
+    __shared__ unsigned int pcnt[kPushLevels], pbase[kPushLevels];
     const SeedStage stage{sbuf, &sn};
     const uint32_t t = threadIdx.x;
     if (t == 0)
         sn = 0;
+    if (t < (uint32_t)kPushLevels)
+        pcnt[t] = 0;
     const uint32_t c = xcd_block(blockIdx.x, gridDim.x);
     const uint32_t c0 = c * (uint32_t)kRefitChunk;
     const uint32_t m = N - c0 < (uint32_t)kRefitChunk ? N - c0 : (uint32_t)kRefitChunk;
@@ -135,7 +141,15 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
                 break;
             uint32_t p = pv & kNodeMask;
             if (pv & kCross) {
-                bad |= !L.push(clev[p], c0, node);
+                uint32_t lev = clev[p];
+                if (lev >= 1 && lev <= (uint32_t)kPushLevels) {
+                    unsigned int k = atomicAdd(&pcnt[lev - 1], 1u);
+                    if (k < (unsigned)kPushStage) {
+                        pstage[lev - 1][k] = node;
+                        break;
+                    }
+                }
+                bad |= !L.push(lev, c0, node);   // a full stage or a higher level
                 break;
             }
             uint32_t slot = p - c0;
@@ -195,6 +209,10 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
     if (t == 0) {
         uint32_t ms = sn < (unsigned)kSeedStage ? sn : (unsigned)kSeedStage;
         seed_res = ms ? seeds.reserve(ms) : 0u;
+    } else if (t <= (uint32_t)kPushLevels) {   // lane t reserves level t's list entries
+        uint32_t c = pcnt[t - 1] < (unsigned)kPushStage ? pcnt[t - 1] : (unsigned)kPushStage;
+        if (c)
+            seed_res = atomicAdd(&L.count[L.base[t] + (c0 >> refit_shift(t))], c);
     }
     // inner nodes completed here (both children arrived) go out in one pass
     if (TP == CD_FP64) {
@@ -260,12 +278,25 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
     }
     if (t == 0)
         sbase = seed_res;
+    else if (t <= (uint32_t)kPushLevels)
+        pbase[t - 1] = seed_res;
     __syncthreads();
     {
         uint32_t ms = sn < (unsigned)kSeedStage ? sn : (unsigned)kSeedStage;
         for (uint32_t k = t; k < ms; k += blockDim.x)
             if (sbase + k < seeds.cap)
                 seeds.items[sbase + k] = sbuf[k];
+    }
+    for (int lv = 0; lv < kPushLevels; ++lv) {
+        uint32_t c = pcnt[lv] < (unsigned)kPushStage ? pcnt[lv] : (unsigned)kPushStage;
+        uint32_t slot = L.base[lv + 1] + (c0 >> refit_shift((uint32_t)lv + 1));
+        for (uint32_t k = t; k < c; k += blockDim.x) {
+            uint32_t at = pbase[lv] + k;
+            if (at < (unsigned)kRefitListCap)
+                L.items[(size_t)slot * kRefitListCap + at] = pstage[lv][k];
+            else
+                bad = true;
+        }
     }
     if (bad)
         atomicOr(err, 2u);
@@ -374,7 +405,7 @@ hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision,
 {
     if (N == 0)
         return hipSuccess;
-    RefitLists L;
+    RefitLists L{};
     size_t slots = refit_list_slots(N, L.base);
     L.items = list_items;
     L.count = list_count;
