@@ -305,6 +305,33 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
 // Phase k >= 1: one workgroup per level-k block climbs from the nodes queued
 // for it, in global memory with workgroup-scope arrival counters, through the
 // nodes of level k; a parent of a higher level gets the node queued instead.
+// What a level climb needs to know about the parent pv points to, before
+// its arrival atomic: the pointer itself, the parent's level, children, skip
+// link and own parent pointer (kEnd or an id out of range: pointer only).
+struct PMeta {
+    uint32_t pv, lev, esc, ppv;
+    uint2 kids;
+};
+__device__ inline PMeta parent_meta(uint32_t N, uint32_t pv, const uint32_t *parent,
+                                    const uint2 *kids, const LinkSink &links,
+                                    const uint8_t *clev)
+{
+    PMeta m;
+    m.pv = pv;
+    m.lev = 0;
+    m.esc = kEnd;
+    m.ppv = kEnd;
+    m.kids = make_uint2(kEnd, kEnd);
+    uint32_t p = pv & kNodeMask;
+    if (pv != kEnd && p < N - 1) {
+        m.lev = clev[p];
+        m.kids = kids[p];
+        m.esc = links.esc_of(p);
+        m.ppv = parent[p];
+    }
+    return m;
+}
+
 template <int TP>
 __global__ __launch_bounds__(kRefitLevelThreads) void k_refit_level(
     uint32_t N, uint32_t lev, const uint32_t *__restrict__ parent, const uint2 *__restrict__ kids,
@@ -332,29 +359,29 @@ __global__ __launch_bounds__(kRefitLevelThreads) void k_refit_level(
         double lo[3], hi[3];
         uint32_t t0, t1;
         NodeIO<TP>::get_box(tree, N, node, lo, hi, t0, t1);
-        uint32_t pv = parent[node];
+        // Everything about a parent that does not depend on the arrival order
+        // (its level, children, skip link and own parent) is loaded one step
+        // ahead, alongside the previous step's sibling box, so a step waits on
+        // the arrival atomic and the sibling's box only.
+        PMeta cur = parent_meta(N, parent[node], parent, kids, links, clev);
         for (int guard = 0;; ++guard) {
-            if (pv == kEnd)
+            if (cur.pv == kEnd)
                 break;
-            uint32_t p = pv & kNodeMask;
+            uint32_t p = cur.pv & kNodeMask;
             if (p >= N - 1 || guard > 160) {
                 ok = false;
                 break;
             }
-            // everything about p that does not depend on the arrival order is
-            // loaded at once; only the sibling's box waits for the acquire
-            uint32_t pl = clev[p];
-            uint2 lr = kids[p];
-            uint32_t pesc = links.esc_of(p);
-            uint32_t ppv = parent[p];
-            if (pl > lev) {
-                ok &= L.push(pl, first_leaf, node);
+            if (cur.lev > lev) {
+                ok &= L.push(cur.lev, first_leaf, node);
                 break;
             }
             unsigned int old = __hip_atomic_fetch_add(&arrive[p], 1u, __ATOMIC_ACQ_REL,
                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
             if (old == 0)
                 break;
+            PMeta nxt = parent_meta(N, cur.ppv, parent, kids, links, clev);
+            uint2 lr = cur.kids;
             if (lr.x != node && lr.y != node) {
                 ok = false;
                 break;
@@ -366,9 +393,9 @@ __global__ __launch_bounds__(kRefitLevelThreads) void k_refit_level(
             if (time_overlap(t0, t1, ot0, ot1) && space_overlap(lo, hi, olo, ohi))
                 stage.push(seeds, lr.x, lr.y);
             unite(lo, hi, t0, t1, olo, ohi, ot0, ot1);
-            NodeIO<TP>::put(tree, N, p, lo, hi, t0, t1, lr.x, pesc);
+            NodeIO<TP>::put(tree, N, p, lo, hi, t0, t1, lr.x, cur.esc);
             node = p;
-            pv = ppv;
+            cur = nxt;
         }
     }
     stage.flush(seeds, &sbase);
