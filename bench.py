@@ -49,10 +49,10 @@ TRAFFIC = {
     ("sort", "fp64", "fixed"): {"fetch_kib": 2139990.0, "write_kib": 4482004.0,
                                 "source": "paper_1901_10475_amd/csrc/k_sort.hip",
                                 "sha1": "08315350322cb1e7c7962b6875935713ffc67b92"},
-    ("refit", "fp64", "fixed"): {"fetch_kib": 2518332.0 + 417692.0,
-                                 "write_kib": 3772824.0 + 102267.0,
+    ("refit", "fp64", "fixed"): {"fetch_kib": 2519448.0 + 376482.0,
+                                 "write_kib": 3749516.0 + 101467.0,
                                  "source": "paper_1901_10475_amd/csrc/k_refit.hip",
-                                 "sha1": "770b9a83be466daa1f57842894d014328a13bef7"},
+                                 "sha1": "1f6ba037b03be7f1dc9a799d9f9ffa3785438602"},
 }
 
 
