@@ -21,10 +21,11 @@ static inline unsigned nblk(uint64_t n, unsigned t) { return (unsigned)((n + t -
 // refit_block(k) = 1024 * 16^k consecutive leaves, level by level; a node
 // belongs to the lowest level whose blocks hold its whole range.
 //   level 0: one workgroup per 1024-leaf chunk, one leaf per thread.  Parents,
-//      children, arrival counters and computed inner boxes are staged in LDS
-//      (77 KB, two workgroups per CU); a sibling leaf is read back from its
-//      record, written before the barrier and still in L2.  Computed inner
-//      records are written out in one coalesced pass at the end.
+//      children, arrival counters, computed inner boxes and the hand-offs to
+//      upper levels are staged in LDS (79.6 KiB, two workgroups per CU); a
+//      sibling leaf is read back from its record, written before the barrier
+//      and still in L2.  Computed inner records are written out in one
+//      coalesced pass at the end.
 //   level k >= 1: one workgroup per level-k block climbs, in global memory with
 //      workgroup-scope counters, from the nodes queued for it by lower levels.
 // A climb that meets a parent of a higher level queues the node for that level
@@ -119,12 +120,13 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
     }
     // The skip links of the records this lane writes at the end, loaded now
     // so that the final pass waits on no global load: FP64, the last quarter
-    // of records (t / 4) + 256 j; FP32, the link record of node c0 + t.
+    // of records t / 4 + j * kRefitChunk / 4; FP32, the link record of node
+    // c0 + t.
     uint32_t esc_w[4] = {0, 0, 0, 0};
     if (TP == CD_FP64) {
         if ((t & 3u) == 3u)
             for (int j = 0; j < 4; ++j) {
-                uint32_t p = c0 + (t >> 2) + 256u * (uint32_t)j;
+                uint32_t p = c0 + (t >> 2) + (uint32_t)(kRefitChunk / 4) * (uint32_t)j;
                 if (p + 1 < N)
                     esc_w[j] = links.esc_of(p);
             }
