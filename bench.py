@@ -52,7 +52,7 @@ TRAFFIC = {
     ("refit", "fp64", "fixed"): {"fetch_kib": 2519448.0 + 376482.0,
                                  "write_kib": 3749516.0 + 101467.0,
                                  "source": "paper_1901_10475_amd/csrc/k_refit.hip",
-                                 "sha1": "af590f1bd369ba0f777bb794558953c2e4b7f870"},
+                                 "sha1": "9f9580ffa1721e34d216ae28a435ec66ee627275"},
 }
 
 

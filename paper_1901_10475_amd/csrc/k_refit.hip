@@ -205,16 +205,17 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
         }
     }
     __syncthreads();
-    // the staged seeds' space is reserved now; the atomic's round trip
-    // overlaps the record pass below
-    uint32_t seed_res = 0;
+    // Space for the staged seeds (lane 0) and for level t's staged hand-offs
+    // (lane t) is reserved now; the atomics' round trips overlap the record
+    // pass below.
+    uint32_t res = 0;
     if (t == 0) {
         uint32_t ms = sn < (unsigned)kSeedStage ? sn : (unsigned)kSeedStage;
-        seed_res = ms ? seeds.reserve(ms) : 0u;
-    } else if (t <= (uint32_t)kPushLevels) {   // lane t reserves level t's list entries
+        res = ms ? seeds.reserve(ms) : 0u;
+    } else if (t <= (uint32_t)kPushLevels) {
         uint32_t c = pcnt[t - 1] < (unsigned)kPushStage ? pcnt[t - 1] : (unsigned)kPushStage;
         if (c)
-            seed_res = atomicAdd(&L.count[L.base[t] + (c0 >> refit_shift(t))], c);
+            res = atomicAdd(&L.count[L.base[t] + (c0 >> refit_shift(t))], c);
     }
     // inner nodes completed here (both children arrived) go out in one pass
     if (TP == CD_FP64) {
@@ -279,9 +280,9 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
         }
     }
     if (t == 0)
-        sbase = seed_res;
+        sbase = res;
     else if (t <= (uint32_t)kPushLevels)
-        pbase[t - 1] = seed_res;
+        pbase[t - 1] = res;
     __syncthreads();
     {
         uint32_t ms = sn < (unsigned)kSeedStage ? sn : (unsigned)kSeedStage;
