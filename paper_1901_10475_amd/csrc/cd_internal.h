@@ -358,6 +358,59 @@ __device__ inline KarrasNode karras_node32(const K &key, uint32_t N, uint32_t i)
     return nd;
 }
 
+// The slab-key view for the Karras pass over one slab, in 32-bit arithmetic:
+// the node's own position i is always in the slab, and a probe below 0 wraps
+// to at least N (N < 2^31).  Same values as karras_delta over SlabKeys: keys
+// of the slab compare their 32-bit codes (then their positions, 96 + clz of
+// the 32-bit XOR being 64 + clz of the 64-bit one), and a position in another
+// slab differs from i in its slab bits, j / m.
+struct SlabKeys32 {
+    const uint32_t *lds;
+    uint32_t base, m, slab;
+};
+
+__device__ inline int slab_delta32(const SlabKeys32 &k, uint32_t N, uint32_t i, uint32_t j)
+{
+    if (j >= N)
+        return -1;
+    uint32_t uj = j - k.base;
+    if (uj < k.m) {
+        uint32_t a = k.lds[i - k.base], b = k.lds[uj];
+        return a != b ? 32 + __builtin_clz(a ^ b) : 96 + __builtin_clz(i ^ j);
+    }
+    return __builtin_clz(k.slab ^ (j / k.m));
+}
+
+// karras_node32 over the 32-bit slab view (same node)
+__device__ inline KarrasNode karras_node_slab(const SlabKeys32 &k, uint32_t N, uint32_t i)
+{
+    int d = slab_delta32(k, N, i, i + 1) >= slab_delta32(k, N, i, i - 1) ? 1 : -1;
+    auto at = [&](uint32_t off) { return d > 0 ? i + off : i - off; };
+    int dmin = slab_delta32(k, N, i, d > 0 ? i - 1 : i + 1);   // delta to i - d
+    uint32_t lmax = 2;
+    while (slab_delta32(k, N, i, at(lmax)) > dmin)
+        lmax *= 2;
+    uint32_t l = 0;
+    for (uint32_t t = lmax / 2; t >= 1; t /= 2)
+        if (slab_delta32(k, N, i, at(l + t)) > dmin)
+            l += t;
+    uint32_t j = at(l);
+    int dnode = slab_delta32(k, N, i, j);
+    uint32_t s = 0, t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (slab_delta32(k, N, i, at(s + t)) > dnode)
+            s += t;
+    } while (t > 1);
+    int gamma = (int)i + (int)s * d + (d < 0 ? -1 : 0);
+    KarrasNode nd;
+    nd.first = i < j ? i : j;
+    nd.last = i < j ? j : i;
+    nd.left = (nd.first == gamma) ? (uint32_t)(N - 1 + gamma) : (uint32_t)gamma;
+    nd.right = (nd.last == gamma + 1) ? (uint32_t)(N - 1 + gamma + 1) : (uint32_t)(gamma + 1);
+    return nd;
+}
+
 // ---- launchers (each returns the launch status) -----------------------------
 
 // boxes

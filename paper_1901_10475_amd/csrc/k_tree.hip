@@ -213,11 +213,12 @@ __global__ __launch_bounds__(kSegThreads) void k_karras_slabs(const uint32_t *__
         sk[k] = codes[base + k];
     __syncthreads();
     const SlabKeys K{sk, base, slab_size, slab << 32};
+    const SlabKeys32 K32{sk, (uint32_t)base, slab_size, (uint32_t)slab};
     for (uint32_t k = threadIdx.x; k < m; k += blockDim.x) {
         uint32_t i = (uint32_t)(base + k);
         if (i + 1 >= N)
             break;
-        KarrasNode nd = karras_node32(K, N, i);
+        KarrasNode nd = karras_node_slab(K32, N, i);
         uint32_t lev = 0;
         while ((uint64_t)(nd.first >> refit_shift(lev)) != (uint64_t)(nd.last >> refit_shift(lev)))
             ++lev;
