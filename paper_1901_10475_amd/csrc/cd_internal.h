@@ -286,45 +286,6 @@ constexpr int kMlpParams = kMlpB3 + 1;   // 4609
 constexpr int kMlpOuterThreads = 256;
 constexpr int kMlpOuterSamples = 128;    // samples per outer-product block
 
-// Keys of a Karras hierarchy over time-major slabs, with one slab's 32-bit
-// codes in LDS: key(g) = slab(g) << 32 | code(g) inside the slab; outside it
-// only the slab bits are returned.  Exact for every comparison that involves a
-// key of the slab itself, since keys of different slabs differ in their slab
-// bits.
-struct SlabKeys {
-    const uint32_t *lds;
-    uint64_t base, m, hi;  // hi = this slab's index << 32
-    __device__ uint64_t operator()(int64_t gi) const
-    {
-        uint64_t g = (uint64_t)gi;
-        if (g - base < m)
-            return hi | lds[g - base];
-        return (g / m) << 32;  // other slabs: only their slab bits matter
-    }
-};
-
-// Two keys of the node's own slab share their slab bits, so their common
-// prefix is 32 plus that of their 32-bit codes: the comparison stays in 32
-// bits (same result as the 64-bit keys).
-template <>
-__host__ __device__ inline int karras_delta<SlabKeys>(const SlabKeys &key, int64_t N, int64_t i,
-                                                      int64_t j)
-{
-    if (j < 0 || j >= N)
-        return -1;
-    uint64_t ui = (uint64_t)i - key.base, uj = (uint64_t)j - key.base;
-    if (ui < key.m && uj < key.m) {
-        uint32_t a = key.lds[ui], b = key.lds[uj];
-        if (a != b)
-            return 32 + __builtin_clz(a ^ b);
-        return 64 + __builtin_clzll((uint64_t)i ^ (uint64_t)j);
-    }
-    uint64_t a = key(i), b = key(j);
-    if (a != b)
-        return __builtin_clzll(a ^ b);
-    return 64 + __builtin_clzll((uint64_t)i ^ (uint64_t)j);
-}
-
 // karras_node with 32-bit index arithmetic (N < 2^30, so lmax <= 2^30 and every
 // probe i + offset stays below 2^31; the exponential probe is formed in 64 bits).
 template <class K>
@@ -358,12 +319,14 @@ __device__ inline KarrasNode karras_node32(const K &key, uint32_t N, uint32_t i)
     return nd;
 }
 
-// The slab-key view for the Karras pass over one slab, in 32-bit arithmetic:
-// the node's own position i is always in the slab, and a probe below 0 wraps
-// to at least N (N < 2^31).  Same values as karras_delta over SlabKeys: keys
-// of the slab compare their 32-bit codes (then their positions, 96 + clz of
-// the 32-bit XOR being 64 + clz of the 64-bit one), and a position in another
-// slab differs from i in its slab bits, j / m.
+// Keys of a Karras hierarchy over time-major slabs of m leaves, key(g) =
+// slab(g) << 32 | code(g), seen from one slab whose 32-bit codes are in LDS.
+// Every comparison involves a key of that slab (the node's own position i),
+// so it is exact without the other slabs' codes: two keys of the slab share
+// their slab bits, so their common prefix is 32 plus that of their codes
+// (equal keys: 64 plus that of the 64-bit positions, 96 + clz of the 32-bit
+// XOR), and a key of another slab differs from key(i) in its slab bits, j / m.
+// 32-bit arithmetic throughout: a probe below 0 wraps to at least N (N < 2^31).
 struct SlabKeys32 {
     const uint32_t *lds;
     uint32_t base, m, slab;
@@ -409,6 +372,27 @@ __device__ inline KarrasNode karras_node_slab(const SlabKeys32 &k, uint32_t N, u
     nd.left = (nd.first == gamma) ? (uint32_t)(N - 1 + gamma) : (uint32_t)gamma;
     nd.right = (nd.last == gamma + 1) ? (uint32_t)(N - 1 + gamma + 1) : (uint32_t)(gamma + 1);
     return nd;
+}
+
+// karras_escape over the 32-bit slab view, for a leaf range ending at r that
+// ends in this slab or at the end of a later one: the next node starts at
+// s = r + 1, and when s starts another slab its direction follows from slab
+// bits alone (with two or more keys per slab it extends right).
+__device__ inline uint32_t slab_escape32(const SlabKeys32 &k, uint32_t N, uint32_t r)
+{
+    if (r >= N - 1)
+        return kEnd;
+    uint32_t s = r + 1;
+    if (s > N - 2)
+        return N - 1 + s;
+    bool right;
+    if (s - k.base < k.m)
+        right = slab_delta32(k, N, s, s + 1) >= slab_delta32(k, N, s, s - 1);
+    else if (k.m >= 2)
+        right = true;
+    else   // one key per slab: s - 1, s and s + 1 are slabs s - 1, s and s + 1
+        right = __builtin_clz(s ^ (s + 1)) >= __builtin_clz(s ^ (s - 1));
+    return right ? s : N - 1 + s;
 }
 
 // ---- launchers (each returns the launch status) -----------------------------

@@ -410,7 +410,7 @@ __global__ __launch_bounds__(kSegThreads) void k_slab_build(
         }
     }
     __syncthreads();
-    const SlabKeys K{xch, base, slab_size, slab << 32};
+    const SlabKeys32 K{xch, (uint32_t)base, slab_size, (uint32_t)slab};
     // kScatterBatch boxes per lane at a time: their loads are all in flight
     // before the first record is written
     constexpr int kScatterBatch = 4;
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(kSegThreads) void k_slab_build(
             uint32_t li = l0 + q * kSegThreads;
             if (li < m) {
                 uint32_t p = vsrc[li];
-                uint32_t esc = karras_escape(K, N, (int64_t)(base + p));
+                uint32_t esc = slab_escape32(K, N, (uint32_t)(base + p));
                 NodeIO<TP>::put(tree, N, (uint32_t)(N - 1 + base + p), lo[q], hi[q], t0[q],
                                 t1[q], ob[q], esc);
             }

@@ -212,7 +212,6 @@ __global__ __launch_bounds__(kSegThreads) void k_karras_slabs(const uint32_t *__
     for (uint32_t k = threadIdx.x; k < m; k += blockDim.x)
         sk[k] = codes[base + k];
     __syncthreads();
-    const SlabKeys K{sk, base, slab_size, slab << 32};
     const SlabKeys32 K32{sk, (uint32_t)base, slab_size, (uint32_t)slab};
     for (uint32_t k = threadIdx.x; k < m; k += blockDim.x) {
         uint32_t i = (uint32_t)(base + k);
@@ -229,7 +228,7 @@ __global__ __launch_bounds__(kSegThreads) void k_karras_slabs(const uint32_t *__
         if (i == 0)
             parent[0] = kEnd;
         kids[i] = make_uint2(nd.left, nd.right);
-        links.put(i, nd.left, karras_escape(K, N, nd.last));
+        links.put(i, nd.left, slab_escape32(K32, N, (uint32_t)nd.last));
     }
 }
 
