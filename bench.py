@@ -46,9 +46,9 @@ BOX_RULES = {"speed": 0, "nu": 1, "ecc": 2}
 BOX_SUFFIX = {"speed": "", "nu": "_box_interval_nu", "ecc": "_box_interval_ecc"}
 
 TRAFFIC = {
-    ("sort", "fp64", "fixed"): {"fetch_kib": 2139990.0, "write_kib": 4482004.0,
+    ("sort", "fp64", "fixed"): {"fetch_kib": 2139373.0, "write_kib": 4481736.0,
                                 "source": "paper_1901_10475_amd/csrc/k_sort.hip",
-                                "sha1": "08315350322cb1e7c7962b6875935713ffc67b92"},
+                                "sha1": "7dea05c184a8bbcfc9a5af99868a81c687804af1"},
     ("refit", "fp64", "fixed"): {"fetch_kib": 2519448.0 + 376482.0,
                                  "write_kib": 3749516.0 + 101467.0,
                                  "source": "paper_1901_10475_amd/csrc/k_refit.hip",
