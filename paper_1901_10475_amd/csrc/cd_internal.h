@@ -286,39 +286,6 @@ constexpr int kMlpParams = kMlpB3 + 1;   // 4609
 constexpr int kMlpOuterThreads = 256;
 constexpr int kMlpOuterSamples = 128;    // samples per outer-product block
 
-// karras_node with 32-bit index arithmetic (N < 2^30, so lmax <= 2^30 and every
-// probe i + offset stays below 2^31; the exponential probe is formed in 64 bits).
-template <class K>
-__device__ inline KarrasNode karras_node32(const K &key, uint32_t N, uint32_t i)
-{
-    const int64_t n = N;
-    const int ii = (int)i;
-    int d = karras_delta(key, n, ii, ii + 1) >= karras_delta(key, n, ii, ii - 1) ? 1 : -1;
-    int dmin = karras_delta(key, n, ii, ii - d);
-    int lmax = 2;
-    while (karras_delta(key, n, ii, (int64_t)ii + (int64_t)lmax * d) > dmin)
-        lmax *= 2;
-    int l = 0;
-    for (int t = lmax / 2; t >= 1; t /= 2)
-        if (karras_delta(key, n, ii, ii + (l + t) * d) > dmin)
-            l += t;
-    int j = ii + l * d;
-    int dnode = karras_delta(key, n, ii, j);
-    int s = 0, t = l;
-    do {
-        t = (t + 1) >> 1;
-        if (karras_delta(key, n, ii, ii + (s + t) * d) > dnode)
-            s += t;
-    } while (t > 1);
-    int gamma = ii + s * d + (d < 0 ? -1 : 0);
-    KarrasNode nd;
-    nd.first = ii < j ? ii : j;
-    nd.last = ii < j ? j : ii;
-    nd.left = (nd.first == gamma) ? (uint32_t)(N - 1 + gamma) : (uint32_t)gamma;
-    nd.right = (nd.last == gamma + 1) ? (uint32_t)(N - 1 + gamma + 1) : (uint32_t)(gamma + 1);
-    return nd;
-}
-
 // Keys of a Karras hierarchy over time-major slabs of m leaves, key(g) =
 // slab(g) << 32 | code(g), seen from one slab whose 32-bit codes are in LDS.
 // Every comparison involves a key of that slab (the node's own position i),
@@ -330,39 +297,56 @@ __device__ inline KarrasNode karras_node32(const K &key, uint32_t N, uint32_t i)
 struct SlabKeys32 {
     const uint32_t *lds;
     uint32_t base, m, slab;
+    __device__ int delta(uint32_t N, uint32_t i, uint32_t j) const
+    {
+        if (j >= N)
+            return -1;
+        uint32_t uj = j - base;
+        if (uj < m) {
+            uint32_t a = lds[i - base], b = lds[uj];
+            return a != b ? 32 + __builtin_clz(a ^ b) : 96 + __builtin_clz(i ^ j);
+        }
+        return __builtin_clz(slab ^ (j / m));
+    }
 };
 
-__device__ inline int slab_delta32(const SlabKeys32 &k, uint32_t N, uint32_t i, uint32_t j)
-{
-    if (j >= N)
-        return -1;
-    uint32_t uj = j - k.base;
-    if (uj < k.m) {
-        uint32_t a = k.lds[i - k.base], b = k.lds[uj];
-        return a != b ? 32 + __builtin_clz(a ^ b) : 96 + __builtin_clz(i ^ j);
+// 64-bit sorted keys seen from node i (its key loaded once), in 32-bit
+// position arithmetic; equal keys compare positions (96 + clz of the 32-bit
+// XOR, i.e. 64 + clz of the 64-bit one).
+struct KeysFrom32 {
+    const uint64_t *keys;
+    uint64_t ki;
+    __device__ int delta(uint32_t N, uint32_t i, uint32_t j) const
+    {
+        if (j >= N)
+            return -1;
+        uint64_t b = keys[j];
+        return ki != b ? __builtin_clzll(ki ^ b) : 96 + __builtin_clz(i ^ j);
     }
-    return __builtin_clz(k.slab ^ (j / k.m));
-}
+};
 
-// karras_node32 over the 32-bit slab view (same node)
-__device__ inline KarrasNode karras_node_slab(const SlabKeys32 &k, uint32_t N, uint32_t i)
+// Karras (2012) node i over a view V (V::delta(N, i, j), -1 outside [0, N)),
+// in 32-bit arithmetic: a probe below 0 wraps to at least N (N < 2^31), and
+// every probe i + offset stays below 2^32.  Same node as karras_node.
+template <class V>
+__device__ inline KarrasNode karras_node_u32(const V &k, uint32_t N, uint32_t i)
 {
-    int d = slab_delta32(k, N, i, i + 1) >= slab_delta32(k, N, i, i - 1) ? 1 : -1;
+    int d = k.delta(N, i, i + 1) >= k.delta(N, i, i - 1) ? 1 : -1;
     auto at = [&](uint32_t off) { return d > 0 ? i + off : i - off; };
-    int dmin = slab_delta32(k, N, i, d > 0 ? i - 1 : i + 1);   // delta to i - d
+    int dmin = k.delta(N, i, d > 0 ? i - 1 : i + 1);   // delta to i - d
     uint32_t lmax = 2;
-    while (slab_delta32(k, N, i, at(lmax)) > dmin)
+    while (k.delta(N, i, at(lmax)) > dmin)
         lmax *= 2;
     uint32_t l = 0;
     for (uint32_t t = lmax / 2; t >= 1; t /= 2)
-        if (slab_delta32(k, N, i, at(l + t)) > dmin)
+        if (k.delta(N, i, at(l + t)) > dmin)
             l += t;
     uint32_t j = at(l);
-    int dnode = slab_delta32(k, N, i, j);
+    int dnode = k.delta(N, i, j);
     uint32_t s = 0, t = l;
     do {
         t = (t + 1) >> 1;
-        if (slab_delta32(k, N, i, at(s + t)) > dnode)
+        if (k.delta(N, i, at(s + t)) > dnode)
             s += t;
     } while (t > 1);
     int gamma = (int)i + (int)s * d + (d < 0 ? -1 : 0);
@@ -372,6 +356,20 @@ __device__ inline KarrasNode karras_node_slab(const SlabKeys32 &k, uint32_t N, u
     nd.left = (nd.first == gamma) ? (uint32_t)(N - 1 + gamma) : (uint32_t)gamma;
     nd.right = (nd.last == gamma + 1) ? (uint32_t)(N - 1 + gamma + 1) : (uint32_t)(gamma + 1);
     return nd;
+}
+
+// karras_escape over 64-bit sorted keys in 32-bit position arithmetic
+__device__ inline uint32_t keys_escape32(const uint64_t *keys, uint32_t N, uint32_t r)
+{
+    if (r >= N - 1)
+        return kEnd;
+    uint32_t s = r + 1;
+    if (s <= N - 2) {
+        KeysFrom32 k{keys, keys[s]};
+        if (k.delta(N, s, s + 1) >= k.delta(N, s, s - 1))
+            return s;
+    }
+    return N - 1 + s;
 }
 
 // karras_escape over the 32-bit slab view, for a leaf range ending at r that
@@ -387,7 +385,7 @@ __device__ inline uint32_t slab_escape32(const SlabKeys32 &k, uint32_t N, uint32
         return N - 1 + s;
     bool right;
     if (s - k.base < k.m)
-        right = slab_delta32(k, N, s, s + 1) >= slab_delta32(k, N, s, s - 1);
+        right = k.delta(N, s, s + 1) >= k.delta(N, s, s - 1);
     else if (k.m >= 2)
         right = true;
     else   // one key per slab: s - 1, s and s + 1 are slabs s - 1, s and s + 1

@@ -174,8 +174,7 @@ __global__ void k_karras(const uint64_t *__restrict__ keys, uint32_t N, uint2 *k
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i + 1 >= N)
         return;
-    KeyArray K{keys};
-    KarrasNode nd = karras_node32(K, N, i);
+    KarrasNode nd = karras_node_u32(KeysFrom32{keys, keys[i]}, N, i);
     uint32_t lev = 0;
     while ((uint64_t)(nd.first >> refit_shift(lev)) != (uint64_t)(nd.last >> refit_shift(lev)))
         ++lev;
@@ -186,10 +185,10 @@ __global__ void k_karras(const uint64_t *__restrict__ keys, uint32_t N, uint2 *k
     if (i == 0)
         parent[0] = kEnd;
     kids[i] = make_uint2(nd.left, nd.right);
-    links.put(i, nd.left, karras_escape(K, N, nd.last));
+    links.put(i, nd.left, keys_escape32(keys, N, (uint32_t)nd.last));
     if (!leaf_links)
         return;
-    links.put(N - 1 + i, 0, karras_escape(K, N, i));
+    links.put(N - 1 + i, 0, keys_escape32(keys, N, i));
     if (i == N - 2)
         links.put(2 * N - 2, 0, kEnd);
 }
@@ -217,7 +216,7 @@ __global__ __launch_bounds__(kSegThreads) void k_karras_slabs(const uint32_t *__
         uint32_t i = (uint32_t)(base + k);
         if (i + 1 >= N)
             break;
-        KarrasNode nd = karras_node_slab(K32, N, i);
+        KarrasNode nd = karras_node_u32(K32, N, i);
         uint32_t lev = 0;
         while ((uint64_t)(nd.first >> refit_shift(lev)) != (uint64_t)(nd.last >> refit_shift(lev)))
             ++lev;
