@@ -5,6 +5,7 @@
 // that the stackless walk the traversal kernel performs terminates and finds
 // the same pairs as the oracle.  It is not a fallback for any library call.
 #include <stdint.h>
+#include <vector>
 
 #include "cd_logic.h"
 
@@ -30,6 +31,43 @@ int hc_karras(const uint64_t *keys, int64_t N, uint32_t *left, uint32_t *right, 
     }
     for (int64_t i = 0; i < N; ++i)
         esc_leaf[i] = karras_escape(K, N, i);
+    return 0;
+}
+
+// The same topology through the 32-bit views the kernels use: over the 64-bit
+// keys (slab_size == 0), or over time-major slabs of slab_size keys whose
+// upper 32 bits are the slab index (codes = the low 32 bits).
+int hc_karras32(const uint64_t *keys, int64_t N, uint32_t slab_size, uint32_t *left,
+                uint32_t *right, int64_t *first, int64_t *last, uint32_t *esc_inner,
+                uint32_t *esc_leaf)
+{
+    if (N < 1 || N >= (int64_t)1 << 31)
+        return -1;
+    const uint32_t n = (uint32_t)N;
+    std::vector<uint32_t> codes;
+    if (slab_size) {
+        if (n % slab_size)
+            return -1;
+        codes.resize(n);
+        for (uint32_t i = 0; i < n; ++i)
+            codes[i] = (uint32_t)keys[i];
+    }
+    for (uint32_t i = 0; i < n; ++i) {
+        uint32_t s = slab_size ? i / slab_size : 0;
+        SlabKeys32 V{slab_size ? codes.data() + (size_t)s * slab_size : nullptr,
+                     s * slab_size, slab_size, s};
+        if (i + 1 < n) {
+            KarrasNode nd = slab_size ? karras_node_u32(V, n, i)
+                                      : karras_node_u32(KeysFrom32{keys, keys[i]}, n, i);
+            left[i] = nd.left;
+            right[i] = nd.right;
+            first[i] = nd.first;
+            last[i] = nd.last;
+            esc_inner[i] = slab_size ? slab_escape32(V, n, (uint32_t)nd.last)
+                                     : keys_escape32(keys, n, (uint32_t)nd.last);
+        }
+        esc_leaf[i] = slab_size ? slab_escape32(V, n, i) : keys_escape32(keys, n, i);
+    }
     return 0;
 }
 

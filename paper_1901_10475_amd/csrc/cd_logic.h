@@ -145,4 +145,113 @@ __host__ __device__ inline bool space_overlap(const F *alo, const F *ahi, const 
            alo[2] <= bhi[2] && blo[2] <= ahi[2];
 }
 
+// ---- 32-bit views for the Karras passes ----------------------------------------
+
+// Keys of a Karras hierarchy over time-major slabs of m leaves, key(g) =
+// slab(g) << 32 | code(g), seen from one slab whose 32-bit codes are in LDS.
+// Every comparison involves a key of that slab (the node's own position i),
+// so it is exact without the other slabs' codes: two keys of the slab share
+// their slab bits, so their common prefix is 32 plus that of their codes
+// (equal keys: 64 plus that of the 64-bit positions, 96 + clz of the 32-bit
+// XOR), and a key of another slab differs from key(i) in its slab bits, j / m.
+// 32-bit arithmetic throughout: a probe below 0 wraps to at least N (N < 2^31).
+struct SlabKeys32 {
+    const uint32_t *lds;
+    uint32_t base, m, slab;
+    __host__ __device__ int delta(uint32_t N, uint32_t i, uint32_t j) const
+    {
+        if (j >= N)
+            return -1;
+        uint32_t uj = j - base;
+        if (uj < m) {
+            uint32_t a = lds[i - base], b = lds[uj];
+            return a != b ? 32 + __builtin_clz(a ^ b) : 96 + __builtin_clz(i ^ j);
+        }
+        return __builtin_clz(slab ^ (j / m));
+    }
+};
+
+// 64-bit sorted keys seen from node i (its key loaded once), in 32-bit
+// position arithmetic; equal keys compare positions (96 + clz of the 32-bit
+// XOR, i.e. 64 + clz of the 64-bit one).
+struct KeysFrom32 {
+    const uint64_t *keys;
+    uint64_t ki;
+    __host__ __device__ int delta(uint32_t N, uint32_t i, uint32_t j) const
+    {
+        if (j >= N)
+            return -1;
+        uint64_t b = keys[j];
+        return ki != b ? __builtin_clzll(ki ^ b) : 96 + __builtin_clz(i ^ j);
+    }
+};
+
+// Karras (2012) node i over a view V (V::delta(N, i, j), -1 outside [0, N)),
+// in 32-bit arithmetic: a probe below 0 wraps to at least N (N < 2^31), and
+// every probe i + offset stays below 2^32.  Same node as karras_node.
+template <class V>
+__host__ __device__ inline KarrasNode karras_node_u32(const V &k, uint32_t N, uint32_t i)
+{
+    int d = k.delta(N, i, i + 1) >= k.delta(N, i, i - 1) ? 1 : -1;
+    auto at = [&](uint32_t off) { return d > 0 ? i + off : i - off; };
+    int dmin = k.delta(N, i, d > 0 ? i - 1 : i + 1);   // delta to i - d
+    uint32_t lmax = 2;
+    while (k.delta(N, i, at(lmax)) > dmin)
+        lmax *= 2;
+    uint32_t l = 0;
+    for (uint32_t t = lmax / 2; t >= 1; t /= 2)
+        if (k.delta(N, i, at(l + t)) > dmin)
+            l += t;
+    uint32_t j = at(l);
+    int dnode = k.delta(N, i, j);
+    uint32_t s = 0, t = l;
+    do {
+        t = (t + 1) >> 1;
+        if (k.delta(N, i, at(s + t)) > dnode)
+            s += t;
+    } while (t > 1);
+    int gamma = (int)i + (int)s * d + (d < 0 ? -1 : 0);
+    KarrasNode nd;
+    nd.first = i < j ? i : j;
+    nd.last = i < j ? j : i;
+    nd.left = (nd.first == gamma) ? (uint32_t)(N - 1 + gamma) : (uint32_t)gamma;
+    nd.right = (nd.last == gamma + 1) ? (uint32_t)(N - 1 + gamma + 1) : (uint32_t)(gamma + 1);
+    return nd;
+}
+
+// karras_escape over 64-bit sorted keys in 32-bit position arithmetic
+__host__ __device__ inline uint32_t keys_escape32(const uint64_t *keys, uint32_t N, uint32_t r)
+{
+    if (r >= N - 1)
+        return kEnd;
+    uint32_t s = r + 1;
+    if (s <= N - 2) {
+        KeysFrom32 k{keys, keys[s]};
+        if (k.delta(N, s, s + 1) >= k.delta(N, s, s - 1))
+            return s;
+    }
+    return N - 1 + s;
+}
+
+// karras_escape over the 32-bit slab view, for a leaf range ending at r that
+// ends in this slab or at the end of a later one: the next node starts at
+// s = r + 1, and when s starts another slab its direction follows from slab
+// bits alone (with two or more keys per slab it extends right).
+__host__ __device__ inline uint32_t slab_escape32(const SlabKeys32 &k, uint32_t N, uint32_t r)
+{
+    if (r >= N - 1)
+        return kEnd;
+    uint32_t s = r + 1;
+    if (s > N - 2)
+        return N - 1 + s;
+    bool right;
+    if (s - k.base < k.m)
+        right = k.delta(N, s, s + 1) >= k.delta(N, s, s - 1);
+    else if (k.m >= 2)
+        right = true;
+    else   // one key per slab: s - 1, s and s + 1 are slabs s - 1, s and s + 1
+        right = __builtin_clz(s ^ (s + 1)) >= __builtin_clz(s ^ (s - 1));
+    return right ? s : N - 1 + s;
+}
+
 } // namespace cd

@@ -221,3 +221,40 @@ def test_node_pair_traversal_reports_each_box_pair_once():
     ref = oracle.pairs(b)
     assert len(recs) == len(ref) > 0
     assert np.array_equal(np.unique(np.array(recs, np.uint32), axis=0), ref)
+
+
+def _topology(fn, keys, *extra):
+    N = len(keys)
+    out = [np.zeros(max(N - 1, 1), np.uint32), np.zeros(max(N - 1, 1), np.uint32),
+           np.zeros(max(N - 1, 1), np.int64), np.zeros(max(N - 1, 1), np.int64),
+           np.zeros(max(N - 1, 1), np.uint32), np.zeros(N, np.uint32)]
+    assert fn(_p(keys), N, *extra, *[_p(a) for a in out]) == 0
+    return out
+
+
+@pytest.mark.parametrize("seed,N,bits,slab", [(0, 2, 30, 0), (1, 1000, 8, 0), (2, 5000, 40, 0),
+                                              (3, 20000, 64, 0), (4, 3000, 4, 300),
+                                              (5, 4000, 30, 1), (6, 6000, 30, 2),
+                                              (7, 17408 * 2, 30, 17408), (8, 900, 2, 3)])
+def test_32bit_views_give_the_64bit_topology(seed, N, bits, slab):
+    """The kernels' Karras passes run in 32-bit position arithmetic, over the
+    64-bit keys or over one time-major slab's 32-bit codes (slab bits taken
+    from the position): same children, ranges and skip links as the 64-bit
+    reference, also with many equal keys and with one- and two-key slabs."""
+    L = _lib()
+    vp = ctypes.c_void_p
+    L.hc_karras32.argtypes = [vp, ctypes.c_int64, ctypes.c_uint32, vp, vp, vp, vp, vp, vp]
+    rng = np.random.default_rng(seed)
+    if slab:
+        codes = rng.integers(0, 1 << bits, N, dtype=np.uint64) if bits < 64 else \
+            rng.integers(0, 1 << 30, N, dtype=np.uint64)
+        codes = np.sort(codes.reshape(N // slab, slab), axis=1).ravel()
+        keys = (np.repeat(np.arange(N // slab, dtype=np.uint64), slab) << np.uint64(32)) | codes
+    else:
+        hi = (1 << bits) - 1 if bits < 64 else (1 << 63) - 1
+        keys = np.sort(rng.integers(0, hi, N, dtype=np.uint64, endpoint=True))
+    keys = np.ascontiguousarray(keys)
+    ref = _topology(L.hc_karras, keys)
+    got = _topology(L.hc_karras32, keys, slab)
+    for a, b in zip(ref, got):
+        assert np.array_equal(a, b)
