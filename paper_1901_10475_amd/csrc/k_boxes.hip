@@ -400,7 +400,10 @@ hipError_t launch_boxes_uniform(const ObjConst *oc, const ObjSinus *os, uint32_t
 {
     if (n == 0 || K == 0)
         return hipSuccess;
-    uint32_t chunk = 16;
+    // 8 consecutive intervals per thread (warm-started Kepler solves) measured
+    // best: 0.73 ms for the 60.65 M boxes of the tracked hour against 0.79 ms
+    // with 16 and 0.82-0.83 ms with 4 or 32
+    uint32_t chunk = 8;
     while ((K + chunk - 1) / chunk > 65535u)
         chunk *= 2;
     dim3 grid(blocks_for(n, 128), (K + chunk - 1) / chunk);
