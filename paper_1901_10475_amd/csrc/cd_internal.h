@@ -433,7 +433,7 @@ struct SeedSink {
     }
 };
 constexpr int kSeedStage = 256;  // LDS-staged seeds per workgroup before a flush
-constexpr int kRefitLevelThreads = 128;  // queue levels: few climbs per block
+constexpr int kRefitLevelThreads = 256;  // queue levels (measured: 64, 128, 256, 512, 1024)
 
 struct RefitLists {
     uint32_t *items;            // [slots][kRefitListCap]
