@@ -49,8 +49,8 @@ TRAFFIC = {
     ("sort", "fp64", "fixed"): {"fetch_kib": 2139373.0, "write_kib": 4481736.0,
                                 "source": "paper_1901_10475_amd/csrc/k_sort.hip",
                                 "sha1": "7dea05c184a8bbcfc9a5af99868a81c687804af1"},
-    ("refit", "fp64", "fixed"): {"fetch_kib": 2519448.0 + 376482.0,
-                                 "write_kib": 3749516.0 + 101467.0,
+    ("refit", "fp64", "fixed"): {"fetch_kib": 2519376.0 + 356730.0,
+                                 "write_kib": 3749515.0 + 101497.0,
                                  "source": "paper_1901_10475_amd/csrc/k_refit.hip",
                                  "sha1": "9f9580ffa1721e34d216ae28a435ec66ee627275"},
 }
