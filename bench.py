@@ -52,7 +52,7 @@ TRAFFIC = {
     ("refit", "fp64", "fixed"): {"fetch_kib": 2519376.0 + 356730.0,
                                  "write_kib": 3749515.0 + 101497.0,
                                  "source": "paper_1901_10475_amd/csrc/k_refit.hip",
-                                 "sha1": "9f9580ffa1721e34d216ae28a435ec66ee627275"},
+                                 "sha1": "b4ff827f77f607f203d985b3231e53215c717fc9"},
 }
 
 

@@ -461,7 +461,8 @@ hipError_t launch_karras(const uint64_t *keys, uint32_t N, uint2 *kids, const Li
 // slab path (time-major slabs of slab_size leaves, slab_size <= kSegCap); the
 // leaf links are written by the slab build
 hipError_t launch_karras_slabs(const uint32_t *codes, uint32_t N, uint32_t slab_size, uint2 *kids,
-                               const LinkSink &links, uint32_t *parent, uint8_t *clev, hipStream_t s);
+                               const LinkSink &links, uint32_t *parent, uint8_t *clev,
+                               hipStream_t s);
 // idx == nullptr: the leaf records are already written (slab build).
 hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision, uint32_t N,
                         const uint32_t *idx, const uint32_t *parent, const uint2 *kids,

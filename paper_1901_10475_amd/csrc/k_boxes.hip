@@ -214,9 +214,11 @@ __device__ inline void object_run(const ObjConst &c, const ObjSinus *os, uint32_
 }
 
 template <int PREC, int RULE>
-__global__ __launch_bounds__(128) void k_boxes_uniform(const ObjConst *__restrict__ oc, const ObjSinus *__restrict__ os,
-                                uint32_t n, uint32_t K, uint32_t dt, uint32_t T, double tick_s,
-                                double half_thr, uint32_t chunk, BoxOut out)
+__global__ __launch_bounds__(128) void k_boxes_uniform(const ObjConst *__restrict__ oc,
+                                                       const ObjSinus *__restrict__ os,
+                                                       uint32_t n, uint32_t K, uint32_t dt,
+                                                       uint32_t T, double tick_s, double half_thr,
+                                                       uint32_t chunk, BoxOut out)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)

@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
     } else if (t <= (uint32_t)kPushLevels) {
         uint32_t c = pcnt[t - 1] < (unsigned)kPushStage ? pcnt[t - 1] : (unsigned)kPushStage;
         if (c)
-            res = atomicAdd(&L.count[L.base[t] + (c0 >> refit_shift(t))], c);
+            res = atomicAdd(&L.count[L.base[t] + (uint32_t)((uint64_t)c0 >> refit_shift(t))], c);
     }
     // inner nodes completed here (both children arrived) go out in one pass
     if (TP == CD_FP64) {
@@ -276,7 +276,8 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
         uint32_t p = c0 + t;
         if (p + 1 < N && cnt[t] == 2) {
             u32x2 l = {kid[t].x, esc_w[0]};
-            __builtin_nontemporal_store(l, (u32x2 *)((Link *)((Box32 *)tree + (2 * (size_t)N - 1)) + p));
+            Link *lrec = (Link *)((Box32 *)tree + (2 * (size_t)N - 1));
+            __builtin_nontemporal_store(l, (u32x2 *)(lrec + p));
         }
     }
     if (t == 0)
@@ -292,7 +293,7 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
     }
     for (int lv = 0; lv < kPushLevels; ++lv) {
         uint32_t c = pcnt[lv] < (unsigned)kPushStage ? pcnt[lv] : (unsigned)kPushStage;
-        uint32_t slot = L.base[lv + 1] + (c0 >> refit_shift((uint32_t)lv + 1));
+        uint32_t slot = L.base[lv + 1] + (uint32_t)((uint64_t)c0 >> refit_shift((uint32_t)lv + 1));
         for (uint32_t k = t; k < c; k += blockDim.x) {
             uint32_t at = pbase[lv] + k;
             if (at < (unsigned)kRefitListCap)
@@ -462,11 +463,11 @@ hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision,
     for (uint32_t k = 1; k <= levels && e == hipSuccess; ++k) {
         uint32_t nb = (uint32_t)(((uint64_t)N + (1ull << refit_shift(k)) - 1) >> refit_shift(k));
         if (tree_precision == CD_FP64)
-            k_refit_level<CD_FP64><<<nb, kRefitLevelThreads, 0, s>>>(N, k, parent, kids, links, clev,
-                                                              tree, arrive, L, seeds, err);
+            k_refit_level<CD_FP64><<<nb, kRefitLevelThreads, 0, s>>>(
+                N, k, parent, kids, links, clev, tree, arrive, L, seeds, err);
         else
-            k_refit_level<CD_FP32><<<nb, kRefitLevelThreads, 0, s>>>(N, k, parent, kids, links, clev,
-                                                              tree, arrive, L, seeds, err);
+            k_refit_level<CD_FP32><<<nb, kRefitLevelThreads, 0, s>>>(
+                N, k, parent, kids, links, clev, tree, arrive, L, seeds, err);
         e = hipGetLastError();
     }
     return e;

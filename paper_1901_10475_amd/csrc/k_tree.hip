@@ -251,7 +251,8 @@ hipError_t launch_karras(const uint64_t *keys, uint32_t N, uint2 *kids, const Li
 }
 
 hipError_t launch_karras_slabs(const uint32_t *codes, uint32_t N, uint32_t slab_size, uint2 *kids,
-                               const LinkSink &links, uint32_t *parent, uint8_t *clev, hipStream_t s)
+                               const LinkSink &links, uint32_t *parent, uint8_t *clev,
+                               hipStream_t s)
 {
     if (N <= 1 || slab_size == 0 || (int64_t)slab_size > kSegCap)
         return hipErrorInvalidValue;
