@@ -268,7 +268,7 @@ int cd_query_pairs_async(const cd_tree *tree, cd_pair *out, int64_t capacity,
  * defaults in brackets. */
 typedef struct {
     uint32_t expand_blocks;   /* workgroups per node-pair level, 64..65536 [2048] */
-    uint32_t expand_threads;  /* lanes per node-pair workgroup: 64, 128 or 256 [256] */
+    uint32_t expand_threads;  /* lanes per node-pair workgroup: 64 .. 1024, a power of 2 [256] */
     uint32_t walk_threads;    /* lanes per per-leaf-walk workgroup: 64, 128 or 256 [256] */
     uint32_t mode;            /* 0 = node pairs, per-leaf walk as fallback; 1 = per-leaf
                                  walk only [0] */

@@ -27,7 +27,7 @@ DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "paper_1901_1047
 def candidates():
     out = []
     for blocks in (512, 1024, 2048, 4096, 8192):
-        for threads in (128, 256):
+        for threads in (128, 256, 512):
             out.append({"mode": 0, "expand_blocks": blocks, "expand_threads": threads,
                         "walk_threads": 256})
     for walk in (64, 128, 256):

@@ -988,8 +988,9 @@ int cd_set_tuning(const cd_tuning *t)
     cd_tuning v = {2048, 256, 256, 0, 96};
     if (t) {
         auto lanes_ok = [](uint32_t x) { return x == 0 || x == 64 || x == 128 || x == 256; };
+        auto expand_ok = [&](uint32_t x) { return lanes_ok(x) || x == 512 || x == 1024; };
         if ((t->expand_blocks && (t->expand_blocks < 64 || t->expand_blocks > 65536)) ||
-            !lanes_ok(t->expand_threads) || !lanes_ok(t->walk_threads) || t->mode > 1 ||
+            !expand_ok(t->expand_threads) || !lanes_ok(t->walk_threads) || t->mode > 1 ||
             t->max_levels > (uint32_t)kExpandMaxLevels)
             return fail(CD_E_INVALID, "tuning field out of range");
         if (t->expand_blocks)

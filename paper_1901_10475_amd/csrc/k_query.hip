@@ -226,7 +226,7 @@ __device__ inline bool load_side(const void *tree, const uint2 *kids, uint32_t N
 }
 
 template <int TP>
-__global__ __launch_bounds__(256) void k_expand(const void *__restrict__ tree,
+__global__ __launch_bounds__(1024) void k_expand(const void *__restrict__ tree,
                                                 const uint2 *__restrict__ kids, uint32_t N,
                                                 const uint2 *__restrict__ in,
                                                 const unsigned int *n_in, uint32_t in_cap,

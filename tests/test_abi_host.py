@@ -192,3 +192,22 @@ def test_band_argument_errors_before_any_launch():
                                   None) == cd.CD_E_INVALID
     assert L.cd_canonical_records(fake, 3, 10, 10, fake, ctypes.byref(cnt), fake, 8,
                                   None) == cd.CD_E_WORKSPACE
+
+
+def test_tuning_ranges():
+    """Launch shapes: node-pair workgroups of 64 to 1024 lanes (powers of 2),
+    per-leaf-walk workgroups of 64, 128 or 256; anything else is rejected and
+    changes nothing."""
+    import paper_1901_10475_amd as cd
+    cd.cd_set_tuning(None)
+    base = cd.cd_get_tuning()
+    for bad in ({"expand_threads": 384}, {"expand_threads": 2048}, {"walk_threads": 512},
+                {"expand_blocks": 32}, {"mode": 2}):
+        with pytest.raises(cd.CDError):
+            cd.cd_set_tuning(bad)
+        assert cd.cd_get_tuning() == base
+    for ok in (512, 1024, 64):
+        cd.cd_set_tuning({"expand_threads": ok})
+        assert cd.cd_get_tuning()["expand_threads"] == ok
+    cd.cd_set_tuning(None)
+    assert cd.cd_get_tuning() == base
