@@ -58,7 +58,9 @@ def test_async_query_equals_eager(name, sc, heur):
     say("  records", P)
     assert P > 0
     for tun in (None, {"mode": 1}, {"mode": 1, "walk_threads": 64}, {"max_levels": 1},
-                {"expand_blocks": 64, "expand_threads": 64}):
+                {"expand_blocks": 64, "expand_threads": 64},
+                {"expand_blocks": 256, "expand_threads": 512},
+                {"expand_blocks": 64, "expand_threads": 1024}):
         for cap in (P, P + 1, 2 * P + 17):
             got, c, s = _async(bp, cap, tun)
             assert s == 0 and c == P, (tun, cap, c, s)
