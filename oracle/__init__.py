@@ -78,6 +78,8 @@ def lib():
                                       ctypes.c_double, ctypes.c_int, _dp, _dp]
         L.or_pairs.restype = ctypes.c_int64
         L.or_pairs.argtypes = [ctypes.c_int64, _dp, _dp, _dp, _dp, _dp, _u32pp]
+        L.or_pairs_bucketed.restype = ctypes.c_int64
+        L.or_pairs_bucketed.argtypes = [ctypes.c_int64, _dp, _dp, _dp, _dp, _dp, _u32pp]
         L.or_pairs_of.restype = ctypes.c_int64
         L.or_pairs_of.argtypes = [ctypes.c_int64, _dp, _dp, _dp, _dp, _dp,
                                   ctypes.c_int64, _dp, _u32pp]
@@ -115,6 +117,8 @@ def lib():
         L.or_free.argtypes = [ctypes.c_void_p]
         L.or_num_threads.restype = ctypes.c_int
         L.or_num_threads.argtypes = []
+        L.or_set_num_threads.restype = None
+        L.or_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -254,6 +258,31 @@ def pairs(b):
     return _take_records(n, out, 4)
 
 
+def pairs_bucketed(b):
+    """The same canonical set as pairs(b), testing only box pairs whose time
+    tags overlap (a t0-ordered sweep with a t1-ordered active list; with a
+    uniform step, all pairs within each time slab)."""
+    arrs = _box_args(b)
+    out = _u32p()
+    n = lib().or_pairs_bucketed(len(b.t0), *[_ptr(x) for x in arrs], ctypes.byref(out))
+    return _take_records(n, out, 4)
+
+
+def window(b, ta, tb):
+    """The boxes whose time tags meet the ticks [ta, tb).  Two time intervals
+    that meet each other and both meet [ta, tb) have a common point inside it
+    (intervals on a line), so pairs(window(b, ta, tb)) is exactly the records
+    of pairs(b) whose [t_lo, t_hi) meets [ta, tb)."""
+    keep = np.nonzero((b.t0 < tb) & (b.t1 > ta))[0]
+    return b.take(keep)
+
+
+def records_in_window(rec, ta, tb):
+    """Rows of a record list whose [t_lo, t_hi) meets the ticks [ta, tb)."""
+    rec = np.asarray(rec).reshape(-1, 4)
+    return rec[(rec[:, 2] < tb) & (rec[:, 3] > ta)]
+
+
 def pairs_of(b, sample):
     """Canonical records that involve at least one sampled box."""
     arrs = _box_args(b)
@@ -365,3 +394,8 @@ def dt_heuristic(elements, tick_s, max_disp_km, T, mu=MU_EARTH):
 
 def num_threads():
     return int(lib().or_num_threads())
+
+
+def set_num_threads(n):
+    """OpenMP threads of later oracle calls."""
+    lib().or_set_num_threads(int(n))

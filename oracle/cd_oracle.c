@@ -524,6 +524,179 @@ int64_t or_time_overlapping_pairs(int64_t N, const uint32_t *t0,
     return c;
 }
 
+/* ---- the bucketed driver: same set, time-overlapping pairs only ---------- */
+
+/* The pair test above fails at once for two boxes whose time tags do not
+ * overlap, so leaving those pairs out cannot change the set.  The sweep
+ * below visits the boxes in order of t0 (ties by index).  A box can overlap
+ * in time only boxes visited before it whose t1 exceeds its t0, or boxes
+ * visited after it (which find it the same way), so each overlapping pair is
+ * tested once, by its later box.  The earlier boxes that may still overlap
+ * form the active list, kept in a binary heap ordered by t1: before a block
+ * of visits the boxes whose t1 is at most the block's first t0 leave it, and
+ * they can never overlap a later box (later boxes start no earlier).
+ *
+ * Visits are taken in blocks of consecutive boxes (a block ends where t0
+ * changes, once it holds at least OR_BLOCK_MIN boxes).  Within a block each
+ * box is tested against the active list at the block's start and against the
+ * boxes of the block visited before it.  With a uniform step (every box of
+ * time slab k tagged [k dt, (k + 1) dt)) every slab is one block whose active
+ * list is empty, so the driver is "all pairs within each slab"; with
+ * per-object steps it is a sweep in t0 order over an active list in t1
+ * order.  The full pair test is still applied to every tested pair. */
+#define OR_BLOCK_MIN 1024
+
+static int cmp_u64(const void *pa, const void *pb)
+{
+    uint64_t a = *(const uint64_t *)pa, b = *(const uint64_t *)pb;
+    return a < b ? -1 : (a > b ? 1 : 0);
+}
+
+typedef struct {
+    uint32_t *box; /* box indices; heap order by t1 */
+    int64_t n, cap;
+} or_heap;
+
+static void heap_push(or_heap *h, const uint32_t *t1, uint32_t b)
+{
+    if (h->n == h->cap) {
+        h->cap = h->cap ? 2 * h->cap : 1024;
+        h->box = (uint32_t *)realloc(h->box, (size_t)h->cap * sizeof(uint32_t));
+    }
+    int64_t c = h->n++;
+    h->box[c] = b;
+    while (c > 0) {
+        int64_t p = (c - 1) / 2;
+        if (t1[h->box[p]] <= t1[h->box[c]])
+            break;
+        uint32_t tmp = h->box[p];
+        h->box[p] = h->box[c];
+        h->box[c] = tmp;
+        c = p;
+    }
+}
+
+static void heap_pop(or_heap *h, const uint32_t *t1)
+{
+    h->box[0] = h->box[--h->n];
+    int64_t c = 0;
+    for (;;) {
+        int64_t l = 2 * c + 1, r = l + 1, m = c;
+        if (l < h->n && t1[h->box[l]] < t1[h->box[m]])
+            m = l;
+        if (r < h->n && t1[h->box[r]] < t1[h->box[m]])
+            m = r;
+        if (m == c)
+            break;
+        uint32_t tmp = h->box[m];
+        h->box[m] = h->box[c];
+        h->box[c] = tmp;
+        c = m;
+    }
+}
+
+/* One box, copied into visiting order so that the tests of a block read
+ * consecutive memory. */
+typedef struct {
+    double lo[3], hi[3];
+    uint32_t t0, t1, obj, pad;
+} or_box;
+
+/* The test of boxes_overlap plus the different-object condition, on copies.
+ * The conditions are taken in the order that rejects most pairs soonest
+ * (first axis, then time, object, other axes); they are all required, so the
+ * order does not change the result. */
+static void test_and_emit(or_vec *out, const or_box *a, const or_box *b)
+{
+    if (!(a->lo[0] <= b->hi[0] && b->lo[0] <= a->hi[0]))
+        return;
+    if (!(a->t0 < b->t1 && b->t0 < a->t1) || a->obj == b->obj)
+        return;
+    for (int d = 1; d < 3; ++d)
+        if (!(a->lo[d] <= b->hi[d] && b->lo[d] <= a->hi[d]))
+            return;
+    vec_push(out, a->obj < b->obj ? a->obj : b->obj, a->obj < b->obj ? b->obj : a->obj,
+             a->t0 > b->t0 ? a->t0 : b->t0, a->t1 < b->t1 ? a->t1 : b->t1);
+}
+
+int64_t or_pairs_bucketed(int64_t N, const double *lo, const double *hi,
+                          const uint32_t *t0, const uint32_t *t1, const uint32_t *obj,
+                          uint32_t **out)
+{
+    int nt = or_num_threads();
+    or_vec *parts = (or_vec *)calloc((size_t)nt, sizeof(or_vec));
+    /* visiting order: (t0, index) ascending */
+    uint64_t *order = (uint64_t *)malloc((size_t)(N > 0 ? N : 1) * sizeof(uint64_t));
+    for (int64_t b = 0; b < N; ++b)
+        order[b] = ((uint64_t)t0[b] << 32) | (uint64_t)b;
+    qsort(order, (size_t)N, sizeof(uint64_t), cmp_u64);
+    or_box *v = (or_box *)malloc((size_t)(N > 0 ? N : 1) * sizeof(or_box));
+    uint32_t *t1v = (uint32_t *)malloc((size_t)(N > 0 ? N : 1) * sizeof(uint32_t));
+    for (int64_t k = 0; k < N; ++k) {
+        int64_t b = (int64_t)(order[k] & 0xFFFFFFFFu);
+        for (int d = 0; d < 3; ++d) {
+            v[k].lo[d] = lo[3 * b + d];
+            v[k].hi[d] = hi[3 * b + d];
+        }
+        v[k].t0 = t0[b];
+        v[k].t1 = t1v[k] = t1[b];
+        v[k].obj = obj[b];
+        v[k].pad = 0;
+    }
+    free(order);
+
+    or_heap active = { 0, 0, 0 }; /* visiting positions, heap order by t1 */
+    or_box *act = NULL;
+    int64_t act_cap = 0;
+    int64_t begin = 0;
+    while (begin < N) {
+        int64_t end = begin + 1;
+        while (end < N && (end - begin < OR_BLOCK_MIN || v[end].t0 == v[end - 1].t0))
+            ++end;
+        while (active.n > 0 && t1v[active.box[0]] <= v[begin].t0)
+            heap_pop(&active, t1v);
+        int64_t nact = active.n;
+        if (nact > act_cap) {
+            act_cap = 2 * nact;
+            act = (or_box *)realloc(act, (size_t)act_cap * sizeof(or_box));
+        }
+        for (int64_t q = 0; q < nact; ++q)
+            act[q] = v[active.box[q]];
+#pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t k = begin; k < end; ++k) {
+#ifdef _OPENMP
+            or_vec *mine = &parts[omp_get_thread_num()];
+#else
+            or_vec *mine = &parts[0];
+#endif
+            for (int64_t q = 0; q < nact; ++q)
+                test_and_emit(mine, &v[k], &act[q]);
+            for (int64_t q = begin; q < k; ++q)
+                test_and_emit(mine, &v[k], &v[q]);
+        }
+        for (int64_t k = begin; k < end; ++k)
+            heap_push(&active, t1v, (uint32_t)k);
+        begin = end;
+    }
+    free(active.box);
+    free(act);
+    free(t1v);
+    free(v);
+    int64_t m = canonical(parts, nt, out);
+    free(parts);
+    return m;
+}
+
+void or_set_num_threads(int nthreads)
+{
+#ifdef _OPENMP
+    if (nthreads > 0)
+        omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Alg. Brute Force                                                          */
 /* ------------------------------------------------------------------------ */

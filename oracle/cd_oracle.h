@@ -76,6 +76,12 @@ int64_t or_pairs(int64_t N, const double *lo, const double *hi,
 int64_t or_pairs_of(int64_t N, const double *lo, const double *hi,
                     const uint32_t *t0, const uint32_t *t1, const uint32_t *obj,
                     int64_t ns, const int64_t *sample, uint32_t **out);
+/* The same canonical set as or_pairs, testing only box pairs whose time tags
+ * overlap: a sweep in t0 order with an active list in t1 order (with a
+ * uniform step, all pairs within each time slab).  N < 2^32. */
+int64_t or_pairs_bucketed(int64_t N, const double *lo, const double *hi,
+                          const uint32_t *t0, const uint32_t *t1, const uint32_t *obj,
+                          uint32_t **out);
 /* Brute-force-equivalent test count: different-object box pairs whose time
  * tags overlap (the work the plain definition cannot skip). */
 int64_t or_time_overlapping_pairs(int64_t N, const uint32_t *t0,
@@ -102,6 +108,8 @@ void or_dt_heuristic(int64_t n, const double *el, double mu, double tick_s,
 
 void or_free(void *p);
 int or_num_threads(void);
+/* OpenMP threads of the later calls (<= 0 leaves the setting unchanged) */
+void or_set_num_threads(int nthreads);
 
 /* ---- bulk interval refinement (resolveCollisions' halving, in bulk) ---- */
 /* rec: R records (i, j, t_lo, t_hi) relative to start; rule as or_boxes;

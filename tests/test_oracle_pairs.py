@@ -185,3 +185,97 @@ def test_recall_against_brute_force_small_catalog():
     hit = {(int(i), int(j)) for _, i, j in w.tolist()}
     for i, j, tc in planted_in:
         assert (i, j) in hit
+
+
+# ---- the bucketed driver: the same set as the literal one ------------------
+
+def _both(b):
+    lit = oracle.pairs(b)
+    buck = oracle.pairs_bucketed(b)
+    assert np.array_equal(lit, buck), (len(lit), len(buck))
+    return lit
+
+
+def test_bucketed_equals_literal_on_box_soups():
+    """Caller-built boxes with ragged tags (overlapping intervals of lengths
+    1..max_len, so the active list carries boxes across blocks), in all five
+    geometries and sizes around the block size."""
+    for kind in ("uniform", "identical", "disjoint", "line", "huge"):
+        for N in (0, 1, 2, 3, 63, 64, 65, 1023, 1024, 1025, 2049, 5000):
+            if kind == "identical" and N > 2049:
+                continue
+            for max_len, T in ((1, 40), (12, 400), (300, 500)):
+                lo, hi, t0, t1, obj = catalog.random_boxes(N + 7 * max_len, N, max(2, N // 4),
+                                                           extent=200, size=6, T=T,
+                                                           max_len=max_len, kind=kind)
+                _both(_soup(lo, hi, t0, t1, obj))
+
+
+def test_bucketed_equals_literal_on_orbit_boxes():
+    """Uniform steps (slabs), per-object steps (sweep), windows, the T + 1
+    sentinel, and dt not dividing T."""
+    sc = catalog.scaled(catalog.small_leo(seed=41, n=700, planted=12), horizon_ticks=61_000)
+    b = oracle.boxes(sc.elements, 10_000, sc.horizon_ticks, TICK, sc.threshold_km)
+    assert len(_both(b)) > 0
+    dt = oracle.dt_heuristic(sc.elements, TICK, 5.0, sc.horizon_ticks)
+    b = oracle.boxes(sc.elements, dt, sc.horizon_ticks, TICK, sc.threshold_km)
+    assert len(_both(b)) > 0
+    b = oracle.boxes(sc.elements, dt * 7, sc.horizon_ticks, TICK, sc.threshold_km,
+                     start=1_234_567)
+    assert len(_both(b)) > 0
+    # mixed populations: per-object steps from 1 tick to beyond T
+    rng = np.random.default_rng(8)
+    el = catalog.tracked_population(rng, 500)
+    dt = rng.integers(1, 90_000, 500).astype(np.uint32)
+    dt[:40] = rng.integers(1, 50, 40)
+    b = oracle.boxes(el, dt, 70_000, TICK, 200.0)
+    assert len(_both(b)) > 0
+
+
+def test_bucketed_equals_literal_on_hand_cases():
+    el = np.array([[6800.0, 0.001, 0.9, 0.2, 0.3, 0.4]] * 2)
+    assert _both(oracle.boxes(el, 10_000, 25_000, TICK, 1.0)).tolist() == \
+        [[0, 1, 0, 10000], [0, 1, 10000, 20000], [0, 1, 20000, 25001]]
+    assert _both(oracle.boxes(el, 1_000, 0, TICK, 1.0)).tolist() == [[0, 1, 0, 1]]
+    b = _soup([[0, 0, 0], [1, 0, 0]], [[1, 1, 1], [2, 1, 1]], [0, 0], [5, 5], [0, 1])
+    assert _both(b).tolist() == [[0, 1, 0, 5]]
+    lo = [[0, 0, 0]] * 2
+    hi = [[1, 1, 1]] * 2
+    assert len(_both(_soup(lo, hi, [0, 10], [10, 20], [0, 1]))) == 0
+    assert _both(_soup(lo, hi, [0, 9], [10, 20], [3, 1])).tolist() == [[1, 3, 9, 10]]
+    assert len(_both(_soup(lo, hi, [0, 0], [10, 10], [2, 2]))) == 0
+    assert len(_both(oracle.boxes(np.zeros((0, 6)), 10, 100, TICK, 1.0))) == 0
+    assert len(_both(oracle.boxes(np.array([[7000.0, 0, 0, 0, 0, 0]]), 10, 100, TICK,
+                                  1.0))) == 0
+
+
+def test_bucketed_result_does_not_depend_on_threads():
+    lo, hi, t0, t1, obj = catalog.random_boxes(9, 3000, 400, extent=60, size=8, T=60,
+                                               max_len=20)
+    b = _soup(lo, hi, t0, t1, obj)
+    ref = oracle.pairs_bucketed(b)
+    nt = oracle.num_threads()
+    try:
+        oracle.set_num_threads(1)
+        assert np.array_equal(oracle.pairs_bucketed(b), ref)
+        oracle.set_num_threads(3)
+        assert np.array_equal(oracle.pairs_bucketed(b), ref)
+    finally:
+        oracle.set_num_threads(nt)
+    assert np.array_equal(oracle.pairs(b), ref)
+
+
+def test_time_window_restriction_is_exact():
+    """The records of the boxes that meet [ta, tb) are exactly the records of
+    all boxes whose interval meets [ta, tb) (the reduction the full-size GPU
+    tests use to check long horizons window by window)."""
+    sc = catalog.scaled(catalog.tracked_hour(seed=17, planted=6), n=900, horizon_ticks=40_000)
+    dt = oracle.dt_heuristic(sc.elements, TICK, 5.0, sc.horizon_ticks) * 3
+    b = oracle.boxes(sc.elements, dt, sc.horizon_ticks, TICK, 400.0)
+    full = oracle.pairs_bucketed(b)
+    assert len(full) > 1000 and np.array_equal(full, oracle.pairs(b))
+    for ta, tb in ((0, 1), (0, 5_000), (12_345, 12_346), (17_000, 23_500), (39_000, 40_001)):
+        got = oracle.pairs_bucketed(oracle.window(b, ta, tb))
+        want = oracle.records_in_window(full, ta, tb)
+        assert np.array_equal(got, want), (ta, tb)
+        assert len(want) > 0
