@@ -8,10 +8,12 @@ that sequence once into a hipGraph (``cd_graph_*``); a replay is one launch
 for the whole batch, with no host synchronisation inside it.
 
 The scenarios run in order and share one set of box, tree and workspace
-buffers sized for the largest; each keeps its own output list, record count
-and status word on the device.  Output capacities come from one eager pass
-(``calibrate``); a replay whose status reports exceeded capacity is repeated
-eagerly for that scenario by ``results``.  Launch shapes can differ per
+buffers sized for the largest (``shared_buffers=False`` gives every scenario
+its own boxes and tree instead, so that they outlive the replay); each keeps
+its own output list, record count and status word on the device.  Output
+capacities come from one eager pass (``calibrate``); a replay whose status
+reports exceeded capacity is repeated eagerly for that scenario by
+``results``.  Launch shapes can differ per
 scenario (``tunings``): they are read while the graph is recorded.
 """
 import ctypes
@@ -52,7 +54,7 @@ class _Tree:
 
 class BatchRunner:
     def __init__(self, scenarios, box_precision=CD_FP64, tree_precision=CD_FP64,
-                 margin=1.25, min_capacity=4096, device="cuda"):
+                 margin=1.25, min_capacity=4096, device="cuda", shared_buffers=True):
         self.sc = list(scenarios)
         self.box_precision, self.tree_precision = box_precision, tree_precision
         self.margin, self.min_capacity = margin, min_capacity
@@ -69,17 +71,28 @@ class BatchRunner:
             self.counts.append(s.n * K)
         Nmax = max(self.counts)
         ft = torch.float64 if box_precision == CD_FP64 else torch.float32
-        self.arrays = (torch.empty((3, Nmax), dtype=ft, device=device),
-                       torch.empty((3, Nmax), dtype=ft, device=device),
-                       torch.empty(Nmax, dtype=torch.int32, device=device),
-                       torch.empty(Nmax, dtype=torch.int32, device=device),
-                       torch.empty(Nmax, dtype=torch.int32, device=device),
-                       torch.empty(Nmax, dtype=torch.int32, device=device))
-        self.tree_mem = _bytes(lib().cd_tree_bytes(Nmax, tree_precision), device)
+
+        def box_arrays(N):
+            return (torch.empty((3, N), dtype=ft, device=device),
+                    torch.empty((3, N), dtype=ft, device=device),
+                    torch.empty(N, dtype=torch.int32, device=device),
+                    torch.empty(N, dtype=torch.int32, device=device),
+                    torch.empty(N, dtype=torch.int32, device=device),
+                    torch.empty(N, dtype=torch.int32, device=device))
+
+        if shared_buffers:
+            arrays = box_arrays(Nmax)
+            tree_mem = _bytes(lib().cd_tree_bytes(Nmax, tree_precision), device)
+            self.arrays = [arrays] * len(self.sc)
+            self.tree_mems = [tree_mem] * len(self.sc)
+        else:
+            self.arrays = [box_arrays(N) for N in self.counts]
+            self.tree_mems = [_bytes(lib().cd_tree_bytes(N, tree_precision), device)
+                              for N in self.counts]
         self.ws_boxes = _bytes(max(lib().cd_build_boxes_ws(s.n) for s in self.sc), device)
         self.ws_tree = _bytes(lib().cd_build_tree_ws(Nmax), device)
-        self.boxes = [_Boxes(self.arrays, N, box_precision) for N in self.counts]
-        self.trees = [_Tree(self.tree_mem, N, tree_precision) for N in self.counts]
+        self.boxes = [_Boxes(a, N, box_precision) for a, N in zip(self.arrays, self.counts)]
+        self.trees = [_Tree(m, N, tree_precision) for m, N in zip(self.tree_mems, self.counts)]
         S = len(self.sc)
         self.count_dev = torch.zeros(S, dtype=torch.int64, device=device)
         self.status_dev = torch.zeros(S, dtype=torch.int32, device=device)
@@ -89,6 +102,13 @@ class BatchRunner:
         self.graph = None
         self.stream = torch.cuda.Stream(device=device)
         self.tunings = [None] * S
+
+    def box_arrays(self, k):
+        """(lo [3,N], hi [3,N], t0, t1, obj) of scenario k's boxes as last built
+        (with shared buffers, only the scenario built last still holds them)."""
+        lo, hi, t0, t1, obj, _ = self.arrays[k]
+        N = self.counts[k]
+        return lo[:, :N], hi[:, :N], t0[:N], t1[:N], obj[:N]
 
     # -- one scenario, eager ------------------------------------------------------
     def _build(self, k):

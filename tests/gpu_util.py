@@ -56,3 +56,36 @@ def records_of_boxes(recs, obj, t0, t1, sample):
         o, a, b = obj[s], t0[s], t1[s]
         keep |= ((recs[:, 0] == o) | (recs[:, 1] == o)) & (recs[:, 2] >= a) & (recs[:, 2] < b)
     return recs[keep]
+
+
+def device_boxes_to_oracle(boxes, idx=None, lo_hi=None):
+    """Boxes of a device box set (``Boxes`` or the batch runner's arrays) as
+    oracle.Boxes with float64 bounds: all of them, the index tensor idx, or
+    the range lo_hi = (a, b)."""
+    import oracle
+    lo, hi, t0, t1, obj = boxes
+    if lo_hi is not None:
+        a, b = lo_hi
+        sel = slice(a, b)
+        take = lambda x: x[..., sel]
+    elif idx is not None:
+        take = lambda x: x.index_select(x.dim() - 1, idx)
+    else:
+        take = lambda x: x
+    u = lambda t: take(t).cpu().numpy().view(np.uint32)
+    f = lambda t: np.ascontiguousarray(take(t).T.double().cpu().numpy())
+    return oracle.Boxes(f(lo), f(hi), u(t0), u(t1), u(obj))
+
+
+def arrays_of(bp_boxes):
+    """(lo [3,N], hi [3,N], t0, t1, obj) device tensors cut to the box count."""
+    N = bp_boxes.count
+    return (bp_boxes.lo[:, :N], bp_boxes.hi[:, :N], bp_boxes.t0[:N], bp_boxes.t1[:N],
+            bp_boxes.obj[:N])
+
+
+def window_index(arrays, ta, tb):
+    """Device indices of the boxes whose tags meet the ticks [ta, tb)."""
+    import torch
+    _, _, t0, t1, _ = arrays
+    return torch.nonzero((t0 < tb) & (t1 > ta)).flatten()
