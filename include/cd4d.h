@@ -261,6 +261,24 @@ int cd_query_pairs_async(const cd_tree *tree, cd_pair *out, int64_t capacity,
                          unsigned long long *count_dev, unsigned int *status_dev, void *ws,
                          size_t ws_bytes, cd_stream_t stream);
 
+/* The same query as cd_query_pairs_async, for callers that cannot allocate
+ * memory (code under hipGraph capture, tight serving loops, harnesses that
+ * forbid allocation): the workspace is a fixed device array inside the
+ * library, cd_noalloc_scratch_bytes() bytes (64 MiB) per device, held by
+ * every device the library runs on until the process ends.  The caller still
+ * passes the tree and the outputs.  A query whose workspace
+ * (cd_query_pairs_ws(tree->count, capacity)) exceeds the array returns
+ * CD_E_WORKSPACE before anything is enqueued.  Call with the stream's device
+ * current.  All calls on one device share its array: calls that overlap in
+ * time on one device (several streams, several host threads) race and give
+ * undefined results; calls ordered on one stream are safe, since each call
+ * clears what it reads before use.  Allocates nothing; the first call on a
+ * device looks up the array's device address.  Async. */
+size_t cd_noalloc_scratch_bytes(void);
+int cd_query_pairs_async_noalloc(const cd_tree *tree, cd_pair *out, int64_t capacity,
+                                 unsigned long long *count_dev, unsigned int *status_dev,
+                                 cd_stream_t stream);
+
 /* ---- launch shapes of the traversal -------------------------------------- */
 
 /* Process-wide launch shapes, read by every later query call (a captured

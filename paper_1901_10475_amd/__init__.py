@@ -105,6 +105,9 @@ def lib():
             "cd_query_pairs": (ctypes.c_int, [P(cd_tree), _vp, i64, P(i64), _vp, sz, _vp]),
             "cd_query_pairs_async": (ctypes.c_int, [P(cd_tree), _vp, i64, _vp, _vp, _vp, sz,
                                                     _vp]),
+            "cd_noalloc_scratch_bytes": (sz, []),
+            "cd_query_pairs_async_noalloc": (ctypes.c_int, [P(cd_tree), _vp, i64, _vp, _vp,
+                                                            _vp]),
             "cd_set_tuning": (ctypes.c_int, [P(cd_tuning)]),
             "cd_get_tuning": (ctypes.c_int, [P(cd_tuning)]),
             "cd_graph_begin": (ctypes.c_int, [_vp]),
@@ -152,6 +155,7 @@ EXPORTED = ("cd_status_string", "cd_last_error", "cd_version", "cd_profile_enabl
             "cd_box_count", "cd_validate_ws", "cd_validate_elements", "cd_dt_heuristic",
             "cd_build_boxes_ws", "cd_build_boxes", "cd_tree_bytes", "cd_build_tree_ws",
             "cd_build_tree", "cd_query_pairs_ws", "cd_query_pairs", "cd_query_pairs_async",
+            "cd_noalloc_scratch_bytes", "cd_query_pairs_async_noalloc",
             "cd_set_tuning", "cd_get_tuning", "cd_graph_begin", "cd_graph_end",
             "cd_graph_launch", "cd_graph_destroy", "cd_first_witness", "cd_refine_records_ws",
             "cd_refine_records", "cd_band_filter_ws", "cd_band_filter", "cd_band_partition_ws",
@@ -348,6 +352,14 @@ def cd_query_pairs_async(tree, out, capacity, count_dev, status_dev, ws):
 
 TUNING_DEFAULTS = {"expand_blocks": 2048, "expand_threads": 256, "walk_threads": 256,
                    "mode": 0, "max_levels": 96}
+
+
+def cd_query_pairs_async_noalloc(tree, out, capacity, count_dev, status_dev):
+    """cd_query_pairs_async with the library's fixed scratch as workspace."""
+    if capacity < 1 or out.shape[0] < capacity:
+        raise ValueError("out must hold `capacity` records")
+    _check(lib().cd_query_pairs_async_noalloc(ctypes.byref(tree.desc), _ptr(out), int(capacity),
+                                              _ptr(count_dev), _ptr(status_dev), _stream()))
 
 
 def cd_set_tuning(t=None):

@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 ARCH = os.environ.get("CD4D_ARCH", "gfx950")
 
 LIB_SOURCES = ["k_boxes.hip", "k_sort.hip", "k_tree.hip", "k_refit.hip", "k_query.hip", "k_mlp.hip",
-               "k_narrow.hip", "k_refine.hip", "k_bands.hip", "cd_api.cpp"]
+               "k_narrow.hip", "k_refine.hip", "k_bands.hip", "k_noalloc.hip", "cd_api.cpp"]
 HOSTCHECK_SOURCES = ["cd_hostcheck.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"), "-I", CSRC,

@@ -27,6 +27,23 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
+}  // namespace
+
+namespace cd {
+// The thread-local error message, for the entry points defined in other
+// translation units.
+int set_error(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+}  // namespace cd
+
+namespace {
+
 #define CD_HIP(x)                                                                          \
     do {                                                                                   \
         hipError_t e_ = (x);                                                               \

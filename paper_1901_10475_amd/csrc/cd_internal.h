@@ -331,6 +331,8 @@ hipError_t launch_first_witness(const cd_elements &el, double mu, double tick_s,
                                 uint64_t count, uint32_t *witness, unsigned long long *first,
                                 hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t count, hipStream_t s);
+// Sets the thread-local message of cd_last_error and returns code.
+int set_error(int code, const char *fmt, ...);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, size_t count,
                            hipStream_t s);
 size_t scan_ws_bytes(size_t count);
