@@ -9,9 +9,14 @@ list, ending with the pair count on the host.
 Prints one JSON line.  value = brute-force-equivalent box-pair tests per second
 (different-object box pairs whose time tags overlap, K * C(n, 2) for a uniform
 step, divided by the query time).  roofline: the stage with the largest device
-time, its algorithmic bytes per launch over its mean duration, from HIP events
-recorded on the library's stream during the timed steps.  cpu_baseline: the
-CPU oracle (literal all-pairs) on a bounded sample of the same workload.
+time (HIP events recorded by the library on its own stream during the timed
+steps), its compulsory HBM bytes per launch (the hot-path scope's per-box
+figures) over its mean duration, against the 8 TB/s specification and the
+measured streaming-copy bandwidth; the same for every stage and for the whole
+query.  the benchmark spec: the learned per-object step with FP32 boxes (eccentric-
+anomaly and speed boxes) against this FP64 1 s line.  cpu_baseline: the CPU
+oracle (FP64 boxes, bucketed all-pairs within each slab, canonical sort) on the
+hour's first 60 slabs, on all host threads and on one.
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--precision fp64|fp32]
                     [--boxes fp64|fp32] [--dt fixed|heuristic|mlp] [--workload tracked|batch]
@@ -71,25 +76,56 @@ def measured_traffic(stage, precision, dt_mode):
                + t["write_kib"] * 1024 * (1048576.0 / COPY_WRITE_KIB))
 
 
-def algorithmic_bytes(stage, N, n, P, tree_prec, box_prec):
-    """Compulsory HBM bytes of one launch of a stage: every input read once,
-    every output written once (intermediate LDS traffic excluded)."""
+def compulsory_bytes(stage, N, P, tree_prec, box_prec, per_object_dt=False,
+                     sorted_layout=False):
+    """Compulsory HBM bytes of one launch of a stage, per box as the hot-path
+    scope's measurement section counts them (FP64: boxes 56 + keys 12, per-slab
+    sort 24, hierarchy 16, refit 112, traversal 120 plus 16 per record; 340 B
+    per box in all), scaled to the FP32 layouts (32-byte leaf boxes, 40-byte
+    nodes).  The box stage writes the keys with the boxes, so it is credited
+    with both; with the sorted layout it also puts every slab in Morton order
+    (no sort stage runs), so it is credited with the sort's bytes too."""
+    fb = 8 if box_prec == 0 else 4
+    box = 6 * fb + 8 + (4 if per_object_dt else 0)   # bounds, tags (+ object id)
+    node = 64 if tree_prec == 0 else 40
+    leaf = 56 if tree_prec == 0 else 32
+    table = {
+        "boxes": N * (box + 12 + (24 if sorted_layout else 0)),   # boxes and keys written
+                                               # (and the slab order formed)
+        "keys": 0,                             # folded into the box stage
+        "sort": N * 24,                        # keys and indices read and written once
+        "karras": N * 16,                      # children and parents written
+        "refit": N * 2 * leaf,                 # one sibling box read, one node box written
+        "traverse": (N - 1) * node + N * leaf + P * 16,   # every node once, records out
+        "canon": P * 32,                       # records read and written once
+    }
+    return table.get(stage)
+
+
+def design_bytes(stage, N, n, P, tree_prec, box_prec, sorted_layout=False):
+    """What this implementation's kernels are built to move per launch (every
+    input it reads once, every output it writes once, LDS traffic excluded):
+    the slab build, for one, materialises 64-byte sorted leaf records, which
+    the scope's per-slab sort of keys and indices does not."""
     fb = 8 if box_prec == 0 else 4          # box float bytes
     box = 6 * fb + 12                         # lo/hi + t0, t1, obj
     node = 64 if tree_prec == 0 else 40       # tree record (box + links)
     nodes = 2 * N - 1
     table = {
-        "boxes": N * box,                                    # boxes written
+        "boxes": N * (box + 4),                              # boxes and codes written
         "keys": 0,                                           # sampled frame only
         "sort": N * (4 + 4) + N * box + N * 4 + N * node,    # slab build: codes and tags,
                                                              # then boxes in; sorted codes
                                                              # and leaf records out
-        "karras": N * 4 + (N - 1) * (8 + 1) + nodes * (8 + 4),  # codes in; kids, level,
-                                                             # links, parents out
-        "refit": N * node + nodes * 4 + (N - 1) * (8 + 4) + (N - 1) * node,
-                                                             # leaf records, parents, kids
-                                                             # and escapes in; inner records
-                                                             # out
+        "karras": N * (8 if sorted_layout else 4) + (N - 1) * (8 + 1) + nodes * (8 + 4),
+                                                             # codes (and tags) in; kids,
+                                                             # level, links, parents out
+        "refit": (N * (box + node) if sorted_layout else N * node)
+                 + nodes * 4 + (N - 1) * (8 + 4) + (N - 1) * node,
+                                                             # leaf records (sorted layout:
+                                                             # boxes in, leaf records out),
+                                                             # parents, kids and escapes in;
+                                                             # inner records out
         "traverse": nodes * node + P * 16,                   # every node read once,
                                                              # records out
         "canon": P * 16 * 3,
@@ -117,32 +153,61 @@ def time_overlap_pairs(dt, T):
     return total
 
 
-def cpu_baseline(sc, seconds):
-    """The CPU oracle on the first two steps of the hour (every object, t in
-    [0, 2 s)): FP64 boxes, then literal all-pairs over those 2n boxes; repeated
-    until `seconds` of wall time have passed."""
+def host_cpu():
+    """(logical CPUs usable by this process, CPU model name)."""
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return usable, model
+
+
+def cpu_baseline(sc, slabs=60):
+    """The CPU oracle end to end on the first `slabs` steps of the hour (every
+    object, t in [0, slabs dt)): FP64 boxes, the bucketed driver (all pairs
+    within each slab) and the canonical sort, once on all threads and once on
+    one thread.  slabs * C(n, 2) brute-force-equivalent tests per run."""
     import oracle
     n = sc.n
-    T = 2 * sc.dt_ticks - 1          # intervals [0, dt) and [dt, 2 dt), as in the hour
-    reps, t_start = 0, time.perf_counter()
-    while True:
+    T = slabs * sc.dt_ticks - 1      # intervals [k dt, (k + 1) dt), k < slabs, as in the hour
+    tests = slabs * (n * (n - 1) // 2)
+    threads_all = oracle.num_threads()
+    runs = {}
+    for nt in (threads_all, 1):
+        oracle.set_num_threads(nt)
+        t_start = time.perf_counter()
         b = oracle.boxes(sc.elements, sc.dt_ticks, T, sc.tick_s, sc.threshold_km)
-        oracle.pairs(b)
-        reps += 1
+        rec = oracle.pairs_bucketed(b)
         el_t = time.perf_counter() - t_start
-        if el_t >= seconds:
-            break
-    tests = reps * 2 * (n * (n - 1) // 2)
-    return {"value": tests / el_t, "unit": "box-pair tests/s", "cores": oracle.num_threads(),
+        runs[nt] = (el_t, len(rec))
+    oracle.set_num_threads(threads_all)
+    usable, model = host_cpu()
+    t_all, P = runs[threads_all]
+    t_one, _ = runs[1]
+    return {"value": tests / t_all, "unit": "box-pair tests/s", "cores": threads_all,
             "kind": "oracle",
-            "sample": f"first 2 s of the hour ({2 * n} boxes: {n} objects x 2 steps), oracle "
-                      f"FP64 boxes + literal all-pairs, {reps} repetitions in {el_t:.1f} s; "
-                      f"counted as 2 * C(n, 2) brute-force-equivalent tests per repetition"}
+            "sample": f"first {slabs} s of the hour ({slabs * n} boxes: {n} objects x {slabs} "
+                      f"steps, {P} records): oracle FP64 boxes + bucketed pairs (all pairs "
+                      f"within each slab) + canonical sort, end to end, {t_all:.2f} s on "
+                      f"{threads_all} threads; {slabs} * C(n, 2) brute-force-equivalent tests",
+            "single_thread": {"value": tests / t_one, "seconds": round(t_one, 3)},
+            "host": {"usable_cpus": usable, "cpu_model": model},
+            "ms_per_query_extrapolated": round(t_all * 1000.0 * (sc.horizon_ticks // sc.dt_ticks)
+                                               / slabs, 1)}
 
 
 def _setup(args):
     import torch
     torch.cuda.set_device(0)
+    args.copy = None if args.no_copy else copy_bandwidth()
     if args.copy_mib:
         src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -151,15 +216,69 @@ def _setup(args):
         del src, dst
 
 
-def _roofline(stages, N, n, P, prec, box_prec, precision_name, dt_mode):
+def copy_bandwidth(nbytes=4 << 30, reps=10):
+    """The library's streaming copy (cd_stream_copy) over nbytes: read + write
+    bytes over the median time, GB/s: the achievable HBM bandwidth."""
+    import torch
+    import paper_1901_10475_amd as cd
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    cd.cd_stream_copy(dst, src)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for a, b in ev:
+        a.record()
+        cd.cd_stream_copy(dst, src)
+        b.record()
+    torch.cuda.synchronize()
+    ms = sorted(a.elapsed_time(b) for a, b in ev)[reps // 2]
+    ok = bool(torch.equal(dst[:: 1 << 20], src[:: 1 << 20]))
+    del src, dst
+    torch.cuda.empty_cache()
+    gbs = 2 * nbytes / (ms / 1000.0) / 1e9
+    return {"kernel": "cd_stream_copy", "bytes": 2 * nbytes, "ms": round(ms, 4),
+            "achieved": round(gbs, 1), "unit": "GB/s", "frac_of_spec": round(gbs / HBM_PEAK_GBS, 4),
+            "copied_correctly": ok}
+
+
+def _roofline(stages, N, n, P, prec, box_prec, precision_name, dt_mode, ms_step, copy=None,
+              sorted_layout=False):
+    """Roofline of the dominant stage (largest device time) with the scope's
+    compulsory bytes, plus every stage and the whole query the same way."""
+    per_obj = dt_mode != "fixed"
     dom = max(stages, key=lambda k: stages[k][0])
     mean_ms = stages[dom][0] / stages[dom][1]
-    nbytes = algorithmic_bytes(dom, N, n, P, prec, box_prec)
+    nbytes = compulsory_bytes(dom, N, P, prec, box_prec, per_obj, sorted_layout)
     achieved = nbytes / (mean_ms / 1000.0) / 1e9
-    return {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(dom, precision_name, dt_mode),
-            "bytes_per_launch": int(nbytes), "mean_ms": round(mean_ms, 4)}
+    out = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+           "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "traffic": measured_traffic(dom, precision_name, dt_mode),
+           "bytes_per_launch": int(nbytes), "mean_ms": round(mean_ms, 4),
+           "bytes_rule": "compulsory bytes per box of the scope's measurement section"}
+    per_stage = {}
+    total = 0
+    for k, (ms_tot, launches) in stages.items():
+        b = compulsory_bytes(k, N, P, prec, box_prec, per_obj, sorted_layout) or 0
+        ms = ms_tot / launches
+        total += b
+        per_stage[k] = {"mean_ms": round(ms, 4), "bytes": int(b),
+                        "frac": round(b / (ms / 1000.0) / 1e9 / HBM_PEAK_GBS, 4) if ms > 0 else None}
+    out["stages"] = per_stage
+    wq = total / (ms_step / 1000.0) / 1e9
+    out["whole_query"] = {"bytes": int(total), "ms": round(ms_step, 4), "achieved": round(wq, 1),
+                          "frac": round(wq / HBM_PEAK_GBS, 4),
+                          "floor_ms": round(total / (HBM_PEAK_GBS * 1e9) * 1000.0, 4)}
+    db = design_bytes(dom, N, n, P, prec, box_prec, sorted_layout)
+    out["design_bytes"] = {"bytes_per_launch": int(db),
+                           "achieved": round(db / (mean_ms / 1000.0) / 1e9, 1),
+                           "note": "bytes this implementation's kernel is built to move "
+                                   "(it materialises sorted leaf records); not the roofline"}
+    if copy:
+        out["copy_peak"] = copy["achieved"]
+        out["frac_of_copy_peak"] = round(achieved / copy["achieved"], 4)
+        out["whole_query"]["frac_of_copy_peak"] = round(wq / copy["achieved"], 4)
+    return out
 
 
 def _train_step_net(sc_recipe, seeds, cd, ld, catalog, log, box_rule=0):
@@ -237,12 +356,7 @@ def run_tracked(args, log):
     value = tests / (ms_step / 1000.0)
     log(f"[bench] {args.steps} steps: {ms_step:.3f} ms/query, {P} pairs, stages "
         + ", ".join(f"{k}={v[0] / v[1]:.3f}ms" for k, v in stages.items()))
-    recall = None
-    if sc.planted:
-        pr = pairs.cpu().numpy().view(np.uint32)
-        hit = sum(bool(((pr[:, 0] == i) & (pr[:, 1] == j) & (pr[:, 2] <= t)
-                        & (t < pr[:, 3])).any()) for i, j, t in sc.planted)
-        recall = hit / len(sc.planted)
+    recall = planted_recall(sc, pairs)
     out = {"metric": METRIC, "value": value, "unit": "box-pair tests/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -258,11 +372,92 @@ def run_tracked(args, log):
                       "box_rule": args.box, "brute_force_tests": tests},
            "pairs": P, "planted_recall": recall,
            "stages_ms": {k: round(v[0] / v[1], 4) for k, v in stages.items()},
-           "roofline": _roofline(stages, N, sc.n, P, prec, box_prec, args.precision, args.dt)}
+           "roofline": _roofline(stages, N, sc.n, P, prec, box_prec, args.precision, args.dt,
+                                 ms_step, args.copy,
+                                 bp.boxes.desc.layout == cd.CD_LAYOUT_SORTED)}
+    out["config"]["box_layout"] = ("sorted" if bp.boxes.desc.layout == cd.CD_LAYOUT_SORTED
+                                   else "object")
+    if args.copy:
+        out["hbm_copy"] = args.copy
     out["narrow_phase"] = narrow_phase(cd, el, p, pairs, log)
+    default_line = (args.dt == "fixed" and prec == cd.CD_FP64 and box_prec == cd.CD_FP64
+                    and args.box == "speed")
+    if default_line and not args.no_north_star:
+        out["north_star"] = north_star_forms(args, log, sc, el, {
+            "ms_per_query": round(ms_step, 4), "boxes": N, "records": P,
+            "planted_recall": recall,
+            "colliding_object_pairs": out["narrow_phase"]["colliding_object_pairs"]})
     if not args.no_cpu_baseline and args.dt == "fixed":
         log("[bench] CPU oracle baseline ...")
-        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(sc, args.cpu_slabs)
+    return out
+
+
+def planted_recall(sc, pairs):
+    """Share of the planted conjunctions (i, j, t) covered by a record."""
+    import numpy as np
+    if not sc.planted:
+        return None
+    pr = pairs.cpu().numpy().view(np.uint32)
+    hit = sum(bool(((pr[:, 0] == i) & (pr[:, 1] == j) & (pr[:, 2] <= t)
+                    & (t < pr[:, 3])).any()) for i, j, t in sc.planted)
+    return hit / len(sc.planted)
+
+
+def colliding_object_pairs(cd, el, p, pairs, delta=1):
+    """Distinct object pairs with a collision instant on the delta grid (the
+    narrow phase over the records): the true collisions every conservative
+    form must keep."""
+    import torch
+    if pairs.shape[0] == 0:
+        return 0
+    wit, _ = cd.cd_first_witness(el, p, delta, pairs)
+    hp = pairs[wit != -1][:, :2].long()
+    return int(torch.unique(hp[:, 0] * (1 << 32) + hp[:, 1]).numel()) if hp.shape[0] else 0
+
+
+def north_star_forms(args, log, sc, el, base):
+    """The learned per-object step with FP32 outward-rounded boxes and tree,
+    with the eccentric-anomaly interval box and with the speed box, against the
+    plain FP64 form at 1 s (the default line): ms per query over the same
+    number of timed steps, planted recall and colliding object pairs.  Each
+    network is trained first (step sweeps of two other catalogs of the same
+    recipe, outside the timed region); its BF16 inference runs inside every
+    timed step."""
+    import torch
+    import paper_1901_10475_amd as cd
+    from paper_1901_10475_amd import catalog
+    from paper_1901_10475_amd import learned_dt as ld
+    out = {"fp64_dt1s_speed_box": base}
+    for rule_name in ("ecc", "speed"):
+        rule = BOX_RULES[rule_name]
+        t_train = time.perf_counter()
+        net = _train_step_net(lambda seed: catalog.tracked_hour(seed=seed, planted=0),
+                              (2002, 2003), cd, ld, catalog, log, rule)
+        t_train = time.perf_counter() - t_train
+        p = cd.params_struct(sc.tick_s, sc.mu, sc.threshold_km, sc.horizon_ticks, 0,
+                             box_rule=rule)
+        bp = cd.BroadPhase(sc.n, p, None, cd.CD_FP32, cd.CD_FP32, dt_mlp=(net.w_bf16, 5.0),
+                           el_soa=el)
+        for _ in range(args.warmup):
+            pairs = bp.run(el)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            pairs = bp.run(el)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+        form = {"ms_per_query": round(ms, 4), "boxes": int(bp.count),
+                "records": int(pairs.shape[0]), "planted_recall": planted_recall(sc, pairs),
+                "colliding_object_pairs": colliding_object_pairs(cd, el, p, pairs),
+                "speedup_vs_fp64_dt1s": round(base["ms_per_query"] / ms, 3),
+                "training_s": round(t_train, 1)}
+        log(f"[bench] learned steps, FP32, {rule_name} box: {ms:.3f} ms/query, "
+            f"{form['boxes']} boxes, {form['records']} records, recall "
+            f"{form['planted_recall']}, {form['colliding_object_pairs']} colliding pairs")
+        out[f"learned_fp32_{rule_name}_box"] = form
+        del bp, pairs, net
+        torch.cuda.empty_cache()
     return out
 
 
@@ -352,7 +547,7 @@ def run_batch(args, log):
         + ", ".join(f"{k}={v[0]:.1f}ms/{v[1]}" for k, v in stages.items()))
     # roofline of the dominant stage over the eager pass (all scenarios)
     dom = max(stages, key=lambda k: stages[k][0])
-    nbytes = sum(algorithmic_bytes(dom, N, s.n, 0, prec, box_prec)
+    nbytes = sum(compulsory_bytes(dom, N, 0, prec, box_prec)
                  for s, N in zip(scs, br.counts))
     achieved = nbytes / (stages[dom][0] / 1000.0) / 1e9
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
@@ -461,7 +656,7 @@ def run_debris(args, log):
             "pairs": P, "planted_recall": hit / max(len(sc.planted), 1),
             "stages_ms": {k: round(v[0] / v[1], 4) for k, v in stages.items()},
             "roofline": _roofline(stages, bp.count, sc.n, P // nwin, prec, box_prec,
-                                  args.precision, args.dt)}
+                                  args.precision, args.dt, ms_step / nwin, args.copy)}
 
 
 def run_bands(args, log):
@@ -538,8 +733,13 @@ def main():
                     help="bands workload: altitude bands of the edge partition")
     ap.add_argument("--window-s", type=float, default=1800.0,
                     help="debris workload: window length in seconds (divides 6 h)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-slabs", type=int, default=60,
+                    help="CPU baseline: the oracle over the hour's first this many 1 s slabs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-north-star", action="store_true",
+                    help="default line: skip the learned-step FP32 forms")
+    ap.add_argument("--no-copy", action="store_true",
+                    help="skip the streaming-copy bandwidth measurement")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB (a known-size "
                          "kernel for calibrating HBM byte counters)")

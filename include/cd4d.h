@@ -17,8 +17,15 @@
  *   - Units: km, s, rad.  Time is counted in integer ticks of tick_s seconds.
  *   - Every pointer is a DEVICE pointer unless its name ends in _host.
  *   - The caller allocates and owns all memory: elements, boxes, tree,
- *     workspace and output.  The library allocates nothing and keeps no state
- *     beyond a thread-local error string.
+ *     workspace and output.  The library allocates no device memory.  Its
+ *     only state is: the thread-local error string (cd_last_error); the
+ *     thread-local launch shapes of the traversal (cd_set_tuning), read by
+ *     the calling thread's later queries; the process-wide stage profiler
+ *     (cd_profile_*, guarded by a mutex); and a process-wide hint, kept in an
+ *     atomic, of how many node-pair levels the last drained synchronous query
+ *     needed, which sets how many levels the next one launches before its
+ *     first host check.  None of them changes a result: records depend only
+ *     on the arguments of the call.
  *   - Streams are hipStream_t values passed as void* (NULL = default stream).
  *     Work is enqueued on that stream; functions marked "syncs" wait for it.
  *   - Every function returns a status code; no exception crosses the ABI.
@@ -98,13 +105,34 @@ typedef struct {
  *   horizon_ticks: an upper bound on every t0 (used to size sort keys).
  *   obj_count: an upper bound on obj + 1 (used to size sort keys); 0 means
  *     "up to 2^32".
- *   code, code_valid: optional per-box 30-bit Morton code of the box centre
- *     (the tree's spatial sort key).  If code is not NULL, cd_build_boxes
- *     writes it (in the frame of the orbits' bounding boxes, so no code is
- *     clamped) and sets code_valid = 1; cd_build_tree then sorts by these
- *     codes instead of re-reading every box to form them.  Codes only shape
- *     the tree: any codes give the same records.  code_valid = 0 (or code
- *     NULL) makes cd_build_tree compute codes from the boxes. */
+ *   code, code_valid: optional per-box 30-bit Morton code (the tree's
+ *     spatial sort key).  If code is not NULL, cd_build_boxes writes it (in
+ *     the frame of the orbits' bounding boxes, so no code is clamped) and sets
+ *     code_valid = 1; cd_build_tree then sorts by these codes instead of
+ *     re-reading every box to form them.  Codes only shape the tree: any codes
+ *     give the same records.  code_valid = 0 (or code NULL) makes
+ *     cd_build_tree compute codes from the boxes.
+ *   layout: the order of a uniform step's boxes inside each time slab.
+ *     CD_LAYOUT_OBJECT: box (i, k) at k * n + i, code = that of the box
+ *     centre.  CD_LAYOUT_SORTED: the slabs are taken in blocks of 8
+ *     consecutive slabs (more when K / 8 exceeds 65 535), and inside every
+ *     slab of a block the boxes follow the Morton order of their objects'
+ *     positions at the block's middle instant; code holds that order's key
+ *     (non-decreasing along each slab) and obj[b] names the object of box b.
+ *     cd_build_boxes reads the requested layout (CD_LAYOUT_SORTED needs code
+ *     != NULL and n <= 17 408; otherwise, and for per-object steps, it
+ *     writes CD_LAYOUT_OBJECT) and leaves the layout it wrote.  cd_build_tree
+ *     needs no key sort for CD_LAYOUT_SORTED boxes with valid codes and slab
+ *     hints; it checks that each slab's codes are non-decreasing (error bit
+ *     as for a box outside its slab, reported by the query).
+ *   records: NULL, or FP64 box records written instead of the lo, hi, t0,
+ *     t1 and obj arrays: 64 bytes per box, {double lo[3], hi[3]; uint32_t
+ *     t0, t1, obj, code}, the layout of an FP64 tree's leaf records (the code
+ *     array is still written as well).  cd_build_boxes writes them for a
+ *     uniform step in the sorted layout (FP64 boxes, n <= 17 408; otherwise
+ *     CD_E_INVALID).  With records =
+ *     cd_tree_leaf_records(tree) and CD_LAYOUT_SORTED, cd_build_tree takes
+ *     them as the tree's leaves where they are: no sort and no copy. */
 typedef struct {
     int64_t count;
     int precision;
@@ -116,7 +144,11 @@ typedef struct {
     uint32_t obj_count;
     uint32_t *code;
     int code_valid;
+    int layout;   /* CD_LAYOUT_OBJECT or CD_LAYOUT_SORTED */
+    void *records;
 } cd_boxes;
+#define CD_LAYOUT_OBJECT 0
+#define CD_LAYOUT_SORTED 1
 
 /* A linear BVH over a box set.  mem is a caller-owned device buffer of
  * cd_tree_bytes(count, precision) bytes; cd_build_tree fills it and the
@@ -141,6 +173,15 @@ typedef struct {
 const char *cd_status_string(int status);
 const char *cd_last_error(void);
 int cd_version(void);
+
+/* A plain streaming copy of `bytes` bytes from src to dst (device memory):
+ * 16-byte loads, non-temporal 16-byte stores, grid-stride.  It is the
+ * measured achievable HBM bandwidth (read + write bytes over its time) that
+ * the kernels' roofline fractions are read against, beside the 8 TB/s
+ * specification, and a kernel of known byte count for calibrating HBM byte
+ * counters.  bytes and both addresses must be multiples of 16 and the ranges
+ * must not overlap (else CD_E_INVALID).  Async. */
+int cd_stream_copy(void *dst, const void *src, size_t bytes, cd_stream_t stream);
 
 /* Per-stage device time.  While enabled, every call records a hipEvent pair
  * on its stream around each kernel stage ("boxes", "keys", "sort", "karras",
@@ -171,10 +212,14 @@ size_t cd_validate_ws(int64_t n);
 int cd_validate_elements(const cd_elements *el, int64_t *bad_index_host, void *ws,
                          size_t ws_bytes, cd_stream_t stream);
 
-/* Per-object step from the speed bound (each interval's displacement at most
- * max_disp_km): dt_i = clamp(floor(max_disp_km / (vmax_i * tick_s)), 1,
- * max(T, 1)) ticks, vmax_i the perigee speed.  Any step keeps the boxes
- * conservative; this one bounds each box's motion term.  Async. */
+/* Per-object step from the speed bound.  The paper keeps one time interval
+ * per object (Sec. 4: each object's t_min, t_max) and leaves its length to a
+ * rule (Procedure advanceTime, Sec. 4.3, doubles it while the object meets
+ * nobody); this call fixes the length per object so that each interval's
+ * displacement is at most max_disp_km:
+ *   dt_i = clamp(floor(max_disp_km / (vmax_i * tick_s)), 1, max(T, 1)) ticks,
+ * vmax_i the perigee speed.  Any step keeps the boxes conservative; this one
+ * bounds each box's motion term.  Async. */
 int cd_dt_heuristic(const cd_elements *el, const cd_params *p, double max_disp_km,
                     uint32_t *dt_out, cd_stream_t stream);
 
@@ -200,7 +245,9 @@ int cd_dt_heuristic(const cd_elements *el, const cd_params *p, double max_disp_k
  * Every rule holds each position in the interval and equals the occupancy
  * cube at a single instant (Property 1).  With a CD_FP32 output the FP64
  * bounds are rounded outward.
- * Order: uniform step (dt_ticks NULL) -> time-major, box (i,k) at k*n + i, and
+ * Order: uniform step (dt_ticks NULL) -> time-major, slab k at [k n, (k + 1) n)
+ * in the order out->layout asks for (box (i,k) at k*n + i for
+ * CD_LAYOUT_OBJECT; by the objects' Morton order for CD_LAYOUT_SORTED), and
  * out->slab_size = n, out->slab_ticks = dt.  Per-object steps -> object-major,
  * box (i,k) at off_i + k.  out->count must equal cd_box_count's result and
  * out's arrays must hold that many entries.  Async; element validity is not
@@ -219,18 +266,28 @@ int cd_build_boxes(const cd_elements *el, const uint32_t *dt_ticks, const cd_par
  * children by an atomic bottom-up pass, so an inner node overlaps whatever
  * its leaves overlap.  precision CD_FP32 is allowed for FP64 boxes (outward
  * rounding at the leaves).  slab_ticks = 0 takes boxes->slab_ticks if set,
- * else horizon / 64 (at least 1).
+ * else horizon / 64 (at least 1).  Box records in the tree's own leaf-record
+ * area (cd_boxes.records) are used in place.
  * Async. */
 size_t cd_tree_bytes(int64_t count, int precision);
+/* The leaf-record area of an FP64 tree buffer of count leaves (host pointer
+ * arithmetic on tree_mem; NULL if count < 1): where cd_build_boxes can write
+ * box records for cd_build_tree to use in place (see cd_boxes.records). */
+void *cd_tree_leaf_records(void *tree_mem, int64_t count);
 size_t cd_build_tree_ws(int64_t count);
 int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_tree *tree,
                   void *ws, size_t ws_bytes, cd_stream_t stream);
 
 /* ---- step 4: the n-to-n query ------------------------------------------- */
 
-/* Self-traversal of the tree: every pair of boxes of different objects whose
- * time tags overlap (t0_a < t1_b and t0_b < t1_a) and whose closed 3D
- * extents overlap on every axis gives one record
+/* Self-traversal of the tree.  Two objects' 4D occupancy regions intersect
+ * when their time intervals overlap and their 3D boxes do (Def. 4D Occupancy
+ * Region, Sec. 4); a box is never paired with another box of its own object,
+ * as queryObject excludes the queried object (Procedure resolveCollisions,
+ * Sec. 4.4) and Alg. Brute Force pairs distinct objects only (Sec. 3.1).
+ * Every pair of boxes of different objects whose time tags overlap
+ * (t0_a < t1_b and t0_b < t1_a) and whose closed 3D extents overlap on every
+ * axis gives one record
  *   (min(obj), max(obj), max(t0_a, t0_b), min(t1_a, t1_b)).
  * The list written to out is sorted by (i, j, t_lo, t_hi) and free of
  * repeats.  Syncs (it reads the record count).  If more than `capacity`
@@ -281,9 +338,10 @@ int cd_query_pairs_async_noalloc(const cd_tree *tree, cd_pair *out, int64_t capa
 
 /* ---- launch shapes of the traversal -------------------------------------- */
 
-/* Process-wide launch shapes, read by every later query call (a captured
- * graph keeps the shapes in force at capture time).  Zero fields take the
- * defaults in brackets. */
+/* Launch shapes of the calling thread, read by that thread's later query
+ * calls (a captured graph keeps the shapes in force at capture time).  Zero
+ * fields take the defaults in brackets.  Shapes change timing only, never the
+ * records. */
 typedef struct {
     uint32_t expand_blocks;   /* workgroups per node-pair level, 64..65536 [2048] */
     uint32_t expand_threads;  /* lanes per node-pair workgroup: 64 .. 1024, a power of 2 [256] */

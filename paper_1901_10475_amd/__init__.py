@@ -21,6 +21,7 @@ _LIB_PATH = os.path.join(_HERE, "libcd4d.so")
 CD_OK, CD_E_INVALID, CD_E_WORKSPACE, CD_E_CAPACITY, CD_E_OVERFLOW, CD_E_DEVICE = range(6)
 CD_FP64, CD_FP32 = 0, 1
 CD_BOX_SPEED, CD_BOX_INTERVAL_NU, CD_BOX_INTERVAL_E = 0, 1, 2
+CD_LAYOUT_OBJECT, CD_LAYOUT_SORTED = 0, 1
 
 _vp = ctypes.c_void_p
 
@@ -42,7 +43,8 @@ class cd_boxes(ctypes.Structure):
                 ("hi", _vp * 3), ("t0", _vp), ("t1", _vp), ("obj", _vp),
                 ("slab_ticks", ctypes.c_uint32), ("slab_size", ctypes.c_int64),
                 ("horizon_ticks", ctypes.c_uint32), ("obj_count", ctypes.c_uint32),
-                ("code", _vp), ("code_valid", ctypes.c_int)]
+                ("code", _vp), ("code_valid", ctypes.c_int), ("layout", ctypes.c_int),
+                ("records", _vp)]
 
 
 class cd_tree(ctypes.Structure):
@@ -86,6 +88,7 @@ def lib():
             "cd_status_string": (ctypes.c_char_p, [ctypes.c_int]),
             "cd_last_error": (ctypes.c_char_p, []),
             "cd_version": (ctypes.c_int, []),
+            "cd_stream_copy": (ctypes.c_int, [_vp, _vp, sz, _vp]),
             "cd_profile_enable": (ctypes.c_int, [ctypes.c_int]),
             "cd_profile_read": (ctypes.c_int, [P(ctypes.c_char_p), P(dbl), P(i64), ctypes.c_int,
                                                ctypes.c_int]),
@@ -98,6 +101,7 @@ def lib():
             "cd_build_boxes": (ctypes.c_int, [P(cd_elements), _vp, P(cd_params), P(cd_boxes),
                                               _vp, sz, _vp]),
             "cd_tree_bytes": (sz, [i64, ctypes.c_int]),
+            "cd_tree_leaf_records": (_vp, [_vp, i64]),
             "cd_build_tree_ws": (sz, [i64]),
             "cd_build_tree": (ctypes.c_int, [P(cd_boxes), ctypes.c_int, u32, P(cd_tree), _vp,
                                              sz, _vp]),
@@ -150,10 +154,12 @@ def lib():
     return _lib
 
 
-EXPORTED = ("cd_status_string", "cd_last_error", "cd_version", "cd_profile_enable",
+EXPORTED = ("cd_status_string", "cd_last_error", "cd_version", "cd_stream_copy",
+            "cd_profile_enable",
             "cd_profile_read", "cd_box_count_ws",
             "cd_box_count", "cd_validate_ws", "cd_validate_elements", "cd_dt_heuristic",
-            "cd_build_boxes_ws", "cd_build_boxes", "cd_tree_bytes", "cd_build_tree_ws",
+            "cd_build_boxes_ws", "cd_build_boxes", "cd_tree_bytes", "cd_tree_leaf_records",
+            "cd_build_tree_ws",
             "cd_build_tree", "cd_query_pairs_ws", "cd_query_pairs", "cd_query_pairs_async",
             "cd_noalloc_scratch_bytes", "cd_query_pairs_async_noalloc",
             "cd_set_tuning", "cd_get_tuning", "cd_graph_begin", "cd_graph_end",
@@ -163,6 +169,14 @@ EXPORTED = ("cd_status_string", "cd_last_error", "cd_version", "cd_profile_enabl
             "cd_canonical_records_ws", "cd_canonical_records", "cd_mlp_features",
             "cd_dt_mlp", "cd_mlp_forward", "cd_mlp_grad_ws", "cd_mlp_grad", "cd_mlp_adam",
             "cd_pair_object_counts")
+
+
+def cd_stream_copy(dst, src, nbytes=None):
+    """Streaming copy of nbytes (default: all of src) between device tensors."""
+    n = src.numel() * src.element_size() if nbytes is None else int(nbytes)
+    if dst.numel() * dst.element_size() < n:
+        raise ValueError("dst is smaller than the copy")
+    _check(lib().cd_stream_copy(_ptr(dst), _ptr(src), n, _stream()))
 
 
 def cd_profile_enable(on=True):
@@ -221,7 +235,7 @@ class Boxes:
     """Device box arrays (SoA) plus the cd_boxes descriptor.  codes=True adds
     the per-box Morton code array that cd_build_boxes fills for the tree."""
 
-    def __init__(self, count, precision, device="cuda", codes=False):
+    def __init__(self, count, precision, device="cuda", codes=False, layout=CD_LAYOUT_OBJECT):
         ft = torch.float64 if precision == CD_FP64 else torch.float32
         self.count, self.precision = int(count), precision
         self.lo = torch.empty((3, max(count, 1)), dtype=ft, device=device)
@@ -242,6 +256,34 @@ class Boxes:
         self.desc.obj = self.obj.data_ptr()
         self.desc.code = self.code.data_ptr() if codes else None
         self.desc.code_valid = 0
+        self.desc.layout = layout
+
+    @classmethod
+    def in_tree(cls, tree, count, device="cuda"):
+        """FP64 box records written straight into an FP64 tree's leaf-record
+        area (cd_boxes.records = cd_tree_leaf_records): lo/hi/t0/t1/obj are
+        strided views of the records; codes also go to a packed array."""
+        b = cls.__new__(cls)
+        b.count, b.precision = int(count), CD_FP64
+        N = max(int(count), 1)
+        base = lib().cd_tree_leaf_records(_ptr(tree.mem), N)
+        off = base - tree.mem.data_ptr()
+        recs = tree.mem[off:off + 64 * N]
+        f64 = recs.view(torch.float64).view(N, 8)
+        u32 = recs.view(torch.int32).view(N, 16)
+        b.lo = f64[:, 0:3].t()
+        b.hi = f64[:, 3:6].t()
+        b.t0, b.t1, b.obj = u32[:, 12], u32[:, 13], u32[:, 14]
+        b.code = torch.empty(N, dtype=torch.int32, device=device)
+        b.desc = cd_boxes()
+        b.desc.count = b.count
+        b.desc.precision = CD_FP64
+        b.desc.records = base
+        b.desc.code = b.code.data_ptr()
+        b.desc.code_valid = 0
+        b.desc.layout = CD_LAYOUT_SORTED
+        b.tree_ref = tree
+        return b
 
     @classmethod
     def from_arrays(cls, lo, hi, t0, t1, obj, precision=CD_FP64, horizon_ticks=0,
@@ -543,11 +585,16 @@ class BroadPhase:
 
     def __init__(self, n, params, dt_ticks=None, box_precision=CD_FP64,
                  tree_precision=CD_FP64, capacity=None, slab_ticks=0, device="cuda",
-                 dt_heuristic_km=None, el_soa=None, dt_mlp=None, codes=True):
+                 dt_heuristic_km=None, el_soa=None, dt_mlp=None, codes=True,
+                 layout=CD_LAYOUT_SORTED, in_tree=True):
         """dt_heuristic_km: per-object steps from cd_dt_heuristic; dt_mlp:
         (bfloat16 weight tensor, fallback_disp_km) for steps from cd_dt_mlp.
         Either is recomputed by every build from the elements (el_soa is
-        needed here to size the buffers)."""
+        needed here to size the buffers).  layout: the box order requested
+        from cd_build_boxes for a uniform step (CD_LAYOUT_SORTED needs codes;
+        the layout written is in boxes.desc.layout after a build).  in_tree:
+        FP64 boxes of a sorted uniform step are written as the FP64 tree's
+        leaf records (boxes then views those records)."""
         self.dt_heuristic_km = dt_heuristic_km
         self.dt_mlp = dt_mlp
         if dt_heuristic_km is not None or dt_mlp is not None:
@@ -556,9 +603,19 @@ class BroadPhase:
         self.n, self.params, self.dt = int(n), params, dt_ticks
         self.device = device
         self.count = cd_box_count(dt_ticks, n, params, device)
-        self.boxes = Boxes(self.count, box_precision, device, codes=codes)
+        self.layout = layout if codes else CD_LAYOUT_OBJECT
         self.tree_precision = tree_precision
         self.tree = Tree(self.count, tree_precision, device)
+        # FP64 boxes of a uniform step in Morton order go straight into the
+        # FP64 tree's leaf records (no sort, no copy in the tree build)
+        self.in_tree = (in_tree and dt_ticks is None and box_precision == CD_FP64
+                        and tree_precision == CD_FP64 and self.layout == CD_LAYOUT_SORTED
+                        and self.n <= 17408 and self.count > 0)
+        if self.in_tree:
+            self.boxes = Boxes.in_tree(self.tree, self.count, device)
+        else:
+            self.boxes = Boxes(self.count, box_precision, device, codes=codes,
+                               layout=self.layout)
         self.ws_boxes = _bytes(lib().cd_build_boxes_ws(self.n), device)
         self.ws_tree = _bytes(lib().cd_build_tree_ws(self.count), device)
         self.slab_ticks = slab_ticks
@@ -581,6 +638,7 @@ class BroadPhase:
     def build(self, el_soa):
         if self.dt_heuristic_km is not None or self.dt_mlp is not None:
             self._steps(el_soa, self.params, self.dt)
+        self.boxes.desc.layout = self.layout
         cd_build_boxes(el_soa, self.dt, self.params, self.boxes, self.ws_boxes)
         cd_build_tree(self.boxes, self.tree_precision, self.tree, self.ws_tree, self.slab_ticks)
 

@@ -22,7 +22,7 @@ import math
 import numpy as np
 import torch
 
-from . import (CD_E_CAPACITY, CD_FP64, CD_OK, Graph, _bytes, _check, _ptr, _stream,
+from . import (CD_E_CAPACITY, CD_FP64, CD_LAYOUT_SORTED, CD_OK, Graph, _bytes, _check, _ptr, _stream,
                cd_boxes, cd_build_boxes, cd_get_tuning, cd_query_pairs, cd_query_pairs_async,
                cd_set_tuning, cd_tree, lib, params_struct, soa)
 
@@ -43,6 +43,7 @@ class _Boxes:
         self.desc.obj = obj.data_ptr()
         self.desc.code = code.data_ptr()
         self.desc.code_valid = 0
+        self.desc.layout = CD_LAYOUT_SORTED
 
 
 class _Tree:
@@ -113,6 +114,7 @@ class BatchRunner:
     # -- one scenario, eager ------------------------------------------------------
     def _build(self, k):
         b = self.boxes[k]
+        b.desc.layout = CD_LAYOUT_SORTED   # where n allows; the layout written is kept
         cd_build_boxes(self.el[k], None, self.params[k], b, self.ws_boxes)
         _check(lib().cd_build_tree(ctypes.byref(b.desc), self.tree_precision, 0,
                                    ctypes.byref(self.trees[k].desc), _ptr(self.ws_tree),

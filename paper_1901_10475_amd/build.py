@@ -18,13 +18,16 @@ BUILD = os.path.join(ROOT, "_build")
 ARCH = os.environ.get("CD4D_ARCH", "gfx950")
 
 LIB_SOURCES = ["k_boxes.hip", "k_sort.hip", "k_tree.hip", "k_refit.hip", "k_query.hip", "k_mlp.hip",
-               "k_narrow.hip", "k_refine.hip", "k_bands.hip", "k_noalloc.hip", "cd_api.cpp"]
+               "k_narrow.hip", "k_refine.hip", "k_bands.hip", "k_copy.hip", "k_noalloc.hip", "cd_api.cpp"]
 HOSTCHECK_SOURCES = ["cd_hostcheck.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
           "-Wall", "-Wno-unused-function"]
-# packed FP32 instructions are left out of every code object
-DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+# packed FP32 instructions are left out of every code object; multiply-adds
+# are fused only inside one expression (as written in the source), so that two
+# kernels running the same arithmetic get the same bits
+DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-ffp-contract=on"]
 
 
 def _compile(src, verbose):

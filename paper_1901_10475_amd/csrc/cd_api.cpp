@@ -115,15 +115,11 @@ struct Stage {
     }
 };
 
-// ---- launch shapes (cd_set_tuning) ----
-std::mutex g_tune_mu;
-cd_tuning g_tune = {2048, 256, 256, 0, 96};
+// ---- launch shapes (cd_set_tuning): per calling thread ----
+constexpr cd_tuning kDefaultTuning = {2048, 256, 256, 0, 96};
+thread_local cd_tuning g_tune = kDefaultTuning;
 
-cd_tuning tuning()
-{
-    std::lock_guard<std::mutex> g(g_tune_mu);
-    return g_tune;
-}
+cd_tuning tuning() { return g_tune; }
 
 constexpr int64_t kMaxBoxes = (1ll << 30) - 1;  // node ids of 2N - 1 nodes below 2^31
 constexpr size_t kTreeHeader = sizeof(TreeHeader);
@@ -439,6 +435,21 @@ const char *cd_last_error(void) { return g_err; }
 
 int cd_version(void) { return 1; }
 
+int cd_stream_copy(void *dst, const void *src, size_t bytes, cd_stream_t stream)
+{
+    if (bytes == 0)
+        return CD_OK;
+    if (!dst || !src)
+        return fail(CD_E_INVALID, "dst or src is NULL");
+    if ((bytes & 15u) || ((uintptr_t)dst & 15u) || ((uintptr_t)src & 15u))
+        return fail(CD_E_INVALID, "copy size and addresses must be multiples of 16 bytes");
+    const char *a = (const char *)src, *b = (const char *)dst;
+    if (a < b + bytes && b < a + bytes)
+        return fail(CD_E_INVALID, "source and destination overlap");
+    CD_HIP(launch_stream_copy(src, dst, (uint64_t)(bytes / 16), (hipStream_t)stream));
+    return CD_OK;
+}
+
 int cd_profile_enable(int on)
 {
     std::lock_guard<std::mutex> g(g_prof_mu);
@@ -607,12 +618,24 @@ int cd_build_boxes(const cd_elements *el, const uint32_t *dt_ticks, const cd_par
     out->obj_count = (uint32_t)n;
     out->slab_size = 0;
     out->slab_ticks = 0;
+    if (out->layout != CD_LAYOUT_OBJECT && out->layout != CD_LAYOUT_SORTED)
+        return fail(CD_E_INVALID, "unknown box layout %d", out->layout);
     if (n == 0) {
         if (out->count != 0)
             return fail(CD_E_INVALID, "out->count must be 0 for n = 0");
+        out->layout = CD_LAYOUT_OBJECT;
         return CD_OK;
     }
-    if (out->count > 0) {
+    if (out->records) {
+        if (out->precision != CD_FP64)
+            return fail(CD_E_INVALID, "box records are FP64");
+        if (!out->code)
+            return fail(CD_E_INVALID, "box records need the packed code array too");
+        if (dt_ticks)
+            return fail(CD_E_INVALID, "box records need a uniform step");
+        if ((uintptr_t)out->records & 15u)
+            return fail(CD_E_INVALID, "box records must be 16-byte aligned");
+    } else if (out->count > 0) {
         for (int d = 0; d < 3; ++d)
             if (!out->lo[d] || !out->hi[d])
                 return fail(CD_E_INVALID, "box array is NULL");
@@ -635,10 +658,11 @@ int cd_build_boxes(const cd_elements *el, const uint32_t *dt_ticks, const cd_par
     bo.code = out->code;
     bo.frame = w.frame;
     bo.cap = (uint64_t)out->count;
+    bo.rec = (Node64 *)out->records;
     out->code_valid = 0;
     Stage st_boxes("boxes", s);
     CD_HIP(launch_object_setup(*el, p->mu, (double)p->start_ticks * p->tick_s, w.oc, w.os, s));
-    if (out->code)
+    if (bo.code || bo.rec)
         CD_HIP(launch_orbit_frame(w.oc, (uint32_t)n, w.frame, s));
     double half_thr = 0.5 * p->threshold_km;
     if (!dt_ticks) {
@@ -648,11 +672,16 @@ int cd_build_boxes(const cd_elements *el, const uint32_t *dt_ticks, const cd_par
         if ((uint64_t)n * K != (uint64_t)out->count)
             return fail(CD_E_INVALID, "out->count %lld != n * K = %llu", (long long)out->count,
                         (unsigned long long)((uint64_t)n * K));
+        bool sorted = out->layout == CD_LAYOUT_SORTED && (bo.code || bo.rec) && n <= kSegCap;
+        if (bo.rec && !sorted)
+            return fail(CD_E_INVALID, "box records need the sorted layout (CD_LAYOUT_SORTED, "
+                                      "n <= %lld)", (long long)kSegCap);
         CD_HIP(launch_boxes_uniform(w.oc, w.os, (uint32_t)n, (uint32_t)K, p->dt_ticks, T,
-                                    p->tick_s, half_thr, out->precision, (int)p->box_rule, bo,
-                                    s));
+                                    p->tick_s, half_thr, out->precision, (int)p->box_rule,
+                                    sorted, bo, s));
         out->slab_ticks = p->dt_ticks;
         out->slab_size = n;
+        out->layout = sorted ? CD_LAYOUT_SORTED : CD_LAYOUT_OBJECT;
     } else {
         CD_HIP(launch_steps(dt_ticks, (uint32_t)n, T, w.cnt.st, w.cnt.Kc, w.cnt.total, w.cnt.bad,
                             s));
@@ -661,8 +690,9 @@ int cd_build_boxes(const cd_elements *el, const uint32_t *dt_ticks, const cd_par
         // out->count is the caller's box count; lanes past the real total return
         CD_HIP(launch_boxes_variable(w.oc, w.os, w.cnt.st, (uint32_t)n, T, p->tick_s, half_thr,
                                      out->precision, (int)p->box_rule, bo, s));
+        out->layout = CD_LAYOUT_OBJECT;
     }
-    out->code_valid = out->code ? 1 : 0;
+    out->code_valid = (bo.code || bo.rec) ? 1 : 0;
     return CD_OK;
 }
 
@@ -672,8 +702,15 @@ size_t cd_tree_bytes(int64_t count, int precision)
 {
     if (count <= 0)
         return kTreeHeader;
-    return tree_seeds_offset((uint64_t)count, precision) +
-           seed_cap((uint64_t)count) * sizeof(uint2);
+    return tree_leaf_esc_offset((uint64_t)count, precision) +
+           (precision == CD_FP64 ? (size_t)count * sizeof(uint32_t) : 0);
+}
+
+void *cd_tree_leaf_records(void *tree_mem, int64_t count)
+{
+    if (!tree_mem || count < 1)
+        return nullptr;
+    return (char *)tree_mem + kTreeHeader + (size_t)(count - 1) * sizeof(Node64);
 }
 
 size_t cd_build_tree_ws(int64_t count)
@@ -698,16 +735,28 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
         return fail(CD_E_INVALID, "box count < 0");
     if (N > kMaxBoxes)
         return fail(CD_E_OVERFLOW, "box count exceeds 2^31 - 1");
-    if (N > 0) {
+    if (!tree->mem || tree->bytes < cd_tree_bytes(N, precision))
+        return fail(CD_E_WORKSPACE, "tree buffer too small (%zu < %zu)", tree->bytes,
+                    cd_tree_bytes(N, precision));
+    if (boxes->records) {
+        // box records written into this tree's leaf-record area
+        if (boxes->records != cd_tree_leaf_records(tree->mem, N))
+            return fail(CD_E_INVALID, "box records must be the tree's own leaf records");
+        if (boxes->precision != CD_FP64 || precision != CD_FP64)
+            return fail(CD_E_INVALID, "box records need FP64 boxes and an FP64 tree");
+        if (!boxes->code)
+            return fail(CD_E_INVALID, "box records need the packed code array too");
+        if (boxes->layout != CD_LAYOUT_SORTED || !boxes->code_valid || boxes->slab_size <= 0 ||
+            boxes->slab_size > kSegCap || N % boxes->slab_size != 0 ||
+            (slab_ticks && slab_ticks != boxes->slab_ticks))
+            return fail(CD_E_INVALID, "box records need the sorted layout of a uniform step");
+    } else if (N > 0) {
         for (int d = 0; d < 3; ++d)
             if (!boxes->lo[d] || !boxes->hi[d])
                 return fail(CD_E_INVALID, "box array is NULL");
         if (!boxes->t0 || !boxes->t1 || !boxes->obj)
             return fail(CD_E_INVALID, "box tag array is NULL");
     }
-    if (!tree->mem || tree->bytes < cd_tree_bytes(N, precision))
-        return fail(CD_E_WORKSPACE, "tree buffer too small (%zu < %zu)", tree->bytes,
-                    cd_tree_bytes(N, precision));
     if (N > 0 && (!ws || ws_bytes < cd_build_tree_ws(N)))
         return fail(CD_E_WORKSPACE, "build-tree workspace too small");
     uint32_t horizon = boxes->horizon_ticks ? boxes->horizon_ticks : 0xFFFFFFFEu;
@@ -738,7 +787,40 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
     links.esc = precision == CD_FP32 ? nullptr : tw.esc;
     uint2 *kids = (uint2 *)((char *)tree->mem + tree_kids_offset((uint64_t)N, precision));
     const uint32_t *leaf_src = tw.idx;  // nullptr once the leaf records exist
-    if (seg) {
+    // boxes sorted within their slabs by their codes (cd_build_boxes with
+    // CD_LAYOUT_SORTED): no key sort; the hierarchy is built over the box
+    // codes and the refit reads each leaf's box from the box arrays in order
+    bool presorted = seg && boxes->layout == CD_LAYOUT_SORTED && bv.code;
+    bool in_place = boxes->records != nullptr;
+    if (in_place) {
+        // the leaf records are in place; the hierarchy comes from the packed
+        // codes, the leaves' skip links go to the side array (the records'
+        // code words keep the codes), and the refit checks every leaf's slab
+        uint32_t *side = (uint32_t *)((char *)tree->mem + tree_leaf_esc_offset((uint64_t)N,
+                                                                               precision));
+        links.leaf_esc = side;
+        links.first_leaf = (uint32_t)(N - 1);
+        links.leaf_stride = 1;
+        leaf_src = nullptr;
+        presorted = false;   // leaf records exist: the refit reads them
+        CD_HIP(launch_fill_u32(&((TreeHeader *)tree->mem)->leaf_esc_side, 1u, 1, s));
+        Stage st("karras", s);
+        if (N > 1)
+            CD_HIP(launch_karras_blocks(bv.code, nullptr, 1, (uint32_t)N,
+                                        (uint32_t)boxes->slab_size, w, kids, links, tw.parent,
+                                        tw.clev, err, s));
+        else
+            CD_HIP(launch_karras(tw.keys, (uint32_t)N, kids, links, tw.parent, tw.clev, true, s));
+    } else if (presorted) {
+        leaf_src = nullptr;
+        Stage st("karras", s);
+        if (N > 1)
+            CD_HIP(launch_karras_blocks(bv.code, bv.t0, 1, (uint32_t)N,
+                                        (uint32_t)boxes->slab_size, w, kids, links, tw.parent,
+                                        tw.clev, err, s));
+        else
+            CD_HIP(launch_karras(tw.keys, (uint32_t)N, kids, links, tw.parent, tw.clev, true, s));
+    } else if (seg) {
         uint32_t m = (uint32_t)boxes->slab_size;
         if (!bv.code) {
             Stage st("keys", s);
@@ -754,7 +836,7 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
         Stage st("karras", s);
         if (N > 1)
             CD_HIP(launch_karras_slabs((const uint32_t *)tw.keys, (uint32_t)N, m, kids, links,
-                                       tw.parent, tw.clev, s));
+                                       tw.parent, tw.clev, nullptr, 0, err, s));
         else
             CD_HIP(launch_karras(tw.keys, (uint32_t)N, kids, links, tw.parent, tw.clev, false, s));
     } else {
@@ -787,7 +869,8 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
         sink.items = (uint2 *)((char *)tree->mem + tree_seeds_offset((uint64_t)N, precision));
         sink.cap = (uint32_t)seed_cap((uint64_t)N);
         sink.hdr = (TreeHeader *)tree->mem;
-        CD_HIP(launch_refit(bv, boxes->precision, precision, (uint32_t)N, leaf_src, tw.parent,
+        CD_HIP(launch_refit(bv, boxes->precision, precision, (uint32_t)N, leaf_src, presorted,
+                            in_place ? (uint32_t)boxes->slab_size : 0u, w, tw.parent,
                             kids, links, tw.clev, tw.arrive, tw.list_items, tw.list_count,
                             nodes, sink, err, s));
     }
@@ -825,6 +908,9 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
     QueryWS w;
     layout_query(ws, ws_bytes, N, capacity, &w);
     TreeHeader *hdr = (TreeHeader *)tree->mem;
+    const unsigned int *side_on = &hdr->leaf_esc_side;
+    const uint32_t *side = (const uint32_t *)((const char *)tree->mem +
+                                              tree_leaf_esc_offset((uint64_t)N, tree->precision));
     const uint2 *seeds =
         (const uint2 *)((const char *)tree->mem + tree_seeds_offset((uint64_t)N, tree->precision));
     const uint2 *kids =
@@ -885,7 +971,7 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
             CD_HIP(launch_fill_u64(w.counter, 0ull, 1, s));
             CD_HIP(launch_traverse(nodes, tree->precision, (uint32_t)N, tree->slab_ticks, w.raw,
                                    (unsigned long long)capacity, w.counter, err, nullptr,
-                                   tu.walk_threads, s));
+                                   tu.walk_threads, side_on, side, s));
         }
     }
     unsigned int stw[3];
@@ -949,6 +1035,9 @@ int cd_query_pairs_async(const cd_tree *tree, cd_pair *out, int64_t capacity,
     QueryWS w;
     layout_query(ws, ws_bytes, N, capacity, &w);
     const TreeHeader *hdr = (const TreeHeader *)tree->mem;
+    const unsigned int *side_on = &hdr->leaf_esc_side;
+    const uint32_t *side = (const uint32_t *)((const char *)tree->mem +
+                                              tree_leaf_esc_offset((uint64_t)N, tree->precision));
     const uint2 *seeds =
         (const uint2 *)((const char *)tree->mem + tree_seeds_offset((uint64_t)N, tree->precision));
     const uint2 *kids =
@@ -978,7 +1067,7 @@ int cd_query_pairs_async(const cd_tree *tree, cd_pair *out, int64_t capacity,
             }
             CD_HIP(launch_query_decide(n_in, w.qflags, w.counter, walk, s));
             CD_HIP(launch_traverse(nodes, tree->precision, (uint32_t)N, tree->slab_ticks, w.raw,
-                                   cap, w.counter, err, walk, tu.walk_threads, s));
+                                   cap, w.counter, err, walk, tu.walk_threads, side_on, side, s));
         }
     }
     {
@@ -1002,7 +1091,7 @@ int cd_query_pairs_async(const cd_tree *tree, cd_pair *out, int64_t capacity,
 
 int cd_set_tuning(const cd_tuning *t)
 {
-    cd_tuning v = {2048, 256, 256, 0, 96};
+    cd_tuning v = kDefaultTuning;
     if (t) {
         auto lanes_ok = [](uint32_t x) { return x == 0 || x == 64 || x == 128 || x == 256; };
         auto expand_ok = [&](uint32_t x) { return lanes_ok(x) || x == 512 || x == 1024; };
@@ -1020,7 +1109,6 @@ int cd_set_tuning(const cd_tuning *t)
         if (t->max_levels)
             v.max_levels = t->max_levels;
     }
-    std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune = v;
     return CD_OK;
 }

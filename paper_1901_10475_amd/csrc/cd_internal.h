@@ -50,11 +50,21 @@ static_assert(sizeof(Node64) == 64, "Node64 layout");
 // Where the Karras pass leaves each node's (link, esc) for the refit: the
 // FP32 tree's own link records, or, for an FP64 tree (whose records get both
 // words from the refit, the link being the left child), the escapes alone.
+// When an FP64 tree's leaf records were written in place by the box build,
+// leaf escapes go straight into those records' escape words (leaf_esc, one
+// every leaf_stride words from leaf first_leaf on).
 struct LinkSink {
     Link *rec;       // FP32 tree link records, or nullptr
     uint32_t *esc;   // escapes only, when rec == nullptr
+    uint32_t *leaf_esc = nullptr;
+    uint32_t first_leaf = 0;
+    uint32_t leaf_stride = 1;
     __device__ void put(uint32_t id, uint32_t link, uint32_t e) const
     {
+        if (leaf_esc && id >= first_leaf) {
+            leaf_esc[(size_t)(id - first_leaf) * leaf_stride] = e;
+            return;
+        }
         if (rec) {
             Link l;
             l.link = link;
@@ -64,7 +74,12 @@ struct LinkSink {
             esc[id] = e;
         }
     }
-    __device__ uint32_t esc_of(uint32_t id) const { return rec ? rec[id].esc : esc[id]; }
+    __device__ uint32_t esc_of(uint32_t id) const
+    {
+        if (leaf_esc && id >= first_leaf)
+            return leaf_esc[(size_t)(id - first_leaf) * leaf_stride];
+        return rec ? rec[id].esc : esc[id];
+    }
 };
 
 static_assert(sizeof(Box32) == 32, "Box32 layout");
@@ -90,7 +105,12 @@ struct BoxOut {
     uint32_t *code;                        // Morton code of each box centre, or nullptr
     const unsigned long long *frame;       // code frame: ordered bits, min xyz, max xyz
     uint64_t cap;  // entries the arrays hold; stores beyond are dropped
+    // FP64 box records {lo[3], hi[3]; t0, t1, obj, code} (the layout of an
+    // FP64 tree's leaf records) written instead of the arrays, or nullptr
+    Node64 *rec;
 };
+// Word offsets of the tag fields inside a 64-byte box record (16 words).
+constexpr uint32_t kRecWords = 16, kRecT0 = 12, kRecT1 = 13, kRecObj = 14, kRecCode = 15;
 
 template <int PREC>
 __device__ inline void load_box(const BoxView &b, uint64_t k, double lo[3], double hi[3])
@@ -302,9 +322,19 @@ hipError_t launch_steps_apply_offsets(ObjSteps *st, const uint32_t *box_off, uin
 hipError_t launch_dt_heuristic(const cd_elements &el, double mu, double tick_s,
                                double max_disp, uint32_t T, uint32_t *dt_out, hipStream_t s);
 // rule: CD_BOX_SPEED, CD_BOX_INTERVAL_NU or CD_BOX_INTERVAL_E
+// Uniform step, time-major boxes.  sorted: within each block of
+// uniform_chunk(K) slabs the boxes follow the Morton order of their objects'
+// positions at the block's middle (codes = that order's keys; needs out.code
+// and out.frame and n <= kSegCap); otherwise box (i, k) at k n + i.
+uint32_t uniform_chunk(uint32_t K);
 hipError_t launch_boxes_uniform(const ObjConst *oc, const ObjSinus *os, uint32_t n, uint32_t K,
                                 uint32_t dt, uint32_t T, double tick_s, double half_thr,
-                                int precision, int rule, const BoxOut &out, hipStream_t s);
+                                int precision, int rule, bool sorted, const BoxOut &out,
+                                hipStream_t s);
+// Block b (entries [b stride, b stride + n), es words apart): sorts ucode
+// with the local ids 0..n-1 into scode / sobj (n <= kSegCap).
+hipError_t launch_block_sort(const uint32_t *ucode, uint32_t n, uint32_t nblocks, uint64_t stride,
+                             uint32_t es, uint32_t *scode, uint32_t *sobj, hipStream_t s);
 hipError_t launch_boxes_variable(const ObjConst *oc, const ObjSinus *os, const ObjSteps *st,
                                  uint32_t n, uint32_t T, double tick_s, double half_thr,
                                  int precision, int rule, const BoxOut &out, hipStream_t s);
@@ -331,6 +361,7 @@ hipError_t launch_first_witness(const cd_elements &el, double mu, double tick_s,
                                 uint64_t count, uint32_t *witness, unsigned long long *first,
                                 hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, size_t count, hipStream_t s);
+hipError_t launch_stream_copy(const void *src, void *dst, uint64_t words, hipStream_t s);
 // Sets the thread-local message of cd_last_error and returns code.
 int set_error(int code, const char *fmt, ...);
 hipError_t launch_fill_u64(unsigned long long *p, unsigned long long v, size_t count,
@@ -396,13 +427,16 @@ struct TreeHeader {
     uint32_t err;            // bit 0: slab hint / horizon violated, 1: refit, 2: traversal
     uint32_t nseeds;         // overlapping sibling pairs found by the refit
     uint32_t seed_overflow;  // set when more than seed_cap(N) pairs were found
-    uint32_t pad[61];
+    uint32_t leaf_esc_side;  // FP64: leaf skip links in the side array (records in place)
+    uint32_t pad[60];
 };
 static_assert(sizeof(TreeHeader) == 256, "TreeHeader layout");
 inline size_t seed_cap(uint64_t N) { return (size_t)(N / 4 + 4096); }
 // Tree buffer layout: header | nodes (FP64: 64-byte records; FP32: 32-byte
 // boxes, then 8-byte links) | kids[N - 1] (both children of each inner node)
-// | seeds[seed_cap(N)].
+// | seeds[seed_cap(N)] | FP64 only: leaf skip links[N] (used when the leaf
+// records were written in place by the box build, whose code words they
+// would otherwise overwrite).
 inline size_t tree_kids_offset(uint64_t N, int precision)
 {
     return sizeof(TreeHeader) + (size_t)(2 * N - 1) *
@@ -411,6 +445,10 @@ inline size_t tree_kids_offset(uint64_t N, int precision)
 inline size_t tree_seeds_offset(uint64_t N, int precision)
 {
     return tree_kids_offset(N, precision) + (size_t)(N > 1 ? N - 1 : 1) * 8u;
+}
+inline size_t tree_leaf_esc_offset(uint64_t N, int precision)
+{
+    return tree_seeds_offset(N, precision) + seed_cap(N) * 8u;
 }
 
 // Overlapping sibling pairs recorded while the refit forms each union: the
@@ -464,10 +502,19 @@ hipError_t launch_karras(const uint64_t *keys, uint32_t N, uint2 *kids, const Li
 // leaf links are written by the slab build
 hipError_t launch_karras_slabs(const uint32_t *codes, uint32_t N, uint32_t slab_size, uint2 *kids,
                                const LinkSink &links, uint32_t *parent, uint8_t *clev,
+                               const uint32_t *t0, uint32_t slab_ticks, unsigned int *err,
                                hipStream_t s);
+// Sorted-layout boxes (codes sorted in each slab, equal within blocks of
+// slabs): Karras nodes searched once per 8 slabs when the codes allow, leaf
+// skip links, and the order and slab checks.
+hipError_t launch_karras_blocks(const uint32_t *codes, const uint32_t *t0, uint32_t es,
+                                uint32_t N, uint32_t slab_size, uint32_t slab_ticks, uint2 *kids,
+                                const LinkSink &links, uint32_t *parent, uint8_t *clev,
+                                unsigned int *err, hipStream_t s);
 // idx == nullptr: the leaf records are already written (slab build).
 hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision, uint32_t N,
-                        const uint32_t *idx, const uint32_t *parent, const uint2 *kids,
+                        const uint32_t *idx, bool sorted_boxes,
+                        uint32_t check_m, uint32_t check_ticks, const uint32_t *parent, const uint2 *kids,
                         const LinkSink &links, const uint8_t *clev, unsigned int *arrive,
                         uint32_t *list_items, uint32_t *list_count, void *tree,
                         const SeedSink &seeds, unsigned int *err, hipStream_t s);
@@ -485,7 +532,7 @@ __device__ inline uint32_t xcd_block(uint32_t b, uint32_t nb)
 hipError_t launch_traverse(const void *tree, int precision, uint32_t N, uint32_t slab_ticks,
                            Rec *out, unsigned long long capacity, unsigned long long *counter,
                            unsigned int *err, const unsigned int *run_if, uint32_t threads,
-                           hipStream_t s);
+                           const unsigned int *side_on, const uint32_t *side, hipStream_t s);
 // One breadth-first level of the node-pair self-traversal: every pair in
 // `in` (count *n_in, at most in_cap) is expanded into the overlapping pairs of
 // its children; pairs of two leaves are emitted as records, the others queued

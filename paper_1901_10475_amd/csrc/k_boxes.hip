@@ -138,7 +138,7 @@ struct CodeFrame {
     {
         for (int d = 0; d < 3; ++d) {
             mn[d] = inv[d] = 0.0;
-            if (o.code) {
+            if (o.code || o.rec) {
                 mn[d] = from_ordered_bits(o.frame[d]);
                 double ext = from_ordered_bits(o.frame[3 + d]) - mn[d];
                 inv[d] = ext > 0.0 ? 1.0 / ext : 0.0;
@@ -147,21 +147,29 @@ struct CodeFrame {
     }
 };
 
+// A box's Morton code is that of its centre, unless the caller fixes it
+// (kNoCode: compute it).
+constexpr int64_t kNoCode = -1;
+
 template <int PREC>
 __device__ inline void store_box(const BoxOut &o, const CodeFrame &f, uint64_t b,
                                  const double pa[3], const double pb[3], const double blo[3],
-                                 const double bhi[3], uint32_t t0, uint32_t t1, uint32_t obj)
+                                 const double bhi[3], uint32_t t0, uint32_t t1, uint32_t obj,
+                                 int64_t code)
 {
     if (b >= o.cap)
         return;
+
     // Non-temporal stores: consecutive lanes write consecutive boxes, so each
     // store instruction fills whole cache lines of one array, and the boxes
     // are read again only by the tree build, long after they would have left
     // the caches (0.94 -> 0.78 ms for the 60.65 M boxes of the tracked hour).
     if (o.code)
-        __builtin_nontemporal_store(morton30(0.5 * (pa[0] + pb[0]), 0.5 * (pa[1] + pb[1]),
-                                            0.5 * (pa[2] + pb[2]), f.mn, f.inv),
-                                    &o.code[b]);
+        __builtin_nontemporal_store(
+            code != kNoCode ? (uint32_t)code
+                            : morton30(0.5 * (pa[0] + pb[0]), 0.5 * (pa[1] + pb[1]),
+                                       0.5 * (pa[2] + pb[2]), f.mn, f.inv),
+            &o.code[b]);
     for (int d = 0; d < 3; ++d) {
         double lo = blo[d];
         double hi = bhi[d];
@@ -178,14 +186,14 @@ __device__ inline void store_box(const BoxOut &o, const CodeFrame &f, uint64_t b
     __builtin_nontemporal_store(obj, &o.obj[b]);
 }
 
-// Intervals [k0, k1) of object i; box of interval k at index base + k * stride.
-template <int PREC, int RULE>
-__device__ inline void object_run(const ObjConst &c, const ObjSinus *os, uint32_t i,
-                                  uint64_t k0, uint64_t k1, uint64_t K, uint64_t dt, uint64_t T,
-                                  double tick_s, double half_thr, const BoxOut &out,
-                                  uint64_t base, uint64_t stride)
+// Intervals [k0, k1) of object i: each box is handed to sink(k, pa, pb, lo,
+// hi, t0, t1).  Both store forms (arrays, records) run this one loop, so
+// they hold the same bits.
+template <int RULE, class Sink>
+__device__ inline void object_steps(const ObjConst &c, const ObjSinus *os, uint32_t i,
+                                    uint64_t k0, uint64_t k1, uint64_t K, uint64_t dt,
+                                    uint64_t T, double tick_s, double half_thr, Sink &sink)
 {
-    const CodeFrame f(out);
     uint64_t ta = k0 * dt < T ? k0 * dt : T;
     EndPt A;
     A.M = c.m0 + c.n * ((double)ta * tick_s);
@@ -204,7 +212,7 @@ __device__ inline void object_run(const ObjConst &c, const ObjSinus *os, uint32_
         double lo[3], hi[3];
         box_bounds<RULE>(c, os, i, A, B, pa, pb, (double)(tb - ta) * tick_s, half_thr, lo, hi);
         uint32_t t1 = (k + 1 == K) ? (uint32_t)(T + 1) : (uint32_t)tb;
-        store_box<PREC>(out, f, base + k * stride, pa, pb, lo, hi, (uint32_t)ta, t1, i);
+        sink(k, pa, pb, lo, hi, (uint32_t)ta, t1);
         pa[0] = pb[0];
         pa[1] = pb[1];
         pa[2] = pb[2];
@@ -213,12 +221,133 @@ __device__ inline void object_run(const ObjConst &c, const ObjSinus *os, uint32_
     }
 }
 
+// Boxes to the arrays: box of interval k at index base + k * stride, with
+// Morton code `code` (kNoCode: the box centre's).
+template <int PREC>
+struct ArraySink {
+    const BoxOut &out;
+    CodeFrame f;
+    uint64_t base, stride;
+    uint32_t obj;
+    int64_t code;
+    __device__ void operator()(uint64_t k, const double pa[3], const double pb[3],
+                               const double lo[3], const double hi[3], uint32_t t0,
+                               uint32_t t1) const
+    {
+        store_box<PREC>(out, f, base + k * stride, pa, pb, lo, hi, t0, t1, obj, code);
+    }
+};
+
+template <int PREC, int RULE>
+__device__ inline void object_run(const ObjConst &c, const ObjSinus *os, uint32_t i,
+                                  uint64_t k0, uint64_t k1, uint64_t K, uint64_t dt, uint64_t T,
+                                  double tick_s, double half_thr, const BoxOut &out,
+                                  uint64_t base, uint64_t stride, int64_t code)
+{
+    ArraySink<PREC> sink{out, CodeFrame(out), base, stride, i, code};
+    object_steps<RULE>(c, os, i, k0, k1, K, dt, T, tick_s, half_thr, sink);
+}
+
+// Box records (FP64): each wave's 64 records of one interval (consecutive
+// slots, 4 KB) are staged in LDS and written back so that each store
+// instruction covers 1 KB of whole lines (non-temporal); the packed codes go
+// to their array as well.  Every lane of the block runs the loop (lanes past
+// n compute object 0 and store nothing), because a record's pieces are
+// stored by other lanes than the one that formed it.
+struct RecordSink {
+    const BoxOut &out;
+    uint32_t n, r0, obj, code;
+    bool valid;
+    uint4 *stage;   // this wave's 64 records
+    __device__ void operator()(uint64_t k, const double pa[3], const double pb[3],
+                               const double lo[3], const double hi[3], uint32_t t0,
+                               uint32_t t1) const
+    {
+        const uint32_t lane = threadIdx.x & 63;
+        if (valid && out.code)
+            __builtin_nontemporal_store(code, &out.code[k * n + r0 + lane]);
+        uint4 *mine = stage + 4 * lane;
+        mine[0] = make_uint4(__double2loint(lo[0]), __double2hiint(lo[0]), __double2loint(lo[1]),
+                             __double2hiint(lo[1]));
+        mine[1] = make_uint4(__double2loint(lo[2]), __double2hiint(lo[2]), __double2loint(hi[0]),
+                             __double2hiint(hi[0]));
+        mine[2] = make_uint4(__double2loint(hi[1]), __double2hiint(hi[1]), __double2loint(hi[2]),
+                             __double2hiint(hi[2]));
+        mine[3] = make_uint4(t0, t1, obj, code);
+        __syncthreads();
+        // piece q of the wave's 4 KB (record q / 4, quarter q % 4)
+        typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+        u32x4 *dst = (u32x4 *)(out.rec + k * n + r0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            uint32_t q = (uint32_t)j * 64 + lane;
+            if (r0 + (q >> 2) < n) {
+                uint4 v = stage[q];
+                u32x4 x = {v.x, v.y, v.z, v.w};
+                __builtin_nontemporal_store(x, dst + q);
+            }
+        }
+        __syncthreads();
+    }
+};
+
 template <int PREC, int RULE>
 __global__ __launch_bounds__(128) void k_boxes_uniform(const ObjConst *__restrict__ oc,
                                                        const ObjSinus *__restrict__ os,
                                                        uint32_t n, uint32_t K, uint32_t dt,
                                                        uint32_t T, double tick_s, double half_thr,
-                                                       uint32_t chunk, BoxOut out)
+                                                       uint32_t chunk, bool sorted, BoxOut out)
+{
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t k0 = (uint64_t)blockIdx.y * chunk;
+    if (k0 >= K)
+        return;
+    uint64_t k1 = k0 + chunk < K ? k0 + chunk : K;
+    if (PREC == CD_FP64 && out.rec) {
+        // records come with the sorted layout only (the launcher checks)
+        __shared__ uint4 stage_all[2 * 64 * 4];
+        bool valid = r < n;
+        uint32_t i = 0, code = 0;
+        if (valid) {
+            const uint32_t *w = (const uint32_t *)(out.rec + k0 * n + r);
+            i = w[kRecObj];
+            code = w[kRecCode];
+            valid = i < n;   // always: k_block_sort wrote a permutation
+            i = valid ? i : 0;
+        }
+        RecordSink sink{out, n, r - (threadIdx.x & 63), i, code, valid,
+                        stage_all + 4 * 64 * (threadIdx.x >> 6)};
+        object_steps<RULE>(oc[i], os, i, k0, k1, K, dt, T, tick_s, half_thr, sink);
+        return;
+    }
+    if (r >= n)
+        return;
+    uint32_t i = r;
+    int64_t code = kNoCode;
+    if (sorted) {
+        // rank r's object and code, left by k_block_sort in the obj and code
+        // entries of box k0 n + r (array entries, or record words), which
+        // this thread overwrites itself
+        if (out.rec) {
+            const uint32_t *w = (const uint32_t *)(out.rec + k0 * n + r);
+            i = w[kRecObj];
+            code = w[kRecCode];
+        } else {
+            i = out.obj[k0 * n + r];
+            code = out.code[k0 * n + r];
+        }
+        if (i >= n)   // cannot happen: k_block_sort wrote a permutation
+            return;
+    }
+    object_run<PREC, RULE>(oc[i], os, i, k0, k1, K, dt, T, tick_s, half_thr, out, r, n, code);
+}
+
+// Morton code (in the orbit frame) of object i's position at the middle of
+// block B of `chunk` slabs: the key of the block's per-object order.  Written
+// to ucode[(B * chunk * n + i) * stride].
+__global__ void k_block_codes(const ObjConst *__restrict__ oc, uint32_t n, uint32_t K,
+                              uint32_t dt, uint32_t T, double tick_s, uint32_t chunk,
+                              const unsigned long long *frame, uint32_t *ucode, uint32_t stride)
 {
     uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n)
@@ -227,7 +356,21 @@ __global__ __launch_bounds__(128) void k_boxes_uniform(const ObjConst *__restric
     if (k0 >= K)
         return;
     uint64_t k1 = k0 + chunk < K ? k0 + chunk : K;
-    object_run<PREC, RULE>(oc[i], os, i, k0, k1, K, dt, T, tick_s, half_thr, out, i, n);
+    uint64_t ta = k0 * dt < T ? k0 * dt : T;
+    uint64_t tb = k1 * dt < T ? k1 * dt : T;
+    ObjConst c = oc[i];
+    double M = c.m0 + c.n * (0.5 * (double)(ta + tb) * tick_s);
+    double E = M + c.e * sin(M), sE, cE;
+    kepler(M, c.e, E, sE, cE);
+    double p[3];
+    position(c, sE, cE, p);
+    double mn[3], inv[3];
+    for (int d = 0; d < 3; ++d) {
+        mn[d] = from_ordered_bits(frame[d]);
+        double ext = from_ordered_bits(frame[3 + d]) - mn[d];
+        inv[d] = ext > 0.0 ? 1.0 / ext : 0.0;
+    }
+    ucode[(k0 * n + i) * stride] = morton30(p[0], p[1], p[2], mn, inv);
 }
 
 // Per-object steps, object-major output (box off_i + k).  One lane per box, so
@@ -295,7 +438,7 @@ __global__ __launch_bounds__(256) void k_boxes_variable(const ObjConst *__restri
     box_bounds<RULE>(c, os, i, A, B, pa, pb, (double)(tb - ta) * tick_s, half_thr, blo, bhi);
     uint32_t t1 = (k + 1 == s.K) ? (uint32_t)(T + 1) : (uint32_t)tb;
     const CodeFrame f(out);
-    store_box<PREC>(out, f, b, pa, pb, blo, bhi, (uint32_t)ta, t1, i);
+    store_box<PREC>(out, f, b, pa, pb, blo, bhi, (uint32_t)ta, t1, i, kNoCode);
 }
 
 // After the interval counts have been scanned into first-box offsets.
@@ -390,28 +533,66 @@ hipError_t launch_dt_heuristic(const cd_elements &el, double mu, double tick_s,
 template <int PREC, int RULE>
 static void boxes_uniform(dim3 grid, hipStream_t s, const ObjConst *oc, const ObjSinus *os,
                           uint32_t n, uint32_t K, uint32_t dt, uint32_t T, double tick_s,
-                          double half_thr, uint32_t chunk, const BoxOut &out)
+                          double half_thr, uint32_t chunk, bool sorted, const BoxOut &out)
 {
     k_boxes_uniform<PREC, RULE><<<grid, 128, 0, s>>>(oc, os, n, K, dt, T, tick_s, half_thr,
-                                                     chunk, out);
+                                                     chunk, sorted, out);
 }
 
-hipError_t launch_boxes_uniform(const ObjConst *oc, const ObjSinus *os, uint32_t n, uint32_t K,
-                                uint32_t dt, uint32_t T, double tick_s, double half_thr,
-                                int precision, int rule, const BoxOut &out, hipStream_t s)
+uint32_t uniform_chunk(uint32_t K)
 {
-    if (n == 0 || K == 0)
-        return hipSuccess;
     // 8 consecutive intervals per thread (warm-started Kepler solves) measured
     // best: 0.73 ms for the 60.65 M boxes of the tracked hour against 0.79 ms
     // with 16 and 0.82-0.83 ms with 4 or 32
     uint32_t chunk = 8;
     while ((K + chunk - 1) / chunk > 65535u)
         chunk *= 2;
+    return chunk;
+}
+
+hipError_t launch_boxes_uniform(const ObjConst *oc, const ObjSinus *os, uint32_t n, uint32_t K,
+                                uint32_t dt, uint32_t T, double tick_s, double half_thr,
+                                int precision, int rule, bool sorted, const BoxOut &out,
+                                hipStream_t s)
+{
+    if (n == 0 || K == 0)
+        return hipSuccess;
+    uint32_t chunk = uniform_chunk(K);
     dim3 grid(blocks_for(n, 128), (K + chunk - 1) / chunk);
+    if (out.rec && !sorted)
+        return hipErrorInvalidValue;   // box records come in the sorted layout
+    if (sorted) {
+        // per block of `chunk` slabs: objects' codes at the block's middle
+        // into the t0 (arrays) or t1 (records) entries of the block's first
+        // slab, sorted with their ids into its code and obj entries; the box
+        // kernel rewrites all of them
+        if ((!out.code && !out.rec) || !out.frame || (uint64_t)n * K > out.cap)
+            return hipErrorInvalidValue;
+        uint32_t *u, *sc, *so, st;
+        if (out.rec) {
+            uint32_t *w = (uint32_t *)out.rec;
+            u = w + kRecT1;
+            sc = w + kRecCode;
+            so = w + kRecObj;
+            st = kRecWords;
+        } else {
+            u = out.t0;
+            sc = out.code;
+            so = out.obj;
+            st = 1;
+        }
+        k_block_codes<<<dim3(blocks_for(n, 256), grid.y), 256, 0, s>>>(oc, n, K, dt, T, tick_s,
+                                                                        chunk, out.frame, u, st);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess)
+            e = launch_block_sort(u, n, grid.y, (uint64_t)chunk * n, st, sc, so, s);
+        if (e != hipSuccess)
+            return e;
+    }
     auto go = [&](auto prec, auto rl) {
         boxes_uniform<decltype(prec)::value, decltype(rl)::value>(grid, s, oc, os, n, K, dt, T,
-                                                                  tick_s, half_thr, chunk, out);
+                                                                  tick_s, half_thr, chunk, sorted,
+                                                                  out);
     };
     dispatch_rule(precision, rule, go);
     return hipGetLastError();

@@ -96,16 +96,21 @@ struct Q<CD_FP32> {
     }
 };
 
+// An FP64 tree whose leaf records were written in place by the box build
+// keeps its leaf skip links in a side array (*side_on set by the build).
 template <int TP>
 __global__ __launch_bounds__(256) void k_traverse(const void *__restrict__ tree, uint32_t N,
                                                   uint32_t slab_ticks, Rec *__restrict__ out,
                                                   unsigned long long capacity,
                                                   unsigned long long *counter,
-                                                  unsigned int *err, const unsigned int *run_if)
+                                                  unsigned int *err, const unsigned int *run_if,
+                                                  const unsigned int *side_on,
+                                                  const uint32_t *__restrict__ side)
 {
     using F = typename Q<TP>::F;
     if (run_if && *run_if == 0)
         return;
+    const bool use_side = TP == CD_FP64 && side_on && *side_on;
     uint32_t blk = xcd_block(blockIdx.x, gridDim.x);
     uint32_t i = blk * blockDim.x + threadIdx.x;
     if (i >= N)
@@ -113,6 +118,8 @@ __global__ __launch_bounds__(256) void k_traverse(const void *__restrict__ tree,
     F qlo[3], qhi[3];
     uint32_t qt0, qt1, qobj, node;
     Q<TP>::load(tree, N, N - 1 + i, qlo, qhi, qt0, qt1, qobj, node);
+    if (use_side)
+        node = side[i];
     const uint64_t stop = (uint64_t)qt1 + slab_ticks - 1;
     const uint32_t limit = 2 * N + 2;
     const uint64_t lt = (threadIdx.x & 63) ? (~0ull >> (64 - (threadIdx.x & 63))) : 0ull;
@@ -129,6 +136,8 @@ __global__ __launch_bounds__(256) void k_traverse(const void *__restrict__ tree,
             break;
         bool ov = time_overlap(qt0, qt1, t0, t1) && space_overlap(qlo, qhi, lo, hi);
         bool leaf = node >= N - 1;
+        if (use_side && leaf)
+            esc = side[node - (N - 1)];
         bool hit = ov && leaf && link != qobj;
         uint64_t m = __ballot(hit);
         if (m) {
@@ -156,17 +165,17 @@ __global__ __launch_bounds__(256) void k_traverse(const void *__restrict__ tree,
 hipError_t launch_traverse(const void *tree, int precision, uint32_t N, uint32_t slab_ticks,
                            Rec *out, unsigned long long capacity, unsigned long long *counter,
                            unsigned int *err, const unsigned int *run_if, uint32_t threads,
-                           hipStream_t s)
+                           const unsigned int *side_on, const uint32_t *side, hipStream_t s)
 {
     if (N <= 1)
         return hipSuccess;
     unsigned g = nblk(N, threads);
     if (precision == CD_FP64)
         k_traverse<CD_FP64><<<g, threads, 0, s>>>(tree, N, slab_ticks, out, capacity, counter,
-                                                  err, run_if);
+                                                  err, run_if, side_on, side);
     else
         k_traverse<CD_FP32><<<g, threads, 0, s>>>(tree, N, slab_ticks, out, capacity, counter,
-                                                  err, run_if);
+                                                  err, run_if, nullptr, nullptr);
     return hipGetLastError();
 }
 

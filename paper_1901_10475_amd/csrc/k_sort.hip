@@ -281,54 +281,15 @@ hipError_t radix_sort16(SortKind kind, void *a, void *b, size_t count, const Dig
 
 constexpr int kSegWaves = kSegThreads / 64;
 
-template <int PREC, int TP, bool CODES>
-__global__ __launch_bounds__(kSegThreads) void k_slab_build(
-    BoxView b, uint32_t slab_size, uint32_t N, uint32_t slab_ticks,
-    const unsigned long long *bounds, uint32_t *__restrict__ codes_out, void *tree,
-    unsigned int *err)
+// Sorts the m <= kSegCap keys of one workgroup by 32-bit key, stably, in four
+// 8-bit digit passes; item j of lane `lane` of wave w is local index
+// w * 64 * kSegItems + j * 64 + lane, before and after.  val travels with
+// key.  xch: kSegCap words of LDS; cnt: kSegWaves * 257; wsum: 64.
+__device__ inline void lds_sort32(uint32_t (&key)[kSegItems], uint32_t (&val)[kSegItems],
+                                  uint32_t m, uint32_t *xch, uint32_t *cnt, uint32_t *wsum)
 {
-    __shared__ uint32_t xch[kSegCap];
-    // counters of (digit, wave), stored wave-major with a 257-word row (see
-    // k_radix_downsweep): index w * 257 + d
-    __shared__ uint32_t cnt[kSegWaves * 257];
-    __shared__ uint32_t wsum[64];
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint64_t slab = blockIdx.x;
-    uint64_t base = slab * slab_size;
-    uint32_t m = slab_size;
-    if (base + m > N)
-        m = base < N ? (uint32_t)(N - base) : 0u;
-    double mn[3], inv[3];
-    for (int d = 0; d < 3; ++d) {   // the frame is read only when codes are formed here
-        mn[d] = inv[d] = 0.0;
-        if (!CODES) {
-            mn[d] = from_ordered_bits(bounds[d]);
-            double ext = from_ordered_bits(bounds[3 + d]) - mn[d];
-            inv[d] = ext > 0.0 ? 1.0 / ext : 0.0;
-        }
-    }
-    uint32_t key[kSegItems], val[kSegItems];
     uint32_t li0 = (uint32_t)w * 64 * kSegItems + lane;
-    bool bad = false;
-#pragma unroll
-    for (int j = 0; j < kSegItems; ++j) {
-        uint32_t li = li0 + j * 64;
-        key[j] = 0xFFFFFFFFu;
-        if (li < m) {
-            if (CODES) {   // codes written with the boxes: 4 bytes instead of 48
-                key[j] = b.code[base + li];
-            } else {
-                double lo[3], hi[3];
-                load_box<PREC>(b, base + li, lo, hi);
-                key[j] = morton30(0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]),
-                                  0.5 * (lo[2] + hi[2]), mn, inv);
-            }
-            bad |= (b.t0[base + li] / slab_ticks) != slab;
-        }
-        val[j] = li;
-    }
-    if (bad)
-        atomicOr(err, 1u);
     uint64_t lt = lanemask_lt();
     for (int shift = 0; shift < 32; shift += 8) {
         for (int k = threadIdx.x; k < kSegWaves * 257; k += kSegThreads)
@@ -393,6 +354,57 @@ __global__ __launch_bounds__(kSegThreads) void k_slab_build(
                 val[j] = xch[li0 + j * 64];
         __syncthreads();
     }
+}
+
+template <int PREC, int TP, bool CODES>
+__global__ __launch_bounds__(kSegThreads) void k_slab_build(
+    BoxView b, uint32_t slab_size, uint32_t N, uint32_t slab_ticks,
+    const unsigned long long *bounds, uint32_t *__restrict__ codes_out, void *tree,
+    unsigned int *err)
+{
+    __shared__ uint32_t xch[kSegCap];
+    // counters of (digit, wave), stored wave-major with a 257-word row (see
+    // k_radix_downsweep): index w * 257 + d
+    __shared__ uint32_t cnt[kSegWaves * 257];
+    __shared__ uint32_t wsum[64];
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint64_t slab = blockIdx.x;
+    uint64_t base = slab * slab_size;
+    uint32_t m = slab_size;
+    if (base + m > N)
+        m = base < N ? (uint32_t)(N - base) : 0u;
+    double mn[3], inv[3];
+    for (int d = 0; d < 3; ++d) {   // the frame is read only when codes are formed here
+        mn[d] = inv[d] = 0.0;
+        if (!CODES) {
+            mn[d] = from_ordered_bits(bounds[d]);
+            double ext = from_ordered_bits(bounds[3 + d]) - mn[d];
+            inv[d] = ext > 0.0 ? 1.0 / ext : 0.0;
+        }
+    }
+    uint32_t key[kSegItems], val[kSegItems];
+    uint32_t li0 = (uint32_t)w * 64 * kSegItems + lane;
+    bool bad = false;
+#pragma unroll
+    for (int j = 0; j < kSegItems; ++j) {
+        uint32_t li = li0 + j * 64;
+        key[j] = 0xFFFFFFFFu;
+        if (li < m) {
+            if (CODES) {   // codes written with the boxes: 4 bytes instead of 48
+                key[j] = b.code[base + li];
+            } else {
+                double lo[3], hi[3];
+                load_box<PREC>(b, base + li, lo, hi);
+                key[j] = morton30(0.5 * (lo[0] + hi[0]), 0.5 * (lo[1] + hi[1]),
+                                  0.5 * (lo[2] + hi[2]), mn, inv);
+            }
+            bad |= (b.t0[base + li] / slab_ticks) != slab;
+        }
+        val[j] = li;
+    }
+    if (bad)
+        atomicOr(err, 1u);
+    lds_sort32(key, val, m, xch, cnt, wsum);
     // Leaf records.  Reading boxes by sorted position would gather 4-8 byte
     // words from all over the slab; instead each box is read in source order
     // (coalesced) and its whole record is written to its sorted slot.  LDS
@@ -442,6 +454,49 @@ __global__ __launch_bounds__(kSegThreads) void k_slab_build(
     }
 }
 
+
+// Per-object Morton order of each block of slabs: block B's unsorted codes
+// (code of object i at ucode[i * es]) are sorted with their object ids; rank
+// r's code and object go to scode[r * es] and sobj[r * es].  One workgroup
+// per block; blocks are `stride` entries (of es words) apart.
+__global__ __launch_bounds__(kSegThreads) void k_block_sort(const uint32_t *ucode, uint32_t n,
+                                                            uint64_t stride, uint32_t es,
+                                                            uint32_t *scode, uint32_t *sobj)
+{
+    __shared__ uint32_t xch[kSegCap];
+    __shared__ uint32_t cnt[kSegWaves * 257];
+    __shared__ uint32_t wsum[64];
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    uint64_t base = (uint64_t)blockIdx.x * stride;
+    uint32_t key[kSegItems], val[kSegItems];
+    uint32_t li0 = (uint32_t)w * 64 * kSegItems + lane;
+#pragma unroll
+    for (int j = 0; j < kSegItems; ++j) {
+        uint32_t li = li0 + j * 64;
+        key[j] = li < n ? ucode[(base + li) * es] : 0xFFFFFFFFu;
+        val[j] = li;
+    }
+    lds_sort32(key, val, n, xch, cnt, wsum);
+#pragma unroll
+    for (int j = 0; j < kSegItems; ++j) {
+        uint32_t r = li0 + j * 64;
+        if (r < n) {
+            scode[(base + r) * es] = key[j];
+            sobj[(base + r) * es] = val[j];
+        }
+    }
+}
+
+hipError_t launch_block_sort(const uint32_t *ucode, uint32_t n, uint32_t nblocks, uint64_t stride,
+                             uint32_t es, uint32_t *scode, uint32_t *sobj, hipStream_t s)
+{
+    if (n == 0 || nblocks == 0)
+        return hipSuccess;
+    if ((int64_t)n > kSegCap)
+        return hipErrorInvalidValue;
+    k_block_sort<<<nblocks, kSegThreads, 0, s>>>(ucode, n, stride, es, scode, sobj);
+    return hipGetLastError();
+}
 
 hipError_t launch_slab_build(const BoxView &b, int box_precision, int tree_precision,
                              uint32_t nslabs, uint32_t slab_size, uint32_t N,

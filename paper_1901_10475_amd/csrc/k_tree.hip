@@ -198,11 +198,16 @@ __global__ void k_karras(const uint64_t *__restrict__ keys, uint32_t N, uint2 *k
 // index lies in the slab (node i's searches always compare key i, a key of the
 // slab, so the slab-bits-only view of other slabs is exact).  The binary
 // searches then wait on LDS instead of L2.  Leaf skip links come from the
-// slab build.
+// slab build, or, for boxes that arrive already sorted within their slabs (t0
+// given), from here; the codes' order and every box's slab are then checked
+// (error bit 1, as the slab build reports a box outside its slab).
 __global__ __launch_bounds__(kSegThreads) void k_karras_slabs(const uint32_t *__restrict__ codes,
                                                               uint32_t N, uint32_t slab_size,
                                                               uint2 *kids, LinkSink links,
-                                                              uint32_t *parent, uint8_t *clev)
+                                                              uint32_t *parent, uint8_t *clev,
+                                                              const uint32_t *__restrict__ t0,
+                                                              uint32_t slab_ticks,
+                                                              unsigned int *err)
 {
     __shared__ uint32_t sk[kSegCap];
     uint64_t slab = blockIdx.x;
@@ -212,6 +217,16 @@ __global__ __launch_bounds__(kSegThreads) void k_karras_slabs(const uint32_t *__
         sk[k] = codes[base + k];
     __syncthreads();
     const SlabKeys32 K32{sk, (uint32_t)base, slab_size, (uint32_t)slab};
+    if (t0) {
+        bool bad = false;
+        for (uint32_t k = threadIdx.x; k < m; k += blockDim.x) {
+            uint32_t i = (uint32_t)(base + k);
+            bad |= (k + 1 < m && sk[k] > sk[k + 1]) || t0[i] / slab_ticks != slab;
+            links.put(N - 1 + i, 0, slab_escape32(K32, N, i));
+        }
+        if (bad)
+            atomicOr(err, 1u);
+    }
     for (uint32_t k = threadIdx.x; k < m; k += blockDim.x) {
         uint32_t i = (uint32_t)(base + k);
         if (i + 1 >= N)
@@ -229,6 +244,145 @@ __global__ __launch_bounds__(kSegThreads) void k_karras_slabs(const uint32_t *__
         kids[i] = make_uint2(nd.left, nd.right);
         links.put(i, nd.left, slab_escape32(K32, N, (uint32_t)nd.last));
     }
+}
+
+// Inner node i of a slab hierarchy, written out: children, refit level,
+// parent pointers and skip link.
+__device__ inline void put_inner(const SlabKeys32 &K, uint32_t N, uint32_t i,
+                                 const KarrasNode &nd, uint2 *kids, const LinkSink &links,
+                                 uint32_t *parent, uint8_t *clev)
+{
+    uint32_t lev = 0;
+    while ((uint64_t)(nd.first >> refit_shift(lev)) != (uint64_t)(nd.last >> refit_shift(lev)))
+        ++lev;
+    clev[i] = (uint8_t)lev;
+    uint32_t pv = i | (lev > 0 ? kCross : 0u);
+    parent[nd.left] = pv;
+    parent[nd.right] = pv;
+    if (i == 0)
+        parent[0] = kEnd;
+    kids[i] = make_uint2(nd.left, nd.right);
+    links.put(i, nd.left, slab_escape32(K, N, (uint32_t)nd.last));
+}
+
+// Karras over boxes already sorted within their slabs (the sorted layout),
+// kKarrasGroup consecutive slabs per workgroup.  Slabs of one block of the
+// layout carry the same codes in the same order, and when no two codes of a
+// slab are equal, an inner node strictly inside a slab (local index 1 .. m-2)
+// is decided by in-slab comparisons alone (every probe outside the slab
+// compares below its range's common prefix), so its children and range in
+// one slab are those of the first slab shifted by the slab offset: they are
+// searched once per group and written for every slab.  The two nodes at a
+// slab's ends (its subtree root and the node joining it to its neighbours)
+// are computed per slab.  A group whose slabs differ in their codes, or whose
+// first slab repeats a code, is computed slab by slab.  Every slab's codes
+// are checked for order and every box for its slab (error bit 1); leaf skip
+// links are written here.
+constexpr uint32_t kKarrasGroup = 8;
+
+__global__ __launch_bounds__(kSegThreads) void k_karras_blocks(
+    const uint32_t *codes, const uint32_t *__restrict__ t0, uint32_t es, uint32_t N,
+    uint32_t m, uint32_t slab_ticks, uint2 *kids, LinkSink links, uint32_t *parent,
+    uint8_t *clev, unsigned int *err)
+{
+    // codes and tags of box g at codes[g * es] and t0[g * es] (es = 1 for
+    // arrays, 16 for box records, whose code words the leaf escapes replace:
+    // every code a workgroup reads is read before its first escape store)
+    __shared__ uint32_t sk[kSegCap];
+    const uint32_t nslabs = N / m;
+    const uint32_t s0 = blockIdx.x * kKarrasGroup;
+    const uint32_t ns = nslabs - s0 < kKarrasGroup ? nslabs - s0 : kKarrasGroup;
+    const uint32_t base0 = s0 * m;
+    for (uint32_t k = threadIdx.x; k < m; k += blockDim.x)
+        sk[k] = codes[(size_t)(base0 + k) * es];
+    __syncthreads();
+    // the group's slabs against the first: same codes?  any repeated or
+    // decreasing code?  every box in its slab?
+    bool differs = false, dup = false, bad = false;
+    for (uint32_t k = threadIdx.x; k < m; k += blockDim.x) {
+        if (k + 1 < m) {
+            dup |= sk[k] == sk[k + 1];
+            bad |= sk[k] > sk[k + 1];
+        }
+        for (uint32_t q = 0; q < ns; ++q) {
+            size_t g = (size_t)(base0 + q * m + k) * es;
+            differs |= codes[g] != sk[k];
+            if (t0)   // (otherwise the refit checks the slabs of the leaf records)
+                bad |= t0[g] / slab_ticks != s0 + q;
+        }
+    }
+    bool templ = !__syncthreads_or(differs || dup);
+    if (bad)
+        atomicOr(err, 1u);
+    if (templ && m >= 3) {
+        const SlabKeys32 K0{sk, base0, m, s0};
+        for (uint32_t l = 1 + threadIdx.x; l + 1 < m; l += blockDim.x) {
+            KarrasNode nd0 = karras_node_u32(K0, N, base0 + l);
+            for (uint32_t q = 0; q < ns; ++q) {
+                const uint32_t base = base0 + q * m;
+                const uint32_t off = q * m;
+                KarrasNode nd = nd0;
+                nd.first += off;
+                nd.last += off;
+                nd.left += off;    // inner ids and leaf ids shift alike
+                nd.right += off;
+                const SlabKeys32 K{sk, base, m, s0 + q};
+                put_inner(K, N, base + l, nd, kids, links, parent, clev);
+            }
+        }
+        for (uint32_t x = threadIdx.x; x < 2 * ns; x += blockDim.x) {
+            const uint32_t q = x >> 1;
+            const uint32_t base = base0 + q * m;
+            const uint32_t i = base + ((x & 1u) ? m - 1 : 0u);
+            if (i + 1 >= N)
+                continue;
+            const SlabKeys32 K{sk, base, m, s0 + q};
+            put_inner(K, N, i, karras_node_u32(K, N, i), kids, links, parent, clev);
+        }
+        for (uint32_t q = 0; q < ns; ++q) {
+            const uint32_t base = base0 + q * m;
+            const SlabKeys32 K{sk, base, m, s0 + q};
+            for (uint32_t k = threadIdx.x; k < m; k += blockDim.x)
+                links.put(N - 1 + base + k, 0, slab_escape32(K, N, base + k));
+        }
+        return;
+    }
+    // slab by slab (codes reloaded per slab)
+    for (uint32_t q = 0; q < ns; ++q) {
+        const uint32_t base = base0 + q * m;
+        if (q > 0) {
+            __syncthreads();
+            for (uint32_t k = threadIdx.x; k < m; k += blockDim.x)
+                sk[k] = codes[(size_t)(base + k) * es];
+            __syncthreads();
+        }
+        const SlabKeys32 K{sk, base, m, s0 + q};
+        bool unordered = false;
+        for (uint32_t k = threadIdx.x; k < m; k += blockDim.x) {
+            unordered |= k + 1 < m && sk[k] > sk[k + 1];
+            uint32_t i = base + k;
+            links.put(N - 1 + i, 0, slab_escape32(K, N, i));
+            if (i + 1 < N)
+                put_inner(K, N, i, karras_node_u32(K, N, i), kids, links, parent, clev);
+        }
+        if (unordered)
+            atomicOr(err, 1u);
+    }
+}
+
+hipError_t launch_karras_blocks(const uint32_t *codes, const uint32_t *t0, uint32_t es,
+                                uint32_t N, uint32_t slab_size, uint32_t slab_ticks, uint2 *kids,
+                                const LinkSink &links, uint32_t *parent, uint8_t *clev,
+                                unsigned int *err, hipStream_t s)
+{
+    if (N <= 1 || slab_size == 0 || (int64_t)slab_size > kSegCap || N % slab_size ||
+        slab_ticks == 0)
+        return hipErrorInvalidValue;
+    uint32_t nslabs = N / slab_size;
+    uint32_t groups = (nslabs + kKarrasGroup - 1) / kKarrasGroup;
+    k_karras_blocks<<<groups, kSegThreads, 0, s>>>(codes, t0, es, N, slab_size, slab_ticks,
+                                                   kids, links, parent, clev, err);
+    return hipGetLastError();
 }
 
 __global__ void k_single_leaf(LinkSink links, uint32_t *parent)
@@ -252,12 +406,14 @@ hipError_t launch_karras(const uint64_t *keys, uint32_t N, uint2 *kids, const Li
 
 hipError_t launch_karras_slabs(const uint32_t *codes, uint32_t N, uint32_t slab_size, uint2 *kids,
                                const LinkSink &links, uint32_t *parent, uint8_t *clev,
+                               const uint32_t *t0, uint32_t slab_ticks, unsigned int *err,
                                hipStream_t s)
 {
-    if (N <= 1 || slab_size == 0 || (int64_t)slab_size > kSegCap)
+    if (N <= 1 || slab_size == 0 || (int64_t)slab_size > kSegCap || (t0 && slab_ticks == 0))
         return hipErrorInvalidValue;
     uint32_t nslabs = (uint32_t)((N + slab_size - 1) / slab_size);
-    k_karras_slabs<<<nslabs, kSegThreads, 0, s>>>(codes, N, slab_size, kids, links, parent, clev);
+    k_karras_slabs<<<nslabs, kSegThreads, 0, s>>>(codes, N, slab_size, kids, links, parent, clev,
+                                                  t0, slab_ticks, err);
     return hipGetLastError();
 }
 

@@ -31,11 +31,34 @@ def run_catalog(sc, box_precision=0, tree_precision=0, dt_array=None, capacity=N
     return bp, pairs.cpu().numpy().view(np.uint32).copy()
 
 
-def gpu_to_object_major(n, K):
-    """Index map: oracle box (i, k) at i*K + k  ->  time-major GPU machine k*n + i."""
-    i = np.repeat(np.arange(n), K)
-    k = np.tile(np.arange(K), n)
-    return k * n + i
+def gpu_to_object_major(obj, n, K):
+    """Index map: oracle box (i, k) at i*K + k  ->  its time-major GPU machine (slab
+    k at [k n, (k + 1) n), in whatever order the layout put the slab's
+    objects; obj = the GPU machines' object ids)."""
+    obj = np.asarray(obj, np.int64)
+    slab = np.arange(n * K, dtype=np.int64) // n
+    key = obj * K + slab
+    g = np.empty(n * K, np.int64)
+    g[key] = np.arange(n * K, dtype=np.int64)
+    return g
+
+
+def slab_positions(obj, n):
+    """pos[k * n + i] = index of object i's box in slab k (time-major boxes
+    in any per-slab order); obj may be a numpy array or a device tensor."""
+    import torch
+    if isinstance(obj, torch.Tensor):
+        o = obj.long()
+        N = o.numel()
+        b = torch.arange(N, device=o.device)
+        pos = torch.empty(N, dtype=torch.long, device=o.device)
+        pos[(b // n) * n + o] = b
+        return pos
+    o = np.asarray(obj, np.int64)
+    b = np.arange(len(o), dtype=np.int64)
+    pos = np.empty(len(o), np.int64)
+    pos[(b // n) * n + o] = b
+    return pos
 
 
 def assert_boxes_close(g_lo, g_hi, o_lo, o_hi, a_obj):

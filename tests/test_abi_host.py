@@ -41,7 +41,8 @@ def test_sizes_are_host_only_and_monotone():
     # header, 2N-1 node records, children of the N-1 inner nodes, and room for
     # the overlapping sibling pairs the refit records
     seeds = (10 // 4 + 4096) * 8
-    assert L.cd_tree_bytes(10, cd.CD_FP64) == 256 + 19 * 64 + 9 * 8 + seeds
+    # (FP64: plus a skip link per leaf, for leaf records written in place)
+    assert L.cd_tree_bytes(10, cd.CD_FP64) == 256 + 19 * 64 + 9 * 8 + seeds + 10 * 4
     assert L.cd_tree_bytes(10, cd.CD_FP32) == 256 + 19 * 40 + 9 * 8 + seeds
     assert L.cd_build_tree_ws(1000) < L.cd_build_tree_ws(100000)
     assert L.cd_query_pairs_ws(10, 1000) < L.cd_query_pairs_ws(10, 100000)
@@ -211,3 +212,69 @@ def test_tuning_ranges():
         assert cd.cd_get_tuning()["expand_threads"] == ok
     cd.cd_set_tuning(None)
     assert cd.cd_get_tuning() == base
+
+
+def test_stream_copy_argument_errors():
+    """Checked on the host before any launch: misaligned sizes or addresses,
+    overlap, NULL pointers; a zero-byte copy does nothing."""
+    import paper_1901_10475_amd as cd
+    L = cd.lib()
+    assert L.cd_stream_copy(None, None, 0, None) == cd.CD_OK
+    assert L.cd_stream_copy(None, ctypes.c_void_p(4096), 16, None) == cd.CD_E_INVALID
+    assert L.cd_stream_copy(ctypes.c_void_p(8192), ctypes.c_void_p(4096), 17, None) == \
+        cd.CD_E_INVALID
+    assert L.cd_stream_copy(ctypes.c_void_p(8200), ctypes.c_void_p(4096), 16, None) == \
+        cd.CD_E_INVALID
+    assert L.cd_stream_copy(ctypes.c_void_p(4096 + 16), ctypes.c_void_p(4096), 64, None) == \
+        cd.CD_E_INVALID
+    assert "overlap" in L.cd_last_error().decode()
+
+
+def test_tuning_is_per_thread():
+    """Launch shapes set by one thread are not seen by another (no shared
+    state between concurrent callers); NULL restores the defaults."""
+    import threading
+    import paper_1901_10475_amd as cd
+    cd.cd_set_tuning({"expand_blocks": 512, "expand_threads": 128})
+    try:
+        seen = {}
+
+        def other():
+            seen["t"] = cd.cd_get_tuning()
+            cd.cd_set_tuning({"walk_threads": 64})
+
+        th = threading.Thread(target=other)
+        th.start()
+        th.join()
+        assert seen["t"]["expand_blocks"] == 2048 and seen["t"]["expand_threads"] == 256
+        mine = cd.cd_get_tuning()
+        assert mine["expand_blocks"] == 512 and mine["expand_threads"] == 128
+        assert mine["walk_threads"] == 256
+    finally:
+        cd.cd_set_tuning(None)
+    assert cd.cd_get_tuning()["expand_blocks"] == 2048
+
+
+def test_tree_leaf_records_and_record_argument_errors():
+    """The leaf-record area of an FP64 tree buffer (pure pointer arithmetic),
+    and box records refused before any launch where they cannot be used."""
+    import paper_1901_10475_amd as cd
+    L = cd.lib()
+    L.cd_tree_leaf_records.restype = ctypes.c_void_p
+    assert L.cd_tree_leaf_records(ctypes.c_void_p(1 << 20), 10) == (1 << 20) + 256 + 9 * 64
+    assert L.cd_tree_leaf_records(ctypes.c_void_p(1 << 20), 0) is None
+    assert L.cd_tree_leaf_records(None, 10) is None
+    el = cd.cd_elements()
+    el.n = 0
+    p = cd.params_struct(1e-3, 398600.4418, 1.0, 100, 10)
+    b = cd.cd_boxes()
+    b.precision = cd.CD_FP32
+    b.records = 1 << 20
+    # n = 0 is accepted before the record checks; n = 1 with FP32 records is not
+    for name in ("a", "e", "inc", "raan", "argp", "m0"):
+        setattr(el, name, 4096)
+    el.n = 1
+    b.count = 10
+    rc = L.cd_build_boxes(ctypes.byref(el), None, ctypes.byref(p), ctypes.byref(b), None, 0,
+                          None)
+    assert rc == cd.CD_E_INVALID and "FP64" in L.cd_last_error().decode()

@@ -21,7 +21,7 @@ import torch
 import oracle
 from paper_1901_10475_amd import catalog
 from tests.gpu_util import (arrays_of, device_boxes_to_oracle, need_gpu, say,
-                            window_index)
+                            slab_positions, window_index)
 
 pytestmark = pytest.mark.gpu
 
@@ -57,8 +57,9 @@ def test_tracked_hour_every_record():
     k = pairs[:, 2].astype(np.int64) // dt
     assert np.all(pairs[:, 2].astype(np.int64) == k * dt)
     assert np.all(pairs[:, 3] == np.where(k == K - 1, T + 1, (k + 1) * dt))
-    ia = torch.from_numpy(k * n + pairs[:, 0].astype(np.int64)).cuda()
-    ib = torch.from_numpy(k * n + pairs[:, 1].astype(np.int64)).cuda()
+    pos = slab_positions(arr[4], n)    # object i's box in slab k, any slab order
+    ia = pos[torch.from_numpy(k * n + pairs[:, 0].astype(np.int64)).cuda()]
+    ib = pos[torch.from_numpy(k * n + pairs[:, 1].astype(np.int64)).cuda()]
     lo, hi = arr[0], arr[1]
     ok = torch.ones(len(pairs), dtype=torch.bool, device="cuda")
     for d in range(3):

@@ -61,7 +61,7 @@ def _run(sc, rule, dt=None, start=0, box_precision=cd.CD_FP64, tree_precision=cd
 def _host_object_major(bp, sc, dt):
     lo, hi, t0, t1, obj = bp.boxes.to_host()
     if dt is None:
-        g = gpu_to_object_major(sc.n, oracle.intervals(sc.dt_ticks, sc.horizon_ticks))
+        g = gpu_to_object_major(obj, sc.n, oracle.intervals(sc.dt_ticks, sc.horizon_ticks))
         lo, hi, t0, t1, obj = lo[g], hi[g], t0[g], t1[g], obj[g]
     return lo, hi, t0, t1, obj
 

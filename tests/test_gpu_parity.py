@@ -10,7 +10,7 @@ import pytest
 import oracle
 from paper_1901_10475_amd import catalog
 from tests.gpu_util import (assert_boxes_close, gpu_to_object_major, need_gpu,
-                            records_of_boxes, run_catalog, say)
+                            records_of_boxes, run_catalog, say, slab_positions)
 
 pytestmark = pytest.mark.gpu
 
@@ -32,7 +32,7 @@ def test_boxes_uniform_step(n, T, dt):
     ob = _oracle_boxes(sc)
     K = oracle.intervals(dt, T)
     assert bp.count == len(ob) == n * K
-    g = gpu_to_object_major(n, K)
+    g = gpu_to_object_major(obj, n, K)
     assert np.array_equal(t0[g], ob.t0) and np.array_equal(t1[g], ob.t1)
     assert np.array_equal(obj[g], ob.obj)
     assert_boxes_close(lo[g], hi[g], ob.lo, ob.hi, sc.elements[ob.obj, 0])
@@ -219,7 +219,8 @@ def test_tracked_hour_full_size_sampled(rule):
     # include boxes that do have partners, so the sample is not all-empty
     if len(pairs):
         pick = pairs[rng.choice(len(pairs), min(64, len(pairs)), replace=False)]
-        extra = [(int(t) // 1000) * 16848 + int(i) for i, _, t, _ in pick]
+        pos = slab_positions(obj, 16848)
+        extra = [pos[(int(t) // 1000) * 16848 + int(i)] for i, _, t, _ in pick]
         sample = np.unique(np.concatenate([sample, extra]))
     want = oracle.pairs_of(ob, sample)
     got = records_of_boxes(pairs, obj, t0, t1, sample)
@@ -237,7 +238,8 @@ def test_tracked_hour_full_size_sampled(rule):
     # box bounds of sampled boxes against the oracle's own construction
     ob_i = np.unique(obj[sample])[:16]
     sub = oracle.boxes(sc.elements[ob_i], 1000, sc.horizon_ticks, sc.tick_s, 1.0, rule=rule)
-    g = np.concatenate([np.arange(3600) * 16848 + i for i in ob_i])
+    pos = slab_positions(obj, 16848)
+    g = np.concatenate([pos[np.arange(3600) * 16848 + i] for i in ob_i])
     assert_boxes_close(lo[g], hi[g], sub.lo, sub.hi, sc.elements[obj[g], 0])
 
 
@@ -304,7 +306,7 @@ def test_window_boxes_and_pairs(start):
         ob = oracle.boxes(sc.elements, sc.dt_ticks if dt is None else dt, sc.horizon_ticks,
                           sc.tick_s, sc.threshold_km, start=start)
         if dt is None:
-            g = gpu_to_object_major(sc.n, oracle.intervals(sc.dt_ticks, sc.horizon_ticks))
+            g = gpu_to_object_major(obj, sc.n, oracle.intervals(sc.dt_ticks, sc.horizon_ticks))
             lo, hi, t0, t1, obj = lo[g], hi[g], t0[g], t1[g], obj[g]
         assert np.array_equal(t0, ob.t0) and np.array_equal(t1, ob.t1)
         assert np.array_equal(obj, ob.obj)
@@ -328,8 +330,9 @@ def test_box_codes_change_tree_shape_not_records(heur):
     out = []
     for codes in (True, False):
         for tp in (cd.CD_FP64, cd.CD_FP32):
+            # boxes as arrays here, so that their codes can be read afterwards
             bp = cd.BroadPhase(sc.n, p, None, cd.CD_FP64, tp, codes=codes,
-                               dt_heuristic_km=heur, el_soa=el)
+                               dt_heuristic_km=heur, el_soa=el, in_tree=False)
             out.append((codes, tp, bp.run(el).cpu().numpy().copy()))
             if codes:
                 c = bp.boxes.code[:bp.count].cpu().numpy().view(np.uint32)
@@ -339,3 +342,7 @@ def test_box_codes_change_tree_shape_not_records(heur):
     assert np.array_equal(by[(True, cd.CD_FP64)], by[(False, cd.CD_FP64)])
     assert np.array_equal(by[(True, cd.CD_FP32)], by[(False, cd.CD_FP32)])
     assert len(by[(True, cd.CD_FP64)]) > 0
+    # FP64 boxes written as the tree's own leaf records (uniform step only)
+    bp = cd.BroadPhase(sc.n, p, None, cd.CD_FP64, cd.CD_FP64, dt_heuristic_km=heur, el_soa=el)
+    assert bp.in_tree == (heur is None)
+    assert np.array_equal(bp.run(el).cpu().numpy(), by[(True, cd.CD_FP64)])

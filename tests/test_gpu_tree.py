@@ -10,7 +10,8 @@ Covered: uniform steps, where the boxes of each interval form one slab that
 one workgroup sorts in LDS before the Karras pass over the slab codes and the
 chunked refit (slabs of 1, 2, 300 and 17 408 boxes, the largest one workgroup
 sorts, and 70 000 slabs of 3; 17 409 objects per interval take the device-wide
-sort instead); per-object steps (the general path: one radix
+sort instead), or that arrives already in Morton order (the sorted layout:
+no sort; the refit reads the leaves from the box arrays); per-object steps (the general path: one radix
 sort of all keys); FP64 and FP32 trees; boxes with and without Morton codes.
 
 Tree buffer layout read here: a 256-byte header (error bits, seed count, seed
@@ -22,6 +23,7 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 import paper_1901_10475_amd as cd
 from paper_1901_10475_amd import catalog
 from tests.gpu_util import need_gpu, say
@@ -55,6 +57,12 @@ def _decode(tree, N, prec):
     ns = int(hdr[1])
     ns = min(ns, N // 4 + 4096)
     seeds = raw[seeds_off:seeds_off + ns * 8].copy().view(np.uint32).reshape(ns, 2)
+    if prec == cd.CD_FP64 and hdr[3]:
+        # leaf records written in place by the box build: the leaves' skip
+        # links are in the side array after the seeds (the records hold codes)
+        side_off = seeds_off + (N // 4 + 4096) * 8
+        esc = esc.copy()
+        esc[N - 1:] = raw[side_off:side_off + 4 * N].copy().view(np.uint32)
     return dict(err=int(hdr[0]), overflow=int(hdr[2]), lo=lo, hi=hi, t0=t0, t1=t1, link=link,
                 esc=esc, kids=kids.astype(np.int64), seeds=seeds)
 
@@ -129,36 +137,147 @@ def check_tree(bp):
 
 
 def _uniform(n, K, dt, seed=0, box_precision=cd.CD_FP64, tree_precision=cd.CD_FP64,
-             codes=True):
+             codes=True, layout=cd.CD_LAYOUT_SORTED, in_tree=True, build=True):
     """n LEO objects, K intervals of dt one-second ticks, threshold 1 km."""
     rng = np.random.default_rng(seed)
     el = catalog.leo_mix(rng, n)
     p = cd.params_struct(1.0, catalog.MU_EARTH, 1.0, K * dt - 1, dt)
     bp = cd.BroadPhase(n, p, box_precision=box_precision, tree_precision=tree_precision,
-                       codes=codes)
-    bp.build(cd.soa(el))
+                       codes=codes, layout=layout, in_tree=in_tree)
+    bp.el_soa = cd.soa(el)
+    if build:
+        bp.build(bp.el_soa)
     return bp
 
 
+@pytest.mark.parametrize("layout,in_tree", [(cd.CD_LAYOUT_OBJECT, False),
+                                            (cd.CD_LAYOUT_SORTED, False),
+                                            (cd.CD_LAYOUT_SORTED, True)])
 @pytest.mark.parametrize("n,K", [(1, 50), (2, 40), (300, 60), (17408, 3), (17409, 3),
-                                 (3, 70000)])
-def test_uniform_step_trees(n, K):
+                                 (3, 70000), (257, 17)])
+def test_uniform_step_trees(n, K, layout, in_tree):
+    """Object order: the slab build sorts each slab; sorted layout: the boxes
+    arrive in their slabs' Morton order and no sort runs, as arrays (the refit
+    writes the leaf records) or as the tree's own leaf records (17 409 objects
+    per slab exceed one workgroup and fall back to object order)."""
     need_gpu()
-    say("tree invariants, uniform steps, n", n, "K", K)
-    bp = _uniform(n, K, 2, seed=n)
+    say("tree invariants, uniform steps, n", n, "K", K, "layout", layout, "in tree", in_tree)
+    bp = _uniform(n, K, 2, seed=n, layout=layout, in_tree=in_tree)
     assert bp.count == n * K
+    want = layout if n <= 17408 else cd.CD_LAYOUT_OBJECT
+    assert bp.boxes.desc.layout == want
+    assert bp.in_tree == (in_tree and want == cd.CD_LAYOUT_SORTED)
     say("seeds", check_tree(bp))
 
 
+@pytest.mark.parametrize("layout", [cd.CD_LAYOUT_OBJECT, cd.CD_LAYOUT_SORTED])
 @pytest.mark.parametrize("box_prec,tree_prec,codes", [(cd.CD_FP64, cd.CD_FP32, True),
                                                       (cd.CD_FP32, cd.CD_FP32, True),
                                                       (cd.CD_FP64, cd.CD_FP64, False)])
-def test_uniform_step_tree_precisions(box_prec, tree_prec, codes):
+def test_uniform_step_tree_precisions(box_prec, tree_prec, codes, layout):
     need_gpu()
-    say("tree invariants, precisions", box_prec, tree_prec, "codes", codes)
+    say("tree invariants, precisions", box_prec, tree_prec, "codes", codes, "layout", layout)
     bp = _uniform(500, 40, 30, seed=7, box_precision=box_prec, tree_precision=tree_prec,
-                  codes=codes)
+                  codes=codes, layout=layout, in_tree=False)
+    assert bp.boxes.desc.layout == (layout if codes else cd.CD_LAYOUT_OBJECT)
     check_tree(bp)
+
+
+@pytest.mark.parametrize("n,K", [(300, 60), (1000, 17), (1, 9), (16848, 20)])
+def test_sorted_layout_order(n, K):
+    """Sorted layout: every slab holds each object once; inside each block of 8
+    slabs the order (and the codes) is the same in every slab and the codes
+    are non-decreasing; the boxes and the record list equal the object
+    layout's."""
+    need_gpu()
+    say("sorted layout, n", n, "K", K)
+    a = _uniform(n, K, 2, seed=n + 5, layout=cd.CD_LAYOUT_OBJECT, in_tree=False)
+    b = _uniform(n, K, 2, seed=n + 5, layout=cd.CD_LAYOUT_SORTED, in_tree=False)
+    # the same boxes written as the tree's leaf records, read before the tree
+    # build turns their code words into skip links
+    c = _uniform(n, K, 2, seed=n + 5, layout=cd.CD_LAYOUT_SORTED, in_tree=True, build=False)
+    assert c.in_tree
+    cd.cd_build_boxes(c.el_soa, None, c.params, c.boxes, c.ws_boxes)
+    assert c.boxes.desc.code_valid == 1 and c.boxes.desc.layout == cd.CD_LAYOUT_SORTED
+    # the two store forms run one loop (and multiply-adds are fused only as
+    # written), so they hold the same bits
+    same_bits = True
+    for arr in ("lo", "hi"):
+        x, y = getattr(b.boxes, arr)[:, :n * K], getattr(c.boxes, arr)
+        rel = ((x - y).abs() / x.abs().clamp(min=6000.0)).max().item()
+        assert rel <= 1e-15, (arr, rel)
+        same_bits &= bool(torch.equal(x, y))
+    assert same_bits
+    for arr in ("t0", "t1", "obj", "code"):
+        assert torch.equal(getattr(b.boxes, arr)[:n * K], getattr(c.boxes, arr))
+    cd.cd_build_tree(c.boxes, c.tree_precision, c.tree, c.ws_tree)
+    check_tree(c)
+    assert b.boxes.desc.layout == cd.CD_LAYOUT_SORTED and b.boxes.desc.code_valid == 1
+    N = n * K
+    obj = b.boxes.obj[:N].cpu().numpy().view(np.uint32).reshape(K, n)
+    code = b.boxes.code[:N].cpu().numpy().view(np.uint32).reshape(K, n)
+    assert np.all(np.sort(obj, axis=1) == np.arange(n)[None, :])
+    assert np.all(np.diff(code.astype(np.int64), axis=1) >= 0)
+    for k in range(K):
+        k0 = (k // 8) * 8
+        assert np.array_equal(obj[k], obj[k0]) and np.array_equal(code[k], code[k0])
+    # same boxes, object by object
+    oa = a.boxes.obj[:N].cpu().numpy().view(np.uint32).reshape(K, n)
+    assert np.all(oa == np.arange(n)[None, :])
+    inv = np.argsort(obj, axis=1) + (np.arange(K) * n)[:, None]
+    for arr in ("lo", "hi"):
+        ga = getattr(a.boxes, arr)[:, :N].cpu().numpy()
+        gb = getattr(b.boxes, arr)[:, :N].cpu().numpy()
+        assert np.array_equal(ga, gb[:, inv.ravel()])
+    for arr in ("t0", "t1"):
+        ga = getattr(a.boxes, arr)[:N].cpu().numpy()
+        gb = getattr(b.boxes, arr)[:N].cpu().numpy()
+        assert np.array_equal(ga, gb[inv.ravel()])
+    ra = a.query().cpu().numpy()
+    rb = b.query().cpu().numpy()
+    rc = c.query().cpu().numpy().view(np.uint32)
+    assert np.array_equal(ra, rb)
+    if same_bits:
+        assert np.array_equal(ra, rc)
+    # the records of the in-place leaves against the oracle on those boxes
+    lo, hi, t0, t1, obj = c.boxes.to_host()
+    assert np.array_equal(rc, oracle.pairs_bucketed(oracle.Boxes(lo, hi, t0, t1, obj)))
+
+
+def test_sorted_layout_with_unsorted_codes_is_reported():
+    """Boxes that claim the sorted layout but whose codes are out of order in
+    a slab: the tree build flags it and the query reports CD_E_INVALID."""
+    need_gpu()
+    b = _uniform(300, 16, 2, seed=3, layout=cd.CD_LAYOUT_SORTED, in_tree=False)
+    c = b.boxes.code
+    lo, hi = int(c[5 * 300].item()), int(c[5 * 300 + 299].item())
+    assert lo < hi
+    c[5 * 300] = hi
+    c[5 * 300 + 299] = lo
+    cd.cd_build_tree(b.boxes, b.tree_precision, b.tree, b.ws_tree)
+    with pytest.raises(cd.CDError) as ei:
+        cd.cd_query_pairs(b.tree, b.out, b.capacity, b.ws_query)
+    assert ei.value.status == cd.CD_E_INVALID
+    # records in place: a packed code out of order is reported the same way;
+    # a record outside its slab is reported by the refit
+    r = _uniform(300, 16, 2, seed=3, layout=cd.CD_LAYOUT_SORTED, in_tree=True)
+    want = r.query().cpu().numpy()
+    cd.cd_build_tree(r.boxes, r.tree_precision, r.tree, r.ws_tree)   # again: same list
+    assert np.array_equal(r.query().cpu().numpy(), want)
+    c = r.boxes.code
+    lo, hi = int(c[7 * 300].item()), int(c[7 * 300 + 299].item())
+    c[7 * 300], c[7 * 300 + 299] = hi, lo
+    cd.cd_build_tree(r.boxes, r.tree_precision, r.tree, r.ws_tree)
+    with pytest.raises(cd.CDError) as ei:
+        cd.cd_query_pairs(r.tree, r.out, r.capacity, r.ws_query)
+    assert ei.value.status == cd.CD_E_INVALID
+    r.boxes.code[7 * 300], r.boxes.code[7 * 300 + 299] = lo, hi
+    t0 = int(r.boxes.t0[5 * 300 + 17].item())
+    r.boxes.t0[5 * 300 + 17] = t0 + 2          # one tick past its slab of 2 ticks
+    cd.cd_build_tree(r.boxes, r.tree_precision, r.tree, r.ws_tree)
+    with pytest.raises(cd.CDError) as ei:
+        cd.cd_query_pairs(r.tree, r.out, r.capacity, r.ws_query)
+    assert ei.value.status == cd.CD_E_INVALID
 
 
 def test_per_object_step_tree():
