@@ -96,6 +96,7 @@ def compulsory_bytes(stage, N, P, tree_prec, box_prec, per_object_dt=False,
         "sort": N * 24,                        # keys and indices read and written once
         "karras": N * 16,                      # children and parents written
         "refit": N * 2 * leaf,                 # one sibling box read, one node box written
+        "hierarchy": N * (16 + 2 * leaf),      # hierarchy and refit in one pass
         "traverse": (N - 1) * node + N * leaf + P * 16,   # every node once, records out
         "canon": P * 32,                       # records read and written once
     }
@@ -126,6 +127,10 @@ def design_bytes(stage, N, n, P, tree_prec, box_prec, sorted_layout=False):
                                                              # boxes in, leaf records out),
                                                              # parents, kids and escapes in;
                                                              # inner records out
+        "hierarchy": N * (node + 4) + (N - 1) * (node + 8) + N * 4,
+                                                             # bottom-up pass: leaf records
+                                                             # and codes in; inner records,
+                                                             # children, leaf skip links out
         "traverse": nodes * node + P * 16,                   # every node read once,
                                                              # records out
         "canon": P * 16 * 3,

@@ -18,7 +18,8 @@ BUILD = os.path.join(ROOT, "_build")
 ARCH = os.environ.get("CD4D_ARCH", "gfx950")
 
 LIB_SOURCES = ["k_boxes.hip", "k_sort.hip", "k_tree.hip", "k_refit.hip", "k_query.hip", "k_mlp.hip",
-               "k_narrow.hip", "k_refine.hip", "k_bands.hip", "k_copy.hip", "k_noalloc.hip", "cd_api.cpp"]
+               "k_narrow.hip", "k_refine.hip", "k_bands.hip", "k_copy.hip", "k_noalloc.hip", "k_agglo.hip",
+               "cd_api.cpp"]
 HOSTCHECK_SOURCES = ["cd_hostcheck.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I", os.path.join(ROOT, "include"), "-I", CSRC,
@@ -45,7 +46,8 @@ def _compile(src, verbose):
 
 
 def _link(objs, out, verbose):
-    cmd = ["hipcc", "-shared", "-fPIC", "--offload-arch=" + ARCH] + objs + ["-o", out + ".tmp"]
+    cmd = (["hipcc", "-shared", "-fPIC", "-Wl,--no-undefined", "--offload-arch=" + ARCH] + objs
+           + ["-o", out + ".tmp"])
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

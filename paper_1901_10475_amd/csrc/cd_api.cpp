@@ -242,6 +242,8 @@ struct TreeWS {
     uint64_t *keys;
     uint32_t *idx, *parent, *arrive, *list_items, *list_count;
     uint8_t *clev;
+    uint8_t *group_templ;   // per group of slabs: Karras nodes shared (sorted layout)
+    void *agglo;            // bottom-up build (in-place leaf records)
     uint32_t *esc;   // escapes of an FP64 tree's nodes, for the refit
     unsigned long long *bounds;
     void *radix;
@@ -261,6 +263,8 @@ size_t layout_tree(void *base, size_t bytes, int64_t N, TreeWS *w)
     w->list_items = c.take<uint32_t>(slots * kRefitListCap);
     w->list_count = c.take<uint32_t>(slots);
     w->clev = c.take<uint8_t>(n);
+    w->group_templ = c.take<uint8_t>(n / 8 + 1);
+    w->agglo = c.take_bytes(agglo_ws_bytes((uint32_t)n));
     w->esc = c.take<uint32_t>(2 * n);
     w->bounds = c.take<unsigned long long>(6);
     w->radix = c.take_bytes(radix_ws_bytes(n));
@@ -792,32 +796,29 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
     // codes and the refit reads each leaf's box from the box arrays in order
     bool presorted = seg && boxes->layout == CD_LAYOUT_SORTED && bv.code;
     bool in_place = boxes->records != nullptr;
+    SeedSink sink;
+    sink.items = (uint2 *)((char *)tree->mem + tree_seeds_offset((uint64_t)N, precision));
+    sink.cap = (uint32_t)seed_cap((uint64_t)N);
+    sink.hdr = (TreeHeader *)tree->mem;
     if (in_place) {
-        // the leaf records are in place; the hierarchy comes from the packed
-        // codes, the leaves' skip links go to the side array (the records'
-        // code words keep the codes), and the refit checks every leaf's slab
+        // the leaf records are in place: hierarchy, inner boxes and skip links
+        // in one bottom-up pass over the packed codes; the leaves' skip links
+        // go to the side array (the records' code words keep the codes)
         uint32_t *side = (uint32_t *)((char *)tree->mem + tree_leaf_esc_offset((uint64_t)N,
                                                                                precision));
-        links.leaf_esc = side;
-        links.first_leaf = (uint32_t)(N - 1);
-        links.leaf_stride = 1;
-        leaf_src = nullptr;
-        presorted = false;   // leaf records exist: the refit reads them
         CD_HIP(launch_fill_u32(&((TreeHeader *)tree->mem)->leaf_esc_side, 1u, 1, s));
-        Stage st("karras", s);
-        if (N > 1)
-            CD_HIP(launch_karras_blocks(bv.code, nullptr, 1, (uint32_t)N,
-                                        (uint32_t)boxes->slab_size, w, kids, links, tw.parent,
-                                        tw.clev, err, s));
-        else
-            CD_HIP(launch_karras(tw.keys, (uint32_t)N, kids, links, tw.parent, tw.clev, true, s));
-    } else if (presorted) {
+        Stage st("hierarchy", s);
+        CD_HIP(launch_agglo(bv.code, (uint32_t)boxes->slab_size, w, (uint32_t)N, nodes, kids,
+                            side, tw.agglo, sink, err, s));
+        return CD_OK;
+    }
+    if (presorted) {
         leaf_src = nullptr;
         Stage st("karras", s);
         if (N > 1)
-            CD_HIP(launch_karras_blocks(bv.code, bv.t0, 1, (uint32_t)N,
-                                        (uint32_t)boxes->slab_size, w, kids, links, tw.parent,
-                                        tw.clev, err, s));
+            CD_HIP(launch_karras_blocks(bv.code, bv.t0, (uint32_t)N,
+                                        (uint32_t)boxes->slab_size, w, tw.group_templ, kids,
+                                        links, tw.parent, tw.clev, err, s));
         else
             CD_HIP(launch_karras(tw.keys, (uint32_t)N, kids, links, tw.parent, tw.clev, true, s));
     } else if (seg) {
@@ -865,12 +866,8 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
     }
     {
         Stage st("refit", s);
-        SeedSink sink;
-        sink.items = (uint2 *)((char *)tree->mem + tree_seeds_offset((uint64_t)N, precision));
-        sink.cap = (uint32_t)seed_cap((uint64_t)N);
-        sink.hdr = (TreeHeader *)tree->mem;
         CD_HIP(launch_refit(bv, boxes->precision, precision, (uint32_t)N, leaf_src, presorted,
-                            in_place ? (uint32_t)boxes->slab_size : 0u, w, tw.parent,
+                            0u, w, tw.parent,
                             kids, links, tw.clev, tw.arrive, tw.list_items, tw.list_count,
                             nodes, sink, err, s));
     }

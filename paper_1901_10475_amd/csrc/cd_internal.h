@@ -473,6 +473,36 @@ struct SeedSink {
     }
 };
 constexpr int kSeedStage = 256;  // LDS-staged seeds per workgroup before a flush
+
+// Per-workgroup seed staging: lanes append to LDS; a full stage or the end of
+// the kernel flushes it with one global atomic.
+struct SeedStage {
+    uint2 *buf;            // LDS, kSeedStage entries
+    unsigned int *n;       // LDS counter
+    __device__ void push(const SeedSink &sink, uint32_t a, uint32_t b) const
+    {
+        unsigned int k = atomicAdd(n, 1u);
+        if (k < (unsigned)kSeedStage) {
+            buf[k] = make_uint2(a, b);
+        } else {  // stage full: this one goes straight out
+            uint2 one = make_uint2(a, b);
+            sink.put_many(&one, 1, sink.reserve(1));
+        }
+    }
+    // all threads of the block call this after the last push
+    __device__ void flush(const SeedSink &sink, unsigned int *base_lds) const
+    {
+        __syncthreads();
+        uint32_t m = *n < (unsigned)kSeedStage ? *n : (unsigned)kSeedStage;
+        if (threadIdx.x == 0)
+            *base_lds = m ? sink.reserve(m) : 0u;
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < m; k += blockDim.x)
+            if (*base_lds + k < sink.cap)
+                sink.items[*base_lds + k] = buf[k];
+    }
+};
+
 constexpr int kRefitLevelThreads = 256;  // queue levels (measured: 64, 128, 256, 512, 1024)
 
 struct RefitLists {
@@ -507,10 +537,19 @@ hipError_t launch_karras_slabs(const uint32_t *codes, uint32_t N, uint32_t slab_
 // Sorted-layout boxes (codes sorted in each slab, equal within blocks of
 // slabs): Karras nodes searched once per 8 slabs when the codes allow, leaf
 // skip links, and the order and slab checks.
-hipError_t launch_karras_blocks(const uint32_t *codes, const uint32_t *t0, uint32_t es,
-                                uint32_t N, uint32_t slab_size, uint32_t slab_ticks, uint2 *kids,
-                                const LinkSink &links, uint32_t *parent, uint8_t *clev,
-                                unsigned int *err, hipStream_t s);
+hipError_t launch_karras_blocks(const uint32_t *codes, const uint32_t *t0, uint32_t N,
+                                uint32_t slab_size, uint32_t slab_ticks, uint8_t *templ,
+                                uint2 *kids, const LinkSink &links, uint32_t *parent,
+                                uint8_t *clev, unsigned int *err, hipStream_t s);
+// Hierarchy and inner boxes in one bottom-up pass (k_agglo.hip) over FP64
+// leaf records already in place in key order (keys: slab j / slab_size above
+// code[j]): inner records, child pairs, leaf skip links (leaf_esc, one per
+// leaf), refit seeds; the leaves' slabs (t0 / slab_ticks) and the key order
+// are checked (error bit 1).  ws: agglo_ws_bytes(N).
+size_t agglo_ws_bytes(uint32_t N);
+hipError_t launch_agglo(const uint32_t *code, uint32_t slab_size, uint32_t slab_ticks,
+                        uint32_t N, void *nodes, uint2 *kids, uint32_t *leaf_esc, void *ws,
+                        const SeedSink &seeds, unsigned int *err, hipStream_t s);
 // idx == nullptr: the leaf records are already written (slab build).
 hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision, uint32_t N,
                         const uint32_t *idx, bool sorted_boxes,

@@ -254,4 +254,118 @@ __host__ __device__ inline uint32_t slab_escape32(const SlabKeys32 &k, uint32_t 
     return right ? s : N - 1 + s;
 }
 
+// ---- bottom-up construction of the same tree -----------------------------------
+//
+// A node covering leaves [f, l] is the left child of its parent when keys l
+// and l+1 share a longer prefix than keys f-1 and f (the parent is [f, l'],
+// split after leaf l), else the right child (parent [f', l], split after
+// f-1); with positions breaking equal keys the two prefixes always differ.
+// Its id in the numbering above: leaf N-1+f when f == l, else l for a left
+// child and f for a right child (the root, [0, N-1], is 0).
+
+// Common prefix of keys a (at position i) and b (at j), equal keys broken by
+// position: clz of the 64-bit XOR, or 96 + clz of the 32-bit position XOR
+// (i != j); written as selects, without branches.
+__host__ __device__ inline int key_prefix(uint64_t a, uint64_t b, uint32_t i, uint32_t j)
+{
+    uint64_t x = a ^ b;
+    uint32_t h = (uint32_t)(x >> 32), l = (uint32_t)x, p = i ^ j;
+    int ch = h ? __builtin_clz(h) : 0, cl = l ? __builtin_clz(l) : 0;
+    int cp = p ? __builtin_clz(p) : 0;
+    return h ? ch : (l ? 32 + cl : 96 + cp);
+}
+
+// key(j) = (j / ms) << 32 | code[j]: time slabs of ms leaves above 32-bit codes.
+struct CodeKeys {
+    const uint32_t *code;
+    uint32_t ms, N;
+    __host__ __device__ uint64_t key(uint32_t j) const
+    {
+        return ((uint64_t)(j / ms) << 32) | code[j];
+    }
+    __host__ __device__ int delta(uint32_t i, uint32_t j) const
+    {
+        return j >= N ? -1 : key_prefix(key(i), key(j), i, j);
+    }
+};
+
+// The same keys for the positions lo, lo + 1, ... held in a window sk (lo may
+// wrap below 0: such positions are outside [0, N) and never read).
+struct WindowKeys {
+    const uint64_t *sk;
+    uint32_t lo, N;
+    __host__ __device__ int delta(uint32_t i, uint32_t j) const
+    {
+        return j >= N ? -1 : key_prefix(sk[i - lo], sk[j - lo], i, j);
+    }
+};
+
+// Adjacent prefixes a(j) = delta(j, j+1), -1 at j = N-1 and below 0, held
+// as a(j) + 1 in one byte each (at most 128) for the positions lo, lo + 1, ...
+// A node's parent side, its sibling's shape and the skip links need only these.
+struct AdjBytes {
+    const uint8_t *d;
+    uint32_t lo, N;
+    __host__ __device__ int at(uint32_t j) const { return j >= N - 1 ? -1 : (int)d[j - lo] - 1; }
+};
+
+// karras_escape from adjacent prefixes: node s = r + 1 extends right when
+// a(s) >= a(s - 1).
+template <class A>
+__host__ __device__ inline uint32_t escape_adj(const A &a, uint32_t N, uint32_t r)
+{
+    if (r >= N - 1)
+        return kEnd;
+    uint32_t s = r + 1;
+    if (s <= N - 2 && a.at(s) >= a.at(s - 1))
+        return s;
+    return N - 1 + s;
+}
+
+// Children of the inner node [f, l] split after leaf g.
+__host__ __device__ inline uint2 agglo_children(uint32_t N, uint32_t f, uint32_t l, uint32_t g)
+{
+    return make_uint2(f == g ? N - 1 + g : g, l == g + 1 ? N - 1 + g + 1 : g + 1);
+}
+
+// Where node [f, l] (not the root) meets its sibling, from dl = a(f - 1) and
+// dr = a(l).
+struct AggloStep {
+    bool right;      // a left child: the parent extends right
+    int prefix;      // key bits the parent's leaves share
+    uint32_t id;     // the node's own id
+    uint32_t split;  // the parent's split: after leaf l (right) or f - 1
+};
+__host__ __device__ inline AggloStep agglo_step(int dl, int dr, uint32_t N, uint32_t f,
+                                                uint32_t l)
+{
+    AggloStep st;
+    st.right = dr > dl;
+    st.prefix = st.right ? dr : dl;
+    st.id = f == l ? N - 1 + f : (st.right ? l : f);
+    st.split = st.right ? l : f - 1;
+    return st;
+}
+
+// Whether the sibling is the single leaf next to the node (l + 1 or f - 1):
+// it is when that leaf's own parent is this node's parent.  Otherwise the
+// sibling is the inner node numbered by that same position (a right child is
+// numbered by its first leaf, a left child by its last).
+template <class A>
+__host__ __device__ inline bool agglo_sibling_is_leaf(const A &a, const AggloStep &st,
+                                                      uint32_t f, uint32_t l)
+{
+    return st.right ? st.prefix > a.at(l + 1) : st.prefix > a.at(f - 2);
+}
+
+// Does the parent of node [f, l] lie within leaves [b0, b1)?  (The node does.)
+template <class V>
+__host__ __device__ inline bool agglo_parent_within(const V &k, uint32_t N, const AggloStep &st,
+                                                    uint32_t f, uint32_t l, uint64_t b0,
+                                                    uint64_t b1)
+{
+    return st.right ? (b1 >= N || k.delta(l, (uint32_t)b1) < st.prefix)
+                    : (b0 == 0 || k.delta(f, (uint32_t)(b0 - 1)) < st.prefix);
+}
+
 } // namespace cd

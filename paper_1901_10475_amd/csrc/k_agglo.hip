@@ -1,0 +1,500 @@
+// k_agglo.hip -- hierarchy, inner boxes and skip links in one bottom-up pass,
+// over leaf records that are already in place in key order.
+//
+// The tree is the AABB tree of Sec. 3.2 over 4D boxes, with the key of leaf j
+// being its time slab (j / m for slabs of m leaves) above the 30-bit Morton
+// code of its centre, as in the top-down build (k_tree.hip).  The same binary
+// radix tree can be found from the leaves up (Apetrei 2014): a node covering
+// leaves [f, l] is the left child of its parent when keys l and l+1 share a
+// longer prefix than keys f-1 and f (the parent is then [f, l'], split after
+// leaf l) and the right child otherwise (parent [f', l], split after f-1).
+// Every split between two neighbouring leaves belongs to exactly one inner
+// node, so it is where that node's two children meet; as in the atomic refit,
+// the second child to arrive goes on with the union of the two boxes and
+// records the pair when the two overlap (a seed of the node-pair traversal).
+// Ties cannot occur: with positions breaking equal keys, the prefixes on the
+// two sides of a node always differ.  A node's parent side, its sibling's
+// shape and every skip link follow from the adjacent prefixes
+// a(j) = delta(j, j+1) alone.
+//
+// Node ids are those of the top-down build: an inner node is numbered by the
+// last leaf of its range when it is a left child, by the first when it is a
+// right child, and the root is 0.  So the tree written here (records, child
+// pairs, skip links, leaf skip links in the side array) is the same tree, and
+// the build needs none of the per-node binary searches nor the parent, level
+// and skip-link arrays that pass the top-down hierarchy to the refit.
+//
+// Passes: one workgroup per chunk of C consecutive items, every meeting held
+// in LDS.  A chunk's nodes whose parents reach outside it (a split at the
+// chunk's edge, or a split whose other child never arrives) are its roots;
+// they are handed up, in position order, as the items of the next pass, which
+// builds the tree above them the same way (the adjacent prefix between two
+// consecutive roots is the one between their end leaves).  Pass 1's items are
+// the leaves; the pass whose items fit one chunk forms the root.  The item
+// counts of later passes stay on the device: each later pass is launched for
+// a bound on its count, as a small grid that strides over the chunks holding
+// items.
+#include "cd_internal.h"
+
+namespace cd {
+
+namespace {
+
+inline unsigned nblk(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
+
+constexpr int kAggChunk = 1024;
+constexpr int kAggOut = 256;   // roots one chunk may hand up
+constexpr int kAggScanThreads = 1024;
+
+// A node handed to the next pass: leaf range, id, and the adjacent prefixes
+// after its first and after its last leaf, a(f) + 1 | (a(l) + 1) << 8.
+struct AggItem {
+    uint32_t f, l, id, a;
+};
+static_assert(sizeof(AggItem) == 16, "AggItem layout");
+
+__device__ inline void load_record(const Node64 *nodes, uint32_t id, double lo[3], double hi[3],
+                                   uint32_t &t0, uint32_t &t1)
+{
+    NodeIO<CD_FP64>::get_box(nodes, 0, id, lo, hi, t0, t1);
+}
+
+// The node at one item position in LDS (64 bytes, four 16-byte words laid
+// out as an FP64 tree record's bounds and tags): its box, its other range
+// end and packed = (dl + 1) | (dr + 1) << 8 | split << 16, with dl and dr the
+// adjacent prefixes before its first and after its last item and split its
+// split relative to the chunk (kNoSplit: the item itself, not yet replaced by
+// a node formed here).
+struct alignas(16) SlotRec {
+    double lo[3], hi[3];
+    uint32_t t0, t1, other, packed;
+};
+static_assert(sizeof(SlotRec) == 64, "SlotRec layout");
+constexpr uint32_t kNoSplit = 0xFFFFu;
+constexpr int kAggSteps = 3;   // merges per round before a climber is parked
+
+__device__ inline uint32_t pack_ends(int dl, int dr, uint32_t split)
+{
+    return (uint32_t)(dl + 1) | ((uint32_t)(dr + 1) << 8) | (split << 16);
+}
+
+__device__ inline void put_slot(SlotRec &r, const double lo[3], const double hi[3], uint32_t t0,
+                                uint32_t t1, uint32_t other, uint32_t packed)
+{
+    SlotRec v;
+    for (int d = 0; d < 3; ++d) {
+        v.lo[d] = lo[d];
+        v.hi[d] = hi[d];
+    }
+    v.t0 = t0;
+    v.t1 = t1;
+    v.other = other;
+    v.packed = packed;
+    r = v;
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// LDS of one chunk pass.
+template <int C, bool LEAVES>
+struct AggShared {
+    uint8_t sa[C + 4];                // a(last leaf) + 1, items C0 - 2 .. C0 + m
+    uint8_t sf[LEAVES ? 1 : C + 1];   // a(first leaf) + 1, items C0 .. C0 + m
+    uint32_t itf[LEAVES ? 1 : C], itl[LEAVES ? 1 : C], itd[LEAVES ? 1 : C];
+    SlotRec rec[C];
+    unsigned int cnt[C / 4];          // four 8-bit arrival counts per word
+    uint32_t park[2][C / 4];          // parked climbers (slots), alternate rounds
+    uint2 sbuf[kSeedStage];
+    AggItem pst[kAggOut];
+    unsigned int sn, sbase, pn, npark[2];
+};
+
+}  // namespace
+
+// One chunk of one pass over M items (LEAVES: the N leaves themselves), C
+// threads, one item per thread.  Every meeting is in LDS: a step is the
+// arrival atomic on the split's count (1: the left child arrived, 2: the
+// right child, 3: both) and one 64-byte read of the sibling's slot.  A slot
+// first holds its item; the node formed with that position as its id end
+// overwrites it (by then the item's parent is formed, and only an ancestor of
+// an item can end at it).  Climbs run in rounds of kAggSteps merges: a
+// climber still going after that many is parked in its node's slot, and the
+// next round resumes the parked ones packed into the first lanes, so the
+// sparse top of the chunk's tree costs one wave rather than every wave.
+// Roots go to out[chunk][0 .. kAggOut) in position order, their count to
+// out_count[chunk].
+template <int C, bool LEAVES>
+__device__ void agglo_chunk(AggShared<C, LEAVES> &S, uint32_t chunk, uint32_t M, CodeKeys G,
+                            uint32_t slab_ticks, const AggItem *__restrict__ in,
+                            Node64 *__restrict__ nodes, uint2 *__restrict__ kids,
+                            uint32_t *__restrict__ leaf_esc, AggItem *__restrict__ out,
+                            uint32_t *__restrict__ out_count, const SeedSink &seeds,
+                            bool &bad, bool &misplaced)
+{
+    const SeedStage stage{S.sbuf, &S.sn};
+    const uint32_t N = G.N, t = threadIdx.x, C0 = chunk * (uint32_t)C;
+    const uint32_t m = M - C0 < (uint32_t)C ? M - C0 : (uint32_t)C;
+    const uint32_t wlo = C0 - 2;   // LDS window: items C0 - 2 .. C0 + m
+    double lo[3], hi[3];
+    uint32_t t0 = 0, t1 = 0;
+    if (LEAVES && t < m) {   // the leaf record's box, in flight with the codes
+        load_record(nodes, N - 1 + C0 + t, lo, hi, t0, t1);
+        misplaced |= t0 / slab_ticks != (C0 + t) / G.ms;
+    }
+    for (uint32_t k = t; k < m + 3; k += C) {
+        const uint32_t K = wlo + k;
+        if (LEAVES) {   // a(j) and the key order, from the codes
+            uint8_t v = 0;
+            if (K < N - 1) {
+                const uint64_t a = G.key(K), b = G.key(K + 1);
+                v = (uint8_t)(key_prefix(a, b, K, K + 1) + 1);
+                misplaced |= a > b;
+            }
+            S.sa[k] = v;
+        } else {
+            const AggItem it = K < M ? in[K] : AggItem{0, 0, 0, 0};
+            S.sa[k] = (uint8_t)(it.a >> 8);
+            if (k >= 2) {
+                S.sf[k - 2] = (uint8_t)it.a;
+                if (k - 2 < m) {
+                    S.itf[k - 2] = it.f;
+                    S.itl[k - 2] = it.l;
+                    S.itd[k - 2] = it.id;
+                }
+            }
+        }
+    }
+    if (t == 0) {
+        S.sn = 0;
+        S.pn = 0;
+        S.npark[0] = 0;
+        S.npark[1] = 0;
+    }
+    if (t < (uint32_t)C / 4)
+        S.cnt[t] = 0;
+    __syncthreads();
+    // item K (in this chunk): first and last leaf, id, prefix after its first leaf
+    const AdjBytes A{S.sa, wlo, M};
+    auto first = [&](uint32_t K) { return LEAVES ? K : S.itf[K - C0]; };
+    auto last = [&](uint32_t K) { return LEAVES ? K : S.itl[K - C0]; };
+    auto item_id = [&](uint32_t K) { return LEAVES ? N - 1 + K : S.itd[K - C0]; };
+    auto a_first = [&](uint32_t K) { return LEAVES ? A.at(K) : (int)S.sf[K - C0] - 1; };
+    if (t < m) {
+        const uint32_t K = C0 + t;
+        if (LEAVES)
+            leaf_esc[K] = escape_adj(A, N, K);
+        else
+            load_record(nodes, item_id(K), lo, hi, t0, t1);
+        put_slot(S.rec[t], lo, hi, t0, t1, K, pack_ends(A.at(K - 1), A.at(K), kNoSplit));
+    }
+    __syncthreads();
+    // hand node [F, L] (items) up to the next pass
+    auto hand_up = [&](uint32_t F, uint32_t L, uint32_t id, int dr) {
+        const unsigned int k = atomicAdd(&S.pn, 1u);
+        if (k < (unsigned)kAggOut)
+            S.pst[k] = AggItem{first(F), last(L), id,
+                               (uint32_t)(a_first(F) + 1) | ((uint32_t)(dr + 1) << 8)};
+    };
+    uint32_t F = C0 + t, L = F, gx = kNoSplit;
+    int dl = A.at(F - 1), dr = A.at(L);
+    bool go = t < m, resumed = false;
+    for (uint32_t round = 0;; ++round) {
+        for (int merges = 0; go; ++merges) {
+            if (F == 0 && L == M - 1) {   // the root
+                if (F < L)
+                    put_slot(S.rec[0], lo, hi, t0, t1, L, pack_ends(dl, dr, gx));
+                go = false;
+                break;
+            }
+            const bool right = dr > dl;   // a left child: the parent extends right
+            const uint32_t id = F == L ? item_id(F) : (right ? last(L) : first(F));
+            const uint32_t s = (right ? L : F) - C0;
+            if (F < L && !resumed)   // formed here: its slot (the id end's)
+                put_slot(S.rec[s], lo, hi, t0, t1, right ? F : L, pack_ends(dl, dr, gx));
+            resumed = false;
+            if (merges == kAggSteps) {   // park it for the next round
+                S.park[round & 1][atomicAdd(&S.npark[round & 1], 1u)] = s;
+                go = false;
+                break;
+            }
+            const uint32_t g = right ? L : F - 1;
+            if (g < C0 || g + 1 >= C0 + m) {   // a split at the chunk's edge
+                hand_up(F, L, id, dr);
+                go = false;
+                break;
+            }
+            const uint32_t gs = g - C0, sh = 8u * (gs & 3u);
+            const unsigned int old = __hip_atomic_fetch_add(&S.cnt[gs >> 2], (right ? 1u : 2u) << sh,
+                                                            __ATOMIC_ACQ_REL,
+                                                            __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (((old >> sh) & 0xFFu) == 0) {   // first to arrive: the sibling goes on
+                go = false;
+                break;
+            }
+            // the sibling's slot (inside the chunk: the split is not at its
+            // edge) holds the single item next to this node, or the node
+            // formed with that item as its id end
+            const uint32_t near = right ? L + 1 : F - 1;
+            const SlotRec o = S.rec[near - C0];
+            const bool single = (o.packed >> 16) == kNoSplit;
+            const uint32_t sid = single ? item_id(near) : (right ? first(near) : last(near));
+            bad |= o.other - C0 >= m || (right ? o.other < near : o.other > near);
+            if (time_overlap(t0, t1, o.t0, o.t1) && space_overlap(lo, hi, o.lo, o.hi))
+                stage.push(seeds, right ? id : sid, right ? sid : id);
+            unite(lo, hi, t0, t1, o.lo, o.hi, o.t0, o.t1);
+            gx = gs;
+            if (right) {
+                L = o.other;
+                dr = (int)((o.packed >> 8) & 0xFFu) - 1;
+            } else {
+                F = o.other;
+                dl = (int)(o.packed & 0xFFu) - 1;
+            }
+        }
+        __syncthreads();
+        const uint32_t np = S.npark[round & 1];
+        __syncthreads();
+        if (np == 0 || round > (uint32_t)C)
+            break;
+        if (t == 0)
+            S.npark[round & 1] = 0;   // next written two rounds on, after a barrier
+        go = t < np;
+        if (go) {   // resume a parked climber from its slot
+            const uint32_t s = S.park[round & 1][t];
+            const SlotRec o = S.rec[s];
+            const uint32_t K = C0 + s;
+            F = o.other < K ? o.other : K;
+            L = o.other < K ? K : o.other;
+            dl = (int)(o.packed & 0xFFu) - 1;
+            dr = (int)((o.packed >> 8) & 0xFFu) - 1;
+            gx = o.packed >> 16;
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = o.lo[d];
+                hi[d] = o.hi[d];
+            }
+            t0 = o.t0;
+            t1 = o.t1;
+            resumed = true;
+        }
+    }
+    // roots whose sibling never arrived (count 1: the left child, 2: the right)
+    if (t + 1 < m) {
+        const uint32_t c = (S.cnt[t >> 2] >> (8u * (t & 3u))) & 0xFFu;
+        if (c == 1 || c == 2) {
+            const uint32_t s = c == 1 ? t : t + 1, K = C0 + s;
+            const uint32_t e = S.rec[s].other;
+            const bool formed = (S.rec[s].packed >> 16) != kNoSplit && (c == 1 ? e < K : e > K);
+            const uint32_t F = formed && c == 1 ? e : K, L = formed && c == 2 ? e : K;
+            const uint32_t id = F == L ? item_id(K) : (c == 1 ? last(L) : first(F));
+            hand_up(F, L, id, A.at(L));
+        }
+    }
+    // records of the nodes formed here: the id end of a left child is its
+    // last item, of a right child (or the root) its first
+    auto node_of = [&](uint32_t r, uint32_t &F, uint32_t &L) {
+        const uint32_t K = C0 + r, e = S.rec[r].other;
+        F = e < K ? e : K;
+        L = e < K ? K : e;
+        return e < K ? last(L) : first(F);
+    };
+    auto kids_of = [&](uint32_t F, uint32_t L, uint32_t g) {
+        return make_uint2(F == g ? item_id(g) : last(g), g + 1 == L ? item_id(L) : first(g + 1));
+    };
+    auto esc_of = [&](uint32_t L) {   // skip link of a node ending with item L
+        const uint32_t r = last(L);
+        if (r >= N - 1)
+            return kEnd;
+        const uint32_t s = r + 1;
+        return s <= N - 2 && a_first(L + 1) >= A.at(L) ? s : N - 1 + s;
+    };
+    auto formed_at = [&](uint32_t r) { return (S.rec[r].packed >> 16) != kNoSplit; };
+    if (LEAVES) {
+        // id = C0 + r: four lanes per record, each writing 16 bytes, so a
+        // wave's store writes 16 whole consecutive records
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t x = t + (uint32_t)C * (uint32_t)j, r = x >> 2, q = x & 3u;
+            if (r < m && formed_at(r)) {
+                uint32_t F, L;
+                const uint32_t id = node_of(r, F, L);
+                u32x4 v = ((const u32x4 *)&S.rec[r])[q];
+                if (q == 3) {
+                    v.z = kids_of(F, L, C0 + (S.rec[r].packed >> 16)).x;
+                    v.w = esc_of(L);
+                }
+                __builtin_nontemporal_store(v, (u32x4 *)(nodes + id) + q);
+            }
+        }
+        if (t < m && formed_at(t)) {
+            uint32_t F, L;
+            const uint32_t id = node_of(t, F, L);
+            kids[id] = kids_of(F, L, C0 + (S.rec[t].packed >> 16));
+        }
+    } else if (t < m && formed_at(t)) {
+        uint32_t F, L;
+        const uint32_t id = node_of(t, F, L);
+        const uint2 kd = kids_of(F, L, C0 + (S.rec[t].packed >> 16));
+        const SlotRec &o = S.rec[t];
+        NodeIO<CD_FP64>::put(nodes, N, id, o.lo, o.hi, o.t0, o.t1, kd.x, esc_of(L));
+        kids[id] = kd;
+    }
+    __syncthreads();
+    // seeds out; roots out in position order (rank: roots starting before)
+    const uint32_t np = S.pn < (unsigned)kAggOut ? S.pn : (unsigned)kAggOut;
+    if (t == 0) {
+        const uint32_t ms = S.sn < (unsigned)kSeedStage ? S.sn : (unsigned)kSeedStage;
+        S.sbase = ms ? seeds.reserve(ms) : 0u;
+        out_count[chunk] = np;
+        bad |= S.pn > (unsigned)kAggOut;
+    }
+    for (uint32_t k = t; k < np; k += C) {
+        const AggItem it = S.pst[k];
+        uint32_t rank = 0;
+        for (uint32_t q = 0; q < np; ++q)
+            rank += S.pst[q].f < it.f;
+        out[(size_t)chunk * kAggOut + rank] = it;
+    }
+    __syncthreads();
+    const uint32_t ms = S.sn < (unsigned)kSeedStage ? S.sn : (unsigned)kSeedStage;
+    for (uint32_t k = t; k < ms; k += C)
+        if (S.sbase + k < seeds.cap)
+            seeds.items[S.sbase + k] = S.sbuf[k];
+    __syncthreads();   // the LDS is reused by the next chunk
+}
+
+// Pass 1: one workgroup per chunk of leaves (consecutive chunks on one XCD).
+template <int C>
+__global__ __launch_bounds__(C) __attribute__((amdgpu_waves_per_eu(8))) void k_agglo_leaves(
+    CodeKeys G, uint32_t slab_ticks, Node64 *__restrict__ nodes, uint2 *__restrict__ kids,
+    uint32_t *__restrict__ leaf_esc, AggItem *__restrict__ out, uint32_t *__restrict__ out_count,
+    SeedSink seeds, unsigned int *err)
+{
+    __shared__ AggShared<C, true> S;
+    bool bad = false, misplaced = false;
+    agglo_chunk<C, true>(S, xcd_block(blockIdx.x, gridDim.x), G.N, G, slab_ticks, nullptr, nodes,
+                         kids, leaf_esc, out, out_count, seeds, bad, misplaced);
+    if (misplaced)
+        atomicOr(err, 1u);
+    if (bad)
+        atomicOr(err, 2u);
+}
+
+// Later passes: the item count is on the device; a small grid strides over
+// the chunks that hold items.
+template <int C>
+__global__ __launch_bounds__(C) void k_agglo_items(CodeKeys G, const AggItem *__restrict__ in,
+                                                   const uint32_t *__restrict__ in_count,
+                                                   Node64 *__restrict__ nodes,
+                                                   uint2 *__restrict__ kids,
+                                                   AggItem *__restrict__ out,
+                                                   uint32_t *__restrict__ out_count,
+                                                   SeedSink seeds, unsigned int *err)
+{
+    __shared__ AggShared<C, false> S;
+    const uint32_t M = *in_count;
+    bool bad = false, misplaced = false;
+    for (uint32_t c = blockIdx.x; (uint64_t)c * C < M; c += gridDim.x)
+        agglo_chunk<C, false>(S, c, M, G, 1, in, nodes, kids, nullptr, out, out_count, seeds, bad,
+                              misplaced);
+    if (bad)
+        atomicOr(err, 2u);
+}
+
+// Exclusive scan of the chunks' root counts (one workgroup) into offsets, and
+// the next pass's item count into *next_count.  Only the ceil(M / C) chunks
+// that had items wrote a count.
+__global__ __launch_bounds__(kAggScanThreads) void k_agglo_scan(const uint32_t *counts,
+                                                                const uint32_t *in_count,
+                                                                uint32_t M_host, uint32_t C,
+                                                                uint32_t *offsets,
+                                                                uint32_t *next_count)
+{
+    __shared__ uint32_t wsum[33];
+    const uint32_t M = in_count ? *in_count : M_host;
+    const uint32_t nc = (M + C - 1) / C;
+    const uint32_t per = (nc + kAggScanThreads - 1) / kAggScanThreads;
+    const uint32_t b = threadIdx.x * per;
+    uint32_t local = 0;
+    for (uint32_t k = 0; k < per && b + k < nc; ++k)
+        local += counts[b + k];
+    uint32_t total;
+    uint32_t run = block_exclusive_scan(local, wsum, &total);
+    for (uint32_t k = 0; k < per && b + k < nc; ++k) {
+        offsets[b + k] = run;
+        run += counts[b + k];
+    }
+    if (threadIdx.x == 0)
+        *next_count = total;
+}
+
+// Every chunk's roots to their places in the next pass's item list (a small
+// grid striding over the chunks that held items).
+__global__ __launch_bounds__(256) void k_agglo_compact(const AggItem *stage, const uint32_t *counts,
+                                                       const uint32_t *offsets,
+                                                       const uint32_t *in_count, uint32_t M_host,
+                                                       uint32_t C, AggItem *next)
+{
+    const uint32_t M = in_count ? *in_count : M_host;
+    const uint32_t nc = (M + C - 1) / C;
+    for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
+        const uint32_t n = counts[c], o = offsets[c];
+        for (uint32_t k = threadIdx.x; k < n; k += blockDim.x)
+            next[o + k] = stage[(size_t)c * kAggOut + k];
+    }
+}
+
+size_t agglo_ws_bytes(uint32_t N)
+{
+    const size_t chunks = (N + kAggChunk - 1) / kAggChunk;
+    return 3 * align_up(chunks * kAggOut * sizeof(AggItem), 256) +
+           2 * align_up((chunks + 1) * sizeof(uint32_t), 256) + 256 + 6 * 256;
+}
+
+hipError_t launch_agglo(const uint32_t *code, uint32_t slab_size, uint32_t slab_ticks,
+                        uint32_t N, void *nodes, uint2 *kids, uint32_t *leaf_esc, void *ws,
+                        const SeedSink &seeds, unsigned int *err, hipStream_t s)
+{
+    if (N == 0)
+        return hipSuccess;
+    if (!code || slab_size == 0 || slab_ticks == 0 || !ws)
+        return hipErrorInvalidValue;
+    constexpr int C = kAggChunk;
+    constexpr uint32_t kItemGrid = 512, kCompactGrid = 1024;
+    const size_t chunks1 = (N + C - 1) / C;
+    Carve cv(ws, agglo_ws_bytes(N));
+    AggItem *stage = cv.take<AggItem>(chunks1 * kAggOut);
+    AggItem *items[2] = {cv.take<AggItem>(chunks1 * kAggOut), cv.take<AggItem>(chunks1 * kAggOut)};
+    uint32_t *counts = cv.take<uint32_t>(chunks1 + 1);
+    uint32_t *offsets = cv.take<uint32_t>(chunks1 + 1);
+    uint32_t *totals = cv.take<uint32_t>(2);   // item counts of alternate passes
+    const CodeKeys G{code, slab_size, N};
+    uint32_t bound = N;   // pass 1: the leaves
+    k_agglo_leaves<C><<<nblk(bound, C), C, 0, s>>>(G, slab_ticks, (Node64 *)nodes, kids, leaf_esc,
+                                                    stage, counts, seeds, err);
+    hipError_t e = hipGetLastError();
+    const uint32_t *in_count = nullptr;   // null: the count is `bound` (pass 1)
+    int cur = 0;
+    while (e == hipSuccess && bound > (uint32_t)C) {
+        const uint32_t nchunks = nblk(bound, C);
+        uint32_t *next_count = totals + cur;
+        k_agglo_scan<<<1, kAggScanThreads, 0, s>>>(counts, in_count, bound, C, offsets,
+                                                   next_count);
+        if ((e = hipGetLastError()) != hipSuccess)
+            break;
+        k_agglo_compact<<<nchunks < kCompactGrid ? nchunks : kCompactGrid, 256, 0, s>>>(
+            stage, counts, offsets, in_count, bound, C, items[cur]);
+        if ((e = hipGetLastError()) != hipSuccess)
+            break;
+        in_count = next_count;
+        const uint64_t b = (uint64_t)nchunks * kAggOut;
+        bound = b < bound ? (uint32_t)b : bound;
+        const uint32_t grid = nblk(bound, C) < kItemGrid ? nblk(bound, C) : kItemGrid;
+        k_agglo_items<C><<<grid, C, 0, s>>>(G, items[cur], in_count, (Node64 *)nodes, kids, stage,
+                                             counts, seeds, err);
+        e = hipGetLastError();
+        cur ^= 1;
+    }
+    return e;
+}
+
+} // namespace cd

@@ -248,12 +248,22 @@ __device__ inline void object_run(const ObjConst &c, const ObjSinus *os, uint32_
     object_steps<RULE>(c, os, i, k0, k1, K, dt, T, tick_s, half_thr, sink);
 }
 
+// LDS written by some lanes of a wave and then read by others: the wave
+// executes its LDS operations in order, so only the compiler must keep them
+// in order (a fence at wavefront scope).
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Box records (FP64): each wave's 64 records of one interval (consecutive
-// slots, 4 KB) are staged in LDS and written back so that each store
-// instruction covers 1 KB of whole lines (non-temporal); the packed codes go
-// to their array as well.  Every lane of the block runs the loop (lanes past
-// n compute object 0 and store nothing), because a record's pieces are
-// stored by other lanes than the one that formed it.
+// slots, 4 KB) are staged in the wave's own LDS area and written back so
+// that each store instruction covers 1 KB of whole lines (non-temporal); the
+// packed codes go to their array as well.  Every lane of the wave runs the
+// loop (lanes past n compute object 0 and store nothing), because a record's
+// pieces are stored by other lanes than the one that formed it.
 struct RecordSink {
     const BoxOut &out;
     uint32_t n, r0, obj, code;
@@ -274,7 +284,7 @@ struct RecordSink {
         mine[2] = make_uint4(__double2loint(hi[1]), __double2hiint(hi[1]), __double2loint(hi[2]),
                              __double2hiint(hi[2]));
         mine[3] = make_uint4(t0, t1, obj, code);
-        __syncthreads();
+        wave_lds_sync();
         // piece q of the wave's 4 KB (record q / 4, quarter q % 4)
         typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
         u32x4 *dst = (u32x4 *)(out.rec + k * n + r0);
@@ -287,7 +297,7 @@ struct RecordSink {
                 __builtin_nontemporal_store(x, dst + q);
             }
         }
-        __syncthreads();
+        wave_lds_sync();
     }
 };
 

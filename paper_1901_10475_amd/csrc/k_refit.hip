@@ -31,35 +31,6 @@ static inline unsigned nblk(uint64_t n, unsigned t) { return (unsigned)((n + t -
 // A climb that meets a parent of a higher level queues the node for that level
 // and block.  Kernel boundaries order each level's writes before the next.
 
-// Per-workgroup seed staging: lanes append to LDS; a full stage or the end of
-// the kernel flushes it with one global atomic.
-struct SeedStage {
-    uint2 *buf;            // LDS, kSeedStage entries
-    unsigned int *n;       // LDS counter
-    __device__ void push(const SeedSink &sink, uint32_t a, uint32_t b) const
-    {
-        unsigned int k = atomicAdd(n, 1u);
-        if (k < (unsigned)kSeedStage) {
-            buf[k] = make_uint2(a, b);
-        } else {  // stage full: this one goes straight out
-            uint2 one = make_uint2(a, b);
-            sink.put_many(&one, 1, sink.reserve(1));
-        }
-    }
-    // all threads of the block call this after the last push
-    __device__ void flush(const SeedSink &sink, unsigned int *base_lds) const
-    {
-        __syncthreads();
-        uint32_t m = *n < (unsigned)kSeedStage ? *n : (unsigned)kSeedStage;
-        if (threadIdx.x == 0)
-            *base_lds = m ? sink.reserve(m) : 0u;
-        __syncthreads();
-        for (uint32_t k = threadIdx.x; k < m; k += blockDim.x)
-            if (*base_lds + k < sink.cap)
-                sink.items[*base_lds + k] = buf[k];
-    }
-};
-
 template <int BP, int TP>
 __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
     BoxView b, uint32_t N, const uint32_t *__restrict__ idx, bool sorted_boxes,

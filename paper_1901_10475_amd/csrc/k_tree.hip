@@ -265,123 +265,124 @@ __device__ inline void put_inner(const SlabKeys32 &K, uint32_t N, uint32_t i,
     links.put(i, nd.left, slab_escape32(K, N, (uint32_t)nd.last));
 }
 
-// Karras over boxes already sorted within their slabs (the sorted layout),
-// kKarrasGroup consecutive slabs per workgroup.  Slabs of one block of the
-// layout carry the same codes in the same order, and when no two codes of a
-// slab are equal, an inner node strictly inside a slab (local index 1 .. m-2)
-// is decided by in-slab comparisons alone (every probe outside the slab
-// compares below its range's common prefix), so its children and range in
-// one slab are those of the first slab shifted by the slab offset: they are
-// searched once per group and written for every slab.  The two nodes at a
-// slab's ends (its subtree root and the node joining it to its neighbours)
-// are computed per slab.  A group whose slabs differ in their codes, or whose
-// first slab repeats a code, is computed slab by slab.  Every slab's codes
-// are checked for order and every box for its slab (error bit 1); leaf skip
-// links are written here.
+// Karras over boxes already sorted within their slabs (the sorted layout).
+// Slabs of one block of the layout carry the same codes in the same order,
+// and when no two codes of a slab are equal, an inner node strictly inside a
+// slab (local index 1 .. m-2) is decided by in-slab comparisons alone (every
+// probe outside the slab compares below its range's common prefix), so its
+// children and range in one slab are those of the group's first slab shifted
+// by the slab offset.  Slabs are taken in groups of kKarrasGroup:
+// k_group_check marks the groups whose slabs share the first slab's codes
+// (with no code repeated), checks every slab's code order and, when tags are
+// given, every box's slab (error bit 1); k_karras_parts then runs one
+// workgroup per slab, which searches a contiguous 1 / kKarrasGroup share of
+// the group's template nodes and writes them for every slab of the group, plus its own slab's two
+// end nodes (its subtree root and the node joining it to its neighbours) and
+// its leaves' skip links.  A group that fails the check is computed slab by
+// slab.
 constexpr uint32_t kKarrasGroup = 8;
 
-__global__ __launch_bounds__(kSegThreads) void k_karras_blocks(
-    const uint32_t *codes, const uint32_t *__restrict__ t0, uint32_t es, uint32_t N,
-    uint32_t m, uint32_t slab_ticks, uint2 *kids, LinkSink links, uint32_t *parent,
-    uint8_t *clev, unsigned int *err)
+__global__ __launch_bounds__(kSegThreads) void k_group_check(
+    const uint32_t *__restrict__ codes, const uint32_t *__restrict__ t0, uint32_t N, uint32_t m,
+    uint32_t slab_ticks, uint8_t *templ, unsigned int *err)
 {
-    // codes and tags of box g at codes[g * es] and t0[g * es] (es = 1 for
-    // arrays, 16 for box records, whose code words the leaf escapes replace:
-    // every code a workgroup reads is read before its first escape store)
-    __shared__ uint32_t sk[kSegCap];
     const uint32_t nslabs = N / m;
     const uint32_t s0 = blockIdx.x * kKarrasGroup;
     const uint32_t ns = nslabs - s0 < kKarrasGroup ? nslabs - s0 : kKarrasGroup;
-    const uint32_t base0 = s0 * m;
-    for (uint32_t k = threadIdx.x; k < m; k += blockDim.x)
-        sk[k] = codes[(size_t)(base0 + k) * es];
-    __syncthreads();
-    // the group's slabs against the first: same codes?  any repeated or
-    // decreasing code?  every box in its slab?
+    const size_t base0 = (size_t)s0 * m;
     bool differs = false, dup = false, bad = false;
     for (uint32_t k = threadIdx.x; k < m; k += blockDim.x) {
-        if (k + 1 < m) {
-            dup |= sk[k] == sk[k + 1];
-            bad |= sk[k] > sk[k + 1];
-        }
+        uint32_t c0 = codes[base0 + k];
         for (uint32_t q = 0; q < ns; ++q) {
-            size_t g = (size_t)(base0 + q * m + k) * es;
-            differs |= codes[g] != sk[k];
+            size_t g = base0 + (size_t)q * m + k;
+            uint32_t c = codes[g];
+            differs |= c != c0;
+            if (k + 1 < m) {
+                uint32_t c1 = codes[g + 1];
+                bad |= c > c1;
+                dup |= q == 0 && c == c1;
+            }
             if (t0)   // (otherwise the refit checks the slabs of the leaf records)
                 bad |= t0[g] / slab_ticks != s0 + q;
         }
     }
-    bool templ = !__syncthreads_or(differs || dup);
+    bool any = __syncthreads_or(differs || dup);
     if (bad)
         atomicOr(err, 1u);
-    if (templ && m >= 3) {
+    if (threadIdx.x == 0)
+        templ[blockIdx.x] = (!any && m >= 3) ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kSegThreads) void k_karras_parts(
+    const uint32_t *__restrict__ codes, const uint8_t *__restrict__ templ, uint32_t N,
+    uint32_t m, uint2 *kids, LinkSink links, uint32_t *parent, uint8_t *clev)
+{
+    __shared__ uint32_t sk[kSegCap];
+    const uint32_t nslabs = N / m;
+    const uint32_t s = blockIdx.x;
+    const uint32_t grp = s / kKarrasGroup, part = s % kKarrasGroup;
+    const uint32_t s0 = grp * kKarrasGroup;
+    const uint32_t ns = nslabs - s0 < kKarrasGroup ? nslabs - s0 : kKarrasGroup;
+    const bool tp = templ[grp] != 0;
+    const uint32_t base = s * m, base0 = s0 * m;
+    // the slab's own codes (the same as the first slab's in a template group)
+    for (uint32_t k = threadIdx.x; k < m; k += blockDim.x)
+        sk[k] = codes[(size_t)base + k];
+    __syncthreads();
+    const SlabKeys32 K{sk, base, m, s};
+    if (tp) {
         const SlabKeys32 K0{sk, base0, m, s0};
-        for (uint32_t l = 1 + threadIdx.x; l + 1 < m; l += blockDim.x) {
+        // template nodes: this part's contiguous share of local indices
+        // 1 .. m-2, each written for every slab (contiguous runs per slab)
+        const uint32_t inner = m - 2, share = (inner + ns - 1) / ns;
+        const uint32_t lo = 1 + (part * share < inner ? part * share : inner);
+        const uint32_t hi = 1 + ((part + 1) * share < inner ? (part + 1) * share : inner);
+        for (uint32_t l = lo + threadIdx.x; l < hi; l += blockDim.x) {
             KarrasNode nd0 = karras_node_u32(K0, N, base0 + l);
             for (uint32_t q = 0; q < ns; ++q) {
-                const uint32_t base = base0 + q * m;
                 const uint32_t off = q * m;
                 KarrasNode nd = nd0;
                 nd.first += off;
                 nd.last += off;
                 nd.left += off;    // inner ids and leaf ids shift alike
                 nd.right += off;
-                const SlabKeys32 K{sk, base, m, s0 + q};
-                put_inner(K, N, base + l, nd, kids, links, parent, clev);
+                const SlabKeys32 Kq{sk, base0 + off, m, s0 + q};
+                put_inner(Kq, N, base0 + off + l, nd, kids, links, parent, clev);
             }
         }
-        for (uint32_t x = threadIdx.x; x < 2 * ns; x += blockDim.x) {
-            const uint32_t q = x >> 1;
-            const uint32_t base = base0 + q * m;
-            const uint32_t i = base + ((x & 1u) ? m - 1 : 0u);
-            if (i + 1 >= N)
-                continue;
-            const SlabKeys32 K{sk, base, m, s0 + q};
-            put_inner(K, N, i, karras_node_u32(K, N, i), kids, links, parent, clev);
-        }
-        for (uint32_t q = 0; q < ns; ++q) {
-            const uint32_t base = base0 + q * m;
-            const SlabKeys32 K{sk, base, m, s0 + q};
-            for (uint32_t k = threadIdx.x; k < m; k += blockDim.x)
-                links.put(N - 1 + base + k, 0, slab_escape32(K, N, base + k));
-        }
-        return;
-    }
-    // slab by slab (codes reloaded per slab)
-    for (uint32_t q = 0; q < ns; ++q) {
-        const uint32_t base = base0 + q * m;
-        if (q > 0) {
-            __syncthreads();
-            for (uint32_t k = threadIdx.x; k < m; k += blockDim.x)
-                sk[k] = codes[(size_t)(base + k) * es];
-            __syncthreads();
-        }
-        const SlabKeys32 K{sk, base, m, s0 + q};
-        bool unordered = false;
-        for (uint32_t k = threadIdx.x; k < m; k += blockDim.x) {
-            unordered |= k + 1 < m && sk[k] > sk[k + 1];
-            uint32_t i = base + k;
-            links.put(N - 1 + i, 0, slab_escape32(K, N, i));
+        // this slab's end nodes
+        if (threadIdx.x < 2) {
+            const uint32_t i = base + (threadIdx.x ? m - 1 : 0u);
             if (i + 1 < N)
                 put_inner(K, N, i, karras_node_u32(K, N, i), kids, links, parent, clev);
         }
-        if (unordered)
-            atomicOr(err, 1u);
+    } else {
+        for (uint32_t k = threadIdx.x; k < m; k += blockDim.x) {
+            const uint32_t i = base + k;
+            if (i + 1 < N)
+                put_inner(K, N, i, karras_node_u32(K, N, i), kids, links, parent, clev);
+        }
     }
+    for (uint32_t k = threadIdx.x; k < m; k += blockDim.x)
+        links.put(N - 1 + base + k, 0, slab_escape32(K, N, base + k));
 }
 
-hipError_t launch_karras_blocks(const uint32_t *codes, const uint32_t *t0, uint32_t es,
-                                uint32_t N, uint32_t slab_size, uint32_t slab_ticks, uint2 *kids,
-                                const LinkSink &links, uint32_t *parent, uint8_t *clev,
-                                unsigned int *err, hipStream_t s)
+hipError_t launch_karras_blocks(const uint32_t *codes, const uint32_t *t0, uint32_t N,
+                                uint32_t slab_size, uint32_t slab_ticks, uint8_t *templ,
+                                uint2 *kids, const LinkSink &links, uint32_t *parent,
+                                uint8_t *clev, unsigned int *err, hipStream_t s)
 {
     if (N <= 1 || slab_size == 0 || (int64_t)slab_size > kSegCap || N % slab_size ||
         slab_ticks == 0)
         return hipErrorInvalidValue;
     uint32_t nslabs = N / slab_size;
     uint32_t groups = (nslabs + kKarrasGroup - 1) / kKarrasGroup;
-    k_karras_blocks<<<groups, kSegThreads, 0, s>>>(codes, t0, es, N, slab_size, slab_ticks,
-                                                   kids, links, parent, clev, err);
+    k_group_check<<<groups, kSegThreads, 0, s>>>(codes, t0, N, slab_size, slab_ticks, templ, err);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    k_karras_parts<<<nslabs, kSegThreads, 0, s>>>(codes, templ, N, slab_size, kids, links, parent,
+                                                  clev);
     return hipGetLastError();
 }
 

@@ -258,3 +258,42 @@ def test_32bit_views_give_the_64bit_topology(seed, N, bits, slab):
     got = _topology(L.hc_karras32, keys, slab)
     for a, b in zip(ref, got):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("seed,N,bits,slab,chunk", [
+    (0, 1, 30, 1, 1024), (1, 2, 30, 1, 1024), (2, 3, 30, 3, 1024), (3, 1000, 8, 1000, 1024),
+    (4, 1024, 30, 512, 1024), (5, 1025, 30, 25, 1024), (6, 3000, 4, 300, 1024),
+    (7, 4000, 30, 1, 1024), (8, 6000, 30, 2, 512), (9, 17408 * 3, 30, 17408, 1024),
+    (10, 16848 * 20, 30, 16848, 1024), (11, 900, 2, 3, 64), (12, 70000, 1, 7000, 256),
+    (13, 16384 * 17 + 5, 30, 16384 * 17 + 5, 1024)])
+def test_bottom_up_build_gives_the_karras_tree(seed, N, bits, slab, chunk):
+    """The bottom-up build (one pass that finds each node's parent from the
+    keys next to its range, and meets its sibling at their split) replayed on
+    the CPU with the kernels' chunk and level structure, lanes in shuffled
+    orders: its key-window reads stay in bounds, every meeting finds the
+    sibling's box where the kernel looks for it, every level meeting's count
+    was cleared, and the tree (children, skip links, leaf skip links) is the
+    top-down Karras tree over the same keys, also with many equal codes, one-
+    to three-key slabs, and sizes that reach level 2 of the queued passes."""
+    L = _lib()
+    vp = ctypes.c_void_p
+    L.hc_agglo.argtypes = [vp, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64,
+                           vp, vp, vp, vp]
+    rng = np.random.default_rng(seed)
+    codes = rng.integers(0, 1 << bits, N, dtype=np.uint64)
+    codes = np.sort(codes.reshape(N // slab, slab), axis=1).ravel()
+    keys = np.ascontiguousarray(
+        (np.repeat(np.arange(N // slab, dtype=np.uint64), slab) << np.uint64(32)) | codes)
+    ref = _topology(L.hc_karras, keys)
+    c32 = np.ascontiguousarray(codes.astype(np.uint32))
+    for order_seed in (1, 2):
+        left = np.zeros(max(N - 1, 1), np.uint32)
+        right, esc_in = np.zeros_like(left), np.zeros_like(left)
+        esc_leaf = np.zeros(N, np.uint32)
+        rc = L.hc_agglo(_p(c32), N, slab, chunk, order_seed, _p(left), _p(right), _p(esc_in),
+                        _p(esc_leaf))
+        assert rc == 0
+        assert np.array_equal(left[:N - 1], ref[0][:N - 1])
+        assert np.array_equal(right[:N - 1], ref[1][:N - 1])
+        assert np.array_equal(esc_in[:N - 1], ref[4][:N - 1])
+        assert np.array_equal(esc_leaf, ref[5])
