@@ -59,17 +59,19 @@ __device__ inline void load_record(const Node64 *nodes, uint32_t id, double lo[3
     NodeIO<CD_FP64>::get_box(nodes, 0, id, lo, hi, t0, t1);
 }
 
-// The node at one item position in LDS (64 bytes, four 16-byte words laid
-// out as an FP64 tree record's bounds and tags): its box, its other range
-// end and packed = (dl + 1) | (dr + 1) << 8 | split << 16, with dl and dr the
-// adjacent prefixes before its first and after its last item and split its
-// split relative to the chunk (kNoSplit: the item itself, not yet replaced by
-// a node formed here).
-struct alignas(16) SlotRec {
+// The node at one item position in LDS: four 16-byte words laid out as an
+// FP64 tree record's (lo0 lo1 | lo2 hi0 | hi1 hi2 | t0 t1 other packed): its
+// box, its other range end and packed = (dl + 1) | (dr + 1) << 8 |
+// split << 16, with dl and dr the adjacent prefixes before its first and
+// after its last item and split its split relative to the chunk (kNoSplit:
+// the item itself, not yet replaced by a node formed here).  Word q of slot s
+// sits at position q ^ ((s >> 1) & 3) of the slot, so that 16-byte accesses
+// by lanes at neighbouring slots fall in different LDS banks.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+struct SlotRec {
     double lo[3], hi[3];
     uint32_t t0, t1, other, packed;
 };
-static_assert(sizeof(SlotRec) == 64, "SlotRec layout");
 constexpr uint32_t kNoSplit = 0xFFFFu;
 constexpr int kAggSteps = 3;   // merges per round before a climber is parked
 
@@ -78,22 +80,51 @@ __device__ inline uint32_t pack_ends(int dl, int dr, uint32_t split)
     return (uint32_t)(dl + 1) | ((uint32_t)(dr + 1) << 8) | (split << 16);
 }
 
-__device__ inline void put_slot(SlotRec &r, const double lo[3], const double hi[3], uint32_t t0,
-                                uint32_t t1, uint32_t other, uint32_t packed)
+__device__ inline uint32_t swz(uint32_t s) { return (s >> 1) & 3u; }
+
+__device__ inline u32x4 two_doubles(double a, double b)
 {
-    SlotRec v;
-    for (int d = 0; d < 3; ++d) {
-        v.lo[d] = lo[d];
-        v.hi[d] = hi[d];
-    }
-    v.t0 = t0;
-    v.t1 = t1;
-    v.other = other;
-    v.packed = packed;
-    r = v;
+    const uint64_t x = __builtin_bit_cast(uint64_t, a), y = __builtin_bit_cast(uint64_t, b);
+    return u32x4{(uint32_t)x, (uint32_t)(x >> 32), (uint32_t)y, (uint32_t)(y >> 32)};
+}
+__device__ inline double first_double(u32x4 v)
+{
+    return __builtin_bit_cast(double, (uint64_t)v.x | ((uint64_t)v.y << 32));
+}
+__device__ inline double second_double(u32x4 v)
+{
+    return __builtin_bit_cast(double, (uint64_t)v.z | ((uint64_t)v.w << 32));
 }
 
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ inline void put_slot(u32x4 (*rec)[4], uint32_t s, const double lo[3],
+                                const double hi[3], uint32_t t0, uint32_t t1, uint32_t other,
+                                uint32_t packed)
+{
+    const uint32_t z = swz(s);
+    rec[s][0 ^ z] = two_doubles(lo[0], lo[1]);
+    rec[s][1 ^ z] = two_doubles(lo[2], hi[0]);
+    rec[s][2 ^ z] = two_doubles(hi[1], hi[2]);
+    rec[s][3 ^ z] = u32x4{t0, t1, other, packed};
+}
+__device__ inline SlotRec get_slot(const u32x4 (*rec)[4], uint32_t s)
+{
+    const uint32_t z = swz(s);
+    const u32x4 a = rec[s][0 ^ z], b = rec[s][1 ^ z], c = rec[s][2 ^ z], d = rec[s][3 ^ z];
+    SlotRec r;
+    r.lo[0] = first_double(a);
+    r.lo[1] = second_double(a);
+    r.lo[2] = first_double(b);
+    r.hi[0] = second_double(b);
+    r.hi[1] = first_double(c);
+    r.hi[2] = second_double(c);
+    r.t0 = d.x;
+    r.t1 = d.y;
+    r.other = d.z;
+    r.packed = d.w;
+    return r;
+}
+// word 3 alone: {t0, t1, other, packed}
+__device__ inline u32x4 slot_tags(const u32x4 (*rec)[4], uint32_t s) { return rec[s][3 ^ swz(s)]; }
 
 // LDS of one chunk pass.
 template <int C, bool LEAVES>
@@ -101,7 +132,7 @@ struct AggShared {
     uint8_t sa[C + 4];                // a(last leaf) + 1, items C0 - 2 .. C0 + m
     uint8_t sf[LEAVES ? 1 : C + 1];   // a(first leaf) + 1, items C0 .. C0 + m
     uint32_t itf[LEAVES ? 1 : C], itl[LEAVES ? 1 : C], itd[LEAVES ? 1 : C];
-    SlotRec rec[C];
+    u32x4 rec[C][4];                  // slot records, words swizzled
     unsigned int cnt[C / 4];          // four 8-bit arrival counts per word
     uint32_t park[2][C / 4];          // parked climbers (slots), alternate rounds
     uint2 sbuf[kSeedStage];
@@ -185,7 +216,7 @@ __device__ void agglo_chunk(AggShared<C, LEAVES> &S, uint32_t chunk, uint32_t M,
             leaf_esc[K] = escape_adj(A, N, K);
         else
             load_record(nodes, item_id(K), lo, hi, t0, t1);
-        put_slot(S.rec[t], lo, hi, t0, t1, K, pack_ends(A.at(K - 1), A.at(K), kNoSplit));
+        put_slot(S.rec, t, lo, hi, t0, t1, K, pack_ends(A.at(K - 1), A.at(K), kNoSplit));
     }
     __syncthreads();
     // hand node [F, L] (items) up to the next pass
@@ -202,7 +233,7 @@ __device__ void agglo_chunk(AggShared<C, LEAVES> &S, uint32_t chunk, uint32_t M,
         for (int merges = 0; go; ++merges) {
             if (F == 0 && L == M - 1) {   // the root
                 if (F < L)
-                    put_slot(S.rec[0], lo, hi, t0, t1, L, pack_ends(dl, dr, gx));
+                    put_slot(S.rec, 0, lo, hi, t0, t1, L, pack_ends(dl, dr, gx));
                 go = false;
                 break;
             }
@@ -210,7 +241,7 @@ __device__ void agglo_chunk(AggShared<C, LEAVES> &S, uint32_t chunk, uint32_t M,
             const uint32_t id = F == L ? item_id(F) : (right ? last(L) : first(F));
             const uint32_t s = (right ? L : F) - C0;
             if (F < L && !resumed)   // formed here: its slot (the id end's)
-                put_slot(S.rec[s], lo, hi, t0, t1, right ? F : L, pack_ends(dl, dr, gx));
+                put_slot(S.rec, s, lo, hi, t0, t1, right ? F : L, pack_ends(dl, dr, gx));
             resumed = false;
             if (merges == kAggSteps) {   // park it for the next round
                 S.park[round & 1][atomicAdd(&S.npark[round & 1], 1u)] = s;
@@ -235,7 +266,7 @@ __device__ void agglo_chunk(AggShared<C, LEAVES> &S, uint32_t chunk, uint32_t M,
             // edge) holds the single item next to this node, or the node
             // formed with that item as its id end
             const uint32_t near = right ? L + 1 : F - 1;
-            const SlotRec o = S.rec[near - C0];
+            const SlotRec o = get_slot(S.rec, near - C0);
             const bool single = (o.packed >> 16) == kNoSplit;
             const uint32_t sid = single ? item_id(near) : (right ? first(near) : last(near));
             bad |= o.other - C0 >= m || (right ? o.other < near : o.other > near);
@@ -261,7 +292,7 @@ __device__ void agglo_chunk(AggShared<C, LEAVES> &S, uint32_t chunk, uint32_t M,
         go = t < np;
         if (go) {   // resume a parked climber from its slot
             const uint32_t s = S.park[round & 1][t];
-            const SlotRec o = S.rec[s];
+            const SlotRec o = get_slot(S.rec, s);
             const uint32_t K = C0 + s;
             F = o.other < K ? o.other : K;
             L = o.other < K ? K : o.other;
@@ -282,8 +313,9 @@ __device__ void agglo_chunk(AggShared<C, LEAVES> &S, uint32_t chunk, uint32_t M,
         const uint32_t c = (S.cnt[t >> 2] >> (8u * (t & 3u))) & 0xFFu;
         if (c == 1 || c == 2) {
             const uint32_t s = c == 1 ? t : t + 1, K = C0 + s;
-            const uint32_t e = S.rec[s].other;
-            const bool formed = (S.rec[s].packed >> 16) != kNoSplit && (c == 1 ? e < K : e > K);
+            const u32x4 w = slot_tags(S.rec, s);
+            const uint32_t e = w.z;
+            const bool formed = (w.w >> 16) != kNoSplit && (c == 1 ? e < K : e > K);
             const uint32_t F = formed && c == 1 ? e : K, L = formed && c == 2 ? e : K;
             const uint32_t id = F == L ? item_id(K) : (c == 1 ? last(L) : first(F));
             hand_up(F, L, id, A.at(L));
@@ -292,7 +324,7 @@ __device__ void agglo_chunk(AggShared<C, LEAVES> &S, uint32_t chunk, uint32_t M,
     // records of the nodes formed here: the id end of a left child is its
     // last item, of a right child (or the root) its first
     auto node_of = [&](uint32_t r, uint32_t &F, uint32_t &L) {
-        const uint32_t K = C0 + r, e = S.rec[r].other;
+        const uint32_t K = C0 + r, e = slot_tags(S.rec, r).z;
         F = e < K ? e : K;
         L = e < K ? K : e;
         return e < K ? last(L) : first(F);
@@ -307,34 +339,34 @@ __device__ void agglo_chunk(AggShared<C, LEAVES> &S, uint32_t chunk, uint32_t M,
         const uint32_t s = r + 1;
         return s <= N - 2 && a_first(L + 1) >= A.at(L) ? s : N - 1 + s;
     };
-    auto formed_at = [&](uint32_t r) { return (S.rec[r].packed >> 16) != kNoSplit; };
+    auto split_at = [&](uint32_t r) { return slot_tags(S.rec, r).w >> 16; };
     if (LEAVES) {
         // id = C0 + r: four lanes per record, each writing 16 bytes, so a
         // wave's store writes 16 whole consecutive records
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t x = t + (uint32_t)C * (uint32_t)j, r = x >> 2, q = x & 3u;
-            if (r < m && formed_at(r)) {
+            if (r < m && split_at(r) != kNoSplit) {
                 uint32_t F, L;
                 const uint32_t id = node_of(r, F, L);
-                u32x4 v = ((const u32x4 *)&S.rec[r])[q];
+                u32x4 v = S.rec[r][q ^ swz(r)];
                 if (q == 3) {
-                    v.z = kids_of(F, L, C0 + (S.rec[r].packed >> 16)).x;
+                    v.z = kids_of(F, L, C0 + (v.w >> 16)).x;
                     v.w = esc_of(L);
                 }
                 __builtin_nontemporal_store(v, (u32x4 *)(nodes + id) + q);
             }
         }
-        if (t < m && formed_at(t)) {
+        if (t < m && split_at(t) != kNoSplit) {
             uint32_t F, L;
             const uint32_t id = node_of(t, F, L);
-            kids[id] = kids_of(F, L, C0 + (S.rec[t].packed >> 16));
+            kids[id] = kids_of(F, L, C0 + split_at(t));
         }
-    } else if (t < m && formed_at(t)) {
+    } else if (t < m && split_at(t) != kNoSplit) {
         uint32_t F, L;
         const uint32_t id = node_of(t, F, L);
-        const uint2 kd = kids_of(F, L, C0 + (S.rec[t].packed >> 16));
-        const SlotRec &o = S.rec[t];
+        const uint2 kd = kids_of(F, L, C0 + split_at(t));
+        const SlotRec o = get_slot(S.rec, t);
         NodeIO<CD_FP64>::put(nodes, N, id, o.lo, o.hi, o.t0, o.t1, kd.x, esc_of(L));
         kids[id] = kd;
     }
@@ -402,7 +434,9 @@ __global__ __launch_bounds__(C) void k_agglo_items(CodeKeys G, const AggItem *__
 
 // Exclusive scan of the chunks' root counts (one workgroup) into offsets, and
 // the next pass's item count into *next_count.  Only the ceil(M / C) chunks
-// that had items wrote a count.
+// that had items wrote a count.  Each wave owns one contiguous segment, read
+// 64 counts at a time: a first sweep sums it, the segment sums are scanned
+// across the waves, and a second sweep writes the offsets.
 __global__ __launch_bounds__(kAggScanThreads) void k_agglo_scan(const uint32_t *counts,
                                                                 const uint32_t *in_count,
                                                                 uint32_t M_host, uint32_t C,
@@ -412,23 +446,32 @@ __global__ __launch_bounds__(kAggScanThreads) void k_agglo_scan(const uint32_t *
     __shared__ uint32_t wsum[33];
     const uint32_t M = in_count ? *in_count : M_host;
     const uint32_t nc = (M + C - 1) / C;
-    const uint32_t per = (nc + kAggScanThreads - 1) / kAggScanThreads;
-    const uint32_t b = threadIdx.x * per;
-    uint32_t local = 0;
-    for (uint32_t k = 0; k < per && b + k < nc; ++k)
-        local += counts[b + k];
+    const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = kAggScanThreads / 64;
+    const uint32_t seg = ((nc + nw - 1) / nw + 63) & ~63u;
+    const uint32_t b0 = w * seg, b1 = b0 + seg < nc ? b0 + seg : nc;
+    uint32_t part = 0;
+    for (uint32_t k = b0 + lane; k < b1; k += 64)
+        part += counts[k];
+    for (int o = 32; o >= 1; o >>= 1)
+        part += __shfl_xor(part, o, 64);
     uint32_t total;
-    uint32_t run = block_exclusive_scan(local, wsum, &total);
-    for (uint32_t k = 0; k < per && b + k < nc; ++k) {
-        offsets[b + k] = run;
-        run += counts[b + k];
+    // every lane of wave w holds the segment sum; lane 0 enters it
+    uint32_t run = block_exclusive_scan(lane == 0 ? part : 0u, wsum, &total);
+    run = __shfl(run, 0, 64);
+    for (uint32_t k0 = b0; k0 < b1; k0 += 64) {
+        const uint32_t k = k0 + lane;
+        const uint32_t v = k < b1 ? counts[k] : 0u;
+        const uint32_t inc = wave_inclusive_scan(v);
+        if (k < b1)
+            offsets[k] = run + inc - v;
+        run += __shfl(inc, 63, 64);
     }
     if (threadIdx.x == 0)
         *next_count = total;
 }
 
-// Every chunk's roots to their places in the next pass's item list (a small
-// grid striding over the chunks that held items).
+// Every chunk's roots to their places in the next pass's item list: one wave
+// per chunk, a small grid striding over the chunks that held items.
 __global__ __launch_bounds__(256) void k_agglo_compact(const AggItem *stage, const uint32_t *counts,
                                                        const uint32_t *offsets,
                                                        const uint32_t *in_count, uint32_t M_host,
@@ -436,9 +479,10 @@ __global__ __launch_bounds__(256) void k_agglo_compact(const AggItem *stage, con
 {
     const uint32_t M = in_count ? *in_count : M_host;
     const uint32_t nc = (M + C - 1) / C;
-    for (uint32_t c = blockIdx.x; c < nc; c += gridDim.x) {
+    const uint32_t lane = threadIdx.x & 63, waves = gridDim.x * (blockDim.x / 64);
+    for (uint32_t c = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); c < nc; c += waves) {
         const uint32_t n = counts[c], o = offsets[c];
-        for (uint32_t k = threadIdx.x; k < n; k += blockDim.x)
+        for (uint32_t k = lane; k < n; k += 64)
             next[o + k] = stage[(size_t)c * kAggOut + k];
     }
 }
@@ -459,7 +503,7 @@ hipError_t launch_agglo(const uint32_t *code, uint32_t slab_size, uint32_t slab_
     if (!code || slab_size == 0 || slab_ticks == 0 || !ws)
         return hipErrorInvalidValue;
     constexpr int C = kAggChunk;
-    constexpr uint32_t kItemGrid = 512, kCompactGrid = 1024;
+    constexpr uint32_t kItemGrid = 512, kCompactGrid = 4096;
     const size_t chunks1 = (N + C - 1) / C;
     Carve cv(ws, agglo_ws_bytes(N));
     AggItem *stage = cv.take<AggItem>(chunks1 * kAggOut);
@@ -481,7 +525,8 @@ hipError_t launch_agglo(const uint32_t *code, uint32_t slab_size, uint32_t slab_
                                                    next_count);
         if ((e = hipGetLastError()) != hipSuccess)
             break;
-        k_agglo_compact<<<nchunks < kCompactGrid ? nchunks : kCompactGrid, 256, 0, s>>>(
+        const uint32_t cgrid = nblk(nchunks, 4);
+        k_agglo_compact<<<cgrid < kCompactGrid ? cgrid : kCompactGrid, 256, 0, s>>>(
             stage, counts, offsets, in_count, bound, C, items[cur]);
         if ((e = hipGetLastError()) != hipSuccess)
             break;
