@@ -532,23 +532,34 @@ def run_batch(args, log):
     br.calibrate()
     cd.cd_profile_enable(False)
     stages = cd.cd_profile_read(reset=True)
-    br.capture()
-    log("[bench] batch captured")
-    for w in range(args.warmup):
-        br.replay()
+    def timed_replays(label):
+        br.capture()
+        log(f"[bench] batch captured ({label} launch shapes)")
+        for w in range(args.warmup):
+            br.replay()
+            res = br.results()
+            log(f"[bench] warmup {w}: {sum(int(r.shape[0]) for r in res)} pairs")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            br.replay()
+        br.stream.synchronize()
+        wall = time.perf_counter() - t0
         res = br.results()
-        log(f"[bench] warmup {w}: {sum(int(r.shape[0]) for r in res)} pairs")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        br.replay()
-    br.stream.synchronize()
-    wall = time.perf_counter() - t0
-    res = br.results()
+        return wall * 1000.0 / args.steps, res
+
+    ms_default, res_default = timed_replays("default")
+    # launch shapes from the autotuner, one search per box-count bucket
+    # (cached per GPU architecture; outside the timed region)
+    chosen = br.autotune(log=None)
+    log("[bench] tuned buckets: " + ", ".join(
+        f"{k.split('|')[2]}: {v[0]}{' (cached)' if v[1] else ''}" for k, v in chosen.items()))
+    ms_step, res = timed_replays("tuned")
     P = sum(int(r.shape[0]) for r in res)
-    ms_step = wall * 1000.0 / args.steps
+    assert P == sum(int(r.shape[0]) for r in res_default)
     tests = br.brute_force_tests()
-    log(f"[bench] {args.steps} replays: {ms_step:.3f} ms/batch, {P} pairs; eager stages "
+    log(f"[bench] {args.steps} replays: {ms_step:.3f} ms/batch tuned, {ms_default:.3f} ms/batch "
+        f"default, {P} pairs; eager stages "
         + ", ".join(f"{k}={v[0]:.1f}ms/{v[1]}" for k, v in stages.items()))
     # roofline of the dominant stage over the eager pass (all scenarios)
     dom = max(stages, key=lambda k: stages[k][0])
@@ -568,7 +579,10 @@ def run_batch(args, log):
             "data": "synthetic (seeded LEO scenarios)",
             "config": {"workload": f"batch64_leo_30min_dt1s", "scenarios": len(scs),
                        "n_min": min(sizes), "n_max": max(sizes), "boxes": br.boxes_total(),
-                       "brute_force_tests": tests, "graph": "one launch per step"},
+                       "brute_force_tests": tests, "graph": "one launch per step",
+                       "in_tree_scenarios": int(sum(br.in_tree)),
+                       "launch_shapes": "autotuned per box-count bucket"},
+            "ms_per_step_default_shapes": round(ms_default, 4),
             "pairs": P, "stages_ms_eager_total": {k: round(v[0], 3) for k, v in stages.items()},
             "roofline": roof}
 

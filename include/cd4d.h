@@ -120,8 +120,9 @@ typedef struct {
  *     positions at the block's middle instant; code holds that order's key
  *     (non-decreasing along each slab) and obj[b] names the object of box b.
  *     cd_build_boxes reads the requested layout (CD_LAYOUT_SORTED needs code
- *     != NULL and n <= 17 408; otherwise, and for per-object steps, it
- *     writes CD_LAYOUT_OBJECT) and leaves the layout it wrote.  cd_build_tree
+ *     != NULL and n <= CD_SORTED_MAX_ARRAYS, or n <= CD_SORTED_MAX_RECORDS
+ *     when writing records; otherwise, and for per-object steps, it writes
+ *     CD_LAYOUT_OBJECT) and leaves the layout it wrote.  cd_build_tree
  *     needs no key sort for CD_LAYOUT_SORTED boxes with valid codes and slab
  *     hints; it checks that each slab's codes are non-decreasing (error bit
  *     as for a box outside its slab, reported by the query).
@@ -129,8 +130,8 @@ typedef struct {
  *     t1 and obj arrays: 64 bytes per box, {double lo[3], hi[3]; uint32_t
  *     t0, t1, obj, code}, the layout of an FP64 tree's leaf records (the code
  *     array is still written as well).  cd_build_boxes writes them for a
- *     uniform step in the sorted layout (FP64 boxes, n <= 17 408; otherwise
- *     CD_E_INVALID).  With records =
+ *     uniform step in the sorted layout (FP64 boxes, n <=
+ *     CD_SORTED_MAX_RECORDS; otherwise CD_E_INVALID).  With records =
  *     cd_tree_leaf_records(tree) and CD_LAYOUT_SORTED, cd_build_tree takes
  *     them as the tree's leaves where they are: no sort and no copy. */
 typedef struct {
@@ -149,6 +150,9 @@ typedef struct {
 } cd_boxes;
 #define CD_LAYOUT_OBJECT 0
 #define CD_LAYOUT_SORTED 1
+/* object counts up to which cd_build_boxes writes CD_LAYOUT_SORTED boxes */
+#define CD_SORTED_MAX_ARRAYS 17408
+#define CD_SORTED_MAX_RECORDS 278528
 
 /* A linear BVH over a box set.  mem is a caller-owned device buffer of
  * cd_tree_bytes(count, precision) bytes; cd_build_tree fills it and the

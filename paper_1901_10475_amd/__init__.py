@@ -22,6 +22,7 @@ CD_OK, CD_E_INVALID, CD_E_WORKSPACE, CD_E_CAPACITY, CD_E_OVERFLOW, CD_E_DEVICE =
 CD_FP64, CD_FP32 = 0, 1
 CD_BOX_SPEED, CD_BOX_INTERVAL_NU, CD_BOX_INTERVAL_E = 0, 1, 2
 CD_LAYOUT_OBJECT, CD_LAYOUT_SORTED = 0, 1
+CD_SORTED_MAX_ARRAYS, CD_SORTED_MAX_RECORDS = 17408, 278528
 
 _vp = ctypes.c_void_p
 
@@ -259,10 +260,12 @@ class Boxes:
         self.desc.layout = layout
 
     @classmethod
-    def in_tree(cls, tree, count, device="cuda"):
+    def in_tree(cls, tree, count, device="cuda", code=None):
         """FP64 box records written straight into an FP64 tree's leaf-record
-        area (cd_boxes.records = cd_tree_leaf_records): lo/hi/t0/t1/obj are
-        strided views of the records; codes also go to a packed array."""
+        area (cd_boxes.records = cd_tree_leaf_records; tree: anything with the
+        tree's byte tensor as .mem): lo/hi/t0/t1/obj are strided views of the
+        records; codes also go to a packed array (`code`, at least count
+        int32 entries, or a new one)."""
         b = cls.__new__(cls)
         b.count, b.precision = int(count), CD_FP64
         N = max(int(count), 1)
@@ -274,7 +277,7 @@ class Boxes:
         b.lo = f64[:, 0:3].t()
         b.hi = f64[:, 3:6].t()
         b.t0, b.t1, b.obj = u32[:, 12], u32[:, 13], u32[:, 14]
-        b.code = torch.empty(N, dtype=torch.int32, device=device)
+        b.code = torch.empty(N, dtype=torch.int32, device=device) if code is None else code[:N]
         b.desc = cd_boxes()
         b.desc.count = b.count
         b.desc.precision = CD_FP64
@@ -610,7 +613,7 @@ class BroadPhase:
         # FP64 tree's leaf records (no sort, no copy in the tree build)
         self.in_tree = (in_tree and dt_ticks is None and box_precision == CD_FP64
                         and tree_precision == CD_FP64 and self.layout == CD_LAYOUT_SORTED
-                        and self.n <= 17408 and self.count > 0)
+                        and self.n <= CD_SORTED_MAX_RECORDS and self.count > 0)
         if self.in_tree:
             self.boxes = Boxes.in_tree(self.tree, self.count, device)
         else:

@@ -10,7 +10,10 @@ for the whole batch, with no host synchronisation inside it.
 The scenarios run in order and share one set of box, tree and workspace
 buffers sized for the largest (``shared_buffers=False`` gives every scenario
 its own boxes and tree instead, so that they outlive the replay); each keeps
-its own output list, record count and status word on the device.  Output
+its own output list, record count and status word on the device.  FP64 boxes
+of an FP64 tree are written as the tree's own leaf records in the sorted
+layout (``Boxes.in_tree``), so every scenario's tree is built bottom-up in
+place; other precisions use box arrays.  Output
 capacities come from one eager pass (``calibrate``); a replay whose status
 reports exceeded capacity is repeated eagerly for that scenario by
 ``results``.  Launch shapes can differ per
@@ -22,9 +25,10 @@ import math
 import numpy as np
 import torch
 
-from . import (CD_E_CAPACITY, CD_FP64, CD_LAYOUT_SORTED, CD_OK, Graph, _bytes, _check, _ptr, _stream,
-               cd_boxes, cd_build_boxes, cd_get_tuning, cd_query_pairs, cd_query_pairs_async,
-               cd_set_tuning, cd_tree, lib, params_struct, soa)
+from . import (CD_E_CAPACITY, CD_FP64, CD_LAYOUT_SORTED, CD_OK, CD_SORTED_MAX_RECORDS, Boxes, Graph,
+               _bytes, _check, _ptr, _stream, cd_boxes, cd_build_boxes, cd_get_tuning,
+               cd_query_pairs, cd_query_pairs_async, cd_set_tuning, cd_tree, lib, params_struct,
+               soa)
 
 
 class _Boxes:
@@ -48,6 +52,7 @@ class _Boxes:
 
 class _Tree:
     def __init__(self, mem, count, precision):
+        self.mem = mem
         self.desc = cd_tree()
         self.desc.mem = mem.data_ptr()
         self.desc.bytes = lib().cd_tree_bytes(int(count), precision)
@@ -73,6 +78,11 @@ class BatchRunner:
         Nmax = max(self.counts)
         ft = torch.float64 if box_precision == CD_FP64 else torch.float32
 
+        # records in the tree where the layout allows (all FP64, n within the
+        # sorted layout's limit), box arrays otherwise
+        self.in_tree = [box_precision == CD_FP64 and tree_precision == CD_FP64
+                        and s.n <= CD_SORTED_MAX_RECORDS for s in self.sc]
+
         def box_arrays(N):
             return (torch.empty((3, N), dtype=ft, device=device),
                     torch.empty((3, N), dtype=ft, device=device),
@@ -81,19 +91,25 @@ class BatchRunner:
                     torch.empty(N, dtype=torch.int32, device=device),
                     torch.empty(N, dtype=torch.int32, device=device))
 
+        need_arrays = not all(self.in_tree)
         if shared_buffers:
-            arrays = box_arrays(Nmax)
+            arrays = box_arrays(Nmax) if need_arrays else None
+            codes = torch.empty(Nmax, dtype=torch.int32, device=device)
             tree_mem = _bytes(lib().cd_tree_bytes(Nmax, tree_precision), device)
             self.arrays = [arrays] * len(self.sc)
+            self.codes = [codes] * len(self.sc)
             self.tree_mems = [tree_mem] * len(self.sc)
         else:
-            self.arrays = [box_arrays(N) for N in self.counts]
+            self.arrays = [None if t else box_arrays(N) for N, t in zip(self.counts, self.in_tree)]
+            self.codes = [torch.empty(N, dtype=torch.int32, device=device) for N in self.counts]
             self.tree_mems = [_bytes(lib().cd_tree_bytes(N, tree_precision), device)
                               for N in self.counts]
         self.ws_boxes = _bytes(max(lib().cd_build_boxes_ws(s.n) for s in self.sc), device)
         self.ws_tree = _bytes(lib().cd_build_tree_ws(Nmax), device)
-        self.boxes = [_Boxes(a, N, box_precision) for a, N in zip(self.arrays, self.counts)]
         self.trees = [_Tree(m, N, tree_precision) for m, N in zip(self.tree_mems, self.counts)]
+        self.boxes = [Boxes.in_tree(tr, N, device, code=c) if t else _Boxes(a, N, box_precision)
+                      for tr, N, t, a, c in zip(self.trees, self.counts, self.in_tree, self.arrays,
+                                                self.codes)]
         S = len(self.sc)
         self.count_dev = torch.zeros(S, dtype=torch.int64, device=device)
         self.status_dev = torch.zeros(S, dtype=torch.int32, device=device)
@@ -107,8 +123,11 @@ class BatchRunner:
     def box_arrays(self, k):
         """(lo [3,N], hi [3,N], t0, t1, obj) of scenario k's boxes as last built
         (with shared buffers, only the scenario built last still holds them)."""
-        lo, hi, t0, t1, obj, _ = self.arrays[k]
         N = self.counts[k]
+        if self.in_tree[k]:
+            b = self.boxes[k]
+            return b.lo[:, :N], b.hi[:, :N], b.t0[:N], b.t1[:N], b.obj[:N]
+        lo, hi, t0, t1, obj, _ = self.arrays[k]
         return lo[:, :N], hi[:, :N], t0[:N], t1[:N], obj[:N]
 
     # -- one scenario, eager ------------------------------------------------------
@@ -131,6 +150,37 @@ class BatchRunner:
             if rc == CD_OK:
                 return out[:cnt]
             cap = int(cnt * self.margin) + 1024
+
+    def query_built(self, k):
+        """Pairs of scenario k's tree as last built (synchronising query)."""
+        cap = max(self.capacity[k], self.min_capacity)
+        while True:
+            out = torch.empty((cap, 4), dtype=torch.int32, device=self.device)
+            ws = _bytes(lib().cd_query_pairs_ws(self.counts[k], cap), self.device)
+            rc, cnt = cd_query_pairs(self.trees[k], out, cap, ws)
+            if rc == CD_OK:
+                return out[:cnt]
+            cap = int(cnt * self.margin) + 1024
+
+    def autotune(self, path=None, reps=2, log=None):
+        """Launch shapes per scenario from the autotuner (autotune.tuned),
+        keyed by box-count bucket: one scenario per bucket is built and its
+        query tuned (or the cached choice taken); every scenario of the bucket
+        gets it.  Returns {bucket key: (tuning, cached)}."""
+        from . import autotune
+        prec = self.tree_precision
+        chosen = {}
+        with torch.cuda.stream(self.stream):
+            for k in range(len(self.sc)):
+                key = autotune.cache_key(prec, self.counts[k], "fixed")
+                if key not in chosen:
+                    self._build(k)
+                    chosen[key] = autotune.tuned(lambda: self.query_built(k), prec,
+                                                 self.counts[k], "fixed", path=path, reps=reps,
+                                                 log=log)
+                self.tunings[k] = chosen[key][0]
+        self.stream.synchronize()
+        return chosen
 
     def calibrate(self):
         """One eager pass: sets every scenario's output capacity."""

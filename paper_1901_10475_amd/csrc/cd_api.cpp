@@ -676,10 +676,11 @@ int cd_build_boxes(const cd_elements *el, const uint32_t *dt_ticks, const cd_par
         if ((uint64_t)n * K != (uint64_t)out->count)
             return fail(CD_E_INVALID, "out->count %lld != n * K = %llu", (long long)out->count,
                         (unsigned long long)((uint64_t)n * K));
-        bool sorted = out->layout == CD_LAYOUT_SORTED && (bo.code || bo.rec) && n <= kSegCap;
+        bool sorted = out->layout == CD_LAYOUT_SORTED && (bo.code || bo.rec) &&
+                      (n <= kSegCap || (bo.rec && n <= kSortedMaxObjects));
         if (bo.rec && !sorted)
             return fail(CD_E_INVALID, "box records need the sorted layout (CD_LAYOUT_SORTED, "
-                                      "n <= %lld)", (long long)kSegCap);
+                                      "n <= %lld)", (long long)kSortedMaxObjects);
         CD_HIP(launch_boxes_uniform(w.oc, w.os, (uint32_t)n, (uint32_t)K, p->dt_ticks, T,
                                     p->tick_s, half_thr, out->precision, (int)p->box_rule,
                                     sorted, bo, s));
@@ -751,7 +752,7 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
         if (!boxes->code)
             return fail(CD_E_INVALID, "box records need the packed code array too");
         if (boxes->layout != CD_LAYOUT_SORTED || !boxes->code_valid || boxes->slab_size <= 0 ||
-            boxes->slab_size > kSegCap || N % boxes->slab_size != 0 ||
+            boxes->slab_size > kSortedMaxObjects || N % boxes->slab_size != 0 ||
             (slab_ticks && slab_ticks != boxes->slab_ticks))
             return fail(CD_E_INVALID, "box records need the sorted layout of a uniform step");
     } else if (N > 0) {

@@ -325,16 +325,21 @@ hipError_t launch_dt_heuristic(const cd_elements &el, double mu, double tick_s,
 // Uniform step, time-major boxes.  sorted: within each block of
 // uniform_chunk(K) slabs the boxes follow the Morton order of their objects'
 // positions at the block's middle (codes = that order's keys; needs out.code
-// and out.frame and n <= kSegCap); otherwise box (i, k) at k n + i.
+// and out.frame; n <= kSegCap, or n <= kSortedMaxObjects with out.rec);
+// otherwise box (i, k) at k n + i.
 uint32_t uniform_chunk(uint32_t K);
 hipError_t launch_boxes_uniform(const ObjConst *oc, const ObjSinus *os, uint32_t n, uint32_t K,
                                 uint32_t dt, uint32_t T, double tick_s, double half_thr,
                                 int precision, int rule, bool sorted, const BoxOut &out,
                                 hipStream_t s);
 // Block b (entries [b stride, b stride + n), es words apart): sorts ucode
-// with the local ids 0..n-1 into scode / sobj (n <= kSegCap).
+// with the local ids 0..n-1 into scode / sobj, stable.  n <= kSegCap: one
+// LDS sort per block; up to kBlockRuns kSegCap runs: the runs are sorted into
+// rcode / robj (same entries, not overlapping ucode, scode or sobj) and
+// merged by rank.
 hipError_t launch_block_sort(const uint32_t *ucode, uint32_t n, uint32_t nblocks, uint64_t stride,
-                             uint32_t es, uint32_t *scode, uint32_t *sobj, hipStream_t s);
+                             uint32_t es, uint32_t *scode, uint32_t *sobj, uint32_t *rcode,
+                             uint32_t *robj, hipStream_t s);
 hipError_t launch_boxes_variable(const ObjConst *oc, const ObjSinus *os, const ObjSteps *st,
                                  uint32_t n, uint32_t T, double tick_s, double half_thr,
                                  int precision, int rule, const BoxOut &out, hipStream_t s);
@@ -386,6 +391,11 @@ hipError_t radix_sort16(SortKind kind, void *a, void *b, size_t count, const Dig
 constexpr int kSegThreads = 1024;
 constexpr int kSegItems = 17;
 constexpr int64_t kSegCap = (int64_t)kSegThreads * kSegItems;
+// Largest object count of the sorted layout: the block sort's runs of kSegCap.
+constexpr int kBlockRuns = 16;
+constexpr int64_t kSortedMaxObjects = kBlockRuns * kSegCap;
+static_assert(kSegCap == CD_SORTED_MAX_ARRAYS && kSortedMaxObjects == CD_SORTED_MAX_RECORDS,
+              "sorted-layout limits of the header");
 // Fixed-step slabs: one workgroup per slab sorts the slab's Morton codes in
 // LDS, writes the sorted 64-bit keys, and writes the slab's leaf records in
 // sorted order while the slab's boxes are still cached.  A leaf's skip link

@@ -578,14 +578,20 @@ hipError_t launch_boxes_uniform(const ObjConst *oc, const ObjSinus *os, uint32_t
         // kernel rewrites all of them
         if ((!out.code && !out.rec) || !out.frame || (uint64_t)n * K > out.cap)
             return hipErrorInvalidValue;
-        uint32_t *u, *sc, *so, st;
+        uint32_t *u, *sc, *so, *rc = nullptr, *ro = nullptr, st;
         if (out.rec) {
+            // words 0 and 1 (the first bound, rewritten by the box kernel)
+            // hold the sort's runs when n needs several
             uint32_t *w = (uint32_t *)out.rec;
             u = w + kRecT1;
             sc = w + kRecCode;
             so = w + kRecObj;
+            rc = w;
+            ro = w + 1;
             st = kRecWords;
         } else {
+            if ((int64_t)n > kSegCap)
+                return hipErrorInvalidValue;
             u = out.t0;
             sc = out.code;
             so = out.obj;
@@ -595,7 +601,7 @@ hipError_t launch_boxes_uniform(const ObjConst *oc, const ObjSinus *os, uint32_t
                                                                         chunk, out.frame, u, st);
         hipError_t e = hipGetLastError();
         if (e == hipSuccess)
-            e = launch_block_sort(u, n, grid.y, (uint64_t)chunk * n, st, sc, so, s);
+            e = launch_block_sort(u, n, grid.y, (uint64_t)chunk * n, st, sc, so, rc, ro, s);
         if (e != hipSuccess)
             return e;
     }

@@ -459,42 +459,99 @@ __global__ __launch_bounds__(kSegThreads) void k_slab_build(
 // (code of object i at ucode[i * es]) are sorted with their object ids; rank
 // r's code and object go to scode[r * es] and sobj[r * es].  One workgroup
 // per block; blocks are `stride` entries (of es words) apart.
+// Run r (grid.y) of block b (grid.x): entries [r S, min(n, (r + 1) S)) of
+// the block (entry k at (b stride + k) es words) sorted in LDS by code,
+// stable, each with its block-local index; written to the same entries of
+// scode / sobj.  With one run (S = n) that is the block's whole order.
 __global__ __launch_bounds__(kSegThreads) void k_block_sort(const uint32_t *ucode, uint32_t n,
-                                                            uint64_t stride, uint32_t es,
-                                                            uint32_t *scode, uint32_t *sobj)
+                                                            uint32_t S, uint64_t stride,
+                                                            uint32_t es, uint32_t *scode,
+                                                            uint32_t *sobj)
 {
     __shared__ uint32_t xch[kSegCap];
     __shared__ uint32_t cnt[kSegWaves * 257];
     __shared__ uint32_t wsum[64];
     int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    uint64_t base = (uint64_t)blockIdx.x * stride;
+    const uint32_t r0 = blockIdx.y * S;
+    if (r0 >= n)
+        return;   // (the whole workgroup)
+    const uint32_t m = n - r0 < S ? n - r0 : S;
+    uint64_t base = (uint64_t)blockIdx.x * stride + r0;
     uint32_t key[kSegItems], val[kSegItems];
     uint32_t li0 = (uint32_t)w * 64 * kSegItems + lane;
 #pragma unroll
     for (int j = 0; j < kSegItems; ++j) {
         uint32_t li = li0 + j * 64;
-        key[j] = li < n ? ucode[(base + li) * es] : 0xFFFFFFFFu;
-        val[j] = li;
+        key[j] = li < m ? ucode[(base + li) * es] : 0xFFFFFFFFu;
+        val[j] = r0 + li;
     }
-    lds_sort32(key, val, n, xch, cnt, wsum);
+    lds_sort32(key, val, m, xch, cnt, wsum);
 #pragma unroll
     for (int j = 0; j < kSegItems; ++j) {
         uint32_t r = li0 + j * 64;
-        if (r < n) {
+        if (r < m) {
             scode[(base + r) * es] = key[j];
             sobj[(base + r) * es] = val[j];
         }
     }
 }
 
+// The R sorted runs of each block merged: entry e of run r goes to position
+// (its index in run r) + (entries of earlier runs with a code <= its code) +
+// (entries of later runs with a smaller code), which is its place in the
+// block's (code, index) order, as one stable sort of the whole block gives.
+__global__ __launch_bounds__(256) void k_block_merge(const uint32_t *rcode, const uint32_t *robj,
+                                                     uint32_t n, uint32_t S, uint32_t R,
+                                                     uint64_t stride, uint32_t es,
+                                                     uint32_t *scode, uint32_t *sobj)
+{
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n)
+        return;
+    const uint64_t base = (uint64_t)blockIdx.y * stride;
+    const uint32_t r = e / S;
+    const uint32_t x = rcode[(base + e) * es], id = robj[(base + e) * es];
+    uint32_t rank = e - r * S;
+    for (uint32_t q = 0; q < R; ++q) {
+        if (q == r)
+            continue;
+        const uint32_t lo0 = q * S, len = n - lo0 < S ? n - lo0 : S;
+        // entries of run q before x: code <= x (q < r) or code < x (q > r)
+        uint32_t lo = 0, hi = len;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1, c = rcode[(base + lo0 + mid) * es];
+            if (q < r ? c <= x : c < x)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        rank += lo;
+    }
+    scode[(base + rank) * es] = x;
+    sobj[(base + rank) * es] = id;
+}
+
 hipError_t launch_block_sort(const uint32_t *ucode, uint32_t n, uint32_t nblocks, uint64_t stride,
-                             uint32_t es, uint32_t *scode, uint32_t *sobj, hipStream_t s)
+                             uint32_t es, uint32_t *scode, uint32_t *sobj, uint32_t *rcode,
+                             uint32_t *robj, hipStream_t s)
 {
     if (n == 0 || nblocks == 0)
         return hipSuccess;
-    if ((int64_t)n > kSegCap)
+    const uint32_t R = (uint32_t)((n + kSegCap - 1) / kSegCap);
+    if (R > (uint32_t)kBlockRuns || (R > 1 && (!rcode || !robj)))
         return hipErrorInvalidValue;
-    k_block_sort<<<nblocks, kSegThreads, 0, s>>>(ucode, n, stride, es, scode, sobj);
+    const uint32_t S = (n + R - 1) / R;
+    if (R == 1) {
+        k_block_sort<<<dim3(nblocks, 1), kSegThreads, 0, s>>>(ucode, n, S, stride, es, scode,
+                                                              sobj);
+        return hipGetLastError();
+    }
+    k_block_sort<<<dim3(nblocks, R), kSegThreads, 0, s>>>(ucode, n, S, stride, es, rcode, robj);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    k_block_merge<<<dim3((n + 255) / 256, nblocks), 256, 0, s>>>(rcode, robj, n, S, R, stride, es,
+                                                                  scode, sobj);
     return hipGetLastError();
 }
 

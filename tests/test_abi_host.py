@@ -25,6 +25,20 @@ def test_library_exports_every_declared_symbol():
     assert set(decl) == set(cd.EXPORTED)
 
 
+def test_header_constants_match_the_binding():
+    """Every #define CD_* integer constant of include/cd4d.h has the same value
+    in the Python binding."""
+    import paper_1901_10475_amd as cd
+    src = open(os.path.join(ROOT, "include", "cd4d.h")).read()
+    defs = dict(re.findall(r"#define\s+(CD_[A-Z_0-9]+)\s+(-?\d+)\b", src))
+    assert "CD_SORTED_MAX_RECORDS" in defs and "CD_LAYOUT_SORTED" in defs
+    for name, value in defs.items():
+        if hasattr(cd, name):
+            assert getattr(cd, name) == int(value), name
+    assert cd.CD_SORTED_MAX_ARRAYS == int(defs["CD_SORTED_MAX_ARRAYS"])
+    assert cd.CD_SORTED_MAX_RECORDS == int(defs["CD_SORTED_MAX_RECORDS"])
+
+
 def test_status_strings_and_version():
     import paper_1901_10475_amd as cd
     L = cd.lib()

@@ -158,13 +158,14 @@ def _uniform(n, K, dt, seed=0, box_precision=cd.CD_FP64, tree_precision=cd.CD_FP
 def test_uniform_step_trees(n, K, layout, in_tree):
     """Object order: the slab build sorts each slab; sorted layout: the boxes
     arrive in their slabs' Morton order and no sort runs, as arrays (the refit
-    writes the leaf records) or as the tree's own leaf records (17 409 objects
-    per slab exceed one workgroup and fall back to object order)."""
+    writes the leaf records; 17 409 objects per slab exceed one workgroup's
+    sort and fall back to object order) or as the tree's own leaf records (up
+    to 16 sorted runs of 17 408 merged per block)."""
     need_gpu()
     say("tree invariants, uniform steps, n", n, "K", K, "layout", layout, "in tree", in_tree)
     bp = _uniform(n, K, 2, seed=n, layout=layout, in_tree=in_tree)
     assert bp.count == n * K
-    want = layout if n <= 17408 else cd.CD_LAYOUT_OBJECT
+    want = layout if n <= cd.CD_SORTED_MAX_ARRAYS or in_tree else cd.CD_LAYOUT_OBJECT
     assert bp.boxes.desc.layout == want
     assert bp.in_tree == (in_tree and want == cd.CD_LAYOUT_SORTED)
     say("seeds", check_tree(bp))
@@ -242,6 +243,41 @@ def test_sorted_layout_order(n, K):
     # the records of the in-place leaves against the oracle on those boxes
     lo, hi, t0, t1, obj = c.boxes.to_host()
     assert np.array_equal(rc, oracle.pairs_bucketed(oracle.Boxes(lo, hi, t0, t1, obj)))
+
+
+@pytest.mark.parametrize("n", [17409, 20000, 36001])
+def test_sorted_layout_from_merged_runs(n):
+    """More objects than one workgroup sorts: each block's codes are sorted in
+    runs and merged by rank.  Every slab holds each object once, in
+    non-decreasing code order with equal codes by object index, the same
+    order in every slab of a block (9 slabs: a block of 8 and one of 1); the
+    boxes and the record list equal the object layout's, and the records equal
+    the oracle's on the in-place leaves."""
+    need_gpu()
+    K = 9
+    say("sorted layout from merged runs, n", n, "K", K)
+    a = _uniform(n, K, 2, seed=n + 7, layout=cd.CD_LAYOUT_OBJECT, in_tree=False)
+    c = _uniform(n, K, 2, seed=n + 7, layout=cd.CD_LAYOUT_SORTED, in_tree=True)
+    assert c.in_tree and c.boxes.desc.layout == cd.CD_LAYOUT_SORTED
+    check_tree(c)
+    N = n * K
+    obj = c.boxes.obj.cpu().numpy().view(np.uint32).reshape(K, n)
+    code = c.boxes.code.cpu().numpy().view(np.uint32).reshape(K, n)
+    assert np.all(np.sort(obj, axis=1) == np.arange(n)[None, :])
+    key = (code.astype(np.int64) << 32) | obj.astype(np.int64)
+    assert np.all(np.diff(key, axis=1) > 0)
+    for k in range(K):
+        k0 = (k // 8) * 8
+        assert np.array_equal(obj[k], obj[k0]) and np.array_equal(code[k], code[k0])
+    lo, hi, t0, t1, ob = c.boxes.to_host()
+    inv = np.argsort(obj, axis=1) + (np.arange(K) * n)[:, None]
+    for arr, got in (("lo", lo), ("hi", hi)):
+        ga = getattr(a.boxes, arr)[:, :N].cpu().numpy()
+        assert np.array_equal(ga.T, got[inv.ravel()])
+    rc = c.query().cpu().numpy().view(np.uint32)
+    assert np.array_equal(a.query().cpu().numpy().view(np.uint32), rc)
+    assert np.array_equal(rc, oracle.pairs_bucketed(oracle.Boxes(lo, hi, t0, t1, ob)))
+    say("records", len(rc))
 
 
 def test_sorted_layout_with_unsorted_codes_is_reported():
