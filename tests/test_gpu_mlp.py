@@ -195,7 +195,12 @@ def _timed(el, p, dt, reps=5):
 def test_trained_network_gains_over_speed_bound_step():
     """Train on step sweeps of two catalogs; on a third (held out) the learned
     steps give a lower cost objective and fewer boxes than the speed-bound
-    step, with every planted conjunction still reported."""
+    step at 5 km, with every planted conjunction still reported.  Against
+    one tuned scalar the network does not win: the uniform rescaling of the
+    speed bound that is best on the training catalogs, and the learned steps
+    times the one scalar that is best on the training catalogs, tie on the
+    held-out catalog (costs within 2 %; the rescaling that is best on the
+    held-out catalog itself is printed too)."""
     need_gpu()
     T, n = 600_000, 6000
     xs, ts = [], []
@@ -214,13 +219,37 @@ def test_trained_network_gains_over_speed_bound_step():
     say("train loss", losses[0], "->", losses[-1], "target var", float(Y.var().item()))
     assert losses[-1] < losses[0]
 
+    # one scalar tuned on the training catalogs, for the uniform rescaling of
+    # the speed bound and for the learned steps alike
+    train = [catalog.projected_debris(seed=seed, n=n, parents=3, horizon_ticks=T, planted=0)
+             for seed in (5101, 5102)]
+    def train_cost(steps_of):
+        tot = 0.0
+        for tc in train:
+            tel, tp = cd.soa(tc.elements), _params(tc)
+            tot += float(ld.run_costs(tel, tp, steps_of(tel, tp), 32.0)[0].sum().item())
+        return tot
+    def uniform(scale):
+        def f(tel, tp):
+            d = torch.empty(tel.shape[1], dtype=torch.int32, device="cuda")
+            cd.cd_dt_heuristic(tel, tp, 5.0 * scale, d)
+            return d
+        return f
+    def scaled_net(c):
+        return lambda tel, tp: torch.clamp((net.dt(tel, tp).double() * c).round(), 1,
+                                           max(T, 1)).to(torch.int32)
+    s_train = min(ld.DEFAULT_SCALES, key=lambda x: train_cost(uniform(x)))
+    c_train = min((0.5, 0.71, 1.0, 1.41, 2.0), key=lambda x: train_cost(scaled_net(x)))
+    say("tuned on the training catalogs: uniform scale", s_train, "network scale", c_train)
+
     sc = catalog.projected_debris(seed=5103, n=n, parents=3, horizon_ticks=T, planted=8)
     el, p = cd.soa(sc.elements), _params(sc)
     dt_h = torch.empty(sc.n, dtype=torch.int32, device="cuda")
     cd.cd_dt_heuristic(el, p, 5.0, dt_h)
     dt_m = net.dt(el, p)
-    runs = [("speed-bound", dt_h), ("learned", dt_m)]
-    for s in (4.0, 8.0):   # uniform rescalings of the speed bound, for reference
+    runs = [("speed-bound", dt_h), ("learned", dt_m),
+            ("learned tuned", scaled_net(c_train)(el, p))]
+    for s in ld.DEFAULT_SCALES:   # uniform rescalings of the speed bound
         d = torch.empty(sc.n, dtype=torch.int32, device="cuda")
         cd.cd_dt_heuristic(el, p, 5.0 * s, d)
         runs.append((f"speed-bound x{s:g}", d))
@@ -235,3 +264,13 @@ def test_trained_network_gains_over_speed_bound_step():
     assert rows["speed-bound"]["recall"] == 1.0 and rows["learned"]["recall"] == 1.0
     assert rows["learned"]["cost"] < rows["speed-bound"]["cost"]
     assert rows["learned"]["boxes"] < rows["speed-bound"]["boxes"]
+    unif = {k: v for k, v in rows.items() if k.startswith("speed-bound x")}
+    best = min(unif, key=lambda k: unif[k]["cost"])
+    fair = unif[f"speed-bound x{s_train:g}"]
+    say("uniform tuned on training", s_train, fair)
+    say("uniform best on the held-out catalog", best, unif[best])
+    say("learned", rows["learned"], "learned tuned", rows["learned tuned"])
+    assert all(v["recall"] == 1.0 for v in rows.values())
+    # the learned steps (with their training-tuned scalar) against the
+    # training-tuned uniform rescaling: a tie, not a gain
+    assert abs(rows["learned tuned"]["cost"] / fair["cost"] - 1.0) <= 0.02
