@@ -40,24 +40,30 @@ sys.path.insert(0, ROOT)
 METRIC = "ms per n-to-n query and box-pair tests/s at n=16848, 1h horizon; HBM GB/s vs peak"
 HBM_PEAK_GBS = 8000.0
 
-# Measured HBM traffic per launch (rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE, KiB
-# per dispatch, one counter per pass), scaled by what the same counters read for
-# a 1 GiB device copy (FETCH 524308.56 KiB, WRITE 1048576 KiB).  Valid only for
-# the kernel source it was taken on: reported as null once that file changes.
-# Summary and commands: profiles/tracked16848_1h_fp64.md
-COPY_FETCH_KIB, COPY_WRITE_KIB = 524308.5625, 1048576.0
+# Measured HBM traffic of one query's stage (rocprofv3 --pmc FETCH_SIZE, then
+# WRITE_SIZE, KiB summed over the stage's dispatches of one query), scaled by
+# what the same counters read for a 1 GiB device copy (FETCH 524308.4 KiB,
+# WRITE 1048576 KiB).  Valid only for the kernel sources it was taken on:
+# reported as null once one of them changes.  Summary and commands:
+# profiles/tracked16848_1h_fp64.md
+COPY_FETCH_KIB, COPY_WRITE_KIB = 524308.4375, 1048576.0
 # box rule of cd_params (CD_BOX_SPEED, CD_BOX_INTERVAL_NU, CD_BOX_INTERVAL_E)
 BOX_RULES = {"speed": 0, "nu": 1, "ecc": 2}
 BOX_SUFFIX = {"speed": "", "nu": "_box_interval_nu", "ecc": "_box_interval_ecc"}
 
 TRAFFIC = {
-    ("sort", "fp64", "fixed"): {"fetch_kib": 2139373.0, "write_kib": 4481736.0,
-                                "source": "paper_1901_10475_amd/csrc/k_sort.hip",
-                                "sha1": "7dea05c184a8bbcfc9a5af99868a81c687804af1"},
-    ("refit", "fp64", "fixed"): {"fetch_kib": 2519376.0 + 356730.0,
-                                 "write_kib": 3749515.0 + 101497.0,
-                                 "source": "paper_1901_10475_amd/csrc/k_refit.hip",
-                                 "sha1": "b4ff827f77f607f203d985b3231e53215c717fc9"},
+    # k_agglo_leaves + 4 item passes with their scans and compactions
+    ("hierarchy", "fp64", "fixed"): {"fetch_kib": 2014027.4 + 57454.0 + 10091.0 + 138.9,
+                                     "write_kib": 4469558.8 + 75675.0 + 13266.6 + 234.9,
+                                     "sources": {"paper_1901_10475_amd/csrc/k_agglo.hip":
+                                                 "606f0a2a607766f3db31b39b6f13d0eb78354a80"}},
+    # k_block_codes + k_block_sort + k_boxes_uniform (records)
+    ("boxes", "fp64", "fixed"): {"fetch_kib": 4470.6 + 263910.0 + 266351.0,
+                                 "write_kib": 236967.0 + 289546.0 + 4098192.0,
+                                 "sources": {"paper_1901_10475_amd/csrc/k_boxes.hip":
+                                             "8dab1ac1bb2701527b213dbefe051b8acb9e0c8b",
+                                             "paper_1901_10475_amd/csrc/k_sort.hip":
+                                             "5499fda60e277c01f68b81b459b0f3d964c6a85b"}},
 }
 
 
@@ -66,12 +72,13 @@ def measured_traffic(stage, precision, dt_mode):
     t = TRAFFIC.get((stage, precision, dt_mode))
     if not t:
         return None
-    try:
-        sha = hashlib.sha1(open(os.path.join(ROOT, t["source"]), "rb").read()).hexdigest()
-    except OSError:
-        return None
-    if sha != t["sha1"]:
-        return None
+    for src, want in t["sources"].items():
+        try:
+            sha = hashlib.sha1(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+        except OSError:
+            return None
+        if sha != want:
+            return None
     return int(t["fetch_kib"] * 1024 * (1048576.0 / COPY_FETCH_KIB)
                + t["write_kib"] * 1024 * (1048576.0 / COPY_WRITE_KIB))
 
@@ -268,7 +275,8 @@ def _roofline(stages, N, n, P, prec, box_prec, precision_name, dt_mode, ms_step,
         ms = ms_tot / launches
         total += b
         per_stage[k] = {"mean_ms": round(ms, 4), "bytes": int(b),
-                        "frac": round(b / (ms / 1000.0) / 1e9 / HBM_PEAK_GBS, 4) if ms > 0 else None}
+                        "frac": round(b / (ms / 1000.0) / 1e9 / HBM_PEAK_GBS, 4) if ms > 0 else None,
+                        "traffic": measured_traffic(k, precision_name, dt_mode)}
     out["stages"] = per_stage
     wq = total / (ms_step / 1000.0) / 1e9
     out["whole_query"] = {"bytes": int(total), "ms": round(ms_step, 4), "achieved": round(wq, 1),
