@@ -392,6 +392,7 @@ def run_tracked(args, log):
                                    else "object")
     if args.copy:
         out["hbm_copy"] = args.copy
+    out["executed_tests"] = executed_tests(cd, bp, N, tests, ms_step, log)
     out["narrow_phase"] = narrow_phase(cd, el, p, pairs, log)
     default_line = (args.dt == "fixed" and prec == cd.CD_FP64 and box_prec == cd.CD_FP64
                     and args.box == "speed")
@@ -404,6 +405,24 @@ def run_tracked(args, log):
         log("[bench] CPU oracle baseline ...")
         out["cpu_baseline"] = cpu_baseline(sc, args.cpu_slabs)
     return out
+
+
+def executed_tests(cd, bp, N, brute_force, ms_step, log):
+    """4D box-box tests the tree actually executes for one query (the
+    counters build, libcd4d_counters.so, one query outside the timed region):
+    the traversal's tests plus the build's one sibling test per inner node,
+    per second at the timed query rate."""
+    with cd.counters_build():
+        cd.cd_counters_reset(None)
+        bp.query()
+        c = cd.cd_counters_read()
+    total = c["tests"] + max(N - 1, 0)
+    rate = total / (ms_step / 1000.0)
+    log(f"[bench] executed tests: {c['tests']} in the traversal + {max(N - 1, 0)} sibling "
+        f"tests = {total} ({rate:.3e}/s at the timed rate; brute force {brute_force})")
+    return {"per_query": total, "traversal": c, "build_sibling_tests": max(N - 1, 0),
+            "per_s": rate, "brute_force_per_executed": round(brute_force / max(total, 1), 1),
+            "from": "CD_COUNTERS build, one query outside the timed region"}
 
 
 def planted_recall(sc, pairs):

@@ -32,6 +32,14 @@
  *     cd_last_error() gives a thread-local message for the last failure.
  *   - Workspace sizes come from the matching *_ws query; passing less returns
  *     CD_E_WORKSPACE before anything is enqueued.
+ *   - CD_DEBUG_SYNC=1 in the environment (read once per process): every call
+ *     that enqueues work also waits for it and returns at once what would
+ *     otherwise surface at a later synchronising call: CD_E_DEVICE for a HIP
+ *     error, CD_E_INVALID from cd_build_tree when the build flagged its
+ *     input (keys out of order, a box outside its slab) and from
+ *     cd_query_pairs_async for status bit 2, CD_E_CAPACITY from
+ *     cd_query_pairs_async for status bit 1.  Skipped while the stream
+ *     records a graph.
  */
 #ifndef CD4D_H
 #define CD4D_H
@@ -347,18 +355,58 @@ int cd_query_pairs_async_noalloc(const cd_tree *tree, cd_pair *out, int64_t capa
  * fields take the defaults in brackets.  Shapes change timing only, never the
  * records. */
 typedef struct {
-    uint32_t expand_blocks;   /* workgroups per node-pair level, 64..65536 [2048] */
-    uint32_t expand_threads;  /* lanes per node-pair workgroup: 64 .. 1024, a power of 2 [256] */
+    uint32_t expand_blocks;   /* workgroups per node-pair level, 64..65536 [2048]; mode 2:
+                                 at most this many, and no more than the device holds
+                                 at once */
+    uint32_t expand_threads;  /* lanes per node-pair workgroup: 64 .. 1024, a power of 2
+                                 [256]; mode 2 always takes 1024 */
     uint32_t walk_threads;    /* lanes per per-leaf-walk workgroup: 64, 128 or 256 [256] */
-    uint32_t mode;            /* 0 = node pairs, per-leaf walk as fallback; 1 = per-leaf
-                                 walk only [0] */
-    uint32_t max_levels;      /* node-pair levels of cd_query_pairs_async, 1..400 [96] */
+    uint32_t mode;            /* 0 = node pairs, one launch per level, per-leaf walk as
+                                 fallback; 1 = per-leaf walk only; 2 = node pairs, every
+                                 level in one launch of a resident grid (levels separated
+                                 by a device-wide wait bounded at 2 s, after which the
+                                 per-leaf walk takes over), per-leaf walk as fallback [0] */
+    uint32_t max_levels;      /* node-pair levels of cd_query_pairs_async in mode 0,
+                                 1..400 [96] */
 } cd_tuning;
 
 /* NULL restores the defaults; out-of-range fields give CD_E_INVALID and
  * change nothing. */
 int cd_set_tuning(const cd_tuning *t);
 int cd_get_tuning(cd_tuning *t);
+
+/* ---- executed-work counters (diagnostic build) --------------------------- */
+
+/* The library built with CD_COUNTERS defined (libcd4d_counters.so, the same
+ * calls and results as libcd4d.so) counts the work the traversal executes:
+ * the brute force of Alg. Brute Force tests every pair of boxes, the tree
+ * tests far fewer, and these counters say how many.  Totals since the last
+ * cd_counters_reset, summed over every query of every thread of the process:
+ *   tests        4D box-box tests executed by the traversal (node pairs: the
+ *                child pairs of every expanded pair; per-leaf walk: one per
+ *                visited node).  The build adds one sibling test per inner
+ *                node (the traversal's seeds), not counted here.
+ *   leaf_tests   of those, tests between two leaf boxes;
+ *   mixed_tests  tests between a leaf box and an inner node;
+ *   leaf_hits    tests of two overlapping leaf boxes of different objects
+ *                (each one appended record, before repeats are removed);
+ *   pairs        node pairs expanded (seeds and queued pairs);
+ *   walk_steps   tests made by per-leaf walks.
+ * visits (optional, a device array of n counts that the caller zeroes): entry
+ * i is incremented for every counted test with a leaf box of object i on one
+ * side (twice for a test of two leaves of object i), so the entries sum to
+ * 2 leaf_tests + mixed_tests. */
+typedef struct {
+    uint64_t tests, leaf_tests, mixed_tests, leaf_hits, pairs, walk_steps;
+} cd_counters;
+
+/* 1 in the CD_COUNTERS build, 0 otherwise (then reset and read return
+ * CD_E_INVALID). */
+int cd_counters_available(void);
+/* Zeroes the totals and binds visits (NULL: none; n < 2^32).  Syncs. */
+int cd_counters_reset(uint32_t *visits, int64_t n, cd_stream_t stream);
+/* Totals so far.  Syncs. */
+int cd_counters_read(cd_counters *out_host, cd_stream_t stream);
 
 /* ---- graphs ------------------------------------------------------------- */
 

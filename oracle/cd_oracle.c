@@ -14,7 +14,8 @@
  *     Kepler's equation instead of by Runge-Kutta; its solution nu(t) is the
  *     function g of Sec. 4.5.  The element set carries the mean anomaly at
  *     t = 0 (m0), from which nu follows.
- *   - The "three rotations involving i, Omega and omega" of Sec. 7.1 are
+ *   - The map of Sec. 7.1 from the orbit plane to space (rotations by the
+ *     inclination, the node and the argument of perigee) is
  *     R_z(Omega) R_x(i) R_z(omega) applied to the perifocal position.
  *   - occ-int over [t_a, t_b] is the axis-aligned hull of the two endpoint
  *     positions grown by vmax*(t_b - t_a)/2 plus the radius r = thr/2, with

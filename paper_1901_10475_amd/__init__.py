@@ -10,6 +10,7 @@ The functions below keep the C names (``cd_build_boxes``, ``cd_build_tree``,
 ``cd_query_pairs``, ...).  ``BroadPhase`` holds one set of buffers and runs the
 three steps in order for repeated queries.
 """
+import contextlib
 import ctypes
 import os
 
@@ -17,6 +18,8 @@ import torch  # noqa: F401  (loads the HIP runtime the library binds to)
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libcd4d.so")
+# the same library built with the traversal's executed-work counters
+_COUNTERS_LIB_PATH = os.path.join(_HERE, "libcd4d_counters.so")
 
 CD_OK, CD_E_INVALID, CD_E_WORKSPACE, CD_E_CAPACITY, CD_E_OVERFLOW, CD_E_DEVICE = range(6)
 CD_FP64, CD_FP32 = 0, 1
@@ -60,6 +63,12 @@ class cd_tuning(ctypes.Structure):
                 ("max_levels", ctypes.c_uint32)]
 
 
+class cd_counters(ctypes.Structure):
+    _fields_ = [("tests", ctypes.c_uint64), ("leaf_tests", ctypes.c_uint64),
+                ("mixed_tests", ctypes.c_uint64), ("leaf_hits", ctypes.c_uint64),
+                ("pairs", ctypes.c_uint64), ("walk_steps", ctypes.c_uint64)]
+
+
 class CDError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"{_status_name(status)} ({status}): {message}")
@@ -71,17 +80,37 @@ def _status_name(s):
             4: "CD_E_OVERFLOW", 5: "CD_E_DEVICE"}.get(s, "CD_E_?")
 
 
-_lib = None
+_libs = {}
+_active = _LIB_PATH
 
 
 def lib():
-    """The loaded libcd4d.so (raises if it has not been built)."""
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB_PATH):
-            raise ImportError(f"{_LIB_PATH} is missing: build it with "
+    """The loaded libcd4d.so (raises if it has not been built); inside
+    ``counters_build()``, libcd4d_counters.so."""
+    return _load(_active)
+
+
+@contextlib.contextmanager
+def counters_build():
+    """Route the enclosed calls of this module through libcd4d_counters.so,
+    the library built with CD_COUNTERS (same calls, same results, plus the
+    executed-work counters of cd_counters_reset / cd_counters_read).  Launch
+    shapes set with cd_set_tuning are per library."""
+    global _active
+    prev = _active
+    _active = _COUNTERS_LIB_PATH
+    try:
+        yield lib()
+    finally:
+        _active = prev
+
+
+def _load(path):
+    if path not in _libs:
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with "
                               "`python -m paper_1901_10475_amd.build`")
-        L = ctypes.CDLL(_LIB_PATH)
+        L = ctypes.CDLL(path)
         P = ctypes.POINTER
         i64, u32, sz, dbl = ctypes.c_int64, ctypes.c_uint32, ctypes.c_size_t, ctypes.c_double
         flt = ctypes.c_float
@@ -146,13 +175,16 @@ def lib():
             "cd_mlp_adam": (ctypes.c_int, [_vp, _vp, _vp, _vp, i64, flt, flt, flt, flt, _vp,
                                            _vp]),
             "cd_pair_object_counts": (ctypes.c_int, [_vp, i64, i64, _vp, _vp]),
+            "cd_counters_available": (ctypes.c_int, []),
+            "cd_counters_reset": (ctypes.c_int, [_vp, i64, _vp]),
+            "cd_counters_read": (ctypes.c_int, [P(cd_counters), _vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
-        _lib = L
-    return _lib
+        _libs[path] = L
+    return _libs[path]
 
 
 EXPORTED = ("cd_status_string", "cd_last_error", "cd_version", "cd_stream_copy",
@@ -169,7 +201,33 @@ EXPORTED = ("cd_status_string", "cd_last_error", "cd_version", "cd_stream_copy",
             "cd_band_partition", "cd_gather_elements", "cd_remap_records",
             "cd_canonical_records_ws", "cd_canonical_records", "cd_mlp_features",
             "cd_dt_mlp", "cd_mlp_forward", "cd_mlp_grad_ws", "cd_mlp_grad", "cd_mlp_adam",
-            "cd_pair_object_counts")
+            "cd_pair_object_counts", "cd_counters_available", "cd_counters_reset",
+            "cd_counters_read")
+
+
+def cd_counters_available():
+    return int(lib().cd_counters_available())
+
+
+def cd_counters_reset(visits=None):
+    """Zero the executed-work totals and bind `visits` (an int32 device tensor
+    of per-object counts that the caller has zeroed, or None)."""
+    # the plain library refuses the call before it would touch a stream
+    s = _stream() if cd_counters_available() else None
+    if visits is not None:
+        if visits.dtype != torch.int32 or not visits.is_cuda or not visits.is_contiguous():
+            raise ValueError("visits must be a contiguous int32 device tensor")
+        _check(lib().cd_counters_reset(_ptr(visits), visits.numel(), s))
+    else:
+        _check(lib().cd_counters_reset(None, 0, s))
+
+
+def cd_counters_read():
+    """Executed-work totals since the last reset, as a dict (syncs)."""
+    c = cd_counters()
+    s = _stream() if cd_counters_available() else None
+    _check(lib().cd_counters_read(ctypes.byref(c), s))
+    return {k: int(getattr(c, k)) for k, _ in cd_counters._fields_}
 
 
 def cd_stream_copy(dst, src, nbytes=None):

@@ -3,8 +3,10 @@
     python -m paper_1901_10475_amd.build
 
 Sources are compiled in parallel with hipcc into objects under _build/ and
-linked in-tree as paper_1901_10475_amd/libcd4d.so (and libcd4d_hostcheck.so,
-which runs the LBVH index arithmetic on the CPU for the pre-flight tests).
+linked in-tree as paper_1901_10475_amd/libcd4d.so, libcd4d_counters.so (the
+same library with the traversal's executed-work counters, CD_COUNTERS) and
+libcd4d_hostcheck.so (the LBVH index arithmetic on the CPU, for the
+pre-flight tests).
 """
 import concurrent.futures as cf
 import os
@@ -31,10 +33,16 @@ DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-p
           "-ffp-contract=on"]
 
 
-def _compile(src, verbose):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+# sources that differ in the executed-work counters build (-DCD_COUNTERS)
+COUNTER_SOURCES = ["k_query.hip", "cd_api.cpp"]
+
+
+def _compile(src, verbose, counters=False):
+    obj = os.path.join(BUILD, os.path.basename(src) + (".counters.o" if counters else ".o"))
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = ["hipcc"] + lang + COMMON + DEVICE + ["-c", os.path.join(CSRC, src), "-o", obj]
+    extra = ["-DCD_COUNTERS"] if counters else []
+    cmd = (["hipcc"] + lang + COMMON + DEVICE + extra
+           + ["-c", os.path.join(CSRC, src), "-o", obj])
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -56,12 +64,15 @@ def _link(objs, out, verbose):
 
 def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
-    srcs = LIB_SOURCES + HOSTCHECK_SOURCES
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = dict(zip(srcs, ex.map(lambda s: _compile(s, verbose), srcs)))
-    _link([objs[s] for s in LIB_SOURCES], os.path.join(PKG, "libcd4d.so"), verbose)
-    _link([objs[s] for s in HOSTCHECK_SOURCES], os.path.join(PKG, "libcd4d_hostcheck.so"),
-          verbose)
+    jobs = [(s, False) for s in LIB_SOURCES + HOSTCHECK_SOURCES]
+    jobs += [(s, True) for s in COUNTER_SOURCES]
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
+        objs = dict(zip(jobs, ex.map(lambda j: _compile(j[0], verbose, j[1]), jobs)))
+    _link([objs[(s, False)] for s in LIB_SOURCES], os.path.join(PKG, "libcd4d.so"), verbose)
+    _link([objs[(s, s in COUNTER_SOURCES)] for s in LIB_SOURCES],
+          os.path.join(PKG, "libcd4d_counters.so"), verbose)
+    _link([objs[(s, False)] for s in HOSTCHECK_SOURCES],
+          os.path.join(PKG, "libcd4d_hostcheck.so"), verbose)
 
 
 if __name__ == "__main__":

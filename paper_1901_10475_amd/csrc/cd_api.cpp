@@ -3,6 +3,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <atomic>
@@ -50,6 +51,46 @@ namespace {
         if (e_ != hipSuccess)                                                              \
             return fail(CD_E_DEVICE, "%s failed: %s", #x, hipGetErrorString(e_));           \
     } while (0)
+
+// CD_DEBUG_SYNC=1 (read once): every call that enqueues work waits for it and
+// reports at once what would otherwise surface at a later synchronising call
+// -- a HIP error, the build's error bits in a tree header, the status word of
+// a device-count query.  Nothing is checked while the stream records a graph.
+bool debug_sync_on()
+{
+    static const bool on = [] {
+        const char *v = getenv("CD_DEBUG_SYNC");
+        return v && *v && strcmp(v, "0") != 0;
+    }();
+    return on;
+}
+
+int debug_sync(hipStream_t s, const char *what, const unsigned int *tree_err = nullptr,
+               const unsigned int *status_dev = nullptr)
+{
+    if (!debug_sync_on())
+        return CD_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+        return CD_OK;
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess)
+        e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(CD_E_DEVICE, "%s: %s (CD_DEBUG_SYNC)", what, hipGetErrorString(e));
+    unsigned int v[2] = {0, 0};
+    if (tree_err && (e = hipMemcpy(&v[0], tree_err, sizeof v[0], hipMemcpyDeviceToHost)) != hipSuccess)
+        return fail(CD_E_DEVICE, "%s: reading the tree header: %s", what, hipGetErrorString(e));
+    if (status_dev &&
+        (e = hipMemcpy(&v[1], status_dev, sizeof v[1], hipMemcpyDeviceToHost)) != hipSuccess)
+        return fail(CD_E_DEVICE, "%s: reading the status: %s", what, hipGetErrorString(e));
+    if (v[0] || (v[1] & 2u))
+        return fail(CD_E_INVALID, "%s: tree inconsistent (error bits 0x%x) (CD_DEBUG_SYNC)", what,
+                    v[0] ? v[0] : v[1]);
+    if (v[1] & 1u)
+        return fail(CD_E_CAPACITY, "%s: more records than the capacity (CD_DEBUG_SYNC)", what);
+    return CD_OK;
+}
 
 // ---- stage timing (cd_profile_*) ----
 struct ProfPending {
@@ -125,11 +166,13 @@ constexpr int64_t kMaxBoxes = (1ll << 30) - 1;  // node ids of 2N - 1 nodes belo
 constexpr size_t kTreeHeader = sizeof(TreeHeader);
 constexpr int kExpandBatch = 12;                 // levels launched between count checks
 constexpr int kExpandMaxLevels = 400;            // > 2 x the deepest possible tree
-// Query control block (32-bit words): [l] queue count after level l - 1,
-// then the per-leaf-walk flag, the level flags, and a status copy (record
-// count low/high, tree error) at an 8-byte-aligned word.
+// Query control block (32-bit words): [l] queue count after level l - 1
+// ([0] stays zero), then the per-leaf-walk flag, the level flags, the
+// one-launch traversal's arrival counter, and a status copy (record count
+// low/high, tree error) at an 8-byte-aligned word.
 constexpr int kCtlWalk = kExpandMaxLevels + 1;
 constexpr int kCtlFlags = kExpandMaxLevels + 2;
+constexpr int kCtlBarrier = kExpandMaxLevels + 3;
 constexpr int kCtlStatus = kExpandMaxLevels + 4;
 constexpr int kCtlWords = kCtlStatus + 4;
 // Node-pair levels the last drained traversal needed: the next synchronous
@@ -451,7 +494,7 @@ int cd_stream_copy(void *dst, const void *src, size_t bytes, cd_stream_t stream)
     if (a < b + bytes && b < a + bytes)
         return fail(CD_E_INVALID, "source and destination overlap");
     CD_HIP(launch_stream_copy(src, dst, (uint64_t)(bytes / 16), (hipStream_t)stream));
-    return CD_OK;
+    return debug_sync((hipStream_t)stream, "cd_stream_copy");
 }
 
 int cd_profile_enable(int on)
@@ -591,7 +634,7 @@ int cd_dt_heuristic(const cd_elements *el, const cd_params *p, double max_disp_k
         return fail(CD_E_INVALID, "dt_out is NULL");
     CD_HIP(launch_dt_heuristic(*el, p->mu, p->tick_s, max_disp_km, p->horizon_ticks, dt_out,
                                (hipStream_t)stream));
-    return CD_OK;
+    return debug_sync((hipStream_t)stream, "cd_dt_heuristic");
 }
 
 // ---- step 2 -----------------------------------------------------------------------------
@@ -698,7 +741,7 @@ int cd_build_boxes(const cd_elements *el, const uint32_t *dt_ticks, const cd_par
         out->layout = CD_LAYOUT_OBJECT;
     }
     out->code_valid = (bo.code || bo.rec) ? 1 : 0;
-    return CD_OK;
+    return debug_sync((hipStream_t)stream, "cd_build_boxes");
 }
 
 // ---- step 3 -----------------------------------------------------------------------------
@@ -872,7 +915,7 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
                             kids, links, tw.clev, tw.arrive, tw.list_items, tw.list_count,
                             nodes, sink, err, s));
     }
-    return CD_OK;
+    return debug_sync((hipStream_t)stream, "cd_build_tree", (const unsigned int *)tree->mem);
 }
 
 // ---- step 4 -----------------------------------------------------------------------------
@@ -921,7 +964,20 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
         // node hand the query to the per-leaf walk, decided from one read of
         // the control block per batch of levels
         bool walk = true;
-        if (N > 1 && tu.mode == 0) {
+        const unsigned int *run_walk = nullptr;
+        if (N > 1 && tu.mode == 2) {
+            // every level in one launch; the walk decided on the device
+            CD_HIP(launch_fill_u32(w.qcount, 0u, kCtlWords, s));
+            CD_HIP(launch_fill_u64(w.counter, 0ull, 1, s));
+            CD_HIP(launch_query_begin(hdr, w.qflags, s));
+            CD_HIP(launch_expand_all(nodes, kids, tree->precision, (uint32_t)N, seeds,
+                                     &hdr->nseeds, (uint32_t)seed_cap((uint64_t)N), w.qa, w.qb,
+                                     w.qcount, w.qcap, kExpandMaxLevels, w.raw,
+                                     (unsigned long long)capacity, w.counter, w.qflags,
+                                     w.qcount + kCtlBarrier, tu.expand_blocks, s));
+            CD_HIP(launch_query_decide(w.qcount, w.qflags, w.counter, w.qcount + kCtlWalk, s));
+            run_walk = w.qcount + kCtlWalk;
+        } else if (N > 1 && tu.mode == 0) {
             CD_HIP(launch_fill_u32(w.qcount, 0u, kCtlWords, s));
             CD_HIP(launch_fill_u64(w.counter, 0ull, 1, s));
             CD_HIP(launch_query_begin(hdr, w.qflags, s));
@@ -965,10 +1021,12 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
             }
         }
         if (walk) {
-            // bounded fallback: one stackless walk per leaf
-            CD_HIP(launch_fill_u64(w.counter, 0ull, 1, s));
+            // bounded fallback: one stackless walk per leaf (in mode 2 only if
+            // the device decided so, from a count it cleared itself)
+            if (!run_walk)
+                CD_HIP(launch_fill_u64(w.counter, 0ull, 1, s));
             CD_HIP(launch_traverse(nodes, tree->precision, (uint32_t)N, tree->slab_ticks, w.raw,
-                                   (unsigned long long)capacity, w.counter, err, nullptr,
+                                   (unsigned long long)capacity, w.counter, err, run_walk,
                                    tu.walk_threads, side_on, side, s));
         }
     }
@@ -1046,9 +1104,19 @@ int cd_query_pairs_async(const cd_tree *tree, cd_pair *out, int64_t capacity,
     CD_HIP(launch_fill_u64(w.counter, 0ull, 1, s));
     {
         Stage st("traverse", s);
-        CD_HIP(launch_fill_u32(w.qcount, 0u, kExpandMaxLevels + 2, s));
-        CD_HIP(launch_fill_u32(w.qflags, tu.mode == 0 ? 0u : 4u, 1, s));
-        if (N > 1) {
+        CD_HIP(launch_fill_u32(w.qcount, 0u, kCtlWords, s));
+        CD_HIP(launch_fill_u32(w.qflags, tu.mode == 1 ? 4u : 0u, 1, s));
+        if (N > 1 && tu.mode == 2) {
+            CD_HIP(launch_query_begin(hdr, w.qflags, s));
+            CD_HIP(launch_expand_all(nodes, kids, tree->precision, (uint32_t)N, seeds,
+                                     &hdr->nseeds, (uint32_t)seed_cap((uint64_t)N), w.qa, w.qb,
+                                     w.qcount, w.qcap, kExpandMaxLevels, w.raw, cap, w.counter,
+                                     w.qflags, w.qcount + kCtlBarrier, tu.expand_blocks, s));
+            // qcount[0] is never written: the flags alone decide
+            CD_HIP(launch_query_decide(w.qcount, w.qflags, w.counter, walk, s));
+            CD_HIP(launch_traverse(nodes, tree->precision, (uint32_t)N, tree->slab_ticks, w.raw,
+                                   cap, w.counter, err, walk, tu.walk_threads, side_on, side, s));
+        } else if (N > 1) {
             CD_HIP(launch_query_begin(hdr, w.qflags, s));
             const uint2 *in = seeds;
             const unsigned int *n_in = &hdr->nseeds;
@@ -1084,7 +1152,52 @@ int cd_query_pairs_async(const cd_tree *tree, cd_pair *out, int64_t capacity,
         }
         CD_HIP(launch_query_finish(w.counter, err, w.pos + cap, cap, count_dev, status_dev, s));
     }
+    return debug_sync((hipStream_t)stream, "cd_query_pairs_async", nullptr, status_dev);
+}
+
+int cd_counters_available(void)
+{
+#ifdef CD_COUNTERS
+    return 1;
+#else
+    return 0;
+#endif
+}
+
+int cd_counters_reset(uint32_t *visits, int64_t n, cd_stream_t stream)
+{
+#ifdef CD_COUNTERS
+    if (n < 0 || n > 0xFFFFFFFFll)
+        return fail(CD_E_INVALID, "n out of range");
+    CD_HIP(counters_reset(visits, visits ? (uint32_t)n : 0u, (hipStream_t)stream));
     return CD_OK;
+#else
+    (void)visits;
+    (void)n;
+    (void)stream;
+    return fail(CD_E_INVALID, "this library was built without CD_COUNTERS");
+#endif
+}
+
+int cd_counters_read(cd_counters *out, cd_stream_t stream)
+{
+#ifdef CD_COUNTERS
+    if (!out)
+        return fail(CD_E_INVALID, "out is NULL");
+    unsigned long long v[kCounterWords];
+    CD_HIP(counters_read(v, (hipStream_t)stream));
+    out->tests = v[0];
+    out->leaf_tests = v[1];
+    out->mixed_tests = v[2];
+    out->leaf_hits = v[3];
+    out->pairs = v[4];
+    out->walk_steps = v[5];
+    return CD_OK;
+#else
+    (void)out;
+    (void)stream;
+    return fail(CD_E_INVALID, "this library was built without CD_COUNTERS");
+#endif
 }
 
 int cd_set_tuning(const cd_tuning *t)
@@ -1094,7 +1207,7 @@ int cd_set_tuning(const cd_tuning *t)
         auto lanes_ok = [](uint32_t x) { return x == 0 || x == 64 || x == 128 || x == 256; };
         auto expand_ok = [&](uint32_t x) { return lanes_ok(x) || x == 512 || x == 1024; };
         if ((t->expand_blocks && (t->expand_blocks < 64 || t->expand_blocks > 65536)) ||
-            !expand_ok(t->expand_threads) || !lanes_ok(t->walk_threads) || t->mode > 1 ||
+            !expand_ok(t->expand_threads) || !lanes_ok(t->walk_threads) || t->mode > 2 ||
             t->max_levels > (uint32_t)kExpandMaxLevels)
             return fail(CD_E_INVALID, "tuning field out of range");
         if (t->expand_blocks)
@@ -1162,7 +1275,7 @@ int cd_graph_launch(cd_graph graph, cd_stream_t stream)
     if (!graph)
         return fail(CD_E_INVALID, "graph is NULL");
     CD_HIP(hipGraphLaunch(graph->exec, (hipStream_t)stream));
-    return CD_OK;
+    return debug_sync((hipStream_t)stream, "cd_graph_launch");
 }
 
 int cd_graph_destroy(cd_graph graph)
@@ -1195,7 +1308,7 @@ int cd_first_witness(const cd_elements *el, const cd_params *p, uint32_t delta_t
     CD_HIP(launch_first_witness(*el, p->mu, p->tick_s, p->start_ticks, p->threshold_km,
                                 p->horizon_ticks, delta_ticks, pairs, (uint64_t)count,
                                 witness_out, first_out, (hipStream_t)stream));
-    return CD_OK;
+    return debug_sync((hipStream_t)stream, "cd_first_witness");
 }
 
 // ---- bulk interval refinement -----------------------------------------------------------
@@ -1432,7 +1545,7 @@ int cd_gather_elements(const cd_elements *el, const uint32_t *ids, int64_t count
     if (count > 0 && (!ids || !out))
         return fail(CD_E_INVALID, "ids or out is NULL");
     CD_HIP(launch_gather_elements(*el, ids, (uint32_t)count, out, (hipStream_t)stream));
-    return CD_OK;
+    return debug_sync((hipStream_t)stream, "cd_gather_elements");
 }
 
 int cd_remap_records(const cd_pair *in, int64_t count, const uint32_t *ids, int64_t nids,
@@ -1444,7 +1557,7 @@ int cd_remap_records(const cd_pair *in, int64_t count, const uint32_t *ids, int6
         return fail(CD_E_INVALID, "in, ids or out is NULL");
     CD_HIP(launch_remap_records(in, (uint32_t)count, ids, (uint32_t)nids, out,
                                 (hipStream_t)stream));
-    return CD_OK;
+    return debug_sync((hipStream_t)stream, "cd_remap_records");
 }
 
 size_t cd_canonical_records_ws(int64_t count)
@@ -1515,7 +1628,7 @@ int cd_mlp_features(const cd_elements *el, const cd_params *p, float *x_out, cd_
     if (el->n > 0 && !x_out)
         return fail(CD_E_INVALID, "x_out is NULL");
     CD_HIP(launch_mlp_features(*el, p->mu, x_out, (hipStream_t)stream));
-    return CD_OK;
+    return debug_sync((hipStream_t)stream, "cd_mlp_features");
 }
 
 int cd_dt_mlp(const cd_elements *el, const uint16_t *w_bf16, double fallback_disp_km,
@@ -1540,7 +1653,7 @@ int cd_dt_mlp(const cd_elements *el, const uint16_t *w_bf16, double fallback_dis
     }
     CD_HIP(launch_dt_mlp(*el, w_bf16, p->mu, p->tick_s, fallback_disp_km, p->horizon_ticks,
                          dt_out, y_out, s));
-    return CD_OK;
+    return debug_sync((hipStream_t)stream, "cd_dt_mlp");
 }
 
 int cd_mlp_forward(const float *w, const float *x, int64_t batch, float *y_out,
@@ -1551,7 +1664,7 @@ int cd_mlp_forward(const float *w, const float *x, int64_t batch, float *y_out,
     if (batch > 0 && (!w || !x || !y_out))
         return fail(CD_E_INVALID, "NULL pointer");
     CD_HIP(launch_mlp_forward(w, x, (uint32_t)batch, y_out, (hipStream_t)stream));
-    return CD_OK;
+    return debug_sync((hipStream_t)stream, "cd_mlp_forward");
 }
 
 size_t cd_mlp_grad_ws(int64_t batch)
@@ -1573,7 +1686,7 @@ int cd_mlp_grad(const float *w, const float *x, const float *target, int64_t bat
     layout_mlp(ws, ws_bytes, batch, &m);
     CD_HIP(launch_mlp_grad(w, x, target, (uint32_t)batch, m.act, m.part, grad_out, loss_out,
                            (hipStream_t)stream));
-    return CD_OK;
+    return debug_sync((hipStream_t)stream, "cd_mlp_grad");
 }
 
 int cd_mlp_adam(float *w, float *m, float *v, const float *g, int64_t step, float lr,
@@ -1588,7 +1701,7 @@ int cd_mlp_adam(float *w, float *m, float *v, const float *g, int64_t step, floa
         return fail(CD_E_INVALID, "Adam hyper-parameters out of range");
     CD_HIP(launch_mlp_adam(w, m, v, g, step, lr, beta1, beta2, eps, w_bf16_out,
                            (hipStream_t)stream));
-    return CD_OK;
+    return debug_sync((hipStream_t)stream, "cd_mlp_adam");
 }
 
 int cd_pair_object_counts(const cd_pair *pairs, int64_t count, int64_t n, uint32_t *counts_out,
@@ -1602,7 +1715,7 @@ int cd_pair_object_counts(const cd_pair *pairs, int64_t count, int64_t n, uint32
         return CD_OK;
     CD_HIP(launch_pair_object_counts(pairs, (uint64_t)count, (uint32_t)n, counts_out,
                                      (hipStream_t)stream));
-    return CD_OK;
+    return debug_sync((hipStream_t)stream, "cd_pair_object_counts");
 }
 
 } // extern "C"

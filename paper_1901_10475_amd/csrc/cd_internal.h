@@ -594,6 +594,26 @@ hipError_t launch_expand(const void *tree, const uint2 *kids, int precision, uin
                          unsigned long long capacity, unsigned long long *counter,
                          unsigned int *flags, int gated, uint32_t blocks, uint32_t threads,
                          hipStream_t s);
+// Every level in one launch of a resident grid (at most `blocks` workgroups of
+// 1 024 lanes), levels separated by a device-wide wait on *bar (zero before
+// the launch).  Level l reads the seeds (l = 0) or the queue written by level
+// l - 1 (qa for even l - 1, qb for odd), its count in qcount[l] (zero before
+// the launch).  Flags as for launch_expand; bit 2 (handover to the per-leaf
+// walk) also when a wait times out or the levels run out with pairs left.
+hipError_t launch_expand_all(const void *tree, const uint2 *kids, int precision, uint32_t N,
+                             const uint2 *seeds, const unsigned int *nseeds, uint32_t seed_cap,
+                             uint2 *qa, uint2 *qb, unsigned int *qcount, uint32_t qcap,
+                             uint32_t max_levels, Rec *out, unsigned long long capacity,
+                             unsigned long long *counter, unsigned int *flags, unsigned int *bar,
+                             uint32_t blocks, hipStream_t s);
+// Executed-work counters of the traversal (built with CD_COUNTERS only):
+// reset binds `visits` (n per-object counts, or NULL) and zeroes the totals;
+// read copies the kCounterWords totals.  Both wait for the stream.
+constexpr int kCounterWords = 6;
+#ifdef CD_COUNTERS
+hipError_t counters_reset(uint32_t *visits, uint32_t nobj, hipStream_t s);
+hipError_t counters_read(unsigned long long *out, hipStream_t s);
+#endif
 // out[0..2] = low and high words of *counter, *tree_err
 hipError_t launch_query_status(const unsigned long long *counter, const unsigned int *tree_err,
                                unsigned int *out, hipStream_t s);

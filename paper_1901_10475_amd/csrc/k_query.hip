@@ -24,6 +24,34 @@ namespace cd {
 
 static inline unsigned nblk(uint64_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
 
+#ifdef CD_COUNTERS
+// Executed-work counters of the traversal (the diagnostic build only), in the
+// order of cd_counters: box-box tests, tests of two leaves, tests of a leaf
+// and an inner node, tests of two overlapping leaves of different objects
+// (each one appended record), node pairs expanded, per-leaf walk steps.  Per
+// object: tests with a leaf box of that object on one side (g_visits, when
+// the caller bound an array).
+__device__ unsigned long long g_ctr[kCounterWords];
+__device__ uint32_t *g_visits;
+__device__ uint32_t g_nobj;
+
+// Wave sum, one atomic per wave; every lane of the wave must call it.
+__device__ inline void ctr_wave_add(int k, uint32_t v)
+{
+    for (int off = 32; off > 0; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    if ((threadIdx.x & 63) == 0 && v)
+        atomicAdd(&g_ctr[k], (unsigned long long)v);
+}
+
+__device__ inline void ctr_visit(uint32_t obj)
+{
+    uint32_t *vis = g_visits;
+    if (vis && obj < g_nobj)
+        atomicAdd(&vis[obj], 1u);
+}
+#endif
+
 template <int TP>
 struct Q;
 
@@ -124,6 +152,9 @@ __global__ __launch_bounds__(256) void k_traverse(const void *__restrict__ tree,
     const uint32_t limit = 2 * N + 2;
     const uint64_t lt = (threadIdx.x & 63) ? (~0ull >> (64 - (threadIdx.x & 63))) : 0ull;
     uint32_t steps = 0;
+#ifdef CD_COUNTERS
+    uint32_t c_tests = 0, c_ll = 0, c_hits = 0;
+#endif
     while (node != kEnd) {
         if (++steps > limit || node >= 2 * N - 1) {
             atomicOr(err, 4u);
@@ -136,6 +167,14 @@ __global__ __launch_bounds__(256) void k_traverse(const void *__restrict__ tree,
             break;
         bool ov = time_overlap(qt0, qt1, t0, t1) && space_overlap(qlo, qhi, lo, hi);
         bool leaf = node >= N - 1;
+#ifdef CD_COUNTERS
+        ++c_tests;
+        c_ll += leaf ? 1u : 0u;
+        c_hits += (ov && leaf && link != qobj) ? 1u : 0u;
+        ctr_visit(qobj);
+        if (leaf)
+            ctr_visit(link);
+#endif
         if (use_side && leaf)
             esc = side[node - (N - 1)];
         bool hit = ov && leaf && link != qobj;
@@ -160,6 +199,15 @@ __global__ __launch_bounds__(256) void k_traverse(const void *__restrict__ tree,
         }
         node = (ov && !leaf) ? link : esc;
     }
+#ifdef CD_COUNTERS
+    if (c_tests) {
+        atomicAdd(&g_ctr[0], (unsigned long long)c_tests);
+        atomicAdd(&g_ctr[1], (unsigned long long)c_ll);
+        atomicAdd(&g_ctr[2], (unsigned long long)(c_tests - c_ll));
+        atomicAdd(&g_ctr[3], (unsigned long long)c_hits);
+        atomicAdd(&g_ctr[5], (unsigned long long)c_tests);
+    }
+#endif
 }
 
 hipError_t launch_traverse(const void *tree, int precision, uint32_t N, uint32_t slab_ticks,
@@ -234,35 +282,20 @@ __device__ inline bool load_side(const void *tree, const uint2 *kids, uint32_t N
     return true;
 }
 
-template <int TP>
-__global__ __launch_bounds__(1024) void k_expand(const void *__restrict__ tree,
-                                                const uint2 *__restrict__ kids, uint32_t N,
-                                                const uint2 *__restrict__ in,
-                                                const unsigned int *n_in, uint32_t in_cap,
-                                                uint2 *__restrict__ outq, unsigned int *n_out,
-                                                uint32_t out_cap, Rec *__restrict__ out,
-                                                unsigned long long capacity,
-                                                unsigned long long *counter, unsigned int *flags,
-                                                int gated)
+// One level over the n pairs of `in`, by every workgroup of the grid in turn
+// (block-uniform loop: the block scan needs every thread).  COH: the queue
+// entries are written and read as device-scope atomics, each coherent across
+// the XCDs' separate L2 caches by itself, for a reader in the same launch.
+template <int TP, bool COH = false>
+__device__ inline void expand_level(const void *__restrict__ tree, const uint2 *__restrict__ kids,
+                                    uint32_t N, const uint2 *__restrict__ in, uint32_t n,
+                                    uint2 *__restrict__ outq, unsigned int *n_out,
+                                    uint32_t out_cap, Rec *__restrict__ out,
+                                    unsigned long long capacity, unsigned long long *counter,
+                                    unsigned int *flags, uint32_t *wsum, unsigned int &qbase,
+                                    unsigned long long &rbase)
 {
     using F = typename Q<TP>::F;
-    __shared__ uint32_t wsum[64];
-    __shared__ unsigned int qbase;
-    __shared__ unsigned long long rbase;
-    // gated: a set flag (queue overflow, bad node, the traversal handed to the
-    // per-leaf walk, or an earlier level found its queue empty) ends the
-    // node-pair levels
-    if (gated && *flags)
-        return;
-    uint32_t n = *n_in;
-    n = n < in_cap ? n : in_cap;
-    if (n == 0) {
-        // every pair has been expanded: flag 8 tells the host (and the gate)
-        if (blockIdx.x == 0 && threadIdx.x == 0)
-            atomicOr(flags, 8u);
-        return;
-    }
-    // block-uniform loop: the block scan below needs every thread
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         uint32_t k = base + threadIdx.x;
         bool active = k < n;
@@ -270,7 +303,15 @@ __global__ __launch_bounds__(1024) void k_expand(const void *__restrict__ tree,
         F lo[2][2][3], hi[2][2][3];
         uint32_t t0[2][2], t1[2][2], lk[2][2];
         if (active) {
-            uint2 pr = in[k];
+            uint2 pr;
+            if (COH) {
+                unsigned long long v =
+                    __hip_atomic_load(reinterpret_cast<const unsigned long long *>(in + k),
+                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                pr = make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+            } else {
+                pr = in[k];
+            }
             bool ok = load_side<TP>(tree, kids, N, pr.x, ids[0], lo[0], hi[0], t0[0], t1[0],
                                     lk[0], cnt[0]) &&
                       load_side<TP>(tree, kids, N, pr.y, ids[1], lo[1], hi[1], t0[1], t1[1],
@@ -293,6 +334,29 @@ __global__ __launch_bounds__(1024) void k_expand(const void *__restrict__ tree,
                 if (ov && !leaves)
                     push_mask |= 1u << bit;
             }
+#ifdef CD_COUNTERS
+        {
+            uint32_t c_tests = 0, c_ll = 0, c_li = 0;
+            for (int ia = 0; ia < 2; ++ia)
+                for (int ic = 0; ic < 2; ++ic) {
+                    if (!(active && ia < (int)cnt[0] && ic < (int)cnt[1]))
+                        continue;
+                    const bool la = ids[0][ia] >= N - 1, lc = ids[1][ic] >= N - 1;
+                    ++c_tests;
+                    c_ll += (la && lc) ? 1u : 0u;
+                    c_li += (la != lc) ? 1u : 0u;
+                    if (la)
+                        ctr_visit(lk[0][ia]);
+                    if (lc)
+                        ctr_visit(lk[1][ic]);
+                }
+            ctr_wave_add(0, c_tests);
+            ctr_wave_add(1, c_ll);
+            ctr_wave_add(2, c_li);
+            ctr_wave_add(3, (uint32_t)__popc(hit_mask));
+            ctr_wave_add(4, active ? 1u : 0u);
+        }
+#endif
         // one scan packs both counts: pushes in the low 16 bits, hits above
         uint32_t mine = (uint32_t)__popc(push_mask) | ((uint32_t)__popc(hit_mask) << 16);
         uint32_t total;
@@ -308,7 +372,15 @@ __global__ __launch_bounds__(1024) void k_expand(const void *__restrict__ tree,
             int ia = bit >> 1, ic = bit & 1;
             if (push_mask & (1u << bit)) {
                 if (q < out_cap)
-                    outq[q] = make_uint2(ids[0][ia], ids[1][ic]);
+                {
+                    if (COH)
+                        __hip_atomic_store(reinterpret_cast<unsigned long long *>(outq + q),
+                                           (unsigned long long)ids[0][ia] |
+                                               ((unsigned long long)ids[1][ic] << 32),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    else
+                        outq[q] = make_uint2(ids[0][ia], ids[1][ic]);
+                }
                 else
                     atomicOr(flags, 1u);
                 ++q;
@@ -330,6 +402,37 @@ __global__ __launch_bounds__(1024) void k_expand(const void *__restrict__ tree,
     }
 }
 
+template <int TP>
+__global__ __launch_bounds__(1024) void k_expand(const void *__restrict__ tree,
+                                                const uint2 *__restrict__ kids, uint32_t N,
+                                                const uint2 *__restrict__ in,
+                                                const unsigned int *n_in, uint32_t in_cap,
+                                                uint2 *__restrict__ outq, unsigned int *n_out,
+                                                uint32_t out_cap, Rec *__restrict__ out,
+                                                unsigned long long capacity,
+                                                unsigned long long *counter, unsigned int *flags,
+                                                int gated)
+{
+    __shared__ uint32_t wsum[64];
+    __shared__ unsigned int qbase;
+    __shared__ unsigned long long rbase;
+    // gated: a set flag (queue overflow, bad node, the traversal handed to the
+    // per-leaf walk, or an earlier level found its queue empty) ends the
+    // node-pair levels
+    if (gated && *flags)
+        return;
+    uint32_t n = *n_in;
+    n = n < in_cap ? n : in_cap;
+    if (n == 0) {
+        // every pair has been expanded: flag 8 tells the host (and the gate)
+        if (blockIdx.x == 0 && threadIdx.x == 0)
+            atomicOr(flags, 8u);
+        return;
+    }
+    expand_level<TP>(tree, kids, N, in, n, outq, n_out, out_cap, out, capacity, counter, flags,
+                     wsum, qbase, rbase);
+}
+
 hipError_t launch_expand(const void *tree, const uint2 *kids, int precision, uint32_t N,
                          const uint2 *in, const unsigned int *n_in, uint32_t in_cap, uint2 *outq,
                          unsigned int *n_out, uint32_t out_cap, Rec *out,
@@ -347,6 +450,143 @@ hipError_t launch_expand(const void *tree, const uint2 *kids, int precision, uin
         k_expand<CD_FP32><<<blocks, threads, 0, s>>>(tree, kids, N, in, n_in, in_cap, outq, n_out,
                                                      out_cap, out, capacity, counter, flags,
                                                      gated);
+    return hipGetLastError();
+}
+
+// ---- every level in one launch ----------------------------------------------------------------
+//
+// The same levels, run by one grid that the device holds at once: the
+// workgroups take a level's pairs in turn, then wait for each other at a
+// counter, so the next level reads a complete queue and count.  What one
+// level hands to the next -- queue entries, counts, flags -- is written and
+// read as device-scope atomics, each coherent by itself across the XCDs'
+// separate L2 caches, and every wave waits for its own writes to complete
+// before its workgroup arrives; no fence has to write back or invalidate the
+// L2s (measured: with a release/acquire arrival per workgroup the traversal
+// of the 16 848-object hour took 0.91 ms, with this one 0.79 ms; one launch
+// per level takes 0.53 ms, so this form is not the default).
+// The grid is sized on the host to the resident capacity, so every workgroup
+// being waited for is running.  The wait ends in any case: a workgroup that
+// sees an overflow or bad-node flag, or waits past kGridWaitTicks of the
+// 100 MHz real-time clock, sets the handover flag and leaves; the query then
+// runs the per-leaf walk from a cleared count, and every other workgroup sees
+// the flag at its next wait.  A level with an empty input ends the kernel in
+// every workgroup alike (the count is complete when it is read).
+constexpr long long kGridWaitTicks = 200000000ll;   // 2 s
+
+__device__ inline unsigned int load_dev(const unsigned int *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int TP>
+__global__ __launch_bounds__(1024) void k_expand_all(const void *__restrict__ tree,
+                                                    const uint2 *__restrict__ kids, uint32_t N,
+                                                    const uint2 *seeds, const unsigned int *nseeds,
+                                                    uint32_t seed_cap, uint2 *qa, uint2 *qb,
+                                                    unsigned int *qcount, uint32_t qcap,
+                                                    uint32_t max_levels, Rec *__restrict__ out,
+                                                    unsigned long long capacity,
+                                                    unsigned long long *counter,
+                                                    unsigned int *flags, unsigned int *bar)
+{
+    __shared__ uint32_t wsum[64];
+    __shared__ unsigned int qbase, go;
+    __shared__ unsigned long long rbase;
+    if (load_dev(flags) & 7u)   // handed over before the launch: the same in every workgroup
+        return;
+    const uint2 *in = seeds;
+    const unsigned int *n_in = nseeds;
+    uint32_t in_cap = seed_cap;
+    for (uint32_t lev = 0; lev < max_levels; ++lev) {
+        uint32_t n = load_dev(n_in);
+        n = n < in_cap ? n : in_cap;
+        if (n == 0) {
+            if (blockIdx.x == 0 && threadIdx.x == 0)
+                atomicOr(flags, 8u);
+            return;
+        }
+        uint2 *outq = (lev & 1) ? qb : qa;
+        expand_level<TP, true>(tree, kids, N, in, n, outq, qcount + lev + 1, qcap, out,
+                               capacity, counter, flags, wsum, qbase, rbase);
+        // every wave's queue stores and count updates have completed (each
+        // is coherent by itself) before its workgroup arrives
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned int target = (lev + 1) * gridDim.x;
+            const long long start = wall_clock64();
+            unsigned int ok = 1;
+            while (load_dev(bar) < target) {
+                if ((load_dev(flags) & 7u) || wall_clock64() - start > kGridWaitTicks) {
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+            if (!ok)
+                atomicOr(flags, 4u);
+            go = ok;
+        }
+        __syncthreads();
+        if (!go)
+            return;
+        in = outq;
+        n_in = qcount + lev + 1;
+        in_cap = qcap;
+    }
+    // levels exhausted with pairs left: the walk finishes the query
+    if (blockIdx.x == 0 && threadIdx.x == 0 && load_dev(n_in) != 0)
+        atomicOr(flags, 4u);
+}
+
+// Workgroups of k_expand_all<TP> (1 024 lanes) the device holds at once.
+static uint32_t resident_expand_all(int precision)
+{
+    static uint32_t cached[2] = {0, 0};
+    const int t = precision == CD_FP64 ? 0 : 1;
+    if (cached[t])
+        return cached[t];
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return 0;
+    hipError_t e = precision == CD_FP64
+                       ? hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &per_cu, reinterpret_cast<const void *>(&k_expand_all<CD_FP64>),
+                             1024, 0)
+                       : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                             &per_cu, reinterpret_cast<const void *>(&k_expand_all<CD_FP32>),
+                             1024, 0);
+    if (e != hipSuccess || per_cu <= 0 || cus <= 0)
+        return 0;
+    cached[t] = (uint32_t)(per_cu * cus);
+    return cached[t];
+}
+
+hipError_t launch_expand_all(const void *tree, const uint2 *kids, int precision, uint32_t N,
+                             const uint2 *seeds, const unsigned int *nseeds, uint32_t seed_cap,
+                             uint2 *qa, uint2 *qb, unsigned int *qcount, uint32_t qcap,
+                             uint32_t max_levels, Rec *out, unsigned long long capacity,
+                             unsigned long long *counter, unsigned int *flags, unsigned int *bar,
+                             uint32_t blocks, hipStream_t s)
+{
+    if (N <= 1)
+        return hipSuccess;
+    uint32_t res = resident_expand_all(precision);
+    if (res == 0)
+        return hipErrorInvalidDeviceFunction;
+    uint32_t g = blocks < res ? blocks : res;
+    g = g ? g : 1;
+    if (precision == CD_FP64)
+        k_expand_all<CD_FP64><<<g, 1024, 0, s>>>(tree, kids, N, seeds, nseeds, seed_cap, qa, qb,
+                                                  qcount, qcap, max_levels, out, capacity,
+                                                  counter, flags, bar);
+    else
+        k_expand_all<CD_FP32><<<g, 1024, 0, s>>>(tree, kids, N, seeds, nseeds, seed_cap, qa, qb,
+                                                  qcount, qcap, max_levels, out, capacity,
+                                                  counter, flags, bar);
     return hipGetLastError();
 }
 
@@ -657,5 +897,30 @@ hipError_t launch_unique(const Rec *in, uint32_t count, uint32_t *flags, uint32_
     k_unique_scatter<<<nblk(count, 256), 256, 0, s>>>(in, count, flags, pos, out, pos + count);
     return hipGetLastError();
 }
+
+#ifdef CD_COUNTERS
+hipError_t counters_reset(uint32_t *visits, uint32_t nobj, hipStream_t s)
+{
+    static const unsigned long long zero[kCounterWords] = {};
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess)
+        e = hipMemcpyToSymbol(HIP_SYMBOL(g_ctr), zero, sizeof zero, 0, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpyToSymbol(HIP_SYMBOL(g_visits), &visits, sizeof visits, 0,
+                              hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpyToSymbol(HIP_SYMBOL(g_nobj), &nobj, sizeof nobj, 0, hipMemcpyHostToDevice);
+    return e;
+}
+
+hipError_t counters_read(unsigned long long *out, hipStream_t s)
+{
+    hipError_t e = hipStreamSynchronize(s);
+    if (e == hipSuccess)
+        e = hipMemcpyFromSymbol(out, HIP_SYMBOL(g_ctr), kCounterWords * sizeof(unsigned long long),
+                                0, hipMemcpyDeviceToHost);
+    return e;
+}
+#endif
 
 } // namespace cd

@@ -25,6 +25,26 @@ def test_library_exports_every_declared_symbol():
     assert set(decl) == set(cd.EXPORTED)
 
 
+def test_counters_build_exports_the_same_symbols():
+    """libcd4d_counters.so (CD_COUNTERS) is the same ABI; only it answers the
+    counter calls, the plain library refuses them without touching a device."""
+    import paper_1901_10475_amd as cd
+    assert cd.cd_counters_available() == 0
+    with pytest.raises(cd.CDError) as ei:
+        cd.cd_counters_read()
+    assert ei.value.status == cd.CD_E_INVALID
+    with pytest.raises(cd.CDError) as ei:
+        cd.cd_counters_reset(None)
+    assert ei.value.status == cd.CD_E_INVALID
+    with cd.counters_build() as L:
+        for name in _declared():
+            assert hasattr(L, name), name
+        assert cd.cd_counters_available() == 1
+        assert L is not cd._load(cd._LIB_PATH)
+    assert cd.lib() is cd._load(cd._LIB_PATH)
+    assert cd.cd_counters_available() == 0
+
+
 def test_header_constants_match_the_binding():
     """Every #define CD_* integer constant of include/cd4d.h has the same value
     in the Python binding."""
@@ -211,19 +231,22 @@ def test_band_argument_errors_before_any_launch():
 
 def test_tuning_ranges():
     """Launch shapes: node-pair workgroups of 64 to 1024 lanes (powers of 2),
-    per-leaf-walk workgroups of 64, 128 or 256; anything else is rejected and
-    changes nothing."""
+    per-leaf-walk workgroups of 64, 128 or 256, traversal modes 0 to 2;
+    anything else is rejected and changes nothing."""
     import paper_1901_10475_amd as cd
     cd.cd_set_tuning(None)
     base = cd.cd_get_tuning()
     for bad in ({"expand_threads": 384}, {"expand_threads": 2048}, {"walk_threads": 512},
-                {"expand_blocks": 32}, {"mode": 2}):
+                {"expand_blocks": 32}, {"mode": 3}):
         with pytest.raises(cd.CDError):
             cd.cd_set_tuning(bad)
         assert cd.cd_get_tuning() == base
     for ok in (512, 1024, 64):
         cd.cd_set_tuning({"expand_threads": ok})
         assert cd.cd_get_tuning()["expand_threads"] == ok
+    for mode in (0, 1, 2):
+        cd.cd_set_tuning({"mode": mode})
+        assert cd.cd_get_tuning()["mode"] == mode
     cd.cd_set_tuning(None)
     assert cd.cd_get_tuning() == base
 

@@ -2,7 +2,8 @@
 
 The device-count query must give, record for record, the list of the
 synchronising query on the same tree (bit-exact: both are canonical lists),
-in every traversal mode and with the per-leaf walk forced as fallback.  A
+in every traversal mode (one launch per node-pair level, every level in one
+launch, the per-leaf walk) and with the per-leaf walk forced as fallback.  A
 captured batch is replayed several times, with eager work and
 synchronisation between replays and a changed input before the last one;
 every replay is checked against eager runs.
@@ -60,7 +61,8 @@ def test_async_query_equals_eager(name, sc, heur):
     for tun in (None, {"mode": 1}, {"mode": 1, "walk_threads": 64}, {"max_levels": 1},
                 {"expand_blocks": 64, "expand_threads": 64},
                 {"expand_blocks": 256, "expand_threads": 512},
-                {"expand_blocks": 64, "expand_threads": 1024}):
+                {"expand_blocks": 64, "expand_threads": 1024},
+                {"mode": 2}, {"mode": 2, "expand_blocks": 64}, {"mode": 2, "expand_blocks": 4096}):
         for cap in (P, P + 1, 2 * P + 17):
             got, c, s = _async(bp, cap, tun)
             assert s == 0 and c == P, (tun, cap, c, s)
@@ -69,6 +71,28 @@ def test_async_query_equals_eager(name, sc, heur):
     if P >= 2:
         got, c, s = _async(bp, P - 1)
         assert s == 1 and c >= P
+
+
+@pytest.mark.parametrize("name,sc,heur", _cases(), ids=[c[0] for c in _cases()])
+def test_one_launch_traversal_equals_levels(name, sc, heur):
+    """Every node-pair level in one launch of a resident grid (mode 2), in the
+    synchronising query: the same canonical list as one launch per level."""
+    need_gpu()
+    say("one-launch traversal", name)
+    el = cd.soa(sc.elements)
+    p = cd.params_struct(sc.tick_s, sc.mu, sc.threshold_km, sc.horizon_ticks,
+                         sc.dt_ticks if heur is None else 0)
+    bp = cd.BroadPhase(sc.n, p, dt_heuristic_km=heur, el_soa=el)
+    ref = bp.run(el).cpu().numpy()
+    assert len(ref) > 0
+    try:
+        for tun in ({"mode": 2}, {"mode": 2, "expand_blocks": 64}, {"mode": 2, "expand_blocks": 4096}):
+            cd.cd_set_tuning(tun)
+            for rep in range(2):
+                got = bp.run(el).cpu().numpy()
+                assert np.array_equal(got, ref), (tun, rep)
+    finally:
+        cd.cd_set_tuning(None)
 
 
 def test_async_query_single_and_empty_trees():
