@@ -14,22 +14,32 @@ catalog, every object gets the speed-bound step for a displacement bound
 s * disp_km, for each scale s of a sweep, and each sweep point is one full
 query.  An object's cost at scale s is
 
-    C_i(s) = K_i(s) + pair_weight * R_i(s)
+    C_i(s) = K_i(s) + pair_weight * R_i(s) + node_weight * V_i(s)
 
-with K_i its number of intervals (its boxes: build, sort and refit work) and
-R_i the number of candidate records naming it (work handed to the narrow
-phase, where each candidate is refined by repeated halving of its interval).
-Record counts of single objects are small and noisy, so the target is not the
+with K_i its number of intervals (its boxes: build, sort and refit work), R_i
+the number of candidate records naming it (work handed to the narrow phase,
+where each candidate is refined by repeated halving of its interval) and V_i
+the traversal's box tests with one of its boxes on a side (counted by the
+library built with CD_COUNTERS; node_weight = 0 leaves the term out).
+Counts of single objects are small and noisy, so the target is not the
 arg-min of the measured C_i but of a cost model fitted to the whole sweep:
-K_i(s) = K_i(1) / s, R_i(s) = r_i s^q, with the exponent q fitted to the
-catalog's total record counts (least squares in log-log) and r_i the pooled
-rate sum_s R_i(s) / sum_s s^q (the maximum-likelihood rate of Poisson counts
-with those means).  The model's minimum is
+K_i(s) = K_i(1) / s, R_i(s) = r_i s^q and V_i(s) = v_i s^u, the exponents q
+and u fitted to the catalog's totals (least squares in log-log) and r_i, v_i
+the pooled rates sum_s R_i(s) / sum_s s^q and sum_s V_i(s) / sum_s s^u (the
+maximum-likelihood rates of Poisson counts with those means).  Without the
+test term the model's minimum is
 
-    s_i* = (K_i(1) / (pair_weight q r_i))^(1 / (q + 1)),
+    s_i* = (K_i(1) / (pair_weight q r_i))^(1 / (q + 1));
 
-clamped to the sweep's range (its largest scale when r_i = 0), and the
-target is log2 of the step s_i* dt_i(1), in seconds.
+with it, s_i* is the minimum over a grid of 512 scales spaced evenly in
+log s across the sweep's range.  s_i* is clamped to the sweep's range (its
+largest scale when r_i = 0 and v_i = 0), and the target is log2 of the step
+s_i* dt_i(1), in seconds.
+
+The default node_weight is the measured cost of one executed traversal test
+over that of one box (boxes, codes, sort, hierarchy and unions) on the
+16 848-object hour at 1 s steps: 0.53 ms for the traversal's 11.78 M tests
+(45 ps each) against 4.38 ms for 60.65 M boxes (72 ps each).
 
 Everything numeric runs in the library's kernels (features, forward, backward,
 Adam, record counts, the broad phase); this module sequences the calls and
@@ -41,11 +51,13 @@ import math
 import numpy as np
 import torch
 
-from . import (CD_FP32, CD_FP64, BroadPhase, _bytes, _check, _ptr, _stream, cd_dt_heuristic,
-               elements_struct, lib)
+from . import (CD_FP32, CD_FP64, BroadPhase, _bytes, _check, _ptr, _stream, cd_counters_reset,
+               cd_dt_heuristic, counters_build, elements_struct, lib)
 
 CD_MLP_PARAMS = 4609
 DEFAULT_SCALES = (0.25, 0.5, 1.0, 2.0, 4.0, 8.0, 16.0, 32.0, 64.0)
+PAIR_WEIGHT = 32.0
+NODE_WEIGHT = 0.6
 
 
 # ---- marshalled C calls --------------------------------------------------------------
@@ -209,48 +221,95 @@ def intervals_of(dt, horizon_ticks):
     return torch.clamp((T + d - 1) // d, min=1) if T > 0 else torch.ones_like(d)
 
 
-def run_costs(el_soa, params, dt, pair_weight, box_precision=CD_FP32, tree_precision=CD_FP32):
-    """One query with per-object steps dt: (per-object cost, records, boxes, pairs)."""
+def _run(el_soa, params, dt, visits_too, box_precision, tree_precision):
+    """One query with per-object steps dt: (pairs, per-object record counts,
+    per-object test counts or None, boxes)."""
     n = el_soa.shape[1]
     bp = BroadPhase(n, params, dt_ticks=dt, box_precision=box_precision,
                     tree_precision=tree_precision)
-    pairs = bp.run(el_soa)
-    counts = cd_pair_object_counts(pairs, n)
+    visits = None
+    if visits_too:
+        visits = torch.zeros(n, dtype=torch.int32, device=el_soa.device)
+        with counters_build():
+            cd_counters_reset(visits)
+            try:
+                pairs = bp.run(el_soa)
+            finally:
+                cd_counters_reset(None)   # unbind before the tensor goes
+    else:
+        pairs = bp.run(el_soa)
+    return pairs, cd_pair_object_counts(pairs, n), visits, bp.count
+
+
+def run_costs(el_soa, params, dt, pair_weight=PAIR_WEIGHT, node_weight=NODE_WEIGHT,
+              box_precision=CD_FP32, tree_precision=CD_FP32):
+    """One query with per-object steps dt: (per-object cost, records, boxes, pairs)."""
+    pairs, counts, visits, boxes = _run(el_soa, params, dt, node_weight > 0, box_precision,
+                                        tree_precision)
     K = intervals_of(dt, params.horizon_ticks)
     cost = K.double() + pair_weight * counts.double()
-    return cost, counts, bp.count, pairs
+    if visits is not None:
+        cost += node_weight * visits.double()
+    return cost, counts, boxes, pairs
 
 
-def sweep_targets(el_soa, params, scales=DEFAULT_SCALES, disp_km=5.0, pair_weight=32.0,
-                  box_precision=CD_FP32, tree_precision=CD_FP32):
+def _growth(scales, totals, lo, hi):
+    """Exponent of a count's growth with the scale: least squares in log-log
+    over the catalog totals, clamped to [lo, hi]."""
+    if len(scales) < 2:
+        return 1.0
+    tot = np.maximum(np.asarray(totals, dtype=np.float64), 1.0)
+    x = float(np.polyfit(np.log(scales), np.log(tot), 1)[0])
+    return min(max(x, lo), hi)
+
+
+def sweep_targets(el_soa, params, scales=DEFAULT_SCALES, disp_km=5.0, pair_weight=PAIR_WEIGHT,
+                  node_weight=NODE_WEIGHT, box_precision=CD_FP32, tree_precision=CD_FP32):
     """(features [n,5], target log2 seconds [n], per-scale summary)."""
     n = el_soa.shape[1]
     scales = sorted(float(s) for s in scales)
-    counts = []
+    counts, visits = [], []
     summary = []
     dt1 = torch.empty(n, dtype=torch.int32, device=el_soa.device)
     cd_dt_heuristic(el_soa, params, disp_km, dt1)
     for s in scales:
         dt = torch.empty(n, dtype=torch.int32, device=el_soa.device)
         cd_dt_heuristic(el_soa, params, disp_km * s, dt)
-        cost, c, boxes, pairs = run_costs(el_soa, params, dt, pair_weight, box_precision,
-                                          tree_precision)
+        pairs, c, v, boxes = _run(el_soa, params, dt, node_weight > 0, box_precision,
+                                  tree_precision)
+        cost = intervals_of(dt, params.horizon_ticks).double() + pair_weight * c.double()
+        if v is not None:
+            cost += node_weight * v.double()
+            visits.append(v.double())
         summary.append({"scale": s, "boxes": int(boxes), "records": int(pairs.shape[0]),
+                        "tests": int(v.sum().item()) if v is not None else None,
                         "cost": float(cost.sum().item())})
         counts.append(c.double())
         del pairs
-    # exponent of the record count's growth with the scale (catalog totals)
-    tot = np.array([max(r["records"], 1) for r in summary], dtype=np.float64)
-    q = float(np.polyfit(np.log(scales), np.log(tot), 1)[0]) if len(scales) > 1 else 1.0
-    q = min(max(q, 0.25), 4.0)
-    sq = sum(s ** q for s in scales)
-    rate = torch.stack(counts).sum(dim=0) / sq
+    q = _growth(scales, [r["records"] for r in summary], 0.25, 4.0)
+    rate = torch.stack(counts).sum(dim=0) / sum(s ** q for s in scales)
     K1 = intervals_of(dt1, params.horizon_ticks).double()
     s_lo, s_hi = scales[0], scales[-1]
-    s_star = torch.where(rate > 0,
-                         (K1 / (pair_weight * q * rate.clamp(min=1e-30))) ** (1.0 / (q + 1.0)),
-                         torch.full_like(K1, s_hi)).clamp(s_lo, s_hi)
+    if not visits:
+        s_star = torch.where(
+            rate > 0, (K1 / (pair_weight * q * rate.clamp(min=1e-30))) ** (1.0 / (q + 1.0)),
+            torch.full_like(K1, s_hi)).clamp(s_lo, s_hi)
+        u = None
+    else:
+        # V_i counts the tests of every box of object i; with fewer, longer
+        # boxes it may fall or grow, so u may take either sign
+        u = _growth(scales, [r["tests"] for r in summary], -4.0, 4.0)
+        vrate = torch.stack(visits).sum(dim=0) / sum(s ** u for s in scales)
+        grid = torch.logspace(math.log2(s_lo), math.log2(s_hi), 512, base=2.0,
+                              dtype=torch.float64, device=K1.device)
+        s_star = torch.empty_like(K1)
+        for a in range(0, n, 8192):   # rows of objects x grid scales
+            b = min(n, a + 8192)
+            C = (K1[a:b, None] / grid + pair_weight * rate[a:b, None] * grid ** q
+                 + node_weight * vrate[a:b, None] * grid ** u)
+            s_star[a:b] = grid[torch.argmin(C, dim=1)]
     target = torch.log2(s_star * dt1.double() * params.tick_s).float()
     for r in summary:
         r["q"] = q
+        r["u"] = u
     return cd_mlp_features(el_soa, params), target, summary
