@@ -306,7 +306,10 @@ __global__ __launch_bounds__(128) void k_boxes_uniform(const ObjConst *__restric
                                                        const ObjSinus *__restrict__ os,
                                                        uint32_t n, uint32_t K, uint32_t dt,
                                                        uint32_t T, double tick_s, double half_thr,
-                                                       uint32_t chunk, bool sorted, BoxOut out)
+                                                       uint32_t chunk, bool sorted,
+                                                       const uint32_t *rank_code,
+                                                       const uint32_t *rank_obj, uint32_t res,
+                                                       BoxOut out)
 {
     uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     uint64_t k0 = (uint64_t)blockIdx.y * chunk;
@@ -319,9 +322,10 @@ __global__ __launch_bounds__(128) void k_boxes_uniform(const ObjConst *__restric
         bool valid = r < n;
         uint32_t i = 0, code = 0;
         if (valid) {
-            const uint32_t *w = (const uint32_t *)(out.rec + k0 * n + r);
-            i = w[kRecObj];
-            code = w[kRecCode];
+            // rank r's object and code, as k_block_sort left them in entries
+            // that only this thread rewrites (rank r of the block's slabs)
+            i = rank_obj[(k0 * n + r) * res];
+            code = rank_code[(k0 * n + r) * res];
             valid = i < n;   // always: k_block_sort wrote a permutation
             i = valid ? i : 0;
         }
@@ -336,16 +340,9 @@ __global__ __launch_bounds__(128) void k_boxes_uniform(const ObjConst *__restric
     int64_t code = kNoCode;
     if (sorted) {
         // rank r's object and code, left by k_block_sort in the obj and code
-        // entries of box k0 n + r (array entries, or record words), which
-        // this thread overwrites itself
-        if (out.rec) {
-            const uint32_t *w = (const uint32_t *)(out.rec + k0 * n + r);
-            i = w[kRecObj];
-            code = w[kRecCode];
-        } else {
-            i = out.obj[k0 * n + r];
-            code = out.code[k0 * n + r];
-        }
+        // entries of box k0 n + r, which this thread overwrites itself
+        i = rank_obj[(k0 * n + r) * res];
+        code = rank_code[(k0 * n + r) * res];
         if (i >= n)   // cannot happen: k_block_sort wrote a permutation
             return;
     }
@@ -543,10 +540,12 @@ hipError_t launch_dt_heuristic(const cd_elements &el, double mu, double tick_s,
 template <int PREC, int RULE>
 static void boxes_uniform(dim3 grid, hipStream_t s, const ObjConst *oc, const ObjSinus *os,
                           uint32_t n, uint32_t K, uint32_t dt, uint32_t T, double tick_s,
-                          double half_thr, uint32_t chunk, bool sorted, const BoxOut &out)
+                          double half_thr, uint32_t chunk, bool sorted, const uint32_t *rank_code,
+                          const uint32_t *rank_obj, uint32_t res, const BoxOut &out)
 {
     k_boxes_uniform<PREC, RULE><<<grid, 128, 0, s>>>(oc, os, n, K, dt, T, tick_s, half_thr,
-                                                     chunk, sorted, out);
+                                                     chunk, sorted, rank_code, rank_obj, res,
+                                                     out);
 }
 
 uint32_t uniform_chunk(uint32_t K)
@@ -571,17 +570,30 @@ hipError_t launch_boxes_uniform(const ObjConst *oc, const ObjSinus *os, uint32_t
     dim3 grid(blocks_for(n, 128), (K + chunk - 1) / chunk);
     if (out.rec && !sorted)
         return hipErrorInvalidValue;   // box records come in the sorted layout
+    uint32_t *sc = nullptr, *so = nullptr, st = 1;
     if (sorted) {
-        // per block of `chunk` slabs: objects' codes at the block's middle
-        // into the t0 (arrays) or t1 (records) entries of the block's first
-        // slab, sorted with their ids into its code and obj entries; the box
-        // kernel rewrites all of them
+        // per block of `chunk` slabs: objects' codes at the block's middle,
+        // sorted with their ids (rank r's code and id where the box kernel
+        // thread of rank r reads them before it rewrites those entries)
         if ((!out.code && !out.rec) || !out.frame || (uint64_t)n * K > out.cap)
             return hipErrorInvalidValue;
-        uint32_t *u, *sc, *so, *rc = nullptr, *ro = nullptr, st;
-        if (out.rec) {
-            // words 0 and 1 (the first bound, rewritten by the box kernel)
-            // hold the sort's runs when n needs several
+        uint32_t *u, *rc = nullptr, *ro = nullptr;
+        const uint32_t runs = (uint32_t)((n + kSegCap - 1) / kSegCap);
+        const uint64_t last = K - (uint64_t)(grid.y - 1) * chunk;   // slabs of the last block
+        if (out.rec && out.code && last >= (runs > 1 ? 5u : 3u)) {
+            // contiguous, in the code array's entries of each block's first
+            // slabs: sorted codes (slab 0), sorted ids (slab 1), unsorted
+            // codes by object (slab 2), the runs' codes and ids (slabs 3, 4)
+            sc = out.code;
+            so = out.code + n;
+            u = out.code + 2 * (uint64_t)n;
+            rc = out.code + 3 * (uint64_t)n;
+            ro = out.code + 4 * (uint64_t)n;
+            st = 1;
+        } else if (out.rec) {
+            // a short last block: one word per record of the block's first
+            // slab (t1: unsorted, code and obj: sorted; words 0 and 1, the
+            // first bound, the runs)
             uint32_t *w = (uint32_t *)out.rec;
             u = w + kRecT1;
             sc = w + kRecCode;
@@ -608,7 +620,7 @@ hipError_t launch_boxes_uniform(const ObjConst *oc, const ObjSinus *os, uint32_t
     auto go = [&](auto prec, auto rl) {
         boxes_uniform<decltype(prec)::value, decltype(rl)::value>(grid, s, oc, os, n, K, dt, T,
                                                                   tick_s, half_thr, chunk, sorted,
-                                                                  out);
+                                                                  sc, so, st, out);
     };
     dispatch_rule(precision, rule, go);
     return hipGetLastError();

@@ -6,13 +6,16 @@ exactly one inner node, the link and skip records walk every node once in
 depth-first pre-order, and the seed list holds exactly the sibling pairs whose
 boxes overlap (closed extents in space, half-open tags in time).
 
-Covered: uniform steps, where the boxes of each interval form one slab that
-one workgroup sorts in LDS before the Karras pass over the slab codes and the
-chunked refit (slabs of 1, 2, 300 and 17 408 boxes, the largest one workgroup
-sorts, and 70 000 slabs of 3; 17 409 objects per interval take the device-wide
-sort instead), or that arrives already in Morton order (the sorted layout:
-no sort; the refit reads the leaves from the box arrays); per-object steps (the general path: one radix
-sort of all keys); FP64 and FP32 trees; boxes with and without Morton codes.
+Covered: uniform steps, where the boxes of each interval form one slab --
+in object order, which one workgroup sorts in LDS per slab before the Karras
+pass and the chunked refit (slabs of 1, 2, 300 and 17 408 boxes, the largest
+one workgroup sorts, and 70 000 slabs of 3; 17 409 objects per interval take
+the device-wide sort instead); in the sorted layout as box arrays (no sort;
+Karras over the block's codes and the chunked refit); or in the sorted layout
+as the tree's own leaf records (the bottom-up pass builds hierarchy and
+unions together; up to 16 sorted runs merged per block); per-object steps
+(the general path: one radix sort of all keys); FP64 and FP32 trees; boxes
+with and without Morton codes.
 
 Tree buffer layout read here: a 256-byte header (error bits, seed count, seed
 overflow), the node records (FP64: 64 bytes each, lo[3], hi[3] as doubles, then
@@ -245,16 +248,17 @@ def test_sorted_layout_order(n, K):
     assert np.array_equal(rc, oracle.pairs_bucketed(oracle.Boxes(lo, hi, t0, t1, obj)))
 
 
-@pytest.mark.parametrize("n", [17409, 20000, 36001])
-def test_sorted_layout_from_merged_runs(n):
+@pytest.mark.parametrize("n,K", [(17409, 9), (20000, 9), (36001, 9), (20000, 16), (36001, 13)])
+def test_sorted_layout_from_merged_runs(n, K):
     """More objects than one workgroup sorts: each block's codes are sorted in
     runs and merged by rank.  Every slab holds each object once, in
     non-decreasing code order with equal codes by object index, the same
-    order in every slab of a block (9 slabs: a block of 8 and one of 1); the
-    boxes and the record list equal the object layout's, and the records equal
-    the oracle's on the in-place leaves."""
+    order in every slab of a block; the boxes and the record list equal the
+    object layout's, and the records equal the oracle's on the in-place
+    leaves.  9 slabs (a block of 8 and one of 1) keep the sort's scratch in
+    the first slab's records; 16 and 13 slabs (last blocks of 8 and 5) keep
+    it in the code array's entries of each block's first five slabs."""
     need_gpu()
-    K = 9
     say("sorted layout from merged runs, n", n, "K", K)
     a = _uniform(n, K, 2, seed=n + 7, layout=cd.CD_LAYOUT_OBJECT, in_tree=False)
     c = _uniform(n, K, 2, seed=n + 7, layout=cd.CD_LAYOUT_SORTED, in_tree=True)
