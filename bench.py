@@ -53,15 +53,15 @@ BOX_SUFFIX = {"speed": "", "nu": "_box_interval_nu", "ecc": "_box_interval_ecc"}
 
 TRAFFIC = {
     # k_agglo_leaves + 4 item passes with their scans and compactions
-    ("hierarchy", "fp64", "fixed"): {"fetch_kib": 2014027.4 + 57454.0 + 10091.0 + 138.9,
-                                     "write_kib": 4469558.8 + 75675.0 + 13266.6 + 234.9,
+    ("hierarchy", "fp64", "fixed"): {"fetch_kib": 2014011.2 + 57395.5 + 10095.2 + 154.1,
+                                     "write_kib": 4469493.0 + 75732.2 + 13266.6 + 234.9,
                                      "sources": {"paper_1901_10475_amd/csrc/k_agglo.hip":
-                                                 "606f0a2a607766f3db31b39b6f13d0eb78354a80"}},
+                                                 "d4c20c009293ecd4b2b467e90068f670e3196348"}},
     # k_block_codes + k_block_sort + k_boxes_uniform (records)
-    ("boxes", "fp64", "fixed"): {"fetch_kib": 4470.6 + 263910.0 + 266351.0,
-                                 "write_kib": 236967.0 + 289546.0 + 4098192.0,
+    ("boxes", "fp64", "fixed"): {"fetch_kib": 3205.5 + 38902.9 + 41182.7,
+                                 "write_kib": 29615.6 + 109782.1 + 4113594.3,
                                  "sources": {"paper_1901_10475_amd/csrc/k_boxes.hip":
-                                             "8dab1ac1bb2701527b213dbefe051b8acb9e0c8b",
+                                             "5a3399e58189a37d740143870da7abded4d8d86c",
                                              "paper_1901_10475_amd/csrc/k_sort.hip":
                                              "5499fda60e277c01f68b81b459b0f3d964c6a85b"}},
 }
@@ -605,6 +605,7 @@ def run_batch(args, log):
             "dtype": "f64" if prec == cd.CD_FP64 and box_prec == cd.CD_FP64 else "f32 tree",
             "data": "synthetic (seeded LEO scenarios)",
             "config": {"workload": f"batch64_leo_30min_dt1s", "scenarios": len(scs),
+                       "branches": len(br.branch_streams),
                        "n_min": min(sizes), "n_max": max(sizes), "boxes": br.boxes_total(),
                        "brute_force_tests": tests, "graph": "one launch per step",
                        "in_tree_scenarios": int(sum(br.in_tree)),

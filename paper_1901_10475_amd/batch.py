@@ -3,14 +3,18 @@
 The paper notes that sub-problems of the collision search are independent
 (Sec. Decomposition of the AABB Tree State Space), which makes batching them
 natural.  ``BatchRunner`` runs the whole path (boxes, tree, canonical pairs)
-for every scenario of a batch, one after another on one stream, and records
-that sequence once into a hipGraph (``cd_graph_*``); a replay is one launch
-for the whole batch, with no host synchronisation inside it.
+for every scenario of a batch and records it once into a hipGraph
+(``cd_graph_*``); a replay is one launch for the whole batch, with no host
+synchronisation inside it.
 
-The scenarios run in order and share one set of box, tree and workspace
-buffers sized for the largest (``shared_buffers=False`` gives every scenario
-its own boxes and tree instead, so that they outlive the replay); each keeps
-its own output list, record count and status word on the device.  FP64 boxes
+The scenarios are dealt to ``branches`` streams (largest first, each to the
+branch with the fewest boxes so far); inside the graph the branches run side
+by side, each one's scenarios in order, so the small scenarios' short,
+latency-bound launches overlap instead of queueing behind each other.  The
+scenarios of a branch share one set of box, tree and workspace buffers sized
+for its largest (``shared_buffers=False`` gives every scenario its own boxes
+and tree instead, so that they outlive the replay); each scenario keeps its
+own output list, record count and status word on the device.  FP64 boxes
 of an FP64 tree are written as the tree's own leaf records in the sorted
 layout (``Boxes.in_tree``), so every scenario's tree is built bottom-up in
 place; other precisions use box arrays.  Output
@@ -60,7 +64,8 @@ class _Tree:
 
 class BatchRunner:
     def __init__(self, scenarios, box_precision=CD_FP64, tree_precision=CD_FP64,
-                 margin=1.25, min_capacity=4096, device="cuda", shared_buffers=True):
+                 margin=1.25, min_capacity=4096, device="cuda", shared_buffers=True,
+                 branches=4):
         self.sc = list(scenarios)
         self.box_precision, self.tree_precision = box_precision, tree_precision
         self.margin, self.min_capacity = margin, min_capacity
@@ -91,26 +96,44 @@ class BatchRunner:
                     torch.empty(N, dtype=torch.int32, device=device),
                     torch.empty(N, dtype=torch.int32, device=device))
 
+        # branches: largest scenario first, each to the branch with the
+        # fewest boxes so far
+        S = len(self.sc)
+        B = max(1, min(int(branches), S))
+        load = [0] * B
+        self.branch_of = [0] * S
+        for k in sorted(range(S), key=lambda k: -self.counts[k]):
+            b = min(range(B), key=lambda b: load[b])
+            self.branch_of[k] = b
+            load[b] += self.counts[k]
+        members = [[k for k in range(S) if self.branch_of[k] == b] for b in range(B)]
+        self.members = members
+
         need_arrays = not all(self.in_tree)
         if shared_buffers:
-            arrays = box_arrays(Nmax) if need_arrays else None
-            codes = torch.empty(Nmax, dtype=torch.int32, device=device)
-            tree_mem = _bytes(lib().cd_tree_bytes(Nmax, tree_precision), device)
-            self.arrays = [arrays] * len(self.sc)
-            self.codes = [codes] * len(self.sc)
-            self.tree_mems = [tree_mem] * len(self.sc)
+            self.arrays, self.codes, self.tree_mems = [None] * S, [None] * S, [None] * S
+            for b in range(B):
+                Nb = max(self.counts[k] for k in members[b])
+                arrays = (box_arrays(Nb) if any(not self.in_tree[k] for k in members[b])
+                          else None)
+                codes = torch.empty(Nb, dtype=torch.int32, device=device)
+                tree_mem = _bytes(lib().cd_tree_bytes(Nb, tree_precision), device)
+                for k in members[b]:
+                    self.arrays[k], self.codes[k], self.tree_mems[k] = arrays, codes, tree_mem
         else:
             self.arrays = [None if t else box_arrays(N) for N, t in zip(self.counts, self.in_tree)]
             self.codes = [torch.empty(N, dtype=torch.int32, device=device) for N in self.counts]
             self.tree_mems = [_bytes(lib().cd_tree_bytes(N, tree_precision), device)
                               for N in self.counts]
-        self.ws_boxes = _bytes(max(lib().cd_build_boxes_ws(s.n) for s in self.sc), device)
-        self.ws_tree = _bytes(lib().cd_build_tree_ws(Nmax), device)
+        # workspaces per branch
+        self.ws_boxes_b = [_bytes(max(lib().cd_build_boxes_ws(self.sc[k].n) for k in members[b]),
+                                  device) for b in range(B)]
+        self.ws_tree_b = [_bytes(lib().cd_build_tree_ws(max(self.counts[k] for k in members[b])),
+                                 device) for b in range(B)]
         self.trees = [_Tree(m, N, tree_precision) for m, N in zip(self.tree_mems, self.counts)]
         self.boxes = [Boxes.in_tree(tr, N, device, code=c) if t else _Boxes(a, N, box_precision)
                       for tr, N, t, a, c in zip(self.trees, self.counts, self.in_tree, self.arrays,
                                                 self.codes)]
-        S = len(self.sc)
         self.count_dev = torch.zeros(S, dtype=torch.int64, device=device)
         self.status_dev = torch.zeros(S, dtype=torch.int32, device=device)
         self.capacity = [0] * S
@@ -118,6 +141,7 @@ class BatchRunner:
         self.ws_query = None
         self.graph = None
         self.stream = torch.cuda.Stream(device=device)
+        self.branch_streams = [torch.cuda.Stream(device=device) for _ in range(B)]
         self.tunings = [None] * S
 
     def box_arrays(self, k):
@@ -133,11 +157,13 @@ class BatchRunner:
     # -- one scenario, eager ------------------------------------------------------
     def _build(self, k):
         b = self.boxes[k]
+        br = self.branch_of[k]
         b.desc.layout = CD_LAYOUT_SORTED   # where n allows; the layout written is kept
-        cd_build_boxes(self.el[k], None, self.params[k], b, self.ws_boxes)
+        cd_build_boxes(self.el[k], None, self.params[k], b, self.ws_boxes_b[br])
+        ws_tree = self.ws_tree_b[br]
         _check(lib().cd_build_tree(ctypes.byref(b.desc), self.tree_precision, 0,
-                                   ctypes.byref(self.trees[k].desc), _ptr(self.ws_tree),
-                                   self.ws_tree.numel(), _stream()))
+                                   ctypes.byref(self.trees[k].desc), _ptr(ws_tree),
+                                   ws_tree.numel(), _stream()))
 
     def run_eager(self, k):
         """Pairs of scenario k by the synchronising query (int32 [P, 4])."""
@@ -195,25 +221,45 @@ class BatchRunner:
     def _alloc_outputs(self):
         self.out = [torch.empty((c, 4), dtype=torch.int32, device=self.device)
                     for c in self.capacity]
-        Nmax, cmax = max(self.counts), max(self.capacity)
-        self.ws_query = _bytes(lib().cd_query_pairs_ws(Nmax, cmax), self.device)
+        self.ws_query = [
+            _bytes(lib().cd_query_pairs_ws(max(self.counts[k] for k in m),
+                                           max(self.capacity[k] for k in m)), self.device)
+            for m in self.members]
 
     def _apply_tuning(self, k):
         cd_set_tuning(self.tunings[k])
 
     # -- the batch as one graph -------------------------------------------------------
-    def enqueue(self):
-        """Enqueue the whole batch (boxes, tree, device-count query per scenario)."""
+    def enqueue_branch(self, b):
+        """Enqueue branch b's scenarios (boxes, tree, device-count query each)
+        on the current stream."""
         saved = cd_get_tuning()
         try:
-            for k in range(len(self.sc)):
+            for k in self.members[b]:
                 self._apply_tuning(k)
                 self._build(k)
                 cd_query_pairs_async(self.trees[k], self.out[k], self.capacity[k],
                                      self.count_dev[k:k + 1], self.status_dev[k:k + 1],
-                                     self.ws_query)
+                                     self.ws_query[b])
         finally:
             cd_set_tuning(saved)
+
+    def enqueue(self):
+        """Enqueue the whole batch from the current stream: the branches fork
+        from it on their own streams and join it again at the end."""
+        main = torch.cuda.current_stream()
+        fork = torch.cuda.Event()
+        fork.record(main)
+        joins = []
+        for b, st in enumerate(self.branch_streams):
+            st.wait_event(fork)
+            with torch.cuda.stream(st):
+                self.enqueue_branch(b)
+            ev = torch.cuda.Event()
+            ev.record(st)
+            joins.append(ev)
+        for ev in joins:
+            main.wait_event(ev)
 
     def capture(self):
         if self.ws_query is None:

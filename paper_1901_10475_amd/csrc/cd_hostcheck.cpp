@@ -187,6 +187,21 @@ int hc_agglo(const uint32_t *codes, int64_t N64, uint32_t ms, uint32_t C, uint64
             if (pass == 0)
                 for (uint32_t K = C0; K < C0 + m; ++K)
                     esc_leaf[K] = escape_adj(A, N, K);
+            // items partition the leaves in order (each starts one leaf after
+            // the previous one ends) and carry their Karras number: the leaf's
+            // own for an item of one leaf, else the last leaf for a left child
+            // (prefix after the last leaf above the one before the first) and
+            // the first for a right child
+            if (pass > 0)
+                for (uint32_t K = C0; K < C0 + m; ++K) {
+                    const uint32_t f = K == 0 ? 0u : items[K - 1].l + 1;
+                    const uint32_t l = items[K].l;
+                    const uint32_t id = f == l ? N - 1 + f : (A.at(K) > A.at(K - 1) ? l : f);
+                    if (items[K].f != f)
+                        return -13;
+                    if (items[K].id != id)
+                        return -14;
+                }
             // slot k: the node whose box it holds, its other end, end
             // prefixes and split (kEnd: still the item itself)
             std::vector<uint32_t> slot_node(m), other(m), spl(m, kEnd), cnt(m, 0);

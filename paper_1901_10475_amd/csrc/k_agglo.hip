@@ -435,13 +435,18 @@ __global__ __launch_bounds__(C) void k_agglo_items(CodeKeys G, const AggItem *__
 // Exclusive scan of the chunks' root counts (one workgroup) into offsets, and
 // the next pass's item count into *next_count.  Only the ceil(M / C) chunks
 // that had items wrote a count.  Each wave owns one contiguous segment, read
-// 64 counts at a time: a first sweep sums it, the segment sums are scanned
-// across the waves, and a second sweep writes the offsets.
+// 64 counts at a time with kScanBatch reads in flight: a first sweep sums it,
+// the segment sums are scanned across the waves, and a second sweep writes
+// the offsets.
+// With `next` set (passes with few chunks) the same workgroup then moves
+// every chunk's roots to their places, as k_agglo_compact does.
 __global__ __launch_bounds__(kAggScanThreads) void k_agglo_scan(const uint32_t *counts,
                                                                 const uint32_t *in_count,
                                                                 uint32_t M_host, uint32_t C,
                                                                 uint32_t *offsets,
-                                                                uint32_t *next_count)
+                                                                uint32_t *next_count,
+                                                                const AggItem *stage,
+                                                                AggItem *next)
 {
     __shared__ uint32_t wsum[33];
     const uint32_t M = in_count ? *in_count : M_host;
@@ -449,25 +454,51 @@ __global__ __launch_bounds__(kAggScanThreads) void k_agglo_scan(const uint32_t *
     const uint32_t lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = kAggScanThreads / 64;
     const uint32_t seg = ((nc + nw - 1) / nw + 63) & ~63u;
     const uint32_t b0 = w * seg, b1 = b0 + seg < nc ? b0 + seg : nc;
+    constexpr uint32_t kScanBatch = 8;
     uint32_t part = 0;
-    for (uint32_t k = b0 + lane; k < b1; k += 64)
-        part += counts[k];
+    for (uint32_t k0 = b0; k0 < b1; k0 += 64 * kScanBatch) {
+        uint32_t v[kScanBatch];
+#pragma unroll
+        for (uint32_t u = 0; u < kScanBatch; ++u) {
+            const uint32_t k = k0 + 64 * u + lane;
+            v[u] = k < b1 ? counts[k] : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kScanBatch; ++u)
+            part += v[u];
+    }
     for (int o = 32; o >= 1; o >>= 1)
         part += __shfl_xor(part, o, 64);
     uint32_t total;
     // every lane of wave w holds the segment sum; lane 0 enters it
     uint32_t run = block_exclusive_scan(lane == 0 ? part : 0u, wsum, &total);
     run = __shfl(run, 0, 64);
-    for (uint32_t k0 = b0; k0 < b1; k0 += 64) {
-        const uint32_t k = k0 + lane;
-        const uint32_t v = k < b1 ? counts[k] : 0u;
-        const uint32_t inc = wave_inclusive_scan(v);
-        if (k < b1)
-            offsets[k] = run + inc - v;
-        run += __shfl(inc, 63, 64);
+    for (uint32_t k0 = b0; k0 < b1; k0 += 64 * kScanBatch) {
+        uint32_t v[kScanBatch];
+#pragma unroll
+        for (uint32_t u = 0; u < kScanBatch; ++u) {
+            const uint32_t k = k0 + 64 * u + lane;
+            v[u] = k < b1 ? counts[k] : 0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kScanBatch; ++u) {
+            const uint32_t k = k0 + 64 * u + lane;
+            const uint32_t inc = wave_inclusive_scan(v[u]);
+            if (k < b1)
+                offsets[k] = run + inc - v[u];
+            run += __shfl(inc, 63, 64);
+        }
     }
     if (threadIdx.x == 0)
         *next_count = total;
+    if (!next)
+        return;
+    __syncthreads();   // the offsets written by the other waves
+    for (uint32_t c = w; c < nc; c += nw) {
+        const uint32_t n = counts[c], o = offsets[c];
+        for (uint32_t k = lane; k < n; k += 64)
+            next[o + k] = stage[(size_t)c * kAggOut + k];
+    }
 }
 
 // Every chunk's roots to their places in the next pass's item list: one wave
@@ -503,7 +534,9 @@ hipError_t launch_agglo(const uint32_t *code, uint32_t slab_size, uint32_t slab_
     if (!code || slab_size == 0 || slab_ticks == 0 || !ws)
         return hipErrorInvalidValue;
     constexpr int C = kAggChunk;
-    constexpr uint32_t kItemGrid = 512, kCompactGrid = 4096;
+    // item passes: workgroups striding over the chunks; compaction grid; up
+    // to kFuseChunks chunks the scan's workgroup also compacts
+    constexpr uint32_t kItemGrid = 512, kCompactGrid = 4096, kFuseChunks = 1024;
     const size_t chunks1 = (N + C - 1) / C;
     Carve cv(ws, agglo_ws_bytes(N));
     AggItem *stage = cv.take<AggItem>(chunks1 * kAggOut);
@@ -521,15 +554,19 @@ hipError_t launch_agglo(const uint32_t *code, uint32_t slab_size, uint32_t slab_
     while (e == hipSuccess && bound > (uint32_t)C) {
         const uint32_t nchunks = nblk(bound, C);
         uint32_t *next_count = totals + cur;
+        const bool fuse = nchunks <= kFuseChunks;
         k_agglo_scan<<<1, kAggScanThreads, 0, s>>>(counts, in_count, bound, C, offsets,
-                                                   next_count);
+                                                   next_count, fuse ? stage : nullptr,
+                                                   fuse ? items[cur] : nullptr);
         if ((e = hipGetLastError()) != hipSuccess)
             break;
-        const uint32_t cgrid = nblk(nchunks, 4);
-        k_agglo_compact<<<cgrid < kCompactGrid ? cgrid : kCompactGrid, 256, 0, s>>>(
-            stage, counts, offsets, in_count, bound, C, items[cur]);
-        if ((e = hipGetLastError()) != hipSuccess)
-            break;
+        if (!fuse) {
+            const uint32_t cgrid = nblk(nchunks, 4);
+            k_agglo_compact<<<cgrid < kCompactGrid ? cgrid : kCompactGrid, 256, 0, s>>>(
+                stage, counts, offsets, in_count, bound, C, items[cur]);
+            if ((e = hipGetLastError()) != hipSuccess)
+                break;
+        }
         in_count = next_count;
         const uint64_t b = (uint64_t)nchunks * kAggOut;
         bound = b < bound ? (uint32_t)b : bound;
