@@ -351,16 +351,34 @@ def run_tracked(args, log):
 
     cd.cd_profile_read(reset=True)
     cd.cd_profile_enable(True)
+    # events on the caller's stream around every step, for the median
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for e0, e1 in evs:
+        e0.record()
         pairs = bp.run(el)
+        e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     cd.cd_profile_enable(False)
     stages = cd.cd_profile_read(reset=True)
     P = int(len(pairs))
     ms_step = wall * 1000.0 / args.steps
+    ms_events = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
+    ms_median = ms_events[len(ms_events) // 2] if len(ms_events) % 2 else \
+        0.5 * (ms_events[len(ms_events) // 2 - 1] + ms_events[len(ms_events) // 2])
+    # transfers outside the timed region: the catalog in, the pair list out
+    torch.cuda.synchronize()
+    t_h = time.perf_counter()
+    el_copy = cd.soa(sc.elements)
+    torch.cuda.synchronize()
+    h2d_ms = (time.perf_counter() - t_h) * 1000.0
+    t_h = time.perf_counter()
+    pairs_host = pairs.cpu()
+    d2h_ms = (time.perf_counter() - t_h) * 1000.0
+    del el_copy, pairs_host
     if args.dt == "fixed":
         K = N // sc.n
         tests = K * sc.n * (sc.n - 1) // 2
@@ -384,6 +402,9 @@ def run_tracked(args, log):
                       "box_precision": args.boxes, "tree_precision": args.precision,
                       "box_rule": args.box, "brute_force_tests": tests},
            "pairs": P, "planted_recall": recall,
+           "ms_per_step_median_events": round(ms_median, 4),
+           "transfers_ms": {"catalog_h2d": round(h2d_ms, 3), "pairs_d2h": round(d2h_ms, 3),
+                            "note": "outside the timed region; pageable host memory"},
            "stages_ms": {k: round(v[0] / v[1], 4) for k, v in stages.items()},
            "roofline": _roofline(stages, N, sc.n, P, prec, box_prec, args.precision, args.dt,
                                  ms_step, args.copy,
@@ -761,7 +782,7 @@ def run_bands(args, log):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["fp64", "fp32"], default="fp64",
                     help="tree precision (boxes stay FP64 unless --boxes fp32)")

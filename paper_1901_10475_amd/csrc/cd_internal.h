@@ -157,6 +157,16 @@ __device__ inline uint64_t lanemask_lt()
     return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+// LDS written by some lanes of a wave and then read by others: the wave
+// executes its LDS operations in order, so only the compiler must keep them
+// in order (a fence at wavefront scope).
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Exclusive scan over all threads of a block (blockDim multiple of 64, <= 1024).
 // `wsum` is LDS scratch of blockDim/64 entries.  Returns the exclusive prefix;
 // *total gets the block sum.

@@ -248,16 +248,6 @@ __device__ inline void object_run(const ObjConst &c, const ObjSinus *os, uint32_
     object_steps<RULE>(c, os, i, k0, k1, K, dt, T, tick_s, half_thr, sink);
 }
 
-// LDS written by some lanes of a wave and then read by others: the wave
-// executes its LDS operations in order, so only the compiler must keep them
-// in order (a fence at wavefront scope).
-__device__ inline void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Box records (FP64): each wave's 64 records of one interval (consecutive
 // slots, 4 KB) are staged in the wave's own LDS area and written back so
 // that each store instruction covers 1 KB of whole lines (non-temporal); the

@@ -715,7 +715,13 @@ __device__ inline bool rec_eq(const Rec &a, const Rec &b)
     return a.i == b.i && a.j == b.j && a.tlo == b.tlo && a.thi == b.thi;
 }
 
-// Bitonic sort of r[0..n2) (n2 a power of two) by the whole workgroup.
+// Bitonic sort of r[0..n2) (n2 a power of two) by the whole workgroup
+// (blockDim a multiple of 64).  Pair t compares records a and a + stride,
+// a = (t / stride) 2 stride + t % stride; for stride <= 64 the pairs of a
+// wave (t and t + blockDim.x for its 64 lanes) stay inside that wave's own
+// 128-record segments, so between two such stages a wave-level sync is
+// enough; a stage reaching farther, or the one before it, waits for the whole
+// workgroup.
 __device__ inline void lds_bitonic(Rec *r, uint32_t n2)
 {
     for (uint32_t size = 2; size <= n2; size <<= 1) {
@@ -730,9 +736,14 @@ __device__ inline void lds_bitonic(Rec *r, uint32_t n2)
                     r[b] = x;
                 }
             }
-            __syncthreads();
+            const uint32_t next = stride > 1 ? stride >> 1 : (size < n2 ? size : 0u);
+            if (stride > 64 || next > 64)
+                __syncthreads();
+            else
+                wave_lds_sync();
         }
     }
+    __syncthreads();
 }
 
 // Records [0, count) into LDS, padded to a power of two with records that
