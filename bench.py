@@ -53,15 +53,15 @@ BOX_SUFFIX = {"speed": "", "nu": "_box_interval_nu", "ecc": "_box_interval_ecc"}
 
 TRAFFIC = {
     # k_agglo_leaves + 4 item passes with their scans and compactions
-    ("hierarchy", "fp64", "fixed"): {"fetch_kib": 2014011.2 + 57395.5 + 10095.2 + 154.1,
-                                     "write_kib": 4469493.0 + 75732.2 + 13266.6 + 234.9,
+    ("hierarchy", "fp64", "fixed"): {"fetch_kib": 2014022.5 + 57393.9 + 10095.1 + 154.1,
+                                     "write_kib": 4469486.2 + 75680.6 + 13266.6 + 234.9,
                                      "sources": {"paper_1901_10475_amd/csrc/k_agglo.hip":
                                                  "d4c20c009293ecd4b2b467e90068f670e3196348"}},
     # k_block_codes + k_block_sort + k_boxes_uniform (records)
-    ("boxes", "fp64", "fixed"): {"fetch_kib": 3205.5 + 38902.9 + 41182.7,
-                                 "write_kib": 29615.6 + 109782.1 + 4113594.3,
+    ("boxes", "fp64", "fixed"): {"fetch_kib": 3205.4 + 38912.1 + 43053.7,
+                                 "write_kib": 29615.6 + 109787.3 + 4113878.6,
                                  "sources": {"paper_1901_10475_amd/csrc/k_boxes.hip":
-                                             "5a3399e58189a37d740143870da7abded4d8d86c",
+                                             "bf37f93ed5022344fdde388ad03e5b9b7779cc91",
                                              "paper_1901_10475_amd/csrc/k_sort.hip":
                                              "5499fda60e277c01f68b81b459b0f3d964c6a85b"}},
 }

@@ -37,9 +37,13 @@ largest scale when r_i = 0 and v_i = 0), and the target is log2 of the step
 s_i* dt_i(1), in seconds.
 
 The default node_weight is the measured cost of one executed traversal test
-over that of one box (boxes, codes, sort, hierarchy and unions) on the
-16 848-object hour at 1 s steps: 0.53 ms for the traversal's 11.78 M tests
-(45 ps each) against 4.38 ms for 60.65 M boxes (72 ps each).
+over that of one box (boxes, keys, sort, hierarchy and unions) on the path
+the network serves -- FP32 boxes and tree with per-object steps, here the
+16 848-object hour with learned steps and the eccentric-anomaly box: 1.89 ms
+for 7.87 M boxes (240 ps each) against 1.01 ms for the traversal's 38.9 M
+tests (26 ps each).  (On the uniform-step FP64 path a box is cheaper, 72 ps
+against 45 ps per test; that ratio, 0.6, trains steps that make the learned
+queries slower.)
 
 Everything numeric runs in the library's kernels (features, forward, backward,
 Adam, record counts, the broad phase); this module sequences the calls and
@@ -57,7 +61,7 @@ from . import (CD_FP32, CD_FP64, BroadPhase, _bytes, _check, _ptr, _stream, cd_c
 CD_MLP_PARAMS = 4609
 DEFAULT_SCALES = (0.25, 0.5, 1.0, 2.0, 4.0, 8.0, 16.0, 32.0, 64.0)
 PAIR_WEIGHT = 32.0
-NODE_WEIGHT = 0.6
+NODE_WEIGHT = 0.1
 
 
 # ---- marshalled C calls --------------------------------------------------------------
