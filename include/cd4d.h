@@ -374,6 +374,11 @@ typedef struct {
  * change nothing. */
 int cd_set_tuning(const cd_tuning *t);
 int cd_get_tuning(cd_tuning *t);
+/* Node-pair levels the calling thread's last cd_query_pairs ran until its
+ * queue was empty (0 when that query used the per-leaf walk, or none ran):
+ * on the same tree, a max_levels with which cd_query_pairs_async needs no
+ * walk. */
+int cd_last_query_levels(void);
 
 /* ---- executed-work counters (diagnostic build) --------------------------- */
 

@@ -176,6 +176,7 @@ def _load(path):
                                            _vp]),
             "cd_pair_object_counts": (ctypes.c_int, [_vp, i64, i64, _vp, _vp]),
             "cd_counters_available": (ctypes.c_int, []),
+            "cd_last_query_levels": (ctypes.c_int, []),
             "cd_counters_reset": (ctypes.c_int, [_vp, i64, _vp]),
             "cd_counters_read": (ctypes.c_int, [P(cd_counters), _vp]),
         }
@@ -202,7 +203,7 @@ EXPORTED = ("cd_status_string", "cd_last_error", "cd_version", "cd_stream_copy",
             "cd_canonical_records_ws", "cd_canonical_records", "cd_mlp_features",
             "cd_dt_mlp", "cd_mlp_forward", "cd_mlp_grad_ws", "cd_mlp_grad", "cd_mlp_adam",
             "cd_pair_object_counts", "cd_counters_available", "cd_counters_reset",
-            "cd_counters_read")
+            "cd_counters_read", "cd_last_query_levels")
 
 
 def cd_counters_available():
@@ -472,6 +473,10 @@ def cd_set_tuning(t=None):
         return
     v = cd_tuning(*(int(t.get(k, 0)) for k, _ in cd_tuning._fields_))
     _check(lib().cd_set_tuning(ctypes.byref(v)))
+
+
+def cd_last_query_levels():
+    return int(lib().cd_last_query_levels())
 
 
 def cd_get_tuning():

@@ -21,7 +21,10 @@ place; other precisions use box arrays.  Output
 capacities come from one eager pass (``calibrate``); a replay whose status
 reports exceeded capacity is repeated eagerly for that scenario by
 ``results``.  Launch shapes can differ per
-scenario (``tunings``): they are read while the graph is recorded.
+scenario (``tunings``): they are read while the graph is recorded.  A
+scenario's replays launch the node-pair levels its eager query needed plus
+two (``cd_last_query_levels``) instead of the default 96; a replay whose
+inputs need more finishes with the per-leaf walk.
 """
 import ctypes
 import math
@@ -31,8 +34,8 @@ import torch
 
 from . import (CD_E_CAPACITY, CD_FP64, CD_LAYOUT_SORTED, CD_OK, CD_SORTED_MAX_RECORDS, Boxes, Graph,
                _bytes, _check, _ptr, _stream, cd_boxes, cd_build_boxes, cd_get_tuning,
-               cd_query_pairs, cd_query_pairs_async, cd_set_tuning, cd_tree, lib, params_struct,
-               soa)
+               cd_last_query_levels, cd_query_pairs, cd_query_pairs_async, cd_set_tuning,
+               cd_tree, lib, params_struct, soa)
 
 
 class _Boxes:
@@ -143,6 +146,9 @@ class BatchRunner:
         self.stream = torch.cuda.Stream(device=device)
         self.branch_streams = [torch.cuda.Stream(device=device) for _ in range(B)]
         self.tunings = [None] * S
+        # node-pair levels each scenario's eager query needed (+2): the
+        # replays launch that many instead of the default
+        self.levels = [0] * S
 
     def box_arrays(self, k):
         """(lo [3,N], hi [3,N], t0, t1, obj) of scenario k's boxes as last built
@@ -209,12 +215,15 @@ class BatchRunner:
         return chosen
 
     def calibrate(self):
-        """One eager pass: sets every scenario's output capacity."""
+        """One eager pass: sets every scenario's output capacity and the
+        node-pair levels its replays launch."""
         with torch.cuda.stream(self.stream):
             for k in range(len(self.sc)):
                 self._apply_tuning(k)
                 P = int(self.run_eager(k).shape[0])
                 self.capacity[k] = max(self.min_capacity, int(math.ceil(P * self.margin)))
+                lv = cd_last_query_levels()
+                self.levels[k] = min(400, lv + 2) if lv > 0 else 0
         self.stream.synchronize()
         self._alloc_outputs()
 
@@ -227,7 +236,10 @@ class BatchRunner:
             for m in self.members]
 
     def _apply_tuning(self, k):
-        cd_set_tuning(self.tunings[k])
+        t = dict(self.tunings[k]) if self.tunings[k] else {}
+        if self.levels[k]:
+            t["max_levels"] = self.levels[k]
+        cd_set_tuning(t or None)
 
     # -- the batch as one graph -------------------------------------------------------
     def enqueue_branch(self, b):

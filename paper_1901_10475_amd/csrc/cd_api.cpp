@@ -178,6 +178,9 @@ constexpr int kCtlWords = kCtlStatus + 4;
 // Node-pair levels the last drained traversal needed: the next synchronous
 // query launches that many before its first count check.
 std::atomic<int> g_expand_levels{kExpandBatch};
+// Node-pair levels the calling thread's last synchronous query needed to
+// drain its queue (0: the per-leaf walk ran, or no query yet).
+thread_local int g_last_levels = 0;
 
 int check_params(const cd_params *p)
 {
@@ -911,9 +914,8 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
     {
         Stage st("refit", s);
         CD_HIP(launch_refit(bv, boxes->precision, precision, (uint32_t)N, leaf_src, presorted,
-                            0u, w, tw.parent,
-                            kids, links, tw.clev, tw.arrive, tw.list_items, tw.list_count,
-                            nodes, sink, err, s));
+                            tw.parent, kids, links, tw.clev, tw.arrive, tw.list_items,
+                            tw.list_count, nodes, sink, err, s));
     }
     return debug_sync((hipStream_t)stream, "cd_build_tree", (const unsigned int *)tree->mem);
 }
@@ -957,6 +959,8 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
     const uint2 *kids =
         (const uint2 *)((const char *)tree->mem + tree_kids_offset((uint64_t)N, tree->precision));
     const cd_tuning tu = tuning();
+    unsigned int stw[3];        // record count low/high, tree error
+    bool status_read = false;   // stw already read with the last control block
     {
         Stage st("traverse", s);
         // node-pair traversal from the refit's overlapping sibling pairs; a
@@ -965,6 +969,8 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
         // the control block per batch of levels
         bool walk = true;
         const unsigned int *run_walk = nullptr;
+        status_read = false;
+        g_last_levels = 0;
         if (N > 1 && tu.mode == 2) {
             // every level in one launch; the walk decided on the device
             CD_HIP(launch_fill_u32(w.qcount, 0u, kCtlWords, s));
@@ -984,7 +990,9 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
             const uint2 *in = seeds;
             const unsigned int *n_in = &hdr->nseeds;
             uint32_t in_cap = (uint32_t)seed_cap((uint64_t)N);
-            unsigned int ctl[kCtlFlags + 1];
+            // the control block with the status copy behind it: a drained
+            // traversal needs no second read
+            unsigned int ctl[kCtlWords];
             int lev = 0;
             int batch = g_expand_levels.load(std::memory_order_relaxed);
             batch = batch < 1 ? 1 : (batch > kExpandMaxLevels ? kExpandMaxLevels : batch);
@@ -1001,6 +1009,7 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
                     n_in = w.qcount + lev + 1;
                     in_cap = w.qcap;
                 }
+                CD_HIP(launch_query_status(w.counter, err, w.qcount + kCtlStatus, s));
                 CD_HIP(hipMemcpyAsync(ctl, w.qcount, sizeof ctl, hipMemcpyDeviceToHost, s));
                 CD_HIP(hipStreamSynchronize(s));
                 qf = ctl[kCtlFlags];
@@ -1018,6 +1027,10 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
                     if (ctl[l])
                         last = l;
                 g_expand_levels.store(last + 2, std::memory_order_relaxed);
+                g_last_levels = last + 1;
+                for (int k = 0; k < 3; ++k)
+                    stw[k] = ctl[kCtlStatus + k];
+                status_read = true;
             }
         }
         if (walk) {
@@ -1030,10 +1043,11 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
                                    tu.walk_threads, side_on, side, s));
         }
     }
-    unsigned int stw[3];
-    CD_HIP(launch_query_status(w.counter, err, w.qcount + kCtlStatus, s));
-    CD_HIP(hipMemcpyAsync(stw, w.qcount + kCtlStatus, sizeof stw, hipMemcpyDeviceToHost, s));
-    CD_HIP(hipStreamSynchronize(s));
+    if (!status_read) {
+        CD_HIP(launch_query_status(w.counter, err, w.qcount + kCtlStatus, s));
+        CD_HIP(hipMemcpyAsync(stw, w.qcount + kCtlStatus, sizeof stw, hipMemcpyDeviceToHost, s));
+        CD_HIP(hipStreamSynchronize(s));
+    }
     unsigned long long cnt = (unsigned long long)stw[0] | ((unsigned long long)stw[1] << 32);
     unsigned int e = stw[2];
     if (e)
@@ -1154,6 +1168,8 @@ int cd_query_pairs_async(const cd_tree *tree, cd_pair *out, int64_t capacity,
     }
     return debug_sync((hipStream_t)stream, "cd_query_pairs_async", nullptr, status_dev);
 }
+
+int cd_last_query_levels(void) { return g_last_levels; }
 
 int cd_counters_available(void)
 {

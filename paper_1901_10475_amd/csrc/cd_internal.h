@@ -50,21 +50,11 @@ static_assert(sizeof(Node64) == 64, "Node64 layout");
 // Where the Karras pass leaves each node's (link, esc) for the refit: the
 // FP32 tree's own link records, or, for an FP64 tree (whose records get both
 // words from the refit, the link being the left child), the escapes alone.
-// When an FP64 tree's leaf records were written in place by the box build,
-// leaf escapes go straight into those records' escape words (leaf_esc, one
-// every leaf_stride words from leaf first_leaf on).
 struct LinkSink {
     Link *rec;       // FP32 tree link records, or nullptr
     uint32_t *esc;   // escapes only, when rec == nullptr
-    uint32_t *leaf_esc = nullptr;
-    uint32_t first_leaf = 0;
-    uint32_t leaf_stride = 1;
     __device__ void put(uint32_t id, uint32_t link, uint32_t e) const
     {
-        if (leaf_esc && id >= first_leaf) {
-            leaf_esc[(size_t)(id - first_leaf) * leaf_stride] = e;
-            return;
-        }
         if (rec) {
             Link l;
             l.link = link;
@@ -74,12 +64,7 @@ struct LinkSink {
             esc[id] = e;
         }
     }
-    __device__ uint32_t esc_of(uint32_t id) const
-    {
-        if (leaf_esc && id >= first_leaf)
-            return leaf_esc[(size_t)(id - first_leaf) * leaf_stride];
-        return rec ? rec[id].esc : esc[id];
-    }
+    __device__ uint32_t esc_of(uint32_t id) const { return rec ? rec[id].esc : esc[id]; }
 };
 
 static_assert(sizeof(Box32) == 32, "Box32 layout");
@@ -572,8 +557,8 @@ hipError_t launch_agglo(const uint32_t *code, uint32_t slab_size, uint32_t slab_
                         const SeedSink &seeds, unsigned int *err, hipStream_t s);
 // idx == nullptr: the leaf records are already written (slab build).
 hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision, uint32_t N,
-                        const uint32_t *idx, bool sorted_boxes,
-                        uint32_t check_m, uint32_t check_ticks, const uint32_t *parent, const uint2 *kids,
+                        const uint32_t *idx, bool sorted_boxes, const uint32_t *parent,
+                        const uint2 *kids,
                         const LinkSink &links, const uint8_t *clev, unsigned int *arrive,
                         uint32_t *list_items, uint32_t *list_count, void *tree,
                         const SeedSink &seeds, unsigned int *err, hipStream_t s);

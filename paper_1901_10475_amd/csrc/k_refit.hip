@@ -34,7 +34,7 @@ static inline unsigned nblk(uint64_t n, unsigned t) { return (unsigned)((n + t -
 template <int BP, int TP>
 __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
     BoxView b, uint32_t N, const uint32_t *__restrict__ idx, bool sorted_boxes,
-    uint32_t check_m, uint32_t check_ticks, const uint32_t *__restrict__ parent,
+    const uint32_t *__restrict__ parent,
     const uint2 *__restrict__ kids, LinkSink links, const uint8_t *clev,
     void *tree, RefitLists L, SeedSink seeds, unsigned int *err)
 {
@@ -83,14 +83,10 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
         NodeIO<TP>::put(tree, N, leaf, lo, hi, t0, t1, b.obj[src], links.esc_of(leaf));
         par_leaf[t] = parent[leaf];
     } else if (t < m) {
-        // leaf records already written in sorted order by the slab build, or
-        // in place by the box build (check_m > 0: every leaf must lie in its
-        // slab of check_m leaves, check_ticks ticks)
+        // leaf records already written in sorted order by the slab build
         uint32_t leaf = N - 1 + c0 + t;
         NodeIO<TP>::get_box(tree, N, leaf, lo, hi, t0, t1);
         par_leaf[t] = parent[leaf];
-        if (check_m && t0 / check_ticks != (c0 + t) / check_m)
-            atomicOr(err, 1u);
     }
     if (c0 + t + 1 < N) {  // inner node c0 + t exists
         kid[t] = kids[c0 + t];
@@ -407,8 +403,8 @@ size_t refit_list_slots(uint32_t N, uint32_t *base)
 }
 
 hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision, uint32_t N,
-                        const uint32_t *idx, bool sorted_boxes, uint32_t check_m,
-                        uint32_t check_ticks, const uint32_t *parent, const uint2 *kids,
+                        const uint32_t *idx, bool sorted_boxes, const uint32_t *parent,
+                        const uint2 *kids,
                         const LinkSink &links, const uint8_t *clev, unsigned int *arrive,
                         uint32_t *list_items, uint32_t *list_count, void *tree,
                         const SeedSink &seeds, unsigned int *err, hipStream_t s)
@@ -431,15 +427,15 @@ hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision,
     uint32_t nchunks = nblk(N, kRefitChunk);
     if (box_precision == CD_FP64 && tree_precision == CD_FP64)
         k_refit_chunks<CD_FP64, CD_FP64><<<nchunks, kRefitChunk, 0, s>>>(
-            b, N, idx, sorted_boxes, check_m, check_ticks, parent, kids, links, clev, tree, L,
+            b, N, idx, sorted_boxes, parent, kids, links, clev, tree, L,
             seeds, err);
     else if (box_precision == CD_FP64)
         k_refit_chunks<CD_FP64, CD_FP32><<<nchunks, kRefitChunk, 0, s>>>(
-            b, N, idx, sorted_boxes, check_m, check_ticks, parent, kids, links, clev, tree, L,
+            b, N, idx, sorted_boxes, parent, kids, links, clev, tree, L,
             seeds, err);
     else
         k_refit_chunks<CD_FP32, CD_FP32><<<nchunks, kRefitChunk, 0, s>>>(
-            b, N, idx, sorted_boxes, check_m, check_ticks, parent, kids, links, clev, tree, L,
+            b, N, idx, sorted_boxes, parent, kids, links, clev, tree, L,
             seeds, err);
     e = hipGetLastError();
     for (uint32_t k = 1; k <= levels && e == hipSuccess; ++k) {

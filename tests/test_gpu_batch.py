@@ -95,6 +95,31 @@ def test_one_launch_traversal_equals_levels(name, sc, heur):
         cd.cd_set_tuning(None)
 
 
+def test_last_query_levels_bound_the_async_levels():
+    """cd_last_query_levels after a synchronising query is the number of
+    node-pair levels the device-count query needs on that tree: with that
+    many it never falls back to the per-leaf walk, with one fewer it does
+    (counted by the counters build); the records are the same either way."""
+    need_gpu()
+    sc = catalog.scaled(catalog.tracked_hour(), n=3000, horizon_ticks=120_000)
+    el = cd.soa(sc.elements)
+    p = cd.params_struct(sc.tick_s, sc.mu, sc.threshold_km, sc.horizon_ticks, sc.dt_ticks)
+    bp = cd.BroadPhase(sc.n, p)
+    ref = bp.run(el).cpu().numpy()
+    P = len(ref)
+    with cd.counters_build():
+        bp.query()
+        lv = cd.cd_last_query_levels()
+        say("levels", lv, "records", P)
+        assert 1 < lv <= 400
+        for levels, walks in ((lv, False), (lv + 3, False), (lv - 1, True)):
+            cd.cd_counters_reset(None)
+            got, c, s = _async(bp, P, {"max_levels": levels})
+            cnt = cd.cd_counters_read()
+            assert s == 0 and np.array_equal(got, ref), levels
+            assert (cnt["walk_steps"] > 0) == walks, (levels, cnt)
+
+
 def test_async_query_single_and_empty_trees():
     need_gpu()
     lo = np.zeros((1, 3))
