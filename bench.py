@@ -476,10 +476,12 @@ def north_star_forms(args, log, sc, el, base):
     number of timed steps, planted recall and colliding object pairs.  Each
     network is trained first (step sweeps of two other catalogs of the same
     recipe, outside the timed region); its BF16 inference runs inside every
-    timed step."""
+    timed step.  The traversal's launch shapes for each form come from the
+    autotuner (the 256-lane default suits the FP64 line; the FP32 per-object
+    trees run faster with 512), searched outside the timed region."""
     import torch
     import paper_1901_10475_amd as cd
-    from paper_1901_10475_amd import catalog
+    from paper_1901_10475_amd import autotune, catalog
     from paper_1901_10475_amd import learned_dt as ld
     out = {"fp64_dt1s_speed_box": base}
     for rule_name in ("ecc", "speed"):
@@ -492,19 +494,27 @@ def north_star_forms(args, log, sc, el, base):
                              box_rule=rule)
         bp = cd.BroadPhase(sc.n, p, None, cd.CD_FP32, cd.CD_FP32, dt_mlp=(net.w_bf16, 5.0),
                            el_soa=el)
-        for _ in range(args.warmup):
-            pairs = bp.run(el)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            pairs = bp.run(el)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+        bp.run(el)
+        # the traversal's launch shapes from the autotuner (cached per GPU
+        # architecture and box-count bucket; outside the timed region)
+        shapes, cached = autotune.tuned(bp.query, cd.CD_FP32, bp.count, f"mlp_{rule_name}")
+        cd.cd_set_tuning(shapes)
+        try:
+            for _ in range(args.warmup):
+                pairs = bp.run(el)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                pairs = bp.run(el)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1000.0 / args.steps
+        finally:
+            cd.cd_set_tuning(None)
         form = {"ms_per_query": round(ms, 4), "boxes": int(bp.count),
                 "records": int(pairs.shape[0]), "planted_recall": planted_recall(sc, pairs),
                 "colliding_object_pairs": colliding_object_pairs(cd, el, p, pairs),
                 "speedup_vs_fp64_dt1s": round(base["ms_per_query"] / ms, 3),
-                "training_s": round(t_train, 1)}
+                "training_s": round(t_train, 1), "launch_shapes": shapes}
         log(f"[bench] learned steps, FP32, {rule_name} box: {ms:.3f} ms/query, "
             f"{form['boxes']} boxes, {form['records']} records, recall "
             f"{form['planted_recall']}, {form['colliding_object_pairs']} colliding pairs")
