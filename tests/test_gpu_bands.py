@@ -96,11 +96,11 @@ def test_gather_remap_canonical():
 
 
 @pytest.mark.parametrize("count", [1, 2, 3, 1000, 4095, 4096, 4097, 20000, 65536, 65537,
-                                   100000])
+                                   100000, 262144, 262145, 400000])
 def test_canonical_records_small_medium_and_radix_paths(count):
-    """Up to 4096 records take the one-workgroup LDS sort, up to 65536 the
-    LDS tiles merged pairwise, more the radix path: all give numpy's sorted
-    unique rows."""
+    """Up to 4096 records take the one-workgroup LDS sort, up to 262144
+    the LDS tiles merged pairwise, more the radix path: all give numpy's
+    sorted unique rows."""
     need_gpu()
     rng = np.random.default_rng(45 + count)
     rec = np.stack([rng.integers(0, 300, count), rng.integers(0, 300, count),
