@@ -273,10 +273,13 @@ int cd_build_boxes(const cd_elements *el, const uint32_t *dt_ticks, const cd_par
 /* Builds an LBVH over the boxes (the AABB tree of Sec. 3.2, built in bulk):
  * each box gets a time-major key [t0 / slab_ticks | 30-bit Morton code of its
  * centre]; keys are radix-sorted (inside one workgroup's LDS per slab when
- * the slab hint is set, device-wide otherwise); a Karras hierarchy is built
- * over the sorted keys and every inner box is set to the exact union of its
- * children by an atomic bottom-up pass, so an inner node overlaps whatever
- * its leaves overlap.  precision CD_FP32 is allowed for FP64 boxes (outward
+ * the slab hint is set, device-wide otherwise); the binary radix (Karras)
+ * hierarchy over the sorted keys has every inner box equal to the exact union
+ * of its children, so an inner node overlaps whatever its leaves overlap.  It
+ * is formed top-down with an atomic refit for slab-hinted box arrays, and
+ * from the leaves up in one pass (hierarchy and unions together) for box
+ * records in place and for box sets without a slab hint (after the
+ * device-wide key sort).  precision CD_FP32 is allowed for FP64 boxes (outward
  * rounding at the leaves).  slab_ticks = 0 takes boxes->slab_ticks if set,
  * else horizon / 64 (at least 1).  Box records in the tree's own leaf-record
  * area (cd_boxes.records) are used in place.

@@ -888,6 +888,8 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
         else
             CD_HIP(launch_karras(tw.keys, (uint32_t)N, kids, links, tw.parent, tw.clev, false, s));
     } else {
+        // per-object steps and other unsorted box sets: one key sort, then
+        // the bottom-up pass reads the boxes through the sorted items
         {
             Stage st("keys", s);
             if (!bv.code)
@@ -895,6 +897,7 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
             CD_HIP(launch_keys(bv, boxes->precision, (uint32_t)N, w, max_slab, 0, tw.bounds,
                                nullptr, tw.kva, err, s));
         }
+        void *res = nullptr;
         {
             Stage st("sort", s);
             DigitPlan plan;
@@ -904,12 +907,17 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
             int sb = bits_for(max_slab);
             for (int sh = 0; sh < sb; sh += 8)
                 plan.shift[plan.npass++] = (uint8_t)(32 + sh);
-            void *res = nullptr;
             CD_HIP(radix_sort16(SORT_KV, tw.kva, tw.kvb, (size_t)N, plan, tw.radix, &res, s));
-            CD_HIP(launch_unpack_kv((const KV *)res, (uint32_t)N, tw.keys, tw.idx, s));
         }
-        Stage st("karras", s);
-        CD_HIP(launch_karras(tw.keys, (uint32_t)N, kids, links, tw.parent, tw.clev, true, s));
+        uint32_t *side = nullptr;
+        if (precision == CD_FP64) {
+            side = (uint32_t *)((char *)tree->mem + tree_leaf_esc_offset((uint64_t)N, precision));
+            CD_HIP(launch_fill_u32(&((TreeHeader *)tree->mem)->leaf_esc_side, 1u, 1, s));
+        }
+        Stage st("hierarchy", s);
+        CD_HIP(launch_agglo_gather((const KV *)res, bv, boxes->precision, precision, (uint32_t)N,
+                                   nodes, kids, side, tw.agglo, sink, err, s));
+        return debug_sync((hipStream_t)stream, "cd_build_tree", (const unsigned int *)tree->mem);
     }
     {
         Stage st("refit", s);

@@ -432,16 +432,16 @@ struct TreeHeader {
     uint32_t err;            // bit 0: slab hint / horizon violated, 1: refit, 2: traversal
     uint32_t nseeds;         // overlapping sibling pairs found by the refit
     uint32_t seed_overflow;  // set when more than seed_cap(N) pairs were found
-    uint32_t leaf_esc_side;  // FP64: leaf skip links in the side array (records in place)
+    uint32_t leaf_esc_side;  // FP64: leaf skip links in the side array (bottom-up build)
     uint32_t pad[60];
 };
 static_assert(sizeof(TreeHeader) == 256, "TreeHeader layout");
 inline size_t seed_cap(uint64_t N) { return (size_t)(N / 4 + 4096); }
 // Tree buffer layout: header | nodes (FP64: 64-byte records; FP32: 32-byte
 // boxes, then 8-byte links) | kids[N - 1] (both children of each inner node)
-// | seeds[seed_cap(N)] | FP64 only: leaf skip links[N] (used when the leaf
-// records were written in place by the box build, whose code words they
-// would otherwise overwrite).
+// | seeds[seed_cap(N)] | FP64 only: leaf skip links[N] (used by the bottom-up
+// build: leaf records written in place by the box build keep their code
+// words where the skip link would go).
 inline size_t tree_kids_offset(uint64_t N, int precision)
 {
     return sizeof(TreeHeader) + (size_t)(2 * N - 1) *
@@ -555,6 +555,15 @@ size_t agglo_ws_bytes(uint32_t N);
 hipError_t launch_agglo(const uint32_t *code, uint32_t slab_size, uint32_t slab_ticks,
                         uint32_t N, void *nodes, uint2 *kids, uint32_t *leaf_esc, void *ws,
                         const SeedSink &seeds, unsigned int *err, hipStream_t s);
+// The same pass over leaves taken from the general key sort: kv holds the N
+// (key, box index) items in key order; pass 1 writes each leaf's record from
+// box kv[j].val (outward-rounded for an FP32 tree) and takes the keys from
+// kv.  FP64 trees (FP64 boxes) put the leaf skip links in leaf_esc; FP32 trees
+// in their link records (leaf_esc unused).  Key order is checked (error bit 1).
+hipError_t launch_agglo_gather(const KV *kv, const BoxView &bv, int box_precision,
+                               int tree_precision, uint32_t N, void *nodes, uint2 *kids,
+                               uint32_t *leaf_esc, void *ws, const SeedSink &seeds,
+                               unsigned int *err, hipStream_t s);
 // idx == nullptr: the leaf records are already written (slab build).
 hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision, uint32_t N,
                         const uint32_t *idx, bool sorted_boxes, const uint32_t *parent,

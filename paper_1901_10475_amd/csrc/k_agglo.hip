@@ -34,6 +34,16 @@
 // counts of later passes stay on the device: each later pass is launched for
 // a bound on its count, as a small grid that strides over the chunks holding
 // items.
+//
+// Leaves come either in place (FP64 records the sorted-layout box build wrote
+// in key order; keys from the slab of each position and the packed codes) or
+// from the general key sort (per-object steps): pass 1 then reads each leaf's
+// box through the sorted (key, box index) items, writes its leaf record and
+// takes the keys from the same items.  An FP32 tree holds the outward-rounded
+// boxes; its nodes are formed from those rounded values (held as doubles,
+// exactly), so unions and sibling tests equal what its float records give.
+#include <type_traits>
+
 #include "cd_internal.h"
 
 namespace cd {
@@ -53,11 +63,17 @@ struct AggItem {
 };
 static_assert(sizeof(AggItem) == 16, "AggItem layout");
 
-__device__ inline void load_record(const Node64 *nodes, uint32_t id, double lo[3], double hi[3],
-                                   uint32_t &t0, uint32_t &t1)
-{
-    NodeIO<CD_FP64>::get_box(nodes, 0, id, lo, hi, t0, t1);
-}
+// Keys of the general path: the key sort's output, (slab << 32 | code, box).
+struct KVKeys {
+    const KV *kv;
+    uint32_t N;
+    __device__ uint64_t key(uint32_t j) const { return kv[j].key; }
+};
+
+// Pass 1's leaf source.  GATHER < 0: FP64 leaf records in place, CodeKeys;
+// otherwise boxes of precision GATHER read through KVKeys.
+template <int GATHER>
+using LeafKeys = typename std::conditional<(GATHER >= 0), KVKeys, CodeKeys>::type;
 
 // The node at one item position in LDS: four 16-byte words laid out as an
 // FP64 tree record's (lo0 lo1 | lo2 hi0 | hi1 hi2 | t0 t1 other packed): its
@@ -154,23 +170,39 @@ struct AggShared {
 // sparse top of the chunk's tree costs one wave rather than every wave.
 // Roots go to out[chunk][0 .. kAggOut) in position order, their count to
 // out_count[chunk].
-template <int C, bool LEAVES>
-__device__ void agglo_chunk(AggShared<C, LEAVES> &S, uint32_t chunk, uint32_t M, CodeKeys G,
-                            uint32_t slab_ticks, const AggItem *__restrict__ in,
-                            Node64 *__restrict__ nodes, uint2 *__restrict__ kids,
-                            uint32_t *__restrict__ leaf_esc, AggItem *__restrict__ out,
-                            uint32_t *__restrict__ out_count, const SeedSink &seeds,
-                            bool &bad, bool &misplaced)
+// TP: tree precision (FP32 only with GATHER >= 0).  The leaf skip links go to
+// leaf_esc (FP64 trees) or into the FP32 tree's link records.
+template <int C, bool LEAVES, int TP, int GATHER>
+__device__ void agglo_chunk(AggShared<C, LEAVES> &S, uint32_t chunk, uint32_t M,
+                            LeafKeys<GATHER> G, const BoxView &bv, uint32_t slab_ticks,
+                            const AggItem *__restrict__ in, void *__restrict__ nodes,
+                            uint2 *__restrict__ kids, uint32_t *__restrict__ leaf_esc,
+                            AggItem *__restrict__ out, uint32_t *__restrict__ out_count,
+                            const SeedSink &seeds, bool &bad, bool &misplaced)
 {
+    static_assert(TP == CD_FP64 || GATHER >= 0, "FP32 trees take their leaves by gather");
     const SeedStage stage{S.sbuf, &S.sn};
     const uint32_t N = G.N, t = threadIdx.x, C0 = chunk * (uint32_t)C;
     const uint32_t m = M - C0 < (uint32_t)C ? M - C0 : (uint32_t)C;
     const uint32_t wlo = C0 - 2;   // LDS window: items C0 - 2 .. C0 + m
     double lo[3], hi[3];
-    uint32_t t0 = 0, t1 = 0;
-    if (LEAVES && t < m) {   // the leaf record's box, in flight with the codes
-        load_record(nodes, N - 1 + C0 + t, lo, hi, t0, t1);
-        misplaced |= t0 / slab_ticks != (C0 + t) / G.ms;
+    uint32_t t0 = 0, t1 = 0, lobj = 0;
+    if (LEAVES && t < m) {   // the leaf's box, in flight with the keys
+        if constexpr (GATHER >= 0) {
+            const uint32_t src = G.kv[C0 + t].val;
+            load_box<(GATHER >= 0 ? GATHER : CD_FP64)>(bv, src, lo, hi);
+            if (TP == CD_FP32)
+                for (int d = 0; d < 3; ++d) {
+                    lo[d] = (double)__double2float_rd(lo[d]);
+                    hi[d] = (double)__double2float_ru(hi[d]);
+                }
+            t0 = bv.t0[src];
+            t1 = bv.t1[src];
+            lobj = bv.obj[src];
+        } else {
+            NodeIO<CD_FP64>::get_box(nodes, N, N - 1 + C0 + t, lo, hi, t0, t1);
+            misplaced |= t0 / slab_ticks != (C0 + t) / G.ms;
+        }
     }
     for (uint32_t k = t; k < m + 3; k += C) {
         const uint32_t K = wlo + k;
@@ -212,10 +244,18 @@ __device__ void agglo_chunk(AggShared<C, LEAVES> &S, uint32_t chunk, uint32_t M,
     auto a_first = [&](uint32_t K) { return LEAVES ? A.at(K) : (int)S.sf[K - C0] - 1; };
     if (t < m) {
         const uint32_t K = C0 + t;
-        if (LEAVES)
-            leaf_esc[K] = escape_adj(A, N, K);
-        else
-            load_record(nodes, item_id(K), lo, hi, t0, t1);
+        if (LEAVES) {
+            const uint32_t e = escape_adj(A, N, K);
+            if (GATHER >= 0 && TP == CD_FP32) {   // the leaf record with its links
+                NodeIO<TP>::put(nodes, N, N - 1 + K, lo, hi, t0, t1, lobj, e);
+            } else {
+                if (GATHER >= 0)   // the record; its skip link goes to the side
+                    NodeIO<CD_FP64>::put(nodes, N, N - 1 + K, lo, hi, t0, t1, lobj, 0u);
+                leaf_esc[K] = e;
+            }
+        } else {
+            NodeIO<TP>::get_box(nodes, N, item_id(K), lo, hi, t0, t1);
+        }
         put_slot(S.rec, t, lo, hi, t0, t1, K, pack_ends(A.at(K - 1), A.at(K), kNoSplit));
     }
     __syncthreads();
@@ -340,7 +380,7 @@ __device__ void agglo_chunk(AggShared<C, LEAVES> &S, uint32_t chunk, uint32_t M,
         return s <= N - 2 && a_first(L + 1) >= A.at(L) ? s : N - 1 + s;
     };
     auto split_at = [&](uint32_t r) { return slot_tags(S.rec, r).w >> 16; };
-    if (LEAVES) {
+    if (LEAVES && TP == CD_FP64) {
         // id = C0 + r: four lanes per record, each writing 16 bytes, so a
         // wave's store writes 16 whole consecutive records
 #pragma unroll
@@ -354,7 +394,7 @@ __device__ void agglo_chunk(AggShared<C, LEAVES> &S, uint32_t chunk, uint32_t M,
                     v.z = kids_of(F, L, C0 + (v.w >> 16)).x;
                     v.w = esc_of(L);
                 }
-                __builtin_nontemporal_store(v, (u32x4 *)(nodes + id) + q);
+                __builtin_nontemporal_store(v, (u32x4 *)((Node64 *)nodes + id) + q);
             }
         }
         if (t < m && split_at(t) != kNoSplit) {
@@ -367,7 +407,7 @@ __device__ void agglo_chunk(AggShared<C, LEAVES> &S, uint32_t chunk, uint32_t M,
         const uint32_t id = node_of(t, F, L);
         const uint2 kd = kids_of(F, L, C0 + split_at(t));
         const SlotRec o = get_slot(S.rec, t);
-        NodeIO<CD_FP64>::put(nodes, N, id, o.lo, o.hi, o.t0, o.t1, kd.x, esc_of(L));
+        NodeIO<TP>::put(nodes, N, id, o.lo, o.hi, o.t0, o.t1, kd.x, esc_of(L));
         kids[id] = kd;
     }
     __syncthreads();
@@ -395,16 +435,17 @@ __device__ void agglo_chunk(AggShared<C, LEAVES> &S, uint32_t chunk, uint32_t M,
 }
 
 // Pass 1: one workgroup per chunk of leaves (consecutive chunks on one XCD).
-template <int C>
+template <int C, int TP, int GATHER>
 __global__ __launch_bounds__(C) __attribute__((amdgpu_waves_per_eu(8))) void k_agglo_leaves(
-    CodeKeys G, uint32_t slab_ticks, Node64 *__restrict__ nodes, uint2 *__restrict__ kids,
-    uint32_t *__restrict__ leaf_esc, AggItem *__restrict__ out, uint32_t *__restrict__ out_count,
-    SeedSink seeds, unsigned int *err)
+    LeafKeys<GATHER> G, BoxView bv, uint32_t slab_ticks, void *__restrict__ nodes,
+    uint2 *__restrict__ kids, uint32_t *__restrict__ leaf_esc, AggItem *__restrict__ out,
+    uint32_t *__restrict__ out_count, SeedSink seeds, unsigned int *err)
 {
     __shared__ AggShared<C, true> S;
     bool bad = false, misplaced = false;
-    agglo_chunk<C, true>(S, xcd_block(blockIdx.x, gridDim.x), G.N, G, slab_ticks, nullptr, nodes,
-                         kids, leaf_esc, out, out_count, seeds, bad, misplaced);
+    agglo_chunk<C, true, TP, GATHER>(S, xcd_block(blockIdx.x, gridDim.x), G.N, G, bv, slab_ticks,
+                                     nullptr, nodes, kids, leaf_esc, out, out_count, seeds, bad,
+                                     misplaced);
     if (misplaced)
         atomicOr(err, 1u);
     if (bad)
@@ -413,10 +454,10 @@ __global__ __launch_bounds__(C) __attribute__((amdgpu_waves_per_eu(8))) void k_a
 
 // Later passes: the item count is on the device; a small grid strides over
 // the chunks that hold items.
-template <int C>
-__global__ __launch_bounds__(C) void k_agglo_items(CodeKeys G, const AggItem *__restrict__ in,
+template <int C, int TP>
+__global__ __launch_bounds__(C) void k_agglo_items(uint32_t N, const AggItem *__restrict__ in,
                                                    const uint32_t *__restrict__ in_count,
-                                                   Node64 *__restrict__ nodes,
+                                                   void *__restrict__ nodes,
                                                    uint2 *__restrict__ kids,
                                                    AggItem *__restrict__ out,
                                                    uint32_t *__restrict__ out_count,
@@ -424,10 +465,12 @@ __global__ __launch_bounds__(C) void k_agglo_items(CodeKeys G, const AggItem *__
 {
     __shared__ AggShared<C, false> S;
     const uint32_t M = *in_count;
+    const KVKeys G{nullptr, N};   // items carry their adjacent prefixes: no keys read
+    const BoxView bv{};
     bool bad = false, misplaced = false;
     for (uint32_t c = blockIdx.x; (uint64_t)c * C < M; c += gridDim.x)
-        agglo_chunk<C, false>(S, c, M, G, 1, in, nodes, kids, nullptr, out, out_count, seeds, bad,
-                              misplaced);
+        agglo_chunk<C, false, TP, 0>(S, c, M, G, bv, 1, in, nodes, kids, nullptr, out, out_count,
+                                     seeds, bad, misplaced);
     if (bad)
         atomicOr(err, 2u);
 }
@@ -525,6 +568,76 @@ size_t agglo_ws_bytes(uint32_t N)
            2 * align_up((chunks + 1) * sizeof(uint32_t), 256) + 256 + 6 * 256;
 }
 
+namespace {
+
+// The workspace: pass 1's roots per chunk (stage), two item lists for
+// alternate passes, per-chunk root counts and offsets, the item counts.
+struct AggPlan {
+    AggItem *stage, *items[2];
+    uint32_t *counts, *offsets, *totals;
+};
+
+AggPlan agglo_plan(void *ws, uint32_t N)
+{
+    const size_t chunks1 = (N + kAggChunk - 1) / kAggChunk;
+    Carve cv(ws, agglo_ws_bytes(N));
+    AggPlan P;
+    P.stage = cv.take<AggItem>(chunks1 * kAggOut);
+    P.items[0] = cv.take<AggItem>(chunks1 * kAggOut);
+    P.items[1] = cv.take<AggItem>(chunks1 * kAggOut);
+    P.counts = cv.take<uint32_t>(chunks1 + 1);
+    P.offsets = cv.take<uint32_t>(chunks1 + 1);
+    P.totals = cv.take<uint32_t>(2);
+    return P;
+}
+
+}  // namespace
+
+namespace {
+
+// Passes 2, 3, ... over the roots pass 1 left in its chunks' slots.
+template <int TP>
+hipError_t agglo_item_passes(uint32_t N, void *nodes, uint2 *kids, const AggPlan &P,
+                             const SeedSink &seeds, unsigned int *err, hipStream_t s)
+{
+    constexpr int C = kAggChunk;
+    // item passes: workgroups striding over the chunks; compaction grid; up
+    // to kFuseChunks chunks the scan's workgroup also compacts
+    constexpr uint32_t kItemGrid = 512, kCompactGrid = 4096, kFuseChunks = 1024;
+    uint32_t bound = N;   // pass 1: the leaves
+    const uint32_t *in_count = nullptr;   // null: the count is `bound` (pass 1)
+    int cur = 0;
+    hipError_t e = hipSuccess;
+    while (e == hipSuccess && bound > (uint32_t)C) {
+        const uint32_t nchunks = nblk(bound, C);
+        uint32_t *next_count = P.totals + cur;
+        const bool fuse = nchunks <= kFuseChunks;
+        k_agglo_scan<<<1, kAggScanThreads, 0, s>>>(P.counts, in_count, bound, C, P.offsets,
+                                                   next_count, fuse ? P.stage : nullptr,
+                                                   fuse ? P.items[cur] : nullptr);
+        if ((e = hipGetLastError()) != hipSuccess)
+            break;
+        if (!fuse) {
+            const uint32_t cgrid = nblk(nchunks, 4);
+            k_agglo_compact<<<cgrid < kCompactGrid ? cgrid : kCompactGrid, 256, 0, s>>>(
+                P.stage, P.counts, P.offsets, in_count, bound, C, P.items[cur]);
+            if ((e = hipGetLastError()) != hipSuccess)
+                break;
+        }
+        in_count = next_count;
+        const uint64_t b = (uint64_t)nchunks * kAggOut;
+        bound = b < bound ? (uint32_t)b : bound;
+        const uint32_t grid = nblk(bound, C) < kItemGrid ? nblk(bound, C) : kItemGrid;
+        k_agglo_items<C, TP><<<grid, C, 0, s>>>(N, P.items[cur], in_count, nodes, kids, P.stage,
+                                                 P.counts, seeds, err);
+        e = hipGetLastError();
+        cur ^= 1;
+    }
+    return e;
+}
+
+}  // namespace
+
 hipError_t launch_agglo(const uint32_t *code, uint32_t slab_size, uint32_t slab_ticks,
                         uint32_t N, void *nodes, uint2 *kids, uint32_t *leaf_esc, void *ws,
                         const SeedSink &seeds, unsigned int *err, hipStream_t s)
@@ -534,49 +647,43 @@ hipError_t launch_agglo(const uint32_t *code, uint32_t slab_size, uint32_t slab_
     if (!code || slab_size == 0 || slab_ticks == 0 || !ws)
         return hipErrorInvalidValue;
     constexpr int C = kAggChunk;
-    // item passes: workgroups striding over the chunks; compaction grid; up
-    // to kFuseChunks chunks the scan's workgroup also compacts
-    constexpr uint32_t kItemGrid = 512, kCompactGrid = 4096, kFuseChunks = 1024;
-    const size_t chunks1 = (N + C - 1) / C;
-    Carve cv(ws, agglo_ws_bytes(N));
-    AggItem *stage = cv.take<AggItem>(chunks1 * kAggOut);
-    AggItem *items[2] = {cv.take<AggItem>(chunks1 * kAggOut), cv.take<AggItem>(chunks1 * kAggOut)};
-    uint32_t *counts = cv.take<uint32_t>(chunks1 + 1);
-    uint32_t *offsets = cv.take<uint32_t>(chunks1 + 1);
-    uint32_t *totals = cv.take<uint32_t>(2);   // item counts of alternate passes
+    const AggPlan P = agglo_plan(ws, N);
     const CodeKeys G{code, slab_size, N};
-    uint32_t bound = N;   // pass 1: the leaves
-    k_agglo_leaves<C><<<nblk(bound, C), C, 0, s>>>(G, slab_ticks, (Node64 *)nodes, kids, leaf_esc,
-                                                    stage, counts, seeds, err);
+    k_agglo_leaves<C, CD_FP64, -1><<<nblk(N, C), C, 0, s>>>(G, BoxView{}, slab_ticks, nodes, kids,
+                                                            leaf_esc, P.stage, P.counts, seeds,
+                                                            err);
     hipError_t e = hipGetLastError();
-    const uint32_t *in_count = nullptr;   // null: the count is `bound` (pass 1)
-    int cur = 0;
-    while (e == hipSuccess && bound > (uint32_t)C) {
-        const uint32_t nchunks = nblk(bound, C);
-        uint32_t *next_count = totals + cur;
-        const bool fuse = nchunks <= kFuseChunks;
-        k_agglo_scan<<<1, kAggScanThreads, 0, s>>>(counts, in_count, bound, C, offsets,
-                                                   next_count, fuse ? stage : nullptr,
-                                                   fuse ? items[cur] : nullptr);
-        if ((e = hipGetLastError()) != hipSuccess)
-            break;
-        if (!fuse) {
-            const uint32_t cgrid = nblk(nchunks, 4);
-            k_agglo_compact<<<cgrid < kCompactGrid ? cgrid : kCompactGrid, 256, 0, s>>>(
-                stage, counts, offsets, in_count, bound, C, items[cur]);
-            if ((e = hipGetLastError()) != hipSuccess)
-                break;
-        }
-        in_count = next_count;
-        const uint64_t b = (uint64_t)nchunks * kAggOut;
-        bound = b < bound ? (uint32_t)b : bound;
-        const uint32_t grid = nblk(bound, C) < kItemGrid ? nblk(bound, C) : kItemGrid;
-        k_agglo_items<C><<<grid, C, 0, s>>>(G, items[cur], in_count, (Node64 *)nodes, kids, stage,
-                                             counts, seeds, err);
-        e = hipGetLastError();
-        cur ^= 1;
-    }
-    return e;
+    return e != hipSuccess ? e : agglo_item_passes<CD_FP64>(N, nodes, kids, P, seeds, err, s);
+}
+
+hipError_t launch_agglo_gather(const KV *kv, const BoxView &bv, int box_precision,
+                               int tree_precision, uint32_t N, void *nodes, uint2 *kids,
+                               uint32_t *leaf_esc, void *ws, const SeedSink &seeds,
+                               unsigned int *err, hipStream_t s)
+{
+    if (N == 0)
+        return hipSuccess;
+    if (!kv || !ws || (tree_precision == CD_FP64 && (!leaf_esc || box_precision != CD_FP64)))
+        return hipErrorInvalidValue;
+    constexpr int C = kAggChunk;
+    const AggPlan P = agglo_plan(ws, N);
+    const KVKeys G{kv, N};
+    const unsigned g = nblk(N, C);
+    if (tree_precision == CD_FP64)
+        k_agglo_leaves<C, CD_FP64, CD_FP64><<<g, C, 0, s>>>(G, bv, 1, nodes, kids, leaf_esc,
+                                                             P.stage, P.counts, seeds, err);
+    else if (box_precision == CD_FP64)
+        k_agglo_leaves<C, CD_FP32, CD_FP64><<<g, C, 0, s>>>(G, bv, 1, nodes, kids, nullptr,
+                                                             P.stage, P.counts, seeds, err);
+    else
+        k_agglo_leaves<C, CD_FP32, CD_FP32><<<g, C, 0, s>>>(G, bv, 1, nodes, kids, nullptr,
+                                                             P.stage, P.counts, seeds, err);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    return tree_precision == CD_FP64
+               ? agglo_item_passes<CD_FP64>(N, nodes, kids, P, seeds, err, s)
+               : agglo_item_passes<CD_FP32>(N, nodes, kids, P, seeds, err, s);
 }
 
 } // namespace cd

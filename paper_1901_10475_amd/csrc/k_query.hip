@@ -124,8 +124,8 @@ struct Q<CD_FP32> {
     }
 };
 
-// An FP64 tree whose leaf records were written in place by the box build
-// keeps its leaf skip links in a side array (*side_on set by the build).
+// An FP64 tree built bottom-up keeps its leaf skip links in a side array
+// (*side_on set by the build).
 template <int TP>
 __global__ __launch_bounds__(256) void k_traverse(const void *__restrict__ tree, uint32_t N,
                                                   uint32_t slab_ticks, Rec *__restrict__ out,
