@@ -889,25 +889,32 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
             CD_HIP(launch_karras(tw.keys, (uint32_t)N, kids, links, tw.parent, tw.clev, false, s));
     } else {
         // per-object steps and other unsorted box sets: one key sort, then
-        // the bottom-up pass reads the boxes through the sorted items
+        // the bottom-up pass reads the boxes through the sorted items.  When
+        // slab, code and box index fit one 64-bit word the sort moves 8-byte
+        // items instead of 16-byte (key, index) pairs.
+        const int sb = bits_for(max_slab), ib = N > 1 ? bits_for((uint64_t)N - 1) : 1;
+        const bool packed = sb + 32 + ib <= 64;
         {
             Stage st("keys", s);
             if (!bv.code)
                 CD_HIP(launch_bounds(bv, boxes->precision, (uint32_t)N, tw.bounds, s));
             CD_HIP(launch_keys(bv, boxes->precision, (uint32_t)N, w, max_slab, 0, tw.bounds,
-                               nullptr, tw.kva, err, s));
+                               nullptr, packed ? nullptr : tw.kva, err, s,
+                               packed ? (uint64_t *)tw.kva : nullptr, (uint32_t)ib));
         }
         void *res = nullptr;
         {
             Stage st("sort", s);
             DigitPlan plan;
             memset(&plan, 0, sizeof plan);
-            for (int sh = 0; sh < 32; sh += 8)
-                plan.shift[plan.npass++] = (uint8_t)sh;
-            int sb = bits_for(max_slab);
-            for (int sh = 0; sh < sb; sh += 8)
-                plan.shift[plan.npass++] = (uint8_t)(32 + sh);
-            CD_HIP(radix_sort16(SORT_KV, tw.kva, tw.kvb, (size_t)N, plan, tw.radix, &res, s));
+            const int base = packed ? ib : 0;   // the key's lowest bit in the item
+            for (int sh = 0; sh < 32 + sb; sh += 8)
+                plan.shift[plan.npass++] = (uint8_t)(base + sh);
+            if (packed)
+                CD_HIP(radix_sort8(tw.kva, tw.kvb, (size_t)N, plan, tw.radix, &res, s));
+            else
+                CD_HIP(radix_sort16(SORT_KV, tw.kva, tw.kvb, (size_t)N, plan, tw.radix, &res,
+                                    s));
         }
         uint32_t *side = nullptr;
         if (precision == CD_FP64) {
@@ -915,8 +922,10 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
             CD_HIP(launch_fill_u32(&((TreeHeader *)tree->mem)->leaf_esc_side, 1u, 1, s));
         }
         Stage st("hierarchy", s);
-        CD_HIP(launch_agglo_gather((const KV *)res, bv, boxes->precision, precision, (uint32_t)N,
-                                   nodes, kids, side, tw.agglo, sink, err, s));
+        CD_HIP(launch_agglo_gather(packed ? nullptr : (const KV *)res,
+                                   packed ? (const uint64_t *)res : nullptr, (uint32_t)ib, bv,
+                                   boxes->precision, precision, (uint32_t)N, nodes, kids, side,
+                                   tw.agglo, sink, err, s));
         return debug_sync((hipStream_t)stream, "cd_build_tree", (const unsigned int *)tree->mem);
     }
     {

@@ -380,6 +380,9 @@ struct DigitPlan {
 };
 hipError_t radix_sort16(SortKind kind, void *a, void *b, size_t count, const DigitPlan &plan,
                         void *ws, void **result, hipStream_t s);
+// The same over 8-byte items (one 64-bit word each; plan.field ignored).
+hipError_t radix_sort8(void *a, void *b, size_t count, const DigitPlan &plan, void *ws,
+                       void **result, hipStream_t s);
 // One workgroup per slab: compute the Morton codes of the slab's boxes, sort
 // (code, box index) inside LDS and write 64-bit keys (slab << 32 | code) and
 // box indices in sorted order.  err bit 1: a box's t0 is outside its slab.
@@ -405,10 +408,13 @@ hipError_t launch_slab_build(const BoxView &b, int box_precision, int tree_preci
 // tree
 hipError_t launch_bounds(const BoxView &b, int precision, uint32_t N,
                          unsigned long long *bounds /*[6]: min xyz, max xyz*/, hipStream_t s);
+// kv: (slab << 32 | code, box index) items; packed (with kv == nullptr): one
+// word per box, slab << (32 + ib) | code << ib | box index (N <= 2^ib).
 hipError_t launch_keys(const BoxView &b, int precision, uint32_t N, uint32_t slab_ticks,
                        uint32_t max_slab, uint32_t slab_size,
                        const unsigned long long *bounds, uint32_t *morton, KV *kv,
-                       unsigned int *err, hipStream_t s);
+                       unsigned int *err, hipStream_t s, uint64_t *packed = nullptr,
+                       uint32_t ib = 0);
 hipError_t launch_unpack_kv(const KV *kv, uint32_t N, uint64_t *keys, uint32_t *idx,
                             hipStream_t s);
 // Refit levels: level-k blocks hold refit_block(k) = kRefitChunk * 16^k
@@ -560,10 +566,12 @@ hipError_t launch_agglo(const uint32_t *code, uint32_t slab_size, uint32_t slab_
 // box kv[j].val (outward-rounded for an FP32 tree) and takes the keys from
 // kv.  FP64 trees (FP64 boxes) put the leaf skip links in leaf_esc; FP32 trees
 // in their link records (leaf_esc unused).  Key order is checked (error bit 1).
-hipError_t launch_agglo_gather(const KV *kv, const BoxView &bv, int box_precision,
-                               int tree_precision, uint32_t N, void *nodes, uint2 *kids,
-                               uint32_t *leaf_esc, void *ws, const SeedSink &seeds,
-                               unsigned int *err, hipStream_t s);
+// With packed set (kv == nullptr) the sorted items are launch_keys' packed
+// words of ib index bits.
+hipError_t launch_agglo_gather(const KV *kv, const uint64_t *packed, uint32_t ib,
+                               const BoxView &bv, int box_precision, int tree_precision,
+                               uint32_t N, void *nodes, uint2 *kids, uint32_t *leaf_esc, void *ws,
+                               const SeedSink &seeds, unsigned int *err, hipStream_t s);
 // idx == nullptr: the leaf records are already written (slab build).
 hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision, uint32_t N,
                         const uint32_t *idx, bool sorted_boxes, const uint32_t *parent,

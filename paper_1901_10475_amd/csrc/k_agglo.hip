@@ -63,11 +63,24 @@ struct AggItem {
 };
 static_assert(sizeof(AggItem) == 16, "AggItem layout");
 
-// Keys of the general path: the key sort's output, (slab << 32 | code, box).
+// Keys of the general path: the key sort's output, (slab << 32 | code, box)
+// items, or words slab << (32 + ib) | code << ib | box when pk is set.
 struct KVKeys {
     const KV *kv;
     uint32_t N;
-    __device__ uint64_t key(uint32_t j) const { return kv[j].key; }
+    const uint64_t *pk;
+    uint32_t ib;
+    __device__ uint64_t key(uint32_t j) const
+    {
+        if (!pk)
+            return kv[j].key;
+        const uint64_t w = pk[j];
+        return ((w >> (32 + ib)) << 32) | (uint32_t)(w >> ib);
+    }
+    __device__ uint32_t box(uint32_t j) const
+    {
+        return pk ? (uint32_t)(pk[j] & ((1ull << ib) - 1)) : kv[j].val;
+    }
 };
 
 // Pass 1's leaf source.  GATHER < 0: FP64 leaf records in place, CodeKeys;
@@ -189,7 +202,7 @@ __device__ void agglo_chunk(AggShared<C, LEAVES> &S, uint32_t chunk, uint32_t M,
     uint32_t t0 = 0, t1 = 0, lobj = 0;
     if (LEAVES && t < m) {   // the leaf's box, in flight with the keys
         if constexpr (GATHER >= 0) {
-            const uint32_t src = G.kv[C0 + t].val;
+            const uint32_t src = G.box(C0 + t);
             load_box<(GATHER >= 0 ? GATHER : CD_FP64)>(bv, src, lo, hi);
             if (TP == CD_FP32)
                 for (int d = 0; d < 3; ++d) {
@@ -465,7 +478,7 @@ __global__ __launch_bounds__(C) void k_agglo_items(uint32_t N, const AggItem *__
 {
     __shared__ AggShared<C, false> S;
     const uint32_t M = *in_count;
-    const KVKeys G{nullptr, N};   // items carry their adjacent prefixes: no keys read
+    const KVKeys G{nullptr, N, nullptr, 0};   // items carry their adjacent prefixes
     const BoxView bv{};
     bool bad = false, misplaced = false;
     for (uint32_t c = blockIdx.x; (uint64_t)c * C < M; c += gridDim.x)
@@ -656,18 +669,19 @@ hipError_t launch_agglo(const uint32_t *code, uint32_t slab_size, uint32_t slab_
     return e != hipSuccess ? e : agglo_item_passes<CD_FP64>(N, nodes, kids, P, seeds, err, s);
 }
 
-hipError_t launch_agglo_gather(const KV *kv, const BoxView &bv, int box_precision,
-                               int tree_precision, uint32_t N, void *nodes, uint2 *kids,
-                               uint32_t *leaf_esc, void *ws, const SeedSink &seeds,
-                               unsigned int *err, hipStream_t s)
+hipError_t launch_agglo_gather(const KV *kv, const uint64_t *packed, uint32_t ib,
+                               const BoxView &bv, int box_precision, int tree_precision,
+                               uint32_t N, void *nodes, uint2 *kids, uint32_t *leaf_esc, void *ws,
+                               const SeedSink &seeds, unsigned int *err, hipStream_t s)
 {
     if (N == 0)
         return hipSuccess;
-    if (!kv || !ws || (tree_precision == CD_FP64 && (!leaf_esc || box_precision != CD_FP64)))
+    if (!(kv || (packed && ib >= 1 && ib <= 32 && (uint64_t)N <= (1ull << ib))) || !ws ||
+        (tree_precision == CD_FP64 && (!leaf_esc || box_precision != CD_FP64)))
         return hipErrorInvalidValue;
     constexpr int C = kAggChunk;
     const AggPlan P = agglo_plan(ws, N);
-    const KVKeys G{kv, N};
+    const KVKeys G{kv, N, kv ? nullptr : packed, ib};
     const unsigned g = nblk(N, C);
     if (tree_precision == CD_FP64)
         k_agglo_leaves<C, CD_FP64, CD_FP64><<<g, C, 0, s>>>(G, bv, 1, nodes, kids, leaf_esc,

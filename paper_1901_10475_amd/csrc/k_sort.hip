@@ -1,10 +1,11 @@
 // k_sort.hip -- fills, device-wide exclusive scan, stable LSD radix sorts.
 //
 // Two radix sorts live here:
-//   * radix_sort16: device-wide, stable, over 16-byte items (key/value pairs or
-//     pair records), 8-bit digits, one histogram + scan + scatter per digit.
-//     It sorts tree keys when boxes are not grouped in slabs and it puts pair
-//     records in canonical order.
+//   * radix_sort16 / radix_sort8: device-wide, stable, over 16-byte items
+//     (key/value pairs or pair records) or 8-byte ones (a key and its box
+//     index packed in one word), 8-bit digits, one histogram + scan + scatter
+//     per digit.  They sort tree keys when boxes are not grouped in slabs and
+//     put pair records in canonical order.
 //   * k_slab_build: one 1024-thread workgroup per time slab; keys stay in
 //     registers and move through LDS between digit passes, so a slab of up to
 //     kSegCap boxes is sorted with one read and one write of global memory.
@@ -127,7 +128,7 @@ hipError_t scan_exclusive_u32(const uint32_t *in, uint32_t *out, size_t count, v
     return hipGetLastError();
 }
 
-// ---- device-wide LSD radix sort of 16-byte items -------------------------------------
+// ---- device-wide LSD radix sort of 16- and 8-byte items -------------------------------
 
 constexpr int kRadThreads = 256;
 constexpr int kRadItems = 16;
@@ -150,9 +151,17 @@ struct DigitRec {
         return (v >> shift) & 0xFFu;
     }
 };
+struct DigitU64 {
+    uint32_t shift;
+    __device__ uint32_t operator()(const uint2 &it) const
+    {
+        uint64_t v = ((uint64_t)it.y << 32) | it.x;
+        return (uint32_t)(v >> shift) & 0xFFu;
+    }
+};
 
-template <typename Digit>
-__global__ __launch_bounds__(kRadThreads) void k_radix_upsweep(const uint4 *in, size_t count,
+template <typename Item, typename Digit>
+__global__ __launch_bounds__(kRadThreads) void k_radix_upsweep(const Item *in, size_t count,
                                                                Digit dig, uint32_t *hist,
                                                                uint32_t nblocks)
 {
@@ -169,8 +178,8 @@ __global__ __launch_bounds__(kRadThreads) void k_radix_upsweep(const uint4 *in, 
     hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-template <typename Digit>
-__global__ __launch_bounds__(kRadThreads) void k_radix_downsweep(const uint4 *in, uint4 *out,
+template <typename Item, typename Digit>
+__global__ __launch_bounds__(kRadThreads) void k_radix_downsweep(const Item *in, Item *out,
                                                                  size_t count, Digit dig,
                                                                  const uint32_t *hist_scan,
                                                                  uint32_t nblocks)
@@ -186,13 +195,13 @@ __global__ __launch_bounds__(kRadThreads) void k_radix_downsweep(const uint4 *in
     dbase[threadIdx.x] = hist_scan[(size_t)threadIdx.x * nblocks + blockIdx.x];
     __syncthreads();
     size_t wbase = (size_t)blockIdx.x * kRadTile + (size_t)w * (64 * kRadItems);
-    uint4 item[kRadItems];
+    Item item[kRadItems];
     uint32_t dg[kRadItems], rk[kRadItems];
     uint64_t lt = lanemask_lt();
     for (int j = 0; j < kRadItems; ++j) {
         size_t g = wbase + (size_t)j * 64 + lane;
         bool valid = g < count;
-        item[j] = valid ? in[g] : make_uint4(0, 0, 0, 0);
+        item[j] = valid ? in[g] : Item{};
         uint32_t d = valid ? dig(item[j]) : 0u;
         uint64_t act = __ballot(valid);
         uint64_t peers = match_digit(d, act);
@@ -265,6 +274,37 @@ hipError_t radix_sort16(SortKind kind, void *a, void *b, size_t count, const Dig
         if (e != hipSuccess)
             return e;
         uint4 *t = src;
+        src = dst;
+        dst = t;
+    }
+    *result = src;
+    return hipSuccess;
+}
+
+hipError_t radix_sort8(void *a, void *b, size_t count, const DigitPlan &plan, void *ws,
+                       void **result, hipStream_t s)
+{
+    *result = a;
+    if (count <= 1 || plan.npass == 0)
+        return hipSuccess;
+    uint32_t nb = (uint32_t)((count + kRadTile - 1) / kRadTile);
+    size_t h = (size_t)nb * 256;
+    uint32_t *hist = (uint32_t *)ws;
+    void *sws = (char *)ws + align_up(h * sizeof(uint32_t), 256);
+    uint2 *src = (uint2 *)a, *dst = (uint2 *)b;
+    for (int p = 0; p < plan.npass; ++p) {
+        const DigitU64 dg{plan.shift[p]};
+        k_radix_upsweep<<<nb, kRadThreads, 0, s>>>(src, count, dg, hist, nb);
+        hipError_t e = hipGetLastError();
+        if (e == hipSuccess)
+            e = scan_exclusive_u32(hist, hist, h, sws, s);
+        if (e == hipSuccess) {
+            k_radix_downsweep<<<nb, kRadThreads, 0, s>>>(src, dst, count, dg, hist, nb);
+            e = hipGetLastError();
+        }
+        if (e != hipSuccess)
+            return e;
+        uint2 *t = src;
         src = dst;
         dst = t;
     }

@@ -320,12 +320,28 @@ def test_sorted_layout_with_unsorted_codes_is_reported():
     assert ei.value.status == cd.CD_E_INVALID
 
 
-def test_per_object_step_tree():
+@pytest.mark.parametrize("box_prec,tree_prec", [(cd.CD_FP64, cd.CD_FP64),
+                                                (cd.CD_FP64, cd.CD_FP32),
+                                                (cd.CD_FP32, cd.CD_FP32)])
+@pytest.mark.parametrize("horizon,disp_km,slab_ticks", [(3000, 20.0, 0), (200000, 2000.0, 1)])
+def test_per_object_step_tree(box_prec, tree_prec, horizon, disp_km, slab_ticks):
+    """The general path: one device-wide key sort, then the bottom-up pass
+    reading each leaf's box through the sorted items.  Slab, code and box
+    index fit one 64-bit word in the first case (8-byte sort items); one-tick
+    slabs over 200 000 ticks need 18 slab bits, so the second sorts 16-byte
+    (key, index) items."""
     need_gpu()
-    say("tree invariants, per-object steps")
+    say(f"tree invariants, per-object steps, boxes {box_prec} tree {tree_prec}, "
+        f"horizon {horizon}, slab ticks {slab_ticks}")
     rng = np.random.default_rng(11)
     el = catalog.leo_mix(rng, 400)
-    p = cd.params_struct(1.0, catalog.MU_EARTH, 1.0, 3000, 0)
-    bp = cd.BroadPhase(400, p, dt_heuristic_km=20.0, el_soa=cd.soa(el))
+    p = cd.params_struct(1.0, catalog.MU_EARTH, 1.0, horizon, 0)
+    bp = cd.BroadPhase(400, p, dt_heuristic_km=disp_km, el_soa=cd.soa(el),
+                       box_precision=box_prec, tree_precision=tree_prec,
+                       slab_ticks=slab_ticks)
     bp.build(cd.soa(el))
+    N = bp.count
+    max_slab = horizon // bp.tree.desc.slab_ticks
+    packed = max_slab.bit_length() + 32 + (N - 1).bit_length() <= 64
+    assert packed == (slab_ticks == 0)
     check_tree(bp)
