@@ -272,7 +272,7 @@ int cd_build_boxes(const cd_elements *el, const uint32_t *dt_ticks, const cd_par
 
 /* Builds an LBVH over the boxes (the AABB tree of Sec. 3.2, built in bulk):
  * each box gets a time-major key [t0 / slab_ticks | 30-bit Morton code of its
- * centre]; keys are radix-sorted (inside one workgroup's LDS per slab when
+ * centre (of a given code, its low 30 bits)]; keys are radix-sorted (inside one workgroup's LDS per slab when
  * the slab hint is set, device-wide otherwise); the binary radix (Karras)
  * hierarchy over the sorted keys has every inner box equal to the exact union
  * of its children, so an inner node overlaps whatever its leaves overlap.  It

@@ -283,13 +283,11 @@ size_t layout_boxes(void *base, size_t bytes, int64_t n, BoxWS *w)
 }
 
 struct TreeWS {
-    uint32_t *morton;
-    KV *kva, *kvb;
-    uint64_t *keys;
-    uint32_t *idx, *parent, *arrive, *list_items, *list_count;
+    KV *kva, *kvb;          // key sort items (16-byte pairs or 8-byte words)
+    uint64_t *keys;         // slab build: sorted codes
+    uint32_t *parent, *arrive, *list_items, *list_count;
     uint8_t *clev;
-    uint8_t *group_templ;   // per group of slabs: Karras nodes shared (sorted layout)
-    void *agglo;            // bottom-up build (in-place leaf records)
+    void *agglo;            // bottom-up build
     uint32_t *esc;   // escapes of an FP64 tree's nodes, for the refit
     unsigned long long *bounds;
     void *radix;
@@ -298,18 +296,15 @@ size_t layout_tree(void *base, size_t bytes, int64_t N, TreeWS *w)
 {
     Carve c(base, bytes);
     size_t n = (size_t)(N > 0 ? N : 1);
-    w->morton = c.take<uint32_t>(n);
     w->kva = c.take<KV>(n);
     w->kvb = c.take<KV>(n);
     w->keys = c.take<uint64_t>(n);
-    w->idx = c.take<uint32_t>(n);
     w->parent = c.take<uint32_t>(2 * n);
     w->arrive = c.take<uint32_t>(n);
     size_t slots = refit_list_slots((uint32_t)n, nullptr) + 1;
     w->list_items = c.take<uint32_t>(slots * kRefitListCap);
     w->list_count = c.take<uint32_t>(slots);
     w->clev = c.take<uint8_t>(n);
-    w->group_templ = c.take<uint8_t>(n / 8 + 1);
     w->agglo = c.take_bytes(agglo_ws_bytes((uint32_t)n));
     w->esc = c.take<uint32_t>(2 * n);
     w->bounds = c.take<unsigned long long>(6);
@@ -830,45 +825,25 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
     uint32_t max_slab = horizon / w;
     bool seg = boxes->slab_size > 0 && boxes->slab_size <= kSegCap && boxes->slab_ticks == w &&
                N % boxes->slab_size == 0;
-    // FP32 trees keep their link records in the tree itself; FP64 records
-    // carry them inline and take the escapes from the workspace during the
-    // refit (their link word is the left child, which the refit holds)
-    LinkSink links;
-    links.rec = precision == CD_FP32 ? (Link *)((Box32 *)nodes + (2 * (size_t)N - 1)) : nullptr;
-    links.esc = precision == CD_FP32 ? nullptr : tw.esc;
     uint2 *kids = (uint2 *)((char *)tree->mem + tree_kids_offset((uint64_t)N, precision));
-    const uint32_t *leaf_src = tw.idx;  // nullptr once the leaf records exist
-    // boxes sorted within their slabs by their codes (cd_build_boxes with
-    // CD_LAYOUT_SORTED): no key sort; the hierarchy is built over the box
-    // codes and the refit reads each leaf's box from the box arrays in order
-    bool presorted = seg && boxes->layout == CD_LAYOUT_SORTED && bv.code;
-    bool in_place = boxes->records != nullptr;
     SeedSink sink;
     sink.items = (uint2 *)((char *)tree->mem + tree_seeds_offset((uint64_t)N, precision));
     sink.cap = (uint32_t)seed_cap((uint64_t)N);
     sink.hdr = (TreeHeader *)tree->mem;
-    if (in_place) {
-        // the leaf records are in place: hierarchy, inner boxes and skip links
-        // in one bottom-up pass over the packed codes; the leaves' skip links
-        // go to the side array (the records' code words keep the codes)
-        uint32_t *side = (uint32_t *)((char *)tree->mem + tree_leaf_esc_offset((uint64_t)N,
-                                                                               precision));
-        CD_HIP(launch_fill_u32(&((TreeHeader *)tree->mem)->leaf_esc_side, 1u, 1, s));
-        Stage st("hierarchy", s);
-        CD_HIP(launch_agglo(bv.code, (uint32_t)boxes->slab_size, w, (uint32_t)N, nodes, kids,
-                            side, tw.agglo, sink, err, s));
-        return CD_OK;
-    }
-    if (presorted) {
-        leaf_src = nullptr;
-        Stage st("karras", s);
-        if (N > 1)
-            CD_HIP(launch_karras_blocks(bv.code, bv.t0, (uint32_t)N,
-                                        (uint32_t)boxes->slab_size, w, tw.group_templ, kids,
-                                        links, tw.parent, tw.clev, err, s));
-        else
-            CD_HIP(launch_karras(tw.keys, (uint32_t)N, kids, links, tw.parent, tw.clev, true, s));
-    } else if (seg) {
+    const bool in_place = boxes->records != nullptr;
+    // boxes sorted within their slabs by their codes (cd_build_boxes with
+    // CD_LAYOUT_SORTED) as arrays: box j is leaf j, no key sort
+    const bool presorted = seg && boxes->layout == CD_LAYOUT_SORTED && bv.code;
+    if (seg && !in_place && !presorted) {
+        // object-order slabs: each slab sorted in one workgroup's LDS with its
+        // leaf records written in sorted order, then the top-down Karras pass
+        // and the refit.  FP32 trees keep their link records in the tree
+        // itself; FP64 records carry them inline and take the escapes from the
+        // workspace during the refit (their link word is the left child).
+        LinkSink links;
+        links.rec = precision == CD_FP32 ? (Link *)((Box32 *)nodes + (2 * (size_t)N - 1))
+                                         : nullptr;
+        links.esc = precision == CD_FP32 ? nullptr : tw.esc;
         uint32_t m = (uint32_t)boxes->slab_size;
         if (!bv.code) {
             Stage st("keys", s);
@@ -880,20 +855,47 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
                                      (uint32_t)N, w, tw.bounds, (uint32_t *)tw.keys, nodes, err,
                                      s));
         }
-        leaf_src = nullptr;
-        Stage st("karras", s);
-        if (N > 1)
+        {
+            Stage st("karras", s);
             CD_HIP(launch_karras_slabs((const uint32_t *)tw.keys, (uint32_t)N, m, kids, links,
-                                       tw.parent, tw.clev, nullptr, 0, err, s));
-        else
-            CD_HIP(launch_karras(tw.keys, (uint32_t)N, kids, links, tw.parent, tw.clev, false, s));
+                                       tw.parent, tw.clev, s));
+        }
+        {
+            Stage st("refit", s);
+            CD_HIP(launch_refit(precision, (uint32_t)N, tw.parent, kids, links, tw.clev,
+                                tw.arrive, tw.list_items, tw.list_count, nodes, sink, err, s));
+        }
+        return debug_sync((hipStream_t)stream, "cd_build_tree", (const unsigned int *)tree->mem);
+    }
+    // every other box set: hierarchy, inner boxes and skip links in one
+    // bottom-up pass; an FP64 tree's leaf skip links go to the side array
+    uint32_t *side = nullptr;
+    if (precision == CD_FP64) {
+        side = (uint32_t *)((char *)tree->mem + tree_leaf_esc_offset((uint64_t)N, precision));
+        CD_HIP(launch_fill_u32(&((TreeHeader *)tree->mem)->leaf_esc_side, 1u, 1, s));
+    }
+    if (in_place) {
+        // the leaf records are in place (the records' code words keep the
+        // codes); keys from the packed codes
+        Stage st("hierarchy", s);
+        CD_HIP(launch_agglo(bv.code, (uint32_t)boxes->slab_size, w, (uint32_t)N, nodes, kids,
+                            side, tw.agglo, sink, err, s));
+        return debug_sync((hipStream_t)stream, "cd_build_tree", (const unsigned int *)tree->mem);
+    }
+    AggLeafSource src{};
+    if (presorted) {
+        // keys from the slab of each position and the codes
+        src.code = bv.code;
+        src.slab_size = (uint32_t)boxes->slab_size;
+        src.slab_ticks = w;
     } else {
-        // per-object steps and other unsorted box sets: one key sort, then
-        // the bottom-up pass reads the boxes through the sorted items.  When
-        // slab, code and box index fit one 64-bit word the sort moves 8-byte
-        // items instead of 16-byte (key, index) pairs.
+        // per-object steps and other unsorted box sets: one key sort, the
+        // boxes then read through the sorted items.  When slab, code and box
+        // index fit one 64-bit word the sort moves 8-byte items instead of
+        // 16-byte (key, index) pairs.
         const int sb = bits_for(max_slab), ib = N > 1 ? bits_for((uint64_t)N - 1) : 1;
-        const bool packed = sb + 32 + ib <= 64;
+        const int cb = (int)kKeyCodeBits;
+        const bool packed = sb + cb + ib <= 64;
         {
             Stage st("keys", s);
             if (!bv.code)
@@ -907,33 +909,28 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
             Stage st("sort", s);
             DigitPlan plan;
             memset(&plan, 0, sizeof plan);
-            const int base = packed ? ib : 0;   // the key's lowest bit in the item
-            for (int sh = 0; sh < 32 + sb; sh += 8)
-                plan.shift[plan.npass++] = (uint8_t)(base + sh);
+            if (packed) {   // code bits, then slab bits, above the box index
+                for (int sh = 0; sh < cb + sb; sh += 8)
+                    plan.shift[plan.npass++] = (uint8_t)(ib + sh);
+            } else {        // code (low word), then slab (high word) of the key
+                for (int sh = 0; sh < cb; sh += 8)
+                    plan.shift[plan.npass++] = (uint8_t)sh;
+                for (int sh = 0; sh < sb; sh += 8)
+                    plan.shift[plan.npass++] = (uint8_t)(32 + sh);
+            }
             if (packed)
                 CD_HIP(radix_sort8(tw.kva, tw.kvb, (size_t)N, plan, tw.radix, &res, s));
             else
                 CD_HIP(radix_sort16(SORT_KV, tw.kva, tw.kvb, (size_t)N, plan, tw.radix, &res,
                                     s));
         }
-        uint32_t *side = nullptr;
-        if (precision == CD_FP64) {
-            side = (uint32_t *)((char *)tree->mem + tree_leaf_esc_offset((uint64_t)N, precision));
-            CD_HIP(launch_fill_u32(&((TreeHeader *)tree->mem)->leaf_esc_side, 1u, 1, s));
-        }
-        Stage st("hierarchy", s);
-        CD_HIP(launch_agglo_gather(packed ? nullptr : (const KV *)res,
-                                   packed ? (const uint64_t *)res : nullptr, (uint32_t)ib, bv,
-                                   boxes->precision, precision, (uint32_t)N, nodes, kids, side,
-                                   tw.agglo, sink, err, s));
-        return debug_sync((hipStream_t)stream, "cd_build_tree", (const unsigned int *)tree->mem);
+        src.kv = packed ? nullptr : (const KV *)res;
+        src.packed = packed ? (const uint64_t *)res : nullptr;
+        src.ib = (uint32_t)ib;
     }
-    {
-        Stage st("refit", s);
-        CD_HIP(launch_refit(bv, boxes->precision, precision, (uint32_t)N, leaf_src, presorted,
-                            tw.parent, kids, links, tw.clev, tw.arrive, tw.list_items,
-                            tw.list_count, nodes, sink, err, s));
-    }
+    Stage st("hierarchy", s);
+    CD_HIP(launch_agglo_gather(src, bv, boxes->precision, precision, (uint32_t)N, nodes, kids,
+                               side, tw.agglo, sink, err, s));
     return debug_sync((hipStream_t)stream, "cd_build_tree", (const unsigned int *)tree->mem);
 }
 

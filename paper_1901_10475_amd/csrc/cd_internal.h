@@ -408,15 +408,16 @@ hipError_t launch_slab_build(const BoxView &b, int box_precision, int tree_preci
 // tree
 hipError_t launch_bounds(const BoxView &b, int precision, uint32_t N,
                          unsigned long long *bounds /*[6]: min xyz, max xyz*/, hipStream_t s);
-// kv: (slab << 32 | code, box index) items; packed (with kv == nullptr): one
-// word per box, slab << (32 + ib) | code << ib | box index (N <= 2^ib).
+// The device-wide key sort's keys: slab << 32 | the code's low kKeyCodeBits
+// bits (Morton codes have 30).  kv: (key, box index) items; packed (with kv
+// == nullptr): one word per box, slab << (30 + ib) | code << ib | box index
+// (N <= 2^ib).
+constexpr uint32_t kKeyCodeBits = 30;
 hipError_t launch_keys(const BoxView &b, int precision, uint32_t N, uint32_t slab_ticks,
                        uint32_t max_slab, uint32_t slab_size,
                        const unsigned long long *bounds, uint32_t *morton, KV *kv,
                        unsigned int *err, hipStream_t s, uint64_t *packed = nullptr,
                        uint32_t ib = 0);
-hipError_t launch_unpack_kv(const KV *kv, uint32_t N, uint64_t *keys, uint32_t *idx,
-                            hipStream_t s);
 // Refit levels: level-k blocks hold refit_block(k) = kRefitChunk * 16^k
 // leaves.  Level 0 runs one workgroup per block with LDS-resident climbing;
 // higher levels climb in global memory from per-block queues.
@@ -535,23 +536,12 @@ struct RefitLists {
 };
 uint32_t refit_levels(uint32_t N);
 size_t refit_list_slots(uint32_t N, uint32_t *base);
-// leaf_links: also write the leaves' link records (skipped when the slab
-// build wrote them).
-hipError_t launch_karras(const uint64_t *keys, uint32_t N, uint2 *kids, const LinkSink &links,
-                         uint32_t *parent, uint8_t *clev, bool leaf_links, hipStream_t s);
-// slab path (time-major slabs of slab_size leaves, slab_size <= kSegCap); the
-// leaf links are written by the slab build
+// Top-down Karras over the slab build's output (time-major slabs of
+// slab_size leaves, slab_size <= kSegCap, codes sorted in each slab); the
+// leaf links are written by the slab build.  N == 1: the leaf alone.
 hipError_t launch_karras_slabs(const uint32_t *codes, uint32_t N, uint32_t slab_size, uint2 *kids,
                                const LinkSink &links, uint32_t *parent, uint8_t *clev,
-                               const uint32_t *t0, uint32_t slab_ticks, unsigned int *err,
                                hipStream_t s);
-// Sorted-layout boxes (codes sorted in each slab, equal within blocks of
-// slabs): Karras nodes searched once per 8 slabs when the codes allow, leaf
-// skip links, and the order and slab checks.
-hipError_t launch_karras_blocks(const uint32_t *codes, const uint32_t *t0, uint32_t N,
-                                uint32_t slab_size, uint32_t slab_ticks, uint8_t *templ,
-                                uint2 *kids, const LinkSink &links, uint32_t *parent,
-                                uint8_t *clev, unsigned int *err, hipStream_t s);
 // Hierarchy and inner boxes in one bottom-up pass (k_agglo.hip) over FP64
 // leaf records already in place in key order (keys: slab j / slab_size above
 // code[j]): inner records, child pairs, leaf skip links (leaf_esc, one per
@@ -561,20 +551,28 @@ size_t agglo_ws_bytes(uint32_t N);
 hipError_t launch_agglo(const uint32_t *code, uint32_t slab_size, uint32_t slab_ticks,
                         uint32_t N, void *nodes, uint2 *kids, uint32_t *leaf_esc, void *ws,
                         const SeedSink &seeds, unsigned int *err, hipStream_t s);
-// The same pass over leaves taken from the general key sort: kv holds the N
-// (key, box index) items in key order; pass 1 writes each leaf's record from
-// box kv[j].val (outward-rounded for an FP32 tree) and takes the keys from
-// kv.  FP64 trees (FP64 boxes) put the leaf skip links in leaf_esc; FP32 trees
-// in their link records (leaf_esc unused).  Key order is checked (error bit 1).
-// With packed set (kv == nullptr) the sorted items are launch_keys' packed
-// words of ib index bits.
-hipError_t launch_agglo_gather(const KV *kv, const uint64_t *packed, uint32_t ib,
-                               const BoxView &bv, int box_precision, int tree_precision,
-                               uint32_t N, void *nodes, uint2 *kids, uint32_t *leaf_esc, void *ws,
-                               const SeedSink &seeds, unsigned int *err, hipStream_t s);
-// idx == nullptr: the leaf records are already written (slab build).
-hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision, uint32_t N,
-                        const uint32_t *idx, bool sorted_boxes, const uint32_t *parent,
+// Where the same pass takes its leaves when they are not records in place:
+// the general key sort's N items in key order (kv: (key, box index) pairs,
+// or packed: launch_keys' words of ib index bits), or box arrays already in
+// key order (code set: the sorted layout, keys (j / slab_size) << 32 |
+// code[j], each box checked against its slab of slab_ticks).
+struct AggLeafSource {
+    const KV *kv;
+    const uint64_t *packed;
+    uint32_t ib;
+    const uint32_t *code;
+    uint32_t slab_size, slab_ticks;
+};
+// Pass 1 writes each leaf's record from its box (outward-rounded for an FP32
+// tree).  FP64 trees (FP64 boxes) put the leaf skip links in leaf_esc; FP32
+// trees in their link records (leaf_esc unused).  Key order is checked
+// (error bit 1).
+hipError_t launch_agglo_gather(const AggLeafSource &src, const BoxView &bv, int box_precision,
+                               int tree_precision, uint32_t N, void *nodes, uint2 *kids,
+                               uint32_t *leaf_esc, void *ws, const SeedSink &seeds,
+                               unsigned int *err, hipStream_t s);
+// Refit of the top-down hierarchy over the leaf records the slab build wrote.
+hipError_t launch_refit(int tree_precision, uint32_t N, const uint32_t *parent,
                         const uint2 *kids,
                         const LinkSink &links, const uint8_t *clev, unsigned int *arrive,
                         uint32_t *list_items, uint32_t *list_count, void *tree,

@@ -63,23 +63,30 @@ struct AggItem {
 };
 static_assert(sizeof(AggItem) == 16, "AggItem layout");
 
-// Keys of the general path: the key sort's output, (slab << 32 | code, box)
-// items, or words slab << (32 + ib) | code << ib | box when pk is set.
+// Keys and boxes of the gathered leaves: the key sort's output, (slab << 32
+// | code, box) items or words slab << (30 + ib) | code << ib | box (pk set);
+// or boxes already in key order (code set: leaf j is box j, its key
+// (j / ms) << 32 | code[j], as for records in place).
 struct KVKeys {
     const KV *kv;
     uint32_t N;
     const uint64_t *pk;
     uint32_t ib;
+    const uint32_t *code;
+    uint32_t ms;
     __device__ uint64_t key(uint32_t j) const
     {
+        if (code)
+            return ((uint64_t)(j / ms) << 32) | code[j];
         if (!pk)
             return kv[j].key;
         const uint64_t w = pk[j];
-        return ((w >> (32 + ib)) << 32) | (uint32_t)(w >> ib);
+        return ((w >> (kKeyCodeBits + ib)) << 32) |
+               ((uint32_t)(w >> ib) & ((1u << kKeyCodeBits) - 1));
     }
     __device__ uint32_t box(uint32_t j) const
     {
-        return pk ? (uint32_t)(pk[j] & ((1ull << ib) - 1)) : kv[j].val;
+        return code ? j : pk ? (uint32_t)(pk[j] & ((1ull << ib) - 1)) : kv[j].val;
     }
 };
 
@@ -212,6 +219,8 @@ __device__ void agglo_chunk(AggShared<C, LEAVES> &S, uint32_t chunk, uint32_t M,
             t0 = bv.t0[src];
             t1 = bv.t1[src];
             lobj = bv.obj[src];
+            if (G.code)   // boxes in key order: each in its slab
+                misplaced |= t0 / slab_ticks != (C0 + t) / G.ms;
         } else {
             NodeIO<CD_FP64>::get_box(nodes, N, N - 1 + C0 + t, lo, hi, t0, t1);
             misplaced |= t0 / slab_ticks != (C0 + t) / G.ms;
@@ -478,7 +487,7 @@ __global__ __launch_bounds__(C) void k_agglo_items(uint32_t N, const AggItem *__
 {
     __shared__ AggShared<C, false> S;
     const uint32_t M = *in_count;
-    const KVKeys G{nullptr, N, nullptr, 0};   // items carry their adjacent prefixes
+    const KVKeys G{nullptr, N, nullptr, 0, nullptr, 1};   // items carry their prefixes
     const BoxView bv{};
     bool bad = false, misplaced = false;
     for (uint32_t c = blockIdx.x; (uint64_t)c * C < M; c += gridDim.x)
@@ -669,28 +678,33 @@ hipError_t launch_agglo(const uint32_t *code, uint32_t slab_size, uint32_t slab_
     return e != hipSuccess ? e : agglo_item_passes<CD_FP64>(N, nodes, kids, P, seeds, err, s);
 }
 
-hipError_t launch_agglo_gather(const KV *kv, const uint64_t *packed, uint32_t ib,
-                               const BoxView &bv, int box_precision, int tree_precision,
-                               uint32_t N, void *nodes, uint2 *kids, uint32_t *leaf_esc, void *ws,
-                               const SeedSink &seeds, unsigned int *err, hipStream_t s)
+hipError_t launch_agglo_gather(const AggLeafSource &src, const BoxView &bv, int box_precision,
+                               int tree_precision, uint32_t N, void *nodes, uint2 *kids,
+                               uint32_t *leaf_esc, void *ws, const SeedSink &seeds,
+                               unsigned int *err, hipStream_t s)
 {
     if (N == 0)
         return hipSuccess;
-    if (!(kv || (packed && ib >= 1 && ib <= 32 && (uint64_t)N <= (1ull << ib))) || !ws ||
+    const bool by_code = src.code && src.slab_size > 0 && src.slab_ticks > 0;
+    const bool by_packed = src.packed && src.ib >= 1 && src.ib <= 32 &&
+                           (uint64_t)N <= (1ull << src.ib);
+    if (!(by_code || by_packed || src.kv) || !ws ||
         (tree_precision == CD_FP64 && (!leaf_esc || box_precision != CD_FP64)))
         return hipErrorInvalidValue;
     constexpr int C = kAggChunk;
     const AggPlan P = agglo_plan(ws, N);
-    const KVKeys G{kv, N, kv ? nullptr : packed, ib};
+    const KVKeys G{by_code || by_packed ? nullptr : src.kv, N, by_code ? nullptr : src.packed,
+                   src.ib, by_code ? src.code : nullptr, by_code ? src.slab_size : 1u};
+    const uint32_t w = by_code ? src.slab_ticks : 1u;
     const unsigned g = nblk(N, C);
     if (tree_precision == CD_FP64)
-        k_agglo_leaves<C, CD_FP64, CD_FP64><<<g, C, 0, s>>>(G, bv, 1, nodes, kids, leaf_esc,
+        k_agglo_leaves<C, CD_FP64, CD_FP64><<<g, C, 0, s>>>(G, bv, w, nodes, kids, leaf_esc,
                                                              P.stage, P.counts, seeds, err);
     else if (box_precision == CD_FP64)
-        k_agglo_leaves<C, CD_FP32, CD_FP64><<<g, C, 0, s>>>(G, bv, 1, nodes, kids, nullptr,
+        k_agglo_leaves<C, CD_FP32, CD_FP64><<<g, C, 0, s>>>(G, bv, w, nodes, kids, nullptr,
                                                              P.stage, P.counts, seeds, err);
     else
-        k_agglo_leaves<C, CD_FP32, CD_FP32><<<g, C, 0, s>>>(G, bv, 1, nodes, kids, nullptr,
+        k_agglo_leaves<C, CD_FP32, CD_FP32><<<g, C, 0, s>>>(G, bv, w, nodes, kids, nullptr,
                                                              P.stage, P.counts, seeds, err);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess)

@@ -31,10 +31,9 @@ static inline unsigned nblk(uint64_t n, unsigned t) { return (unsigned)((n + t -
 // A climb that meets a parent of a higher level queues the node for that level
 // and block.  Kernel boundaries order each level's writes before the next.
 
-template <int BP, int TP>
+template <int TP>
 __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
-    BoxView b, uint32_t N, const uint32_t *__restrict__ idx, bool sorted_boxes,
-    const uint32_t *__restrict__ parent,
+    uint32_t N, const uint32_t *__restrict__ parent,
     const uint2 *__restrict__ kids, LinkSink links, const uint8_t *clev,
     void *tree, RefitLists L, SeedSink seeds, unsigned int *err)
 {
@@ -60,29 +59,7 @@ __global__ __launch_bounds__(kRefitChunk) void k_refit_chunks(
     double lo[3], hi[3];
     uint32_t t0 = 0, t1 = 0;
     bool bad = false;
-    if (t < m && (idx || sorted_boxes)) {
-        // leaf i is box idx[i], or box i itself when the boxes are sorted;
-        // its record is written here
-        uint32_t i = c0 + t;
-        uint32_t src = sorted_boxes ? i : idx[i];
-        if (src >= N) {
-            bad = true;
-            src = 0;
-        }
-        load_box<BP>(b, src, lo, hi);
-        if (TP == CD_FP32 && BP == CD_FP64) {
-            // the unions must see the rounded leaves, as the traversal does
-            for (int d = 0; d < 3; ++d) {
-                lo[d] = __double2float_rd(lo[d]);
-                hi[d] = __double2float_ru(hi[d]);
-            }
-        }
-        t0 = b.t0[src];
-        t1 = b.t1[src];
-        uint32_t leaf = N - 1 + i;
-        NodeIO<TP>::put(tree, N, leaf, lo, hi, t0, t1, b.obj[src], links.esc_of(leaf));
-        par_leaf[t] = parent[leaf];
-    } else if (t < m) {
+    if (t < m) {
         // leaf records already written in sorted order by the slab build
         uint32_t leaf = N - 1 + c0 + t;
         NodeIO<TP>::get_box(tree, N, leaf, lo, hi, t0, t1);
@@ -402,8 +379,7 @@ size_t refit_list_slots(uint32_t N, uint32_t *base)
     return slots;
 }
 
-hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision, uint32_t N,
-                        const uint32_t *idx, bool sorted_boxes, const uint32_t *parent,
+hipError_t launch_refit(int tree_precision, uint32_t N, const uint32_t *parent,
                         const uint2 *kids,
                         const LinkSink &links, const uint8_t *clev, unsigned int *arrive,
                         uint32_t *list_items, uint32_t *list_count, void *tree,
@@ -425,18 +401,12 @@ hipError_t launch_refit(const BoxView &b, int box_precision, int tree_precision,
             return e;
     }
     uint32_t nchunks = nblk(N, kRefitChunk);
-    if (box_precision == CD_FP64 && tree_precision == CD_FP64)
-        k_refit_chunks<CD_FP64, CD_FP64><<<nchunks, kRefitChunk, 0, s>>>(
-            b, N, idx, sorted_boxes, parent, kids, links, clev, tree, L,
-            seeds, err);
-    else if (box_precision == CD_FP64)
-        k_refit_chunks<CD_FP64, CD_FP32><<<nchunks, kRefitChunk, 0, s>>>(
-            b, N, idx, sorted_boxes, parent, kids, links, clev, tree, L,
-            seeds, err);
+    if (tree_precision == CD_FP64)
+        k_refit_chunks<CD_FP64><<<nchunks, kRefitChunk, 0, s>>>(N, parent, kids, links, clev,
+                                                                 tree, L, seeds, err);
     else
-        k_refit_chunks<CD_FP32, CD_FP32><<<nchunks, kRefitChunk, 0, s>>>(
-            b, N, idx, sorted_boxes, parent, kids, links, clev, tree, L,
-            seeds, err);
+        k_refit_chunks<CD_FP32><<<nchunks, kRefitChunk, 0, s>>>(N, parent, kids, links, clev,
+                                                                 tree, L, seeds, err);
     e = hipGetLastError();
     for (uint32_t k = 1; k <= levels && e == hipSuccess; ++k) {
         uint32_t nb = (uint32_t)(((uint64_t)N + (1ull << refit_shift(k)) - 1) >> refit_shift(k));

@@ -7,15 +7,16 @@ depth-first pre-order, and the seed list holds exactly the sibling pairs whose
 boxes overlap (closed extents in space, half-open tags in time).
 
 Covered: uniform steps, where the boxes of each interval form one slab --
-in object order, which one workgroup sorts in LDS per slab before the Karras
-pass and the chunked refit (slabs of 1, 2, 300 and 17 408 boxes, the largest
-one workgroup sorts, and 70 000 slabs of 3; 17 409 objects per interval take
-the device-wide sort instead); in the sorted layout as box arrays (no sort;
-Karras over the block's codes and the chunked refit); or in the sorted layout
-as the tree's own leaf records (the bottom-up pass builds hierarchy and
-unions together; up to 16 sorted runs merged per block); per-object steps
-(the general path: one radix sort of all keys); FP64 and FP32 trees; boxes
-with and without Morton codes.
+in object order, which one workgroup sorts in LDS per slab before the
+top-down Karras pass and the chunked refit (slabs of 1, 2, 300 and 17 408
+boxes, the largest one workgroup sorts, and 70 000 slabs of 3; 17 409
+objects per interval take the device-wide sort and the bottom-up pass
+instead); in the sorted layout as box arrays (no sort; the bottom-up pass
+reads box j as leaf j) or as the tree's own leaf records (the bottom-up pass
+over the records in place; up to 16 sorted runs merged per block);
+per-object steps (one radix sort of all keys, then the bottom-up pass reads
+the boxes through the sorted items); FP64 and FP32 trees; boxes with and
+without Morton codes.
 
 Tree buffer layout read here: a 256-byte header (error bits, seed count, seed
 overflow), the node records (FP64: 64 bytes each, lo[3], hi[3] as doubles, then
@@ -326,10 +327,10 @@ def test_sorted_layout_with_unsorted_codes_is_reported():
 @pytest.mark.parametrize("horizon,disp_km,slab_ticks", [(3000, 20.0, 0), (200000, 2000.0, 1)])
 def test_per_object_step_tree(box_prec, tree_prec, horizon, disp_km, slab_ticks):
     """The general path: one device-wide key sort, then the bottom-up pass
-    reading each leaf's box through the sorted items.  Slab, code and box
-    index fit one 64-bit word in the first case (8-byte sort items); one-tick
-    slabs over 200 000 ticks need 18 slab bits, so the second sorts 16-byte
-    (key, index) items."""
+    reading each leaf's box through the sorted items.  Slab, 30-bit code and
+    box index fit one 64-bit word in the first case (8-byte sort items);
+    one-tick slabs over 200 000 ticks need 18 slab bits, so the second sorts
+    16-byte (key, index) items."""
     need_gpu()
     say(f"tree invariants, per-object steps, boxes {box_prec} tree {tree_prec}, "
         f"horizon {horizon}, slab ticks {slab_ticks}")
@@ -342,6 +343,6 @@ def test_per_object_step_tree(box_prec, tree_prec, horizon, disp_km, slab_ticks)
     bp.build(cd.soa(el))
     N = bp.count
     max_slab = horizon // bp.tree.desc.slab_ticks
-    packed = max_slab.bit_length() + 32 + (N - 1).bit_length() <= 64
+    packed = max_slab.bit_length() + 30 + (N - 1).bit_length() <= 64
     assert packed == (slab_ticks == 0)
     check_tree(bp)
