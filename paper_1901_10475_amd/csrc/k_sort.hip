@@ -160,22 +160,38 @@ struct DigitU64 {
     }
 };
 
+// Digit counts of one tile.  Lanes count into one of 16 copies of the
+// histogram (by lane mod 16, rows of 257 words so that the copies of one
+// digit sit in different banks): a tile whose items share a digit (a slab
+// digit, say) then contends 4 lanes deep instead of 4 096.
 template <typename Item, typename Digit>
 __global__ __launch_bounds__(kRadThreads) void k_radix_upsweep(const Item *in, size_t count,
                                                                Digit dig, uint32_t *hist,
                                                                uint32_t nblocks)
 {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    constexpr int kCopies = 16;
+    __shared__ uint32_t h[kCopies * 257];
+    for (int k = threadIdx.x; k < kCopies * 257; k += kRadThreads)
+        h[k] = 0;
     __syncthreads();
     size_t base = (size_t)blockIdx.x * kRadTile;
+    uint32_t dg[kRadItems];   // every load in flight before the first count
+#pragma unroll
     for (int k = 0; k < kRadItems; ++k) {
         size_t g = base + (size_t)k * kRadThreads + threadIdx.x;
-        if (g < count)
-            atomicAdd(&h[dig(in[g])], 1u);
+        dg[k] = g < count ? dig(in[g]) : 256u;
     }
+    uint32_t *mine = h + (threadIdx.x % kCopies) * 257;
+#pragma unroll
+    for (int k = 0; k < kRadItems; ++k)
+        if (dg[k] < 256u)
+            atomicAdd(&mine[dg[k]], 1u);
     __syncthreads();
-    hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int q = 0; q < kCopies; ++q)
+        sum += h[q * 257 + threadIdx.x];
+    hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = sum;
 }
 
 template <typename Item, typename Digit>
@@ -198,10 +214,14 @@ __global__ __launch_bounds__(kRadThreads) void k_radix_downsweep(const Item *in,
     Item item[kRadItems];
     uint32_t dg[kRadItems], rk[kRadItems];
     uint64_t lt = lanemask_lt();
+#pragma unroll
+    for (int j = 0; j < kRadItems; ++j) {   // every load in flight before the ranking
+        size_t g = wbase + (size_t)j * 64 + lane;
+        item[j] = g < count ? in[g] : Item{};
+    }
     for (int j = 0; j < kRadItems; ++j) {
         size_t g = wbase + (size_t)j * 64 + lane;
         bool valid = g < count;
-        item[j] = valid ? in[g] : Item{};
         uint32_t d = valid ? dig(item[j]) : 0u;
         uint64_t act = __ballot(valid);
         uint64_t peers = match_digit(d, act);
