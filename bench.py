@@ -52,18 +52,18 @@ BOX_RULES = {"speed": 0, "nu": 1, "ecc": 2}
 BOX_SUFFIX = {"speed": "", "nu": "_box_interval_nu", "ecc": "_box_interval_ecc"}
 
 TRAFFIC = {
-    # k_agglo_leaves + 4 item passes with their scans and compactions
-    ("hierarchy", "fp64", "fixed"): {"fetch_kib": 2014022.5 + 57393.9 + 10095.1 + 154.1,
-                                     "write_kib": 4469486.2 + 75680.6 + 13266.6 + 234.9,
+    # k_agglo_leaves + 8 item passes with their scans and compactions
+    ("hierarchy", "fp64", "fixed"): {"fetch_kib": 2014019.7 + 57452.5 + 10084.2 + 154.1,
+                                     "write_kib": 4469510.2 + 75683.7 + 13266.6 + 234.9,
                                      "sources": {"paper_1901_10475_amd/csrc/k_agglo.hip":
-                                                 "d4c20c009293ecd4b2b467e90068f670e3196348"}},
+                                                 "5cd4ac788798fc9103eb37ffd7c0fbe8be30b23c"}},
     # k_block_codes + k_block_sort + k_boxes_uniform (records)
-    ("boxes", "fp64", "fixed"): {"fetch_kib": 3205.4 + 38912.1 + 43053.7,
-                                 "write_kib": 29615.6 + 109787.3 + 4113878.6,
+    ("boxes", "fp64", "fixed"): {"fetch_kib": 3205.6 + 38913.2 + 43762.8,
+                                 "write_kib": 29615.6 + 109775.7 + 4114047.9,
                                  "sources": {"paper_1901_10475_amd/csrc/k_boxes.hip":
                                              "bf37f93ed5022344fdde388ad03e5b9b7779cc91",
                                              "paper_1901_10475_amd/csrc/k_sort.hip":
-                                             "5499fda60e277c01f68b81b459b0f3d964c6a85b"}},
+                                             "fb1eebe7f8229aa0d8e2160512a508b55f851817"}},
 }
 
 
