@@ -694,11 +694,10 @@ hipError_t launch_query_finish(const unsigned long long *counter, const unsigned
     return hipGetLastError();
 }
 
-// Small lists (count <= kSmallCanon) in one workgroup: the records in LDS,
-// a bitonic sort on the full (i, j, t_lo, t_hi) order (padded with records
-// that sort last), then repeat flags, one block scan and the scatter.  The
-// order and the count equal the radix path's; one launch instead of a pass
-// triple per digit.
+// Small lists (count <= kSmallCanon) in one workgroup: a stable LSD radix
+// sort on the full (i, j, t_lo, t_hi) order, then repeat flags, one block
+// scan and the scatter.  The order and the count equal the radix path's; one
+// launch instead of a pass triple per digit.
 __device__ inline bool rec_less(const Rec &a, const Rec &b)
 {
     if (a.i != b.i)
@@ -715,77 +714,141 @@ __device__ inline bool rec_eq(const Rec &a, const Rec &b)
     return a.i == b.i && a.j == b.j && a.tlo == b.tlo && a.thi == b.thi;
 }
 
-// Bitonic sort of r[0..n2) (n2 a power of two) by the whole workgroup
-// (blockDim a multiple of 64).  Pair t compares records a and a + stride,
-// a = (t / stride) 2 stride + t % stride; for stride <= 64 the pairs of a
-// wave (t and t + blockDim.x for its 64 lanes) stay inside that wave's own
-// 128-record segments, so between two such stages a wave-level sync is
-// enough; a stage reaching farther, or the one before it, waits for the whole
-// workgroup.
-__device__ inline void lds_bitonic(Rec *r, uint32_t n2)
+constexpr int kRecPer = kSmallCanon / 1024;   // records per lane of a 1 024-lane workgroup
+
+struct RecSortLds {
+    Rec xch[kSmallCanon];
+    uint32_t cnt[16 * 257];   // per (wave, digit), rows of 257 words
+    uint32_t wsum[33];
+    unsigned int fmax[4];     // largest value of each field
+};
+
+__device__ inline uint32_t rec_field(const Rec &r, uint32_t f)
 {
-    for (uint32_t size = 2; size <= n2; size <<= 1) {
-        for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            for (uint32_t t = threadIdx.x; t < n2 / 2; t += blockDim.x) {
-                uint32_t a = (t / stride) * stride * 2 + (t % stride);
-                uint32_t b = a + stride;
-                bool up = (a & size) == 0;
-                Rec x = r[a], y = r[b];
-                if (rec_less(y, x) == up && !rec_eq(x, y)) {
-                    r[a] = y;
-                    r[b] = x;
-                }
-            }
-            const uint32_t next = stride > 1 ? stride >> 1 : (size < n2 ? size : 0u);
-            if (stride > 64 || next > 64)
-                __syncthreads();
-            else
-                wave_lds_sync();
-        }
-    }
-    __syncthreads();
+    return f == 0 ? r.thi : f == 1 ? r.tlo : f == 2 ? r.j : r.i;
 }
 
-// Records [0, count) into LDS, padded to a power of two with records that
-// sort last; returns that power.
-__device__ inline uint32_t lds_load_padded(Rec *r, const Rec *__restrict__ in, uint32_t count)
+// Stable LSD radix sort of the m <= kSmallCanon records a 1 024-lane
+// workgroup holds kRecPer per lane (item q of lane `lane` in wave w at place
+// w * 64 * kRecPer + q * 64 + lane).  Fields from the least significant
+// (t_hi) to the most (i), 8-bit digits, each field only over the bits its
+// largest value in this list uses.  A digit's rank: the lanes holding it
+// found by ballots, a per-(wave, digit) counter, a digit-major scan of the
+// counters.  On return the sorted records are S.xch[0 .. m).
+__device__ inline void lds_radix_rec(Rec (&x)[kRecPer], uint32_t m, RecSortLds &S)
 {
-    uint32_t n2 = 2;
-    while (n2 < count)
-        n2 <<= 1;
-    for (uint32_t k = threadIdx.x; k < n2; k += blockDim.x) {
-        Rec x;
-        if (k < count) {
-            x = in[k];
-        } else {
-            x.i = x.j = x.tlo = x.thi = 0xFFFFFFFFu;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint32_t p0 = (uint32_t)w * 64 * kRecPer + lane;
+    const uint64_t lt = lanemask_lt();
+    if (threadIdx.x < 4)
+        S.fmax[threadIdx.x] = 0;
+    __syncthreads();
+    {
+        uint32_t mx[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int q = 0; q < kRecPer; ++q)
+            if (p0 + q * 64 < m)
+                for (uint32_t f = 0; f < 4; ++f)
+                    mx[f] = max(mx[f], rec_field(x[q], f));
+        for (uint32_t f = 0; f < 4; ++f) {
+            for (int o = 32; o >= 1; o >>= 1)
+                mx[f] = max(mx[f], (uint32_t)__shfl_xor(mx[f], o, 64));
+            if (lane == 0)
+                atomicMax(&S.fmax[f], mx[f]);
         }
-        r[k] = x;
     }
     __syncthreads();
-    return n2;
+    bool moved = false;   // S.xch holds the current order
+    for (uint32_t f = 0; f < 4; ++f) {
+        const uint32_t fm = S.fmax[f];
+        for (uint32_t shift = 0; shift < 32 && (fm >> shift) != 0; shift += 8) {
+            for (int k = threadIdx.x; k < 16 * 257; k += blockDim.x)
+                S.cnt[k] = 0;
+            __syncthreads();
+            uint32_t rk[kRecPer], dg[kRecPer];
+#pragma unroll
+            for (int q = 0; q < kRecPer; ++q) {
+                const bool valid = p0 + q * 64 < m;
+                const uint32_t d = valid ? (rec_field(x[q], f) >> shift) & 0xFFu : 0u;
+                const uint64_t peers = match_digit(d, __ballot(valid));
+                const uint32_t c = valid ? S.cnt[w * 257 + d] : 0u;
+                const uint32_t mine = (uint32_t)__popcll(peers & lt);
+                if (valid && mine == 0)
+                    S.cnt[w * 257 + d] = c + (uint32_t)__popcll(peers);
+                rk[q] = c + mine;
+                dg[q] = d;
+            }
+            __syncthreads();
+            {   // exclusive scan of the 4 096 counters in (digit, wave) order
+                uint32_t v[4], sum = 0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t o = threadIdx.x * 4 + k;
+                    v[k] = S.cnt[(o % 16) * 257 + o / 16];
+                    sum += v[k];
+                }
+                uint32_t total;
+                uint32_t run = block_exclusive_scan(sum, S.wsum, &total);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t o = threadIdx.x * 4 + k;
+                    S.cnt[(o % 16) * 257 + o / 16] = run;
+                    run += v[k];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < kRecPer; ++q)
+                if (p0 + q * 64 < m)
+                    S.xch[S.cnt[w * 257 + dg[q]] + rk[q]] = x[q];
+            __syncthreads();
+#pragma unroll
+            for (int q = 0; q < kRecPer; ++q)
+                if (p0 + q * 64 < m)
+                    x[q] = S.xch[p0 + q * 64];
+            moved = true;
+            __syncthreads();
+        }
+    }
+    if (!moved) {   // a single distinct record (or none): already in order
+#pragma unroll
+        for (int q = 0; q < kRecPer; ++q)
+            if (p0 + q * 64 < m)
+                S.xch[p0 + q * 64] = x[q];
+        __syncthreads();
+    }
+}
+
+// Records [0, count) of `in` into the lanes, kRecPer per lane.
+__device__ inline void load_lanes(Rec (&x)[kRecPer], const Rec *__restrict__ in, uint32_t count)
+{
+    const uint32_t p0 = (threadIdx.x >> 6) * 64 * kRecPer + (threadIdx.x & 63);
+#pragma unroll
+    for (int q = 0; q < kRecPer; ++q)
+        if (p0 + q * 64 < count)
+            x[q] = in[p0 + q * 64];
 }
 
 __global__ __launch_bounds__(1024) void k_small_canon(const Rec *__restrict__ in,
                                                       uint32_t count, Rec *__restrict__ out,
                                                       uint32_t *total)
 {
-    __shared__ Rec r[kSmallCanon];
-    __shared__ uint32_t wsum[64];
-    uint32_t n2 = lds_load_padded(r, in, count);
-    lds_bitonic(r, n2);
-    // repeats dropped: each thread owns up to 4 consecutive records
-    constexpr int kPer = kSmallCanon / 1024;
-    uint32_t k0 = threadIdx.x * kPer;
-    uint32_t f[kPer], mine = 0;
-    for (int q = 0; q < kPer; ++q) {
+    __shared__ RecSortLds S;
+    Rec x[kRecPer];
+    load_lanes(x, in, count);
+    lds_radix_rec(x, count, S);
+    // repeats dropped: each thread owns up to kRecPer consecutive records
+    const Rec *r = S.xch;
+    uint32_t k0 = threadIdx.x * kRecPer;
+    uint32_t f[kRecPer], mine = 0;
+    for (int q = 0; q < kRecPer; ++q) {
         uint32_t k = k0 + q;
         f[q] = (k < count && (k == 0 || !rec_eq(r[k], r[k - 1]))) ? 1u : 0u;
         mine += f[q];
     }
     uint32_t all;
-    uint32_t pos = block_exclusive_scan(mine, wsum, &all);
-    for (int q = 0; q < kPer; ++q)
+    uint32_t pos = block_exclusive_scan(mine, S.wsum, &all);
+    for (int q = 0; q < kRecPer; ++q)
         if (f[q])
             out[pos++] = r[k0 + q];
     if (threadIdx.x == 0)
@@ -796,13 +859,14 @@ __global__ __launch_bounds__(1024) void k_small_canon(const Rec *__restrict__ in
 __global__ __launch_bounds__(1024) void k_tile_sort(const Rec *__restrict__ in, uint32_t count,
                                                     Rec *__restrict__ out)
 {
-    __shared__ Rec r[kSmallCanon];
+    __shared__ RecSortLds S;
     uint32_t base = blockIdx.x * (uint32_t)kSmallCanon;
     uint32_t m = count - base < (uint32_t)kSmallCanon ? count - base : (uint32_t)kSmallCanon;
-    uint32_t n2 = lds_load_padded(r, in + base, m);
-    lds_bitonic(r, n2);
+    Rec x[kRecPer];
+    load_lanes(x, in + base, m);
+    lds_radix_rec(x, m, S);
     for (uint32_t k = threadIdx.x; k < m; k += blockDim.x)
-        out[base + k] = r[k];
+        out[base + k] = S.xch[k];
 }
 
 // ... then sorted runs of `width` records are merged pairwise: output k finds

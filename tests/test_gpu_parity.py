@@ -138,6 +138,33 @@ def test_box_soups_general_path(kind, N):
         assert np.array_equal(got, want), (kind, N, tp)
 
 
+@pytest.mark.parametrize("kind", ["uniform", "identical", "line"])
+@pytest.mark.parametrize("N", [65, 4097])
+def test_box_soups_wide_keys(kind, N):
+    """The key sort's 16-byte (key, index) items: time tags scaled by 2^20
+    (half-open overlaps, hence records up to the same scale, are unchanged)
+    over one-tick slabs need 29 slab bits, so slab, code and box index no
+    longer fit one 64-bit word.  FP64 and FP32 trees against the oracle."""
+    need_gpu()
+    say("soup wide keys", kind, N)
+    import paper_1901_10475_amd as cd
+    lo, hi, t0, t1, obj = catalog.random_boxes(N + 7, N, max(2, N // 4), extent=200, size=6,
+                                               T=400, max_len=12, kind=kind)
+    scale = 1 << 20
+    t0, t1 = t0.astype(np.int64) * scale, t1.astype(np.int64) * scale
+    assert t1.max() < 2 ** 32 - 1
+    t0, t1 = t0.astype(np.uint32), t1.astype(np.uint32)
+    H = 400 * scale
+    assert (H // 1).bit_length() + 30 + (N - 1).bit_length() > 64
+    ob = oracle.Boxes(lo, hi, t0, t1, obj)
+    for tp in (cd.CD_FP64, cd.CD_FP32):
+        b = cd.Boxes.from_arrays(lo, hi, t0, t1, obj, cd.CD_FP64, horizon_ticks=H,
+                                 obj_count=max(2, N // 4))
+        got = cd.query_boxes(b, tp, slab_ticks=1, capacity=64).cpu().numpy().view(np.uint32)
+        want = oracle.pairs(ob if tp == cd.CD_FP64 else oracle.outward_f32(ob))
+        assert np.array_equal(got, want), (kind, N, tp)
+
+
 def test_capacity_retry_gives_identical_set():
     need_gpu()
     say("capacity retry")
