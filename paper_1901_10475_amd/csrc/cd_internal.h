@@ -665,7 +665,7 @@ hipError_t launch_gather_elements(const cd_elements &el, const uint32_t *ids, ui
 hipError_t launch_remap_records(const cd_pair *in, uint32_t count, const uint32_t *ids,
                                 uint32_t nids, cd_pair *out, hipStream_t s);
 // The canonical list of at most kSmallCanon records in one workgroup (LDS
-// bitonic sort + repeat removal); *total = records written.
+// radix sort + repeat removal); *total = records written.
 constexpr int kSmallCanon = 4096;
 hipError_t launch_small_canon(const Rec *in, uint32_t count, Rec *out, uint32_t *total,
                               hipStream_t s);
