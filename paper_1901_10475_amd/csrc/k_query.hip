@@ -239,8 +239,11 @@ hipError_t launch_traverse(const void *tree, int precision, uint32_t N, uint32_t
 // ballot and one atomic.
 
 // Side s of a pair: a leaf stays itself, an inner node is replaced by its two
-// children (kids of the tree).  Loads the boxes of the resulting nodes.
-template <int TP>
+// children (kids of the tree).  Loads the boxes of the resulting nodes, and
+// the leaves' object ids unless LINKS is false (FP32: the ids sit in the
+// link array, a second cache line, and are then read only for leaf pairs
+// whose boxes overlap).
+template <int TP, bool LINKS = true>
 __device__ inline bool load_side(const void *tree, const uint2 *kids, uint32_t N, uint32_t x,
                                  uint32_t ids[2], typename Q<TP>::F lo[2][3],
                                  typename Q<TP>::F hi[2][3], uint32_t t0[2], uint32_t t1[2],
@@ -252,7 +255,12 @@ __device__ inline bool load_side(const void *tree, const uint2 *kids, uint32_t N
         return false;
     if (x >= N - 1) {
         ids[0] = x;
-        Q<TP>::load(tree, N, x, lo[0], hi[0], t0[0], t1[0], lk[0], e);
+        if (LINKS || TP == CD_FP64) {
+            Q<TP>::load(tree, N, x, lo[0], hi[0], t0[0], t1[0], lk[0], e);
+        } else {
+            Q<TP>::load_box(tree, N, x, lo[0], hi[0], t0[0], t1[0]);
+            lk[0] = 0;
+        }
         cnt = 1;
         return true;
     }
@@ -270,11 +278,11 @@ __device__ inline bool load_side(const void *tree, const uint2 *kids, uint32_t N
     // FP32: an inner child's link (a second cache line) is never used, its
     // children come from kids, so only a leaf child pays for the object id
     lk[0] = lk[1] = 0;
-    if (kk.x >= N - 1)
+    if (LINKS && kk.x >= N - 1)
         Q<TP>::load(tree, N, kk.x, lo[0], hi[0], t0[0], t1[0], lk[0], e);
     else
         Q<TP>::load_box(tree, N, kk.x, lo[0], hi[0], t0[0], t1[0]);
-    if (kk.y >= N - 1)
+    if (LINKS && kk.y >= N - 1)
         Q<TP>::load(tree, N, kk.y, lo[1], hi[1], t0[1], t1[1], lk[1], e);
     else
         Q<TP>::load_box(tree, N, kk.y, lo[1], hi[1], t0[1], t1[1]);
@@ -296,6 +304,11 @@ __device__ inline void expand_level(const void *__restrict__ tree, const uint2 *
                                     unsigned long long &rbase)
 {
     using F = typename Q<TP>::F;
+#ifdef CD_COUNTERS
+    constexpr bool kLinks = true;   // the node-visit counts need every leaf's object
+#else
+    constexpr bool kLinks = TP == CD_FP64;   // FP32: object ids only for overlapping leaf pairs
+#endif
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += gridDim.x * blockDim.x) {
         uint32_t k = base + threadIdx.x;
         bool active = k < n;
@@ -312,10 +325,10 @@ __device__ inline void expand_level(const void *__restrict__ tree, const uint2 *
             } else {
                 pr = in[k];
             }
-            bool ok = load_side<TP>(tree, kids, N, pr.x, ids[0], lo[0], hi[0], t0[0], t1[0],
-                                    lk[0], cnt[0]) &&
-                      load_side<TP>(tree, kids, N, pr.y, ids[1], lo[1], hi[1], t0[1], t1[1],
-                                    lk[1], cnt[1]);
+            bool ok = load_side<TP, kLinks>(tree, kids, N, pr.x, ids[0], lo[0], hi[0], t0[0],
+                                            t1[0], lk[0], cnt[0]) &&
+                      load_side<TP, kLinks>(tree, kids, N, pr.y, ids[1], lo[1], hi[1], t0[1],
+                                            t1[1], lk[1], cnt[1]);
             if (!ok) {
                 atomicOr(flags, 2u);
                 active = false;
@@ -329,6 +342,11 @@ __device__ inline void expand_level(const void *__restrict__ tree, const uint2 *
                           space_overlap(lo[0][ia], hi[0][ia], lo[1][ic], hi[1][ic]);
                 bool leaves = ov && ids[0][ia] >= N - 1 && ids[1][ic] >= N - 1;
                 int bit = ia * 2 + ic;
+                if (!kLinks && leaves) {
+                    const uint2 *links = (const uint2 *)((const Box32 *)tree + (2 * (size_t)N - 1));
+                    lk[0][ia] = links[ids[0][ia]].x;
+                    lk[1][ic] = links[ids[1][ic]].x;
+                }
                 if (leaves && lk[0][ia] != lk[1][ic])
                     hit_mask |= 1u << bit;
                 if (ov && !leaves)
