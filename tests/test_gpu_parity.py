@@ -116,10 +116,12 @@ def test_fp32_boxes_are_outward_rounded():
 
 
 @pytest.mark.parametrize("kind", ["uniform", "identical", "disjoint", "line", "huge"])
-@pytest.mark.parametrize("N", [0, 1, 2, 3, 63, 64, 65, 1000, 4095, 4097, 20000])
+@pytest.mark.parametrize("N", [0, 1, 2, 3, 63, 64, 65, 1000, 1024, 1025, 2048, 4095, 4097,
+                               20000])
 def test_box_soups_general_path(kind, N):
-    """Caller-built boxes (device-wide sort path), ragged sizes, degenerate
-    geometry; FP64 and FP32 trees.  Identical boxes overlap in space
+    """Caller-built boxes (device-wide sort path), ragged sizes (the bottom-up
+    pass's 1 024-leaf chunks: one exactly full, one leaf over, two full),
+    degenerate geometry; FP64 and FP32 trees.  Identical boxes overlap in space
     everywhere (20 000 of them: 6-7 M records, only the time tags separate
     them), so the node-pair queue overflows into the per-leaf walk and the
     records into the radix canonical path."""
