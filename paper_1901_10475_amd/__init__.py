@@ -280,7 +280,8 @@ def elements_struct(el_soa):
     assert el_soa.dtype == torch.float64 and el_soa.is_cuda and el_soa.dim() == 2
     assert el_soa.shape[0] == 6 and el_soa.is_contiguous()
     n = el_soa.shape[1]
-    rows = [ctypes.c_void_p(el_soa[k].data_ptr() if n else 0) for k in range(6)]
+    base, row = el_soa.data_ptr(), el_soa.stride(0) * el_soa.element_size()
+    rows = [ctypes.c_void_p(base + k * row if n else 0) for k in range(6)]
     return cd_elements(*rows, n)
 
 

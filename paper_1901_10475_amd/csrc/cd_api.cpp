@@ -168,12 +168,14 @@ constexpr int kExpandBatch = 12;                 // levels launched between coun
 constexpr int kExpandMaxLevels = 400;            // > 2 x the deepest possible tree
 // Query control block (32-bit words): [l] queue count after level l - 1
 // ([0] stays zero), then the per-leaf-walk flag, the level flags, the
-// one-launch traversal's arrival counter, and a status copy (record count
-// low/high, tree error) at an 8-byte-aligned word.
+// one-launch traversal's arrival counter, a status copy (record count
+// low/high, tree error) at an 8-byte-aligned word, and the result of a small
+// canonical list formed before the host read the count.
 constexpr int kCtlWalk = kExpandMaxLevels + 1;
 constexpr int kCtlFlags = kExpandMaxLevels + 2;
 constexpr int kCtlBarrier = kExpandMaxLevels + 3;
 constexpr int kCtlStatus = kExpandMaxLevels + 4;
+constexpr int kCtlCanon = kCtlStatus + 3;   // small canonical list done: records + 1
 constexpr int kCtlWords = kCtlStatus + 4;
 // Node-pair levels the last drained traversal needed: the next synchronous
 // query launches that many before its first count check.
@@ -181,6 +183,11 @@ std::atomic<int> g_expand_levels{kExpandBatch};
 // Node-pair levels the calling thread's last synchronous query needed to
 // drain its queue (0: the per-leaf walk ran, or no query yet).
 thread_local int g_last_levels = 0;
+// Raw record count of the calling thread's last synchronous query: when it
+// fits the one-workgroup canonical list, the next query forms that list right
+// after its node-pair levels, before the host reads the count, which saves a
+// round trip to the host.
+thread_local unsigned long long g_last_records = 0;
 
 int check_params(const cd_params *p)
 {
@@ -706,8 +713,10 @@ int cd_build_boxes(const cd_elements *el, const uint32_t *dt_ticks, const cd_par
     bo.rec = (Node64 *)out->records;
     out->code_valid = 0;
     Stage st_boxes("boxes", s);
-    CD_HIP(launch_object_setup(*el, p->mu, (double)p->start_ticks * p->tick_s, w.oc, w.os, s));
-    if (bo.code || bo.rec)
+    const bool frame = bo.code || bo.rec;
+    CD_HIP(launch_object_setup(*el, p->mu, (double)p->start_ticks * p->tick_s, w.oc, w.os,
+                               frame ? w.frame : nullptr, s));
+    if (frame)
         CD_HIP(launch_orbit_frame(w.oc, (uint32_t)n, w.frame, s));
     double half_thr = 0.5 * p->threshold_km;
     if (!dt_ticks) {
@@ -975,8 +984,15 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
     const cd_tuning tu = tuning();
     unsigned int stw[3];        // record count low/high, tree error
     bool status_read = false;   // stw already read with the last control block
+    unsigned int canon_done = 0;   // records + 1 of a list formed before the count was read
     {
-        Stage st("traverse", s);
+        // the stage ends early when the small canonical list is formed with
+        // the first control-block read (its own stage)
+        Stage *trav = new Stage("traverse", s);
+        struct StageEnd {
+            Stage *&p;
+            ~StageEnd() { delete p; }
+        } trav_end{trav};
         // node-pair traversal from the refit's overlapping sibling pairs; a
         // build error or lost seeds (k_query_begin), a queue overflow or a bad
         // node hand the query to the per-leaf walk, decided from one read of
@@ -1011,7 +1027,10 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
             int batch = g_expand_levels.load(std::memory_order_relaxed);
             batch = batch < 1 ? 1 : (batch > kExpandMaxLevels ? kExpandMaxLevels : batch);
             unsigned int qf = 0;
+            bool try_canon = g_last_records <= (unsigned long long)kSmallCanon;
             while (lev < kExpandMaxLevels) {
+                if (!trav)
+                    trav = new Stage("traverse", s);
                 int end = lev + batch < kExpandMaxLevels ? lev + batch : kExpandMaxLevels;
                 for (; lev < end; ++lev) {
                     uint2 *outq = (lev & 1) ? w.qb : w.qa;
@@ -1024,6 +1043,16 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
                     in_cap = w.qcap;
                 }
                 CD_HIP(launch_query_status(w.counter, err, w.qcount + kCtlStatus, s));
+                if (try_canon) {
+                    // the list, if the levels drained and the count fits
+                    delete trav;
+                    trav = nullptr;
+                    Stage c("canon", s);
+                    CD_HIP(launch_small_canon_gated(w.raw, w.counter, w.qflags, err,
+                                                    (uint32_t)capacity, (Rec *)out,
+                                                    w.qcount + kCtlCanon, s));
+                    try_canon = false;
+                }
                 CD_HIP(hipMemcpyAsync(ctl, w.qcount, sizeof ctl, hipMemcpyDeviceToHost, s));
                 CD_HIP(hipStreamSynchronize(s));
                 qf = ctl[kCtlFlags];
@@ -1045,9 +1074,12 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
                 for (int k = 0; k < 3; ++k)
                     stw[k] = ctl[kCtlStatus + k];
                 status_read = true;
+                canon_done = ctl[kCtlCanon];
             }
         }
         if (walk) {
+            if (!trav)
+                trav = new Stage("traverse", s);
             // bounded fallback: one stackless walk per leaf (in mode 2 only if
             // the device decided so, from a count it cleared itself)
             if (!run_walk)
@@ -1064,6 +1096,7 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
     }
     unsigned long long cnt = (unsigned long long)stw[0] | ((unsigned long long)stw[1] << 32);
     unsigned int e = stw[2];
+    g_last_records = cnt;
     if (e)
         return fail(CD_E_INVALID, "tree inconsistent (error bits 0x%x): boxes disagree with "
                                   "their slab hint or horizon, or the build failed", e);
@@ -1071,6 +1104,10 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
     if (cnt > (unsigned long long)capacity)
         return fail(CD_E_CAPACITY, "%llu records exceed capacity %lld", cnt,
                     (long long)capacity);
+    if (canon_done) {   // formed with the control block just read
+        *count_host = (int64_t)(canon_done - 1);
+        return CD_OK;
+    }
     if (cnt == 0)
         return CD_OK;
     uint32_t count = (uint32_t)cnt;
@@ -1390,7 +1427,7 @@ int cd_refine_records(const cd_elements *el, const cd_params *p, uint32_t delta_
     {
         Stage st("refine", s);
         CD_HIP(launch_object_setup(*el, p->mu, (double)p->start_ticks * p->tick_s, w.oc, w.os,
-                                   s));
+                                   nullptr, s));
         CD_HIP(launch_fill_u32(w.ctl, 0u, kRefCtlWords, s));
         CD_HIP(launch_fill_u32(w.ctl, (uint32_t)count, 1, s));
         CD_HIP(launch_fill_u64(w.counter, 0ull, 1, s));

@@ -304,9 +304,12 @@ constexpr int kMlpOuterSamples = 128;    // samples per outer-product block
 // ---- launchers (each returns the launch status) -----------------------------
 
 // boxes
+// Per-object constants; with frame set, also the orbit frame's empty start
+// (launch_orbit_frame then forms the frame over it).
 hipError_t launch_object_setup(const cd_elements &el, double mu, double start_s, ObjConst *oc,
-                               ObjSinus *os, hipStream_t s);
-// union of the orbits' bounding boxes (ordered bits: min xyz, max xyz)
+                               ObjSinus *os, unsigned long long *frame, hipStream_t s);
+// union of the orbits' bounding boxes (ordered bits: min xyz, max xyz), over
+// the start launch_object_setup wrote
 hipError_t launch_orbit_frame(const ObjConst *oc, uint32_t n, unsigned long long *frame,
                               hipStream_t s);
 hipError_t launch_validate(const cd_elements &el, unsigned long long *first_bad, hipStream_t s);
@@ -669,6 +672,13 @@ hipError_t launch_remap_records(const cd_pair *in, uint32_t count, const uint32_
 constexpr int kSmallCanon = 4096;
 hipError_t launch_small_canon(const Rec *in, uint32_t count, Rec *out, uint32_t *total,
                               hipStream_t s);
+// The same with the count still on the device: runs only if the node-pair
+// levels drained (*qflags == 8), *tree_err == 0 and *counter <= min(capacity,
+// kSmallCanon); then *done = records written + 1 (else *done is untouched).
+hipError_t launch_small_canon_gated(const Rec *in, const unsigned long long *counter,
+                                    const unsigned int *qflags, const unsigned int *tree_err,
+                                    uint32_t capacity, Rec *out, unsigned int *done,
+                                    hipStream_t s);
 // kSmallCanon < count <= kMediumCanon: tiles sorted in LDS, merged pairwise,
 // then repeats removed (launch_unique; total at pos[count]).  a holds the
 // records and is overwritten; b is scratch of count records.  Up to 2^18

@@ -36,9 +36,11 @@ namespace cd {
 // x_d(E) = a (cos E - e) P_d + b sin E Q_d = -a e P_d + R_d cos(E - phi_d) with
 // R_d cos phi_d = a P_d and R_d sin phi_d = b Q_d.
 __global__ void k_object_setup(cd_elements el, double mu, double start_s, ObjConst *oc,
-                               ObjSinus *os)
+                               ObjSinus *os, unsigned long long *frame)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (frame && i < 6)   // the orbit frame's start: empty (min at the top, max at 0)
+        frame[i] = i < 3 ? ~0ull : 0ull;
     if (i >= el.n)
         return;
     ObjConst c = object_const(el.a[i], el.e[i], el.inc[i], el.raan[i], el.argp[i], el.m0[i], mu,
@@ -477,22 +479,20 @@ static void dispatch_rule(int precision, int rule, F &&go)
 }
 
 hipError_t launch_object_setup(const cd_elements &el, double mu, double start_s, ObjConst *oc,
-                               ObjSinus *os, hipStream_t s)
+                               ObjSinus *os, unsigned long long *frame, hipStream_t s)
 {
-    if (el.n == 0)
+    if (el.n == 0 && !frame)
         return hipSuccess;
-    k_object_setup<<<blocks_for(el.n, 256), 256, 0, s>>>(el, mu, start_s, oc, os);
+    const uint64_t threads = el.n > 6 ? (uint64_t)el.n : 6u;
+    k_object_setup<<<blocks_for(threads, 256), 256, 0, s>>>(el, mu, start_s, oc, os, frame);
     return hipGetLastError();
 }
 
 hipError_t launch_orbit_frame(const ObjConst *oc, uint32_t n, unsigned long long *frame,
                               hipStream_t s)
 {
-    hipError_t e = launch_fill_u64(frame, ~0ull, 3, s);
-    if (e == hipSuccess)
-        e = launch_fill_u64(frame + 3, 0ull, 3, s);
-    if (e != hipSuccess || n == 0)
-        return e;
+    if (n == 0)
+        return hipSuccess;
     k_orbit_frame<<<blocks_for(n, 256), 256, 0, s>>>(oc, n, frame);
     return hipGetLastError();
 }

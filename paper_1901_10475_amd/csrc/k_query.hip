@@ -847,11 +847,11 @@ __device__ inline void load_lanes(Rec (&x)[kRecPer], const Rec *__restrict__ in,
             x[q] = in[p0 + q * 64];
 }
 
-__global__ __launch_bounds__(1024) void k_small_canon(const Rec *__restrict__ in,
-                                                      uint32_t count, Rec *__restrict__ out,
-                                                      uint32_t *total)
+// The canonical list of count <= kSmallCanon records; returns the number
+// written (every thread).
+__device__ inline uint32_t small_canon(const Rec *__restrict__ in, uint32_t count,
+                                       Rec *__restrict__ out, RecSortLds &S)
 {
-    __shared__ RecSortLds S;
     Rec x[kRecPer];
     load_lanes(x, in, count);
     lds_radix_rec(x, count, S);
@@ -869,8 +869,37 @@ __global__ __launch_bounds__(1024) void k_small_canon(const Rec *__restrict__ in
     for (int q = 0; q < kRecPer; ++q)
         if (f[q])
             out[pos++] = r[k0 + q];
+    return all;
+}
+
+__global__ __launch_bounds__(1024) void k_small_canon(const Rec *__restrict__ in,
+                                                      uint32_t count, Rec *__restrict__ out,
+                                                      uint32_t *total)
+{
+    __shared__ RecSortLds S;
+    const uint32_t all = small_canon(in, count, out, S);
     if (threadIdx.x == 0)
         *total = all;
+}
+
+// The same, enqueued before the host knows the count: it runs only when the
+// node-pair levels drained their queue (flag 8, no other flag), the tree has
+// no error bits and the record count fits both the small path and the
+// capacity; *done = records written + 1 then, else it stays 0.
+__global__ __launch_bounds__(1024) void k_small_canon_gated(const Rec *__restrict__ in,
+                                                            const unsigned long long *counter,
+                                                            const unsigned int *qflags,
+                                                            const unsigned int *tree_err,
+                                                            uint32_t limit, Rec *__restrict__ out,
+                                                            unsigned int *done)
+{
+    __shared__ RecSortLds S;
+    const unsigned long long c = *counter;
+    if (*qflags != 8u || *tree_err != 0u || c > (unsigned long long)limit)
+        return;
+    const uint32_t all = c ? small_canon(in, (uint32_t)c, out, S) : 0u;
+    if (threadIdx.x == 0)
+        *done = all + 1;
 }
 
 // Medium lists: each workgroup sorts one kSmallCanon-record tile in LDS ...
@@ -924,6 +953,16 @@ hipError_t launch_small_canon(const Rec *in, uint32_t count, Rec *out, uint32_t 
     if (count == 0 || count > (uint32_t)kSmallCanon)
         return hipErrorInvalidValue;
     k_small_canon<<<1, 1024, 0, s>>>(in, count, out, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_small_canon_gated(const Rec *in, const unsigned long long *counter,
+                                    const unsigned int *qflags, const unsigned int *tree_err,
+                                    uint32_t capacity, Rec *out, unsigned int *done,
+                                    hipStream_t s)
+{
+    const uint32_t limit = capacity < (uint32_t)kSmallCanon ? capacity : (uint32_t)kSmallCanon;
+    k_small_canon_gated<<<1, 1024, 0, s>>>(in, counter, qflags, tree_err, limit, out, done);
     return hipGetLastError();
 }
 
