@@ -24,8 +24,11 @@
  *     (cd_profile_*, guarded by a mutex); and a process-wide hint, kept in an
  *     atomic, of how many node-pair levels the last drained synchronous query
  *     needed, which sets how many levels the next one launches before its
- *     first host check.  None of them changes a result: records depend only
- *     on the arguments of the call.
+ *     first host check; and, per thread, the last synchronous query's level
+ *     count (cd_last_query_levels) and raw record count (when that fitted the
+ *     one-workgroup canonical list, the next query forms its list before the
+ *     first host check, on the device's count).  None of them changes a
+ *     result: records depend only on the arguments of the call.
  *   - Streams are hipStream_t values passed as void* (NULL = default stream).
  *     Work is enqueued on that stream; functions marked "syncs" wait for it.
  *   - Every function returns a status code; no exception crosses the ABI.
