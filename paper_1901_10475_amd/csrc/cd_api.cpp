@@ -184,9 +184,10 @@ std::atomic<int> g_expand_levels{kExpandBatch};
 // drain its queue (0: the per-leaf walk ran, or no query yet).
 thread_local int g_last_levels = 0;
 // Raw record count of the calling thread's last synchronous query: when it
-// fits the one-workgroup canonical list, the next query forms that list right
-// after its node-pair levels, before the host reads the count, which saves a
-// round trip to the host.
+// fits the one-workgroup canonical list (or the tile-and-merge path, with a
+// quarter to spare), the next query forms that list right after its
+// node-pair levels, before the host reads the count, which saves a round
+// trip to the host.
 thread_local unsigned long long g_last_records = 0;
 
 int check_params(const cd_params *p)
@@ -1027,7 +1028,18 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
             int batch = g_expand_levels.load(std::memory_order_relaxed);
             batch = batch < 1 ? 1 : (batch > kExpandMaxLevels ? kExpandMaxLevels : batch);
             unsigned int qf = 0;
-            bool try_canon = g_last_records <= (unsigned long long)kSmallCanon;
+            bool try_canon = true;
+            const unsigned long long last = g_last_records;
+            uint32_t plan = 0;   // bound of a tile-and-merge list formed early
+            if (last > (unsigned long long)kSmallCanon && last <= (unsigned long long)kMediumCanon) {
+                unsigned long long b = (last + last / 4 + kSmallCanon) / kSmallCanon * kSmallCanon;
+                b = b < (unsigned long long)kMediumCanon ? b : (unsigned long long)kMediumCanon;
+                b = b < (unsigned long long)capacity ? b : (unsigned long long)capacity;
+                plan = b > (unsigned long long)kSmallCanon ? (uint32_t)b : 0u;
+                try_canon = plan != 0;
+            } else if (last > (unsigned long long)kSmallCanon) {
+                try_canon = false;
+            }
             while (lev < kExpandMaxLevels) {
                 if (!trav)
                     trav = new Stage("traverse", s);
@@ -1048,9 +1060,15 @@ int cd_query_pairs(const cd_tree *tree, cd_pair *out, int64_t capacity, int64_t 
                     delete trav;
                     trav = nullptr;
                     Stage c("canon", s);
-                    CD_HIP(launch_small_canon_gated(w.raw, w.counter, w.qflags, err,
-                                                    (uint32_t)capacity, (Rec *)out,
-                                                    w.qcount + kCtlCanon, s));
+                    if (plan) {
+                        const DevCount g{w.counter, w.qflags, err, (uint32_t)kSmallCanon, plan};
+                        CD_HIP(launch_medium_canon(w.raw, w.alt, plan, w.flags, w.pos, w.scan,
+                                                   (Rec *)out, s, g, w.qcount + kCtlCanon, 1u));
+                    } else {
+                        CD_HIP(launch_small_canon_gated(w.raw, w.counter, w.qflags, err,
+                                                        (uint32_t)capacity, (Rec *)out,
+                                                        w.qcount + kCtlCanon, s));
+                    }
                     try_canon = false;
                 }
                 CD_HIP(hipMemcpyAsync(ctl, w.qcount, sizeof ctl, hipMemcpyDeviceToHost, s));

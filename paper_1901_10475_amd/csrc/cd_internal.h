@@ -685,10 +685,36 @@ hipError_t launch_small_canon_gated(const Rec *in, const unsigned long long *cou
 // records six merge passes cost less than the radix path's ten digit passes
 // (three launches each): 69 589 records took 0.72 ms by radix.
 constexpr int kMediumCanon = 1 << 18;
+// A record count read on the device when the kernels run, for lists
+// enqueued before the host knows it: valid when the node-pair levels drained
+// (*qflags == 8), the tree has no error bits and lo < count <= hi; the
+// kernels then use it (the host's count, an upper bound, sizes their grids)
+// and do nothing otherwise.  counter == nullptr: the host's count.
+struct DevCount {
+    const unsigned long long *counter;
+    const unsigned int *qflags, *tree_err;
+    uint32_t lo, hi;
+    __device__ bool get(uint32_t host, uint32_t &count) const
+    {
+        if (!counter) {
+            count = host;
+            return true;
+        }
+        const unsigned long long c = *counter;
+        if (*qflags != 8u || *tree_err != 0u || c <= lo || c > hi)
+            return false;
+        count = (uint32_t)c;
+        return true;
+    }
+};
+// With g.counter set, count is the bound g.hi and the list's length + bias
+// goes to *total (else to pos[count]).
 hipError_t launch_medium_canon(Rec *a, Rec *b, uint32_t count, uint32_t *flags, uint32_t *pos,
-                               void *scan_ws, Rec *out, hipStream_t s);
+                               void *scan_ws, Rec *out, hipStream_t s, const DevCount &g = {},
+                               unsigned int *total = nullptr, uint32_t bias = 0);
 hipError_t launch_unique(const Rec *in, uint32_t count, uint32_t *flags, uint32_t *pos,
-                         void *scan_ws, Rec *out, hipStream_t s);
+                         void *scan_ws, Rec *out, hipStream_t s, const DevCount &g = {},
+                         unsigned int *total = nullptr, uint32_t bias = 0);
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 

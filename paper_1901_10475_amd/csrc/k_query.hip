@@ -903,11 +903,16 @@ __global__ __launch_bounds__(1024) void k_small_canon_gated(const Rec *__restric
 }
 
 // Medium lists: each workgroup sorts one kSmallCanon-record tile in LDS ...
-__global__ __launch_bounds__(1024) void k_tile_sort(const Rec *__restrict__ in, uint32_t count,
-                                                    Rec *__restrict__ out)
+__global__ __launch_bounds__(1024) void k_tile_sort(const Rec *__restrict__ in, uint32_t bound,
+                                                    Rec *__restrict__ out, DevCount g)
 {
     __shared__ RecSortLds S;
+    uint32_t count;
+    if (!g.get(bound, count))
+        return;
     uint32_t base = blockIdx.x * (uint32_t)kSmallCanon;
+    if (base >= count)
+        return;
     uint32_t m = count - base < (uint32_t)kSmallCanon ? count - base : (uint32_t)kSmallCanon;
     Rec x[kRecPer];
     load_lanes(x, in + base, m);
@@ -919,9 +924,13 @@ __global__ __launch_bounds__(1024) void k_tile_sort(const Rec *__restrict__ in, 
 // ... then sorted runs of `width` records are merged pairwise: output k finds
 // by binary search how many of its predecessors come from the left run (the
 // stable merge path: on equal records the left run goes first).
-__global__ __launch_bounds__(256) void k_merge_runs(const Rec *__restrict__ in, uint32_t count,
-                                                    uint32_t width, Rec *__restrict__ out)
+__global__ __launch_bounds__(256) void k_merge_runs(const Rec *__restrict__ in, uint32_t bound,
+                                                    uint32_t width, Rec *__restrict__ out,
+                                                    DevCount g)
 {
+    uint32_t count;
+    if (!g.get(bound, count))
+        return;
     uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= count)
         return;
@@ -967,16 +976,19 @@ hipError_t launch_small_canon_gated(const Rec *in, const unsigned long long *cou
 }
 
 hipError_t launch_medium_canon(Rec *a, Rec *b, uint32_t count, uint32_t *flags, uint32_t *pos,
-                               void *scan_ws, Rec *out, hipStream_t s)
+                               void *scan_ws, Rec *out, hipStream_t s, const DevCount &g,
+                               unsigned int *total, uint32_t bias)
 {
-    if (count <= (uint32_t)kSmallCanon || count > (uint32_t)kMediumCanon)
+    if (count <= (uint32_t)kSmallCanon || count > (uint32_t)kMediumCanon ||
+        (g.counter && (!total || g.hi != count || !g.qflags || !g.tree_err)))
         return hipErrorInvalidValue;
     uint32_t tiles = (count + kSmallCanon - 1) / kSmallCanon;
-    k_tile_sort<<<tiles, 1024, 0, s>>>(a, count, b);
+    k_tile_sort<<<tiles, 1024, 0, s>>>(a, count, b, g);
     hipError_t e = hipGetLastError();
     Rec *src = b, *dst = a;
+    // passes for the bound; with a smaller device count the last ones copy
     for (uint32_t w = kSmallCanon; e == hipSuccess && w < count; w *= 2) {
-        k_merge_runs<<<nblk(count, 256), 256, 0, s>>>(src, count, w, dst);
+        k_merge_runs<<<nblk(count, 256), 256, 0, s>>>(src, count, w, dst, g);
         e = hipGetLastError();
         Rec *t = src;
         src = dst;
@@ -984,16 +996,23 @@ hipError_t launch_medium_canon(Rec *a, Rec *b, uint32_t count, uint32_t *flags, 
     }
     if (e != hipSuccess)
         return e;
-    return launch_unique(src, count, flags, pos, scan_ws, out, s);
+    return launch_unique(src, count, flags, pos, scan_ws, out, s, g, total, bias);
 }
 
 // ---- canonical list: sorted records, repeats dropped -----------------------------------------
 
-__global__ void k_unique_flags(const Rec *in, uint32_t count, uint32_t *flags)
+__global__ void k_unique_flags(const Rec *in, uint32_t bound, uint32_t *flags, DevCount g)
 {
-    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= count)
+    uint32_t count;
+    if (!g.get(bound, count))
         return;
+    uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= bound)
+        return;
+    if (r >= count) {   // past a device count: nothing to keep
+        flags[r] = 0u;
+        return;
+    }
     bool f = true;
     if (r > 0) {
         Rec a = in[r - 1], b = in[r];
@@ -1002,31 +1021,38 @@ __global__ void k_unique_flags(const Rec *in, uint32_t count, uint32_t *flags)
     flags[r] = f ? 1u : 0u;
 }
 
-__global__ void k_unique_scatter(const Rec *in, uint32_t count, const uint32_t *flags,
-                                 const uint32_t *pos, Rec *out, uint32_t *total)
+__global__ void k_unique_scatter(const Rec *in, uint32_t bound, const uint32_t *flags,
+                                 const uint32_t *pos, Rec *out, uint32_t *total, uint32_t bias,
+                                 DevCount g)
 {
+    uint32_t count;
+    if (!g.get(bound, count))
+        return;
     uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= count)
         return;
     if (flags[r])
         out[pos[r]] = in[r];
     if (r == count - 1)
-        *total = pos[r] + flags[r];
+        *total = pos[r] + flags[r] + bias;
 }
 
 hipError_t launch_unique(const Rec *in, uint32_t count, uint32_t *flags, uint32_t *pos,
-                         void *scan_ws, Rec *out, hipStream_t s)
+                         void *scan_ws, Rec *out, hipStream_t s, const DevCount &g,
+                         unsigned int *total, uint32_t bias)
 {
-    // total is written to pos[count] (pos holds count + 1 entries)
+    // total is written to pos[count] (pos holds count + 1 entries), or with a
+    // device count to *total
     if (count == 0)
         return launch_fill_u32(pos, 0u, 1, s);
-    k_unique_flags<<<nblk(count, 256), 256, 0, s>>>(in, count, flags);
+    k_unique_flags<<<nblk(count, 256), 256, 0, s>>>(in, count, flags, g);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess)
         e = scan_exclusive_u32(flags, pos, count, scan_ws, s);
     if (e != hipSuccess)
         return e;
-    k_unique_scatter<<<nblk(count, 256), 256, 0, s>>>(in, count, flags, pos, out, pos + count);
+    k_unique_scatter<<<nblk(count, 256), 256, 0, s>>>(in, count, flags, pos, out,
+                                                      g.counter ? total : pos + count, bias, g);
     return hipGetLastError();
 }
 
