@@ -167,6 +167,32 @@ def test_box_soups_wide_keys(kind, N):
         assert np.array_equal(got, want), (kind, N, tp)
 
 
+def test_early_canonical_list_across_path_changes():
+    """A synchronising query forms the canonical list before the host reads
+    the count when the calling thread's previous query took the same path
+    (one workgroup up to 4 096 records, tiles and merges above); the guess is
+    checked on the device.  Queries alternating between the two paths, each
+    twice in a row (first with the other path's guess, then with its own):
+    every list equals the oracle's."""
+    need_gpu()
+    import paper_1901_10475_amd as cd
+    cases = {}
+    for N in (450, 800):   # identical boxes: records set by the time tags alone
+        lo, hi, t0, t1, obj = catalog.random_boxes(N + 3, N, N // 4, extent=200, size=6, T=400,
+                                                   max_len=12, kind="identical")
+        want = oracle.pairs(oracle.Boxes(lo, hi, t0, t1, obj))
+        b = cd.Boxes.from_arrays(lo, hi, t0, t1, obj, cd.CD_FP64, horizon_ticks=400,
+                                 obj_count=N // 4)
+        cases[N] = (b, want)
+    assert len(cases[450][1]) <= 4096 < len(cases[800][1]) <= 1 << 18
+    for N in (450, 800, 450, 800, 800, 450):
+        b, want = cases[N]
+        for rep in range(2):
+            got = cd.query_boxes(b, cd.CD_FP64, slab_ticks=16,
+                                 capacity=2 * len(want)).cpu().numpy().view(np.uint32)
+            assert np.array_equal(got, want), (N, rep)
+
+
 def test_capacity_retry_gives_identical_set():
     need_gpu()
     say("capacity retry")
