@@ -902,17 +902,20 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
         // per-object steps and other unsorted box sets: one key sort, the
         // boxes then read through the sorted items.  When slab, code and box
         // index fit one 64-bit word the sort moves 8-byte items instead of
-        // 16-byte (key, index) pairs.
+        // 16-byte (key, index) pairs; box sets too large for the whole code
+        // keep its top bits (at least kMinPackedCodeBits of 30)
         const int sb = bits_for(max_slab), ib = N > 1 ? bits_for((uint64_t)N - 1) : 1;
-        const int cb = (int)kKeyCodeBits;
-        const bool packed = sb + cb + ib <= 64;
+        const int room = 64 - sb - ib;
+        const int cb = room < (int)kKeyCodeBits ? room : (int)kKeyCodeBits;
+        const bool packed = cb >= (int)kMinPackedCodeBits;
         {
             Stage st("keys", s);
             if (!bv.code)
                 CD_HIP(launch_bounds(bv, boxes->precision, (uint32_t)N, tw.bounds, s));
             CD_HIP(launch_keys(bv, boxes->precision, (uint32_t)N, w, max_slab, 0, tw.bounds,
                                nullptr, packed ? nullptr : tw.kva, err, s,
-                               packed ? (uint64_t *)tw.kva : nullptr, (uint32_t)ib));
+                               packed ? (uint64_t *)tw.kva : nullptr, (uint32_t)ib,
+                               packed ? (uint32_t)cb : kKeyCodeBits));
         }
         void *res = nullptr;
         {
@@ -923,7 +926,7 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
                 for (int sh = 0; sh < cb + sb; sh += 8)
                     plan.shift[plan.npass++] = (uint8_t)(ib + sh);
             } else {        // code (low word), then slab (high word) of the key
-                for (int sh = 0; sh < cb; sh += 8)
+                for (int sh = 0; sh < (int)kKeyCodeBits; sh += 8)
                     plan.shift[plan.npass++] = (uint8_t)sh;
                 for (int sh = 0; sh < sb; sh += 8)
                     plan.shift[plan.npass++] = (uint8_t)(32 + sh);
@@ -937,6 +940,7 @@ int cd_build_tree(const cd_boxes *boxes, int precision, uint32_t slab_ticks, cd_
         src.kv = packed ? nullptr : (const KV *)res;
         src.packed = packed ? (const uint64_t *)res : nullptr;
         src.ib = (uint32_t)ib;
+        src.cb = (uint32_t)(packed ? cb : kKeyCodeBits);
     }
     Stage st("hierarchy", s);
     CD_HIP(launch_agglo_gather(src, bv, boxes->precision, precision, (uint32_t)N, nodes, kids,

@@ -413,14 +413,16 @@ hipError_t launch_bounds(const BoxView &b, int precision, uint32_t N,
                          unsigned long long *bounds /*[6]: min xyz, max xyz*/, hipStream_t s);
 // The device-wide key sort's keys: slab << 32 | the code's low kKeyCodeBits
 // bits (Morton codes have 30).  kv: (key, box index) items; packed (with kv
-// == nullptr): one word per box, slab << (30 + ib) | code << ib | box index
-// (N <= 2^ib).
-constexpr uint32_t kKeyCodeBits = 30;
+// == nullptr): one word per box, slab << (cb + ib) | code' << ib | box index
+// (N <= 2^ib), code' the code's top cb bits (cb <= kKeyCodeBits: large box
+// sets give up the lowest code bits, which only shape the tree, to keep
+// 8-byte sort items).
+constexpr uint32_t kKeyCodeBits = 30, kMinPackedCodeBits = 24;
 hipError_t launch_keys(const BoxView &b, int precision, uint32_t N, uint32_t slab_ticks,
                        uint32_t max_slab, uint32_t slab_size,
                        const unsigned long long *bounds, uint32_t *morton, KV *kv,
                        unsigned int *err, hipStream_t s, uint64_t *packed = nullptr,
-                       uint32_t ib = 0);
+                       uint32_t ib = 0, uint32_t cb = kKeyCodeBits);
 // Refit levels: level-k blocks hold refit_block(k) = kRefitChunk * 16^k
 // leaves.  Level 0 runs one workgroup per block with LDS-resident climbing;
 // higher levels climb in global memory from per-block queues.
@@ -556,13 +558,13 @@ hipError_t launch_agglo(const uint32_t *code, uint32_t slab_size, uint32_t slab_
                         const SeedSink &seeds, unsigned int *err, hipStream_t s);
 // Where the same pass takes its leaves when they are not records in place:
 // the general key sort's N items in key order (kv: (key, box index) pairs,
-// or packed: launch_keys' words of ib index bits), or box arrays already in
+// or packed: launch_keys' words of ib index and cb code bits), or box arrays already in
 // key order (code set: the sorted layout, keys (j / slab_size) << 32 |
 // code[j], each box checked against its slab of slab_ticks).
 struct AggLeafSource {
     const KV *kv;
     const uint64_t *packed;
-    uint32_t ib;
+    uint32_t ib, cb;   // packed words: index and code bits
     const uint32_t *code;
     uint32_t slab_size, slab_ticks;
 };

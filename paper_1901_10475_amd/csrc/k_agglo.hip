@@ -64,14 +64,14 @@ struct AggItem {
 static_assert(sizeof(AggItem) == 16, "AggItem layout");
 
 // Keys and boxes of the gathered leaves: the key sort's output, (slab << 32
-// | code, box) items or words slab << (30 + ib) | code << ib | box (pk set);
+// | code, box) items or words slab << (cb + ib) | code << ib | box (pk set);
 // or boxes already in key order (code set: leaf j is box j, its key
 // (j / ms) << 32 | code[j], as for records in place).
 struct KVKeys {
     const KV *kv;
     uint32_t N;
     const uint64_t *pk;
-    uint32_t ib;
+    uint32_t ib, cb;
     const uint32_t *code;
     uint32_t ms;
     __device__ uint64_t key(uint32_t j) const
@@ -81,8 +81,7 @@ struct KVKeys {
         if (!pk)
             return kv[j].key;
         const uint64_t w = pk[j];
-        return ((w >> (kKeyCodeBits + ib)) << 32) |
-               ((uint32_t)(w >> ib) & ((1u << kKeyCodeBits) - 1));
+        return ((w >> (cb + ib)) << 32) | ((uint32_t)(w >> ib) & ((1u << cb) - 1));
     }
     __device__ uint32_t box(uint32_t j) const
     {
@@ -487,7 +486,7 @@ __global__ __launch_bounds__(C) void k_agglo_items(uint32_t N, const AggItem *__
 {
     __shared__ AggShared<C, false> S;
     const uint32_t M = *in_count;
-    const KVKeys G{nullptr, N, nullptr, 0, nullptr, 1};   // items carry their prefixes
+    const KVKeys G{nullptr, N, nullptr, 0, 0, nullptr, 1};   // items carry their prefixes
     const BoxView bv{};
     bool bad = false, misplaced = false;
     for (uint32_t c = blockIdx.x; (uint64_t)c * C < M; c += gridDim.x)
@@ -687,14 +686,15 @@ hipError_t launch_agglo_gather(const AggLeafSource &src, const BoxView &bv, int 
         return hipSuccess;
     const bool by_code = src.code && src.slab_size > 0 && src.slab_ticks > 0;
     const bool by_packed = src.packed && src.ib >= 1 && src.ib <= 32 &&
-                           (uint64_t)N <= (1ull << src.ib);
+                           (uint64_t)N <= (1ull << src.ib) && src.cb >= 1 &&
+                           src.cb <= kKeyCodeBits;
     if (!(by_code || by_packed || src.kv) || !ws ||
         (tree_precision == CD_FP64 && (!leaf_esc || box_precision != CD_FP64)))
         return hipErrorInvalidValue;
     constexpr int C = kAggChunk;
     const AggPlan P = agglo_plan(ws, N);
     const KVKeys G{by_code || by_packed ? nullptr : src.kv, N, by_code ? nullptr : src.packed,
-                   src.ib, by_code ? src.code : nullptr, by_code ? src.slab_size : 1u};
+                   src.ib, src.cb, by_code ? src.code : nullptr, by_code ? src.slab_size : 1u};
     const uint32_t w = by_code ? src.slab_ticks : 1u;
     const unsigned g = nblk(N, C);
     if (tree_precision == CD_FP64)

@@ -85,7 +85,7 @@ hipError_t launch_bounds(const BoxView &b, int precision, uint32_t N, unsigned l
 template <int PREC>
 __global__ void k_keys(BoxView b, uint32_t N, uint32_t slab_ticks, uint32_t max_slab,
                        uint32_t slab_size, const unsigned long long *bounds, uint32_t *morton,
-                       KV *kv, unsigned int *err, uint64_t *packed, uint32_t ib)
+                       KV *kv, unsigned int *err, uint64_t *packed, uint32_t ib, uint32_t cb)
 {
     uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= N)
@@ -125,23 +125,26 @@ __global__ void k_keys(BoxView b, uint32_t N, uint32_t slab_ticks, uint32_t max_
         x.pad = 0;
         kv[k] = x;
     } else if (packed) {
-        packed[k] = ((uint64_t)slab << (kKeyCodeBits + ib)) | ((uint64_t)m << ib) | k;
+        packed[k] = ((uint64_t)slab << (cb + ib)) | ((uint64_t)(m >> (kKeyCodeBits - cb)) << ib) |
+                    k;
     }
 }
 
 hipError_t launch_keys(const BoxView &b, int precision, uint32_t N, uint32_t slab_ticks,
                        uint32_t max_slab, uint32_t slab_size, const unsigned long long *bounds,
                        uint32_t *morton, KV *kv, unsigned int *err, hipStream_t s,
-                       uint64_t *packed, uint32_t ib)
+                       uint64_t *packed, uint32_t ib, uint32_t cb)
 {
+    if (packed && (cb > kKeyCodeBits || cb == 0))
+        return hipErrorInvalidValue;
     if (N == 0)
         return hipSuccess;
     if (precision == CD_FP64)
         k_keys<CD_FP64><<<nblk(N, 256), 256, 0, s>>>(b, N, slab_ticks, max_slab, slab_size,
-                                                     bounds, morton, kv, err, packed, ib);
+                                                     bounds, morton, kv, err, packed, ib, cb);
     else
         k_keys<CD_FP32><<<nblk(N, 256), 256, 0, s>>>(b, N, slab_ticks, max_slab, slab_size,
-                                                     bounds, morton, kv, err, packed, ib);
+                                                     bounds, morton, kv, err, packed, ib, cb);
     return hipGetLastError();
 }
 

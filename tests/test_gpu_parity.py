@@ -143,10 +143,12 @@ def test_box_soups_general_path(kind, N):
 @pytest.mark.parametrize("kind", ["uniform", "identical", "line"])
 @pytest.mark.parametrize("N", [65, 4097])
 def test_box_soups_wide_keys(kind, N):
-    """The key sort's 16-byte (key, index) items: time tags scaled by 2^20
-    (half-open overlaps, hence records up to the same scale, are unchanged)
-    over one-tick slabs need 29 slab bits, so slab, code and box index no
-    longer fit one 64-bit word.  FP64 and FP32 trees against the oracle."""
+    """Wide keys: time tags scaled by 2^20 (half-open overlaps, hence records
+    up to the same scale, are unchanged) over one-tick slabs need 29 slab
+    bits, so slab, 30-bit code and box index no longer fit one 64-bit word:
+    65 boxes keep the code's top 28 bits in 8-byte items, 4 097 boxes would
+    keep fewer than 24 and sort 16-byte (key, index) items.  FP64 and FP32
+    trees against the oracle."""
     need_gpu()
     say("soup wide keys", kind, N)
     import paper_1901_10475_amd as cd

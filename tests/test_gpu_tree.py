@@ -324,13 +324,15 @@ def test_sorted_layout_with_unsorted_codes_is_reported():
 @pytest.mark.parametrize("box_prec,tree_prec", [(cd.CD_FP64, cd.CD_FP64),
                                                 (cd.CD_FP64, cd.CD_FP32),
                                                 (cd.CD_FP32, cd.CD_FP32)])
-@pytest.mark.parametrize("horizon,disp_km,slab_ticks", [(3000, 20.0, 0), (200000, 2000.0, 1)])
+@pytest.mark.parametrize("horizon,disp_km,slab_ticks", [(3000, 20.0, 0), (200000, 2000.0, 1),
+                                                      (1 << 22, 20000.0, 1)])
 def test_per_object_step_tree(box_prec, tree_prec, horizon, disp_km, slab_ticks):
     """The general path: one device-wide key sort, then the bottom-up pass
     reading each leaf's box through the sorted items.  Slab, 30-bit code and
-    box index fit one 64-bit word in the first case (8-byte sort items);
-    one-tick slabs over 200 000 ticks need 18 slab bits, so the second sorts
-    16-byte (key, index) items."""
+    box index fit one 64-bit word in the first case (8-byte sort items); with
+    one-tick slabs over 200 000 ticks (18 slab bits) the word keeps the
+    code's top 27 bits; over 2^22 ticks (23 slab bits) fewer than 24 would
+    remain, so the third sorts 16-byte (key, index) items."""
     need_gpu()
     say(f"tree invariants, per-object steps, boxes {box_prec} tree {tree_prec}, "
         f"horizon {horizon}, slab ticks {slab_ticks}")
@@ -343,6 +345,7 @@ def test_per_object_step_tree(box_prec, tree_prec, horizon, disp_km, slab_ticks)
     bp.build(cd.soa(el))
     N = bp.count
     max_slab = horizon // bp.tree.desc.slab_ticks
-    packed = max_slab.bit_length() + 30 + (N - 1).bit_length() <= 64
-    assert packed == (slab_ticks == 0)
+    room = 64 - max_slab.bit_length() - (N - 1).bit_length()
+    assert (room >= 30, room >= 24) == {3000: (True, True), 200000: (False, True),
+                                        1 << 22: (False, False)}[horizon], (N, room)
     check_tree(bp)
