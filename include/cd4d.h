@@ -525,9 +525,9 @@ int cd_remap_records(const cd_pair *in, int64_t count, const uint32_t *ids, int6
                      cd_pair *out, cd_stream_t stream);
 
 /* The canonical list of any records (sorted by i, j, t_lo, t_hi; repeats
- * removed), e.g. the bands' records merged: out[0..*count_host).  Record
- * fields must fit horizon_ticks + 1 (times) and obj_count (ids).
- * Synchronises. */
+ * removed), e.g. the bands' records merged: out[0..*count_host).  t_lo must
+ * be at most horizon_ticks + 1 and ids below obj_count (both size the sort
+ * keys); t_hi may take any value.  Synchronises. */
 size_t cd_canonical_records_ws(int64_t count);
 int cd_canonical_records(const cd_pair *in, int64_t count, uint32_t horizon_ticks,
                          uint32_t obj_count, cd_pair *out, int64_t *count_host, void *ws,

@@ -338,7 +338,9 @@ DigitPlan record_plan_bits(uint32_t horizon_ticks, uint32_t obj_count)
     DigitPlan plan;
     memset(&plan, 0, sizeof plan);
     const int fields[4] = {3, 2, 1, 0};  // t_hi, t_lo, j, i
-    const int widths[4] = {tb, tb, ob, ob};
+    // t_lo is some box's t0 (at most the horizon); t_hi some box's t1, which
+    // caller-built boxes may put past it: all 32 bits
+    const int widths[4] = {32, tb, ob, ob};
     for (int f = 0; f < 4; ++f)
         for (int sh = 0; sh < widths[f]; sh += 8) {
             plan.field[plan.npass] = (uint8_t)fields[f];

@@ -113,3 +113,20 @@ def test_canonical_records_small_medium_and_radix_paths(count):
     got = cd.cd_canonical_records(t, 3001, 300).cpu().numpy().view(np.uint32)
     want = np.unique(rec, axis=0)
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("count", [3000, 100000, 300000])
+def test_canonical_records_end_times_past_the_horizon(count):
+    """Only t_lo and the ids are bounded by the sort-key sizes: t_hi may take
+    any 32-bit value (a caller's box may end past the horizon) on every path."""
+    need_gpu()
+    rng = np.random.default_rng(77 + count)
+    rec = np.stack([rng.integers(0, 300, count), rng.integers(0, 300, count),
+                    rng.integers(0, 3001, count),
+                    rng.integers(0, (1 << 32) - 1, count, dtype=np.uint64)],
+                   axis=1).astype(np.uint32)
+    rec[-5:, :3] = rec[0, :3]                        # same (i, j, t_lo), other t_hi
+    rec[-5:, 3] = [3001, 1 << 12, 1 << 20, (1 << 31) + 5, (1 << 32) - 2]
+    t = torch.from_numpy(rec.view(np.int32)).cuda()
+    got = cd.cd_canonical_records(t, 3000, 300).cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, np.unique(rec, axis=0))
