@@ -13,7 +13,7 @@ time (HIP events recorded by the library on its own stream during the timed
 steps), its compulsory HBM bytes per launch (the hot-path scope's per-box
 figures) over its mean duration, against the 8 TB/s specification and the
 measured streaming-copy bandwidth; the same for every stage and for the whole
-query.  the benchmark spec: the learned per-object step with FP32 boxes (eccentric-
+query.  learned_steps: the learned per-object step with FP32 boxes (eccentric-
 anomaly and speed boxes) against this FP64 1 s line.  cpu_baseline: the CPU
 oracle (FP64 boxes, bucketed all-pairs within each slab, canonical sort) on the
 hour's first 60 slabs, on all host threads and on one.
@@ -417,8 +417,8 @@ def run_tracked(args, log):
     out["narrow_phase"] = narrow_phase(cd, el, p, pairs, log)
     default_line = (args.dt == "fixed" and prec == cd.CD_FP64 and box_prec == cd.CD_FP64
                     and args.box == "speed")
-    if default_line and not args.no_north_star:
-        out["north_star"] = north_star_forms(args, log, sc, el, {
+    if default_line and not args.no_learned_steps:
+        out["learned_steps"] = learned_step_forms(args, log, sc, el, {
             "ms_per_query": round(ms_step, 4), "boxes": N, "records": P,
             "planted_recall": recall,
             "colliding_object_pairs": out["narrow_phase"]["colliding_object_pairs"]})
@@ -469,7 +469,7 @@ def colliding_object_pairs(cd, el, p, pairs, delta=1):
     return int(torch.unique(hp[:, 0] * (1 << 32) + hp[:, 1]).numel()) if hp.shape[0] else 0
 
 
-def north_star_forms(args, log, sc, el, base):
+def learned_step_forms(args, log, sc, el, base):
     """The learned per-object step with FP32 outward-rounded boxes and tree,
     with the eccentric-anomaly interval box and with the speed box, against the
     plain FP64 form at 1 s (the default line): ms per query over the same
@@ -814,7 +814,7 @@ def main():
     ap.add_argument("--cpu-slabs", type=int, default=60,
                     help="CPU baseline: the oracle over the hour's first this many 1 s slabs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-north-star", action="store_true",
+    ap.add_argument("--no-learned-steps", action="store_true",
                     help="default line: skip the learned-step FP32 forms")
     ap.add_argument("--no-copy", action="store_true",
                     help="skip the streaming-copy bandwidth measurement")
