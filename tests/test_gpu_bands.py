@@ -95,7 +95,7 @@ def test_gather_remap_canonical():
     assert c.tolist() == [[1, 2, 0, 4], [1, 2, 9, 10], [5, 6, 2, 3]]
 
 
-@pytest.mark.parametrize("count", [1, 2, 3, 1000, 4095, 4096, 4097, 20000, 65536, 65537,
+@pytest.mark.parametrize("count", [0, 1, 2, 3, 1000, 4095, 4096, 4097, 20000, 65536, 65537,
                                    100000, 262144, 262145, 400000])
 def test_canonical_records_small_medium_and_radix_paths(count):
     """Up to 4096 records take the one-workgroup LDS sort, up to 262144
